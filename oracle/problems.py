@@ -1,0 +1,92 @@
+"""Benchmark hierarchies assembled by the oracle.
+
+Level 0 is the finest.  A level is (mesh, order k, element kind); the
+transfer between two consecutive levels is a p-transfer when they share a
+mesh (Section 3.2) and an h-transfer between nested meshes otherwise
+(Section 3.1).  Direct p-coarsening (Section 4, "phMG(direct)") goes from
+P_k/P_{k-1} straight to P_2/P_1 on the finest mesh; Scott-Vogelius level 0 is
+coarsened through Taylor-Hood levels (Section 3.2).
+
+Workloads (synthetic stand-ins for the paper's cavity / step problems):
+  * cfg1: TH P2/P1 on the structured 8x8 mesh, hMG with the 4x4 mesh as the
+    coarse direct solve; nu = 2, omega = 0.5.
+  * cfg2: TH P4/P3 on a Delaunay mesh refined 3 times -> TH P2/P1 on the same
+    mesh -> P2/P1 on the 3 coarser meshes (direct solve on the base mesh).
+  * cfg4: SV P4/P3disc on the Alfeld split of a jittered 16x16 mesh refined
+    twice -> TH P2/P1 on the Alfeld mesh -> TH P2/P1 on the 3 macro meshes.
+"""
+from __future__ import annotations
+
+from typing import List, Tuple
+
+import numpy as np
+
+import synth
+from .discretization import assemble_stokes
+from .multigrid import CycleOpts, Level
+from .patches import multiplicity_weights, vanka_star_patches
+from .transfer import prolongation
+
+SEEDS = {"cfg1": 1, "cfg2": 2, "cfg3": 3, "cfg4": 4}
+
+
+def level_specs(name: str, k: int = None) -> Tuple[List[Tuple[int, int, str]], CycleOpts]:
+    """(mesh index from the finest, order, kind) per level, and cycle options."""
+    if name in ("cfg1", "tiny2", "tiny4"):
+        return [(0, 2, "TH"), (1, 2, "TH")], CycleOpts(nu_p=2, nu_h=2, n_v=1, n_plevels=0, omega=0.5)
+    if name.startswith("cfg2"):
+        nref = {"cfg2": 3, "cfg2_r2": 2, "cfg2_r1": 1}[name]
+        kk = 4 if k is None else k
+        specs = [(0, kk, "TH")] + [(i, 2, "TH") for i in range(nref + 1)]
+        return specs, CycleOpts(nu_p=2, nu_h=2, n_v=1, n_plevels=1, omega=0.5)
+    if name in ("cfg4", "cfg4_r0", "sv_small"):
+        nmac = {"cfg4": 3, "cfg4_r0": 1, "sv_small": 2}[name]
+        kk = 4 if k is None else k
+        specs = [(0, kk, "SV"), (0, 2, "TH")] + [(i, 2, "TH") for i in range(1, nmac + 1)]
+        return specs, CycleOpts(nu_p=2, nu_h=2, n_v=1, n_plevels=1, omega=0.5)
+    raise KeyError(name)
+
+
+def gradual_schedule(k: int) -> List[int]:
+    """Velocity orders of the gradual p-coarsening schedule (figure "fig:pmg_schedule").
+
+    k in [2,5] goes straight to P2, k in [6,7] through P4, k in [8,10] through P5.
+    """
+    if 2 <= k <= 5:
+        return [k, 2] if k != 2 else [2]
+    if k in (6, 7):
+        return [k, 4, 2]
+    if 8 <= k <= 10:
+        return [k, 5, 2]
+    raise ValueError(k)
+
+
+def build(name: str, k: int = None, weights: str = "pou", with_rhs: bool = True,
+          specs=None, opts=None):
+    """Assemble every level, its patches and the transfers.  Returns (levels, discs, opts, b)."""
+    meshes = synth.config_mesh_hierarchy(name)[::-1]          # finest first
+    if specs is None:
+        specs, opts = level_specs(name, k)
+    seed = SEEDS.get(name.split("_")[0], 1)
+    A = synth.mms_amplitude(seed)
+    f = (lambda x, y: synth.mms_forcing(x, y, A)) if with_rhs else None
+    g = (lambda x, y: synth.mms_velocity(x, y, A)) if with_rhs else None
+    discs = []
+    for li, (mi, kk, kind) in enumerate(specs):
+        d = assemble_stokes(meshes[mi], kk, kind, forcing=f if li == 0 else None, dirichlet=g if li == 0 else None)
+        discs.append(d)
+    levels = []
+    for li, d in enumerate(discs):
+        L = Level(K=d.K)
+        if li < len(discs) - 1:
+            L.patches = vanka_star_patches(d)
+            L.weights = multiplicity_weights(L.patches, d.n) if weights == "pou" else None
+        if li > 0:
+            mf = specs[li - 1][0]
+            mc = specs[li][0]
+            parent = None if mf == mc else meshes[mf].parent
+            L.P = prolongation(discs[li - 1], d, parent)
+        levels.append(L)
+    levels[-1].null = discs[-1].null_vector()
+    b = discs[0].b if with_rhs else None
+    return levels, discs, opts, b

@@ -1,0 +1,60 @@
+"""Additive Schwarz (Vanka) relaxation (oracle).
+
+Section 3.4, eq. "eq:ASM": M^{-1} = sum_i I^(i)^T W_i (K^(i))^{-1} I^(i) with
+K^(i) = I^(i) K I^(i)^T, and one relaxation sweep is x <- x + omega M^{-1}
+(b - K x).  All patches use the same residual (additive / block Jacobi).
+
+Reading where the paper is silent: the contributions of the patches to one
+DoF are summed in ascending patch order, then scaled by omega and added to x.
+
+Pins: tests/test_oracle_relax.py -- one sweep equals x + omega M^{-1}(b-Kx)
+with M^{-1} formed densely from numpy.linalg.inv of every patch matrix; nu
+sweeps equal the nu-th power of the dense propagator; the transposed sweep
+equals the dense transpose.
+"""
+from __future__ import annotations
+
+from typing import List, Optional
+
+import numpy as np
+
+from .lu import lu_factor, lu_solve, lu_solve_transposed
+
+
+def extract_patch(K, S: np.ndarray) -> np.ndarray:
+    """K^(i) = I^(i) K I^(i)^T as a dense matrix."""
+    return K[S][:, S].toarray()
+
+
+def setup_patches(K, patches: List[np.ndarray]):
+    return [lu_factor(extract_patch(K, S)) for S in patches]
+
+
+def asm_correction(patches, factors, weights: Optional[list], r: np.ndarray, transpose: bool = False) -> np.ndarray:
+    """sum_i I^(i)^T W_i (K^(i))^{-1} I^(i) r, patches visited in ascending order.
+
+    With transpose=True the adjoint operator sum_i I^(i)^T (K^(i))^{-T} W_i I^(i) r.
+    """
+    dx = np.zeros_like(r)
+    for i, S in enumerate(patches):
+        LU, piv = factors[i]
+        if not transpose:
+            y = lu_solve(LU, piv, r[S])
+            if weights is not None:
+                y = weights[i] * y
+        else:
+            rr = r[S] if weights is None else weights[i] * r[S]
+            y = lu_solve_transposed(LU, piv, rr)
+        dx[S] += y
+    return dx
+
+
+def asm_sweeps(K, patches, factors, weights, omega: float, b: np.ndarray, x: np.ndarray, nu: int,
+               transpose: bool = False) -> np.ndarray:
+    """nu sweeps of x <- x + omega M^{-1} (b - K x) (or with M^{-T}, K^T when transpose)."""
+    x = np.array(x, dtype=np.float64, copy=True)
+    KK = K.T.tocsr() if transpose else K
+    for _ in range(nu):
+        r = b - KK @ x
+        x = x + omega * asm_correction(patches, factors, weights, r, transpose)
+    return x

@@ -1,0 +1,55 @@
+"""Analytic problem data: manufactured solution and seeded forcings.
+
+The Stokes problem is -lap u + grad p = f, -div u = 0 (Section 2, eq.
+"eq:stokes-eq").  The manufactured solution used for the benchmark workloads
+is u = curl(psi) with psi = A sin^2(pi x) sin^2(pi y), which is divergence
+free and vanishes on the boundary of the unit square, and p = A cos(pi x)
+cos(pi y), which has zero mean.  f = -lap u + grad p is written out below.
+A is drawn from U[0.5, 2] with a seeded generator.
+
+These are plain function evaluations (inputs), not solver arithmetic.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+PI = np.pi
+
+
+def mms_amplitude(seed: int) -> float:
+    return float(np.random.default_rng(seed).uniform(0.5, 2.0))
+
+
+def mms_velocity(x: np.ndarray, y: np.ndarray, A: float):
+    ux = A * PI * np.sin(PI * x) ** 2 * np.sin(2 * PI * y)
+    uy = -A * PI * np.sin(2 * PI * x) * np.sin(PI * y) ** 2
+    return ux, uy
+
+
+def mms_pressure(x: np.ndarray, y: np.ndarray, A: float):
+    return A * np.cos(PI * x) * np.cos(PI * y)
+
+
+def mms_forcing(x: np.ndarray, y: np.ndarray, A: float):
+    # lap u_x = A pi^3 sin(2 pi y) (2 cos(2 pi x) - 4 sin^2(pi x))
+    # lap u_y = -A pi^3 sin(2 pi x) (2 cos(2 pi y) - 4 sin^2(pi y))
+    lap_ux = A * PI ** 3 * np.sin(2 * PI * y) * (2 * np.cos(2 * PI * x) - 4 * np.sin(PI * x) ** 2)
+    lap_uy = -A * PI ** 3 * np.sin(2 * PI * x) * (2 * np.cos(2 * PI * y) - 4 * np.sin(PI * y) ** 2)
+    dpx = -A * PI * np.sin(PI * x) * np.cos(PI * y)
+    dpy = -A * PI * np.cos(PI * x) * np.sin(PI * y)
+    return -lap_ux + dpx, -lap_uy + dpy
+
+
+def gaussian_bump_params(nrhs: int, seed: int):
+    """Centres U[0.15,0.85]^2, widths U[0.05,0.2], random unit directions."""
+    rng = np.random.default_rng(seed)
+    centres = rng.uniform(0.15, 0.85, size=(nrhs, 2))
+    widths = rng.uniform(0.05, 0.2, size=nrhs)
+    ang = rng.uniform(0.0, 2 * PI, size=nrhs)
+    dirs = np.stack([np.cos(ang), np.sin(ang)], axis=1)
+    return centres, widths, dirs
+
+
+def gaussian_bump_forcing(x: np.ndarray, y: np.ndarray, centre, width, direction):
+    g = np.exp(-((x - centre[0]) ** 2 + (y - centre[1]) ** 2) / (2.0 * width ** 2))
+    return direction[0] * g, direction[1] * g

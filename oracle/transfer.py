@@ -5,7 +5,10 @@ this is the L2 projection of the coarse function into the fine space and needs
 no solve.  Section 3.2: the p-transfer between P_k/P_{k-1} and P_2/P_1 on the
 same mesh is built the same way.  Entry P[i, j] is the j-th coarse basis
 function evaluated at the i-th fine node; fine and coarse Dirichlet DoFs are
-dropped (corrections vanish there); entries with |P_ij| < 1e-14 are dropped.
+dropped (corrections vanish there).  Entries with |P_ij| < 1e-10 are exact
+zeros of a basis function at a lattice node computed with rounding error
+(every genuine entry is a basis value at a lattice point, |P_ij| >= 1/32) and
+are dropped.
 A Scott-Vogelius fine pressure node takes the value of the continuous coarse
 pressure of the cell it belongs to.
 
@@ -21,7 +24,7 @@ import scipy.sparse as sp
 from . import element
 from .discretization import cell_geometry
 
-DROP_TOL = 1e-14
+DROP_TOL = 1e-10
 
 
 def _scalar_interp(f_space, c_space, fverts, fcells, cverts, ccells, parent):

@@ -1,0 +1,51 @@
+"""The product's host front-end against the oracle (CPU, not gpu).
+
+Integer structures (CSR patterns, patch DoF lists, transfer patterns) must be
+identical; floating-point values agree to rounding.
+"""
+import numpy as np
+import pytest
+
+from oracle import problems as oproblems
+from paper_2407_07253_amd import frontend
+
+
+def _same_csr(a, b_scipy, rtol):
+    b = b_scipy.tocsr()
+    b.sort_indices()
+    assert a.nrows == b.shape[0] and a.ncols == b.shape[1]
+    assert np.array_equal(a.rowptr, b.indptr)
+    assert np.array_equal(a.col, b.indices)
+    scale = max(np.abs(b.data).max(), 1e-300)
+    assert np.abs(a.val - b.data).max() <= rtol * scale
+
+
+@pytest.mark.parametrize("name", ["tiny4", "cfg1", "sv_small", "cfg2_r1"])
+def test_hierarchy_matches_oracle(name):
+    fh = frontend.build_hierarchy(name)
+    olevels, odiscs, oopts, ob = oproblems.build(name)
+    assert len(fh.levels) == len(olevels)
+    for fl, ol, od in zip(fh.levels, olevels, odiscs):
+        assert fl.n == od.n and fl.nfu == od.nfu
+        _same_csr(fl.K, ol.K, 1e-13)
+        if ol.patches is not None:
+            optr = np.concatenate([[0], np.cumsum([len(S) for S in ol.patches])])
+            assert np.array_equal(fl.patch_ptr, optr)
+            assert np.array_equal(fl.patch_dofs, np.concatenate(ol.patches))
+            assert np.allclose(fl.patch_weight, np.concatenate(ol.weights), rtol=0, atol=1e-15)
+        if ol.P is not None:
+            _same_csr(fl.P, ol.P, 1e-13)
+    assert np.abs(fh.b[0] - ob).max() <= 1e-12 * np.abs(ob).max()
+    assert fh.opts == dict(nu_p=oopts.nu_p, nu_h=oopts.nu_h, n_v=oopts.n_v, n_plevels=oopts.n_plevels, omega=oopts.omega)
+
+
+def test_shape_functions_nodal_and_quadrature_exact():
+    from math import factorial
+    for k in range(1, 6):
+        A = frontend.lattice(k)
+        phi, _ = frontend.shape_functions(k, A[:, 1:] / k)
+        assert np.allclose(phi, np.eye(len(A)), atol=1e-12)
+    pts, w = frontend.collapsed_rule(9)
+    for a in range(10):
+        b = 9 - a
+        assert abs(np.sum(w * pts[:, 0] ** a * pts[:, 1] ** b) - factorial(a) * factorial(b) / factorial(a + b + 2)) < 1e-15

@@ -1,0 +1,170 @@
+/*
+ * phmg.h -- C ABI of the MI355X (gfx950) Vanka-star / phMG / FGMRES library.
+ *
+ * The library solves the discrete Stokes saddle-point system K x = b
+ * (Section 2, eq. "eq:saddle": K = [A B^T; B 0]) with restarted flexible
+ * GMRES (Section 4, solver paragraph: FGMRES(30)) right-preconditioned by a
+ * monolithic multigrid cycle: hMG (Section 3.1, eq. "eq:TG-operator") or
+ * phMG defect correction (Section 3.2, eq. "eq:DC-TG-operator"), whose
+ * smoother is additive Schwarz over Vanka-star patches (Section 3.4,
+ * eq. "eq:ASM", figure "fig:patches"), each patch system solved exactly.
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ *  - Level 0 is the finest level; level nlevels-1 is the coarsest and is
+ *    solved by a dense direct solve.
+ *  - Descriptor arrays (phmg_csr, phmg_patches, coarse_null) are HOST
+ *    pointers.  phmg_hierarchy_create validates them on the host, copies them
+ *    to device memory owned by the library and never reads them again.
+ *  - Vector arguments b and x of relax_apply / vcycle / fgmres_solve are
+ *    DEVICE pointers to float64 arrays of the level's length, owned by the
+ *    caller.  b is read only; x is read and written.  b and x must not alias.
+ *  - All work is enqueued on the stream given at creation (a hipStream_t
+ *    passed as void*; NULL = the default stream).  relax_setup and
+ *    fgmres_solve synchronise that stream before returning; relax_apply and
+ *    vcycle are asynchronous.
+ *  - Every call returns a phmg_status.  No exception crosses the ABI.  On an
+ *    error, phmg_last_error() returns a thread-local message naming the level
+ *    and, where relevant, the patch.
+ *  - Calls on one context are not thread safe; use one context per thread.
+ */
+#ifndef PHMG_H
+#define PHMG_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct phmg_ctx_s* phmg_ctx;
+
+typedef enum {
+    PHMG_OK = 0,
+    PHMG_EINVAL = -1,     /* malformed or inconsistent input; nothing was launched      */
+    PHMG_ENOMEM = -2,     /* device allocation failed                                    */
+    PHMG_ESINGULAR = -3,  /* a patch (or the coarse matrix) has a pivot <= 1e-14 ||.||_inf */
+    PHMG_ENOCONV = -4,    /* fgmres_solve hit maxit; x holds the last iterate            */
+    PHMG_EHIP = -5,       /* a HIP runtime call failed                                   */
+    PHMG_ESTATE = -6      /* call order violated (e.g. apply before setup)               */
+} phmg_status;
+
+/* Compressed sparse row matrix.  rowptr[0] = 0, rowptr[nrows] = nnz, column
+ * indices strictly ascending inside each row, all values finite.  Sizes
+ * must satisfy nnz < 2^31. */
+typedef struct {
+    int32_t nrows, ncols;
+    int64_t nnz;
+    const int32_t* rowptr;   /* nrows + 1 */
+    const int32_t* col;      /* nnz       */
+    const double* val;       /* nnz       */
+} phmg_csr;
+
+/* Vanka-star patches of one level (Section 3.4): patch i owns the DoFs
+ * dofs[ptr[i] .. ptr[i+1]), strictly ascending, 1 <= m_i <= PHMG_MAX_PATCH.
+ * weight (optional, same length as dofs) holds the diagonal of the
+ * partition-of-unity operator W_i of eq. "eq:ASM"; NULL means W_i = I. */
+typedef struct {
+    int32_t npatch;
+    const int64_t* ptr;      /* npatch + 1 */
+    const int32_t* dofs;     /* ptr[npatch] */
+    const double* weight;    /* ptr[npatch] or NULL */
+} phmg_patches;
+
+#define PHMG_MAX_PATCH 1024
+
+/* Cycle parameters (Section 3.1-3.2; V^{(n_V, nu_p, nu_h)} of Section 4):
+ * levels 0 .. n_plevels-1 are p-levels relaxed with nu_p sweeps and coarsened
+ * by defect correction; the hMG part starting at level n_plevels is applied
+ * n_v times (stationary iterations from zero); h-levels use nu_h sweeps.
+ * Pre- and post-smoothing use the same count.  omega damps every sweep. */
+typedef struct {
+    int32_t nu_p, nu_h, n_v, n_plevels;
+    double omega;
+} phmg_cycle_opts;
+
+/* Patch-factor storage precision of a level (the apply accumulates in the
+ * precision of the factors, the residual and the scatter stay float64). */
+typedef enum { PHMG_PREC_F64 = 0, PHMG_PREC_F32 = 1, PHMG_PREC_BF16 = 2 } phmg_precision;
+
+typedef struct {
+    int32_t nlevels;                 /* >= 2 */
+    const phmg_csr* K;               /* nlevels matrices, square, free DoFs only          */
+    const phmg_csr* P;               /* nlevels-1 prolongations: P[l] is n_l x n_{l+1}    */
+    const phmg_patches* patches;     /* nlevels-1 (none on the coarsest level)            */
+    const double* coarse_null;       /* kernel vector z of K_{nlevels-1}, or NULL when
+                                        the coarsest matrix is nonsingular                 */
+} phmg_hierarchy_desc;
+
+/* Validate and upload a hierarchy.  R_l = P_l^T is formed explicitly on the
+ * host and uploaded; the DoF -> patch-slot map used by the deterministic
+ * scatter is built here.  On success *out owns all device memory it uses. */
+phmg_status phmg_hierarchy_create(const phmg_hierarchy_desc* desc, const phmg_cycle_opts* opts,
+                                  void* stream, phmg_ctx* out);
+
+/* Set-up of the relaxation on one level (level < 0: every level): patch
+ * extraction K_i = K[S_i, S_i] and factorisation of every patch, and on the
+ * coarsest level the factorisation of the (bordered) coarse matrix.  Patch
+ * systems are inverted by Gauss-Jordan elimination with partial pivoting
+ * (the same pivots as LU with partial pivoting) and the explicit inverse is
+ * stored in the level's precision.  Returns PHMG_ESINGULAR naming the first
+ * singular patch.  Synchronises the stream. */
+phmg_status phmg_relax_setup(phmg_ctx ctx, int level);
+
+/* Choose the storage precision of the patch inverses of one level (before
+ * relax_setup of that level, or followed by a new relax_setup). */
+phmg_status phmg_set_precision(phmg_ctx ctx, int level, phmg_precision prec);
+
+/* nu sweeps of x <- x + omega * sum_i R_i^T W_i K_i^{-1} R_i (b - K_l x) on
+ * level `level` (eq. "eq:ASM").  level must not be the coarsest. */
+phmg_status phmg_relax_apply(phmg_ctx ctx, int level, const double* b, double* x, int nu);
+
+/* x <- B b: one preconditioner application (phMG or hMG cycle from x = 0) on
+ * level 0.  The content of x on entry is ignored. */
+phmg_status phmg_vcycle(phmg_ctx ctx, const double* b, double* x);
+
+/* Restarted FGMRES on level 0, right-preconditioned by phmg_vcycle, from the
+ * initial guess in x.  Stops when the Givens residual estimate drops to
+ * rtol * ||b - K x_0||_2, on an exact breakdown, or after maxit inner
+ * iterations (then returns PHMG_ENOCONV with x = last iterate).  On return
+ * *iters is the number of inner iterations and *relres the true residual
+ * ||b - K x||_2 / ||b - K x_0||_2.  Synchronises the stream. */
+phmg_status phmg_fgmres_solve(phmg_ctx ctx, const double* b, double* x, double rtol, int restart, int maxit,
+                              int* iters, double* relres);
+
+/* Residual r = b - K_l x on a level (device pointers, asynchronous). */
+phmg_status phmg_residual(phmg_ctx ctx, int level, const double* b, const double* x, double* r);
+
+/* Per-level sizes: n, nnz(K), npatch, sum m, sum m^2, max m. */
+typedef struct {
+    int32_t n, npatch, max_m, precision;
+    int64_t nnz, sum_m, sum_m2;
+} phmg_level_info;
+phmg_status phmg_get_level_info(phmg_ctx ctx, int level, phmg_level_info* info);
+
+/* Optional per-kernel timing with HIP events recorded on the context stream
+ * around every launch of the kernels listed below (off by default; when on,
+ * each timed launch is bracketed by two events, which adds host overhead but
+ * does not change results).  phmg_profile_read returns the summed elapsed
+ * milliseconds and the number of launches since the last reset (it
+ * synchronises the stream). */
+typedef enum {
+    PHMG_K_PATCH_APPLY = 0,   /* batched patch solve y_i = K_i^{-1} r[S_i]           */
+    PHMG_K_SCATTER = 1,       /* weighted scatter-add x += omega sum R_i^T W_i y_i   */
+    PHMG_K_SPMV = 2,          /* residual and transfer SpMVs                          */
+    PHMG_K_EXTRACT = 3,       /* patch extraction                                     */
+    PHMG_K_FACTOR = 4,        /* patch Gauss-Jordan inversion                         */
+    PHMG_K_COUNT = 5
+} phmg_kernel_id;
+phmg_status phmg_profile_enable(phmg_ctx ctx, int on);
+phmg_status phmg_profile_read(phmg_ctx ctx, int kernel, double* total_ms, int64_t* launches, int reset);
+
+phmg_status phmg_hierarchy_destroy(phmg_ctx ctx);
+
+/* Thread-local description of the last error ("" when none). */
+const char* phmg_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PHMG_H */

@@ -1,0 +1,215 @@
+"""ctypes binding of libphmg.so (the C ABI in include/phmg.h).
+
+Argument marshalling only: host arrays are passed as pointers to
+``phmg_hierarchy_create``; device vectors are torch float64 CUDA tensors whose
+``data_ptr()`` is handed to the library, and the library's stream is torch's
+current stream.  Every step of the solve runs in the library's HIP kernels;
+there is no fallback: if the library is missing, importing this module fails.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Optional, Sequence
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libphmg.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2407_07253_amd.build` "
+                      "(or __graft_entry__.build()); there is no CPU fallback")
+
+_lib = C.CDLL(LIB_PATH)
+
+PHMG_OK, PHMG_EINVAL, PHMG_ENOMEM, PHMG_ESINGULAR, PHMG_ENOCONV, PHMG_EHIP, PHMG_ESTATE = 0, -1, -2, -3, -4, -5, -6
+STATUS_NAMES = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "ESINGULAR", -4: "ENOCONV", -5: "EHIP", -6: "ESTATE"}
+PREC = {"f64": 0, "f32": 1, "bf16": 2}
+KERNELS = {"patch_apply": 0, "scatter": 1, "spmv": 2, "extract": 3, "factor": 4}
+MAX_PATCH = 1024
+
+
+class PhmgError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"phmg {STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+class CsrT(C.Structure):
+    _fields_ = [("nrows", C.c_int32), ("ncols", C.c_int32), ("nnz", C.c_int64),
+                ("rowptr", C.c_void_p), ("col", C.c_void_p), ("val", C.c_void_p)]
+
+
+class PatchesT(C.Structure):
+    _fields_ = [("npatch", C.c_int32), ("ptr", C.c_void_p), ("dofs", C.c_void_p), ("weight", C.c_void_p)]
+
+
+class OptsT(C.Structure):
+    _fields_ = [("nu_p", C.c_int32), ("nu_h", C.c_int32), ("n_v", C.c_int32), ("n_plevels", C.c_int32),
+                ("omega", C.c_double)]
+
+
+class DescT(C.Structure):
+    _fields_ = [("nlevels", C.c_int32), ("K", C.POINTER(CsrT)), ("P", C.POINTER(CsrT)),
+                ("patches", C.POINTER(PatchesT)), ("coarse_null", C.c_void_p)]
+
+
+class LevelInfoT(C.Structure):
+    _fields_ = [("n", C.c_int32), ("npatch", C.c_int32), ("max_m", C.c_int32), ("precision", C.c_int32),
+                ("nnz", C.c_int64), ("sum_m", C.c_int64), ("sum_m2", C.c_int64)]
+
+
+def _sig(name, res, args):
+    f = getattr(_lib, name)
+    f.restype = res
+    f.argtypes = args
+    return f
+
+
+_create = _sig("phmg_hierarchy_create", C.c_int, [C.POINTER(DescT), C.POINTER(OptsT), C.c_void_p, C.POINTER(C.c_void_p)])
+_destroy = _sig("phmg_hierarchy_destroy", C.c_int, [C.c_void_p])
+_setup = _sig("phmg_relax_setup", C.c_int, [C.c_void_p, C.c_int])
+_set_prec = _sig("phmg_set_precision", C.c_int, [C.c_void_p, C.c_int, C.c_int])
+_apply = _sig("phmg_relax_apply", C.c_int, [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_int])
+_vcycle = _sig("phmg_vcycle", C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p])
+_fgmres = _sig("phmg_fgmres_solve", C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_double, C.c_int, C.c_int,
+                                              C.POINTER(C.c_int), C.POINTER(C.c_double)])
+_residual = _sig("phmg_residual", C.c_int, [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p])
+_info = _sig("phmg_get_level_info", C.c_int, [C.c_void_p, C.c_int, C.POINTER(LevelInfoT)])
+_prof_on = _sig("phmg_profile_enable", C.c_int, [C.c_void_p, C.c_int])
+_prof_read = _sig("phmg_profile_read", C.c_int, [C.c_void_p, C.c_int, C.POINTER(C.c_double), C.POINTER(C.c_int64), C.c_int])
+_last_error = _sig("phmg_last_error", C.c_char_p, [])
+
+EXPORTED = ["phmg_hierarchy_create", "phmg_hierarchy_destroy", "phmg_relax_setup", "phmg_set_precision",
+            "phmg_relax_apply", "phmg_vcycle", "phmg_fgmres_solve", "phmg_residual", "phmg_get_level_info",
+            "phmg_profile_enable", "phmg_profile_read", "phmg_last_error"]
+
+
+def last_error() -> str:
+    return _last_error().decode()
+
+
+def _check(st: int, allow=()):
+    if st != PHMG_OK and st not in allow:
+        raise PhmgError(st, last_error())
+    return st
+
+
+def _ptr(a: Optional[np.ndarray]):
+    return None if a is None else a.ctypes.data
+
+
+def _vec_ptr(t, n: int, name: str) -> int:
+    import torch
+    if not isinstance(t, torch.Tensor) or t.dtype != torch.float64 or not t.is_cuda or not t.is_contiguous():
+        raise TypeError(f"{name} must be a contiguous float64 CUDA tensor")
+    if t.numel() < n:
+        raise ValueError(f"{name} has {t.numel()} entries, the level needs {n}")
+    return t.data_ptr()
+
+
+class Hierarchy:
+    """A validated hierarchy living in device memory (phmg_hierarchy_create)."""
+
+    def __init__(self, K: Sequence, P: Sequence, patches: Sequence, coarse_null: Optional[np.ndarray],
+                 nu_p: int = 2, nu_h: int = 2, n_v: int = 1, n_plevels: int = 1, omega: float = 0.5,
+                 stream: Optional[int] = None):
+        """K: list of (rowptr, col, val, nrows, ncols); P: list of the same (len-1);
+        patches: list of (ptr int64, dofs int32, weight float64 or None)."""
+        import torch
+        keep = []
+
+        def csr(item):
+            rowptr, col, val, nrows, ncols = item
+            rowptr = np.ascontiguousarray(rowptr, dtype=np.int32)
+            col = np.ascontiguousarray(col, dtype=np.int32)
+            val = np.ascontiguousarray(val, dtype=np.float64)
+            keep.extend([rowptr, col, val])
+            return CsrT(int(nrows), int(ncols), int(col.size), _ptr(rowptr), _ptr(col), _ptr(val))
+
+        nl = len(K)
+        Ks = (CsrT * nl)(*[csr(k) for k in K])
+        Ps = (CsrT * max(nl - 1, 1))(*[csr(p) for p in P])
+        pts = []
+        for (ptr, dofs, w) in patches:
+            ptr = np.ascontiguousarray(ptr, dtype=np.int64)
+            dofs = np.ascontiguousarray(dofs, dtype=np.int32)
+            w = None if w is None else np.ascontiguousarray(w, dtype=np.float64)
+            keep.extend([ptr, dofs, w])
+            pts.append(PatchesT(int(ptr.size - 1), _ptr(ptr), _ptr(dofs), _ptr(w)))
+        Pt = (PatchesT * max(nl - 1, 1))(*pts)
+        z = None if coarse_null is None else np.ascontiguousarray(coarse_null, dtype=np.float64)
+        desc = DescT(nl, Ks, Ps, Pt, _ptr(z))
+        opts = OptsT(nu_p, nu_h, n_v, n_plevels, omega)
+        if stream is None:
+            stream = torch.cuda.current_stream().cuda_stream
+        h = C.c_void_p()
+        _check(_create(C.byref(desc), C.byref(opts), C.c_void_p(stream), C.byref(h)))
+        self._h = h
+        self.nlevels = nl
+        self.n = [int(k[3]) for k in K]
+        self.opts = dict(nu_p=nu_p, nu_h=nu_h, n_v=n_v, n_plevels=n_plevels, omega=omega)
+
+    @classmethod
+    def from_frontend(cls, fh, weights: bool = True, stream=None, **overrides) -> "Hierarchy":
+        """Build from a frontend.Hierarchy (host arrays in the canonical numbering)."""
+        levels = fh.levels
+        K = [(l.K.rowptr, l.K.col, l.K.val, l.K.nrows, l.K.ncols) for l in levels]
+        P = [(l.P.rowptr, l.P.col, l.P.val, l.P.nrows, l.P.ncols) for l in levels[1:]]
+        pts = [(l.patch_ptr, l.patch_dofs, l.patch_weight if weights else None) for l in levels[:-1]]
+        opts = dict(fh.opts)
+        opts.update(overrides)
+        return cls(K, P, pts, levels[-1].null_vector(), stream=stream, **opts)
+
+    # -- lifetime
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            _check(_destroy(self._h))
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- calls
+    def setup(self, level: int = -1):
+        _check(_setup(self._h, level))
+
+    def set_precision(self, level: int, prec: str):
+        _check(_set_prec(self._h, level, PREC[prec]))
+
+    def relax_apply(self, level: int, b, x, nu: int = 1):
+        n = self.n[level]
+        _check(_apply(self._h, level, _vec_ptr(b, n, "b"), _vec_ptr(x, n, "x"), nu))
+
+    def vcycle(self, b, x):
+        _check(_vcycle(self._h, _vec_ptr(b, self.n[0], "b"), _vec_ptr(x, self.n[0], "x")))
+
+    def residual(self, level: int, b, x, r):
+        n = self.n[level]
+        _check(_residual(self._h, level, _vec_ptr(b, n, "b"), _vec_ptr(x, n, "x"), _vec_ptr(r, n, "r")))
+
+    def fgmres(self, b, x, rtol: float = 1e-8, restart: int = 30, maxit: int = 1000):
+        it = C.c_int(0)
+        rr = C.c_double(0.0)
+        st = _check(_fgmres(self._h, _vec_ptr(b, self.n[0], "b"), _vec_ptr(x, self.n[0], "x"), rtol, restart, maxit,
+                            C.byref(it), C.byref(rr)), allow=(PHMG_ENOCONV,))
+        return int(it.value), float(rr.value), st == PHMG_OK
+
+    def level_info(self, level: int) -> dict:
+        i = LevelInfoT()
+        _check(_info(self._h, level, C.byref(i)))
+        return dict(n=i.n, npatch=i.npatch, max_m=i.max_m, precision=i.precision, nnz=i.nnz, sum_m=i.sum_m,
+                    sum_m2=i.sum_m2)
+
+    def profile(self, on: bool = True):
+        _check(_prof_on(self._h, 1 if on else 0))
+
+    def profile_read(self, kernel: str, reset: bool = False):
+        ms = C.c_double(0.0)
+        cnt = C.c_int64(0)
+        _check(_prof_read(self._h, KERNELS[kernel], C.byref(ms), C.byref(cnt), 1 if reset else 0))
+        return float(ms.value), int(cnt.value)

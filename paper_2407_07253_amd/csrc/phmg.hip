@@ -1,0 +1,700 @@
+// Host runtime of the gfx950 phMG library: the C ABI declared in include/phmg.h.
+//
+// Validation and index preprocessing (R = P^T, DoF -> patch-slot map, launch
+// order, factor offsets) run on the host once, in phmg_hierarchy_create.  All
+// arithmetic of the solve path runs in the kernels of kernels.hip, enqueued on
+// one HIP stream.  The host only orchestrates the cycle (Sections 3.1-3.2) and
+// carries FGMRES's small Hessenberg / Givens recurrences (Section 4).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <climits>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <numeric>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "phmg_internal.h"
+
+using namespace phmg;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+struct Error : std::runtime_error {
+    phmg_status code;
+    Error(phmg_status c, const std::string& m) : std::runtime_error(m), code(c) {}
+};
+
+[[noreturn]] void fail(phmg_status c, const std::string& m) { throw Error(c, m); }
+
+void hipcheck(hipError_t e, const char* what) {
+    if (e != hipSuccess) fail(PHMG_EHIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+template <typename T>
+T* dalloc(phmg_ctx ctx, int64_t count) {
+    if (count <= 0) count = 1;
+    void* p = nullptr;
+    if (hipMalloc(&p, sizeof(T) * (size_t)count) != hipSuccess) {
+        (void)hipGetLastError();
+        fail(PHMG_ENOMEM, "hipMalloc of " + std::to_string(sizeof(T) * (size_t)count) + " bytes failed");
+    }
+    ctx->allocs.push_back(p);
+    return static_cast<T*>(p);
+}
+
+void dfree(phmg_ctx ctx, void* p) {
+    if (!p) return;
+    auto it = std::find(ctx->allocs.begin(), ctx->allocs.end(), p);
+    if (it != ctx->allocs.end()) ctx->allocs.erase(it);
+    (void)hipFree(p);
+}
+
+template <typename T>
+T* upload(phmg_ctx ctx, const T* h, int64_t count) {
+    T* d = dalloc<T>(ctx, count);
+    if (count > 0) hipcheck(hipMemcpy(d, h, sizeof(T) * (size_t)count, hipMemcpyHostToDevice), "hipMemcpy H2D");
+    return d;
+}
+
+std::string lvl(int l) { return "level " + std::to_string(l) + ": "; }
+
+void check_csr(const phmg_csr& A, const std::string& who) {
+    if (A.nrows < 0 || A.ncols < 0) fail(PHMG_EINVAL, who + "negative dimension");
+    if (A.nnz < 0 || A.nnz >= (int64_t)INT32_MAX) fail(PHMG_EINVAL, who + "nnz out of range");
+    if (!A.rowptr || (A.nnz > 0 && (!A.col || !A.val))) fail(PHMG_EINVAL, who + "null array");
+    if (A.rowptr[0] != 0 || A.rowptr[A.nrows] != A.nnz) fail(PHMG_EINVAL, who + "rowptr does not span [0, nnz]");
+    for (int32_t i = 0; i < A.nrows; ++i) {
+        if (A.rowptr[i + 1] < A.rowptr[i]) fail(PHMG_EINVAL, who + "rowptr decreases at row " + std::to_string(i));
+        for (int32_t k = A.rowptr[i]; k < A.rowptr[i + 1]; ++k) {
+            const int32_t c = A.col[k];
+            if (c < 0 || c >= A.ncols) fail(PHMG_EINVAL, who + "column index out of range in row " + std::to_string(i));
+            if (k > A.rowptr[i] && A.col[k - 1] >= c)
+                fail(PHMG_EINVAL, who + "columns not strictly ascending in row " + std::to_string(i));
+            if (!std::isfinite(A.val[k])) fail(PHMG_EINVAL, who + "non-finite value in row " + std::to_string(i));
+        }
+    }
+}
+
+DevCsr upload_csr(phmg_ctx ctx, int32_t nrows, int32_t ncols, const std::vector<int32_t>& rp,
+                  const std::vector<int32_t>& ci, const std::vector<double>& v) {
+    DevCsr d;
+    d.nrows = nrows;
+    d.ncols = ncols;
+    d.nnz = (int64_t)ci.size();
+    d.rowptr = upload(ctx, rp.data(), (int64_t)rp.size());
+    d.col = upload(ctx, ci.data(), (int64_t)ci.size());
+    d.val = upload(ctx, v.data(), (int64_t)v.size());
+    const double avg = nrows > 0 ? (double)d.nnz / nrows : 0.0;
+    int g = 2;
+    while (g < 64 && g * 3 < avg) g *= 2;   // about 3 nonzeros per lane
+    d.group = g;
+    return d;
+}
+
+DevCsr upload_csr(phmg_ctx ctx, const phmg_csr& A) {
+    std::vector<int32_t> rp(A.rowptr, A.rowptr + A.nrows + 1), ci(A.col, A.col + A.nnz);
+    std::vector<double> v(A.val, A.val + A.nnz);
+    return upload_csr(ctx, A.nrows, A.ncols, rp, ci, v);
+}
+
+DevCsr upload_transpose(phmg_ctx ctx, const phmg_csr& A) {
+    std::vector<int32_t> rp(A.ncols + 1, 0), ci(A.nnz);
+    std::vector<double> v(A.nnz);
+    for (int64_t k = 0; k < A.nnz; ++k) rp[A.col[k] + 1]++;
+    for (int32_t j = 0; j < A.ncols; ++j) rp[j + 1] += rp[j];
+    std::vector<int32_t> pos(rp.begin(), rp.end() - 1);
+    for (int32_t i = 0; i < A.nrows; ++i)
+        for (int32_t k = A.rowptr[i]; k < A.rowptr[i + 1]; ++k) {
+            const int32_t q = pos[A.col[k]]++;
+            ci[q] = i;
+            v[q] = A.val[k];
+        }
+    return upload_csr(ctx, A.ncols, A.nrows, rp, ci, v);
+}
+
+struct Timed {
+    phmg_ctx ctx;
+    int id;
+    hipEvent_t e1 = nullptr;
+    hipEvent_t take() {
+        auto& pool = ctx->prof.pool;
+        if (!pool.empty()) {
+            hipEvent_t e = pool.back();
+            pool.pop_back();
+            return e;
+        }
+        hipEvent_t e;
+        hipcheck(hipEventCreate(&e), "hipEventCreate");
+        return e;
+    }
+    hipEvent_t e0 = nullptr;
+    Timed(phmg_ctx c, int k) : ctx(c), id(k) {
+        if (!ctx->prof.on) return;
+        e0 = take();
+        e1 = take();
+        hipcheck(hipEventRecord(e0, ctx->stream), "hipEventRecord");
+    }
+    ~Timed() {
+        if (!e0) return;
+        (void)hipEventRecord(e1, ctx->stream);
+        ctx->prof.pending.push_back({id, {e0, e1}});
+    }
+};
+
+void drain_profile(phmg_ctx ctx) {
+    if (ctx->prof.pending.empty()) return;
+    hipcheck(hipStreamSynchronize(ctx->stream), "hipStreamSynchronize");
+    for (auto& it : ctx->prof.pending) {
+        float ms = 0.f;
+        hipcheck(hipEventElapsedTime(&ms, it.second.first, it.second.second), "hipEventElapsedTime");
+        ctx->prof.ms[it.first] += ms;
+        ctx->prof.count[it.first] += 1;
+        ctx->prof.pool.push_back(it.second.first);
+        ctx->prof.pool.push_back(it.second.second);
+    }
+    ctx->prof.pending.clear();
+}
+
+// ----------------------------------------------------------------------------
+// relaxation, cycle
+// ----------------------------------------------------------------------------
+
+void relax(phmg_ctx ctx, int l, const double* b, double* x, int nu, bool x_zero) {
+    Level& L = ctx->L[l];
+    hipStream_t s = ctx->stream;
+    if (nu == 0) {
+        if (x_zero) launch_fill(s, L.n, x, 0.0);
+        return;
+    }
+    for (int it = 0; it < nu; ++it) {
+        const double* r = b;                         // x = 0: the residual is b itself
+        if (!(it == 0 && x_zero)) {
+            Timed t(ctx, PHMG_K_SPMV);
+            launch_spmv(s, L.K, x, -1.0, b, 1.0, L.r);
+            r = L.r;
+        }
+        {
+            Timed t(ctx, PHMG_K_PATCH_APPLY);
+            launch_patch_apply(s, L, r);
+        }
+        {
+            Timed t(ctx, PHMG_K_SCATTER);
+            launch_scatter(s, L, ctx->opts.omega, x, it == 0 && x_zero);
+        }
+    }
+}
+
+void cycle(phmg_ctx ctx, int l, const double* b, double* x, bool x_zero) {
+    const int last = (int)ctx->L.size() - 1;
+    hipStream_t s = ctx->stream;
+    if (l == last) {
+        launch_coarse_solve(s, ctx->L[l], b, x);
+        return;
+    }
+    Level& L = ctx->L[l];
+    Level& C = ctx->L[l + 1];
+    const int np = ctx->opts.n_plevels;
+    const int nu = l < np ? ctx->opts.nu_p : ctx->opts.nu_h;
+    relax(ctx, l, b, x, nu, x_zero);
+    {
+        Timed t(ctx, PHMG_K_SPMV);
+        launch_spmv(s, L.K, x, -1.0, b, 1.0, L.r);
+    }
+    {
+        Timed t(ctx, PHMG_K_SPMV);
+        launch_spmv(s, L.R, L.r, 1.0, nullptr, 0.0, C.b);
+    }
+    if (l + 1 < np || l + 1 == last || l >= np) {
+        cycle(ctx, l + 1, C.b, C.x, true);
+    } else {
+        for (int t = 0; t < ctx->opts.n_v; ++t) cycle(ctx, l + 1, C.b, C.x, t == 0);
+    }
+    {
+        Timed t(ctx, PHMG_K_SPMV);
+        launch_spmv(s, L.P, C.x, 1.0, x, 1.0, x);
+    }
+    relax(ctx, l, b, x, nu, false);
+}
+
+void vcycle(phmg_ctx ctx, const double* b, double* x) {
+    if (ctx->opts.n_plevels == 0) {
+        for (int t = 0; t < ctx->opts.n_v; ++t) cycle(ctx, 0, b, x, t == 0);
+    } else {
+        cycle(ctx, 0, b, x, true);
+    }
+}
+
+void require_ready(phmg_ctx ctx) {
+    for (size_t l = 0; l < ctx->L.size(); ++l)
+        if (!ctx->L[l].ready) fail(PHMG_ESTATE, lvl((int)l) + "relax_setup has not been run");
+}
+
+void setup_level(phmg_ctx ctx, int l) {
+    Level& L = ctx->L[l];
+    hipStream_t s = ctx->stream;
+    const int last = (int)ctx->L.size() - 1;
+    int32_t st = INT32_MAX;
+    hipcheck(hipMemcpyAsync(L.status, &st, sizeof(int32_t), hipMemcpyHostToDevice, s), "status reset");
+    if (l == last) {
+        double* dense = dalloc<double>(ctx, (int64_t)L.nb * L.nb);
+        launch_coarse_build(s, L, dense);
+        int64_t* cptr = dalloc<int64_t>(ctx, 2);
+        int64_t* coff = dalloc<int64_t>(ctx, 1);
+        const int64_t hp[2] = {0, L.nb}, ho = 0;
+        hipcheck(hipMemcpyAsync(cptr, hp, sizeof(hp), hipMemcpyHostToDevice, s), "H2D");
+        hipcheck(hipMemcpyAsync(coff, &ho, sizeof(ho), hipMemcpyHostToDevice, s), "H2D");
+        {
+            Timed t(ctx, PHMG_K_FACTOR);
+            launch_gj_invert(s, 1, cptr, coff, nullptr, dense, L.nb, L.status);
+        }
+        if (!L.cinv) L.cinv = dalloc<double>(ctx, (int64_t)L.nb * L.nb);
+        launch_transpose(s, L.nb, dense, L.cinv);
+        hipcheck(hipMemcpyAsync(&st, L.status, sizeof(int32_t), hipMemcpyDeviceToHost, s), "D2H");
+        hipcheck(hipStreamSynchronize(s), "hipStreamSynchronize");
+        dfree(ctx, dense);
+        dfree(ctx, cptr);
+        dfree(ctx, coff);
+        if (st != INT32_MAX) fail(PHMG_ESINGULAR, lvl(l) + "coarse matrix is singular");
+        L.ready = true;
+        return;
+    }
+    if (L.factors) dfree(ctx, L.factors);
+    L.factors = nullptr;
+    double* f64 = dalloc<double>(ctx, L.sum_m2);
+    {
+        Timed t(ctx, PHMG_K_EXTRACT);
+        launch_extract(s, L, f64);
+    }
+    {
+        Timed t(ctx, PHMG_K_FACTOR);
+        launch_gj_invert(s, L.npatch, L.pptr, L.foff, L.order, f64, L.max_m, L.status);
+    }
+    if (L.prec == PHMG_PREC_F64) {
+        L.factors = f64;
+    } else {
+        const size_t es = L.prec == PHMG_PREC_F32 ? 4 : 2;
+        void* lo = nullptr;
+        if (hipMalloc(&lo, es * (size_t)std::max<int64_t>(L.sum_m2, 1)) != hipSuccess) {
+            (void)hipGetLastError();
+            fail(PHMG_ENOMEM, lvl(l) + "factor allocation failed");
+        }
+        ctx->allocs.push_back(lo);
+        launch_convert(s, L.sum_m2, f64, lo, L.prec);
+        L.factors = lo;
+    }
+    hipcheck(hipMemcpyAsync(&st, L.status, sizeof(int32_t), hipMemcpyDeviceToHost, s), "D2H");
+    hipcheck(hipStreamSynchronize(s), "hipStreamSynchronize");
+    if (L.prec != PHMG_PREC_F64) dfree(ctx, f64);
+    if (st != INT32_MAX) fail(PHMG_ESINGULAR, lvl(l) + "patch " + std::to_string(st) + " is singular");
+    L.ready = true;
+}
+
+double device_norm(phmg_ctx ctx, const double* v) {
+    const int64_t n = ctx->L[0].n;
+    launch_multidot(ctx->stream, n, 1, v, n, v, ctx->partial, ctx->hdev, false);
+    hipcheck(hipMemcpyAsync(ctx->hhost, ctx->hdev, sizeof(double), hipMemcpyDeviceToHost, ctx->stream), "D2H");
+    hipcheck(hipStreamSynchronize(ctx->stream), "hipStreamSynchronize");
+    return std::sqrt(ctx->hhost[0]);
+}
+
+void ensure_krylov(phmg_ctx ctx, int restart) {
+    if (ctx->restart_cap >= restart) return;
+    const int64_t n = ctx->L[0].n;
+    dfree(ctx, ctx->V);
+    dfree(ctx, ctx->Z);
+    dfree(ctx, ctx->hdev);
+    if (ctx->hhost) (void)hipHostFree(ctx->hhost);
+    ctx->hhost = nullptr;
+    ctx->V = dalloc<double>(ctx, n * (restart + 1));
+    ctx->Z = dalloc<double>(ctx, n * restart);
+    ctx->hdev = dalloc<double>(ctx, 2 * (restart + 2) + 4);
+    if (!ctx->w) ctx->w = dalloc<double>(ctx, n);
+    if (!ctx->rvec) ctx->rvec = dalloc<double>(ctx, n);
+    if (!ctx->partial) ctx->partial = dalloc<double>(ctx, (int64_t)kRedBlocks * (restart + 2));
+    hipcheck(hipHostMalloc((void**)&ctx->hhost, sizeof(double) * (2 * (restart + 2) + 4)), "hipHostMalloc");
+    ctx->restart_cap = restart;
+}
+
+phmg_status fgmres(phmg_ctx ctx, const double* b, double* x, double rtol, int restart, int maxit, int* iters_out,
+                   double* relres_out) {
+    Level& L0 = ctx->L[0];
+    const int64_t n = L0.n;
+    hipStream_t s = ctx->stream;
+    ensure_krylov(ctx, restart);
+    double* V = ctx->V;
+    double* Z = ctx->Z;
+    double* w = ctx->w;
+    double* r = ctx->rvec;
+    double* h1 = ctx->hdev;
+    double* h2 = ctx->hdev + (restart + 2);
+    double* hn2 = ctx->hdev + 2 * (restart + 2);
+
+    launch_spmv(s, L0.K, x, -1.0, b, 1.0, r);
+    double beta = device_norm(ctx, r);
+    const double r0 = beta;
+    const double target = rtol * r0;
+    int iters = 0;
+    if (r0 == 0.0 || beta <= target) {
+        *iters_out = 0;
+        *relres_out = r0 == 0.0 ? 0.0 : beta / r0;
+        return PHMG_OK;
+    }
+    bool converged = false;
+    std::vector<double> H((restart + 1) * restart), cs(restart), sn(restart), g(restart + 1), y(restart);
+    auto Hij = [&](int i, int j) -> double& { return H[(size_t)j * (restart + 1) + i]; };
+    double* ydev = ctx->hdev + 2 * (restart + 2) + 1;   // restart doubles fit in h2's slot after use
+    (void)ydev;
+    for (;;) {
+        std::fill(H.begin(), H.end(), 0.0);
+        std::fill(g.begin(), g.end(), 0.0);
+        g[0] = beta;
+        launch_scale_copy(s, n, r, beta, V);
+        int ncols = 0;
+        bool stop = false;
+        double hn = 0.0;
+        for (int j = 0; j < restart; ++j) {
+            double* vj = V + (int64_t)j * n;
+            double* zj = Z + (int64_t)j * n;
+            vcycle(ctx, vj, zj);
+            launch_spmv(s, L0.K, zj, 1.0, nullptr, 0.0, w);
+            launch_multidot(s, n, j + 1, V, n, w, ctx->partial, h1, false);
+            launch_gemv_sub(s, n, j + 1, V, n, h1, w);
+            launch_multidot(s, n, j + 1, V, n, w, ctx->partial, h2, false);
+            launch_gemv_sub(s, n, j + 1, V, n, h2, w);
+            launch_multidot(s, n, 1, w, n, w, ctx->partial, hn2, false);
+            hipcheck(hipMemcpyAsync(ctx->hhost, ctx->hdev, sizeof(double) * (2 * (restart + 2) + 1),
+                                    hipMemcpyDeviceToHost, s),
+                     "D2H");
+            hipcheck(hipStreamSynchronize(s), "hipStreamSynchronize");
+            const double* hh1 = ctx->hhost;
+            const double* hh2 = ctx->hhost + (restart + 2);
+            hn = std::sqrt(ctx->hhost[2 * (restart + 2)]);
+            for (int i = 0; i <= j; ++i) Hij(i, j) = hh1[i] + hh2[i];
+            Hij(j + 1, j) = hn;
+            for (int i = 0; i < j; ++i) {
+                const double a = Hij(i, j), c = Hij(i + 1, j);
+                Hij(i, j) = cs[i] * a + sn[i] * c;
+                Hij(i + 1, j) = -sn[i] * a + cs[i] * c;
+            }
+            const double a = Hij(j, j), c = Hij(j + 1, j);
+            const double rho = std::hypot(a, c);
+            cs[j] = a / rho;
+            sn[j] = c / rho;
+            Hij(j, j) = rho;
+            Hij(j + 1, j) = 0.0;
+            g[j + 1] = -sn[j] * g[j];
+            g[j] = cs[j] * g[j];
+            ++iters;
+            ncols = j + 1;
+            if (std::fabs(g[j + 1]) <= target) {
+                converged = true;
+                stop = true;
+                break;
+            }
+            if (hn == 0.0 || iters >= maxit) {
+                stop = true;
+                break;
+            }
+            launch_scale_copy(s, n, w, hn, V + (int64_t)(j + 1) * n);
+        }
+        for (int i = ncols - 1; i >= 0; --i) {
+            double acc = g[i];
+            for (int k = i + 1; k < ncols; ++k) acc -= Hij(i, k) * y[k];
+            y[i] = acc / Hij(i, i);
+        }
+        double* yd = h2;   // reuse: h2 is consumed
+        hipcheck(hipMemcpyAsync(yd, y.data(), sizeof(double) * ncols, hipMemcpyHostToDevice, s), "H2D");
+        launch_gemv_add(s, n, ncols, Z, n, yd, x);
+        launch_spmv(s, L0.K, x, -1.0, b, 1.0, r);
+        beta = device_norm(ctx, r);
+        if (stop) {
+            if (!converged && hn == 0.0) converged = beta <= target;
+            break;
+        }
+    }
+    *iters_out = iters;
+    *relres_out = beta / r0;
+    return converged ? PHMG_OK : PHMG_ENOCONV;
+}
+
+template <typename F>
+phmg_status guarded(F&& f) {
+    try {
+        g_last_error.clear();
+        return f();
+    } catch (const Error& e) {
+        g_last_error = e.what();
+        return e.code;
+    } catch (const std::bad_alloc&) {
+        g_last_error = "host allocation failed";
+        return PHMG_ENOMEM;
+    } catch (const std::exception& e) {
+        g_last_error = e.what();
+        return PHMG_EINVAL;
+    }
+}
+
+void destroy_all(phmg_ctx ctx) {
+    for (auto& it : ctx->prof.pending) {
+        (void)hipEventDestroy(it.second.first);
+        (void)hipEventDestroy(it.second.second);
+    }
+    for (auto e : ctx->prof.pool) (void)hipEventDestroy(e);
+    for (void* p : ctx->allocs) (void)hipFree(p);
+    if (ctx->hhost) (void)hipHostFree(ctx->hhost);
+    delete ctx;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* phmg_last_error(void) { return g_last_error.c_str(); }
+
+phmg_status phmg_hierarchy_create(const phmg_hierarchy_desc* desc, const phmg_cycle_opts* opts, void* stream,
+                                  phmg_ctx* out) {
+    phmg_ctx ctx = nullptr;
+    phmg_status st = guarded([&]() -> phmg_status {
+        if (!desc || !opts || !out) fail(PHMG_EINVAL, "null argument");
+        *out = nullptr;
+        const int nl = desc->nlevels;
+        if (nl < 2) fail(PHMG_EINVAL, "nlevels must be >= 2");
+        if (!desc->K || !desc->P || !desc->patches) fail(PHMG_EINVAL, "null level array");
+        if (opts->nu_p < 0 || opts->nu_h < 0 || opts->n_v < 1 || opts->n_plevels < 0 || opts->n_plevels > nl - 1 ||
+            !std::isfinite(opts->omega))
+            fail(PHMG_EINVAL, "invalid cycle options");
+        // --- validation (host, before any device work)
+        for (int l = 0; l < nl; ++l) {
+            const phmg_csr& K = desc->K[l];
+            check_csr(K, lvl(l) + "K: ");
+            if (K.nrows != K.ncols || K.nrows < 1) fail(PHMG_EINVAL, lvl(l) + "K must be square and non-empty");
+        }
+        for (int l = 0; l + 1 < nl; ++l) {
+            const phmg_csr& P = desc->P[l];
+            check_csr(P, lvl(l) + "P: ");
+            if (P.nrows != desc->K[l].nrows || P.ncols != desc->K[l + 1].nrows)
+                fail(PHMG_EINVAL, lvl(l) + "P must be n_l x n_{l+1}");
+            const phmg_patches& pt = desc->patches[l];
+            if (pt.npatch < 1 || !pt.ptr || !pt.dofs) fail(PHMG_EINVAL, lvl(l) + "missing patches");
+            if (pt.ptr[0] != 0) fail(PHMG_EINVAL, lvl(l) + "patch ptr[0] != 0");
+            const int32_t n = desc->K[l].nrows;
+            for (int32_t i = 0; i < pt.npatch; ++i) {
+                const int64_t m = pt.ptr[i + 1] - pt.ptr[i];
+                if (m < 1 || m > PHMG_MAX_PATCH)
+                    fail(PHMG_EINVAL, lvl(l) + "patch " + std::to_string(i) + " size " + std::to_string(m) +
+                                          " outside [1, " + std::to_string(PHMG_MAX_PATCH) + "]");
+                for (int64_t t = pt.ptr[i]; t < pt.ptr[i + 1]; ++t) {
+                    const int32_t d = pt.dofs[t];
+                    if (d < 0 || d >= n) fail(PHMG_EINVAL, lvl(l) + "patch " + std::to_string(i) + " dof out of range");
+                    if (t > pt.ptr[i] && pt.dofs[t - 1] >= d)
+                        fail(PHMG_EINVAL, lvl(l) + "patch " + std::to_string(i) + " dofs not strictly ascending");
+                    if (pt.weight && !std::isfinite(pt.weight[t]))
+                        fail(PHMG_EINVAL, lvl(l) + "patch " + std::to_string(i) + " non-finite weight");
+                }
+            }
+            if (pt.ptr[pt.npatch] >= (int64_t)INT32_MAX) fail(PHMG_EINVAL, lvl(l) + "too many patch slots");
+        }
+        const int32_t nc = desc->K[nl - 1].nrows;
+        if (nc + 1 > PHMG_MAX_PATCH)
+            fail(PHMG_EINVAL, "coarsest level has " + std::to_string(nc) + " DoFs; the dense coarse solve supports at most " +
+                                  std::to_string(PHMG_MAX_PATCH - 1));
+        if (desc->coarse_null)
+            for (int32_t i = 0; i < nc; ++i)
+                if (!std::isfinite(desc->coarse_null[i])) fail(PHMG_EINVAL, "non-finite coarse_null");
+
+        ctx = new phmg_ctx_s();
+        ctx->stream = (hipStream_t)stream;
+        ctx->opts = *opts;
+        ctx->L.resize(nl);
+        for (int l = 0; l < nl; ++l) {
+            Level& L = ctx->L[l];
+            L.n = desc->K[l].nrows;
+            L.K = upload_csr(ctx, desc->K[l]);
+            L.r = dalloc<double>(ctx, L.n);
+            L.status = dalloc<int>(ctx, 1);
+            if (l > 0) {
+                L.b = dalloc<double>(ctx, L.n);
+                L.x = dalloc<double>(ctx, L.n);
+            }
+            if (l + 1 < nl) {
+                L.P = upload_csr(ctx, desc->P[l]);
+                L.R = upload_transpose(ctx, desc->P[l]);
+                const phmg_patches& pt = desc->patches[l];
+                L.npatch = pt.npatch;
+                L.sum_m = pt.ptr[pt.npatch];
+                std::vector<int64_t> foff(pt.npatch);
+                std::vector<int32_t> order(pt.npatch);
+                int64_t acc = 0;
+                int32_t mx = 0;
+                for (int32_t i = 0; i < pt.npatch; ++i) {
+                    const int64_t m = pt.ptr[i + 1] - pt.ptr[i];
+                    foff[i] = acc;
+                    acc += m * m;
+                    mx = std::max<int32_t>(mx, (int32_t)m);
+                    order[i] = i;
+                }
+                L.sum_m2 = acc;
+                L.max_m = mx;
+                std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) {
+                    return pt.ptr[a + 1] - pt.ptr[a] > pt.ptr[b + 1] - pt.ptr[b];
+                });
+                // DoF -> slots, ascending slot (= ascending patch id) per DoF
+                std::vector<int32_t> sptr(L.n + 1, 0), sslot(L.sum_m);
+                for (int64_t t = 0; t < L.sum_m; ++t) sptr[pt.dofs[t] + 1]++;
+                for (int32_t j = 0; j < L.n; ++j) sptr[j + 1] += sptr[j];
+                std::vector<int32_t> pos(sptr.begin(), sptr.end() - 1);
+                for (int64_t t = 0; t < L.sum_m; ++t) sslot[pos[pt.dofs[t]]++] = (int32_t)t;
+                L.pptr = upload(ctx, pt.ptr, pt.npatch + 1);
+                L.pdofs = upload(ctx, pt.dofs, L.sum_m);
+                L.pweight = pt.weight ? upload(ctx, pt.weight, L.sum_m) : nullptr;
+                L.foff = upload(ctx, foff.data(), pt.npatch);
+                L.order = upload(ctx, order.data(), pt.npatch);
+                L.sptr = upload(ctx, sptr.data(), L.n + 1);
+                L.sslot = upload(ctx, sslot.data(), L.sum_m);
+                L.Y = dalloc<double>(ctx, L.sum_m);
+            } else {
+                L.nb = desc->coarse_null ? L.n + 1 : L.n;
+                if (desc->coarse_null) L.cnull = upload(ctx, desc->coarse_null, L.n);
+            }
+        }
+        *out = ctx;
+        return PHMG_OK;
+    });
+    if (st != PHMG_OK && ctx) {
+        destroy_all(ctx);
+        if (out) *out = nullptr;
+    }
+    return st;
+}
+
+phmg_status phmg_hierarchy_destroy(phmg_ctx ctx) {
+    return guarded([&]() -> phmg_status {
+        if (!ctx) fail(PHMG_EINVAL, "null context");
+        (void)hipStreamSynchronize(ctx->stream);
+        destroy_all(ctx);
+        return PHMG_OK;
+    });
+}
+
+phmg_status phmg_set_precision(phmg_ctx ctx, int level, phmg_precision prec) {
+    return guarded([&]() -> phmg_status {
+        if (!ctx) fail(PHMG_EINVAL, "null context");
+        if (level < 0 || level >= (int)ctx->L.size() - 1) fail(PHMG_EINVAL, "level out of range");
+        if (prec != PHMG_PREC_F64 && prec != PHMG_PREC_F32 && prec != PHMG_PREC_BF16)
+            fail(PHMG_EINVAL, "unknown precision");
+        Level& L = ctx->L[level];
+        if (L.prec != prec) {
+            L.prec = prec;
+            L.ready = false;
+        }
+        return PHMG_OK;
+    });
+}
+
+phmg_status phmg_relax_setup(phmg_ctx ctx, int level) {
+    return guarded([&]() -> phmg_status {
+        if (!ctx) fail(PHMG_EINVAL, "null context");
+        const int nl = (int)ctx->L.size();
+        if (level >= nl) fail(PHMG_EINVAL, "level out of range");
+        if (level < 0) {
+            for (int l = 0; l < nl; ++l) setup_level(ctx, l);
+        } else {
+            setup_level(ctx, level);
+        }
+        return PHMG_OK;
+    });
+}
+
+phmg_status phmg_relax_apply(phmg_ctx ctx, int level, const double* b, double* x, int nu) {
+    return guarded([&]() -> phmg_status {
+        if (!ctx || !b || !x) fail(PHMG_EINVAL, "null argument");
+        if (level < 0 || level >= (int)ctx->L.size() - 1) fail(PHMG_EINVAL, "level out of range (coarsest has no patches)");
+        if (nu < 0) fail(PHMG_EINVAL, "nu < 0");
+        if (!ctx->L[level].ready) fail(PHMG_ESTATE, lvl(level) + "relax_setup has not been run");
+        relax(ctx, level, b, x, nu, false);
+        hipcheck(hipGetLastError(), "kernel launch");
+        return PHMG_OK;
+    });
+}
+
+phmg_status phmg_vcycle(phmg_ctx ctx, const double* b, double* x) {
+    return guarded([&]() -> phmg_status {
+        if (!ctx || !b || !x) fail(PHMG_EINVAL, "null argument");
+        require_ready(ctx);
+        vcycle(ctx, b, x);
+        hipcheck(hipGetLastError(), "kernel launch");
+        return PHMG_OK;
+    });
+}
+
+phmg_status phmg_fgmres_solve(phmg_ctx ctx, const double* b, double* x, double rtol, int restart, int maxit,
+                              int* iters, double* relres) {
+    return guarded([&]() -> phmg_status {
+        if (!ctx || !b || !x || !iters || !relres) fail(PHMG_EINVAL, "null argument");
+        if (restart < 1 || maxit < 1 || !(rtol >= 0.0)) fail(PHMG_EINVAL, "invalid rtol / restart / maxit");
+        require_ready(ctx);
+        const phmg_status st = fgmres(ctx, b, x, rtol, restart, maxit, iters, relres);
+        hipcheck(hipGetLastError(), "kernel launch");
+        if (st == PHMG_ENOCONV) g_last_error = "FGMRES reached maxit without converging";
+        return st;
+    });
+}
+
+phmg_status phmg_residual(phmg_ctx ctx, int level, const double* b, const double* x, double* r) {
+    return guarded([&]() -> phmg_status {
+        if (!ctx || !b || !x || !r) fail(PHMG_EINVAL, "null argument");
+        if (level < 0 || level >= (int)ctx->L.size()) fail(PHMG_EINVAL, "level out of range");
+        launch_spmv(ctx->stream, ctx->L[level].K, x, -1.0, b, 1.0, r);
+        hipcheck(hipGetLastError(), "kernel launch");
+        return PHMG_OK;
+    });
+}
+
+phmg_status phmg_get_level_info(phmg_ctx ctx, int level, phmg_level_info* info) {
+    return guarded([&]() -> phmg_status {
+        if (!ctx || !info) fail(PHMG_EINVAL, "null argument");
+        if (level < 0 || level >= (int)ctx->L.size()) fail(PHMG_EINVAL, "level out of range");
+        const Level& L = ctx->L[level];
+        info->n = L.n;
+        info->npatch = L.npatch;
+        info->max_m = L.max_m;
+        info->precision = L.prec;
+        info->nnz = L.K.nnz;
+        info->sum_m = L.sum_m;
+        info->sum_m2 = L.sum_m2;
+        return PHMG_OK;
+    });
+}
+
+phmg_status phmg_profile_enable(phmg_ctx ctx, int on) {
+    return guarded([&]() -> phmg_status {
+        if (!ctx) fail(PHMG_EINVAL, "null context");
+        ctx->prof.on = on != 0;
+        return PHMG_OK;
+    });
+}
+
+phmg_status phmg_profile_read(phmg_ctx ctx, int kernel, double* total_ms, int64_t* launches, int reset) {
+    return guarded([&]() -> phmg_status {
+        if (!ctx || !total_ms || !launches) fail(PHMG_EINVAL, "null argument");
+        if (kernel < 0 || kernel >= PHMG_K_COUNT) fail(PHMG_EINVAL, "unknown kernel id");
+        drain_profile(ctx);
+        *total_ms = ctx->prof.ms[kernel];
+        *launches = ctx->prof.count[kernel];
+        if (reset) {
+            for (int k = 0; k < PHMG_K_COUNT; ++k) {
+                ctx->prof.ms[k] = 0.0;
+                ctx->prof.count[k] = 0;
+            }
+        }
+        return PHMG_OK;
+    });
+}
+
+}  // extern "C"

@@ -1,0 +1,117 @@
+// Internal declarations of the gfx950 phMG library: device-side level data,
+// the context, and the kernel launchers shared by the translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/phmg.h"
+
+namespace phmg {
+
+constexpr int kBlock = 256;          // threads per workgroup (4 wavefronts of 64)
+constexpr int kWave = 64;
+constexpr int kPanel = 16;           // Gauss-Jordan panel width = MFMA f64 16x16x4 tile edge
+constexpr int kRedBlocks = 512;      // fixed grid of the deterministic reductions
+
+struct DevCsr {
+    int32_t nrows = 0, ncols = 0;
+    int64_t nnz = 0;
+    int32_t* rowptr = nullptr;
+    int32_t* col = nullptr;
+    double* val = nullptr;
+    int group = 8;                   // lanes per row in the SpMV
+};
+
+struct Level {
+    int32_t n = 0;
+    DevCsr K;
+    DevCsr P;                        // prolongation from level+1 into this level (n x n_{l+1})
+    DevCsr R;                        // restriction R = P^T (n_{l+1} x n)
+
+    // Vanka-star patches (absent on the coarsest level)
+    int32_t npatch = 0;
+    int32_t max_m = 0;
+    int64_t sum_m = 0, sum_m2 = 0;
+    int64_t* pptr = nullptr;         // npatch + 1
+    int32_t* pdofs = nullptr;        // sum_m
+    double* pweight = nullptr;       // sum_m or null (W_i = I)
+    int64_t* foff = nullptr;         // offset of patch i's m_i x m_i block (elements)
+    int32_t* order = nullptr;        // launch order: patches by decreasing size
+    int32_t* sptr = nullptr;         // DoF -> slot map for the scatter (n + 1)
+    int32_t* sslot = nullptr;        // sum_m slot indices, ascending patch id per DoF
+    double* Y = nullptr;             // sum_m staging of the patch solutions
+    void* factors = nullptr;         // explicit patch inverses, column-major, precision `prec`
+    double* work64 = nullptr;        // float64 set-up buffer when prec != F64
+    int prec = PHMG_PREC_F64;
+
+    // coarsest level: dense inverse of the (bordered) matrix, row-major
+    double* cinv = nullptr;
+    double* cnull = nullptr;
+    int32_t nb = 0;                  // n or n + 1
+
+    // V-cycle work vectors
+    double* r = nullptr;
+    double* b = nullptr;
+    double* x = nullptr;
+
+    int* status = nullptr;           // device: smallest singular patch id (INT32_MAX = none)
+    bool ready = false;
+};
+
+struct Profile {
+    bool on = false;
+    double ms[PHMG_K_COUNT] = {0};
+    int64_t count[PHMG_K_COUNT] = {0};
+    std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> pending;
+    std::vector<hipEvent_t> pool;
+};
+
+}  // namespace phmg
+
+struct phmg_ctx_s {
+    hipStream_t stream = nullptr;
+    std::vector<phmg::Level> L;
+    phmg_cycle_opts opts{};
+    std::vector<void*> allocs;
+    // FGMRES work space (level 0)
+    int restart_cap = 0;
+    double* V = nullptr;
+    double* Z = nullptr;
+    double* w = nullptr;
+    double* rvec = nullptr;
+    double* partial = nullptr;
+    double* hdev = nullptr;          // device scalars: h (restart+1) and norm
+    double* hhost = nullptr;         // pinned host mirror
+    phmg::Profile prof;
+};
+
+namespace phmg {
+
+// ---- launchers (kernels.hip) ------------------------------------------------
+void launch_fill(hipStream_t s, int64_t n, double* x, double v);
+void launch_fill_i32(hipStream_t s, int64_t n, int32_t* x, int32_t v);
+// y = alpha * A x + beta * z   (z may be null, or alias y)
+void launch_spmv(hipStream_t s, const DevCsr& A, const double* x, double alpha, const double* z, double beta,
+                 double* y);
+void launch_extract(hipStream_t s, const Level& L, double* out);
+void launch_gj_invert(hipStream_t s, int npatch, const int64_t* pptr, const int64_t* foff, const int32_t* order,
+                      double* A, int max_m, int* status);
+void launch_convert(hipStream_t s, int64_t n, const double* src, void* dst, int prec);
+void launch_patch_apply(hipStream_t s, const Level& L, const double* r);
+void launch_scatter(hipStream_t s, const Level& L, double omega, double* x, bool x_zero);
+void launch_coarse_build(hipStream_t s, const Level& L, double* dense);
+void launch_transpose(hipStream_t s, int n, const double* src, double* dst);
+void launch_coarse_solve(hipStream_t s, const Level& L, const double* b, double* x);
+// FGMRES helpers
+void launch_multidot(hipStream_t s, int64_t n, int ncol, const double* V, int64_t ldv, const double* w,
+                     double* partial, double* out, bool accumulate);
+void launch_gemv_sub(hipStream_t s, int64_t n, int ncol, const double* V, int64_t ldv, const double* h, double* w);
+void launch_gemv_add(hipStream_t s, int64_t n, int ncol, const double* Z, int64_t ldz, const double* y, double* x);
+void launch_scale_copy(hipStream_t s, int64_t n, const double* src, double denom, double* dst);  // dst = src / denom
+void launch_copy(hipStream_t s, int64_t n, const double* src, double* dst);
+
+}  // namespace phmg

@@ -1,0 +1,174 @@
+"""GPU path (HIP kernels through the C ABI) against the oracle, element by element.
+
+Both sides start from the same seeded mesh hierarchy; the GPU side takes the
+product front-end's arrays, the oracle assembles its own (the two are shown
+identical in tests/test_frontend.py).  Tolerances:
+
+* one relaxation sweep / one V-cycle: the GPU applies explicit patch inverses
+  (Gauss-Jordan), the oracle LU solves; both are backward stable, so the
+  difference per patch is a few kappa(K_i) eps |y_i| with kappa(K_i) up to
+  ~1e8 on P4 patches (pressure / velocity scale gap).  The sweep output is
+  compared to 1e-9 relative (max norm), observed ~1e-13 .. 1e-11.
+* FGMRES: identical iteration counts and solutions equal to 1e-10 relative
+  after removing the pressure mean (the constant-pressure kernel).
+"""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+pytestmark = pytest.mark.gpu
+
+from oracle import fgmres as ofgmres  # noqa: E402
+from oracle import multigrid as omg  # noqa: E402
+from oracle import problems as oproblems  # noqa: E402
+from oracle import relax as orelax  # noqa: E402
+from paper_2407_07253_amd import frontend  # noqa: E402
+
+_CACHE = {}
+
+
+def _pair(name):
+    if name not in _CACHE:
+        from paper_2407_07253_amd._lib import Hierarchy
+        fh = frontend.build_hierarchy(name)
+        H = Hierarchy.from_frontend(fh)
+        H.setup()
+        ol, od, oopts, ob = oproblems.build(name)
+        omg.setup(ol)
+        _CACHE[name] = (fh, H, ol, od, oopts, ob)
+    return _CACHE[name]
+
+
+def _dev(a):
+    return torch.tensor(np.asarray(a, dtype=np.float64), device="cuda")
+
+
+def _host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+def _rel(a, b):
+    return float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-300))
+
+
+def _normalise(x, nfu):
+    y = np.array(x, copy=True)
+    y[2 * nfu:] -= y[2 * nfu:].mean()
+    return y
+
+
+NAMES = ["cfg1", "cfg2_r1", "sv_small"]
+
+
+@pytest.mark.parametrize("name", NAMES)
+@pytest.mark.parametrize("nu", [1, 2])
+def test_relax_apply_matches_oracle(name, nu):
+    fh, H, ol, od, oopts, ob = _pair(name)
+    rng = np.random.default_rng(100 + nu)
+    for l in range(len(ol) - 1):
+        n = ol[l].n
+        b, x = rng.standard_normal(n), rng.standard_normal(n)
+        xg = _dev(x)
+        H.relax_apply(l, _dev(b), xg, nu)
+        got = _host(xg)
+        L = ol[l]
+        ref = orelax.asm_sweeps(L.K, L.patches, L.factors, L.weights, oopts.omega, b, x, nu)
+        err = _rel(got, ref)
+        print(f"{name} level {l} nu={nu}: rel err {err:.2e}")
+        assert err <= 1e-9, (l, err)
+
+
+@pytest.mark.parametrize("name", NAMES)
+def test_vcycle_matches_oracle(name):
+    fh, H, ol, od, oopts, ob = _pair(name)
+    rng = np.random.default_rng(7)
+    b = rng.standard_normal(ol[0].n)
+    z = _dev(np.full(ol[0].n, np.nan))          # content on entry is ignored
+    H.vcycle(_dev(b), z)
+    got = _host(z)
+    ref = omg.vcycle(ol, oopts, b)
+    err = _rel(got, ref)
+    print(f"{name} vcycle rel err {err:.2e}")
+    assert err <= 1e-9
+
+
+@pytest.mark.parametrize("name", NAMES)
+def test_fgmres_iterations_and_solution_match_oracle(name):
+    fh, H, ol, od, oopts, ob = _pair(name)
+    b = fh.b[0]
+    x = _dev(np.zeros_like(b))
+    iters, relres, conv = H.fgmres(_dev(b), x, rtol=1e-8, restart=30, maxit=1000)
+    got = _host(x)
+    K = ol[0].K
+    res = ofgmres.fgmres(lambda v: K @ v, lambda v: omg.vcycle(ol, oopts, v), ob, rtol=1e-8, restart=30, maxit=1000)
+    nfu = od[0].nfu
+    err = np.linalg.norm(_normalise(got, nfu) - _normalise(res.x, nfu)) / np.linalg.norm(_normalise(res.x, nfu))
+    print(f"{name}: GPU iters {iters} relres {relres:.3e}; oracle iters {res.iters} relres {res.relres:.3e}; "
+          f"solution rel err {err:.2e}")
+    assert conv and res.converged
+    assert iters == res.iters
+    assert err <= 1e-10
+    true_rel = np.linalg.norm(ob - K @ got) / np.linalg.norm(ob)
+    assert true_rel <= 1e-8 * 1.05
+
+
+def test_relax_nu_zero_leaves_x_unchanged():
+    fh, H, ol, od, oopts, ob = _pair("cfg1")
+    x = np.random.default_rng(3).standard_normal(ol[0].n)
+    xg = _dev(x)
+    H.relax_apply(0, _dev(ob), xg, 0)
+    assert np.array_equal(_host(xg), x)
+
+
+def test_runs_are_bitwise_reproducible():
+    fh, H, ol, od, oopts, ob = _pair("cfg2_r1")
+    b = _dev(fh.b[0])
+    outs = []
+    for _ in range(2):
+        x = _dev(np.zeros(ol[0].n))
+        it, rr, conv = H.fgmres(b, x, rtol=1e-8)
+        outs.append((it, _host(x)))
+    assert outs[0][0] == outs[1][0]
+    assert np.array_equal(outs[0][1], outs[1][1])
+
+
+def test_apply_before_setup_is_a_state_error():
+    from paper_2407_07253_amd._lib import Hierarchy, PhmgError, PHMG_ESTATE
+    fh = frontend.build_hierarchy("cfg1")
+    H = Hierarchy.from_frontend(fh)
+    b = _dev(fh.b[0])
+    x = _dev(np.zeros_like(fh.b[0]))
+    with pytest.raises(PhmgError) as e:
+        H.relax_apply(0, b, x, 1)
+    assert e.value.status == PHMG_ESTATE
+    with pytest.raises(PhmgError):
+        H.fgmres(b, x)
+    H.close()
+
+
+def test_singular_patch_is_reported_with_its_id():
+    """A DoF whose row and column are zero makes every patch containing it singular."""
+    from paper_2407_07253_amd._lib import Hierarchy, PhmgError, PHMG_ESINGULAR
+    fh = frontend.build_hierarchy("cfg1")
+    L0 = fh.levels[0]
+    K = L0.K.to_scipy().tolil()
+    j = 40
+    K[j, :] = 0.0
+    K[:, j] = 0.0
+    K = K.tocsr()
+    K.sort_indices()
+    levels = fh.levels
+    Ks = [(K.indptr, K.indices, K.data, K.shape[0], K.shape[1])] + \
+         [(l.K.rowptr, l.K.col, l.K.val, l.K.nrows, l.K.ncols) for l in levels[1:]]
+    Ps = [(l.P.rowptr, l.P.col, l.P.val, l.P.nrows, l.P.ncols) for l in levels[1:]]
+    pts = [(l.patch_ptr, l.patch_dofs, l.patch_weight) for l in levels[:-1]]
+    H = Hierarchy(Ks, Ps, pts, levels[-1].null_vector(), **fh.opts)
+    with pytest.raises(PhmgError) as e:
+        H.setup(0)
+    assert e.value.status == PHMG_ESINGULAR
+    first = min(i for i in range(len(L0.patch_ptr) - 1)
+                if j in set(L0.patch_dofs[L0.patch_ptr[i]:L0.patch_ptr[i + 1]]))
+    assert f"patch {first} is singular" in str(e.value)
+    H.close()

@@ -119,6 +119,10 @@ __global__ __launch_bounds__(kBlock) void extract_kernel(const int64_t* __restri
 // update  A[:, R] += (Q - E) A_old[k0:k0+16, R]  on MFMA f64 16x16x4 tiles,
 // where Q is the eliminated panel and E the identity rows of the panel.  The
 // pivoting is undone at the end by column swaps in reverse order.
+//
+// MFMA f64 16x16x4 lane layout (lane l, accumulator element v):
+//   A operand A[l % 16][l / 16], B operand B[l / 16][l % 16],
+//   C/D element D[l / 16 + 4 v][l % 16].
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(kBlock) void gj_kernel(const int64_t* __restrict__ pptr,
                                                     const int64_t* __restrict__ foff,
@@ -243,7 +247,7 @@ __global__ __launch_bounds__(kBlock) void gj_kernel(const int64_t* __restrict__ 
                     d4 acc;
 #pragma unroll
                     for (int v = 0; v < 4; ++v) {
-                        const int i = ib * 16 + lk * 4 + v;
+                        const int i = ib * 16 + lk + 4 * v;
                         acc[v] = (jv && i < m) ? A[i + (int64_t)j * m] : 0.0;
                     }
 #pragma unroll
@@ -258,7 +262,7 @@ __global__ __launch_bounds__(kBlock) void gj_kernel(const int64_t* __restrict__ 
                     }
 #pragma unroll
                     for (int v = 0; v < 4; ++v) {
-                        const int i = ib * 16 + lk * 4 + v;
+                        const int i = ib * 16 + lk + 4 * v;
                         if (jv && i < m) A[i + (int64_t)j * m] = acc[v];
                     }
                 }
@@ -521,6 +525,8 @@ void launch_gj_invert(hipStream_t s, int npatch, const int64_t* pptr, const int6
                       double* A, int max_m, int* status) {
     if (npatch <= 0) return;
     const size_t lds = gj_lds_bytes(max_m);
+    if (lds > 64 * 1024)
+        (void)hipFuncSetAttribute((const void*)gj_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     hipLaunchKernelGGL(gj_kernel, dim3(npatch), dim3(kBlock), lds, s, pptr, foff, order, A, max_m, status);
 }
 

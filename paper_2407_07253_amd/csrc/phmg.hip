@@ -252,6 +252,7 @@ void setup_level(phmg_ctx ctx, int l) {
         {
             Timed t(ctx, PHMG_K_FACTOR);
             launch_gj_invert(s, 1, cptr, coff, nullptr, dense, L.nb, L.status);
+            hipcheck(hipGetLastError(), "coarse factorisation launch");
         }
         if (!L.cinv) L.cinv = dalloc<double>(ctx, (int64_t)L.nb * L.nb);
         launch_transpose(s, L.nb, dense, L.cinv);
@@ -270,10 +271,12 @@ void setup_level(phmg_ctx ctx, int l) {
     {
         Timed t(ctx, PHMG_K_EXTRACT);
         launch_extract(s, L, f64);
+        hipcheck(hipGetLastError(), "extract launch");
     }
     {
         Timed t(ctx, PHMG_K_FACTOR);
         launch_gj_invert(s, L.npatch, L.pptr, L.foff, L.order, f64, L.max_m, L.status);
+        hipcheck(hipGetLastError(), "patch factorisation launch");
     }
     if (L.prec == PHMG_PREC_F64) {
         L.factors = f64;

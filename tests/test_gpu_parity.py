@@ -8,7 +8,7 @@ identical in tests/test_frontend.py).  Tolerances:
   (Gauss-Jordan), the oracle LU solves; both are backward stable, so the
   difference per patch is a few kappa(K_i) eps |y_i| with kappa(K_i) up to
   ~1e8 on P4 patches (pressure / velocity scale gap).  The sweep output is
-  compared to 1e-9 relative (max norm), observed ~1e-13 .. 1e-11.
+  compared to 1e-11 relative (max norm); observed 3e-16 .. 1.2e-14 on MI355X.
 * FGMRES: identical iteration counts and solutions equal to 1e-10 relative
   after removing the pressure mean (the constant-pressure kernel).
 """
@@ -77,7 +77,7 @@ def test_relax_apply_matches_oracle(name, nu):
         ref = orelax.asm_sweeps(L.K, L.patches, L.factors, L.weights, oopts.omega, b, x, nu)
         err = _rel(got, ref)
         print(f"{name} level {l} nu={nu}: rel err {err:.2e}")
-        assert err <= 1e-9, (l, err)
+        assert err <= 1e-11, (l, err)
 
 
 @pytest.mark.parametrize("name", NAMES)
@@ -91,7 +91,7 @@ def test_vcycle_matches_oracle(name):
     ref = omg.vcycle(ol, oopts, b)
     err = _rel(got, ref)
     print(f"{name} vcycle rel err {err:.2e}")
-    assert err <= 1e-9
+    assert err <= 1e-11
 
 
 @pytest.mark.parametrize("name", NAMES)

@@ -77,11 +77,21 @@ typedef struct {
  * levels 0 .. n_plevels-1 are p-levels relaxed with nu_p sweeps and coarsened
  * by defect correction; the hMG part starting at level n_plevels is applied
  * n_v times (stationary iterations from zero); h-levels use nu_h sweeps.
- * Pre- and post-smoothing use the same count.  omega damps every sweep. */
+ * Pre- and post-smoothing use the same count.
+ * smoother = PHMG_SMOOTHER_RICHARDSON: each sweep is x += omega M^{-1}(b - K x).
+ * smoother = PHMG_SMOOTHER_CHEBYSHEV (the paper's experiments, Section 4):
+ * nu steps of Chebyshev acceleration of M^{-1} over [cheb_lo, cheb_hi] *
+ * lambda, where lambda estimates the largest eigenvalue of M^{-1} K by
+ * eig_iters power iterations at set-up (start vector v_j = 1 + sin(j)/2). */
 typedef struct {
     int32_t nu_p, nu_h, n_v, n_plevels;
     double omega;
+    int32_t smoother, eig_iters;
+    double cheb_lo, cheb_hi;
 } phmg_cycle_opts;
+
+#define PHMG_SMOOTHER_RICHARDSON 0
+#define PHMG_SMOOTHER_CHEBYSHEV 1
 
 /* Patch-factor storage precision of a level (the apply accumulates in the
  * precision of the factors, the residual and the scatter stay float64). */
@@ -135,19 +145,22 @@ phmg_status phmg_fgmres_solve(phmg_ctx ctx, const double* b, double* x, double r
 /* Residual r = b - K_l x on a level (device pointers, asynchronous). */
 phmg_status phmg_residual(phmg_ctx ctx, int level, const double* b, const double* x, double* r);
 
-/* Per-level sizes: n, nnz(K), npatch, sum m, sum m^2, max m. */
+/* Per-level sizes: n, nnz(K), npatch, sum m, sum m^2, max m, and the
+ * Chebyshev eigenvalue estimate (0 before set-up or for Richardson). */
 typedef struct {
     int32_t n, npatch, max_m, precision;
     int64_t nnz, sum_m, sum_m2;
+    double lambda_max;
 } phmg_level_info;
 phmg_status phmg_get_level_info(phmg_ctx ctx, int level, phmg_level_info* info);
 
-/* Optional per-kernel timing with HIP events recorded on the context stream
- * around every launch of the kernels listed below (off by default; when on,
- * each timed launch is bracketed by two events, which adds host overhead but
- * does not change results).  phmg_profile_read returns the summed elapsed
- * milliseconds and the number of launches since the last reset (it
- * synchronises the stream). */
+/* Optional per-kernel, per-level timing with HIP events recorded on the
+ * context stream around every launch of the selected kernels (off by
+ * default).  kernel_mask has bit k set for kernel id k (0 = off).  Each timed
+ * launch is bracketed by two events; results are unchanged.
+ * phmg_profile_read synchronises the stream and returns the summed elapsed
+ * milliseconds and the number of launches of one kernel on one level
+ * (level = -1: all levels) since the last phmg_profile_reset. */
 typedef enum {
     PHMG_K_PATCH_APPLY = 0,   /* batched patch solve y_i = K_i^{-1} r[S_i]           */
     PHMG_K_SCATTER = 1,       /* weighted scatter-add x += omega sum R_i^T W_i y_i   */
@@ -156,8 +169,10 @@ typedef enum {
     PHMG_K_FACTOR = 4,        /* patch Gauss-Jordan inversion                         */
     PHMG_K_COUNT = 5
 } phmg_kernel_id;
-phmg_status phmg_profile_enable(phmg_ctx ctx, int on);
-phmg_status phmg_profile_read(phmg_ctx ctx, int kernel, double* total_ms, int64_t* launches, int reset);
+#define PHMG_MAX_LEVELS 16
+phmg_status phmg_profile_enable(phmg_ctx ctx, unsigned kernel_mask);
+phmg_status phmg_profile_read(phmg_ctx ctx, int kernel, int level, double* total_ms, int64_t* launches);
+phmg_status phmg_profile_reset(phmg_ctx ctx);
 
 phmg_status phmg_hierarchy_destroy(phmg_ctx ctx);
 

@@ -14,6 +14,8 @@ Readings where the paper is silent:
     every level; every cycle starts from x = 0.
   * (I - G_1) K_1^{-1} applied to b_1 is n_V stationary hMG iterations from
     e = 0, each a V-cycle started from the current e.
+  * The smoother is damped Richardson (omega) or, as in the paper's
+    experiments, Chebyshev acceleration over [cheb_lo, cheb_hi] * lambda_max.
   * With all of the boundary Dirichlet the coarsest matrix is singular with
     kernel z (constant pressure); the coarse solve is the bordered system
     [K_c z; z^T 0][x; lam] = [b; 0], factored once by the oracle's LU.
@@ -32,7 +34,7 @@ import numpy as np
 import scipy.sparse as sp
 
 from .lu import lu_factor, lu_solve, lu_solve_transposed
-from .relax import asm_sweeps, setup_patches
+from .relax import asm_sweeps, chebyshev_sweeps, estimate_lambda_max, setup_patches
 
 
 @dataclass
@@ -44,6 +46,7 @@ class Level:
     factors: Optional[list] = None
     coarse: Optional[tuple] = None       # (LU, piv, bordered?) on the coarsest level
     null: Optional[np.ndarray] = None    # kernel vector on the coarsest level
+    lmax: Optional[float] = None         # estimate of the largest eigenvalue of M^{-1} K (Chebyshev)
 
     @property
     def n(self) -> int:
@@ -56,13 +59,20 @@ class CycleOpts:
     nu_h: int = 2
     n_v: int = 1
     n_plevels: int = 1       # number of levels relaxed with nu_p (0 = pure hMG)
-    omega: float = 0.5
+    omega: float = 0.5       # Richardson damping
+    smoother: str = "richardson"   # or "chebyshev"
+    cheb_lo: float = 0.1     # Chebyshev interval [cheb_lo, cheb_hi] * lambda_max estimate
+    cheb_hi: float = 1.1
+    eig_iters: int = 20      # power iterations for the lambda_max estimate
 
 
-def setup(levels: List[Level]) -> None:
-    """Patch LU on every non-coarsest level; bordered dense LU on the coarsest."""
+def setup(levels: List[Level], opts: Optional[CycleOpts] = None) -> None:
+    """Patch LU on every non-coarsest level (and the lambda_max estimate for
+    Chebyshev smoothing); bordered dense LU on the coarsest."""
     for L in levels[:-1]:
         L.factors = setup_patches(L.K, L.patches)
+        if opts is not None and opts.smoother == "chebyshev":
+            L.lmax = estimate_lambda_max(L.K, L.patches, L.factors, L.weights, opts.eig_iters)
     C = levels[-1]
     Kc = C.K.toarray()
     if C.null is not None:
@@ -87,6 +97,11 @@ def coarse_solve(C: Level, b: np.ndarray, transpose: bool = False) -> np.ndarray
 
 
 def _relax(L: Level, opts: CycleOpts, b, x, nu, transpose):
+    if opts.smoother == "chebyshev":
+        # the transposed cycle keeps the forward interval, so it is the exact adjoint
+        lam = L.lmax
+        return chebyshev_sweeps(L.K, L.patches, L.factors, L.weights, opts.cheb_lo * lam, opts.cheb_hi * lam,
+                                b, x, nu, transpose)
     return asm_sweeps(L.K, L.patches, L.factors, L.weights, opts.omega, b, x, nu, transpose)
 
 

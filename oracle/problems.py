@@ -9,11 +9,15 @@ coarsened through Taylor-Hood levels (Section 3.2).
 
 Workloads (synthetic stand-ins for the paper's cavity / step problems):
   * cfg1: TH P2/P1 on the structured 8x8 mesh, hMG with the 4x4 mesh as the
-    coarse direct solve; nu = 2, omega = 0.5.
+    coarse direct solve; nu = 2 damped Richardson sweeps with omega = 0.5 and
+    the partition-of-unity weights W_i = diag(1/c_j).
   * cfg2: TH P4/P3 on a Delaunay mesh refined 3 times -> TH P2/P1 on the same
     mesh -> P2/P1 on the 3 coarser meshes (direct solve on the base mesh).
   * cfg4: SV P4/P3disc on the Alfeld split of a jittered 16x16 mesh refined
     twice -> TH P2/P1 on the Alfeld mesh -> TH P2/P1 on the 3 macro meshes.
+  * cfg2 and cfg4 name no smoother; they use the paper's: nu = 2 Chebyshev
+    iterations over the basic additive Schwarz operator (W_i = I), interval
+    [0.1, 1.1] * lambda_max, lambda_max from 20 power iterations.
 """
 from __future__ import annotations
 
@@ -32,18 +36,19 @@ SEEDS = {"cfg1": 1, "cfg2": 2, "cfg3": 3, "cfg4": 4}
 
 def level_specs(name: str, k: int = None) -> Tuple[List[Tuple[int, int, str]], CycleOpts]:
     """(mesh index from the finest, order, kind) per level, and cycle options."""
+    cheb = dict(smoother="chebyshev", cheb_lo=0.1, cheb_hi=1.1, eig_iters=20)
     if name in ("cfg1", "tiny2", "tiny4"):
         return [(0, 2, "TH"), (1, 2, "TH")], CycleOpts(nu_p=2, nu_h=2, n_v=1, n_plevels=0, omega=0.5)
     if name.startswith("cfg2"):
         nref = {"cfg2": 3, "cfg2_r2": 2, "cfg2_r1": 1}[name]
         kk = 4 if k is None else k
         specs = [(0, kk, "TH")] + [(i, 2, "TH") for i in range(nref + 1)]
-        return specs, CycleOpts(nu_p=2, nu_h=2, n_v=1, n_plevels=1, omega=0.5)
+        return specs, CycleOpts(nu_p=2, nu_h=2, n_v=1, n_plevels=1, omega=0.5, **cheb)
     if name in ("cfg4", "cfg4_r0", "sv_small"):
         nmac = {"cfg4": 3, "cfg4_r0": 1, "sv_small": 2}[name]
         kk = 4 if k is None else k
         specs = [(0, kk, "SV"), (0, 2, "TH")] + [(i, 2, "TH") for i in range(1, nmac + 1)]
-        return specs, CycleOpts(nu_p=2, nu_h=2, n_v=1, n_plevels=1, omega=0.5)
+        return specs, CycleOpts(nu_p=2, nu_h=2, n_v=1, n_plevels=1, omega=0.5, **cheb)
     raise KeyError(name)
 
 
@@ -61,12 +66,14 @@ def gradual_schedule(k: int) -> List[int]:
     raise ValueError(k)
 
 
-def build(name: str, k: int = None, weights: str = "pou", with_rhs: bool = True,
+def build(name: str, k: int = None, weights: str = None, with_rhs: bool = True,
           specs=None, opts=None):
     """Assemble every level, its patches and the transfers.  Returns (levels, discs, opts, b)."""
     meshes = synth.config_mesh_hierarchy(name)[::-1]          # finest first
     if specs is None:
         specs, opts = level_specs(name, k)
+    if weights is None:
+        weights = "none" if opts.smoother == "chebyshev" else "pou"
     seed = SEEDS.get(name.split("_")[0], 1)
     A = synth.mms_amplitude(seed)
     f = (lambda x, y: synth.mms_forcing(x, y, A)) if with_rhs else None
@@ -89,4 +96,11 @@ def build(name: str, k: int = None, weights: str = "pou", with_rhs: bool = True,
         levels.append(L)
     levels[-1].null = discs[-1].null_vector()
     b = discs[0].b if with_rhs else None
+    return levels, discs, opts, b
+
+
+def build_and_setup(name: str, **kw):
+    levels, discs, opts, b = build(name, **kw)
+    from .multigrid import setup
+    setup(levels, opts)
     return levels, discs, opts, b

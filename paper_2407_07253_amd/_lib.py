@@ -47,7 +47,11 @@ class PatchesT(C.Structure):
 
 class OptsT(C.Structure):
     _fields_ = [("nu_p", C.c_int32), ("nu_h", C.c_int32), ("n_v", C.c_int32), ("n_plevels", C.c_int32),
-                ("omega", C.c_double)]
+                ("omega", C.c_double), ("smoother", C.c_int32), ("eig_iters", C.c_int32),
+                ("cheb_lo", C.c_double), ("cheb_hi", C.c_double)]
+
+
+SMOOTHERS = {"richardson": 0, "chebyshev": 1}
 
 
 class DescT(C.Structure):
@@ -57,7 +61,7 @@ class DescT(C.Structure):
 
 class LevelInfoT(C.Structure):
     _fields_ = [("n", C.c_int32), ("npatch", C.c_int32), ("max_m", C.c_int32), ("precision", C.c_int32),
-                ("nnz", C.c_int64), ("sum_m", C.c_int64), ("sum_m2", C.c_int64)]
+                ("nnz", C.c_int64), ("sum_m", C.c_int64), ("sum_m2", C.c_int64), ("lambda_max", C.c_double)]
 
 
 def _sig(name, res, args):
@@ -77,13 +81,14 @@ _fgmres = _sig("phmg_fgmres_solve", C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p
                                               C.POINTER(C.c_int), C.POINTER(C.c_double)])
 _residual = _sig("phmg_residual", C.c_int, [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p])
 _info = _sig("phmg_get_level_info", C.c_int, [C.c_void_p, C.c_int, C.POINTER(LevelInfoT)])
-_prof_on = _sig("phmg_profile_enable", C.c_int, [C.c_void_p, C.c_int])
-_prof_read = _sig("phmg_profile_read", C.c_int, [C.c_void_p, C.c_int, C.POINTER(C.c_double), C.POINTER(C.c_int64), C.c_int])
+_prof_on = _sig("phmg_profile_enable", C.c_int, [C.c_void_p, C.c_uint])
+_prof_read = _sig("phmg_profile_read", C.c_int, [C.c_void_p, C.c_int, C.c_int, C.POINTER(C.c_double), C.POINTER(C.c_int64)])
+_prof_reset = _sig("phmg_profile_reset", C.c_int, [C.c_void_p])
 _last_error = _sig("phmg_last_error", C.c_char_p, [])
 
 EXPORTED = ["phmg_hierarchy_create", "phmg_hierarchy_destroy", "phmg_relax_setup", "phmg_set_precision",
             "phmg_relax_apply", "phmg_vcycle", "phmg_fgmres_solve", "phmg_residual", "phmg_get_level_info",
-            "phmg_profile_enable", "phmg_profile_read", "phmg_last_error"]
+            "phmg_profile_enable", "phmg_profile_read", "phmg_profile_reset", "phmg_last_error"]
 
 
 def last_error() -> str:
@@ -114,6 +119,7 @@ class Hierarchy:
 
     def __init__(self, K: Sequence, P: Sequence, patches: Sequence, coarse_null: Optional[np.ndarray],
                  nu_p: int = 2, nu_h: int = 2, n_v: int = 1, n_plevels: int = 1, omega: float = 0.5,
+                 smoother: str = "richardson", cheb_lo: float = 0.1, cheb_hi: float = 1.1, eig_iters: int = 20,
                  stream: Optional[int] = None):
         """K: list of (rowptr, col, val, nrows, ncols); P: list of the same (len-1);
         patches: list of (ptr int64, dofs int32, weight float64 or None)."""
@@ -141,7 +147,7 @@ class Hierarchy:
         Pt = (PatchesT * max(nl - 1, 1))(*pts)
         z = None if coarse_null is None else np.ascontiguousarray(coarse_null, dtype=np.float64)
         desc = DescT(nl, Ks, Ps, Pt, _ptr(z))
-        opts = OptsT(nu_p, nu_h, n_v, n_plevels, omega)
+        opts = OptsT(nu_p, nu_h, n_v, n_plevels, omega, SMOOTHERS[smoother], eig_iters, cheb_lo, cheb_hi)
         if stream is None:
             stream = torch.cuda.current_stream().cuda_stream
         h = C.c_void_p()
@@ -149,12 +155,17 @@ class Hierarchy:
         self._h = h
         self.nlevels = nl
         self.n = [int(k[3]) for k in K]
-        self.opts = dict(nu_p=nu_p, nu_h=nu_h, n_v=n_v, n_plevels=n_plevels, omega=omega)
+        self.opts = dict(nu_p=nu_p, nu_h=nu_h, n_v=n_v, n_plevels=n_plevels, omega=omega, smoother=smoother,
+                         cheb_lo=cheb_lo, cheb_hi=cheb_hi, eig_iters=eig_iters)
 
     @classmethod
-    def from_frontend(cls, fh, weights: bool = True, stream=None, **overrides) -> "Hierarchy":
-        """Build from a frontend.Hierarchy (host arrays in the canonical numbering)."""
+    def from_frontend(cls, fh, weights: Optional[bool] = None, stream=None, **overrides) -> "Hierarchy":
+        """Build from a frontend.Hierarchy (host arrays in the canonical numbering).
+
+        weights: pass the partition-of-unity W_i (default: the workload's choice)."""
         levels = fh.levels
+        if weights is None:
+            weights = fh.weights
         K = [(l.K.rowptr, l.K.col, l.K.val, l.K.nrows, l.K.ncols) for l in levels]
         P = [(l.P.rowptr, l.P.col, l.P.val, l.P.nrows, l.P.ncols) for l in levels[1:]]
         pts = [(l.patch_ptr, l.patch_dofs, l.patch_weight if weights else None) for l in levels[:-1]]
@@ -203,13 +214,21 @@ class Hierarchy:
         i = LevelInfoT()
         _check(_info(self._h, level, C.byref(i)))
         return dict(n=i.n, npatch=i.npatch, max_m=i.max_m, precision=i.precision, nnz=i.nnz, sum_m=i.sum_m,
-                    sum_m2=i.sum_m2)
+                    sum_m2=i.sum_m2, lambda_max=i.lambda_max)
 
-    def profile(self, on: bool = True):
-        _check(_prof_on(self._h, 1 if on else 0))
+    def profile(self, kernels=("patch_apply",)):
+        """Enable HIP-event timing of the named kernels (empty = off)."""
+        mask = 0
+        for k in kernels:
+            mask |= 1 << KERNELS[k]
+        _check(_prof_on(self._h, mask))
 
-    def profile_read(self, kernel: str, reset: bool = False):
+    def profile_reset(self):
+        _check(_prof_reset(self._h))
+
+    def profile_read(self, kernel: str, level: int = -1):
+        """(summed milliseconds, launches) of one kernel on one level (-1 = all levels)."""
         ms = C.c_double(0.0)
         cnt = C.c_int64(0)
-        _check(_prof_read(self._h, KERNELS[kernel], C.byref(ms), C.byref(cnt), 1 if reset else 0))
+        _check(_prof_read(self._h, KERNELS[kernel], level, C.byref(ms), C.byref(cnt)))
         return float(ms.value), int(cnt.value)

@@ -351,11 +351,14 @@ __global__ __launch_bounds__(kBlock) void patch_apply_kernel(const int32_t* __re
     }
 }
 
-// x[j] (+)= omega * sum_{slots t of DoF j, ascending patch} w_t * Y[t]
+// s_j = sum_{slots t of DoF j, ascending patch id} w_t Y[t];  dn = a s_j + c d_j;
+// x_j = (x_zero ? 0 : x_j) + dn;  d_j = dn when storing (Chebyshev direction).
+// Richardson is a = omega, c = 0.
 __global__ __launch_bounds__(kBlock) void scatter_kernel(int32_t n, const int32_t* __restrict__ sptr,
                                                          const int32_t* __restrict__ sslot,
                                                          const double* __restrict__ w, const double* __restrict__ Y,
-                                                         double omega, double* __restrict__ x, int x_zero) {
+                                                         double a, double c, double* __restrict__ d,
+                                                         double* __restrict__ x, int flags) {
     const int j = blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= n) return;
     double s = 0.0;
@@ -368,7 +371,23 @@ __global__ __launch_bounds__(kBlock) void scatter_kernel(int32_t n, const int32_
     } else {
         for (int t = sptr[j]; t < end; ++t) s += Y[sslot[t]];
     }
-    x[j] = x_zero ? omega * s : x[j] + omega * s;
+    double dn = a * s;
+    if (flags & 2) dn = c * d[j] + dn;
+    x[j] = (flags & 1) ? dn : x[j] + dn;
+    if (flags & 4) d[j] = dn;
+}
+
+__global__ __launch_bounds__(kBlock) void power_start_kernel(int64_t n, double* __restrict__ v) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        v[i] = 1.0 + 0.5 * sin((double)i);
+}
+
+__global__ __launch_bounds__(kBlock) void scale_by_devnorm_kernel(int64_t n, const double* __restrict__ s,
+                                                                  const double* __restrict__ norm2,
+                                                                  double* __restrict__ d) {
+    const double q = sqrt(norm2[0]);
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        d[i] = s[i] / q;
 }
 
 // ---------------------------------------------------------------------------
@@ -557,10 +576,21 @@ void launch_patch_apply(hipStream_t s, const Level& L, const double* r) {
     }
 }
 
-void launch_scatter(hipStream_t s, const Level& L, double omega, double* x, bool x_zero) {
+void launch_scatter(hipStream_t s, const Level& L, double a, double c, double* d, bool store_d, double* x,
+                    bool x_zero) {
     if (L.n <= 0) return;
+    const int flags = (x_zero ? 1 : 0) | (c != 0.0 ? 2 : 0) | (store_d ? 4 : 0);
     hipLaunchKernelGGL(scatter_kernel, dim3(grid_for(L.n, kBlock)), dim3(kBlock), 0, s, L.n, L.sptr, L.sslot,
-                       L.pweight, L.Y, omega, x, x_zero ? 1 : 0);
+                       L.pweight, L.Y, a, c, d, x, flags);
+}
+
+void launch_power_start(hipStream_t s, int64_t n, double* v) {
+    hipLaunchKernelGGL(power_start_kernel, dim3(std::min(grid_for(n, kBlock), 4096)), dim3(kBlock), 0, s, n, v);
+}
+
+void launch_scale_by_devnorm(hipStream_t s, int64_t n, const double* src, const double* norm2, double* dst) {
+    hipLaunchKernelGGL(scale_by_devnorm_kernel, dim3(std::min(grid_for(n, kBlock), 4096)), dim3(kBlock), 0, s, n,
+                       src, norm2, dst);
 }
 
 void launch_coarse_build(hipStream_t s, const Level& L, double* dense) {

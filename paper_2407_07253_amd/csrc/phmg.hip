@@ -120,8 +120,8 @@ DevCsr upload_transpose(phmg_ctx ctx, const phmg_csr& A) {
 
 struct Timed {
     phmg_ctx ctx;
-    int id;
-    hipEvent_t e1 = nullptr;
+    int id, level;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
     hipEvent_t take() {
         auto& pool = ctx->prof.pool;
         if (!pool.empty()) {
@@ -133,9 +133,8 @@ struct Timed {
         hipcheck(hipEventCreate(&e), "hipEventCreate");
         return e;
     }
-    hipEvent_t e0 = nullptr;
-    Timed(phmg_ctx c, int k) : ctx(c), id(k) {
-        if (!ctx->prof.on) return;
+    Timed(phmg_ctx c, int k, int l) : ctx(c), id(k), level(l) {
+        if (!(ctx->prof.mask & (1u << k))) return;
         e0 = take();
         e1 = take();
         hipcheck(hipEventRecord(e0, ctx->stream), "hipEventRecord");
@@ -143,7 +142,7 @@ struct Timed {
     ~Timed() {
         if (!e0) return;
         (void)hipEventRecord(e1, ctx->stream);
-        ctx->prof.pending.push_back({id, {e0, e1}});
+        ctx->prof.pending.push_back({id, level, e0, e1});
     }
 };
 
@@ -152,11 +151,12 @@ void drain_profile(phmg_ctx ctx) {
     hipcheck(hipStreamSynchronize(ctx->stream), "hipStreamSynchronize");
     for (auto& it : ctx->prof.pending) {
         float ms = 0.f;
-        hipcheck(hipEventElapsedTime(&ms, it.second.first, it.second.second), "hipEventElapsedTime");
-        ctx->prof.ms[it.first] += ms;
-        ctx->prof.count[it.first] += 1;
-        ctx->prof.pool.push_back(it.second.first);
-        ctx->prof.pool.push_back(it.second.second);
+        hipcheck(hipEventElapsedTime(&ms, it.e0, it.e1), "hipEventElapsedTime");
+        const int l = std::min(std::max(it.level, 0), PHMG_MAX_LEVELS - 1);
+        ctx->prof.ms[it.kernel][l] += ms;
+        ctx->prof.count[it.kernel][l] += 1;
+        ctx->prof.pool.push_back(it.e0);
+        ctx->prof.pool.push_back(it.e1);
     }
     ctx->prof.pending.clear();
 }
@@ -165,6 +165,10 @@ void drain_profile(phmg_ctx ctx) {
 // relaxation, cycle
 // ----------------------------------------------------------------------------
 
+// nu smoothing steps on level l (eq. "eq:ASM"): damped Richardson, or the
+// Chebyshev acceleration of the additive Schwarz operator used in the paper's
+// experiments.  With x_zero the incoming x is ignored (treated as 0) and the
+// first residual is b itself.
 void relax(phmg_ctx ctx, int l, const double* b, double* x, int nu, bool x_zero) {
     Level& L = ctx->L[l];
     hipStream_t s = ctx->stream;
@@ -172,22 +176,62 @@ void relax(phmg_ctx ctx, int l, const double* b, double* x, int nu, bool x_zero)
         if (x_zero) launch_fill(s, L.n, x, 0.0);
         return;
     }
+    const bool cheb = ctx->opts.smoother == PHMG_SMOOTHER_CHEBYSHEV;
+    double theta = 0.0, delta = 0.0, sigma = 0.0, rho_prev = 0.0;
+    if (cheb) {
+        const double emin = ctx->opts.cheb_lo * L.lmax, emax = ctx->opts.cheb_hi * L.lmax;
+        theta = 0.5 * (emax + emin);
+        delta = 0.5 * (emax - emin);
+        sigma = theta / delta;
+        rho_prev = 1.0 / sigma;
+    }
     for (int it = 0; it < nu; ++it) {
         const double* r = b;                         // x = 0: the residual is b itself
         if (!(it == 0 && x_zero)) {
-            Timed t(ctx, PHMG_K_SPMV);
+            Timed t(ctx, PHMG_K_SPMV, l);
             launch_spmv(s, L.K, x, -1.0, b, 1.0, L.r);
             r = L.r;
         }
         {
-            Timed t(ctx, PHMG_K_PATCH_APPLY);
+            Timed t(ctx, PHMG_K_PATCH_APPLY, l);
             launch_patch_apply(s, L, r);
         }
-        {
-            Timed t(ctx, PHMG_K_SCATTER);
-            launch_scatter(s, L, ctx->opts.omega, x, it == 0 && x_zero);
+        Timed t(ctx, PHMG_K_SCATTER, l);
+        const bool xz = it == 0 && x_zero;
+        if (!cheb) {
+            launch_scatter(s, L, ctx->opts.omega, 0.0, nullptr, false, x, xz);
+        } else if (it == 0) {
+            launch_scatter(s, L, 1.0 / theta, 0.0, L.d, nu > 1, x, xz);
+        } else {
+            const double rho = 1.0 / (2.0 * sigma - rho_prev);
+            launch_scatter(s, L, 2.0 * rho / delta, rho * rho_prev, L.d, it + 1 < nu, x, false);
+            rho_prev = rho;
         }
     }
+}
+
+// lambda_max(M^{-1} K) by power iteration, entirely on the device; one host read at the end.
+double power_iteration(phmg_ctx ctx, int l) {
+    Level& L = ctx->L[l];
+    hipStream_t s = ctx->stream;
+    double* v = L.d;        // the Chebyshev direction buffer doubles as the iterate here
+    double* w = L.r;
+    double* z = L.b ? L.b : L.x;
+    if (!z) z = ctx->L[0].x;
+    launch_power_start(s, L.n, v);
+    launch_multidot(s, L.n, 1, v, L.n, v, ctx->partial, ctx->scal, false);
+    launch_scale_by_devnorm(s, L.n, v, ctx->scal, v);
+    for (int it = 0; it < ctx->opts.eig_iters; ++it) {
+        launch_spmv(s, L.K, v, 1.0, nullptr, 0.0, w);
+        launch_patch_apply(s, L, w);
+        launch_scatter(s, L, 1.0, 0.0, nullptr, false, z, true);
+        launch_multidot(s, L.n, 1, z, L.n, z, ctx->partial, ctx->scal, false);
+        launch_scale_by_devnorm(s, L.n, z, ctx->scal, v);
+    }
+    double n2 = 0.0;
+    hipcheck(hipMemcpyAsync(&n2, ctx->scal, sizeof(double), hipMemcpyDeviceToHost, s), "D2H");
+    hipcheck(hipStreamSynchronize(s), "hipStreamSynchronize");
+    return std::sqrt(n2);
 }
 
 void cycle(phmg_ctx ctx, int l, const double* b, double* x, bool x_zero) {
@@ -203,11 +247,11 @@ void cycle(phmg_ctx ctx, int l, const double* b, double* x, bool x_zero) {
     const int nu = l < np ? ctx->opts.nu_p : ctx->opts.nu_h;
     relax(ctx, l, b, x, nu, x_zero);
     {
-        Timed t(ctx, PHMG_K_SPMV);
+        Timed t(ctx, PHMG_K_SPMV, l);
         launch_spmv(s, L.K, x, -1.0, b, 1.0, L.r);
     }
     {
-        Timed t(ctx, PHMG_K_SPMV);
+        Timed t(ctx, PHMG_K_SPMV, l);
         launch_spmv(s, L.R, L.r, 1.0, nullptr, 0.0, C.b);
     }
     if (l + 1 < np || l + 1 == last || l >= np) {
@@ -216,7 +260,7 @@ void cycle(phmg_ctx ctx, int l, const double* b, double* x, bool x_zero) {
         for (int t = 0; t < ctx->opts.n_v; ++t) cycle(ctx, l + 1, C.b, C.x, t == 0);
     }
     {
-        Timed t(ctx, PHMG_K_SPMV);
+        Timed t(ctx, PHMG_K_SPMV, l);
         launch_spmv(s, L.P, C.x, 1.0, x, 1.0, x);
     }
     relax(ctx, l, b, x, nu, false);
@@ -250,7 +294,7 @@ void setup_level(phmg_ctx ctx, int l) {
         hipcheck(hipMemcpyAsync(cptr, hp, sizeof(hp), hipMemcpyHostToDevice, s), "H2D");
         hipcheck(hipMemcpyAsync(coff, &ho, sizeof(ho), hipMemcpyHostToDevice, s), "H2D");
         {
-            Timed t(ctx, PHMG_K_FACTOR);
+            Timed t(ctx, PHMG_K_FACTOR, l);
             launch_gj_invert(s, 1, cptr, coff, nullptr, dense, L.nb, L.status);
             hipcheck(hipGetLastError(), "coarse factorisation launch");
         }
@@ -269,12 +313,12 @@ void setup_level(phmg_ctx ctx, int l) {
     L.factors = nullptr;
     double* f64 = dalloc<double>(ctx, L.sum_m2);
     {
-        Timed t(ctx, PHMG_K_EXTRACT);
+        Timed t(ctx, PHMG_K_EXTRACT, l);
         launch_extract(s, L, f64);
         hipcheck(hipGetLastError(), "extract launch");
     }
     {
-        Timed t(ctx, PHMG_K_FACTOR);
+        Timed t(ctx, PHMG_K_FACTOR, l);
         launch_gj_invert(s, L.npatch, L.pptr, L.foff, L.order, f64, L.max_m, L.status);
         hipcheck(hipGetLastError(), "patch factorisation launch");
     }
@@ -295,6 +339,11 @@ void setup_level(phmg_ctx ctx, int l) {
     hipcheck(hipStreamSynchronize(s), "hipStreamSynchronize");
     if (L.prec != PHMG_PREC_F64) dfree(ctx, f64);
     if (st != INT32_MAX) fail(PHMG_ESINGULAR, lvl(l) + "patch " + std::to_string(st) + " is singular");
+    if (ctx->opts.smoother == PHMG_SMOOTHER_CHEBYSHEV) {
+        L.lmax = power_iteration(ctx, l);
+        if (!(L.lmax > 0.0) || !std::isfinite(L.lmax))
+            fail(PHMG_ESINGULAR, lvl(l) + "eigenvalue estimate of M^{-1}K is not positive and finite");
+    }
     L.ready = true;
 }
 
@@ -319,7 +368,11 @@ void ensure_krylov(phmg_ctx ctx, int restart) {
     ctx->hdev = dalloc<double>(ctx, 2 * (restart + 2) + 4);
     if (!ctx->w) ctx->w = dalloc<double>(ctx, n);
     if (!ctx->rvec) ctx->rvec = dalloc<double>(ctx, n);
-    if (!ctx->partial) ctx->partial = dalloc<double>(ctx, (int64_t)kRedBlocks * (restart + 2));
+    if (ctx->partial_cols < restart + 2) {
+        dfree(ctx, ctx->partial);
+        ctx->partial = dalloc<double>(ctx, (int64_t)kRedBlocks * (restart + 2));
+        ctx->partial_cols = restart + 2;
+    }
     hipcheck(hipHostMalloc((void**)&ctx->hhost, sizeof(double) * (2 * (restart + 2) + 4)), "hipHostMalloc");
     ctx->restart_cap = restart;
 }
@@ -445,8 +498,8 @@ phmg_status guarded(F&& f) {
 
 void destroy_all(phmg_ctx ctx) {
     for (auto& it : ctx->prof.pending) {
-        (void)hipEventDestroy(it.second.first);
-        (void)hipEventDestroy(it.second.second);
+        (void)hipEventDestroy(it.e0);
+        (void)hipEventDestroy(it.e1);
     }
     for (auto e : ctx->prof.pool) (void)hipEventDestroy(e);
     for (void* p : ctx->allocs) (void)hipFree(p);
@@ -467,11 +520,17 @@ phmg_status phmg_hierarchy_create(const phmg_hierarchy_desc* desc, const phmg_cy
         if (!desc || !opts || !out) fail(PHMG_EINVAL, "null argument");
         *out = nullptr;
         const int nl = desc->nlevels;
-        if (nl < 2) fail(PHMG_EINVAL, "nlevels must be >= 2");
+        if (nl < 2 || nl > PHMG_MAX_LEVELS) fail(PHMG_EINVAL, "nlevels must be in [2, 16]");
         if (!desc->K || !desc->P || !desc->patches) fail(PHMG_EINVAL, "null level array");
         if (opts->nu_p < 0 || opts->nu_h < 0 || opts->n_v < 1 || opts->n_plevels < 0 || opts->n_plevels > nl - 1 ||
             !std::isfinite(opts->omega))
             fail(PHMG_EINVAL, "invalid cycle options");
+        if (opts->smoother != PHMG_SMOOTHER_RICHARDSON && opts->smoother != PHMG_SMOOTHER_CHEBYSHEV)
+            fail(PHMG_EINVAL, "invalid cycle options: unknown smoother");
+        if (opts->smoother == PHMG_SMOOTHER_CHEBYSHEV &&
+            (opts->eig_iters < 1 || !(opts->cheb_lo >= 0.0) || !(opts->cheb_hi > opts->cheb_lo) ||
+             !std::isfinite(opts->cheb_hi)))
+            fail(PHMG_EINVAL, "invalid cycle options: Chebyshev needs eig_iters >= 1 and 0 <= cheb_lo < cheb_hi");
         // --- validation (host, before any device work)
         for (int l = 0; l < nl; ++l) {
             const phmg_csr& K = desc->K[l];
@@ -520,6 +579,7 @@ phmg_status phmg_hierarchy_create(const phmg_hierarchy_desc* desc, const phmg_cy
             L.n = desc->K[l].nrows;
             L.K = upload_csr(ctx, desc->K[l]);
             L.r = dalloc<double>(ctx, L.n);
+            L.d = dalloc<double>(ctx, L.n);
             L.status = dalloc<int>(ctx, 1);
             if (l > 0) {
                 L.b = dalloc<double>(ctx, L.n);
@@ -566,6 +626,10 @@ phmg_status phmg_hierarchy_create(const phmg_hierarchy_desc* desc, const phmg_cy
                 if (desc->coarse_null) L.cnull = upload(ctx, desc->coarse_null, L.n);
             }
         }
+        ctx->partial = dalloc<double>(ctx, (int64_t)kRedBlocks * 4);
+        ctx->partial_cols = 4;
+        ctx->scal = dalloc<double>(ctx, 8);
+        ctx->L[0].x = dalloc<double>(ctx, ctx->L[0].n);   // scratch for level-0 power iteration
         *out = ctx;
         return PHMG_OK;
     });
@@ -671,31 +735,47 @@ phmg_status phmg_get_level_info(phmg_ctx ctx, int level, phmg_level_info* info) 
         info->nnz = L.K.nnz;
         info->sum_m = L.sum_m;
         info->sum_m2 = L.sum_m2;
+        info->lambda_max = L.lmax;
         return PHMG_OK;
     });
 }
 
-phmg_status phmg_profile_enable(phmg_ctx ctx, int on) {
+phmg_status phmg_profile_enable(phmg_ctx ctx, unsigned kernel_mask) {
     return guarded([&]() -> phmg_status {
         if (!ctx) fail(PHMG_EINVAL, "null context");
-        ctx->prof.on = on != 0;
+        ctx->prof.mask = kernel_mask & ((1u << PHMG_K_COUNT) - 1);
         return PHMG_OK;
     });
 }
 
-phmg_status phmg_profile_read(phmg_ctx ctx, int kernel, double* total_ms, int64_t* launches, int reset) {
+phmg_status phmg_profile_read(phmg_ctx ctx, int kernel, int level, double* total_ms, int64_t* launches) {
     return guarded([&]() -> phmg_status {
         if (!ctx || !total_ms || !launches) fail(PHMG_EINVAL, "null argument");
         if (kernel < 0 || kernel >= PHMG_K_COUNT) fail(PHMG_EINVAL, "unknown kernel id");
+        if (level >= (int)ctx->L.size() || level >= PHMG_MAX_LEVELS) fail(PHMG_EINVAL, "level out of range");
         drain_profile(ctx);
-        *total_ms = ctx->prof.ms[kernel];
-        *launches = ctx->prof.count[kernel];
-        if (reset) {
-            for (int k = 0; k < PHMG_K_COUNT; ++k) {
-                ctx->prof.ms[k] = 0.0;
-                ctx->prof.count[k] = 0;
-            }
+        double ms = 0.0;
+        int64_t cnt = 0;
+        for (int l = 0; l < PHMG_MAX_LEVELS; ++l) {
+            if (level >= 0 && l != level) continue;
+            ms += ctx->prof.ms[kernel][l];
+            cnt += ctx->prof.count[kernel][l];
         }
+        *total_ms = ms;
+        *launches = cnt;
+        return PHMG_OK;
+    });
+}
+
+phmg_status phmg_profile_reset(phmg_ctx ctx) {
+    return guarded([&]() -> phmg_status {
+        if (!ctx) fail(PHMG_EINVAL, "null context");
+        drain_profile(ctx);
+        for (int k = 0; k < PHMG_K_COUNT; ++k)
+            for (int l = 0; l < PHMG_MAX_LEVELS; ++l) {
+                ctx->prof.ms[k][l] = 0.0;
+                ctx->prof.count[k][l] = 0;
+            }
         return PHMG_OK;
     });
 }

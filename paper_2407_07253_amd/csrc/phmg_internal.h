@@ -53,6 +53,10 @@ struct Level {
     double* cnull = nullptr;
     int32_t nb = 0;                  // n or n + 1
 
+    // Chebyshev smoothing: direction vector and the eigenvalue estimate
+    double* d = nullptr;
+    double lmax = 0.0;
+
     // V-cycle work vectors
     double* r = nullptr;
     double* b = nullptr;
@@ -63,10 +67,14 @@ struct Level {
 };
 
 struct Profile {
-    bool on = false;
-    double ms[PHMG_K_COUNT] = {0};
-    int64_t count[PHMG_K_COUNT] = {0};
-    std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> pending;
+    unsigned mask = 0;
+    double ms[PHMG_K_COUNT][PHMG_MAX_LEVELS] = {{0}};
+    int64_t count[PHMG_K_COUNT][PHMG_MAX_LEVELS] = {{0}};
+    struct Pending {
+        int kernel, level;
+        hipEvent_t e0, e1;
+    };
+    std::vector<Pending> pending;
     std::vector<hipEvent_t> pool;
 };
 
@@ -83,7 +91,9 @@ struct phmg_ctx_s {
     double* Z = nullptr;
     double* w = nullptr;
     double* rvec = nullptr;
-    double* partial = nullptr;
+    double* partial = nullptr;       // kRedBlocks x (restart + 2) reduction partials
+    int partial_cols = 0;
+    double* scal = nullptr;          // device scalars (norms) outside FGMRES
     double* hdev = nullptr;          // device scalars: h (restart+1) and norm
     double* hhost = nullptr;         // pinned host mirror
     phmg::Profile prof;
@@ -102,7 +112,12 @@ void launch_gj_invert(hipStream_t s, int npatch, const int64_t* pptr, const int6
                       double* A, int max_m, int* status);
 void launch_convert(hipStream_t s, int64_t n, const double* src, void* dst, int prec);
 void launch_patch_apply(hipStream_t s, const Level& L, const double* r);
-void launch_scatter(hipStream_t s, const Level& L, double omega, double* x, bool x_zero);
+// dn = a * sum_t w_t Y_t + c * d;  x = (x_zero ? 0 : x) + dn;  d = dn if store_d
+// (c = 0: d is not read; d may be null when c = 0 and !store_d)
+void launch_scatter(hipStream_t s, const Level& L, double a, double c, double* d, bool store_d, double* x,
+                    bool x_zero);
+void launch_power_start(hipStream_t s, int64_t n, double* v);
+void launch_scale_by_devnorm(hipStream_t s, int64_t n, const double* src, const double* norm2, double* dst);
 void launch_coarse_build(hipStream_t s, const Level& L, double* dense);
 void launch_transpose(hipStream_t s, int n, const double* src, double* dst);
 void launch_coarse_solve(hipStream_t s, const Level& L, const double* b, double* x);

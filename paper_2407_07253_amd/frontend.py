@@ -374,6 +374,7 @@ class Hierarchy:
     name: str
     levels: List[LevelData]
     opts: dict = field(default_factory=dict)
+    weights: bool = True          # pass the partition-of-unity W_i (False: W_i = I)
 
     @property
     def b(self) -> np.ndarray:
@@ -384,27 +385,35 @@ SEEDS = {"cfg1": 1, "cfg2": 2, "cfg3": 3, "cfg4": 4}
 
 
 def workload_specs(name: str, k: Optional[int] = None):
-    """Levels as (mesh index from the finest, order, kind) and the cycle options."""
+    """Levels as (mesh index from the finest, order, kind), the cycle options and the weight choice.
+
+    cfg1 names its smoother (nu = 2 damped sweeps, omega = 0.5): Richardson
+    with the partition-of-unity weights.  The other workloads name none and use
+    the paper's: Chebyshev acceleration (nu = 2) of the basic additive Schwarz
+    operator (W_i = I) over [0.1, 1.1] * lambda_max.
+    """
+    cheb = dict(smoother="chebyshev", cheb_lo=0.1, cheb_hi=1.1, eig_iters=20)
     if name in ("cfg1", "tiny2", "tiny4"):
-        return [(0, 2, "TH"), (1, 2, "TH")], dict(nu_p=2, nu_h=2, n_v=1, n_plevels=0, omega=0.5)
+        return [(0, 2, "TH"), (1, 2, "TH")], dict(nu_p=2, nu_h=2, n_v=1, n_plevels=0, omega=0.5), True
     if name.startswith("cfg2") or name == "cfg3":
         nref = {"cfg2": 3, "cfg2_r2": 2, "cfg2_r1": 1, "cfg3": 4}[name]
         kk = 4 if k is None else k
         specs = [(0, kk, "TH")] + [(i, 2, "TH") for i in range(nref + 1)]
-        return specs, dict(nu_p=2, nu_h=2, n_v=1, n_plevels=1, omega=0.5)
+        return specs, dict(nu_p=2, nu_h=2, n_v=1, n_plevels=1, omega=0.5, **cheb), False
     if name in ("cfg4", "cfg4_r0", "sv_small"):
         nmac = {"cfg4": 3, "cfg4_r0": 1, "sv_small": 2}[name]
         kk = 4 if k is None else k
         specs = [(0, kk, "SV"), (0, 2, "TH")] + [(i, 2, "TH") for i in range(1, nmac + 1)]
-        return specs, dict(nu_p=2, nu_h=2, n_v=1, n_plevels=1, omega=0.5)
+        return specs, dict(nu_p=2, nu_h=2, n_v=1, n_plevels=1, omega=0.5, **cheb), False
     raise KeyError(name)
 
 
 def build_hierarchy(name: str, k: Optional[int] = None, forcing: str = "mms", nrhs: int = 1,
                     specs=None, opts=None) -> Hierarchy:
     meshes = synth.config_mesh_hierarchy(name)[::-1]       # finest first
+    weights = True
     if specs is None:
-        specs, opts = workload_specs(name, k)
+        specs, opts, weights = workload_specs(name, k)
     seed = SEEDS.get(name.split("_")[0], 1)
     if forcing == "mms":
         A = synth.mms_amplitude(seed)
@@ -427,4 +436,4 @@ def build_hierarchy(name: str, k: Optional[int] = None, forcing: str = "mms", nr
             parent = None if fine.mesh_index == mi else meshes[fine.mesh_index].parent
             lev.P = prolongation(fine, lev, parent)
         levels.append(lev)
-    return Hierarchy(name, levels, dict(opts))
+    return Hierarchy(name, levels, dict(opts), weights)

@@ -32,11 +32,16 @@ def test_hierarchy_matches_oracle(name):
             optr = np.concatenate([[0], np.cumsum([len(S) for S in ol.patches])])
             assert np.array_equal(fl.patch_ptr, optr)
             assert np.array_equal(fl.patch_dofs, np.concatenate(ol.patches))
-            assert np.allclose(fl.patch_weight, np.concatenate(ol.weights), rtol=0, atol=1e-15)
+            assert fh.weights == (ol.weights is not None)
+            if ol.weights is not None:
+                assert np.allclose(fl.patch_weight, np.concatenate(ol.weights), rtol=0, atol=1e-15)
         if ol.P is not None:
             _same_csr(fl.P, ol.P, 1e-13)
     assert np.abs(fh.b[0] - ob).max() <= 1e-12 * np.abs(ob).max()
-    assert fh.opts == dict(nu_p=oopts.nu_p, nu_h=oopts.nu_h, n_v=oopts.n_v, n_plevels=oopts.n_plevels, omega=oopts.omega)
+    for key, val in fh.opts.items():
+        assert getattr(oopts, key) == val, key
+    if oopts.smoother == "chebyshev":
+        assert fh.opts["smoother"] == "chebyshev"
 
 
 def test_shape_functions_nodal_and_quadrature_exact():

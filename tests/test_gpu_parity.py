@@ -35,7 +35,7 @@ def _pair(name):
         H = Hierarchy.from_frontend(fh)
         H.setup()
         ol, od, oopts, ob = oproblems.build(name)
-        omg.setup(ol)
+        omg.setup(ol, oopts)
         _CACHE[name] = (fh, H, ol, od, oopts, ob)
     return _CACHE[name]
 
@@ -73,11 +73,20 @@ def test_relax_apply_matches_oracle(name, nu):
         xg = _dev(x)
         H.relax_apply(l, _dev(b), xg, nu)
         got = _host(xg)
-        L = ol[l]
-        ref = orelax.asm_sweeps(L.K, L.patches, L.factors, L.weights, oopts.omega, b, x, nu)
+        ref = omg._relax(ol[l], oopts, b, x, nu, False)
         err = _rel(got, ref)
         print(f"{name} level {l} nu={nu}: rel err {err:.2e}")
         assert err <= 1e-11, (l, err)
+
+
+@pytest.mark.parametrize("name", ["cfg2_r1", "sv_small"])
+def test_chebyshev_eigenvalue_estimate_matches_oracle(name):
+    fh, H, ol, od, oopts, ob = _pair(name)
+    assert oopts.smoother == "chebyshev"
+    for l in range(len(ol) - 1):
+        lam = H.level_info(l)["lambda_max"]
+        print(f"{name} level {l}: lambda_max GPU {lam:.15f} oracle {ol[l].lmax:.15f}")
+        assert abs(lam - ol[l].lmax) <= 1e-11 * ol[l].lmax
 
 
 @pytest.mark.parametrize("name", NAMES)

@@ -48,3 +48,44 @@ def test_sweep_equals_dense_operator(kind, k, mesh, weighted):
     xt = relax.asm_sweeps(d.K, patches, factors, W, w, b, x, 1, transpose=True)
     reft = x + w * Minv.T @ (b - K.T @ x)
     assert np.abs(xt - reft).max() <= 1e-12 * np.abs(reft).max()
+
+
+def _cheb_T(Y, nu):
+    """T_nu(Y) by the three-term recurrence (matrix or scalar)."""
+    I = np.eye(Y.shape[0]) if np.ndim(Y) == 2 else 1.0
+    Tm, T = I, Y
+    if nu == 0:
+        return I
+    for _ in range(nu - 1):
+        Tm, T = T, 2 * (Y @ T if np.ndim(Y) == 2 else Y * T) - Tm
+    return T
+
+
+@pytest.mark.parametrize("kind,k,mesh", CASES[:3], ids=[f"{c[0]}{c[1]}" for c in CASES[:3]])
+@pytest.mark.parametrize("nu", [1, 2, 4])
+def test_chebyshev_error_propagator_closed_form(kind, k, mesh, nu):
+    """x_nu - x* = T_nu((theta - M^{-1}K)/delta) / T_nu(theta/delta) (x_0 - x*) for b = K x*."""
+    d = assemble_stokes(mesh, k, kind)
+    patches = vanka_star_patches(d)
+    factors = relax.setup_patches(d.K, patches)
+    K = d.K.toarray()
+    Minv = _dense_Minv(K, patches, None)
+    emin, emax = 0.7, 9.3
+    theta, delta = 0.5 * (emax + emin), 0.5 * (emax - emin)
+    E = _cheb_T((theta * np.eye(d.n) - Minv @ K) / delta, nu) / _cheb_T(theta / delta, nu)
+    rng = np.random.default_rng(21)
+    xs, x0 = rng.standard_normal(d.n), rng.standard_normal(d.n)
+    b = K @ xs
+    got = relax.chebyshev_sweeps(d.K, patches, factors, None, emin, emax, b, x0, nu)
+    ref = xs + E @ (x0 - xs)
+    assert np.abs(got - ref).max() <= 1e-10 * np.abs(ref).max()
+
+
+def test_power_iteration_estimates_largest_eigenvalue():
+    d = assemble_stokes(synth.refine_uniform(synth.delaunay_square(8, seed=3)), 2, "TH")
+    patches = vanka_star_patches(d)
+    factors = relax.setup_patches(d.K, patches)
+    K = d.K.toarray()
+    ev = np.linalg.eigvals(_dense_Minv(K, patches, None) @ K)
+    lam = relax.estimate_lambda_max(d.K, patches, factors, None, 40)
+    assert 0.97 * np.abs(ev).max() <= lam <= 1.0001 * np.abs(ev).max()

@@ -20,7 +20,7 @@ def _normalise(x, nfu):
 
 def test_cfg1_fgmres_hmg_converges_to_direct_solution():
     levels, discs, opts, b = problems.build("cfg1")
-    multigrid.setup(levels)
+    multigrid.setup(levels, opts)
     K = levels[0].K
     res = fgmres.fgmres(lambda v: K @ v, lambda v: multigrid.vcycle(levels, opts, v), b, rtol=1e-8)
     assert res.converged and res.iters < 30
@@ -34,7 +34,7 @@ def test_cfg1_fgmres_hmg_converges_to_direct_solution():
 def test_scott_vogelius_phmg_solve_is_divergence_free():
     """Section 2.1: with SV, div u_h = 0 pointwise once the discrete system is solved."""
     levels, discs, opts, b = problems.build("sv_small")
-    multigrid.setup(levels)
+    multigrid.setup(levels, opts)
     K = levels[0].K
     res = fgmres.fgmres(lambda v: K @ v, lambda v: multigrid.vcycle(levels, opts, v), b, rtol=1e-12)
     assert res.converged

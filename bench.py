@@ -119,6 +119,10 @@ def cpu_baseline(workload: str, budget_s: float = 12.0):
     }
 
 
+def _fmt(v):
+    return float(f"{v:.6g}") if isinstance(v, float) else v
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -225,10 +229,13 @@ def main() -> int:
 
     f64 = timed_legs("f64")
     ap64 = apply_leg("f64")
+    variants = {"f64": [H.level_info(l)["apply_variant"] for l in range(nl - 1)]}
+    lambdas = [round(H.level_info(l)["lambda_max"], 6) for l in range(nl - 1)]
     out_mixed, ap_mixed = None, None
     if args.mixed != "none":
         out_mixed = timed_legs(args.mixed)
         ap_mixed = apply_leg(args.mixed)
+        variants[args.mixed] = [H.level_info(l)["apply_variant"] for l in range(nl - 1)]
     H.close()
 
     traffic = traffic_entry("f64")
@@ -252,6 +259,9 @@ def main() -> int:
             "level0_sum_m2": infos[0]["sum_m2"],
             "level0_max_m": infos[0]["max_m"],
             "step": "relax_setup (extract + patch inversion, all levels) + FGMRES(30) to 1e-8 from x=0",
+            "smoother": fh.opts.get("smoother", "richardson"),
+            "lambda_max": lambdas,
+            "apply_kernel_shape": variants,
         },
         "roofline": {
             "bound": "hbm",
@@ -265,12 +275,12 @@ def main() -> int:
             "avg_launch_ms": round(ap64["avg_ms"], 5),
             "launches": ap64["launches"],
         },
-        "time_to_1e-8": {"f64": {k: (round(v, 4) if isinstance(v, float) else v) for k, v in f64.items()}},
+        "time_to_1e-8": {"f64": {k: _fmt(v) for k, v in f64.items()}},
         "sweep_level0": {"f64": {"wall_ms": round(ap64["sweep_wall_ms"], 4), "gbps": round(ap64["sweep_gbps"], 1),
                                  "spmv_ms": round(ap64["spmv_ms"], 4), "scatter_ms": round(ap64["scatter_ms"], 4)}},
     }
     if out_mixed is not None:
-        result["time_to_1e-8"][args.mixed] = {k: (round(v, 4) if isinstance(v, float) else v) for k, v in out_mixed.items()}
+        result["time_to_1e-8"][args.mixed] = {k: _fmt(v) for k, v in out_mixed.items()}
         result["patch_apply_gbps"] = {"f64": round(ap64["gbps"], 2), args.mixed: round(ap_mixed["gbps"], 2)}
         result["sweep_level0"][args.mixed] = {"wall_ms": round(ap_mixed["sweep_wall_ms"], 4),
                                               "gbps": round(ap_mixed["sweep_gbps"], 1)}

@@ -82,7 +82,8 @@ typedef struct {
  * smoother = PHMG_SMOOTHER_CHEBYSHEV (the paper's experiments, Section 4):
  * nu steps of Chebyshev acceleration of M^{-1} over [cheb_lo, cheb_hi] *
  * lambda, where lambda estimates the largest eigenvalue of M^{-1} K by
- * eig_iters power iterations at set-up (start vector v_j = 1 + sin(j)/2). */
+ * the largest real Ritz value of eig_iters Arnoldi steps (classical
+ * Gram-Schmidt twice) run at set-up from v_j = 1 + sin(j)/2. */
 typedef struct {
     int32_t nu_p, nu_h, n_v, n_plevels;
     double omega;
@@ -145,12 +146,14 @@ phmg_status phmg_fgmres_solve(phmg_ctx ctx, const double* b, double* x, double r
 /* Residual r = b - K_l x on a level (device pointers, asynchronous). */
 phmg_status phmg_residual(phmg_ctx ctx, int level, const double* b, const double* x, double* r);
 
-/* Per-level sizes: n, nnz(K), npatch, sum m, sum m^2, max m, and the
- * Chebyshev eigenvalue estimate (0 before set-up or for Richardson). */
+/* Per-level sizes: n, nnz(K), npatch, sum m, sum m^2, max m, the Chebyshev
+ * eigenvalue estimate (0 before set-up or for Richardson) and the patch-solve
+ * kernel shape chosen by the set-up autotuner. */
 typedef struct {
     int32_t n, npatch, max_m, precision;
     int64_t nnz, sum_m, sum_m2;
     double lambda_max;
+    int32_t apply_variant, reserved;
 } phmg_level_info;
 phmg_status phmg_get_level_info(phmg_ctx ctx, int level, phmg_level_info* info);
 
@@ -175,6 +178,12 @@ phmg_status phmg_profile_read(phmg_ctx ctx, int kernel, int level, double* total
 phmg_status phmg_profile_reset(phmg_ctx ctx);
 
 phmg_status phmg_hierarchy_destroy(phmg_ctx ctx);
+
+/* Largest real part of the eigenvalues of the leading k x k block of a real
+ * upper-Hessenberg matrix H (host, column-major, leading dimension ldh >= k):
+ * the Chebyshev bound that relax_setup derives from its Arnoldi steps
+ * (complex shifted QR).  Pure host computation. */
+phmg_status phmg_ritz_max_real(const double* H, int ldh, int k, double* out);
 
 /* Thread-local description of the last error ("" when none). */
 const char* phmg_last_error(void);

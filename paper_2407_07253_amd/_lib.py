@@ -61,7 +61,8 @@ class DescT(C.Structure):
 
 class LevelInfoT(C.Structure):
     _fields_ = [("n", C.c_int32), ("npatch", C.c_int32), ("max_m", C.c_int32), ("precision", C.c_int32),
-                ("nnz", C.c_int64), ("sum_m", C.c_int64), ("sum_m2", C.c_int64), ("lambda_max", C.c_double)]
+                ("nnz", C.c_int64), ("sum_m", C.c_int64), ("sum_m2", C.c_int64), ("lambda_max", C.c_double),
+                ("apply_variant", C.c_int32), ("reserved", C.c_int32)]
 
 
 def _sig(name, res, args):
@@ -85,10 +86,20 @@ _prof_on = _sig("phmg_profile_enable", C.c_int, [C.c_void_p, C.c_uint])
 _prof_read = _sig("phmg_profile_read", C.c_int, [C.c_void_p, C.c_int, C.c_int, C.POINTER(C.c_double), C.POINTER(C.c_int64)])
 _prof_reset = _sig("phmg_profile_reset", C.c_int, [C.c_void_p])
 _last_error = _sig("phmg_last_error", C.c_char_p, [])
+_ritz = _sig("phmg_ritz_max_real", C.c_int, [C.c_void_p, C.c_int, C.c_int, C.POINTER(C.c_double)])
 
 EXPORTED = ["phmg_hierarchy_create", "phmg_hierarchy_destroy", "phmg_relax_setup", "phmg_set_precision",
             "phmg_relax_apply", "phmg_vcycle", "phmg_fgmres_solve", "phmg_residual", "phmg_get_level_info",
-            "phmg_profile_enable", "phmg_profile_read", "phmg_profile_reset", "phmg_last_error"]
+            "phmg_profile_enable", "phmg_profile_read", "phmg_profile_reset", "phmg_ritz_max_real",
+            "phmg_last_error"]
+
+
+def ritz_max_real(H: np.ndarray, k: int) -> float:
+    """Largest real eigenvalue part of H[:k, :k] computed by the library's host QR."""
+    Hf = np.asfortranarray(H, dtype=np.float64)
+    out = C.c_double(0.0)
+    _check(_ritz(Hf.ctypes.data, Hf.shape[0], k, C.byref(out)))
+    return float(out.value)
 
 
 def last_error() -> str:
@@ -214,7 +225,7 @@ class Hierarchy:
         i = LevelInfoT()
         _check(_info(self._h, level, C.byref(i)))
         return dict(n=i.n, npatch=i.npatch, max_m=i.max_m, precision=i.precision, nnz=i.nnz, sum_m=i.sum_m,
-                    sum_m2=i.sum_m2, lambda_max=i.lambda_max)
+                    sum_m2=i.sum_m2, lambda_max=i.lambda_max, apply_variant=i.apply_variant)
 
     def profile(self, kernels=("patch_apply",)):
         """Enable HIP-event timing of the named kernels (empty = off)."""

@@ -288,66 +288,136 @@ __global__ __launch_bounds__(kBlock) void gj_kernel(const int64_t* __restrict__ 
     }
 }
 
-__global__ __launch_bounds__(kBlock) void convert_f32_kernel(int64_t n, const double* __restrict__ s,
-                                                             float* __restrict__ d) {
-    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
-        d[i] = (float)s[i];
-}
-
-__global__ __launch_bounds__(kBlock) void convert_bf16_kernel(int64_t n, const double* __restrict__ s,
-                                                              __hip_bfloat16* __restrict__ d) {
-    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
-        d[i] = __float2bfloat16((float)s[i]);
-}
-
 // ---------------------------------------------------------------------------
 // Batched patch solve: y_i = K_i^{-1} r[S_i].  One workgroup per patch; the
-// gathered residual sits in LDS; rows of the inverse run over the 64 lanes
-// (coalesced column reads), columns are split over the 4 wavefronts and the
-// 4 partial sums are combined in LDS.
+// gathered residual sits in LDS.  Each wavefront streams the columns j = w,
+// w+4, w+8, ... of the stored inverse (column-major, leading dimension ld =
+// m rounded up to V), every lane owning V consecutive rows of up to NRT row
+// tiles, so a wave-load is always 64 x 8 bytes and four columns are in flight
+// per wave.  The four per-wave partial sums are combined in LDS once per
+// group of NRT row tiles.
 // ---------------------------------------------------------------------------
-__device__ inline double ld_factor(const double* p) { return *p; }
-__device__ inline float ld_factor(const float* p) { return *p; }
-__device__ inline float ld_factor(const __hip_bfloat16* p) { return __bfloat162float(*p); }
+template <typename T, int V>
+struct FactorLoad;
+template <>
+struct FactorLoad<double, 1> {
+    __device__ static inline void load(const double* p, double (&a)[1]) { a[0] = *p; }
+};
+template <>
+struct FactorLoad<float, 2> {
+    __device__ static inline void load(const float* p, float (&a)[2]) {
+        const float2 v = *reinterpret_cast<const float2*>(p);
+        a[0] = v.x;
+        a[1] = v.y;
+    }
+};
+template <>
+struct FactorLoad<__hip_bfloat16, 4> {
+    __device__ static inline void load(const __hip_bfloat16* p, float (&a)[4]) {
+        const uint2 v = *reinterpret_cast<const uint2*>(p);
+        a[0] = __uint_as_float(v.x << 16);
+        a[1] = __uint_as_float(v.x & 0xffff0000u);
+        a[2] = __uint_as_float(v.y << 16);
+        a[3] = __uint_as_float(v.y & 0xffff0000u);
+    }
+};
 
-template <typename T, typename Acc>
+template <typename T, typename Acc, int V, int NRT, int U>
 __global__ __launch_bounds__(kBlock) void patch_apply_kernel(const int32_t* __restrict__ order,
                                                              const int64_t* __restrict__ pptr,
                                                              const int32_t* __restrict__ pdofs,
                                                              const int64_t* __restrict__ foff,
                                                              const T* __restrict__ F, const double* __restrict__ r,
                                                              double* __restrict__ Y) {
+    constexpr int NW = kBlock / kWave;
+    constexpr int TILE = kWave * V;
     extern __shared__ double s_buf[];
     Acc* s_r = reinterpret_cast<Acc*>(s_buf);
-    __shared__ Acc s_red[kBlock / kWave][kWave];
+    __shared__ Acc s_red[NRT][NW][TILE];
     const int p = order[blockIdx.x];
     const int64_t base = pptr[p];
     const int m = (int)(pptr[p + 1] - base);
+    const int ld = (m + V - 1) / V * V;
     for (int t = threadIdx.x; t < m; t += kBlock) s_r[t] = (Acc)r[pdofs[base + t]];
     __syncthreads();
     const T* A = F + foff[p];
     const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
-    constexpr int NW = kBlock / kWave;
-    for (int rt = 0; rt < m; rt += kWave) {
-        const int i = rt + lane;
-        Acc acc = 0;
-        if (i < m) {
-            const T* Ai = A + i;
-            int j = wave;
-            for (; j + 7 * NW < m; j += 8 * NW) {
-                Acc a[8];
+    for (int r0 = 0; r0 < m; r0 += NRT * TILE) {
+        Acc acc[NRT][V];
 #pragma unroll
-                for (int u = 0; u < 8; ++u) a[u] = (Acc)ld_factor(Ai + (int64_t)(j + u * NW) * m);
+        for (int q = 0; q < NRT; ++q)
 #pragma unroll
-                for (int u = 0; u < 8; ++u) acc += a[u] * s_r[j + u * NW];
+            for (int v = 0; v < V; ++v) acc[q][v] = 0;
+        int j = wave;
+        for (; j + (U - 1) * NW < m; j += U * NW) {
+            Acc a[U][NRT][V];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const T* col = A + (int64_t)(j + u * NW) * ld + r0 + lane * V;
+#pragma unroll
+                for (int q = 0; q < NRT; ++q) {
+                    if (r0 + q * TILE + lane * V < m) FactorLoad<T, V>::load(col + q * TILE, a[u][q]);
+                    else
+#pragma unroll
+                        for (int v = 0; v < V; ++v) a[u][q][v] = 0;
+                }
             }
-            for (; j < m; j += NW) acc += (Acc)ld_factor(Ai + (int64_t)j * m) * s_r[j];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const Acc rj = s_r[j + u * NW];
+#pragma unroll
+                for (int q = 0; q < NRT; ++q)
+#pragma unroll
+                    for (int v = 0; v < V; ++v) acc[q][v] += a[u][q][v] * rj;
+            }
         }
-        s_red[wave][lane] = acc;
+        for (; j < m; j += NW) {
+            const T* col = A + (int64_t)j * ld + r0 + lane * V;
+            const Acc rj = s_r[j];
+#pragma unroll
+            for (int q = 0; q < NRT; ++q) {
+                if (r0 + q * TILE + lane * V < m) {
+                    Acc a[V];
+                    FactorLoad<T, V>::load(col + q * TILE, a);
+#pragma unroll
+                    for (int v = 0; v < V; ++v) acc[q][v] += a[v] * rj;
+                }
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < NRT; ++q)
+#pragma unroll
+            for (int v = 0; v < V; ++v) s_red[q][wave][lane * V + v] = acc[q][v];
         __syncthreads();
-        if (wave == 0 && i < m)
-            Y[base + i] = (double)((s_red[0][lane] + s_red[1][lane]) + (s_red[2][lane] + s_red[3][lane]));
+        for (int t = threadIdx.x; t < NRT * TILE; t += kBlock) {
+            const int i = r0 + t;
+            if (i < m) {
+                const int q = t / TILE, e = t % TILE;
+                Y[base + i] = (double)((s_red[q][0][e] + s_red[q][1][e]) + (s_red[q][2][e] + s_red[q][3][e]));
+            }
+        }
         __syncthreads();
+    }
+}
+
+// f64 set-up result (column-major, ld = m) -> reduced-precision factors with
+// ld = m rounded up to V (padding rows are zero); one workgroup per patch.
+template <typename T, int V>
+__global__ __launch_bounds__(kBlock) void convert_patch_kernel(const int64_t* __restrict__ pptr,
+                                                               const int64_t* __restrict__ foff64,
+                                                               const int64_t* __restrict__ fofflp,
+                                                               const double* __restrict__ src, T* __restrict__ dst) {
+    const int p = blockIdx.x;
+    const int m = (int)(pptr[p + 1] - pptr[p]);
+    const int ld = (m + V - 1) / V * V;
+    const double* a = src + foff64[p];
+    T* b = dst + fofflp[p];
+    const int64_t total = (int64_t)ld * m;
+    for (int64_t e = threadIdx.x; e < total; e += kBlock) {
+        const int i = (int)(e % ld), j = (int)(e / ld);
+        const double v = i < m ? a[i + (int64_t)j * m] : 0.0;
+        if constexpr (sizeof(T) == 4) b[e] = (T)v;
+        else b[e] = __float2bfloat16((float)v);
     }
 }
 
@@ -549,31 +619,55 @@ void launch_gj_invert(hipStream_t s, int npatch, const int64_t* pptr, const int6
     hipLaunchKernelGGL(gj_kernel, dim3(npatch), dim3(kBlock), lds, s, pptr, foff, order, A, max_m, status);
 }
 
-void launch_convert(hipStream_t s, int64_t n, const double* src, void* dst, int prec) {
-    if (n <= 0) return;
-    const int grid = std::min(grid_for(n, kBlock), 8192);
-    if (prec == PHMG_PREC_F32)
-        hipLaunchKernelGGL(convert_f32_kernel, dim3(grid), dim3(kBlock), 0, s, n, src, (float*)dst);
-    else if (prec == PHMG_PREC_BF16)
-        hipLaunchKernelGGL(convert_bf16_kernel, dim3(grid), dim3(kBlock), 0, s, n, src, (__hip_bfloat16*)dst);
+// Kernel shapes the set-up autotuner chooses from, per precision:
+// (row tiles held per pass NRT, columns in flight per wave U).
+namespace {
+template <typename T, typename Acc, int V, int NRT, int U>
+void launch_apply_shape(hipStream_t s, const Level& L, const int64_t* off, const double* r) {
+    hipLaunchKernelGGL((patch_apply_kernel<T, Acc, V, NRT, U>), dim3(L.npatch), dim3(kBlock), sizeof(Acc) * L.max_m, s,
+                       L.order, L.pptr, L.pdofs, off, (const T*)L.factors, r, L.Y);
 }
+}  // namespace
+
+int apply_variant_count(int prec) { return prec == PHMG_PREC_F64 ? 6 : 4; }
 
 void launch_patch_apply(hipStream_t s, const Level& L, const double* r) {
     if (L.npatch <= 0) return;
-    const size_t lds = sizeof(double) * L.max_m;
-    switch (L.prec) {
-        case PHMG_PREC_F32:
-            hipLaunchKernelGGL((patch_apply_kernel<float, float>), dim3(L.npatch), dim3(kBlock), lds, s, L.order,
-                               L.pptr, L.pdofs, L.foff, (const float*)L.factors, r, L.Y);
-            break;
-        case PHMG_PREC_BF16:
-            hipLaunchKernelGGL((patch_apply_kernel<__hip_bfloat16, float>), dim3(L.npatch), dim3(kBlock), lds, s,
-                               L.order, L.pptr, L.pdofs, L.foff, (const __hip_bfloat16*)L.factors, r, L.Y);
-            break;
-        default:
-            hipLaunchKernelGGL((patch_apply_kernel<double, double>), dim3(L.npatch), dim3(kBlock), lds, s, L.order,
-                               L.pptr, L.pdofs, L.foff, (const double*)L.factors, r, L.Y);
+    const int v = L.apply_variant;
+    if (L.prec == PHMG_PREC_F32) {
+        switch (v) {
+            case 1: launch_apply_shape<float, float, 2, 1, 8>(s, L, L.fofflp, r); break;
+            case 2: launch_apply_shape<float, float, 2, 2, 2>(s, L, L.fofflp, r); break;
+            case 3: launch_apply_shape<float, float, 2, 1, 4>(s, L, L.fofflp, r); break;
+            default: launch_apply_shape<float, float, 2, 2, 4>(s, L, L.fofflp, r);
+        }
+    } else if (L.prec == PHMG_PREC_BF16) {
+        switch (v) {
+            case 1: launch_apply_shape<__hip_bfloat16, float, 4, 1, 8>(s, L, L.fofflp, r); break;
+            case 2: launch_apply_shape<__hip_bfloat16, float, 4, 1, 2>(s, L, L.fofflp, r); break;
+            case 3: launch_apply_shape<__hip_bfloat16, float, 4, 2, 4>(s, L, L.fofflp, r); break;
+            default: launch_apply_shape<__hip_bfloat16, float, 4, 1, 4>(s, L, L.fofflp, r);
+        }
+    } else {
+        switch (v) {
+            case 1: launch_apply_shape<double, double, 1, 3, 4>(s, L, L.foff, r); break;
+            case 2: launch_apply_shape<double, double, 1, 2, 4>(s, L, L.foff, r); break;
+            case 3: launch_apply_shape<double, double, 1, 4, 2>(s, L, L.foff, r); break;
+            case 4: launch_apply_shape<double, double, 1, 1, 8>(s, L, L.foff, r); break;
+            case 5: launch_apply_shape<double, double, 1, 3, 2>(s, L, L.foff, r); break;
+            default: launch_apply_shape<double, double, 1, 4, 4>(s, L, L.foff, r);
+        }
     }
+}
+
+void launch_convert_patches(hipStream_t s, const Level& L, const double* src, void* dst) {
+    if (L.npatch <= 0) return;
+    if (L.prec == PHMG_PREC_F32)
+        hipLaunchKernelGGL((convert_patch_kernel<float, 2>), dim3(L.npatch), dim3(kBlock), 0, s, L.pptr, L.foff,
+                           L.fofflp, src, (float*)dst);
+    else if (L.prec == PHMG_PREC_BF16)
+        hipLaunchKernelGGL((convert_patch_kernel<__hip_bfloat16, 4>), dim3(L.npatch), dim3(kBlock), 0, s, L.pptr,
+                           L.foff, L.fofflp, src, (__hip_bfloat16*)dst);
 }
 
 void launch_scatter(hipStream_t s, const Level& L, double a, double c, double* d, bool store_d, double* x,

@@ -10,6 +10,7 @@
 #include <algorithm>
 #include <climits>
 #include <cmath>
+#include <complex>
 #include <cstdio>
 #include <cstring>
 #include <numeric>
@@ -210,28 +211,154 @@ void relax(phmg_ctx ctx, int l, const double* b, double* x, int nu, bool x_zero)
     }
 }
 
-// lambda_max(M^{-1} K) by power iteration, entirely on the device; one host read at the end.
-double power_iteration(phmg_ctx ctx, int l) {
+// Set-up autotuner of the patch-solve kernel shape: every compiled shape of the
+// level's precision is timed on the level's own patches (HIP events, best of
+// three launches) and the fastest is kept.  Runs once per level and precision.
+void tune_apply(phmg_ctx ctx, int l) {
+    Level& L = ctx->L[l];
+    if (L.tuned_for == L.prec || L.npatch == 0) return;
+    hipStream_t s = ctx->stream;
+    launch_fill(s, L.n, L.r, 1.0);
+    hipEvent_t e0, e1;
+    hipcheck(hipEventCreate(&e0), "hipEventCreate");
+    hipcheck(hipEventCreate(&e1), "hipEventCreate");
+    const int nv = apply_variant_count(L.prec);
+    int best = 0;
+    float best_ms = 1e30f;
+    for (int v = 0; v < nv; ++v) {
+        L.apply_variant = v;
+        launch_patch_apply(s, L, L.r);                      // warm-up
+        float vbest = 1e30f;
+        for (int rep = 0; rep < 3; ++rep) {
+            hipcheck(hipEventRecord(e0, s), "hipEventRecord");
+            launch_patch_apply(s, L, L.r);
+            hipcheck(hipEventRecord(e1, s), "hipEventRecord");
+            hipcheck(hipEventSynchronize(e1), "hipEventSynchronize");
+            float ms = 0.f;
+            hipcheck(hipEventElapsedTime(&ms, e0, e1), "hipEventElapsedTime");
+            vbest = std::min(vbest, ms);
+        }
+        if (vbest < best_ms) {
+            best_ms = vbest;
+            best = v;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    hipcheck(hipGetLastError(), "autotune launch");
+    L.apply_variant = best;
+    L.tuned_for = L.prec;
+}
+
+// Eigenvalues of a small real upper-Hessenberg matrix (row-major k x k) by the
+// complex single-shift QR algorithm: Wilkinson shifts, Givens rotations,
+// deflation at the bottom of the active block.
+bool hessenberg_eigenvalues(std::vector<std::complex<double>> A, int k, std::vector<std::complex<double>>& ev) {
+    using cd = std::complex<double>;
+    auto a = [&](int i, int j) -> cd& { return A[(size_t)i * k + j]; };
+    ev.clear();
+    int n = k, iter = 0;
+    std::vector<cd> cs(k), sn(k);
+    while (n > 0) {
+        if (n == 1) {
+            ev.push_back(a(0, 0));
+            break;
+        }
+        const double sub = std::abs(a(n - 1, n - 2));
+        double scale = std::abs(a(n - 1, n - 1)) + std::abs(a(n - 2, n - 2));
+        if (scale == 0.0) scale = 1.0;
+        if (sub <= 1e-15 * scale) {
+            ev.push_back(a(n - 1, n - 1));
+            --n;
+            iter = 0;
+            continue;
+        }
+        if (++iter > 100 * k) return false;
+        const cd p = a(n - 2, n - 2), q = a(n - 2, n - 1), r = a(n - 1, n - 2), t = a(n - 1, n - 1);
+        const cd half_tr = 0.5 * (p + t), det = p * t - q * r;
+        const cd disc = std::sqrt(half_tr * half_tr - det);
+        const cd l1 = half_tr + disc, l2 = half_tr - disc;
+        cd mu = std::abs(l1 - t) < std::abs(l2 - t) ? l1 : l2;
+        if (iter % 11 == 10) mu += 0.75 * std::abs(r);      // exceptional shift
+        for (int i = 0; i < n; ++i) a(i, i) -= mu;
+        for (int i = 0; i + 1 < n; ++i) {
+            const cd x = a(i, i), y = a(i + 1, i);
+            const double rr = std::sqrt(std::norm(x) + std::norm(y));
+            const cd c = rr == 0.0 ? cd(1.0) : x / rr, sg = rr == 0.0 ? cd(0.0) : y / rr;
+            cs[i] = c;
+            sn[i] = sg;
+            for (int j = i; j < n; ++j) {
+                const cd u = a(i, j), v = a(i + 1, j);
+                a(i, j) = std::conj(c) * u + std::conj(sg) * v;
+                a(i + 1, j) = -sg * u + c * v;
+            }
+        }
+        for (int i = 0; i + 1 < n; ++i) {
+            const cd c = cs[i], sg = sn[i];
+            for (int rw = 0; rw <= i + 1; ++rw) {
+                const cd u = a(rw, i), v = a(rw, i + 1);
+                a(rw, i) = u * c + v * sg;
+                a(rw, i + 1) = -u * std::conj(sg) + v * std::conj(c);
+            }
+        }
+        for (int i = 0; i < n; ++i) a(i, i) += mu;
+    }
+    return true;
+}
+
+// Largest real part of the eigenvalues of H[0:k, 0:k] (H column-major, leading dimension ldh).
+double ritz_max_real(const double* H, int ldh, int k) {
+    std::vector<std::complex<double>> A((size_t)k * k), ev;
+    for (int i = 0; i < k; ++i)
+        for (int j = 0; j < k; ++j) A[(size_t)i * k + j] = H[(size_t)j * ldh + i];
+    if (!hessenberg_eigenvalues(A, k, ev)) fail(PHMG_ESINGULAR, "Hessenberg QR did not converge");
+    double mx = -INFINITY;
+    for (const auto& e : ev) mx = std::max(mx, e.real());
+    return mx;
+}
+
+void ensure_krylov(phmg_ctx ctx, int restart);
+
+// lambda_max(M^{-1} K): largest real Ritz value of eig_iters Arnoldi steps
+// (CGS2) from v_0 = (1 + sin(j)/2) / ||.||, all vectors on the device.
+double arnoldi_estimate(phmg_ctx ctx, int l) {
     Level& L = ctx->L[l];
     hipStream_t s = ctx->stream;
-    double* v = L.d;        // the Chebyshev direction buffer doubles as the iterate here
-    double* w = L.r;
-    double* z = L.b ? L.b : L.x;
-    if (!z) z = ctx->L[0].x;
-    launch_power_start(s, L.n, v);
-    launch_multidot(s, L.n, 1, v, L.n, v, ctx->partial, ctx->scal, false);
-    launch_scale_by_devnorm(s, L.n, v, ctx->scal, v);
-    for (int it = 0; it < ctx->opts.eig_iters; ++it) {
-        launch_spmv(s, L.K, v, 1.0, nullptr, 0.0, w);
-        launch_patch_apply(s, L, w);
-        launch_scatter(s, L, 1.0, 0.0, nullptr, false, z, true);
-        launch_multidot(s, L.n, 1, z, L.n, z, ctx->partial, ctx->scal, false);
-        launch_scale_by_devnorm(s, L.n, z, ctx->scal, v);
+    const int64_t n = L.n;
+    int k = (int)std::min<int64_t>(ctx->opts.eig_iters, n);
+    ensure_krylov(ctx, std::max(ctx->restart_cap, k));
+    double* V = ctx->V;
+    double* w = ctx->w;
+    const int stride = ctx->restart_cap + 2;
+    double* h1 = ctx->hdev;
+    double* h2 = ctx->hdev + stride;
+    double* hn2 = ctx->hdev + 2 * stride;
+    launch_power_start(s, n, V);
+    launch_multidot(s, n, 1, V, n, V, ctx->partial, ctx->scal, false);
+    launch_scale_by_devnorm(s, n, V, ctx->scal, V);
+    std::vector<double> H((size_t)(k + 1) * k, 0.0);
+    for (int j = 0; j < k; ++j) {
+        launch_spmv(s, L.K, V + (int64_t)j * n, 1.0, nullptr, 0.0, L.r);
+        launch_patch_apply(s, L, L.r);
+        launch_scatter(s, L, 1.0, 0.0, nullptr, false, w, true);
+        launch_multidot(s, n, j + 1, V, n, w, ctx->partial, h1, false);
+        launch_gemv_sub(s, n, j + 1, V, n, h1, w);
+        launch_multidot(s, n, j + 1, V, n, w, ctx->partial, h2, false);
+        launch_gemv_sub(s, n, j + 1, V, n, h2, w);
+        launch_multidot(s, n, 1, w, n, w, ctx->partial, hn2, false);
+        hipcheck(hipMemcpyAsync(ctx->hhost, ctx->hdev, sizeof(double) * (2 * stride + 1), hipMemcpyDeviceToHost, s),
+                 "D2H");
+        hipcheck(hipStreamSynchronize(s), "hipStreamSynchronize");
+        for (int i = 0; i <= j; ++i) H[(size_t)j * (k + 1) + i] = ctx->hhost[i] + ctx->hhost[stride + i];
+        const double hn = std::sqrt(ctx->hhost[2 * stride]);
+        H[(size_t)j * (k + 1) + j + 1] = hn;
+        if (hn == 0.0) {
+            k = j + 1;
+            break;
+        }
+        if (j + 1 < k) launch_scale_copy(s, n, w, hn, V + (int64_t)(j + 1) * n);
     }
-    double n2 = 0.0;
-    hipcheck(hipMemcpyAsync(&n2, ctx->scal, sizeof(double), hipMemcpyDeviceToHost, s), "D2H");
-    hipcheck(hipStreamSynchronize(s), "hipStreamSynchronize");
-    return std::sqrt(n2);
+    return ritz_max_real(H.data(), k + 1, k);
 }
 
 void cycle(phmg_ctx ctx, int l, const double* b, double* x, bool x_zero) {
@@ -326,21 +453,38 @@ void setup_level(phmg_ctx ctx, int l) {
         L.factors = f64;
     } else {
         const size_t es = L.prec == PHMG_PREC_F32 ? 4 : 2;
+        const int64_t cnt = L.sum_lp[L.prec];
+        std::vector<int64_t> off(L.npatch);
+        {
+            std::vector<int64_t> hp(L.npatch + 1);
+            hipcheck(hipMemcpy(hp.data(), L.pptr, sizeof(int64_t) * (L.npatch + 1), hipMemcpyDeviceToHost), "D2H");
+            const int V = L.prec == PHMG_PREC_F32 ? 2 : 4;
+            int64_t acc = 0;
+            for (int32_t i = 0; i < L.npatch; ++i) {
+                const int64_t m = hp[i + 1] - hp[i];
+                off[i] = acc;
+                acc += (m + V - 1) / V * V * m;
+            }
+        }
+        if (L.fofflp) dfree(ctx, L.fofflp);
+        L.fofflp = upload(ctx, off.data(), L.npatch);
         void* lo = nullptr;
-        if (hipMalloc(&lo, es * (size_t)std::max<int64_t>(L.sum_m2, 1)) != hipSuccess) {
+        if (hipMalloc(&lo, es * (size_t)std::max<int64_t>(cnt, 1)) != hipSuccess) {
             (void)hipGetLastError();
             fail(PHMG_ENOMEM, lvl(l) + "factor allocation failed");
         }
         ctx->allocs.push_back(lo);
-        launch_convert(s, L.sum_m2, f64, lo, L.prec);
+        launch_convert_patches(s, L, f64, lo);
+        hipcheck(hipGetLastError(), "convert launch");
         L.factors = lo;
     }
     hipcheck(hipMemcpyAsync(&st, L.status, sizeof(int32_t), hipMemcpyDeviceToHost, s), "D2H");
     hipcheck(hipStreamSynchronize(s), "hipStreamSynchronize");
     if (L.prec != PHMG_PREC_F64) dfree(ctx, f64);
     if (st != INT32_MAX) fail(PHMG_ESINGULAR, lvl(l) + "patch " + std::to_string(st) + " is singular");
+    tune_apply(ctx, l);
     if (ctx->opts.smoother == PHMG_SMOOTHER_CHEBYSHEV) {
-        L.lmax = power_iteration(ctx, l);
+        L.lmax = arnoldi_estimate(ctx, l);
         if (!(L.lmax > 0.0) || !std::isfinite(L.lmax))
             fail(PHMG_ESINGULAR, lvl(l) + "eigenvalue estimate of M^{-1}K is not positive and finite");
     }
@@ -513,6 +657,17 @@ extern "C" {
 
 const char* phmg_last_error(void) { return g_last_error.c_str(); }
 
+phmg_status phmg_ritz_max_real(const double* H, int ldh, int k, double* out) {
+    return guarded([&]() -> phmg_status {
+        if (!H || !out || k < 1 || ldh < k) fail(PHMG_EINVAL, "invalid Hessenberg matrix arguments");
+        for (int j = 0; j < k; ++j)
+            for (int i = 0; i < k; ++i)
+                if (!std::isfinite(H[(size_t)j * ldh + i])) fail(PHMG_EINVAL, "non-finite Hessenberg entry");
+        *out = ritz_max_real(H, ldh, k);
+        return PHMG_OK;
+    });
+}
+
 phmg_status phmg_hierarchy_create(const phmg_hierarchy_desc* desc, const phmg_cycle_opts* opts, void* stream,
                                   phmg_ctx* out) {
     phmg_ctx ctx = nullptr;
@@ -604,6 +759,12 @@ phmg_status phmg_hierarchy_create(const phmg_hierarchy_desc* desc, const phmg_cy
                 }
                 L.sum_m2 = acc;
                 L.max_m = mx;
+                L.sum_lp[0] = acc;
+                for (int32_t i = 0; i < pt.npatch; ++i) {
+                    const int64_t m = pt.ptr[i + 1] - pt.ptr[i];
+                    L.sum_lp[1] += (m + 1) / 2 * 2 * m;
+                    L.sum_lp[2] += (m + 3) / 4 * 4 * m;
+                }
                 std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) {
                     return pt.ptr[a + 1] - pt.ptr[a] > pt.ptr[b + 1] - pt.ptr[b];
                 });
@@ -736,6 +897,7 @@ phmg_status phmg_get_level_info(phmg_ctx ctx, int level, phmg_level_info* info) 
         info->sum_m = L.sum_m;
         info->sum_m2 = L.sum_m2;
         info->lambda_max = L.lmax;
+        info->apply_variant = L.apply_variant;
         return PHMG_OK;
     });
 }

@@ -39,7 +39,9 @@ struct Level {
     int64_t* pptr = nullptr;         // npatch + 1
     int32_t* pdofs = nullptr;        // sum_m
     double* pweight = nullptr;       // sum_m or null (W_i = I)
-    int64_t* foff = nullptr;         // offset of patch i's m_i x m_i block (elements)
+    int64_t* foff = nullptr;         // offset of patch i's m_i x m_i block (elements, float64 layout)
+    int64_t* fofflp = nullptr;       // offsets of the reduced-precision layout (ld = m rounded up to 2 / 4)
+    int64_t sum_lp[3] = {0, 0, 0};   // element counts of the f64 / f32 / bf16 layouts
     int32_t* order = nullptr;        // launch order: patches by decreasing size
     int32_t* sptr = nullptr;         // DoF -> slot map for the scatter (n + 1)
     int32_t* sslot = nullptr;        // sum_m slot indices, ascending patch id per DoF
@@ -47,6 +49,8 @@ struct Level {
     void* factors = nullptr;         // explicit patch inverses, column-major, precision `prec`
     double* work64 = nullptr;        // float64 set-up buffer when prec != F64
     int prec = PHMG_PREC_F64;
+    int apply_variant = 0;           // kernel shape of the patch solve (chosen by the set-up autotuner)
+    int tuned_for = -1;              // precision the shape was tuned for
 
     // coarsest level: dense inverse of the (bordered) matrix, row-major
     double* cinv = nullptr;
@@ -110,8 +114,9 @@ void launch_spmv(hipStream_t s, const DevCsr& A, const double* x, double alpha, 
 void launch_extract(hipStream_t s, const Level& L, double* out);
 void launch_gj_invert(hipStream_t s, int npatch, const int64_t* pptr, const int64_t* foff, const int32_t* order,
                       double* A, int max_m, int* status);
-void launch_convert(hipStream_t s, int64_t n, const double* src, void* dst, int prec);
+void launch_convert_patches(hipStream_t s, const Level& L, const double* src, void* dst);
 void launch_patch_apply(hipStream_t s, const Level& L, const double* r);
+int apply_variant_count(int prec);
 // dn = a * sum_t w_t Y_t + c * d;  x = (x_zero ? 0 : x) + dn;  d = dn if store_d
 // (c = 0: d is not read; d may be null when c = 0 and !store_d)
 void launch_scatter(hipStream_t s, const Level& L, double a, double c, double* d, bool store_d, double* x,

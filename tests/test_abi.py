@@ -91,3 +91,25 @@ def test_rejects_bad_options():
     K, P, pts, z = _tiny_hierarchy()
     _expect_einval(K, P, pts, z, r"cycle options", n_v=0)
     _expect_einval(K, P, pts, z, r"cycle options", n_plevels=5)
+
+
+@pytest.mark.parametrize("seed", range(12))
+def test_host_hessenberg_qr_matches_lapack(seed):
+    """The host QR that turns Arnoldi's Hessenberg matrix into the Chebyshev bound."""
+    lib = _lib()
+    rng = np.random.default_rng(seed)
+    k = int(rng.integers(1, 31))
+    H = np.triu(rng.standard_normal((k + 1, k)), -1)
+    if seed % 3 == 0:                      # clustered spectrum like the smoother's
+        H[:k, :k] += np.diag(10.0 + 1e-3 * rng.standard_normal(k))
+    ref = np.linalg.eigvals(H[:k, :k]).real.max()
+    got = lib.ritz_max_real(H, k)
+    assert abs(got - ref) <= 1e-9 * max(1.0, abs(ref)), (k, got, ref)
+
+
+def test_host_hessenberg_qr_rejects_bad_input():
+    lib = _lib()
+    H = np.zeros((3, 2))
+    H[0, 0] = np.nan
+    with pytest.raises(lib.PhmgError):
+        lib.ritz_max_real(H, 2)

@@ -81,11 +81,11 @@ def test_chebyshev_error_propagator_closed_form(kind, k, mesh, nu):
     assert np.abs(got - ref).max() <= 1e-10 * np.abs(ref).max()
 
 
-def test_power_iteration_estimates_largest_eigenvalue():
+def test_arnoldi_estimates_largest_eigenvalue():
     d = assemble_stokes(synth.refine_uniform(synth.delaunay_square(8, seed=3)), 2, "TH")
     patches = vanka_star_patches(d)
     factors = relax.setup_patches(d.K, patches)
     K = d.K.toarray()
     ev = np.linalg.eigvals(_dense_Minv(K, patches, None) @ K)
-    lam = relax.estimate_lambda_max(d.K, patches, factors, None, 40)
-    assert 0.97 * np.abs(ev).max() <= lam <= 1.0001 * np.abs(ev).max()
+    lam = relax.estimate_lambda_max(d.K, patches, factors, None, 20)
+    assert 0.995 * ev.real.max() <= lam <= 1.0001 * ev.real.max()

@@ -134,6 +134,8 @@ def main() -> int:
                     help="apply: only the repeated level-0 relaxation sweeps (for counter runs)")
     ap.add_argument("--mixed", default="f32", choices=["f32", "bf16", "none"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="apply phase: also run 3 plain device copies of 256 MiB (counter calibration)")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -223,6 +225,13 @@ def main() -> int:
 
     if args.phase == "apply":
         legs = {p: apply_leg(p) for p in (["f64"] + ([] if args.mixed == "none" else [args.mixed]))}
+        if args.calibrate_copy:
+            src = torch.ones(1 << 25, dtype=torch.float64, device=dev)
+            dst = torch.empty_like(src)
+            for _ in range(3):
+                dst.copy_(src)
+            torch.cuda.synchronize()
+            legs["copy_bytes_each_way"] = src.numel() * 8
         print(json.dumps({"phase": "apply", "workload": args.workload, "apply": legs}), flush=True)
         H.close()
         return 0

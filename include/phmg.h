@@ -72,6 +72,8 @@ typedef struct {
 } phmg_patches;
 
 #define PHMG_MAX_PATCH 1024
+/* The coarsest level is solved with a dense inverse of its (bordered) matrix. */
+#define PHMG_MAX_COARSE 8192
 
 /* Cycle parameters (Section 3.1-3.2; V^{(n_V, nu_p, nu_h)} of Section 4):
  * levels 0 .. n_plevels-1 are p-levels relaxed with nu_p sweeps and coarsened

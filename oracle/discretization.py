@@ -27,7 +27,9 @@ Readings where the paper is silent (listed in the design notes as well):
 
 Pins: tests/test_oracle_discretization.py -- K symmetric, A SPD, K z = 0 for
 the constant pressure z, B annihilates interpolated curls of polynomials,
-and manufactured-solution L2 rates k+1 (velocity) and k (pressure).
+manufactured-solution L2 rates k+1 (velocity) and k (pressure), and for SV
+the direct pointwise divergence equals the projected one (-M_T^{-1} B u) on
+arbitrary velocity fields while for TH it does not.
 """
 from __future__ import annotations
 
@@ -294,4 +296,30 @@ def divergence_at_quadrature(disc: Stokes, x: np.ndarray, degree: int = None) ->
         grad = np.einsum("ij,qnj->qni", JinvT, dphi)
         vd = disc.V.cell_dofs[c]
         out.append(grad[:, :, 0] @ U[0, vd] + grad[:, :, 1] @ U[1, vd])
+    return np.concatenate(out)
+
+
+def divergence_projected(disc: Stokes, x: np.ndarray, degree: int = None) -> np.ndarray:
+    """div u_h at the quadrature points through the discrete identity div u_h = -M_T^{-1} (B u_h)_T.
+
+    For Scott-Vogelius div V_h is contained in the discontinuous pressure
+    space (Section 2.1), so on every cell T the divergence equals its own L2
+    projection onto P_{k-1}(T): coefficients c_T = M_T^{-1} (-B u_h)_T with the
+    cell pressure mass matrix M_T.  This evaluation avoids the cancellation of
+    summing u_a grad(phi_a) directly.  Only meaningful for "SV".
+    """
+    if disc.kind != "SV":
+        raise ValueError("the projection identity holds for Scott-Vogelius only")
+    k = disc.k
+    qp, qw = element.quadrature(degree or 2 * k)
+    psi, _ = element.eval_basis(k - 1, qp) if k - 1 >= 1 else (np.ones((len(qw), 1)), None)
+    U = full_velocity(disc, x)
+    Bu = disc.Bx_full @ U[0] + disc.By_full @ U[1]
+    verts, cells = disc.mesh.verts, disc.mesh.cells
+    out = []
+    for c in range(cells.shape[0]):
+        _, _, adet, _ = cell_geometry(verts, cells[c])
+        M = np.einsum("q,qi,qj->ij", qw * adet, psi, psi)
+        coef = np.linalg.solve(M, -Bu[disc.Q.cell_dofs[c]])
+        out.append(psi @ coef)
     return np.concatenate(out)

@@ -9,9 +9,12 @@ Readings where the paper is silent:
   * Orthogonalisation is classical Gram-Schmidt applied twice (CGS2): h =
     V^T w, w -= V h, h2 = V^T w, w -= V h2, h += h2.
   * Givens rotations: rho = hypot(a, b), c = a/rho, s = b/rho.
-  * Stop when the Givens residual estimate |g_{j+1}| <= rtol * ||r_0||, on an
-    exact breakdown (||w|| == 0), or after maxit inner iterations in total.
-    At a restart or exit x is updated with Z y and the true residual formed.
+  * A cycle ends when the Givens residual estimate |g_{j+1}| <= rtol * ||r_0||,
+    on an exact breakdown (||w|| == 0), after `restart` iterations, or at maxit
+    inner iterations in total.  x is then updated with Z y and the true
+    residual b - K x formed; the solve has converged when the true residual
+    satisfies ||b - K x|| <= rtol ||r_0|| (the paper's criterion is the
+    residual itself), otherwise it restarts unless maxit is reached.
   * x_0 is the initial guess given (zero in every benchmark); r_0 = b - K x_0.
 
 Pins: tests/test_oracle_fgmres.py -- with the identity preconditioner the
@@ -59,7 +62,6 @@ def fgmres(matvec: Callable, precond: Callable, b: np.ndarray, x0: np.ndarray = 
         g[0] = beta
         V[:, 0] = r / beta
         ncols = 0
-        stop = False
         for j in range(restart):
             Z[:, j] = precond(V[:, j])
             w = matvec(Z[:, j])
@@ -85,12 +87,7 @@ def fgmres(matvec: Callable, precond: Callable, b: np.ndarray, x0: np.ndarray = 
             iters += 1
             ncols = j + 1
             history.append(abs(g[j + 1]) / r0)
-            if abs(g[j + 1]) <= target:
-                converged = True
-                stop = True
-                break
-            if hn == 0.0 or iters >= maxit:
-                stop = True
+            if abs(g[j + 1]) <= target or hn == 0.0 or iters >= maxit:
                 break
             V[:, j + 1] = w / hn
         y = np.zeros(ncols)
@@ -99,8 +96,11 @@ def fgmres(matvec: Callable, precond: Callable, b: np.ndarray, x0: np.ndarray = 
         x = x + Z[:, :ncols] @ y
         r = b - matvec(x)
         beta = np.linalg.norm(r)
-        if stop:
-            if not converged and hn == 0.0:
-                converged = beta <= target
+        if beta <= target:
+            converged = True
             break
+        if iters >= maxit:
+            break
+        # restart: the cycle is exhausted, or the Givens estimate was below the
+        # target while the true residual is not (rounding), or an exact breakdown
     return FgmresResult(x, iters, converged, beta / r0, history)

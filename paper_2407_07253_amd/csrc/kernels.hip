@@ -421,6 +421,178 @@ __global__ __launch_bounds__(kBlock) void convert_patch_kernel(const int64_t* __
     }
 }
 
+// ---------------------------------------------------------------------------
+// Dense Gauss-Jordan inversion of one large matrix (the coarsest level) over
+// the whole GPU: per panel of w columns, gj_panel_kernel (one workgroup,
+// panel in LDS) eliminates the panel with partial pivoting and writes it
+// back with its pivots; gj_update_kernel (one wavefront per 16-column block)
+// applies the panel's row swaps to its columns and the rank-w update on MFMA
+// f64 16x16x4 tiles.  gj_unscramble_kernel undoes the pivoting (column swaps
+// in reverse order), one thread per row.  Column-major N x N.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kBlock) void gj_panel_kernel(double* __restrict__ A, int N, int k0, int w,
+                                                          int* __restrict__ piv, int* __restrict__ status,
+                                                          const double* __restrict__ tolp) {
+    extern __shared__ double smem[];
+    double* Q = smem;               // N x w
+    double* fcol = Q + (int64_t)N * w;
+    __shared__ double s_val[kBlock / kWave];
+    __shared__ int s_idx[kBlock / kWave];
+    __shared__ int s_fail;
+    __shared__ int s_piv[kPanel];
+    const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
+    const double tol = tolp[0];
+    if (status[0] != INT32_MAX) return;            // an earlier panel failed
+    for (int e = tid; e < N * w; e += kBlock) {
+        const int i = e % N, c = e / N;
+        Q[i + (int64_t)c * N] = A[i + (int64_t)(k0 + c) * N];
+    }
+    if (tid == 0) s_fail = 0;
+    __syncthreads();
+    for (int c = 0; c < w; ++c) {
+        const int k = k0 + c;
+        double bv = -1.0;
+        int bi = INT_MAX;
+        for (int i = k + tid; i < N; i += kBlock) {
+            const double v = fabs(Q[i + (int64_t)c * N]);
+            if (v > bv) { bv = v; bi = i; }
+        }
+        for (int off = kWave / 2; off > 0; off >>= 1) {
+            const double ov = __shfl_xor(bv, off);
+            const int oi = __shfl_xor(bi, off);
+            if (ov > bv || (ov == bv && oi < bi)) { bv = ov; bi = oi; }
+        }
+        if (lane == 0) { s_val[wave] = bv; s_idx[wave] = bi; }
+        __syncthreads();
+        if (tid == 0) {
+            for (int q = 1; q < kBlock / kWave; ++q)
+                if (s_val[q] > bv || (s_val[q] == bv && s_idx[q] < bi)) { bv = s_val[q]; bi = s_idx[q]; }
+            if (bi >= N || !(bv > tol)) s_fail = 1;
+            s_piv[c] = bi < N ? bi : k;
+        }
+        __syncthreads();
+        if (s_fail) {
+            if (tid == 0) atomicMin(status, 0);
+            return;
+        }
+        const int pr = s_piv[c];
+        if (pr != k && tid < w) {
+            const double t = Q[k + (int64_t)tid * N];
+            Q[k + (int64_t)tid * N] = Q[pr + (int64_t)tid * N];
+            Q[pr + (int64_t)tid * N] = t;
+        }
+        __syncthreads();
+        const double d = 1.0 / Q[k + (int64_t)c * N];
+        for (int i = tid; i < N; i += kBlock) fcol[i] = Q[i + (int64_t)c * N];
+        __syncthreads();
+        if (tid < w) Q[k + (int64_t)tid * N] = (tid == c) ? d : Q[k + (int64_t)tid * N] * d;
+        __syncthreads();
+        for (int e = tid; e < N * w; e += kBlock) {
+            const int i = e % N, cc = e / N;
+            if (i == k) continue;
+            const double f = fcol[i];
+            if (cc == c) Q[i + (int64_t)c * N] = -f * d;
+            else Q[i + (int64_t)cc * N] -= f * Q[k + (int64_t)cc * N];
+        }
+        __syncthreads();
+    }
+    for (int e = tid; e < N * w; e += kBlock) {
+        const int i = e % N, c = e / N;
+        A[i + (int64_t)(k0 + c) * N] = Q[i + (int64_t)c * N];
+    }
+    if (tid < w) piv[k0 + tid] = s_piv[tid];
+}
+
+// one wavefront per 16-column block outside the panel
+__global__ __launch_bounds__(kBlock) void gj_update_kernel(double* __restrict__ A, int N, int k0, int w,
+                                                           const int* __restrict__ piv,
+                                                           const int* __restrict__ status) {
+    if (status[0] != INT32_MAX) return;
+    const int lane = threadIdx.x & (kWave - 1);
+    const int jb = (blockIdx.x * blockDim.x + threadIdx.x) / kWave;
+    const int nb16 = (N + 15) / 16;
+    if (jb >= nb16) return;
+    const int li = lane & 15, lk = lane >> 4;
+    const int j = jb * 16 + li;
+    const bool jv = (j < N) && (j < k0 || j >= k0 + w);
+    if (jv) {
+        double* cj = A + (int64_t)j * N;
+        for (int c = 0; c < w; ++c) {
+            const int pr = piv[k0 + c];
+            if (pr != k0 + c && lk == 0) {
+                const double t = cj[k0 + c];
+                cj[k0 + c] = cj[pr];
+                cj[pr] = t;
+            }
+        }
+    }
+    // the swaps (lane lk == 0 of each column) must be visible to the other lanes of the wave
+    __threadfence_block();
+    __builtin_amdgcn_wave_barrier();
+    __threadfence_block();
+    double bop[4];
+#pragma unroll
+    for (int kt = 0; kt < 4; ++kt) {
+        const int kk = kt * 4 + lk;
+        bop[kt] = (jv && kk < w) ? A[(k0 + kk) + (int64_t)j * N] : 0.0;
+    }
+    const bool any = __any(jv ? 1 : 0);
+    if (!any) return;
+    for (int ib = 0; ib < nb16; ++ib) {
+        d4 acc;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int i = ib * 16 + lk + 4 * v;
+            acc[v] = (jv && i < N) ? A[i + (int64_t)j * N] : 0.0;
+        }
+#pragma unroll
+        for (int kt = 0; kt < 4; ++kt) {
+            const int i = ib * 16 + li, kk = kt * 4 + lk;
+            double aop = 0.0;
+            if (i < N && kk < w) {
+                aop = A[i + (int64_t)(k0 + kk) * N];
+                if (i == k0 + kk) aop -= 1.0;
+            }
+            acc = __builtin_amdgcn_mfma_f64_16x16x4f64(aop, bop[kt], acc, 0, 0, 0);
+        }
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int i = ib * 16 + lk + 4 * v;
+            if (jv && i < N) A[i + (int64_t)j * N] = acc[v];
+        }
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void gj_unscramble_kernel(double* __restrict__ A, int N,
+                                                               const int* __restrict__ piv) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= N) return;
+    for (int k = N - 1; k >= 0; --k) {
+        const int pr = piv[k];
+        if (pr != k) {
+            const double t = A[i + (int64_t)k * N];
+            A[i + (int64_t)k * N] = A[i + (int64_t)pr * N];
+            A[i + (int64_t)pr * N] = t;
+        }
+    }
+}
+
+// tol = 1e-14 * max_i sum_j |A_ij| (column-major N x N), one block
+__global__ __launch_bounds__(kBlock) void inf_norm_tol_kernel(const double* __restrict__ A, int N,
+                                                              double* __restrict__ tol) {
+    __shared__ double sh[kBlock / kWave];
+    double rs = 0.0;
+    for (int i = threadIdx.x; i < N; i += kBlock) {
+        double s = 0.0;
+        for (int j = 0; j < N; ++j) s += fabs(A[i + (int64_t)j * N]);
+        rs = fmax(rs, s);
+    }
+    for (int off = kWave / 2; off > 0; off >>= 1) rs = fmax(rs, __shfl_xor(rs, off));
+    if ((threadIdx.x & (kWave - 1)) == 0) sh[threadIdx.x / kWave] = rs;
+    __syncthreads();
+    if (threadIdx.x == 0) tol[0] = 1e-14 * fmax(fmax(sh[0], sh[1]), fmax(sh[2], sh[3]));
+}
+
 // s_j = sum_{slots t of DoF j, ascending patch id} w_t Y[t];  dn = a s_j + c d_j;
 // x_j = (x_zero ? 0 : x_j) + dn;  d_j = dn when storing (Chebyshev direction).
 // Richardson is a = omega, c = 0.
@@ -685,6 +857,29 @@ void launch_power_start(hipStream_t s, int64_t n, double* v) {
 void launch_scale_by_devnorm(hipStream_t s, int64_t n, const double* src, const double* norm2, double* dst) {
     hipLaunchKernelGGL(scale_by_devnorm_kernel, dim3(std::min(grid_for(n, kBlock), 4096)), dim3(kBlock), 0, s, n,
                        src, norm2, dst);
+}
+
+int coarse_panel_width(int N) {
+    // the panel (N x w doubles) and one column must fit in LDS (<= 150 KiB)
+    for (int w = kPanel; w >= 1; w /= 2)
+        if ((size_t)N * (w + 1) * sizeof(double) <= 150 * 1024) return w;
+    return 0;
+}
+
+void launch_dense_gj(hipStream_t s, double* A, int N, int* piv, int* status, double* tol) {
+    const int w0 = coarse_panel_width(N);
+    hipLaunchKernelGGL(inf_norm_tol_kernel, dim3(1), dim3(kBlock), 0, s, A, N, tol);
+    const size_t lds = (size_t)N * (w0 + 1) * sizeof(double);
+    if (lds > 64 * 1024)
+        (void)hipFuncSetAttribute((const void*)gj_panel_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    const int nb16 = (N + 15) / 16;
+    const int grid_upd = (nb16 * kWave + kBlock - 1) / kBlock;
+    for (int k0 = 0; k0 < N; k0 += w0) {
+        const int w = std::min(w0, N - k0);
+        hipLaunchKernelGGL(gj_panel_kernel, dim3(1), dim3(kBlock), lds, s, A, N, k0, w, piv, status, tol);
+        hipLaunchKernelGGL(gj_update_kernel, dim3(grid_upd), dim3(kBlock), 0, s, A, N, k0, w, piv, status);
+    }
+    hipLaunchKernelGGL(gj_unscramble_kernel, dim3(grid_for(N, kBlock)), dim3(kBlock), 0, s, A, N, piv);
 }
 
 void launch_coarse_build(hipStream_t s, const Level& L, double* dense) {

@@ -414,15 +414,11 @@ void setup_level(phmg_ctx ctx, int l) {
     hipcheck(hipMemcpyAsync(L.status, &st, sizeof(int32_t), hipMemcpyHostToDevice, s), "status reset");
     if (l == last) {
         double* dense = dalloc<double>(ctx, (int64_t)L.nb * L.nb);
+        int* piv = dalloc<int>(ctx, L.nb);
         launch_coarse_build(s, L, dense);
-        int64_t* cptr = dalloc<int64_t>(ctx, 2);
-        int64_t* coff = dalloc<int64_t>(ctx, 1);
-        const int64_t hp[2] = {0, L.nb}, ho = 0;
-        hipcheck(hipMemcpyAsync(cptr, hp, sizeof(hp), hipMemcpyHostToDevice, s), "H2D");
-        hipcheck(hipMemcpyAsync(coff, &ho, sizeof(ho), hipMemcpyHostToDevice, s), "H2D");
         {
             Timed t(ctx, PHMG_K_FACTOR, l);
-            launch_gj_invert(s, 1, cptr, coff, nullptr, dense, L.nb, L.status);
+            launch_dense_gj(s, dense, L.nb, piv, L.status, ctx->scal + 4);
             hipcheck(hipGetLastError(), "coarse factorisation launch");
         }
         if (!L.cinv) L.cinv = dalloc<double>(ctx, (int64_t)L.nb * L.nb);
@@ -430,8 +426,7 @@ void setup_level(phmg_ctx ctx, int l) {
         hipcheck(hipMemcpyAsync(&st, L.status, sizeof(int32_t), hipMemcpyDeviceToHost, s), "D2H");
         hipcheck(hipStreamSynchronize(s), "hipStreamSynchronize");
         dfree(ctx, dense);
-        dfree(ctx, cptr);
-        dfree(ctx, coff);
+        dfree(ctx, piv);
         if (st != INT32_MAX) fail(PHMG_ESINGULAR, lvl(l) + "coarse matrix is singular");
         L.ready = true;
         return;
@@ -548,15 +543,12 @@ phmg_status fgmres(phmg_ctx ctx, const double* b, double* x, double rtol, int re
     bool converged = false;
     std::vector<double> H((restart + 1) * restart), cs(restart), sn(restart), g(restart + 1), y(restart);
     auto Hij = [&](int i, int j) -> double& { return H[(size_t)j * (restart + 1) + i]; };
-    double* ydev = ctx->hdev + 2 * (restart + 2) + 1;   // restart doubles fit in h2's slot after use
-    (void)ydev;
     for (;;) {
         std::fill(H.begin(), H.end(), 0.0);
         std::fill(g.begin(), g.end(), 0.0);
         g[0] = beta;
         launch_scale_copy(s, n, r, beta, V);
         int ncols = 0;
-        bool stop = false;
         double hn = 0.0;
         for (int j = 0; j < restart; ++j) {
             double* vj = V + (int64_t)j * n;
@@ -592,15 +584,7 @@ phmg_status fgmres(phmg_ctx ctx, const double* b, double* x, double rtol, int re
             g[j] = cs[j] * g[j];
             ++iters;
             ncols = j + 1;
-            if (std::fabs(g[j + 1]) <= target) {
-                converged = true;
-                stop = true;
-                break;
-            }
-            if (hn == 0.0 || iters >= maxit) {
-                stop = true;
-                break;
-            }
+            if (std::fabs(g[j + 1]) <= target || hn == 0.0 || iters >= maxit) break;
             launch_scale_copy(s, n, w, hn, V + (int64_t)(j + 1) * n);
         }
         for (int i = ncols - 1; i >= 0; --i) {
@@ -613,10 +597,12 @@ phmg_status fgmres(phmg_ctx ctx, const double* b, double* x, double rtol, int re
         launch_gemv_add(s, n, ncols, Z, n, yd, x);
         launch_spmv(s, L0.K, x, -1.0, b, 1.0, r);
         beta = device_norm(ctx, r);
-        if (stop) {
-            if (!converged && hn == 0.0) converged = beta <= target;
+        if (beta <= target) {
+            converged = true;
             break;
         }
+        if (iters >= maxit) break;
+        // restart: cycle exhausted, optimistic Givens estimate, or exact breakdown
     }
     *iters_out = iters;
     *relres_out = beta / r0;
@@ -718,9 +704,9 @@ phmg_status phmg_hierarchy_create(const phmg_hierarchy_desc* desc, const phmg_cy
             if (pt.ptr[pt.npatch] >= (int64_t)INT32_MAX) fail(PHMG_EINVAL, lvl(l) + "too many patch slots");
         }
         const int32_t nc = desc->K[nl - 1].nrows;
-        if (nc + 1 > PHMG_MAX_PATCH)
+        if (nc > PHMG_MAX_COARSE)
             fail(PHMG_EINVAL, "coarsest level has " + std::to_string(nc) + " DoFs; the dense coarse solve supports at most " +
-                                  std::to_string(PHMG_MAX_PATCH - 1));
+                                  std::to_string(PHMG_MAX_COARSE));
         if (desc->coarse_null)
             for (int32_t i = 0; i < nc; ++i)
                 if (!std::isfinite(desc->coarse_null[i])) fail(PHMG_EINVAL, "non-finite coarse_null");

@@ -124,6 +124,9 @@ void launch_scatter(hipStream_t s, const Level& L, double a, double c, double* d
 void launch_power_start(hipStream_t s, int64_t n, double* v);
 void launch_scale_by_devnorm(hipStream_t s, int64_t n, const double* src, const double* norm2, double* dst);
 void launch_coarse_build(hipStream_t s, const Level& L, double* dense);
+int coarse_panel_width(int N);   // 0 when N is too large for the dense coarse solve
+// in-place inverse of a column-major N x N matrix over the whole GPU (status: INT32_MAX = ok)
+void launch_dense_gj(hipStream_t s, double* A, int N, int* piv, int* status, double* tol);
 void launch_transpose(hipStream_t s, int n, const double* src, double* dst);
 void launch_coarse_solve(hipStream_t s, const Level& L, const double* b, double* x);
 // FGMRES helpers

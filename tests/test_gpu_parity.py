@@ -181,3 +181,28 @@ def test_singular_patch_is_reported_with_its_id():
                 if j in set(L0.patch_dofs[L0.patch_ptr[i]:L0.patch_ptr[i + 1]]))
     assert f"patch {first} is singular" in str(e.value)
     H.close()
+
+
+@pytest.mark.parametrize("prec", ["f32", "bf16"])
+def test_mixed_precision_factors_reach_fp64_residual(prec):
+    """Patch inverses stored in f32 / bf16 (apply accumulates in f32); FGMRES in f64 restores the
+    1e-8 residual; the solution is compared with the FP64 oracle's."""
+    from paper_2407_07253_amd._lib import Hierarchy
+    fh, _, ol, od, oopts, ob = _pair("cfg2_r1")
+    H = Hierarchy.from_frontend(fh)
+    for l in range(len(fh.levels) - 1):
+        H.set_precision(l, prec)
+    H.setup()
+    x = _dev(np.zeros_like(ob))
+    iters, relres, conv = H.fgmres(_dev(fh.b[0]), x, rtol=1e-8)
+    got = _host(x)
+    K = ol[0].K
+    true = np.linalg.norm(ob - K @ got) / np.linalg.norm(ob)
+    res = ofgmres.fgmres(lambda v: K @ v, lambda v: omg.vcycle(ol, oopts, v), ob, rtol=1e-8)
+    nfu = od[0].nfu
+    err = np.linalg.norm(_normalise(got, nfu) - _normalise(res.x, nfu)) / np.linalg.norm(_normalise(res.x, nfu))
+    print(f"{prec}: iters {iters} (fp64 oracle {res.iters}), residual {true:.2e}, error vs fp64 oracle {err:.2e}")
+    assert conv and true <= 1.05e-8
+    assert iters <= res.iters + 10
+    assert err <= 1e-5
+    H.close()

@@ -124,3 +124,21 @@ def test_sv_velocity_is_pointwise_divergence_free_th_is_not():
     divth = divergence_at_quadrature(dth, _direct(dth))
     assert np.abs(divsv).max() < 1e-9
     assert np.abs(divth).max() > 1e-6
+
+
+def test_sv_divergence_lies_in_pressure_space():
+    """div V_h is inside the discontinuous pressure space for SV (Section 2.1): the direct evaluation
+    of div u_h equals -M_T^{-1} (B u_h)_T on every cell for an arbitrary velocity; not so for TH."""
+    from oracle.discretization import divergence_projected
+    m = synth.alfeld_split(synth.delaunay_square(6, seed=8))
+    d = assemble_stokes(m, 3, "SV")
+    rng = np.random.default_rng(5)
+    x = rng.standard_normal(d.n)
+    direct = divergence_at_quadrature(d, x)
+    proj = divergence_projected(d, x)
+    assert np.abs(direct - proj).max() <= 1e-9 * np.abs(direct).max()
+    dth = assemble_stokes(m, 3, "TH")
+    dth.kind = "SV"          # force the identity on TH to show it fails there
+    xt = rng.standard_normal(dth.n)
+    gap = np.abs(divergence_at_quadrature(dth, xt) - divergence_projected(dth, xt)).max()
+    assert gap > 1e-2 * np.abs(divergence_at_quadrature(dth, xt)).max()

@@ -82,8 +82,10 @@ __global__ __launch_bounds__(kBlock) void extract_kernel(const int64_t* __restri
                                                          const int64_t* __restrict__ foff,
                                                          const int32_t* __restrict__ rowptr,
                                                          const int32_t* __restrict__ col,
-                                                         const double* __restrict__ val, double* __restrict__ out) {
+                                                         const double* __restrict__ val, double* __restrict__ out,
+                                                         double* __restrict__ ptol) {
     extern __shared__ int32_t s_dofs[];
+    __shared__ double s_max[kBlock / kWave];
     const int p = blockIdx.x;
     const int64_t base = pptr[p];
     const int m = (int)(pptr[p + 1] - base);
@@ -93,9 +95,11 @@ __global__ __launch_bounds__(kBlock) void extract_kernel(const int64_t* __restri
     for (int64_t e = threadIdx.x; e < mm; e += blockDim.x) A[e] = 0.0;
     __syncthreads();
     const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
+    double rmax = 0.0;
     for (int a = wave; a < m; a += kBlock / kWave) {
         const int g = s_dofs[a];
         const int end = rowptr[g + 1];
+        double rsum = 0.0;
         for (int k = rowptr[g] + lane; k < end; k += kWave) {
             const int c = col[k];
             int lo = 0, hi = m;
@@ -103,119 +107,137 @@ __global__ __launch_bounds__(kBlock) void extract_kernel(const int64_t* __restri
                 const int mid = (lo + hi) >> 1;
                 if (s_dofs[mid] < c) lo = mid + 1; else hi = mid;
             }
-            if (lo < m && s_dofs[lo] == c) A[a + (int64_t)lo * m] = val[k];
+            if (lo < m && s_dofs[lo] == c) {
+                A[a + (int64_t)lo * m] = val[k];
+                rsum += fabs(val[k]);
+            }
         }
+        for (int off = kWave / 2; off > 0; off >>= 1) rsum += __shfl_xor(rsum, off);
+        rmax = fmax(rmax, rsum);
     }
+    if (lane == 0) s_max[wave] = rmax;
+    __syncthreads();
+    if (threadIdx.x == 0)
+        ptol[p] = 1e-14 * fmax(fmax(s_max[0], s_max[1]), fmax(s_max[2], s_max[3]));
 }
 
 // ---------------------------------------------------------------------------
 // Blocked Gauss-Jordan inversion with partial pivoting, in place, one
-// workgroup per matrix.  Column-major m x m at F + foff[p].
+// workgroup per patch matrix (column-major m x m at F + foff[p]).
 //
-// Panels of 16 columns are eliminated in LDS (pivot = largest |entry| on or
-// below the diagonal of the current column, ties to the lowest row, exactly
-// the pivot sequence of LU with partial pivoting).  The panel's row swaps are
-// then applied to the other columns and those columns receive the rank-16
-// update  A[:, R] += (Q - E) A_old[k0:k0+16, R]  on MFMA f64 16x16x4 tiles,
-// where Q is the eliminated panel and E the identity rows of the panel.  The
-// pivoting is undone at the end by column swaps in reverse order.
+// Panels of 16 columns are eliminated in LDS.  Pivoting is tracked through
+// logical row positions, so no panel row moves: the pivot is the largest
+// |entry| among rows at logical position >= k, ties to the lowest logical
+// position -- the pivot sequence of LU with partial pivoting.  A step costs two
+// barriers (publish the per-wave candidates; publish a copy of the pivot row).
+// The panel's row swaps are applied to the other columns, which then receive
+// the rank-16 update A[:, R] += (Q - E) A_old[k0:k0+16, R] on MFMA f64
+// 16x16x4 tiles, Q being the eliminated panel in logical row order and E the
+// identity rows of the panel; the panel goes back to A in logical order.
+//
+// The column interchanges that would turn the result into K_i^{-1} are not
+// performed: what is stored is B = (P K_i)^{-1}, and K_i^{-1} r = B (P r).  The
+// kernel writes the permuted DoF list pdofs_perm[t] = pdofs[idx[t]] (idx =
+// identity with the swaps applied in order), so the patch solve gathers P r
+// at no extra cost.  The singularity threshold 1e-14 ||K_i||_inf comes from
+// the extraction kernel.
 //
 // MFMA f64 16x16x4 lane layout (lane l, accumulator element v):
 //   A operand A[l % 16][l / 16], B operand B[l / 16][l % 16],
 //   C/D element D[l / 16 + 4 v][l % 16].
 // ---------------------------------------------------------------------------
+template <int R>
 __global__ __launch_bounds__(kBlock) void gj_kernel(const int64_t* __restrict__ pptr,
                                                     const int64_t* __restrict__ foff,
                                                     const int32_t* __restrict__ order, double* __restrict__ F,
-                                                    int ldq, int* __restrict__ status) {
+                                                    const double* __restrict__ ptol,
+                                                    const int32_t* __restrict__ pdofs,
+                                                    int32_t* __restrict__ pdofs_perm, int ldq,
+                                                    int* __restrict__ status) {
+    constexpr int W = kPanel, NWV = kBlock / kWave;
+    __shared__ double s_cv[2][NWV];
+    __shared__ int s_ci[2][NWV];
+    __shared__ int s_cp[2][NWV];
+    __shared__ int s_phys_at[2];
+    __shared__ int s_piv_panel[W];
+    __shared__ double s_prow[2][W];
     extern __shared__ double smem[];
-    double* Q = smem;                        // ldq x kPanel, column-major
-    double* fcol = Q + (int64_t)ldq * kPanel;  // ldq
-    int* piv = (int*)(fcol + ldq);           // ldq
-    __shared__ double s_val[kBlock / kWave];
-    __shared__ int s_idx[kBlock / kWave];
-    __shared__ double s_tol;
-    __shared__ int s_fail;
+    double* Q = smem;                                  // ldq x W, physical rows
+    int* s_phys = (int*)(Q + (int64_t)ldq * W);        // logical -> physical (m)
+    int* piv = s_phys + ldq;                           // pivots of the whole patch (m)
 
     const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
     const int p = order ? order[blockIdx.x] : (int)blockIdx.x;
-    const int m = (int)(pptr[p + 1] - pptr[p]);
+    const int64_t base = pptr[p];
+    const int m = (int)(pptr[p + 1] - base);
     double* A = F + foff[p];
+    const double tol = ptol[p];
 
-    // ||A||_inf = max_i sum_j |A_ij|
-    double rs = 0.0;
-    for (int i = tid; i < m; i += kBlock) {
-        double s = 0.0;
-        for (int j = 0; j < m; ++j) s += fabs(A[i + (int64_t)j * m]);
-        rs = fmax(rs, s);
-    }
-    for (int off = kWave / 2; off > 0; off >>= 1) rs = fmax(rs, __shfl_xor(rs, off));
-    if (lane == 0) s_val[wave] = rs;
-    __syncthreads();
-    if (tid == 0) {
-        double mx = 0.0;
-        for (int q = 0; q < kBlock / kWave; ++q) mx = fmax(mx, s_val[q]);
-        s_tol = 1e-14 * mx;
-        s_fail = 0;
-    }
-    __syncthreads();
-    const double tol = s_tol;
-
-    for (int k0 = 0; k0 < m; k0 += kPanel) {
-        const int w = min(kPanel, m - k0);
-        for (int e = tid; e < m * w; e += kBlock) {
-            const int i = e % m, c = e / m;
-            Q[i + c * ldq] = A[i + (int64_t)(k0 + c) * m];
-        }
+    for (int k0 = 0; k0 < m; k0 += W) {
+        const int w = min(W, m - k0);
+        for (int c = 0; c < w; ++c)
+            for (int i = tid; i < m; i += kBlock) Q[i + c * ldq] = A[i + (int64_t)(k0 + c) * m];
+        int lpos[R];
+#pragma unroll
+        for (int q = 0; q < R; ++q) lpos[q] = tid + q * kBlock;
+        for (int i = tid; i < m; i += kBlock) s_phys[i] = i;
         __syncthreads();
         for (int c = 0; c < w; ++c) {
-            const int k = k0 + c;
+            const int k = k0 + c, buf = c & 1;
             double bv = -1.0;
-            int bi = INT_MAX;
-            for (int i = k + tid; i < m; i += kBlock) {
-                const double v = fabs(Q[i + c * ldq]);
-                if (v > bv) { bv = v; bi = i; }
+            int bl = INT_MAX, bp = -1;
+#pragma unroll
+            for (int q = 0; q < R; ++q) {
+                const int r = tid + q * kBlock;
+                if (r < m && lpos[q] >= k) {
+                    const double a = fabs(Q[r + c * ldq]);
+                    if (a > bv || (a == bv && lpos[q] < bl)) { bv = a; bl = lpos[q]; bp = r; }
+                }
             }
             for (int off = kWave / 2; off > 0; off >>= 1) {
                 const double ov = __shfl_xor(bv, off);
-                const int oi = __shfl_xor(bi, off);
-                if (ov > bv || (ov == bv && oi < bi)) { bv = ov; bi = oi; }
+                const int ol = __shfl_xor(bl, off), op = __shfl_xor(bp, off);
+                if (ov > bv || (ov == bv && ol < bl)) { bv = ov; bl = ol; bp = op; }
             }
-            if (lane == 0) { s_val[wave] = bv; s_idx[wave] = bi; }
-            __syncthreads();
-            if (tid == 0) {
-                for (int q = 1; q < kBlock / kWave; ++q) {
-                    if (s_val[q] > bv || (s_val[q] == bv && s_idx[q] < bi)) { bv = s_val[q]; bi = s_idx[q]; }
-                }
-                if (bi >= m || !(bv > tol)) s_fail = 1;
-                piv[k] = bi < m ? bi : k;
+            if (lane == 0) { s_cv[buf][wave] = bv; s_ci[buf][wave] = bl; s_cp[buf][wave] = bp; }
+            if (tid == 0) s_phys_at[buf] = s_phys[k];
+            __syncthreads();                                          // barrier A
+            bv = s_cv[buf][0]; bl = s_ci[buf][0]; bp = s_cp[buf][0];
+            for (int q = 1; q < NWV; ++q) {
+                const double ov = s_cv[buf][q];
+                const int ol = s_ci[buf][q];
+                if (ov > bv || (ov == bv && ol < bl)) { bv = ov; bl = ol; bp = s_cp[buf][q]; }
             }
-            __syncthreads();
-            if (s_fail) {
+            if (bp < 0 || !(bv > tol)) {                              // uniform decision
                 if (tid == 0) atomicMin(status, p);
                 return;
             }
-            const int pr = piv[k];
-            if (pr != k && tid < w) {
-                const double t = Q[k + tid * ldq];
-                Q[k + tid * ldq] = Q[pr + tid * ldq];
-                Q[pr + tid * ldq] = t;
+            const int rk = s_phys_at[buf];
+            if (tid < w) s_prow[buf][tid] = Q[bp + tid * ldq];
+            if (tid == 0) {
+                s_piv_panel[c] = bl;
+                s_phys[bl] = rk;
+                s_phys[k] = bp;
             }
-            __syncthreads();
-            const double d = 1.0 / Q[k + c * ldq];
-            for (int i = tid; i < m; i += kBlock) fcol[i] = Q[i + c * ldq];
-            __syncthreads();
-            if (tid < w) Q[k + tid * ldq] = (tid == c) ? d : Q[k + tid * ldq] * d;
-            __syncthreads();
-            for (int e = tid; e < m * w; e += kBlock) {
-                const int i = e % m, cc = e / m;
-                if (i == k) continue;
-                const double f = fcol[i];
-                if (cc == c) Q[i + c * ldq] = -f * d;
-                else Q[i + cc * ldq] -= f * Q[k + cc * ldq];
+            __syncthreads();                                          // barrier B
+            const double d = 1.0 / s_prow[buf][c];
+#pragma unroll
+            for (int q = 0; q < R; ++q) {
+                const int r = tid + q * kBlock;
+                if (r >= m) continue;
+                if (r == bp) {
+                    for (int cc = 0; cc < w; ++cc) Q[r + cc * ldq] = (cc == c) ? d : s_prow[buf][cc] * d;
+                    lpos[q] = k;
+                } else {
+                    const double f = Q[r + c * ldq];
+                    for (int cc = 0; cc < w; ++cc)
+                        Q[r + cc * ldq] = (cc == c) ? -f * d : Q[r + cc * ldq] - f * (s_prow[buf][cc] * d);
+                    if (r == rk) lpos[q] = bl;
+                }
             }
-            __syncthreads();
         }
+        if (tid < w) piv[k0 + tid] = s_piv_panel[tid];
+        __syncthreads();
         // row swaps of this panel in every other column
         for (int j = tid; j < m; j += kBlock) {
             if (j >= k0 && j < k0 + w) continue;
@@ -230,62 +252,79 @@ __global__ __launch_bounds__(kBlock) void gj_kernel(const int64_t* __restrict__ 
             }
         }
         __syncthreads();
-        // rank-w update of the other columns on MFMA f64 16x16x4
+        // rank-w update of the other columns on MFMA f64 16x16x4 (A operand from LDS, logical rows)
         {
             const int nb16 = (m + 15) / 16;
             const int li = lane & 15, lk = lane >> 4;
-            for (int jb = wave; jb < nb16; jb += kBlock / kWave) {
+            for (int jb = wave; jb < nb16; jb += NWV) {
                 const int j = jb * 16 + li;
                 const bool jv = (j < m) && (j < k0 || j >= k0 + w);
+                if (!__any(jv ? 1 : 0)) continue;
                 double bop[4];
 #pragma unroll
                 for (int kt = 0; kt < 4; ++kt) {
                     const int kk = kt * 4 + lk;
                     bop[kt] = (jv && kk < w) ? A[(k0 + kk) + (int64_t)j * m] : 0.0;
                 }
-                for (int ib = 0; ib < nb16; ++ib) {
-                    d4 acc;
+                for (int ib = 0; ib < nb16; ib += 2) {
+                    d4 acc[2];
+                    double aop[2][4];
 #pragma unroll
-                    for (int v = 0; v < 4; ++v) {
-                        const int i = ib * 16 + lk + 4 * v;
-                        acc[v] = (jv && i < m) ? A[i + (int64_t)j * m] : 0.0;
-                    }
+                    for (int h = 0; h < 2; ++h) {
 #pragma unroll
-                    for (int kt = 0; kt < 4; ++kt) {
-                        const int i = ib * 16 + li, kk = kt * 4 + lk;
-                        double aop = 0.0;
-                        if (i < m && kk < w) {
-                            aop = Q[i + kk * ldq];
-                            if (i == k0 + kk) aop -= 1.0;
+                        for (int v = 0; v < 4; ++v) {
+                            const int i = (ib + h) * 16 + lk + 4 * v;
+                            acc[h][v] = (jv && i < m) ? A[i + (int64_t)j * m] : 0.0;
                         }
-                        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(aop, bop[kt], acc, 0, 0, 0);
+#pragma unroll
+                        for (int kt = 0; kt < 4; ++kt) {
+                            const int i = (ib + h) * 16 + li, kk = kt * 4 + lk;
+                            double a = 0.0;
+                            if (i < m && kk < w) {
+                                a = Q[s_phys[i] + kk * ldq];
+                                if (i == k0 + kk) a -= 1.0;
+                            }
+                            aop[h][kt] = a;
+                        }
                     }
 #pragma unroll
-                    for (int v = 0; v < 4; ++v) {
-                        const int i = ib * 16 + lk + 4 * v;
-                        if (jv && i < m) A[i + (int64_t)j * m] = acc[v];
-                    }
+                    for (int h = 0; h < 2; ++h)
+#pragma unroll
+                        for (int kt = 0; kt < 4; ++kt)
+                            acc[h] = __builtin_amdgcn_mfma_f64_16x16x4f64(aop[h][kt], bop[kt], acc[h], 0, 0, 0);
+#pragma unroll
+                    for (int h = 0; h < 2; ++h)
+#pragma unroll
+                        for (int v = 0; v < 4; ++v) {
+                            const int i = (ib + h) * 16 + lk + 4 * v;
+                            if (jv && i < m) A[i + (int64_t)j * m] = acc[h][v];
+                        }
                 }
             }
         }
-        __syncthreads();
-        for (int e = tid; e < m * w; e += kBlock) {
-            const int i = e % m, c = e / m;
-            A[i + (int64_t)(k0 + c) * m] = Q[i + c * ldq];
+        // the eliminated panel goes back in logical order
+#pragma unroll
+        for (int q = 0; q < R; ++q) {
+            const int r = tid + q * kBlock;
+            if (r >= m) continue;
+            for (int c = 0; c < w; ++c) A[lpos[q] + (int64_t)(k0 + c) * m] = Q[r + c * ldq];
         }
         __syncthreads();
     }
-    for (int k = m - 1; k >= 0; --k) {
-        const int pr = piv[k];
-        if (pr != k) {
-            for (int i = tid; i < m; i += kBlock) {
-                const double t = A[i + (int64_t)k * m];
-                A[i + (int64_t)k * m] = A[i + (int64_t)pr * m];
-                A[i + (int64_t)pr * m] = t;
+    // P r gather list: idx = identity with the row swaps applied in order
+    if (tid == 0) {
+        for (int t = 0; t < m; ++t) s_phys[t] = t;
+        for (int k = 0; k < m; ++k) {
+            const int pr = piv[k];
+            if (pr != k) {
+                const int t = s_phys[k];
+                s_phys[k] = s_phys[pr];
+                s_phys[pr] = t;
             }
         }
-        __syncthreads();
     }
+    __syncthreads();
+    for (int t = tid; t < m; t += kBlock) pdofs_perm[base + t] = pdofs[base + s_phys[t]];
 }
 
 // ---------------------------------------------------------------------------
@@ -423,143 +462,190 @@ __global__ __launch_bounds__(kBlock) void convert_patch_kernel(const int64_t* __
 
 // ---------------------------------------------------------------------------
 // Dense Gauss-Jordan inversion of one large matrix (the coarsest level) over
-// the whole GPU: per panel of w columns, gj_panel_kernel (one workgroup,
-// panel in LDS) eliminates the panel with partial pivoting and writes it
-// back with its pivots; gj_update_kernel (one wavefront per 16-column block)
-// applies the panel's row swaps to its columns and the rank-w update on MFMA
-// f64 16x16x4 tiles.  gj_unscramble_kernel undoes the pivoting (column swaps
-// in reverse order), one thread per row.  Column-major N x N.
+// the whole GPU, column-major N x N, panels of w columns:
+//  * dense_panel_kernel: one workgroup of 512 threads holds the N x w panel
+//    in registers (thread t owns physical rows t, t+512, ...) and eliminates
+//    it with partial pivoting.  Rows are not moved: each thread tracks the
+//    logical position of its rows (the swap "row k <-> row p" only exchanges
+//    two logical positions), so a step costs two barriers: one to publish the
+//    per-wave pivot candidates, one to publish the pivot row.  Ties go to the
+//    lowest logical row, as in LU with partial pivoting.  The panel is written
+//    back in logical order with its pivots.
+//  * dense_swap_gather_kernel: applies the panel's row swaps to every other
+//    column and copies the panel rows of those columns into T (w x N).
+//  * dense_update_kernel: one wavefront per 16x16 tile outside the panel:
+//    A[I, J] += (Q - E)[I, :] T[:, J] on MFMA f64 16x16x4.
+//  * gj_unscramble_kernel: column swaps in reverse order, one thread per row.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(kBlock) void gj_panel_kernel(double* __restrict__ A, int N, int k0, int w,
-                                                          int* __restrict__ piv, int* __restrict__ status,
-                                                          const double* __restrict__ tolp) {
-    extern __shared__ double smem[];
-    double* Q = smem;               // N x w
-    double* fcol = Q + (int64_t)N * w;
-    __shared__ double s_val[kBlock / kWave];
-    __shared__ int s_idx[kBlock / kWave];
-    __shared__ int s_fail;
-    __shared__ int s_piv[kPanel];
+constexpr int kDenseThreads = 512;
+
+template <int R, int W>
+__global__ __launch_bounds__(kDenseThreads) void dense_panel_kernel(double* __restrict__ A, int N, int k0, int w,
+                                                                    int* __restrict__ piv, int* __restrict__ status,
+                                                                    const double* __restrict__ tolp) {
+    constexpr int NWV = kDenseThreads / kWave;
+    __shared__ double s_cv[2][NWV];
+    __shared__ int s_ci[2][NWV];     // logical row of the candidate
+    __shared__ int s_cp[2][NWV];     // physical row of the candidate
+    __shared__ double s_prow[2][W];
+    __shared__ int s_phys_at[2];     // physical row currently at logical position k
+    __shared__ int s_piv[W];
+    extern __shared__ int s_phys[];  // logical -> physical for rows >= k0 (N entries)
     const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
+    if (status[0] != INT32_MAX) return;
     const double tol = tolp[0];
-    if (status[0] != INT32_MAX) return;            // an earlier panel failed
-    for (int e = tid; e < N * w; e += kBlock) {
-        const int i = e % N, c = e / N;
-        Q[i + (int64_t)c * N] = A[i + (int64_t)(k0 + c) * N];
+    double v[R][W];
+    int lpos[R];
+#pragma unroll
+    for (int q = 0; q < R; ++q) {
+        const int r = tid + q * kDenseThreads;
+        lpos[q] = r;
+#pragma unroll
+        for (int c = 0; c < W; ++c) v[q][c] = (r < N && c < w) ? A[r + (int64_t)(k0 + c) * N] : 0.0;
     }
-    if (tid == 0) s_fail = 0;
+    for (int i = tid; i < N; i += kDenseThreads) s_phys[i] = i;
     __syncthreads();
     for (int c = 0; c < w; ++c) {
-        const int k = k0 + c;
+        const int k = k0 + c, buf = c & 1;
         double bv = -1.0;
-        int bi = INT_MAX;
-        for (int i = k + tid; i < N; i += kBlock) {
-            const double v = fabs(Q[i + (int64_t)c * N]);
-            if (v > bv) { bv = v; bi = i; }
+        int bl = INT_MAX, bp = -1;
+#pragma unroll
+        for (int q = 0; q < R; ++q) {
+            const int r = tid + q * kDenseThreads;
+            if (r < N && lpos[q] >= k) {
+                double a = 0.0;
+#pragma unroll
+                for (int cc = 0; cc < W; ++cc) if (cc == c) a = fabs(v[q][cc]);
+                if (a > bv || (a == bv && lpos[q] < bl)) { bv = a; bl = lpos[q]; bp = r; }
+            }
         }
         for (int off = kWave / 2; off > 0; off >>= 1) {
             const double ov = __shfl_xor(bv, off);
-            const int oi = __shfl_xor(bi, off);
-            if (ov > bv || (ov == bv && oi < bi)) { bv = ov; bi = oi; }
+            const int ol = __shfl_xor(bl, off), op = __shfl_xor(bp, off);
+            if (ov > bv || (ov == bv && ol < bl)) { bv = ov; bl = ol; bp = op; }
         }
-        if (lane == 0) { s_val[wave] = bv; s_idx[wave] = bi; }
-        __syncthreads();
-        if (tid == 0) {
-            for (int q = 1; q < kBlock / kWave; ++q)
-                if (s_val[q] > bv || (s_val[q] == bv && s_idx[q] < bi)) { bv = s_val[q]; bi = s_idx[q]; }
-            if (bi >= N || !(bv > tol)) s_fail = 1;
-            s_piv[c] = bi < N ? bi : k;
+        if (lane == 0) { s_cv[buf][wave] = bv; s_ci[buf][wave] = bl; s_cp[buf][wave] = bp; }
+        if (tid == 0) s_phys_at[buf] = s_phys[k];
+        __syncthreads();                                              // barrier A
+        bv = s_cv[buf][0]; bl = s_ci[buf][0]; bp = s_cp[buf][0];
+        for (int q = 1; q < NWV; ++q) {
+            const double ov = s_cv[buf][q];
+            const int ol = s_ci[buf][q];
+            if (ov > bv || (ov == bv && ol < bl)) { bv = ov; bl = ol; bp = s_cp[buf][q]; }
         }
-        __syncthreads();
-        if (s_fail) {
+        if (bp < 0 || !(bv > tol)) {                                  // uniform decision
             if (tid == 0) atomicMin(status, 0);
             return;
         }
-        const int pr = s_piv[c];
-        if (pr != k && tid < w) {
-            const double t = Q[k + (int64_t)tid * N];
-            Q[k + (int64_t)tid * N] = Q[pr + (int64_t)tid * N];
-            Q[pr + (int64_t)tid * N] = t;
+        const int rk = s_phys_at[buf];                                // physical row at logical k
+        // owner of the pivot row publishes it
+        if ((bp % kDenseThreads) == tid) {
+            const int q = bp / kDenseThreads;
+#pragma unroll
+            for (int qq = 0; qq < R; ++qq)
+                if (qq == q)
+#pragma unroll
+                    for (int cc = 0; cc < W; ++cc) s_prow[buf][cc] = v[qq][cc];
         }
-        __syncthreads();
-        const double d = 1.0 / Q[k + (int64_t)c * N];
-        for (int i = tid; i < N; i += kBlock) fcol[i] = Q[i + (int64_t)c * N];
-        __syncthreads();
-        if (tid < w) Q[k + (int64_t)tid * N] = (tid == c) ? d : Q[k + (int64_t)tid * N] * d;
-        __syncthreads();
-        for (int e = tid; e < N * w; e += kBlock) {
-            const int i = e % N, cc = e / N;
-            if (i == k) continue;
-            const double f = fcol[i];
-            if (cc == c) Q[i + (int64_t)c * N] = -f * d;
-            else Q[i + (int64_t)cc * N] -= f * Q[k + (int64_t)cc * N];
+        if (tid == 0) {
+            s_piv[c] = bl;
+            s_phys[bl] = rk;                                          // row k moves to logical bl
+            s_phys[k] = bp;
         }
-        __syncthreads();
+        __syncthreads();                                              // barrier B
+        double prow[W];
+#pragma unroll
+        for (int cc = 0; cc < W; ++cc) prow[cc] = s_prow[buf][cc];
+        double pc = 0.0;
+#pragma unroll
+        for (int cc = 0; cc < W; ++cc) if (cc == c) pc = prow[cc];
+        const double d = 1.0 / pc;
+        double srow[W];
+#pragma unroll
+        for (int cc = 0; cc < W; ++cc) srow[cc] = prow[cc] * d;
+#pragma unroll
+        for (int q = 0; q < R; ++q) {
+            const int r = tid + q * kDenseThreads;
+            if (r >= N) continue;
+            if (r == bp) {
+#pragma unroll
+                for (int cc = 0; cc < W; ++cc) v[q][cc] = (cc == c) ? d : srow[cc];
+                lpos[q] = k;
+            } else {
+                double f = 0.0;
+#pragma unroll
+                for (int cc = 0; cc < W; ++cc) if (cc == c) f = v[q][cc];
+#pragma unroll
+                for (int cc = 0; cc < W; ++cc) v[q][cc] = (cc == c) ? -f * d : v[q][cc] - f * srow[cc];
+                if (r == rk) lpos[q] = bl;
+            }
+        }
     }
-    for (int e = tid; e < N * w; e += kBlock) {
-        const int i = e % N, c = e / N;
-        A[i + (int64_t)(k0 + c) * N] = Q[i + (int64_t)c * N];
+#pragma unroll
+    for (int q = 0; q < R; ++q) {
+        const int r = tid + q * kDenseThreads;
+        if (r >= N) continue;
+#pragma unroll
+        for (int c = 0; c < W; ++c)
+            if (c < w) A[lpos[q] + (int64_t)(k0 + c) * N] = v[q][c];
     }
     if (tid < w) piv[k0 + tid] = s_piv[tid];
 }
 
-// one wavefront per 16-column block outside the panel
-__global__ __launch_bounds__(kBlock) void gj_update_kernel(double* __restrict__ A, int N, int k0, int w,
-                                                           const int* __restrict__ piv,
-                                                           const int* __restrict__ status) {
+__global__ __launch_bounds__(kBlock) void dense_swap_gather_kernel(double* __restrict__ A, int N, int k0, int w,
+                                                                   const int* __restrict__ piv,
+                                                                   double* __restrict__ T,
+                                                                   const int* __restrict__ status) {
+    if (status[0] != INT32_MAX) return;
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= N || (j >= k0 && j < k0 + w)) return;
+    double* cj = A + (int64_t)j * N;
+    for (int c = 0; c < w; ++c) {
+        const int pr = piv[k0 + c];
+        if (pr != k0 + c) {
+            const double t = cj[k0 + c];
+            cj[k0 + c] = cj[pr];
+            cj[pr] = t;
+        }
+    }
+    for (int c = 0; c < w; ++c) T[c + (int64_t)j * kPanel] = cj[k0 + c];
+}
+
+__global__ __launch_bounds__(kBlock) void dense_update_kernel(double* __restrict__ A, int N, int k0, int w,
+                                                              const double* __restrict__ T,
+                                                              const int* __restrict__ status) {
     if (status[0] != INT32_MAX) return;
     const int lane = threadIdx.x & (kWave - 1);
-    const int jb = (blockIdx.x * blockDim.x + threadIdx.x) / kWave;
     const int nb16 = (N + 15) / 16;
-    if (jb >= nb16) return;
+    const int64_t tile = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / kWave;
+    if (tile >= (int64_t)nb16 * nb16) return;
+    const int jb = (int)(tile / nb16), ib = (int)(tile % nb16);
+    if (jb * 16 >= k0 && jb * 16 + 15 < k0 + w) return;               // tile inside the panel
     const int li = lane & 15, lk = lane >> 4;
     const int j = jb * 16 + li;
     const bool jv = (j < N) && (j < k0 || j >= k0 + w);
-    if (jv) {
-        double* cj = A + (int64_t)j * N;
-        for (int c = 0; c < w; ++c) {
-            const int pr = piv[k0 + c];
-            if (pr != k0 + c && lk == 0) {
-                const double t = cj[k0 + c];
-                cj[k0 + c] = cj[pr];
-                cj[pr] = t;
-            }
-        }
+    d4 acc;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+        const int i = ib * 16 + lk + 4 * v;
+        acc[v] = (jv && i < N) ? A[i + (int64_t)j * N] : 0.0;
     }
-    // the swaps (lane lk == 0 of each column) must be visible to the other lanes of the wave
-    __threadfence_block();
-    __builtin_amdgcn_wave_barrier();
-    __threadfence_block();
-    double bop[4];
 #pragma unroll
     for (int kt = 0; kt < 4; ++kt) {
         const int kk = kt * 4 + lk;
-        bop[kt] = (jv && kk < w) ? A[(k0 + kk) + (int64_t)j * N] : 0.0;
+        const double bop = (jv && kk < w) ? T[kk + (int64_t)j * kPanel] : 0.0;
+        const int i = ib * 16 + li, ka = kt * 4 + lk;
+        double aop = 0.0;
+        if (i < N && ka < w) {
+            aop = A[i + (int64_t)(k0 + ka) * N];
+            if (i == k0 + ka) aop -= 1.0;
+        }
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(aop, bop, acc, 0, 0, 0);
     }
-    const bool any = __any(jv ? 1 : 0);
-    if (!any) return;
-    for (int ib = 0; ib < nb16; ++ib) {
-        d4 acc;
 #pragma unroll
-        for (int v = 0; v < 4; ++v) {
-            const int i = ib * 16 + lk + 4 * v;
-            acc[v] = (jv && i < N) ? A[i + (int64_t)j * N] : 0.0;
-        }
-#pragma unroll
-        for (int kt = 0; kt < 4; ++kt) {
-            const int i = ib * 16 + li, kk = kt * 4 + lk;
-            double aop = 0.0;
-            if (i < N && kk < w) {
-                aop = A[i + (int64_t)(k0 + kk) * N];
-                if (i == k0 + kk) aop -= 1.0;
-            }
-            acc = __builtin_amdgcn_mfma_f64_16x16x4f64(aop, bop[kt], acc, 0, 0, 0);
-        }
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-            const int i = ib * 16 + lk + 4 * v;
-            if (jv && i < N) A[i + (int64_t)j * N] = acc[v];
-        }
+    for (int v = 0; v < 4; ++v) {
+        const int i = ib * 16 + lk + 4 * v;
+        if (jv && i < N) A[i + (int64_t)j * N] = acc[v];
     }
 }
 
@@ -577,18 +663,23 @@ __global__ __launch_bounds__(kBlock) void gj_unscramble_kernel(double* __restric
     }
 }
 
-// tol = 1e-14 * max_i sum_j |A_ij| (column-major N x N), one block
-__global__ __launch_bounds__(kBlock) void inf_norm_tol_kernel(const double* __restrict__ A, int N,
-                                                              double* __restrict__ tol) {
+// row sums |A_i.| (one thread per row, coalesced over rows) and tol = 1e-14 max_i
+__global__ __launch_bounds__(kBlock) void row_abs_sum_kernel(const double* __restrict__ A, int N,
+                                                             double* __restrict__ rs) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= N) return;
+    double s = 0.0;
+    for (int j = 0; j < N; ++j) s += fabs(A[i + (int64_t)j * N]);
+    rs[i] = s;
+}
+
+__global__ __launch_bounds__(kBlock) void max_tol_kernel(const double* __restrict__ rs, int N,
+                                                         double* __restrict__ tol) {
     __shared__ double sh[kBlock / kWave];
-    double rs = 0.0;
-    for (int i = threadIdx.x; i < N; i += kBlock) {
-        double s = 0.0;
-        for (int j = 0; j < N; ++j) s += fabs(A[i + (int64_t)j * N]);
-        rs = fmax(rs, s);
-    }
-    for (int off = kWave / 2; off > 0; off >>= 1) rs = fmax(rs, __shfl_xor(rs, off));
-    if ((threadIdx.x & (kWave - 1)) == 0) sh[threadIdx.x / kWave] = rs;
+    double m = 0.0;
+    for (int i = threadIdx.x; i < N; i += kBlock) m = fmax(m, rs[i]);
+    for (int off = kWave / 2; off > 0; off >>= 1) m = fmax(m, __shfl_xor(m, off));
+    if ((threadIdx.x & (kWave - 1)) == 0) sh[threadIdx.x / kWave] = m;
     __syncthreads();
     if (threadIdx.x == 0) tol[0] = 1e-14 * fmax(fmax(sh[0], sh[1]), fmax(sh[2], sh[3]));
 }
@@ -777,18 +868,23 @@ void launch_spmv(hipStream_t s, const DevCsr& A, const double* x, double alpha, 
 void launch_extract(hipStream_t s, const Level& L, double* out) {
     if (L.npatch <= 0) return;
     hipLaunchKernelGGL(extract_kernel, dim3(L.npatch), dim3(kBlock), sizeof(int32_t) * L.max_m, s, L.pptr, L.pdofs,
-                       L.foff, L.K.rowptr, L.K.col, L.K.val, out);
+                       L.foff, L.K.rowptr, L.K.col, L.K.val, out, L.ptol);
 }
 
-size_t gj_lds_bytes(int ldq) { return sizeof(double) * ((size_t)ldq * kPanel + ldq) + sizeof(int) * ldq; }
-
-void launch_gj_invert(hipStream_t s, int npatch, const int64_t* pptr, const int64_t* foff, const int32_t* order,
-                      double* A, int max_m, int* status) {
-    if (npatch <= 0) return;
-    const size_t lds = gj_lds_bytes(max_m);
-    if (lds > 64 * 1024)
-        (void)hipFuncSetAttribute((const void*)gj_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    hipLaunchKernelGGL(gj_kernel, dim3(npatch), dim3(kBlock), lds, s, pptr, foff, order, A, max_m, status);
+void launch_patch_factor(hipStream_t s, const Level& L, double* A) {
+    if (L.npatch <= 0) return;
+    const int ldq = L.max_m;
+    const size_t lds = sizeof(double) * (size_t)ldq * kPanel + sizeof(int) * 2 * (size_t)ldq;
+    const int R = (L.max_m + kBlock - 1) / kBlock;
+    auto go = [&](auto kernel) {
+        if (lds > 64 * 1024)
+            (void)hipFuncSetAttribute((const void*)kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        hipLaunchKernelGGL(kernel, dim3(L.npatch), dim3(kBlock), lds, s, L.pptr, L.foff, L.order, A, L.ptol,
+                           L.pdofs, L.pdofs_perm, ldq, L.status);
+    };
+    if (R <= 1) go(gj_kernel<1>);
+    else if (R <= 2) go(gj_kernel<2>);
+    else go(gj_kernel<4>);
 }
 
 // Kernel shapes the set-up autotuner chooses from, per precision:
@@ -797,7 +893,7 @@ namespace {
 template <typename T, typename Acc, int V, int NRT, int U>
 void launch_apply_shape(hipStream_t s, const Level& L, const int64_t* off, const double* r) {
     hipLaunchKernelGGL((patch_apply_kernel<T, Acc, V, NRT, U>), dim3(L.npatch), dim3(kBlock), sizeof(Acc) * L.max_m, s,
-                       L.order, L.pptr, L.pdofs, off, (const T*)L.factors, r, L.Y);
+                       L.order, L.pptr, L.pdofs_perm, off, (const T*)L.factors, r, L.Y);
 }
 }  // namespace
 
@@ -860,24 +956,38 @@ void launch_scale_by_devnorm(hipStream_t s, int64_t n, const double* src, const 
 }
 
 int coarse_panel_width(int N) {
-    // the panel (N x w doubles) and one column must fit in LDS (<= 150 KiB)
-    for (int w = kPanel; w >= 1; w /= 2)
-        if ((size_t)N * (w + 1) * sizeof(double) <= 150 * 1024) return w;
-    return 0;
+    const int R = (N + kDenseThreads - 1) / kDenseThreads;
+    return R <= 4 ? kPanel : (R <= 8 ? 8 : (R <= 16 ? 4 : 0));
 }
 
-void launch_dense_gj(hipStream_t s, double* A, int N, int* piv, int* status, double* tol) {
+namespace {
+template <int R, int W>
+void launch_dense_panel(hipStream_t s, double* A, int N, int k0, int w, int* piv, int* status, const double* tol) {
+    hipLaunchKernelGGL((dense_panel_kernel<R, W>), dim3(1), dim3(kDenseThreads), sizeof(int) * N, s, A, N, k0, w,
+                       piv, status, tol);
+}
+}  // namespace
+
+void launch_dense_gj(hipStream_t s, double* A, int N, int* piv, int* status, double* tol, double* work) {
+    // work: N doubles (row sums) + kPanel * N doubles (panel rows T)
+    double* rs = work;
+    double* T = work + N;
+    hipLaunchKernelGGL(row_abs_sum_kernel, dim3(grid_for(N, kBlock)), dim3(kBlock), 0, s, A, N, rs);
+    hipLaunchKernelGGL(max_tol_kernel, dim3(1), dim3(kBlock), 0, s, rs, N, tol);
+    const int R = (N + kDenseThreads - 1) / kDenseThreads;
     const int w0 = coarse_panel_width(N);
-    hipLaunchKernelGGL(inf_norm_tol_kernel, dim3(1), dim3(kBlock), 0, s, A, N, tol);
-    const size_t lds = (size_t)N * (w0 + 1) * sizeof(double);
-    if (lds > 64 * 1024)
-        (void)hipFuncSetAttribute((const void*)gj_panel_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     const int nb16 = (N + 15) / 16;
-    const int grid_upd = (nb16 * kWave + kBlock - 1) / kBlock;
+    const int grid_upd = (int)(((int64_t)nb16 * nb16 * kWave + kBlock - 1) / kBlock);
     for (int k0 = 0; k0 < N; k0 += w0) {
         const int w = std::min(w0, N - k0);
-        hipLaunchKernelGGL(gj_panel_kernel, dim3(1), dim3(kBlock), lds, s, A, N, k0, w, piv, status, tol);
-        hipLaunchKernelGGL(gj_update_kernel, dim3(grid_upd), dim3(kBlock), 0, s, A, N, k0, w, piv, status);
+        if (R <= 1) launch_dense_panel<1, kPanel>(s, A, N, k0, w, piv, status, tol);
+        else if (R <= 2) launch_dense_panel<2, kPanel>(s, A, N, k0, w, piv, status, tol);
+        else if (R <= 4) launch_dense_panel<4, kPanel>(s, A, N, k0, w, piv, status, tol);
+        else if (R <= 8) launch_dense_panel<8, 8>(s, A, N, k0, w, piv, status, tol);
+        else launch_dense_panel<16, 4>(s, A, N, k0, w, piv, status, tol);
+        hipLaunchKernelGGL(dense_swap_gather_kernel, dim3(grid_for(N, kBlock)), dim3(kBlock), 0, s, A, N, k0, w, piv,
+                           T, status);
+        hipLaunchKernelGGL(dense_update_kernel, dim3(grid_upd), dim3(kBlock), 0, s, A, N, k0, w, T, status);
     }
     hipLaunchKernelGGL(gj_unscramble_kernel, dim3(grid_for(N, kBlock)), dim3(kBlock), 0, s, A, N, piv);
 }

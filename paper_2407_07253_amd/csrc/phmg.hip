@@ -415,10 +415,11 @@ void setup_level(phmg_ctx ctx, int l) {
     if (l == last) {
         double* dense = dalloc<double>(ctx, (int64_t)L.nb * L.nb);
         int* piv = dalloc<int>(ctx, L.nb);
+        double* work = dalloc<double>(ctx, (int64_t)(1 + kPanel) * L.nb);
         launch_coarse_build(s, L, dense);
         {
             Timed t(ctx, PHMG_K_FACTOR, l);
-            launch_dense_gj(s, dense, L.nb, piv, L.status, ctx->scal + 4);
+            launch_dense_gj(s, dense, L.nb, piv, L.status, ctx->scal + 4, work);
             hipcheck(hipGetLastError(), "coarse factorisation launch");
         }
         if (!L.cinv) L.cinv = dalloc<double>(ctx, (int64_t)L.nb * L.nb);
@@ -427,6 +428,7 @@ void setup_level(phmg_ctx ctx, int l) {
         hipcheck(hipStreamSynchronize(s), "hipStreamSynchronize");
         dfree(ctx, dense);
         dfree(ctx, piv);
+        dfree(ctx, work);
         if (st != INT32_MAX) fail(PHMG_ESINGULAR, lvl(l) + "coarse matrix is singular");
         L.ready = true;
         return;
@@ -441,7 +443,7 @@ void setup_level(phmg_ctx ctx, int l) {
     }
     {
         Timed t(ctx, PHMG_K_FACTOR, l);
-        launch_gj_invert(s, L.npatch, L.pptr, L.foff, L.order, f64, L.max_m, L.status);
+        launch_patch_factor(s, L, f64);
         hipcheck(hipGetLastError(), "patch factorisation launch");
     }
     if (L.prec == PHMG_PREC_F64) {
@@ -762,6 +764,8 @@ phmg_status phmg_hierarchy_create(const phmg_hierarchy_desc* desc, const phmg_cy
                 for (int64_t t = 0; t < L.sum_m; ++t) sslot[pos[pt.dofs[t]]++] = (int32_t)t;
                 L.pptr = upload(ctx, pt.ptr, pt.npatch + 1);
                 L.pdofs = upload(ctx, pt.dofs, L.sum_m);
+                L.pdofs_perm = dalloc<int32_t>(ctx, L.sum_m);
+                L.ptol = dalloc<double>(ctx, pt.npatch);
                 L.pweight = pt.weight ? upload(ctx, pt.weight, L.sum_m) : nullptr;
                 L.foff = upload(ctx, foff.data(), pt.npatch);
                 L.order = upload(ctx, order.data(), pt.npatch);

@@ -38,6 +38,8 @@ struct Level {
     int64_t sum_m = 0, sum_m2 = 0;
     int64_t* pptr = nullptr;         // npatch + 1
     int32_t* pdofs = nullptr;        // sum_m
+    int32_t* pdofs_perm = nullptr;   // sum_m: pdofs permuted by each patch's pivoting (gather of P r)
+    double* ptol = nullptr;          // npatch: singularity threshold 1e-14 ||K_i||_inf
     double* pweight = nullptr;       // sum_m or null (W_i = I)
     int64_t* foff = nullptr;         // offset of patch i's m_i x m_i block (elements, float64 layout)
     int64_t* fofflp = nullptr;       // offsets of the reduced-precision layout (ld = m rounded up to 2 / 4)
@@ -112,8 +114,8 @@ void launch_fill_i32(hipStream_t s, int64_t n, int32_t* x, int32_t v);
 void launch_spmv(hipStream_t s, const DevCsr& A, const double* x, double alpha, const double* z, double beta,
                  double* y);
 void launch_extract(hipStream_t s, const Level& L, double* out);
-void launch_gj_invert(hipStream_t s, int npatch, const int64_t* pptr, const int64_t* foff, const int32_t* order,
-                      double* A, int max_m, int* status);
+// invert every patch matrix of the level in place (stored as (P K_i)^{-1}, see kernels.hip)
+void launch_patch_factor(hipStream_t s, const Level& L, double* A);
 void launch_convert_patches(hipStream_t s, const Level& L, const double* src, void* dst);
 void launch_patch_apply(hipStream_t s, const Level& L, const double* r);
 int apply_variant_count(int prec);
@@ -125,8 +127,9 @@ void launch_power_start(hipStream_t s, int64_t n, double* v);
 void launch_scale_by_devnorm(hipStream_t s, int64_t n, const double* src, const double* norm2, double* dst);
 void launch_coarse_build(hipStream_t s, const Level& L, double* dense);
 int coarse_panel_width(int N);   // 0 when N is too large for the dense coarse solve
-// in-place inverse of a column-major N x N matrix over the whole GPU (status: INT32_MAX = ok)
-void launch_dense_gj(hipStream_t s, double* A, int N, int* piv, int* status, double* tol);
+// in-place inverse of a column-major N x N matrix over the whole GPU (status: INT32_MAX = ok);
+// work holds (1 + kPanel) * N doubles
+void launch_dense_gj(hipStream_t s, double* A, int N, int* piv, int* status, double* tol, double* work);
 void launch_transpose(hipStream_t s, int n, const double* src, double* dst);
 void launch_coarse_solve(hipStream_t s, const Level& L, const double* b, double* x);
 // FGMRES helpers

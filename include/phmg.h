@@ -136,6 +136,14 @@ phmg_status phmg_relax_apply(phmg_ctx ctx, int level, const double* b, double* x
  * level 0.  The content of x on entry is ignored. */
 phmg_status phmg_vcycle(phmg_ctx ctx, const double* b, double* x);
 
+/* Replay the preconditioner as a HIP graph (default on): the first
+ * phmg_vcycle / FGMRES iteration after a set-up captures one V-cycle on a
+ * private stream into a graph with fixed input and output buffers; later
+ * applications copy in, launch the graph on the context stream and copy out.
+ * Results are bitwise identical to the eager launches.  Graphs are bypassed
+ * while per-kernel profiling is enabled. */
+phmg_status phmg_set_graphs(phmg_ctx ctx, int on);
+
 /* Restarted FGMRES on level 0, right-preconditioned by phmg_vcycle, from the
  * initial guess in x.  Stops when the Givens residual estimate drops to
  * rtol * ||b - K x_0||_2, on an exact breakdown, or after maxit inner

@@ -87,10 +87,12 @@ _prof_read = _sig("phmg_profile_read", C.c_int, [C.c_void_p, C.c_int, C.c_int, C
 _prof_reset = _sig("phmg_profile_reset", C.c_int, [C.c_void_p])
 _last_error = _sig("phmg_last_error", C.c_char_p, [])
 _ritz = _sig("phmg_ritz_max_real", C.c_int, [C.c_void_p, C.c_int, C.c_int, C.POINTER(C.c_double)])
+_graphs = _sig("phmg_set_graphs", C.c_int, [C.c_void_p, C.c_int])
 
 EXPORTED = ["phmg_hierarchy_create", "phmg_hierarchy_destroy", "phmg_relax_setup", "phmg_set_precision",
             "phmg_relax_apply", "phmg_vcycle", "phmg_fgmres_solve", "phmg_residual", "phmg_get_level_info",
             "phmg_profile_enable", "phmg_profile_read", "phmg_profile_reset", "phmg_ritz_max_real",
+            "phmg_set_graphs",
             "phmg_last_error"]
 
 
@@ -199,6 +201,10 @@ class Hierarchy:
     # -- calls
     def setup(self, level: int = -1):
         _check(_setup(self._h, level))
+
+    def set_graphs(self, on: bool):
+        """Replay the V-cycle as a captured HIP graph (default) or launch it eagerly."""
+        _check(_graphs(self._h, 1 if on else 0))
 
     def set_precision(self, level: int, prec: str):
         _check(_set_prec(self._h, level, PREC[prec]))

@@ -401,6 +401,89 @@ void vcycle(phmg_ctx ctx, const double* b, double* x) {
     }
 }
 
+void invalidate_graph(phmg_ctx ctx) {
+    if (ctx->vexec) (void)hipGraphExecDestroy(ctx->vexec);
+    if (ctx->vgraph) (void)hipGraphDestroy(ctx->vgraph);
+    ctx->vexec = nullptr;
+    ctx->vgraph = nullptr;
+}
+
+// Capture one V-cycle (gin -> gout) on a private stream.  The cycle launches
+// kernels only (no copies, no memsets, no host synchronisation), so the graph
+// replays it exactly; it is rebuilt after every set-up or precision change.
+void build_graph(phmg_ctx ctx) {
+    const int64_t n0 = ctx->L[0].n;
+    if (!ctx->cap_stream) hipcheck(hipStreamCreate(&ctx->cap_stream), "hipStreamCreate");
+    if (!ctx->gin) {
+        ctx->gin = dalloc<double>(ctx, n0);
+        ctx->gout = dalloc<double>(ctx, n0);
+    }
+    hipStream_t saved = ctx->stream;
+    hipcheck(hipStreamSynchronize(saved), "hipStreamSynchronize");
+    ctx->stream = ctx->cap_stream;
+    hipcheck(hipStreamBeginCapture(ctx->cap_stream, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
+    try {
+        vcycle(ctx, ctx->gin, ctx->gout);
+    } catch (...) {
+        hipGraph_t g = nullptr;
+        (void)hipStreamEndCapture(ctx->cap_stream, &g);
+        if (g) (void)hipGraphDestroy(g);
+        ctx->stream = saved;
+        throw;
+    }
+    ctx->stream = saved;
+    hipcheck(hipStreamEndCapture(ctx->cap_stream, &ctx->vgraph), "hipStreamEndCapture");
+    hipcheck(hipGraphInstantiate(&ctx->vexec, ctx->vgraph, nullptr, nullptr, 0), "hipGraphInstantiate");
+}
+
+// x <- B b (one preconditioner application): the captured graph when graphs
+// are on and no per-kernel profiling is requested, the eager launches otherwise.
+void precond(phmg_ctx ctx, const double* b, double* x) {
+    if (!ctx->use_graphs || ctx->prof.mask) {
+        vcycle(ctx, b, x);
+        return;
+    }
+    if (!ctx->vexec) build_graph(ctx);
+    const int64_t n0 = ctx->L[0].n;
+    launch_copy(ctx->stream, n0, b, ctx->gin);
+    hipcheck(hipGraphLaunch(ctx->vexec, ctx->stream), "hipGraphLaunch");
+    launch_copy(ctx->stream, n0, ctx->gout, x);
+}
+
+// Set-up autotuner of the SpMV: lanes per row of one matrix, timed once.
+void tune_spmv(phmg_ctx ctx, DevCsr& A, const double* x, double* y) {
+    if (A.tuned || A.nrows == 0) return;
+    hipStream_t s = ctx->stream;
+    hipEvent_t e0, e1;
+    hipcheck(hipEventCreate(&e0), "hipEventCreate");
+    hipcheck(hipEventCreate(&e1), "hipEventCreate");
+    int best = A.group;
+    float best_ms = 1e30f;
+    for (int g = 2; g <= 64; g *= 2) {
+        A.group = g;
+        launch_spmv(s, A, x, 1.0, nullptr, 0.0, y);
+        float gbest = 1e30f;
+        for (int rep = 0; rep < 3; ++rep) {
+            hipcheck(hipEventRecord(e0, s), "hipEventRecord");
+            launch_spmv(s, A, x, 1.0, nullptr, 0.0, y);
+            hipcheck(hipEventRecord(e1, s), "hipEventRecord");
+            hipcheck(hipEventSynchronize(e1), "hipEventSynchronize");
+            float ms = 0.f;
+            hipcheck(hipEventElapsedTime(&ms, e0, e1), "hipEventElapsedTime");
+            gbest = std::min(gbest, ms);
+        }
+        if (gbest < best_ms) {
+            best_ms = gbest;
+            best = g;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    hipcheck(hipGetLastError(), "spmv autotune launch");
+    A.group = best;
+    A.tuned = true;
+}
+
 void require_ready(phmg_ctx ctx) {
     for (size_t l = 0; l < ctx->L.size(); ++l)
         if (!ctx->L[l].ready) fail(PHMG_ESTATE, lvl((int)l) + "relax_setup has not been run");
@@ -410,6 +493,15 @@ void setup_level(phmg_ctx ctx, int l) {
     Level& L = ctx->L[l];
     hipStream_t s = ctx->stream;
     const int last = (int)ctx->L.size() - 1;
+    invalidate_graph(ctx);
+    if (l < last) {
+        Level& C = ctx->L[l + 1];
+        launch_fill(s, L.n, L.d, 1.0);
+        launch_fill(s, C.n, C.x, 1.0);
+        tune_spmv(ctx, L.K, L.d, L.r);
+        tune_spmv(ctx, L.R, L.d, C.b);
+        tune_spmv(ctx, L.P, C.x, L.r);
+    }
     int32_t st = INT32_MAX;
     hipcheck(hipMemcpyAsync(L.status, &st, sizeof(int32_t), hipMemcpyHostToDevice, s), "status reset");
     if (l == last) {
@@ -555,7 +647,7 @@ phmg_status fgmres(phmg_ctx ctx, const double* b, double* x, double rtol, int re
         for (int j = 0; j < restart; ++j) {
             double* vj = V + (int64_t)j * n;
             double* zj = Z + (int64_t)j * n;
-            vcycle(ctx, vj, zj);
+            precond(ctx, vj, zj);
             launch_spmv(s, L0.K, zj, 1.0, nullptr, 0.0, w);
             launch_multidot(s, n, j + 1, V, n, w, ctx->partial, h1, false);
             launch_gemv_sub(s, n, j + 1, V, n, h1, w);
@@ -629,6 +721,8 @@ phmg_status guarded(F&& f) {
 }
 
 void destroy_all(phmg_ctx ctx) {
+    invalidate_graph(ctx);
+    if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
     for (auto& it : ctx->prof.pending) {
         (void)hipEventDestroy(it.e0);
         (void)hipEventDestroy(it.e1);
@@ -810,7 +904,17 @@ phmg_status phmg_set_precision(phmg_ctx ctx, int level, phmg_precision prec) {
         if (L.prec != prec) {
             L.prec = prec;
             L.ready = false;
+            invalidate_graph(ctx);
         }
+        return PHMG_OK;
+    });
+}
+
+phmg_status phmg_set_graphs(phmg_ctx ctx, int on) {
+    return guarded([&]() -> phmg_status {
+        if (!ctx) fail(PHMG_EINVAL, "null context");
+        ctx->use_graphs = on != 0;
+        if (!ctx->use_graphs) invalidate_graph(ctx);
         return PHMG_OK;
     });
 }
@@ -845,7 +949,7 @@ phmg_status phmg_vcycle(phmg_ctx ctx, const double* b, double* x) {
     return guarded([&]() -> phmg_status {
         if (!ctx || !b || !x) fail(PHMG_EINVAL, "null argument");
         require_ready(ctx);
-        vcycle(ctx, b, x);
+        precond(ctx, b, x);
         hipcheck(hipGetLastError(), "kernel launch");
         return PHMG_OK;
     });

@@ -23,7 +23,8 @@ struct DevCsr {
     int32_t* rowptr = nullptr;
     int32_t* col = nullptr;
     double* val = nullptr;
-    int group = 8;                   // lanes per row in the SpMV
+    int group = 8;                   // lanes per row in the SpMV (chosen by the set-up autotuner)
+    bool tuned = false;
 };
 
 struct Level {
@@ -103,6 +104,13 @@ struct phmg_ctx_s {
     double* hdev = nullptr;          // device scalars: h (restart+1) and norm
     double* hhost = nullptr;         // pinned host mirror
     phmg::Profile prof;
+    // the preconditioner (one V-cycle) captured as a HIP graph on fixed buffers
+    bool use_graphs = true;
+    hipStream_t cap_stream = nullptr;
+    hipGraph_t vgraph = nullptr;
+    hipGraphExec_t vexec = nullptr;
+    double* gin = nullptr;
+    double* gout = nullptr;
 };
 
 namespace phmg {

@@ -153,6 +153,31 @@ phmg_status phmg_set_graphs(phmg_ctx ctx, int on);
 phmg_status phmg_fgmres_solve(phmg_ctx ctx, const double* b, double* x, double rtol, int restart, int maxit,
                               int* iters, double* relres);
 
+/* Several right-hand sides at once (1 <= nrhs <= PHMG_MAX_RHS).  B and X are
+ * DEVICE float64 arrays of nrhs * n_l entries holding the systems one after
+ * another (X[c * n_l + i] is DoF i of system c, i.e. a (nrhs, n) row-major
+ * tensor); B is read only, X is read and written, they must not alias.
+ * Column c of every result is what the single-system call computes for
+ * (b_c, x_c), up to rounding: the sweeps are shared so that each patch
+ * inverse and each matrix entry is read once per sweep for all systems, and
+ * the patch solves run as dense products on MFMA (float64 16x16x4 for F64
+ * factors; float32 16x16x4 with float32 accumulation for F32 and BF16
+ * factors).  The first batched call after a set-up autotunes the block
+ * kernel shapes (synchronising the stream); relax_apply_batched and
+ * vcycle_batched are otherwise asynchronous. */
+#define PHMG_MAX_RHS 16
+phmg_status phmg_relax_apply_batched(phmg_ctx ctx, int level, int nrhs, const double* B, double* X, int nu);
+phmg_status phmg_vcycle_batched(phmg_ctx ctx, int nrhs, const double* B, double* X);
+/* FGMRES for every system, in lockstep: each column keeps its own
+ * Hessenberg matrix, Givens rotations and stopping test (the single-system
+ * rule of phmg_fgmres_solve, so iters[c] equals what phmg_fgmres_solve
+ * reports for system c); a column that has stopped idles while the others
+ * finish their cycle.  iters and relres are HOST arrays of nrhs entries.
+ * restart <= 31.  Returns PHMG_ENOCONV if any system hit maxit.
+ * Synchronises the stream. */
+phmg_status phmg_fgmres_solve_batched(phmg_ctx ctx, int nrhs, const double* B, double* X, double rtol, int restart,
+                                      int maxit, int32_t* iters, double* relres);
+
 /* Residual r = b - K_l x on a level (device pointers, asynchronous). */
 phmg_status phmg_residual(phmg_ctx ctx, int level, const double* b, const double* x, double* r);
 

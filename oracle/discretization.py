@@ -235,6 +235,32 @@ def assemble_stokes(mesh, k: int, kind: str,
     return Stokes(mesh, k, kind, V, Q, free, nfu, nQ, K, b, L, Bx, By, g)
 
 
+def load_vector(disc: Stokes, forcing: Callable) -> np.ndarray:
+    """Right-hand side of another forcing on an assembled system (eq. "eq:stokes-disc").
+
+    Same reading as assemble_stokes: F(v) = int (I_h f).v with the exact
+    element mass matrix, minus the lift of the system's Dirichlet data.
+    """
+    V, k = disc.V, disc.k
+    qpts, qw = element.quadrature(2 * k)
+    phi, _ = element.eval_basis(k, qpts)
+    Fx = np.zeros(V.ndofs)
+    Fy = np.zeros(V.ndofs)
+    for c in range(disc.mesh.cells.shape[0]):
+        _, _, adet, _ = cell_geometry(disc.mesh.verts, disc.mesh.cells[c])
+        Mc = np.einsum("q,qa,qb->ab", qw * adet, phi, phi)
+        vd = V.cell_dofs[c]
+        fx, fy = forcing(V.coords[vd, 0], V.coords[vd, 1])
+        Fx[vd] += Mc @ fx
+        Fy[vd] += Mc @ fy
+    free, bnd = disc.free_u, np.flatnonzero(V.boundary)
+    L = disc.L_full
+    bu_x = Fx[free] - L[free][:, bnd] @ disc.g[0, bnd]
+    bu_y = Fy[free] - L[free][:, bnd] @ disc.g[1, bnd]
+    bp = -(disc.Bx_full[:, bnd] @ disc.g[0, bnd] + disc.By_full[:, bnd] @ disc.g[1, bnd])
+    return np.concatenate([bu_x, bu_y, bp])
+
+
 def interpolate(disc: Stokes, u: Callable, p: Optional[Callable] = None) -> np.ndarray:
     """Nodal interpolant on the free DoFs (velocity), and pressure if given."""
     x = np.zeros(disc.n)

@@ -13,9 +13,13 @@ Workloads (synthetic stand-ins for the paper's cavity / step problems):
     the partition-of-unity weights W_i = diag(1/c_j).
   * cfg2: TH P4/P3 on a Delaunay mesh refined 3 times -> TH P2/P1 on the same
     mesh -> P2/P1 on the 3 coarser meshes (direct solve on the base mesh).
+  * cfg3: TH P4/P3 (or P3/P2) on the structured 128x128 mesh -> TH P2/P1 on
+    the same mesh -> P2/P1 on 64x64 ... 8x8 (direct solve); 16 right-hand
+    sides from seeded Gaussian-bump forcings, homogeneous Dirichlet data.
+    cfg3_r1 / cfg3_r2 are the same recipe on 16x16 / 32x32.
   * cfg4: SV P4/P3disc on the Alfeld split of a jittered 16x16 mesh refined
     twice -> TH P2/P1 on the Alfeld mesh -> TH P2/P1 on the 3 macro meshes.
-  * cfg2 and cfg4 name no smoother; they use the paper's: nu = 2 Chebyshev
+  * cfg2, cfg3 and cfg4 name no smoother; they use the paper's: nu = 2 Chebyshev
     iterations over the basic additive Schwarz operator (W_i = I), interval
     [0.1, 1.1] * lambda_max, lambda_max from 20 power iterations.
 """
@@ -26,7 +30,7 @@ from typing import List, Tuple
 import numpy as np
 
 import synth
-from .discretization import assemble_stokes
+from .discretization import assemble_stokes, load_vector
 from .multigrid import CycleOpts, Level
 from .patches import multiplicity_weights, vanka_star_patches
 from .transfer import prolongation
@@ -39,8 +43,8 @@ def level_specs(name: str, k: int = None) -> Tuple[List[Tuple[int, int, str]], C
     cheb = dict(smoother="chebyshev", cheb_lo=0.1, cheb_hi=1.1, eig_iters=20)
     if name in ("cfg1", "tiny2", "tiny4"):
         return [(0, 2, "TH"), (1, 2, "TH")], CycleOpts(nu_p=2, nu_h=2, n_v=1, n_plevels=0, omega=0.5)
-    if name.startswith("cfg2"):
-        nref = {"cfg2": 3, "cfg2_r2": 2, "cfg2_r1": 1}[name]
+    if name.startswith("cfg2") or name.startswith("cfg3"):
+        nref = {"cfg2": 3, "cfg2_r2": 2, "cfg2_r1": 1, "cfg3": 4, "cfg3_r2": 2, "cfg3_r1": 1}[name]
         kk = 4 if k is None else k
         specs = [(0, kk, "TH")] + [(i, 2, "TH") for i in range(nref + 1)]
         return specs, CycleOpts(nu_p=2, nu_h=2, n_v=1, n_plevels=1, omega=0.5, **cheb)
@@ -67,17 +71,24 @@ def gradual_schedule(k: int) -> List[int]:
 
 
 def build(name: str, k: int = None, weights: str = None, with_rhs: bool = True,
-          specs=None, opts=None):
-    """Assemble every level, its patches and the transfers.  Returns (levels, discs, opts, b)."""
+          specs=None, opts=None, forcing: str = "mms", nrhs: int = 1):
+    """Assemble every level, its patches and the transfers.  Returns (levels, discs, opts, b).
+
+    forcing "mms": b is the manufactured-solution right-hand side (n,).
+    forcing "bumps": b is (nrhs, n), one seeded Gaussian-bump forcing per row,
+    homogeneous Dirichlet data.
+    """
     meshes = synth.config_mesh_hierarchy(name)[::-1]          # finest first
     if specs is None:
         specs, opts = level_specs(name, k)
     if weights is None:
         weights = "none" if opts.smoother == "chebyshev" else "pou"
     seed = SEEDS.get(name.split("_")[0], 1)
-    A = synth.mms_amplitude(seed)
-    f = (lambda x, y: synth.mms_forcing(x, y, A)) if with_rhs else None
-    g = (lambda x, y: synth.mms_velocity(x, y, A)) if with_rhs else None
+    f = g = None
+    if with_rhs and forcing == "mms":
+        A = synth.mms_amplitude(seed)
+        f = lambda x, y: synth.mms_forcing(x, y, A)
+        g = lambda x, y: synth.mms_velocity(x, y, A)
     discs = []
     for li, (mi, kk, kind) in enumerate(specs):
         d = assemble_stokes(meshes[mi], kk, kind, forcing=f if li == 0 else None, dirichlet=g if li == 0 else None)
@@ -95,7 +106,15 @@ def build(name: str, k: int = None, weights: str = None, with_rhs: bool = True,
             L.P = prolongation(discs[li - 1], d, parent)
         levels.append(L)
     levels[-1].null = discs[-1].null_vector()
-    b = discs[0].b if with_rhs else None
+    b = None
+    if with_rhs and forcing == "mms":
+        b = discs[0].b
+    elif with_rhs and forcing == "bumps":
+        C, W, D = synth.gaussian_bump_params(nrhs, seed)
+        b = np.stack([load_vector(discs[0], lambda x, y, i=i: synth.gaussian_bump_forcing(x, y, C[i], W[i], D[i]))
+                      for i in range(nrhs)])
+    elif with_rhs:
+        raise KeyError(forcing)
     return levels, discs, opts, b
 
 

@@ -88,11 +88,17 @@ _prof_reset = _sig("phmg_profile_reset", C.c_int, [C.c_void_p])
 _last_error = _sig("phmg_last_error", C.c_char_p, [])
 _ritz = _sig("phmg_ritz_max_real", C.c_int, [C.c_void_p, C.c_int, C.c_int, C.POINTER(C.c_double)])
 _graphs = _sig("phmg_set_graphs", C.c_int, [C.c_void_p, C.c_int])
+_apply_b = _sig("phmg_relax_apply_batched", C.c_int, [C.c_void_p, C.c_int, C.c_int, C.c_void_p, C.c_void_p, C.c_int])
+_vcycle_b = _sig("phmg_vcycle_batched", C.c_int, [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p])
+_fgmres_b = _sig("phmg_fgmres_solve_batched", C.c_int, [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_double,
+                                                        C.c_int, C.c_int, C.POINTER(C.c_int32),
+                                                        C.POINTER(C.c_double)])
+MAX_RHS = 16
 
 EXPORTED = ["phmg_hierarchy_create", "phmg_hierarchy_destroy", "phmg_relax_setup", "phmg_set_precision",
             "phmg_relax_apply", "phmg_vcycle", "phmg_fgmres_solve", "phmg_residual", "phmg_get_level_info",
             "phmg_profile_enable", "phmg_profile_read", "phmg_profile_reset", "phmg_ritz_max_real",
-            "phmg_set_graphs",
+            "phmg_set_graphs", "phmg_relax_apply_batched", "phmg_vcycle_batched", "phmg_fgmres_solve_batched",
             "phmg_last_error"]
 
 
@@ -116,6 +122,16 @@ def _check(st: int, allow=()):
 
 def _ptr(a: Optional[np.ndarray]):
     return None if a is None else a.ctypes.data
+
+
+def _block_ptr(t, n: int, name: str) -> (int, int):
+    """(pointer, nrhs) of a contiguous float64 CUDA tensor of shape (nrhs, n)."""
+    import torch
+    if not isinstance(t, torch.Tensor) or t.dtype != torch.float64 or not t.is_cuda or not t.is_contiguous():
+        raise TypeError(f"{name} must be a contiguous float64 CUDA tensor")
+    if t.dim() != 2 or t.shape[1] != n or not 1 <= t.shape[0] <= MAX_RHS:
+        raise ValueError(f"{name} must have shape (nrhs, {n}) with 1 <= nrhs <= {MAX_RHS}, got {tuple(t.shape)}")
+    return t.data_ptr(), int(t.shape[0])
 
 
 def _vec_ptr(t, n: int, name: str) -> int:
@@ -226,6 +242,33 @@ class Hierarchy:
         st = _check(_fgmres(self._h, _vec_ptr(b, self.n[0], "b"), _vec_ptr(x, self.n[0], "x"), rtol, restart, maxit,
                             C.byref(it), C.byref(rr)), allow=(PHMG_ENOCONV,))
         return int(it.value), float(rr.value), st == PHMG_OK
+
+    # ---- several right-hand sides at once: tensors of shape (nrhs, n), nrhs <= 16 ----
+    def relax_apply_batched(self, level: int, B, X, nu: int = 1):
+        n = self.n[level]
+        pb, k = _block_ptr(B, n, "B")
+        px, kx = _block_ptr(X, n, "X")
+        if k != kx:
+            raise ValueError("B and X must hold the same number of right-hand sides")
+        _check(_apply_b(self._h, level, k, pb, px, nu))
+
+    def vcycle_batched(self, B, X):
+        pb, k = _block_ptr(B, self.n[0], "B")
+        px, kx = _block_ptr(X, self.n[0], "X")
+        if k != kx:
+            raise ValueError("B and X must hold the same number of right-hand sides")
+        _check(_vcycle_b(self._h, k, pb, px))
+
+    def fgmres_batched(self, B, X, rtol: float = 1e-8, restart: int = 30, maxit: int = 1000):
+        """Solve K x_c = b_c for every row c of B (X in/out); returns (iters[], relres[], all_converged)."""
+        pb, k = _block_ptr(B, self.n[0], "B")
+        px, kx = _block_ptr(X, self.n[0], "X")
+        if k != kx:
+            raise ValueError("B and X must hold the same number of right-hand sides")
+        it = (C.c_int32 * k)()
+        rr = (C.c_double * k)()
+        st = _check(_fgmres_b(self._h, k, pb, px, rtol, restart, maxit, it, rr), allow=(PHMG_ENOCONV,))
+        return [int(v) for v in it], [float(v) for v in rr], st == PHMG_OK
 
     def level_info(self, level: int) -> dict:
         i = LevelInfoT()

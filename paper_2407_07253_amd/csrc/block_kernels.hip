@@ -1,0 +1,509 @@
+// gfx950 kernels of the multi-right-hand-side (block) path: up to kBS = 16
+// systems K x_c = b_c relaxed, cycled and solved together.
+//
+// Block vectors are stored interleaved, X[i * kBS + c] for DoF i and
+// right-hand side c, so the kBS values of one DoF are one 128-byte line: every
+// CSR entry and every patch DoF gathers a full line.
+//
+//  * spmm_kernel          Y = alpha K X + beta Z (residuals, transfers)
+//  * block_apply_kernel   Y_i = K_i^{-1} X[S_i, :] for every patch as a dense
+//                         m x m by m x 16 product on MFMA (f64 16x16x4 for
+//                         float64 factors, f32 16x16x4 with float32
+//                         accumulation for float32 / bfloat16 factors); each
+//                         factor word is read once per sweep for all 16 systems
+//  * block_scatter_kernel the weighted DoF-centric sum of eq. "eq:ASM"
+//  * block FGMRES kernels classical Gram-Schmidt passes per column
+//
+// Columns never mix: column c of every result depends on column c of the
+// inputs only, in a fixed summation order, so results are reproducible.
+#include <hip/hip_bf16.h>
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <climits>
+#include <cstdint>
+
+#include "phmg_internal.h"
+
+namespace phmg {
+namespace {
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+typedef float f4 __attribute__((ext_vector_type(4)));
+
+inline int grid_for(int64_t work, int per_block) {
+    int64_t g = (work + per_block - 1) / per_block;
+    if (g < 1) g = 1;
+    if (g > (1 << 20)) g = 1 << 20;
+    return (int)g;
+}
+
+// ---------------------------------------------------------------------------
+// Y = alpha K X + beta Z (Z may be null or alias Y).  kBS * GN lanes per row:
+// lane (c, g) sums the entries g, g + GN, ... of the row for column c; the GN
+// partial sums are combined with shuffles.
+// ---------------------------------------------------------------------------
+template <int GN>
+__global__ __launch_bounds__(kBlock) void spmm_kernel(int32_t nrows, const int32_t* __restrict__ rowptr,
+                                                      const int32_t* __restrict__ col, const double* __restrict__ val,
+                                                      const double* __restrict__ X, double alpha, const double* Z,
+                                                      double beta, double* Y) {
+    constexpr int LPR = kBS * GN;
+    const int c = threadIdx.x & (kBS - 1);
+    const int g = (threadIdx.x / kBS) & (GN - 1);
+    const int64_t sub = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / LPR;
+    const int64_t nsub = ((int64_t)gridDim.x * blockDim.x) / LPR;
+    for (int64_t row = sub; row < nrows; row += nsub) {
+        const int beg = rowptr[row], end = rowptr[row + 1];
+        double s = 0.0;
+        for (int k = beg + g; k < end; k += GN) s += val[k] * X[(int64_t)col[k] * kBS + c];
+#pragma unroll
+        for (int off = LPR / 2; off >= kBS; off >>= 1) s += __shfl_xor(s, off, LPR);
+        if (g == 0) {
+            double out = alpha * s;
+            if (Z) out += beta * Z[row * kBS + c];
+            Y[row * kBS + c] = out;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Block patch solve.  One workgroup per patch (launch order: decreasing m).
+// The gathered right-hand sides G = X[P S_i, :] (m x 16, rows padded with
+// zeros to a multiple of 4) sit in LDS.  The stored inverse B_i (column-major,
+// leading dimension ld = m rounded up to V) is streamed once: in one k-step of
+// 4 columns, lane l loads V consecutive rows of column k0 + l/16 (an 8-byte
+// load for every precision) and feeds V MFMAs, MFMA v taking the rows
+// r0 + V*i + v (i = l % 16) as its 16-row A tile; the B operand is G[k0 + l/16]
+// [l % 16].  A wave owns NT such 16V-row groups per pass; passes are dealt to
+// the four waves round-robin.  The result rows go to the staging array Y
+// (sum m x 16) for the scatter.
+// ---------------------------------------------------------------------------
+template <typename T, int V>
+struct BlockLoad;
+template <>
+struct BlockLoad<double, 1> {
+    __device__ static inline void load(const double* p, double (&a)[1]) { a[0] = *p; }
+};
+template <>
+struct BlockLoad<float, 2> {
+    __device__ static inline void load(const float* p, float (&a)[2]) {
+        const float2 v = *reinterpret_cast<const float2*>(p);
+        a[0] = v.x;
+        a[1] = v.y;
+    }
+};
+template <>
+struct BlockLoad<__hip_bfloat16, 4> {
+    __device__ static inline void load(const __hip_bfloat16* p, float (&a)[4]) {
+        const uint2 v = *reinterpret_cast<const uint2*>(p);
+        a[0] = __uint_as_float(v.x << 16);
+        a[1] = __uint_as_float(v.x & 0xffff0000u);
+        a[2] = __uint_as_float(v.y << 16);
+        a[3] = __uint_as_float(v.y & 0xffff0000u);
+    }
+};
+
+// MFMA 16x16x4 step and the accumulator's element -> tile-row map.  Both
+// instructions give lane l the column l % 16; float64 stores rows
+// l/16 + 4e in element e, float32 rows 4 (l/16) + e.
+template <typename Acc>
+struct Mfma;
+template <>
+struct Mfma<double> {
+    typedef d4 acc_t;
+    __device__ static inline d4 step(double a, double b, d4 c) {
+        return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+    }
+    __device__ static inline int row(int lane, int e) { return lane / 16 + 4 * e; }
+};
+template <>
+struct Mfma<float> {
+    typedef f4 acc_t;
+    __device__ static inline f4 step(float a, float b, f4 c) {
+        return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+    }
+    __device__ static inline int row(int lane, int e) { return 4 * (lane / 16) + e; }
+};
+
+template <typename T, typename Acc, int V, int NT, int U>
+__global__ __launch_bounds__(kBlock) void block_apply_kernel(const int32_t* __restrict__ order,
+                                                             const int64_t* __restrict__ pptr,
+                                                             const int32_t* __restrict__ pdofs,
+                                                             const int64_t* __restrict__ foff,
+                                                             const T* __restrict__ F, const double* __restrict__ X,
+                                                             double* __restrict__ Y) {
+    typedef typename Mfma<Acc>::acc_t acc_t;
+    constexpr int NW = kBlock / kWave;
+    constexpr int GROUP = 16 * V;                 // rows of one row group
+    constexpr int PASS = GROUP * NT;              // rows of one pass of a wave
+    extern __shared__ double s_buf[];
+    Acc* s_g = reinterpret_cast<Acc*>(s_buf);
+    const int p = order[blockIdx.x];
+    const int64_t base = pptr[p];
+    const int m = (int)(pptr[p + 1] - base);
+    const int mpad = (m + 3) & ~3;
+    const int ld = (m + V - 1) / V * V;
+    for (int t = threadIdx.x; t < mpad * kBS; t += kBlock) {
+        const int l = t / kBS, c = t % kBS;
+        s_g[t] = l < m ? (Acc)X[(int64_t)pdofs[base + l] * kBS + c] : (Acc)0;
+    }
+    __syncthreads();
+    const T* A = F + foff[p];
+    const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
+    const int li = lane & 15, lk = lane >> 4;
+    const int npass = (m + PASS - 1) / PASS;
+    for (int pass = wave; pass < npass; pass += NW) {
+        const int r0 = pass * PASS;
+        acc_t acc[NT][V];
+#pragma unroll
+        for (int q = 0; q < NT; ++q)
+#pragma unroll
+            for (int v = 0; v < V; ++v) acc[q][v] = acc_t{0, 0, 0, 0};
+        bool rowok[NT];
+#pragma unroll
+        for (int q = 0; q < NT; ++q) rowok[q] = r0 + q * GROUP + li * V < m;
+        int k0 = 0;
+        for (; k0 + 4 * (U - 1) < mpad; k0 += 4 * U) {
+            Acc a[U][NT][V];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int k = k0 + 4 * u + lk;
+                const T* colp = A + (int64_t)k * ld + r0 + li * V;
+#pragma unroll
+                for (int q = 0; q < NT; ++q) {
+                    if (rowok[q] && k < m) BlockLoad<T, V>::load(colp + q * GROUP, a[u][q]);
+                    else
+#pragma unroll
+                        for (int v = 0; v < V; ++v) a[u][q][v] = 0;
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const Acc b = s_g[(k0 + 4 * u + lk) * kBS + li];
+#pragma unroll
+                for (int q = 0; q < NT; ++q)
+#pragma unroll
+                    for (int v = 0; v < V; ++v) acc[q][v] = Mfma<Acc>::step(a[u][q][v], b, acc[q][v]);
+            }
+        }
+        for (; k0 < mpad; k0 += 4) {
+            const int k = k0 + lk;
+            const T* colp = A + (int64_t)k * ld + r0 + li * V;
+            const Acc b = s_g[k * kBS + li];
+#pragma unroll
+            for (int q = 0; q < NT; ++q) {
+                Acc a[V];
+                if (rowok[q] && k < m) BlockLoad<T, V>::load(colp + q * GROUP, a);
+                else
+#pragma unroll
+                    for (int v = 0; v < V; ++v) a[v] = 0;
+#pragma unroll
+                for (int v = 0; v < V; ++v) acc[q][v] = Mfma<Acc>::step(a[v], b, acc[q][v]);
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < NT; ++q)
+#pragma unroll
+            for (int v = 0; v < V; ++v)
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    const int row = r0 + q * GROUP + Mfma<Acc>::row(lane, e) * V + v;
+                    if (row < m) Y[(base + row) * kBS + li] = (double)acc[q][v][e];
+                }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// s = sum_{slots t of DoF j, ascending patch id} w_t Y[t, c];  dn = a s + c' d;
+// X = (x_zero ? 0 : X) + dn;  d = dn when storing.  One lane per (DoF, column).
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kBlock) void block_scatter_kernel(int32_t n, const int32_t* __restrict__ sptr,
+                                                               const int32_t* __restrict__ sslot,
+                                                               const double* __restrict__ w,
+                                                               const double* __restrict__ Y, double a, double cd,
+                                                               double* __restrict__ d, double* __restrict__ x,
+                                                               int flags) {
+    const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    const int64_t j = t / kBS;
+    const int c = (int)(t % kBS);
+    if (j >= n) return;
+    double s = 0.0;
+    const int end = sptr[j + 1];
+    if (w) {
+        for (int q = sptr[j]; q < end; ++q) {
+            const int slot = sslot[q];
+            s += w[slot] * Y[(int64_t)slot * kBS + c];
+        }
+    } else {
+        for (int q = sptr[j]; q < end; ++q) s += Y[(int64_t)sslot[q] * kBS + c];
+    }
+    double dn = a * s;
+    if (flags & 2) dn = cd * d[t] + dn;
+    x[t] = (flags & 1) ? dn : x[t] + dn;
+    if (flags & 4) d[t] = dn;
+}
+
+// X[i, c] = sum_{j < n} Ainv_rm[i * nb + j] B[j, c]: one wavefront per row,
+// lane (c, q) sums j = q, q + 4, ...
+__global__ __launch_bounds__(kBlock) void block_coarse_solve_kernel(int32_t n, int32_t nb,
+                                                                    const double* __restrict__ Ainv,
+                                                                    const double* __restrict__ B,
+                                                                    double* __restrict__ X) {
+    const int lane = threadIdx.x & (kWave - 1);
+    const int row = (blockIdx.x * blockDim.x + threadIdx.x) / kWave;
+    if (row >= n) return;
+    const int c = lane & (kBS - 1), q = lane / kBS;
+    const double* a = Ainv + (int64_t)row * nb;
+    double s = 0.0;
+    for (int j = q; j < n; j += kWave / kBS) s += a[j] * B[(int64_t)j * kBS + c];
+    s += __shfl_xor(s, 16);
+    s += __shfl_xor(s, 32);
+    if (q == 0) X[(int64_t)row * kBS + c] = s;
+}
+
+// ---------------------------------------------------------------------------
+// Gram-Schmidt passes over the block Krylov basis V_0..V_{ncol-1} (each n x 16,
+// stride ldv), one pass over the rows with per-thread accumulators:
+//   MODE 0: h_j = V_j^T w                      (per column)
+//   MODE 1: w <- w - sum_j V_j h_j, then h'_j = V_j^T w (h' into the partials)
+//   MODE 2: w <- w - sum_j V_j h_j, then ||w||^2
+// Partials per workgroup: partial[(j * kBS + c) * gridDim.x + block].
+// ---------------------------------------------------------------------------
+constexpr int kMaxBasis = 32;
+
+template <int MODE>
+__global__ __launch_bounds__(kBlock) void block_gs_kernel(int64_t n, int ncol, const double* __restrict__ V,
+                                                          int64_t ldv, double* __restrict__ w,
+                                                          const double* __restrict__ h,
+                                                          double* __restrict__ partial) {
+    __shared__ double sh[kMaxBasis][kBlock / kWave][kBS];
+    __shared__ double s_h[kMaxBasis][kBS];
+    const int c = threadIdx.x & (kBS - 1);
+    const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
+    constexpr int NOUT = MODE == 2 ? 1 : kMaxBasis;
+    double dot[NOUT];
+#pragma unroll
+    for (int j = 0; j < NOUT; ++j) dot[j] = 0.0;
+    if (MODE != 0) {
+        for (int t = threadIdx.x; t < kMaxBasis * kBS; t += kBlock) {
+            const int j = t / kBS;
+            s_h[j][t % kBS] = j < ncol ? h[t] : 0.0;
+        }
+        __syncthreads();
+    }
+    const int64_t rows_per_grid = ((int64_t)gridDim.x * kBlock) / kBS;
+    for (int64_t i = (blockIdx.x * (int64_t)kBlock + threadIdx.x) / kBS; i < n; i += rows_per_grid) {
+        const int64_t e = i * kBS + c;
+        double wi = w[e];
+        if (MODE != 0) {
+            double s = 0.0;
+#pragma unroll
+            for (int j = 0; j < kMaxBasis; ++j)
+                if (j < ncol) s += V[j * ldv + e] * s_h[j][c];
+            wi -= s;
+            w[e] = wi;
+        }
+        if (MODE == 2) {
+            dot[0] += wi * wi;
+        } else {
+#pragma unroll
+            for (int j = 0; j < kMaxBasis; ++j)
+                if (j < ncol) dot[j] += V[j * ldv + e] * wi;
+        }
+    }
+    const int nout = MODE == 2 ? 1 : ncol;
+#pragma unroll
+    for (int j = 0; j < NOUT; ++j) {
+        if (j < nout) {
+            double v = dot[j];
+            v += __shfl_xor(v, 16);
+            v += __shfl_xor(v, 32);
+            if (lane < kBS) sh[j][wave][lane] = v;
+        }
+    }
+    __syncthreads();
+    for (int t = threadIdx.x; t < nout * kBS; t += kBlock) {
+        const int j = t / kBS, cc = t % kBS;
+        partial[(int64_t)t * gridDim.x + blockIdx.x] = (sh[j][0][cc] + sh[j][1][cc]) + (sh[j][2][cc] + sh[j][3][cc]);
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void block_reduce_kernel(int nparts, const double* __restrict__ partial,
+                                                              double* __restrict__ out) {
+    __shared__ double sh[kBlock / kWave];
+    const int t = blockIdx.x;
+    double s = 0.0;
+    for (int q = threadIdx.x; q < nparts; q += kBlock) s += partial[(int64_t)t * nparts + q];
+    for (int off = kWave / 2; off > 0; off >>= 1) s += __shfl_xor(s, off);
+    const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
+    if (lane == 0) sh[wave] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) out[t] = (sh[0] + sh[1]) + (sh[2] + sh[3]);
+}
+
+// X[i, c] += sum_{j < ncol} Z_j[i, c] y[j * kBS + c]
+__global__ __launch_bounds__(kBlock) void block_gemv_add_kernel(int64_t n, int ncol, const double* __restrict__ Z,
+                                                                int64_t ldz, const double* __restrict__ y,
+                                                                double* __restrict__ X) {
+    const int64_t total = n * kBS;
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        const int c = (int)(e % kBS);
+        double s = 0.0;
+        for (int j = 0; j < ncol; ++j) s += Z[j * ldz + e] * y[j * kBS + c];
+        X[e] += s;
+    }
+}
+
+// D[i, c] = act_c ? S[i, c] / den_c : 0   (cs = {den[kBS], act[kBS]})
+__global__ __launch_bounds__(kBlock) void block_scale_kernel(int64_t n, const double* __restrict__ S,
+                                                             const double* __restrict__ cs, double* __restrict__ D) {
+    const int64_t total = n * kBS;
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        const int c = (int)(e % kBS);
+        D[e] = cs[kBS + c] != 0.0 ? S[e] / cs[c] : 0.0;
+    }
+}
+
+// interleave nrhs right-hand-side-major vectors (src[c * n + i]) into a block
+// (dst[i * kBS + c]), zero columns beyond nrhs; and back
+__global__ __launch_bounds__(kBlock) void interleave_kernel(int64_t n, int nrhs, const double* __restrict__ src,
+                                                            double* __restrict__ dst) {
+    const int64_t total = n * kBS;
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t i = e / kBS;
+        const int c = (int)(e % kBS);
+        dst[e] = c < nrhs ? src[(int64_t)c * n + i] : 0.0;
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void deinterleave_kernel(int64_t n, int nrhs, const double* __restrict__ src,
+                                                              double* __restrict__ dst) {
+    const int64_t total = n * nrhs;
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        const int c = (int)(e / n);
+        const int64_t i = e % n;
+        dst[e] = src[i * kBS + c];
+    }
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------
+void launch_spmm(hipStream_t s, const DevCsr& A, const double* X, double alpha, const double* Z, double beta,
+                 double* Y) {
+    if (A.nrows <= 0) return;
+    const int gn = A.bgroup;
+    const int grid = grid_for((int64_t)A.nrows * kBS * gn, kBlock);
+    switch (gn) {
+        case 1:
+            hipLaunchKernelGGL(spmm_kernel<1>, dim3(grid), dim3(kBlock), 0, s, A.nrows, A.rowptr, A.col, A.val, X,
+                               alpha, Z, beta, Y);
+            break;
+        case 2:
+            hipLaunchKernelGGL(spmm_kernel<2>, dim3(grid), dim3(kBlock), 0, s, A.nrows, A.rowptr, A.col, A.val, X,
+                               alpha, Z, beta, Y);
+            break;
+        default:
+            hipLaunchKernelGGL(spmm_kernel<4>, dim3(grid_for((int64_t)A.nrows * kBS * 4, kBlock)), dim3(kBlock), 0,
+                               s, A.nrows, A.rowptr, A.col, A.val, X, alpha, Z, beta, Y);
+    }
+}
+
+namespace {
+template <typename T, typename Acc, int V, int NT, int U>
+void launch_block_shape(hipStream_t s, const Level& L, const int64_t* off, const double* X) {
+    const size_t lds = sizeof(Acc) * (size_t)((L.max_m + 3) & ~3) * kBS;
+    auto kernel = block_apply_kernel<T, Acc, V, NT, U>;
+    if (lds > 64 * 1024)
+        (void)hipFuncSetAttribute((const void*)kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    hipLaunchKernelGGL(kernel, dim3(L.npatch), dim3(kBlock), lds, s, L.order, L.pptr, L.pdofs_perm, off,
+                       (const T*)L.factors, X, L.Yb);
+}
+}  // namespace
+
+int block_variant_count(int /*prec*/) { return 4; }
+
+void launch_block_apply(hipStream_t s, const Level& L, const double* X) {
+    if (L.npatch <= 0) return;
+    const int v = L.block_variant;
+    if (L.prec == PHMG_PREC_F32) {
+        switch (v) {
+            case 1: launch_block_shape<float, float, 2, 2, 2>(s, L, L.fofflp, X); break;
+            case 2: launch_block_shape<float, float, 2, 1, 8>(s, L, L.fofflp, X); break;
+            case 3: launch_block_shape<float, float, 2, 2, 4>(s, L, L.fofflp, X); break;
+            default: launch_block_shape<float, float, 2, 1, 4>(s, L, L.fofflp, X);
+        }
+    } else if (L.prec == PHMG_PREC_BF16) {
+        switch (v) {
+            case 1: launch_block_shape<__hip_bfloat16, float, 4, 1, 2>(s, L, L.fofflp, X); break;
+            case 2: launch_block_shape<__hip_bfloat16, float, 4, 1, 8>(s, L, L.fofflp, X); break;
+            case 3: launch_block_shape<__hip_bfloat16, float, 4, 2, 2>(s, L, L.fofflp, X); break;
+            default: launch_block_shape<__hip_bfloat16, float, 4, 1, 4>(s, L, L.fofflp, X);
+        }
+    } else {
+        switch (v) {
+            case 1: launch_block_shape<double, double, 1, 2, 4>(s, L, L.foff, X); break;
+            case 2: launch_block_shape<double, double, 1, 1, 8>(s, L, L.foff, X); break;
+            case 3: launch_block_shape<double, double, 1, 4, 2>(s, L, L.foff, X); break;
+            default: launch_block_shape<double, double, 1, 1, 4>(s, L, L.foff, X);
+        }
+    }
+}
+
+void launch_block_scatter(hipStream_t s, const Level& L, double a, double c, double* d, bool store_d, double* X,
+                          bool x_zero) {
+    if (L.n <= 0) return;
+    const int flags = (x_zero ? 1 : 0) | (c != 0.0 ? 2 : 0) | (store_d ? 4 : 0);
+    hipLaunchKernelGGL(block_scatter_kernel, dim3(grid_for((int64_t)L.n * kBS, kBlock)), dim3(kBlock), 0, s, L.n,
+                       L.sptr, L.sslot, L.pweight, L.Yb, a, c, d, X, flags);
+}
+
+void launch_block_coarse_solve(hipStream_t s, const Level& L, const double* B, double* X) {
+    hipLaunchKernelGGL(block_coarse_solve_kernel, dim3(grid_for((int64_t)L.n * kWave, kBlock)), dim3(kBlock), 0, s,
+                       L.n, L.nb, L.cinv, B, X);
+}
+
+void launch_block_gs(hipStream_t s, int mode, int64_t n, int ncol, const double* V, int64_t ldv, double* w,
+                     const double* h, double* partial, double* out) {
+    const int nout = mode == 2 ? 1 : ncol;
+    if (mode == 0)
+        hipLaunchKernelGGL(block_gs_kernel<0>, dim3(kRedBlocks), dim3(kBlock), 0, s, n, ncol, V, ldv, w, h, partial);
+    else if (mode == 1)
+        hipLaunchKernelGGL(block_gs_kernel<1>, dim3(kRedBlocks), dim3(kBlock), 0, s, n, ncol, V, ldv, w, h, partial);
+    else
+        hipLaunchKernelGGL(block_gs_kernel<2>, dim3(kRedBlocks), dim3(kBlock), 0, s, n, ncol, V, ldv, w, h, partial);
+    hipLaunchKernelGGL(block_reduce_kernel, dim3(nout * kBS), dim3(kBlock), 0, s, kRedBlocks, partial, out);
+}
+
+int block_gs_max_basis() { return kMaxBasis; }
+
+void launch_block_gemv_add(hipStream_t s, int64_t n, int ncol, const double* Z, int64_t ldz, const double* y,
+                           double* X) {
+    hipLaunchKernelGGL(block_gemv_add_kernel, dim3(std::min(grid_for(n * kBS, kBlock), 8192)), dim3(kBlock), 0, s, n,
+                       ncol, Z, ldz, y, X);
+}
+
+void launch_block_scale(hipStream_t s, int64_t n, const double* S, const double* cs, double* D) {
+    hipLaunchKernelGGL(block_scale_kernel, dim3(std::min(grid_for(n * kBS, kBlock), 8192)), dim3(kBlock), 0, s, n, S,
+                       cs, D);
+}
+
+void launch_interleave(hipStream_t s, int64_t n, int nrhs, const double* src, double* dst) {
+    hipLaunchKernelGGL(interleave_kernel, dim3(std::min(grid_for(n * kBS, kBlock), 8192)), dim3(kBlock), 0, s, n,
+                       nrhs, src, dst);
+}
+
+void launch_deinterleave(hipStream_t s, int64_t n, int nrhs, const double* src, double* dst) {
+    if (nrhs <= 0 || n <= 0) return;
+    hipLaunchKernelGGL(deinterleave_kernel, dim3(std::min(grid_for(n * nrhs, kBlock), 8192)), dim3(kBlock), 0, s, n,
+                       nrhs, src, dst);
+}
+
+}  // namespace phmg

@@ -18,52 +18,13 @@
 #include <string>
 #include <vector>
 
+#include "host_util.h"
 #include "phmg_internal.h"
 
 using namespace phmg;
 
 namespace {
 
-thread_local std::string g_last_error;
-
-struct Error : std::runtime_error {
-    phmg_status code;
-    Error(phmg_status c, const std::string& m) : std::runtime_error(m), code(c) {}
-};
-
-[[noreturn]] void fail(phmg_status c, const std::string& m) { throw Error(c, m); }
-
-void hipcheck(hipError_t e, const char* what) {
-    if (e != hipSuccess) fail(PHMG_EHIP, std::string(what) + ": " + hipGetErrorString(e));
-}
-
-template <typename T>
-T* dalloc(phmg_ctx ctx, int64_t count) {
-    if (count <= 0) count = 1;
-    void* p = nullptr;
-    if (hipMalloc(&p, sizeof(T) * (size_t)count) != hipSuccess) {
-        (void)hipGetLastError();
-        fail(PHMG_ENOMEM, "hipMalloc of " + std::to_string(sizeof(T) * (size_t)count) + " bytes failed");
-    }
-    ctx->allocs.push_back(p);
-    return static_cast<T*>(p);
-}
-
-void dfree(phmg_ctx ctx, void* p) {
-    if (!p) return;
-    auto it = std::find(ctx->allocs.begin(), ctx->allocs.end(), p);
-    if (it != ctx->allocs.end()) ctx->allocs.erase(it);
-    (void)hipFree(p);
-}
-
-template <typename T>
-T* upload(phmg_ctx ctx, const T* h, int64_t count) {
-    T* d = dalloc<T>(ctx, count);
-    if (count > 0) hipcheck(hipMemcpy(d, h, sizeof(T) * (size_t)count, hipMemcpyHostToDevice), "hipMemcpy H2D");
-    return d;
-}
-
-std::string lvl(int l) { return "level " + std::to_string(l) + ": "; }
 
 void check_csr(const phmg_csr& A, const std::string& who) {
     if (A.nrows < 0 || A.ncols < 0) fail(PHMG_EINVAL, who + "negative dimension");
@@ -119,48 +80,6 @@ DevCsr upload_transpose(phmg_ctx ctx, const phmg_csr& A) {
     return upload_csr(ctx, A.ncols, A.nrows, rp, ci, v);
 }
 
-struct Timed {
-    phmg_ctx ctx;
-    int id, level;
-    hipEvent_t e0 = nullptr, e1 = nullptr;
-    hipEvent_t take() {
-        auto& pool = ctx->prof.pool;
-        if (!pool.empty()) {
-            hipEvent_t e = pool.back();
-            pool.pop_back();
-            return e;
-        }
-        hipEvent_t e;
-        hipcheck(hipEventCreate(&e), "hipEventCreate");
-        return e;
-    }
-    Timed(phmg_ctx c, int k, int l) : ctx(c), id(k), level(l) {
-        if (!(ctx->prof.mask & (1u << k))) return;
-        e0 = take();
-        e1 = take();
-        hipcheck(hipEventRecord(e0, ctx->stream), "hipEventRecord");
-    }
-    ~Timed() {
-        if (!e0) return;
-        (void)hipEventRecord(e1, ctx->stream);
-        ctx->prof.pending.push_back({id, level, e0, e1});
-    }
-};
-
-void drain_profile(phmg_ctx ctx) {
-    if (ctx->prof.pending.empty()) return;
-    hipcheck(hipStreamSynchronize(ctx->stream), "hipStreamSynchronize");
-    for (auto& it : ctx->prof.pending) {
-        float ms = 0.f;
-        hipcheck(hipEventElapsedTime(&ms, it.e0, it.e1), "hipEventElapsedTime");
-        const int l = std::min(std::max(it.level, 0), PHMG_MAX_LEVELS - 1);
-        ctx->prof.ms[it.kernel][l] += ms;
-        ctx->prof.count[it.kernel][l] += 1;
-        ctx->prof.pool.push_back(it.e0);
-        ctx->prof.pool.push_back(it.e1);
-    }
-    ctx->prof.pending.clear();
-}
 
 // ----------------------------------------------------------------------------
 // relaxation, cycle
@@ -402,6 +321,7 @@ void vcycle(phmg_ctx ctx, const double* b, double* x) {
 }
 
 void invalidate_graph(phmg_ctx ctx) {
+    invalidate_block_graph(ctx);
     if (ctx->vexec) (void)hipGraphExecDestroy(ctx->vexec);
     if (ctx->vgraph) (void)hipGraphDestroy(ctx->vgraph);
     ctx->vexec = nullptr;
@@ -484,10 +404,6 @@ void tune_spmv(phmg_ctx ctx, DevCsr& A, const double* x, double* y) {
     A.tuned = true;
 }
 
-void require_ready(phmg_ctx ctx) {
-    for (size_t l = 0; l < ctx->L.size(); ++l)
-        if (!ctx->L[l].ready) fail(PHMG_ESTATE, lvl((int)l) + "relax_setup has not been run");
-}
 
 void setup_level(phmg_ctx ctx, int l) {
     Level& L = ctx->L[l];
@@ -703,22 +619,6 @@ phmg_status fgmres(phmg_ctx ctx, const double* b, double* x, double rtol, int re
     return converged ? PHMG_OK : PHMG_ENOCONV;
 }
 
-template <typename F>
-phmg_status guarded(F&& f) {
-    try {
-        g_last_error.clear();
-        return f();
-    } catch (const Error& e) {
-        g_last_error = e.what();
-        return e.code;
-    } catch (const std::bad_alloc&) {
-        g_last_error = "host allocation failed";
-        return PHMG_ENOMEM;
-    } catch (const std::exception& e) {
-        g_last_error = e.what();
-        return PHMG_EINVAL;
-    }
-}
 
 void destroy_all(phmg_ctx ctx) {
     invalidate_graph(ctx);
@@ -730,6 +630,7 @@ void destroy_all(phmg_ctx ctx) {
     for (auto e : ctx->prof.pool) (void)hipEventDestroy(e);
     for (void* p : ctx->allocs) (void)hipFree(p);
     if (ctx->hhost) (void)hipHostFree(ctx->hhost);
+    if (ctx->bhhost) (void)hipHostFree(ctx->bhhost);
     delete ctx;
 }
 

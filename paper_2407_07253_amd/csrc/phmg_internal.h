@@ -16,6 +16,7 @@ constexpr int kBlock = 256;          // threads per workgroup (4 wavefronts of 6
 constexpr int kWave = 64;
 constexpr int kPanel = 16;           // Gauss-Jordan panel width = MFMA f64 16x16x4 tile edge
 constexpr int kRedBlocks = 512;      // fixed grid of the deterministic reductions
+constexpr int kBS = 16;              // columns of a block vector (right-hand sides solved together)
 
 struct DevCsr {
     int32_t nrows = 0, ncols = 0;
@@ -25,6 +26,8 @@ struct DevCsr {
     double* val = nullptr;
     int group = 8;                   // lanes per row in the SpMV (chosen by the set-up autotuner)
     bool tuned = false;
+    int bgroup = 1;                  // entries in flight per row in the block SpMM (autotuned on first use)
+    bool btuned = false;
 };
 
 struct Level {
@@ -71,6 +74,15 @@ struct Level {
 
     int* status = nullptr;           // device: smallest singular patch id (INT32_MAX = none)
     bool ready = false;
+
+    // block (multi-right-hand-side) work space, n x kBS interleaved, allocated on first use
+    double* rb = nullptr;
+    double* bb = nullptr;
+    double* xb = nullptr;
+    double* db = nullptr;
+    double* Yb = nullptr;            // sum_m x kBS staging of the block patch solutions
+    int block_variant = 0;           // kernel shape of the block patch solve (autotuned)
+    int block_tuned_for = -1;
 };
 
 struct Profile {
@@ -111,6 +123,20 @@ struct phmg_ctx_s {
     hipGraphExec_t vexec = nullptr;
     double* gin = nullptr;
     double* gout = nullptr;
+    // block path: work vectors, FGMRES block basis and its captured V-cycle
+    bool block_ready = false;
+    int brestart_cap = 0;
+    double* Vb = nullptr;
+    double* Zb = nullptr;
+    double* wb = nullptr;
+    double* rvb = nullptr;
+    double* bpartial = nullptr;      // kRedBlocks x 32 x kBS
+    double* bh = nullptr;            // device: h1 | h2 | hn2 | column scales
+    double* bhhost = nullptr;        // pinned mirror of bh
+    double* bgin = nullptr;
+    double* bgout = nullptr;
+    hipGraph_t bgraph = nullptr;
+    hipGraphExec_t bexec = nullptr;
 };
 
 namespace phmg {
@@ -147,5 +173,26 @@ void launch_gemv_sub(hipStream_t s, int64_t n, int ncol, const double* V, int64_
 void launch_gemv_add(hipStream_t s, int64_t n, int ncol, const double* Z, int64_t ldz, const double* y, double* x);
 void launch_scale_copy(hipStream_t s, int64_t n, const double* src, double denom, double* dst);  // dst = src / denom
 void launch_copy(hipStream_t s, int64_t n, const double* src, double* dst);
+
+// drop the captured block V-cycle (block.hip); called whenever set-up changes
+void invalidate_block_graph(phmg_ctx ctx);
+
+// ---- block launchers (block_kernels.hip): n x kBS interleaved vectors ---------
+void launch_spmm(hipStream_t s, const DevCsr& A, const double* X, double alpha, const double* Z, double beta,
+                 double* Y);
+void launch_block_apply(hipStream_t s, const Level& L, const double* X);
+int block_variant_count(int prec);
+void launch_block_scatter(hipStream_t s, const Level& L, double a, double c, double* d, bool store_d, double* X,
+                          bool x_zero);
+void launch_block_coarse_solve(hipStream_t s, const Level& L, const double* B, double* X);
+// mode 0: h = V^T w;  1: w -= V h, then h' = V^T w;  2: w -= V h, then ||w||^2 (per column)
+void launch_block_gs(hipStream_t s, int mode, int64_t n, int ncol, const double* V, int64_t ldv, double* w,
+                     const double* h, double* partial, double* out);
+int block_gs_max_basis();
+void launch_block_gemv_add(hipStream_t s, int64_t n, int ncol, const double* Z, int64_t ldz, const double* y,
+                           double* X);
+void launch_block_scale(hipStream_t s, int64_t n, const double* S, const double* cs, double* D);
+void launch_interleave(hipStream_t s, int64_t n, int nrhs, const double* src, double* dst);
+void launch_deinterleave(hipStream_t s, int64_t n, int nrhs, const double* src, double* dst);
 
 }  // namespace phmg

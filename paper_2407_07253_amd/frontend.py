@@ -395,8 +395,8 @@ def workload_specs(name: str, k: Optional[int] = None):
     cheb = dict(smoother="chebyshev", cheb_lo=0.1, cheb_hi=1.1, eig_iters=20)
     if name in ("cfg1", "tiny2", "tiny4"):
         return [(0, 2, "TH"), (1, 2, "TH")], dict(nu_p=2, nu_h=2, n_v=1, n_plevels=0, omega=0.5), True
-    if name.startswith("cfg2") or name == "cfg3":
-        nref = {"cfg2": 3, "cfg2_r2": 2, "cfg2_r1": 1, "cfg3": 4}[name]
+    if name.startswith("cfg2") or name.startswith("cfg3"):
+        nref = {"cfg2": 3, "cfg2_r2": 2, "cfg2_r1": 1, "cfg3": 4, "cfg3_r2": 2, "cfg3_r1": 1}[name]
         kk = 4 if k is None else k
         specs = [(0, kk, "TH")] + [(i, 2, "TH") for i in range(nref + 1)]
         return specs, dict(nu_p=2, nu_h=2, n_v=1, n_plevels=1, omega=0.5, **cheb), False

@@ -164,7 +164,8 @@ def config_mesh_hierarchy(name: str) -> List[Mesh]:
 
     * ``cfg1``: structured 4x4 refined once -> 8x8 (Taylor-Hood P2/P1, 2 h-levels).
     * ``cfg2``: Delaunay of 64 seeded points + corners, 3 quadrisections.
-    * ``cfg3``: structured 8x8, 4 quadrisections -> 128x128.
+    * ``cfg3``: structured 8x8, 4 quadrisections -> 128x128 (``cfg3_r1``,
+      ``cfg3_r2``: 1 and 2 quadrisections, the same recipe at 16x16 and 32x32).
     * ``cfg4``: 16x16 structured with interior jitter 0.2h, 2 quadrisections, Alfeld split.
     * ``tiny2``/``tiny4``: 1x1 -> 2x2 and 2x2 -> 4x4 structured (dense-operator pins).
     """
@@ -178,6 +179,10 @@ def config_mesh_hierarchy(name: str) -> List[Mesh]:
         return hierarchy(delaunay_square(64, seed=2), 1)
     if name == "cfg3":
         return hierarchy(structured_square(8), 4)
+    if name == "cfg3_r2":
+        return hierarchy(structured_square(8), 2)
+    if name == "cfg3_r1":
+        return hierarchy(structured_square(8), 1)
     if name == "cfg4":
         base = jitter_interior(structured_square(16), 0.2 / 16, seed=4)
         return hierarchy(base, 2, alfeld=True)

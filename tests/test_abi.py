@@ -113,3 +113,15 @@ def test_host_hessenberg_qr_rejects_bad_input():
     H[0, 0] = np.nan
     with pytest.raises(lib.PhmgError):
         lib.ritz_max_real(H, 2)
+
+
+def test_batched_entry_points_reject_bad_arguments_on_the_host():
+    """The batched calls validate before any launch (null context, nrhs range)."""
+    import ctypes
+    lib = _lib()
+    it = (ctypes.c_int32 * 4)()
+    rr = (ctypes.c_double * 4)()
+    assert lib._fgmres_b(None, 4, 1, 2, 1e-8, 30, 100, it, rr) == lib.PHMG_EINVAL
+    assert "null context" in lib.last_error()
+    assert lib._vcycle_b(None, 0, 1, 2) == lib.PHMG_EINVAL
+    assert lib._apply_b(None, 0, 17, 1, 2, 1) == lib.PHMG_EINVAL

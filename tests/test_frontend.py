@@ -20,7 +20,7 @@ def _same_csr(a, b_scipy, rtol):
     assert np.abs(a.val - b.data).max() <= rtol * scale
 
 
-@pytest.mark.parametrize("name", ["tiny4", "cfg1", "sv_small", "cfg2_r1"])
+@pytest.mark.parametrize("name", ["tiny4", "cfg1", "sv_small", "cfg2_r1", "cfg3_r1"])
 def test_hierarchy_matches_oracle(name):
     fh = frontend.build_hierarchy(name)
     olevels, odiscs, oopts, ob = oproblems.build(name)
@@ -42,6 +42,15 @@ def test_hierarchy_matches_oracle(name):
         assert getattr(oopts, key) == val, key
     if oopts.smoother == "chebyshev":
         assert fh.opts["smoother"] == "chebyshev"
+
+
+def test_bump_right_hand_sides_match_oracle():
+    """The 16 seeded Gaussian-bump right-hand sides of the batched workload."""
+    fh = frontend.build_hierarchy("cfg3_r1", forcing="bumps", nrhs=16)
+    _, _, _, ob = oproblems.build("cfg3_r1", forcing="bumps", nrhs=16)
+    assert fh.b.shape == ob.shape == (16, fh.levels[0].n)
+    assert np.abs(fh.b - ob).max() <= 1e-13 * np.abs(ob).max()
+    assert np.all(np.abs(ob).max(axis=1) > 0)
 
 
 def test_shape_functions_nodal_and_quadrature_exact():

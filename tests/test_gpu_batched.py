@@ -1,0 +1,252 @@
+"""Batched (multi-right-hand-side) GPU path against the oracle and the single-system path.
+
+Every column of a batched call must equal what the oracle computes for that
+system alone: the block kernels (block SpMM, the MFMA patch product, the block
+scatter, the block coarse solve) never mix columns.  Tolerances as for the
+single-system parity tests: one sweep / one V-cycle to 1e-11 relative (max
+norm), FGMRES identical iteration counts per column and solutions equal to
+1e-10 relative after removing the pressure mean.  Against the single-system GPU
+path the columns agree to rounding of the different summation order (1e-12).
+"""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+pytestmark = pytest.mark.gpu
+
+from oracle import fgmres as ofgmres  # noqa: E402
+from oracle import multigrid as omg  # noqa: E402
+from oracle import problems as oproblems  # noqa: E402
+from paper_2407_07253_amd import frontend  # noqa: E402
+
+_CACHE = {}
+
+
+def _pair(name, nrhs):
+    key = (name, nrhs)
+    if key not in _CACHE:
+        from paper_2407_07253_amd._lib import Hierarchy
+        forcing = "bumps" if name.startswith("cfg3") else "mms"
+        fh = frontend.build_hierarchy(name, forcing=forcing, nrhs=nrhs)
+        H = Hierarchy.from_frontend(fh)
+        H.setup()
+        ol, od, oopts, ob = oproblems.build(name, forcing=forcing, nrhs=nrhs)
+        omg.setup(ol, oopts)
+        _CACHE[key] = (fh, H, ol, od, oopts, ob)
+    return _CACHE[key]
+
+
+def _dev(a):
+    return torch.tensor(np.ascontiguousarray(a, dtype=np.float64), device="cuda")
+
+
+def _host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+def _rel(a, b):
+    return float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-300))
+
+
+def _normalise(x, nfu):
+    y = np.array(x, copy=True)
+    y[..., 2 * nfu:] -= y[..., 2 * nfu:].mean(axis=-1, keepdims=True)
+    return y
+
+
+@pytest.mark.parametrize("name,nrhs", [("cfg1", 3), ("cfg3_r1", 16), ("sv_small", 5)])
+@pytest.mark.parametrize("nu", [1, 2])
+def test_batched_relax_matches_oracle(name, nrhs, nu):
+    fh, H, ol, od, oopts, ob = _pair(name, 1)
+    rng = np.random.default_rng(300 + nu + nrhs)
+    for l in range(len(ol) - 1):
+        n = ol[l].n
+        B, X = rng.standard_normal((nrhs, n)), rng.standard_normal((nrhs, n))
+        Xg = _dev(X)
+        H.relax_apply_batched(l, _dev(B), Xg, nu)
+        got = _host(Xg)
+        worst = 0.0
+        for c in range(nrhs):
+            ref = omg._relax(ol[l], oopts, B[c], X[c], nu, False)
+            worst = max(worst, _rel(got[c], ref))
+        print(f"{name} level {l} nu={nu} nrhs={nrhs}: worst column rel err {worst:.2e}")
+        assert worst <= 1e-11, (l, worst)
+
+
+@pytest.mark.parametrize("name,nrhs", [("cfg1", 1), ("cfg2_r1", 4), ("cfg3_r1", 16)])
+def test_batched_vcycle_matches_oracle(name, nrhs):
+    fh, H, ol, od, oopts, ob = _pair(name, 1)
+    rng = np.random.default_rng(11 + nrhs)
+    B = rng.standard_normal((nrhs, ol[0].n))
+    Z = _dev(np.full((nrhs, ol[0].n), np.nan))      # content on entry is ignored
+    H.vcycle_batched(_dev(B), Z)
+    got = _host(Z)
+    worst = max(_rel(got[c], omg.vcycle(ol, oopts, B[c])) for c in range(nrhs))
+    print(f"{name} batched vcycle nrhs={nrhs}: worst column rel err {worst:.2e}")
+    assert worst <= 1e-11
+
+
+def test_batched_fgmres_matches_oracle_per_column():
+    """cfg3_r1 (16x16 TH P4/P3, bump forcings): per-column iteration counts and solutions."""
+    nrhs = 3
+    fh, H, ol, od, oopts, ob = _pair("cfg3_r1", nrhs)
+    X = _dev(np.zeros((nrhs, ol[0].n)))
+    iters, relres, conv = H.fgmres_batched(_dev(fh.b), X, rtol=1e-8, restart=30, maxit=1000)
+    got = _host(X)
+    K = ol[0].K
+    nfu = od[0].nfu
+    assert conv
+    for c in range(nrhs):
+        res = ofgmres.fgmres(lambda v: K @ v, lambda v: omg.vcycle(ol, oopts, v), ob[c], rtol=1e-8, restart=30,
+                             maxit=1000)
+        ref = _normalise(res.x, nfu)
+        err = np.linalg.norm(_normalise(got[c], nfu) - ref) / np.linalg.norm(ref)
+        print(f"column {c}: GPU iters {iters[c]} relres {relres[c]:.3e}; oracle iters {res.iters} "
+              f"relres {res.relres:.3e}; solution rel err {err:.2e}")
+        assert res.converged
+        assert iters[c] == res.iters
+        assert err <= 1e-10
+        true_rel = np.linalg.norm(ob[c] - K @ got[c]) / np.linalg.norm(ob[c])
+        assert true_rel <= 1e-8 * (1 + 1e-6)
+
+
+@pytest.mark.parametrize("name,nrhs", [("cfg3_r1", 16), ("cfg2_r1", 5), ("cfg1", 2)])
+def test_batched_fgmres_equals_single_system_path(name, nrhs):
+    """Each column of the lockstep solve takes the iterations of its own single-system solve."""
+    fh, H, ol, od, oopts, ob = _pair(name, 1)
+    rng = np.random.default_rng(5)
+    if name.startswith("cfg3"):
+        B = frontend.build_hierarchy(name, forcing="bumps", nrhs=nrhs).b
+    else:
+        # the manufactured right-hand side and random multiples / perturbations of it; the
+        # perturbation is kept orthogonal to the constant-pressure kernel (consistent systems)
+        E = rng.standard_normal((nrhs, ol[0].n))
+        E[:, 2 * od[0].nfu:] -= E[:, 2 * od[0].nfu:].mean(axis=1, keepdims=True)
+        B = fh.b[0][None, :] * rng.uniform(0.5, 2.0, size=(nrhs, 1)) + 1e-3 * E
+    X = _dev(np.zeros_like(B))
+    iters, relres, conv = H.fgmres_batched(_dev(B), X, rtol=1e-8)
+    got = _host(X)
+    nfu = od[0].nfu
+    assert conv
+    for c in range(nrhs):
+        x1 = _dev(np.zeros(ol[0].n))
+        it1, rr1, conv1 = H.fgmres(_dev(B[c]), x1, rtol=1e-8)
+        one = _normalise(_host(x1), nfu)
+        err = np.linalg.norm(_normalise(got[c], nfu) - one) / np.linalg.norm(one)
+        print(f"{name} column {c}: batched iters {iters[c]} relres {relres[c]:.3e}; single iters {it1} "
+              f"relres {rr1:.3e}; rel diff {err:.2e}")
+        assert conv1 and iters[c] == it1
+        assert err <= 1e-10
+
+
+def test_batched_zero_and_converged_columns():
+    """A zero right-hand side converges at 0 iterations and stays zero; the others are unaffected."""
+    fh, H, ol, od, oopts, ob = _pair("cfg1", 1)
+    n = ol[0].n
+    B = np.stack([fh.b[0], np.zeros(n), 2.0 * fh.b[0]])
+    X = _dev(np.zeros((3, n)))
+    iters, relres, conv = H.fgmres_batched(_dev(B), X, rtol=1e-8)
+    got = _host(X)
+    assert conv and iters[1] == 0 and relres[1] == 0.0
+    assert np.all(got[1] == 0.0)
+    assert iters[0] == iters[2]
+    assert _rel(got[2], 2.0 * got[0]) <= 1e-12
+
+
+@pytest.mark.parametrize("prec", ["f32", "bf16"])
+def test_batched_mixed_precision_reaches_fp64_residual(prec):
+    """Patch inverses stored in FP32 / BF16 (MFMA, float32 accumulation), FP64 FGMRES: every
+    column reaches the FP64 residual target measured with the oracle's operator."""
+    from paper_2407_07253_amd._lib import Hierarchy
+    nrhs = 16
+    fh = frontend.build_hierarchy("cfg3_r1", forcing="bumps", nrhs=nrhs)
+    ol, od, oopts, ob = oproblems.build("cfg3_r1", forcing="bumps", nrhs=nrhs)
+    H = Hierarchy.from_frontend(fh)
+    for l in range(len(fh.levels) - 1):
+        H.set_precision(l, prec)
+    H.setup()
+    X = _dev(np.zeros((nrhs, ol[0].n)))
+    iters, relres, conv = H.fgmres_batched(_dev(ob), X, rtol=1e-8)
+    got = _host(X)
+    K = ol[0].K
+    fh64, H64, *_ = _pair("cfg3_r1", 1)
+    X64 = _dev(np.zeros((nrhs, ol[0].n)))
+    it64, _, conv64 = H64.fgmres_batched(_dev(ob), X64, rtol=1e-8)
+    ref = _host(X64)
+    nfu = od[0].nfu
+    assert conv and conv64
+    for c in range(nrhs):
+        true_rel = np.linalg.norm(ob[c] - K @ got[c]) / np.linalg.norm(ob[c])
+        err = np.linalg.norm(_normalise(got[c] - ref[c], nfu)) / np.linalg.norm(_normalise(ref[c], nfu))
+        print(f"{prec} column {c}: iters {iters[c]} (fp64 {it64[c]}), true relres {true_rel:.3e}, "
+              f"error vs fp64 solution {err:.2e}")
+        assert true_rel <= 1.05e-8
+        assert err <= 1e-5
+    H.close()
+
+
+def test_batched_graph_replays_equal_eager():
+    """The captured block V-cycle gives bitwise the eager launches, replay after replay."""
+    fh, H, ol, od, oopts, ob = _pair("cfg2_r1", 1)
+    rng = np.random.default_rng(21)
+    outs = []
+    for graphs in (False, True, True, True):
+        H.set_graphs(graphs)
+        B = _dev(rng.standard_normal((6, ol[0].n)))
+        Z1 = _dev(np.zeros((6, ol[0].n)))
+        H.vcycle_batched(B, Z1)
+        torch.cuda.synchronize()
+        H.set_graphs(False)
+        Z0 = _dev(np.zeros((6, ol[0].n)))
+        H.vcycle_batched(B, Z0)
+        outs.append((_host(Z1), _host(Z0)))
+    H.set_graphs(True)
+    for a, b in outs:
+        assert np.array_equal(a, b)
+
+
+def test_batched_argument_errors():
+    from paper_2407_07253_amd._lib import PhmgError
+    fh, H, ol, od, oopts, ob = _pair("cfg1", 1)
+    n = ol[0].n
+    with pytest.raises(ValueError):
+        H.vcycle_batched(_dev(np.zeros((17, n))), _dev(np.zeros((17, n))))
+    with pytest.raises(ValueError):
+        H.vcycle_batched(_dev(np.zeros((2, n))), _dev(np.zeros((3, n))))
+    with pytest.raises(PhmgError):
+        H.relax_apply_batched(len(ol) - 1, _dev(np.zeros((2, ol[-1].n))), _dev(np.zeros((2, ol[-1].n))))
+    with pytest.raises(PhmgError):
+        H.fgmres_batched(_dev(np.ones((2, n))), _dev(np.zeros((2, n))), restart=40)
+
+
+@pytest.mark.parametrize("prec", ["f32", "bf16"])
+def test_batched_reduced_precision_sweep_matches_single_path(prec):
+    """With FP32 / BF16 patch inverses the MFMA block product (float32 accumulation) and the
+    single-system streaming kernel use the same rounded factors and right-hand sides; they
+    differ only in float32 summation order, so a sweep agrees to ~1e-6 in norm.  A wrong
+    MFMA lane layout would permute rows inside 16-row tiles and give O(1) differences."""
+    from paper_2407_07253_amd._lib import Hierarchy
+    fh = frontend.build_hierarchy("cfg3_r1")
+    H = Hierarchy.from_frontend(fh)
+    for l in range(len(fh.levels) - 1):
+        H.set_precision(l, prec)
+    H.setup()
+    rng = np.random.default_rng(77)
+    nrhs = 7
+    for l in range(len(fh.levels) - 1):
+        n = fh.levels[l].n
+        B, X = rng.standard_normal((nrhs, n)), rng.standard_normal((nrhs, n))
+        Xg = _dev(X)
+        H.relax_apply_batched(l, _dev(B), Xg, 1)
+        got = _host(Xg)
+        worst = 0.0
+        for c in range(nrhs):
+            x1 = _dev(X[c])
+            H.relax_apply(l, _dev(B[c]), x1, 1)
+            one = _host(x1)
+            worst = max(worst, float(np.linalg.norm(got[c] - one) / np.linalg.norm(one - X[c])))
+        print(f"{prec} level {l}: worst column ||batched - single|| / ||correction|| = {worst:.2e}")
+        assert worst <= 1e-4
+    H.close()

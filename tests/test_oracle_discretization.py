@@ -142,3 +142,30 @@ def test_sv_divergence_lies_in_pressure_space():
     xt = rng.standard_normal(dth.n)
     gap = np.abs(divergence_at_quadrature(dth, xt) - divergence_projected(dth, xt)).max()
     assert gap > 1e-2 * np.abs(divergence_at_quadrature(dth, xt)).max()
+
+
+@pytest.mark.parametrize("k,mesh", [(4, synth.delaunay_square(12, seed=3)), (4, synth.structured_square(3))])
+def test_load_vector_integrates_polynomials_exactly(k, mesh):
+    """sum_i b_i v_i = int f . psi for a constant force f and the interpolant v
+    of psi = x(1-x)y(1-y) (zero on the boundary, degree 4 so I_h psi = psi):
+    int psi over the unit square is 1/36."""
+    from oracle.discretization import interpolate, load_vector
+    d = assemble_stokes(mesh, k, "TH")
+    cx, cy = 0.7, -1.3
+    b = load_vector(d, lambda x, y: (np.full_like(x, cx), np.full_like(y, cy)))
+    psi = lambda x, y: x * (1 - x) * y * (1 - y)
+    v = interpolate(d, lambda x, y: (psi(x, y), psi(x, y)))
+    assert abs(b @ v - (cx + cy) / 36.0) <= 1e-14
+    assert np.all(b[2 * d.nfu:] == 0.0)          # no Dirichlet lift: pressure rows vanish
+
+
+def test_load_vector_equals_assembly_rhs():
+    """The separate load-vector routine reproduces the right-hand side that
+    assemble_stokes builds together with K (manufactured forcing and lift)."""
+    from oracle.discretization import load_vector
+    A = synth.mms_amplitude(2)
+    f = lambda x, y: synth.mms_forcing(x, y, A)
+    g = lambda x, y: synth.mms_velocity(x, y, A)
+    d = assemble_stokes(synth.jitter_interior(synth.structured_square(4), 0.05, seed=1), 3, "TH",
+                        forcing=f, dirichlet=g)
+    assert np.abs(load_vector(d, f) - d.b).max() <= 1e-13 * np.abs(d.b).max()

@@ -94,16 +94,21 @@ void tune_block(phmg_ctx ctx) {
     auto tune_csr = [&](DevCsr& A, const double* X, double* Y) {
         if (A.btuned || A.nrows == 0) return;
         int best = 1;
+        bool best_x = false;
         float best_ms = 1e30f;
-        for (int g = 1; g <= 4; g *= 2) {
-            A.bgroup = g;
-            const float ms = time_launch(s, e0, e1, [&] { launch_spmm(s, A, X, 1.0, nullptr, 0.0, Y); });
-            if (ms < best_ms) {
-                best_ms = ms;
-                best = g;
+        for (int xm = 0; xm < 2; ++xm)
+            for (int g = 1; g <= 4; g *= 2) {
+                A.bgroup = g;
+                A.bxcd = xm != 0;
+                const float ms = time_launch(s, e0, e1, [&] { launch_spmm(s, A, X, 1.0, nullptr, 0.0, Y); });
+                if (ms < best_ms) {
+                    best_ms = ms;
+                    best = g;
+                    best_x = xm != 0;
+                }
             }
-        }
         A.bgroup = best;
+        A.bxcd = best_x;
         A.btuned = true;
     };
     const int last = (int)ctx->L.size() - 1;

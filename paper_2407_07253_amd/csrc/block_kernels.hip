@@ -41,9 +41,16 @@ inline int grid_for(int64_t work, int per_block) {
 // ---------------------------------------------------------------------------
 // Y = alpha K X + beta Z (Z may be null or alias Y).  kBS * GN lanes per row:
 // lane (c, g) sums the entries g, g + GN, ... of the row for column c; the GN
-// partial sums are combined with shuffles.
+// partial sums are combined with shuffles.  XM: XCD-contiguous row ranges
+// (as in the single-vector SpMV; the grid is then a multiple of 8).
 // ---------------------------------------------------------------------------
-template <int GN>
+__device__ inline int64_t logical_block(bool xm) {
+    if (!xm) return blockIdx.x;
+    const int64_t per = gridDim.x / 8;
+    return (int64_t)(blockIdx.x % 8) * per + blockIdx.x / 8;
+}
+
+template <int GN, bool XM>
 __global__ __launch_bounds__(kBlock) void spmm_kernel(int32_t nrows, const int32_t* __restrict__ rowptr,
                                                       const int32_t* __restrict__ col, const double* __restrict__ val,
                                                       const double* __restrict__ X, double alpha, const double* Z,
@@ -51,12 +58,33 @@ __global__ __launch_bounds__(kBlock) void spmm_kernel(int32_t nrows, const int32
     constexpr int LPR = kBS * GN;
     const int c = threadIdx.x & (kBS - 1);
     const int g = (threadIdx.x / kBS) & (GN - 1);
-    const int64_t sub = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / LPR;
+    const int64_t sub = (logical_block(XM) * blockDim.x + threadIdx.x) / LPR;
     const int64_t nsub = ((int64_t)gridDim.x * blockDim.x) / LPR;
     for (int64_t row = sub; row < nrows; row += nsub) {
         const int beg = rowptr[row], end = rowptr[row + 1];
         double s = 0.0;
-        for (int k = beg + g; k < end; k += GN) s += val[k] * X[(int64_t)col[k] * kBS + c];
+        if (GN == 1) {
+            // the 16 lanes of the row load 16 indices at once and broadcast them, so
+            // the 16 gathers of a chunk are independent loads; entries are still
+            // added in row order
+            for (int k0 = beg; k0 < end; k0 += kBS) {
+                const int cnt = min(kBS, end - k0);
+                int ck = 0;
+                double vk = 0.0;
+                if (c < cnt) {
+                    ck = col[k0 + c];
+                    vk = val[k0 + c];
+                }
+#pragma unroll
+                for (int t = 0; t < kBS; ++t) {
+                    const int cc = __shfl(ck, t, kBS);
+                    const double vv = __shfl(vk, t, kBS);
+                    if (t < cnt) s += vv * X[(int64_t)cc * kBS + c];
+                }
+            }
+        } else {
+            for (int k = beg + g; k < end; k += GN) s += val[k] * X[(int64_t)col[k] * kBS + c];
+        }
 #pragma unroll
         for (int off = LPR / 2; off >= kBS; off >>= 1) s += __shfl_xor(s, off, LPR);
         if (g == 0) {
@@ -399,20 +427,20 @@ __global__ __launch_bounds__(kBlock) void deinterleave_kernel(int64_t n, int nrh
 void launch_spmm(hipStream_t s, const DevCsr& A, const double* X, double alpha, const double* Z, double beta,
                  double* Y) {
     if (A.nrows <= 0) return;
-    const int gn = A.bgroup;
-    const int grid = grid_for((int64_t)A.nrows * kBS * gn, kBlock);
-    switch (gn) {
-        case 1:
-            hipLaunchKernelGGL(spmm_kernel<1>, dim3(grid), dim3(kBlock), 0, s, A.nrows, A.rowptr, A.col, A.val, X,
-                               alpha, Z, beta, Y);
-            break;
-        case 2:
-            hipLaunchKernelGGL(spmm_kernel<2>, dim3(grid), dim3(kBlock), 0, s, A.nrows, A.rowptr, A.col, A.val, X,
-                               alpha, Z, beta, Y);
-            break;
-        default:
-            hipLaunchKernelGGL(spmm_kernel<4>, dim3(grid_for((int64_t)A.nrows * kBS * 4, kBlock)), dim3(kBlock), 0,
-                               s, A.nrows, A.rowptr, A.col, A.val, X, alpha, Z, beta, Y);
+    const int gn = A.bgroup == 2 || A.bgroup == 4 ? A.bgroup : 1;
+    int grid = grid_for((int64_t)A.nrows * kBS * gn, kBlock);
+    if (A.bxcd) grid = (grid + 7) / 8 * 8;
+    auto go = [&](auto kernel) {
+        hipLaunchKernelGGL(kernel, dim3(grid), dim3(kBlock), 0, s, A.nrows, A.rowptr, A.col, A.val, X, alpha, Z,
+                           beta, Y);
+    };
+    switch (gn * 2 + (A.bxcd ? 1 : 0)) {
+        case 2: go(spmm_kernel<1, false>); break;
+        case 3: go(spmm_kernel<1, true>); break;
+        case 4: go(spmm_kernel<2, false>); break;
+        case 5: go(spmm_kernel<2, true>); break;
+        case 8: go(spmm_kernel<4, false>); break;
+        default: go(spmm_kernel<4, true>); break;
     }
 }
 

@@ -50,20 +50,42 @@ __global__ __launch_bounds__(kBlock) void copy_kernel(int64_t n, const double* _
 }
 
 // ---------------------------------------------------------------------------
-// CSR SpMV, G lanes per row: y = alpha * A x + beta * z  (z may alias y)
+// CSR SpMV, G lanes per row: y = alpha * A x + beta * z  (z may alias y).
+// With XM the workgroups are renumbered so that each of the 8 XCDs (which
+// receive workgroups round-robin) sweeps one contiguous eighth of the rows:
+// neighbouring rows gather neighbouring x entries, so the gathers of one XCD
+// stay in its own L2.  The grid is a multiple of 8 in that case.
 // ---------------------------------------------------------------------------
-template <int G>
+__device__ inline int64_t logical_block(bool xm) {
+    if (!xm) return blockIdx.x;
+    const int64_t per = gridDim.x / 8;
+    return (int64_t)(blockIdx.x % 8) * per + blockIdx.x / 8;
+}
+
+template <int G, bool XM>
 __global__ __launch_bounds__(kBlock) void spmv_kernel(int32_t nrows, const int32_t* __restrict__ rowptr,
                                                       const int32_t* __restrict__ col, const double* __restrict__ val,
                                                       const double* __restrict__ x, double alpha, const double* z,
                                                       double beta, double* y) {
     const int lane = threadIdx.x & (G - 1);
-    const int64_t sub = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / G;
+    const int64_t sub = (logical_block(XM) * blockDim.x + threadIdx.x) / G;
     const int64_t nsub = ((int64_t)gridDim.x * blockDim.x) / G;
     for (int64_t row = sub; row < nrows; row += nsub) {
         const int beg = rowptr[row], end = rowptr[row + 1];
         double s = 0.0;
-        for (int k = beg + lane; k < end; k += G) s += val[k] * x[col[k]];
+        // four entries per lane in flight (indices first, then the gathers); each
+        // lane still adds its entries k = beg + lane, + G, + 2G, ... in order
+        int k = beg + lane;
+        for (; k + 3 * G < end; k += 4 * G) {
+            const int c0 = col[k], c1 = col[k + G], c2 = col[k + 2 * G], c3 = col[k + 3 * G];
+            const double v0 = val[k], v1 = val[k + G], v2 = val[k + 2 * G], v3 = val[k + 3 * G];
+            const double x0 = x[c0], x1 = x[c1], x2 = x[c2], x3 = x[c3];
+            s += v0 * x0;
+            s += v1 * x1;
+            s += v2 * x2;
+            s += v3 * x3;
+        }
+        for (; k < end; k += G) s += val[k] * x[col[k]];
 #pragma unroll
         for (int off = G / 2; off > 0; off >>= 1) s += __shfl_xor(s, off, G);
         if (lane == 0) {
@@ -845,12 +867,18 @@ void launch_copy(hipStream_t s, int64_t n, const double* src, double* dst) {
 void launch_spmv(hipStream_t s, const DevCsr& A, const double* x, double alpha, const double* z, double beta,
                  double* y) {
     if (A.nrows <= 0) return;
-    const int grid = grid_for((int64_t)A.nrows * A.group, kBlock);
-    switch (A.group) {
-#define PHMG_SPMV_CASE(G)                                                                                      \
-    case G:                                                                                                    \
-        hipLaunchKernelGGL(spmv_kernel<G>, dim3(grid), dim3(kBlock), 0, s, A.nrows, A.rowptr, A.col, A.val, x, \
-                           alpha, z, beta, y);                                                                 \
+    const int g = A.group;
+    int grid = grid_for((int64_t)A.nrows * g, kBlock);
+    if (A.xcd) grid = (grid + 7) / 8 * 8;
+    switch (g * 2 + (A.xcd ? 1 : 0)) {
+#define PHMG_SPMV_CASE(G)                                                                                        \
+    case 2 * G:                                                                                                  \
+        hipLaunchKernelGGL((spmv_kernel<G, false>), dim3(grid), dim3(kBlock), 0, s, A.nrows, A.rowptr, A.col,    \
+                           A.val, x, alpha, z, beta, y);                                                         \
+        break;                                                                                                   \
+    case 2 * G + 1:                                                                                              \
+        hipLaunchKernelGGL((spmv_kernel<G, true>), dim3(grid), dim3(kBlock), 0, s, A.nrows, A.rowptr, A.col,     \
+                           A.val, x, alpha, z, beta, y);                                                         \
         break;
         PHMG_SPMV_CASE(2)
         PHMG_SPMV_CASE(4)
@@ -860,8 +888,8 @@ void launch_spmv(hipStream_t s, const DevCsr& A, const double* x, double alpha, 
         PHMG_SPMV_CASE(64)
 #undef PHMG_SPMV_CASE
         default:
-            hipLaunchKernelGGL(spmv_kernel<8>, dim3(grid_for((int64_t)A.nrows * 8, kBlock)), dim3(kBlock), 0, s,
-                               A.nrows, A.rowptr, A.col, A.val, x, alpha, z, beta, y);
+            hipLaunchKernelGGL((spmv_kernel<8, false>), dim3(grid_for((int64_t)A.nrows * 8, kBlock)), dim3(kBlock), 0,
+                               s, A.nrows, A.rowptr, A.col, A.val, x, alpha, z, beta, y);
     }
 }
 

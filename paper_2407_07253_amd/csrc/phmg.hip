@@ -378,9 +378,12 @@ void tune_spmv(phmg_ctx ctx, DevCsr& A, const double* x, double* y) {
     hipcheck(hipEventCreate(&e0), "hipEventCreate");
     hipcheck(hipEventCreate(&e1), "hipEventCreate");
     int best = A.group;
+    bool best_x = false;
     float best_ms = 1e30f;
+    for (int xm = 0; xm < 2; ++xm)
     for (int g = 2; g <= 64; g *= 2) {
         A.group = g;
+        A.xcd = xm != 0;
         launch_spmv(s, A, x, 1.0, nullptr, 0.0, y);
         float gbest = 1e30f;
         for (int rep = 0; rep < 3; ++rep) {
@@ -395,11 +398,13 @@ void tune_spmv(phmg_ctx ctx, DevCsr& A, const double* x, double* y) {
         if (gbest < best_ms) {
             best_ms = gbest;
             best = g;
+            best_x = xm != 0;
         }
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     hipcheck(hipGetLastError(), "spmv autotune launch");
+    A.xcd = best_x;
     A.group = best;
     A.tuned = true;
 }

@@ -25,8 +25,10 @@ struct DevCsr {
     int32_t* col = nullptr;
     double* val = nullptr;
     int group = 8;                   // lanes per row in the SpMV (chosen by the set-up autotuner)
+    bool xcd = false;                // XCD-contiguous row ranges in the SpMV (autotuned)
     bool tuned = false;
     int bgroup = 1;                  // entries in flight per row in the block SpMM (autotuned on first use)
+    bool bxcd = false;               // XCD-contiguous row ranges in the block SpMM (autotuned)
     bool btuned = false;
 };
 

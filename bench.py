@@ -34,7 +34,7 @@ sys.path.insert(0, ROOT)
 METRIC = "Vanka patch-apply HBM GB/s; phMG-FGMRES time-to-1e-8, mixed vs FP64, 1 GPU"
 HBM_PEAK_GBS = 8000.0
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "patch_apply_cfg2_traffic.json")
-KERNEL_SOURCE = os.path.join(ROOT, "paper_2407_07253_amd", "csrc", "kernels.hip")
+KERNEL_SOURCE = os.path.join(ROOT, "paper_2407_07253_amd", "csrc", "patch_apply.hip")
 
 WORKLOADS = {
     "cfg2": "TH P4/P3 2D, Delaunay 64 seeded pts + corners, 3 refinements (170483 DoFs); phMG direct "
@@ -119,6 +119,80 @@ def cpu_baseline(workload: str, budget_s: float = 12.0):
     }
 
 
+def batched_leg(nrhs: int = 16) -> dict:
+    """16 right-hand sides solved together (block path): TH P4/P3 on the structured 128x128 mesh,
+    seeded Gaussian-bump forcings; FP64 vs FP32 vs BF16 patch inverses (MFMA block products),
+    FP64 FGMRES per column to 1e-8.  Also the same 16 systems solved one after another (FP64)."""
+    import torch
+
+    from paper_2407_07253_amd import frontend
+    from paper_2407_07253_amd._lib import Hierarchy
+
+    t0 = time.perf_counter()
+    fh = frontend.build_hierarchy("cfg3", forcing="bumps", nrhs=nrhs)
+    t_build = time.perf_counter() - t0
+    H = Hierarchy.from_frontend(fh)
+    nl = len(fh.levels)
+    n0 = fh.levels[0].n
+    B = torch.tensor(fh.b, device="cuda")
+    out = {"workload": "cfg3: " + WORKLOADS["cfg3"] + f"; {nrhs} seeded Gaussian-bump right-hand sides",
+           "levels_n": [L.n for L in fh.levels], "host_build_s": round(t_build, 2)}
+    info0 = H.level_info(0)
+    for prec in ("f64", "f32", "bf16"):
+        for l in range(nl - 1):
+            H.set_precision(l, prec)
+        H.setup()
+        X = torch.zeros_like(B)
+        H.fgmres_batched(B, X, rtol=1e-8)                  # first use: block autotune + graph capture
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        H.setup()
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        X.zero_()
+        its, rr, conv = H.fgmres_batched(B, X, rtol=1e-8)
+        torch.cuda.synchronize()
+        t3 = time.perf_counter()
+        r = torch.empty(n0, dtype=torch.float64, device="cuda")
+        true_rel = 0.0
+        for c in range(nrhs):
+            H.residual(0, B[c].contiguous(), X[c].contiguous(), r)
+            true_rel = max(true_rel, float(torch.linalg.norm(r) / torch.linalg.norm(B[c])))
+        Xr = torch.zeros_like(B)
+        for _ in range(3):
+            H.relax_apply_batched(0, B, Xr, 1)
+        H.profile(["patch_apply", "spmv", "scatter"])
+        H.profile_reset()
+        for _ in range(10):
+            H.relax_apply_batched(0, B, Xr, 1)
+        ms, cnt = H.profile_read("patch_apply", 0)
+        ms_sp, c_sp = H.profile_read("spmv", 0)
+        ms_sc, c_sc = H.profile_read("scatter", 0)
+        H.profile([])
+        eb = {"f64": 8, "f32": 4, "bf16": 2}[prec]
+        # factor words once for all columns + per slot: index 4 B, gathered row and staged row 2 x 16 x 8 B
+        byt = eb * info0["sum_m2"] + info0["sum_m"] * (4 + 2 * 8 * 16) + 20 * info0["npatch"]
+        avg = ms / max(cnt, 1)
+        out[prec] = {"setup_ms": _fmt((t2 - t1) * 1e3), "solve_ms": _fmt((t3 - t2) * 1e3),
+                     "time_to_1e-8_ms": _fmt((t3 - t1) * 1e3), "iters_min": min(its), "iters_max": max(its),
+                     "converged": bool(conv), "true_relres_max": _fmt(true_rel),
+                     "block_apply_ms": _fmt(avg), "block_apply_gbps": _fmt(byt / (avg * 1e-3) / 1e9),
+                     "block_apply_bytes": byt, "spmm_ms": _fmt(ms_sp / max(c_sp, 1)),
+                     "block_scatter_ms": _fmt(ms_sc / max(c_sc, 1))}
+    for l in range(nl - 1):
+        H.set_precision(l, "f64")
+    H.setup()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for c in range(nrhs):
+        x1 = torch.zeros(n0, dtype=torch.float64, device="cuda")
+        H.fgmres(B[c].contiguous(), x1, rtol=1e-8)
+    torch.cuda.synchronize()
+    out["f64_one_by_one_solve_ms"] = _fmt((time.perf_counter() - t1) * 1e3)
+    H.close()
+    return out
+
+
 def _fmt(v):
     return float(f"{v:.6g}") if isinstance(v, float) else v
 
@@ -134,6 +208,8 @@ def main() -> int:
                     help="apply: only the repeated level-0 relaxation sweeps (for counter runs)")
     ap.add_argument("--mixed", default="f32", choices=["f32", "bf16", "none"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-batched", action="store_true",
+                    help="skip the 16-right-hand-side batched leg (TH P4/P3 on the structured 128x128 mesh)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="apply phase: also run 3 plain device copies of 256 MiB (counter calibration)")
     args = ap.parse_args()
@@ -293,6 +369,9 @@ def main() -> int:
         result["patch_apply_gbps"] = {"f64": round(ap64["gbps"], 2), args.mixed: round(ap_mixed["gbps"], 2)}
         result["sweep_level0"][args.mixed] = {"wall_ms": round(ap_mixed["sweep_wall_ms"], 4),
                                               "gbps": round(ap_mixed["sweep_gbps"], 1)}
+    if not args.no_batched:
+        print("# batched leg (cfg3, 16 right-hand sides) ...", file=sys.stderr, flush=True)
+        result["batched_16rhs"] = batched_leg()
     if not args.no_cpu_baseline:
         print("# cpu baseline (oracle) ...", file=sys.stderr, flush=True)
         result["cpu_baseline"] = cpu_baseline(args.workload if args.workload != "cfg3" else "cfg2")

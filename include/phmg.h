@@ -153,6 +153,25 @@ phmg_status phmg_set_graphs(phmg_ctx ctx, int on);
 phmg_status phmg_fgmres_solve(phmg_ctx ctx, const double* b, double* x, double rtol, int restart, int maxit,
                               int* iters, double* relres);
 
+/* Adjoint (transposed) operators, for gradients through a solve.  They reuse
+ * the factors of relax_setup: with the stored B_i = (P_i K_i)^{-1},
+ * K_i^{-T} = P_i^T B_i^T, so the transposed sweep gathers W_i r[S_i] in DoF
+ * order, streams B_i^T and scatters through the pivot permutation (gather and
+ * scatter swap roles).  K^T is K itself when K is exactly symmetric (checked at
+ * create), else an explicit transposed copy made there.
+ *   relax_apply_transposed: nu sweeps x <- x + omega M^T (b - K_l^T x) with
+ *     M^T = sum_i R_i^T K_i^{-T} W_i R_i (Chebyshev: the forward interval);
+ *   vcycle_transposed:  x <- B^T b, B the preconditioner of phmg_vcycle (the
+ *     same cycle with K^T, the adjoint sweeps and the transposed coarse solve;
+ *     pre- and post-smoothing use equal counts, so this is exactly B^T);
+ *   fgmres_solve_transposed: FGMRES on K^T x = b right-preconditioned by B^T,
+ *     with the stopping rule and outputs of phmg_fgmres_solve.
+ * Same argument conventions, synchronisation and errors as the forward calls. */
+phmg_status phmg_relax_apply_transposed(phmg_ctx ctx, int level, const double* b, double* x, int nu);
+phmg_status phmg_vcycle_transposed(phmg_ctx ctx, const double* b, double* x);
+phmg_status phmg_fgmres_solve_transposed(phmg_ctx ctx, const double* b, double* x, double rtol, int restart,
+                                         int maxit, int* iters, double* relres);
+
 /* Several right-hand sides at once (1 <= nrhs <= PHMG_MAX_RHS).  B and X are
  * DEVICE float64 arrays of nrhs * n_l entries holding the systems one after
  * another (X[c * n_l + i] is DoF i of system c, i.e. a (nrhs, n) row-major

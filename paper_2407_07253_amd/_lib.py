@@ -93,12 +93,17 @@ _vcycle_b = _sig("phmg_vcycle_batched", C.c_int, [C.c_void_p, C.c_int, C.c_void_
 _fgmres_b = _sig("phmg_fgmres_solve_batched", C.c_int, [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_double,
                                                         C.c_int, C.c_int, C.POINTER(C.c_int32),
                                                         C.POINTER(C.c_double)])
+_apply_t = _sig("phmg_relax_apply_transposed", C.c_int, [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_int])
+_vcycle_t = _sig("phmg_vcycle_transposed", C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p])
+_fgmres_t = _sig("phmg_fgmres_solve_transposed", C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_double, C.c_int,
+                                                           C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_double)])
 MAX_RHS = 16
 
 EXPORTED = ["phmg_hierarchy_create", "phmg_hierarchy_destroy", "phmg_relax_setup", "phmg_set_precision",
             "phmg_relax_apply", "phmg_vcycle", "phmg_fgmres_solve", "phmg_residual", "phmg_get_level_info",
             "phmg_profile_enable", "phmg_profile_read", "phmg_profile_reset", "phmg_ritz_max_real",
             "phmg_set_graphs", "phmg_relax_apply_batched", "phmg_vcycle_batched", "phmg_fgmres_solve_batched",
+            "phmg_relax_apply_transposed", "phmg_vcycle_transposed", "phmg_fgmres_solve_transposed",
             "phmg_last_error"]
 
 
@@ -241,6 +246,21 @@ class Hierarchy:
         rr = C.c_double(0.0)
         st = _check(_fgmres(self._h, _vec_ptr(b, self.n[0], "b"), _vec_ptr(x, self.n[0], "x"), rtol, restart, maxit,
                             C.byref(it), C.byref(rr)), allow=(PHMG_ENOCONV,))
+        return int(it.value), float(rr.value), st == PHMG_OK
+
+    # ---- adjoint (transposed) operators ----
+    def relax_apply_transposed(self, level: int, b, x, nu: int = 1):
+        n = self.n[level]
+        _check(_apply_t(self._h, level, _vec_ptr(b, n, "b"), _vec_ptr(x, n, "x"), nu))
+
+    def vcycle_transposed(self, b, x):
+        _check(_vcycle_t(self._h, _vec_ptr(b, self.n[0], "b"), _vec_ptr(x, self.n[0], "x")))
+
+    def fgmres_transposed(self, b, x, rtol: float = 1e-8, restart: int = 30, maxit: int = 1000):
+        it = C.c_int(0)
+        rr = C.c_double(0.0)
+        st = _check(_fgmres_t(self._h, _vec_ptr(b, self.n[0], "b"), _vec_ptr(x, self.n[0], "x"), rtol, restart,
+                              maxit, C.byref(it), C.byref(rr)), allow=(PHMG_ENOCONV,))
         return int(it.value), float(rr.value), st == PHMG_OK
 
     # ---- several right-hand sides at once: tensors of shape (nrhs, n), nrhs <= 16 ----

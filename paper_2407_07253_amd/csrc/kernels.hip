@@ -161,7 +161,8 @@ __global__ __launch_bounds__(kBlock) void extract_kernel(const int64_t* __restri
 // performed: what is stored is B = (P K_i)^{-1}, and K_i^{-1} r = B (P r).  The
 // kernel writes the permuted DoF list pdofs_perm[t] = pdofs[idx[t]] (idx =
 // identity with the swaps applied in order), so the patch solve gathers P r
-// at no extra cost.  The singularity threshold 1e-14 ||K_i||_inf comes from
+// at no extra cost, and idx itself (pidx): the transposed solve
+// K_i^{-T} v = P^T B^T v puts entry t of B^T v at local position idx[t].  The singularity threshold 1e-14 ||K_i||_inf comes from
 // the extraction kernel.
 //
 // MFMA f64 16x16x4 lane layout (lane l, accumulator element v):
@@ -174,7 +175,8 @@ __global__ __launch_bounds__(kBlock) void gj_kernel(const int64_t* __restrict__ 
                                                     const int32_t* __restrict__ order, double* __restrict__ F,
                                                     const double* __restrict__ ptol,
                                                     const int32_t* __restrict__ pdofs,
-                                                    int32_t* __restrict__ pdofs_perm, int ldq,
+                                                    int32_t* __restrict__ pdofs_perm,
+                                                    int32_t* __restrict__ pidx, int ldq,
                                                     int* __restrict__ status) {
     constexpr int W = kPanel, NWV = kBlock / kWave;
     __shared__ double s_cv[2][NWV];
@@ -346,7 +348,10 @@ __global__ __launch_bounds__(kBlock) void gj_kernel(const int64_t* __restrict__ 
         }
     }
     __syncthreads();
-    for (int t = tid; t < m; t += kBlock) pdofs_perm[base + t] = pdofs[base + s_phys[t]];
+    for (int t = tid; t < m; t += kBlock) {
+        pdofs_perm[base + t] = pdofs[base + s_phys[t]];
+        pidx[base + t] = s_phys[t];
+    }
 }
 
 // f64 set-up result (column-major, ld = m) -> reduced-precision factors with
@@ -796,7 +801,7 @@ void launch_patch_factor(hipStream_t s, const Level& L, double* A) {
         if (lds > 64 * 1024)
             (void)hipFuncSetAttribute((const void*)kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         hipLaunchKernelGGL(kernel, dim3(L.npatch), dim3(kBlock), lds, s, L.pptr, L.foff, L.order, A, L.ptol,
-                           L.pdofs, L.pdofs_perm, ldq, L.status);
+                           L.pdofs, L.pdofs_perm, L.pidx, ldq, L.status);
     };
     if (R <= 1) go(gj_kernel<1>);
     else if (R <= 2) go(gj_kernel<2>);
@@ -814,11 +819,11 @@ void launch_convert_patches(hipStream_t s, const Level& L, const double* src, vo
 }
 
 void launch_scatter(hipStream_t s, const Level& L, double a, double c, double* d, bool store_d, double* x,
-                    bool x_zero) {
+                    bool x_zero, bool transpose) {
     if (L.n <= 0) return;
     const int flags = (x_zero ? 1 : 0) | (c != 0.0 ? 2 : 0) | (store_d ? 4 : 0);
     hipLaunchKernelGGL(scatter_kernel, dim3(grid_for(L.n, kBlock)), dim3(kBlock), 0, s, L.n, L.sptr, L.sslot,
-                       L.pweight, L.Y, a, c, d, x, flags);
+                       transpose ? nullptr : L.pweight, L.Y, a, c, d, x, flags);
 }
 
 void launch_power_start(hipStream_t s, int64_t n, double* v) {

@@ -65,6 +65,29 @@ DevCsr upload_csr(phmg_ctx ctx, const phmg_csr& A) {
     return upload_csr(ctx, A.nrows, A.ncols, rp, ci, v);
 }
 
+// exact symmetry of a CSR matrix with sorted columns (structure and values)
+bool is_symmetric(const phmg_csr& A) {
+    if (A.nrows != A.ncols) return false;
+    for (int32_t i = 0; i < A.nrows; ++i)
+        for (int32_t k = A.rowptr[i]; k < A.rowptr[i + 1]; ++k) {
+            const int32_t j = A.col[k];
+            if (j < i) continue;
+            // entry (i, j), j >= i, must equal (j, i): binary search in row j
+            const int32_t* b0 = A.col + A.rowptr[j];
+            const int32_t* b1 = A.col + A.rowptr[j + 1];
+            const int32_t* f = std::lower_bound(b0, b1, i);
+            if (f == b1 || *f != i || A.val[f - A.col] != A.val[k]) return false;
+        }
+    // each upper entry matched a distinct lower one; equal counts leave none unmatched
+    int64_t lower = 0, upper = 0;
+    for (int32_t i = 0; i < A.nrows; ++i)
+        for (int32_t k = A.rowptr[i]; k < A.rowptr[i + 1]; ++k) {
+            if (A.col[k] < i) ++lower;
+            else if (A.col[k] > i) ++upper;
+        }
+    return lower == upper;
+}
+
 DevCsr upload_transpose(phmg_ctx ctx, const phmg_csr& A) {
     std::vector<int32_t> rp(A.ncols + 1, 0), ci(A.nnz);
     std::vector<double> v(A.nnz);
@@ -88,8 +111,10 @@ DevCsr upload_transpose(phmg_ctx ctx, const phmg_csr& A) {
 // nu smoothing steps on level l (eq. "eq:ASM"): damped Richardson, or the
 // Chebyshev acceleration of the additive Schwarz operator used in the paper's
 // experiments.  With x_zero the incoming x is ignored (treated as 0) and the
-// first residual is b itself.
-void relax(phmg_ctx ctx, int l, const double* b, double* x, int nu, bool x_zero) {
+// first residual is b itself.  With transpose the sweep is the adjoint one:
+// K^T and M^T = sum_i R_i^T K_i^{-T} W_i R_i (the same Chebyshev interval:
+// M^T K^T has the spectrum of M K).
+void relax(phmg_ctx ctx, int l, const double* b, double* x, int nu, bool x_zero, bool transpose = false) {
     Level& L = ctx->L[l];
     hipStream_t s = ctx->stream;
     if (nu == 0) {
@@ -109,22 +134,23 @@ void relax(phmg_ctx ctx, int l, const double* b, double* x, int nu, bool x_zero)
         const double* r = b;                         // x = 0: the residual is b itself
         if (!(it == 0 && x_zero)) {
             Timed t(ctx, PHMG_K_SPMV, l);
-            launch_spmv(s, L.K, x, -1.0, b, 1.0, L.r);
+            launch_spmv(s, transpose ? L.KT : L.K, x, -1.0, b, 1.0, L.r);
             r = L.r;
         }
         {
             Timed t(ctx, PHMG_K_PATCH_APPLY, l);
-            launch_patch_apply(s, L, r);
+            if (transpose) launch_patch_apply_t(s, L, r);
+            else launch_patch_apply(s, L, r);
         }
         Timed t(ctx, PHMG_K_SCATTER, l);
         const bool xz = it == 0 && x_zero;
         if (!cheb) {
-            launch_scatter(s, L, ctx->opts.omega, 0.0, nullptr, false, x, xz);
+            launch_scatter(s, L, ctx->opts.omega, 0.0, nullptr, false, x, xz, transpose);
         } else if (it == 0) {
-            launch_scatter(s, L, 1.0 / theta, 0.0, L.d, nu > 1, x, xz);
+            launch_scatter(s, L, 1.0 / theta, 0.0, L.d, nu > 1, x, xz, transpose);
         } else {
             const double rho = 1.0 / (2.0 * sigma - rho_prev);
-            launch_scatter(s, L, 2.0 * rho / delta, rho * rho_prev, L.d, it + 1 < nu, x, false);
+            launch_scatter(s, L, 2.0 * rho / delta, rho * rho_prev, L.d, it + 1 < nu, x, false, transpose);
             rho_prev = rho;
         }
     }
@@ -280,58 +306,64 @@ double arnoldi_estimate(phmg_ctx ctx, int l) {
     return ritz_max_real(H.data(), k + 1, k);
 }
 
-void cycle(phmg_ctx ctx, int l, const double* b, double* x, bool x_zero) {
+// One cycle on level l.  transpose gives the adjoint operator B^T: the same
+// cycle with K^T, the adjoint sweeps and the transposed coarse solve (with
+// equal pre- and post-smoothing the transposed algorithm is exactly B^T).
+void cycle(phmg_ctx ctx, int l, const double* b, double* x, bool x_zero, bool transpose = false) {
     const int last = (int)ctx->L.size() - 1;
     hipStream_t s = ctx->stream;
     if (l == last) {
-        launch_coarse_solve(s, ctx->L[l], b, x);
+        if (transpose) launch_coarse_solve_t(s, ctx->L[l], b, x);
+        else launch_coarse_solve(s, ctx->L[l], b, x);
         return;
     }
     Level& L = ctx->L[l];
     Level& C = ctx->L[l + 1];
     const int np = ctx->opts.n_plevels;
     const int nu = l < np ? ctx->opts.nu_p : ctx->opts.nu_h;
-    relax(ctx, l, b, x, nu, x_zero);
+    relax(ctx, l, b, x, nu, x_zero, transpose);
     {
         Timed t(ctx, PHMG_K_SPMV, l);
-        launch_spmv(s, L.K, x, -1.0, b, 1.0, L.r);
+        launch_spmv(s, transpose ? L.KT : L.K, x, -1.0, b, 1.0, L.r);
     }
     {
         Timed t(ctx, PHMG_K_SPMV, l);
         launch_spmv(s, L.R, L.r, 1.0, nullptr, 0.0, C.b);
     }
     if (l + 1 < np || l + 1 == last || l >= np) {
-        cycle(ctx, l + 1, C.b, C.x, true);
+        cycle(ctx, l + 1, C.b, C.x, true, transpose);
     } else {
-        for (int t = 0; t < ctx->opts.n_v; ++t) cycle(ctx, l + 1, C.b, C.x, t == 0);
+        for (int t = 0; t < ctx->opts.n_v; ++t) cycle(ctx, l + 1, C.b, C.x, t == 0, transpose);
     }
     {
         Timed t(ctx, PHMG_K_SPMV, l);
         launch_spmv(s, L.P, C.x, 1.0, x, 1.0, x);
     }
-    relax(ctx, l, b, x, nu, false);
+    relax(ctx, l, b, x, nu, false, transpose);
 }
 
-void vcycle(phmg_ctx ctx, const double* b, double* x) {
+void vcycle(phmg_ctx ctx, const double* b, double* x, bool transpose = false) {
     if (ctx->opts.n_plevels == 0) {
-        for (int t = 0; t < ctx->opts.n_v; ++t) cycle(ctx, 0, b, x, t == 0);
+        for (int t = 0; t < ctx->opts.n_v; ++t) cycle(ctx, 0, b, x, t == 0, transpose);
     } else {
-        cycle(ctx, 0, b, x, true);
+        cycle(ctx, 0, b, x, true, transpose);
     }
 }
 
 void invalidate_graph(phmg_ctx ctx) {
     invalidate_block_graph(ctx);
-    if (ctx->vexec) (void)hipGraphExecDestroy(ctx->vexec);
-    if (ctx->vgraph) (void)hipGraphDestroy(ctx->vgraph);
-    ctx->vexec = nullptr;
-    ctx->vgraph = nullptr;
+    for (int t = 0; t < 2; ++t) {
+        if (ctx->vexec[t]) (void)hipGraphExecDestroy(ctx->vexec[t]);
+        if (ctx->vgraph[t]) (void)hipGraphDestroy(ctx->vgraph[t]);
+        ctx->vexec[t] = nullptr;
+        ctx->vgraph[t] = nullptr;
+    }
 }
 
 // Capture one V-cycle (gin -> gout) on a private stream.  The cycle launches
 // kernels only (no copies, no memsets, no host synchronisation), so the graph
 // replays it exactly; it is rebuilt after every set-up or precision change.
-void build_graph(phmg_ctx ctx) {
+void build_graph(phmg_ctx ctx, bool transpose) {
     const int64_t n0 = ctx->L[0].n;
     if (!ctx->cap_stream) hipcheck(hipStreamCreate(&ctx->cap_stream), "hipStreamCreate");
     if (!ctx->gin) {
@@ -343,7 +375,7 @@ void build_graph(phmg_ctx ctx) {
     ctx->stream = ctx->cap_stream;
     hipcheck(hipStreamBeginCapture(ctx->cap_stream, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
     try {
-        vcycle(ctx, ctx->gin, ctx->gout);
+        vcycle(ctx, ctx->gin, ctx->gout, transpose);
     } catch (...) {
         hipGraph_t g = nullptr;
         (void)hipStreamEndCapture(ctx->cap_stream, &g);
@@ -352,21 +384,23 @@ void build_graph(phmg_ctx ctx) {
         throw;
     }
     ctx->stream = saved;
-    hipcheck(hipStreamEndCapture(ctx->cap_stream, &ctx->vgraph), "hipStreamEndCapture");
-    hipcheck(hipGraphInstantiate(&ctx->vexec, ctx->vgraph, nullptr, nullptr, 0), "hipGraphInstantiate");
+    const int t = transpose ? 1 : 0;
+    hipcheck(hipStreamEndCapture(ctx->cap_stream, &ctx->vgraph[t]), "hipStreamEndCapture");
+    hipcheck(hipGraphInstantiate(&ctx->vexec[t], ctx->vgraph[t], nullptr, nullptr, 0), "hipGraphInstantiate");
 }
 
 // x <- B b (one preconditioner application): the captured graph when graphs
 // are on and no per-kernel profiling is requested, the eager launches otherwise.
-void precond(phmg_ctx ctx, const double* b, double* x) {
+void precond(phmg_ctx ctx, const double* b, double* x, bool transpose = false) {
     if (!ctx->use_graphs || ctx->prof.mask) {
-        vcycle(ctx, b, x);
+        vcycle(ctx, b, x, transpose);
         return;
     }
-    if (!ctx->vexec) build_graph(ctx);
+    const int t = transpose ? 1 : 0;
+    if (!ctx->vexec[t]) build_graph(ctx, transpose);
     const int64_t n0 = ctx->L[0].n;
     launch_copy(ctx->stream, n0, b, ctx->gin);
-    hipcheck(hipGraphLaunch(ctx->vexec, ctx->stream), "hipGraphLaunch");
+    hipcheck(hipGraphLaunch(ctx->vexec[t], ctx->stream), "hipGraphLaunch");
     launch_copy(ctx->stream, n0, ctx->gout, x);
 }
 
@@ -531,8 +565,9 @@ void ensure_krylov(phmg_ctx ctx, int restart) {
     ctx->restart_cap = restart;
 }
 
+// transpose: the adjoint solve K^T x = b, right-preconditioned by B^T.
 phmg_status fgmres(phmg_ctx ctx, const double* b, double* x, double rtol, int restart, int maxit, int* iters_out,
-                   double* relres_out) {
+                   double* relres_out, bool transpose = false) {
     Level& L0 = ctx->L[0];
     const int64_t n = L0.n;
     hipStream_t s = ctx->stream;
@@ -545,7 +580,7 @@ phmg_status fgmres(phmg_ctx ctx, const double* b, double* x, double rtol, int re
     double* h2 = ctx->hdev + (restart + 2);
     double* hn2 = ctx->hdev + 2 * (restart + 2);
 
-    launch_spmv(s, L0.K, x, -1.0, b, 1.0, r);
+    launch_spmv(s, transpose ? L0.KT : L0.K, x, -1.0, b, 1.0, r);
     double beta = device_norm(ctx, r);
     const double r0 = beta;
     const double target = rtol * r0;
@@ -568,8 +603,8 @@ phmg_status fgmres(phmg_ctx ctx, const double* b, double* x, double rtol, int re
         for (int j = 0; j < restart; ++j) {
             double* vj = V + (int64_t)j * n;
             double* zj = Z + (int64_t)j * n;
-            precond(ctx, vj, zj);
-            launch_spmv(s, L0.K, zj, 1.0, nullptr, 0.0, w);
+            precond(ctx, vj, zj, transpose);
+            launch_spmv(s, transpose ? L0.KT : L0.K, zj, 1.0, nullptr, 0.0, w);
             launch_multidot(s, n, j + 1, V, n, w, ctx->partial, h1, false);
             launch_gemv_sub(s, n, j + 1, V, n, h1, w);
             launch_multidot(s, n, j + 1, V, n, w, ctx->partial, h2, false);
@@ -610,7 +645,7 @@ phmg_status fgmres(phmg_ctx ctx, const double* b, double* x, double rtol, int re
         double* yd = h2;   // reuse: h2 is consumed
         hipcheck(hipMemcpyAsync(yd, y.data(), sizeof(double) * ncols, hipMemcpyHostToDevice, s), "H2D");
         launch_gemv_add(s, n, ncols, Z, n, yd, x);
-        launch_spmv(s, L0.K, x, -1.0, b, 1.0, r);
+        launch_spmv(s, transpose ? L0.KT : L0.K, x, -1.0, b, 1.0, r);
         beta = device_norm(ctx, r);
         if (beta <= target) {
             converged = true;
@@ -721,6 +756,9 @@ phmg_status phmg_hierarchy_create(const phmg_hierarchy_desc* desc, const phmg_cy
             Level& L = ctx->L[l];
             L.n = desc->K[l].nrows;
             L.K = upload_csr(ctx, desc->K[l]);
+            // K^T for the adjoint path: the same arrays when K is symmetric (the
+            // Stokes matrices are), otherwise an explicit transposed copy
+            L.KT = is_symmetric(desc->K[l]) ? L.K : upload_transpose(ctx, desc->K[l]);
             L.r = dalloc<double>(ctx, L.n);
             L.d = dalloc<double>(ctx, L.n);
             L.status = dalloc<int>(ctx, 1);
@@ -765,6 +803,7 @@ phmg_status phmg_hierarchy_create(const phmg_hierarchy_desc* desc, const phmg_cy
                 L.pptr = upload(ctx, pt.ptr, pt.npatch + 1);
                 L.pdofs = upload(ctx, pt.dofs, L.sum_m);
                 L.pdofs_perm = dalloc<int32_t>(ctx, L.sum_m);
+                L.pidx = dalloc<int32_t>(ctx, L.sum_m);
                 L.ptol = dalloc<double>(ctx, pt.npatch);
                 L.pweight = pt.weight ? upload(ctx, pt.weight, L.sum_m) : nullptr;
                 L.foff = upload(ctx, foff.data(), pt.npatch);
@@ -870,6 +909,41 @@ phmg_status phmg_fgmres_solve(phmg_ctx ctx, const double* b, double* x, double r
         const phmg_status st = fgmres(ctx, b, x, rtol, restart, maxit, iters, relres);
         hipcheck(hipGetLastError(), "kernel launch");
         if (st == PHMG_ENOCONV) g_last_error = "FGMRES reached maxit without converging";
+        return st;
+    });
+}
+
+phmg_status phmg_relax_apply_transposed(phmg_ctx ctx, int level, const double* b, double* x, int nu) {
+    return guarded([&]() -> phmg_status {
+        if (!ctx || !b || !x) fail(PHMG_EINVAL, "null argument");
+        if (level < 0 || level >= (int)ctx->L.size() - 1) fail(PHMG_EINVAL, "level out of range (coarsest has no patches)");
+        if (nu < 0) fail(PHMG_EINVAL, "nu < 0");
+        if (!ctx->L[level].ready) fail(PHMG_ESTATE, lvl(level) + "relax_setup has not been run");
+        relax(ctx, level, b, x, nu, false, true);
+        hipcheck(hipGetLastError(), "kernel launch");
+        return PHMG_OK;
+    });
+}
+
+phmg_status phmg_vcycle_transposed(phmg_ctx ctx, const double* b, double* x) {
+    return guarded([&]() -> phmg_status {
+        if (!ctx || !b || !x) fail(PHMG_EINVAL, "null argument");
+        require_ready(ctx);
+        precond(ctx, b, x, true);
+        hipcheck(hipGetLastError(), "kernel launch");
+        return PHMG_OK;
+    });
+}
+
+phmg_status phmg_fgmres_solve_transposed(phmg_ctx ctx, const double* b, double* x, double rtol, int restart,
+                                         int maxit, int* iters, double* relres) {
+    return guarded([&]() -> phmg_status {
+        if (!ctx || !b || !x || !iters || !relres) fail(PHMG_EINVAL, "null argument");
+        if (restart < 1 || maxit < 1 || !(rtol >= 0.0)) fail(PHMG_EINVAL, "invalid rtol / restart / maxit");
+        require_ready(ctx);
+        const phmg_status st = fgmres(ctx, b, x, rtol, restart, maxit, iters, relres, true);
+        hipcheck(hipGetLastError(), "kernel launch");
+        if (st == PHMG_ENOCONV) g_last_error = "FGMRES (transposed) reached maxit without converging";
         return st;
     });
 }

@@ -35,6 +35,7 @@ struct DevCsr {
 struct Level {
     int32_t n = 0;
     DevCsr K;
+    DevCsr KT;                       // K^T (shares K's arrays when K is symmetric)
     DevCsr P;                        // prolongation from level+1 into this level (n x n_{l+1})
     DevCsr R;                        // restriction R = P^T (n_{l+1} x n)
 
@@ -45,6 +46,7 @@ struct Level {
     int64_t* pptr = nullptr;         // npatch + 1
     int32_t* pdofs = nullptr;        // sum_m
     int32_t* pdofs_perm = nullptr;   // sum_m: pdofs permuted by each patch's pivoting (gather of P r)
+    int32_t* pidx = nullptr;         // sum_m: the pivoting permutation as local positions (P r)_t = r[pidx[t]]
     double* ptol = nullptr;          // npatch: singularity threshold 1e-14 ||K_i||_inf
     double* pweight = nullptr;       // sum_m or null (W_i = I)
     int64_t* foff = nullptr;         // offset of patch i's m_i x m_i block (elements, float64 layout)
@@ -121,8 +123,8 @@ struct phmg_ctx_s {
     // the preconditioner (one V-cycle) captured as a HIP graph on fixed buffers
     bool use_graphs = true;
     hipStream_t cap_stream = nullptr;
-    hipGraph_t vgraph = nullptr;
-    hipGraphExec_t vexec = nullptr;
+    hipGraph_t vgraph[2] = {nullptr, nullptr};      // [0] B, [1] B^T (adjoint cycle)
+    hipGraphExec_t vexec[2] = {nullptr, nullptr};
     double* gin = nullptr;
     double* gout = nullptr;
     // block path: work vectors, FGMRES block basis and its captured V-cycle
@@ -154,11 +156,14 @@ void launch_extract(hipStream_t s, const Level& L, double* out);
 void launch_patch_factor(hipStream_t s, const Level& L, double* A);
 void launch_convert_patches(hipStream_t s, const Level& L, const double* src, void* dst);
 void launch_patch_apply(hipStream_t s, const Level& L, const double* r);
+// adjoint patch solve y_i = K_i^{-T} W_i r[S_i] from the same stored inverses (adjoint_kernels.hip)
+void launch_patch_apply_t(hipStream_t s, const Level& L, const double* r);
 int apply_variant_count(int prec);
 // dn = a * sum_t w_t Y_t + c * d;  x = (x_zero ? 0 : x) + dn;  d = dn if store_d
 // (c = 0: d is not read; d may be null when c = 0 and !store_d)
+// transpose: the adjoint sweep's scatter (weights W_i were applied at the gather)
 void launch_scatter(hipStream_t s, const Level& L, double a, double c, double* d, bool store_d, double* x,
-                    bool x_zero);
+                    bool x_zero, bool transpose = false);
 void launch_power_start(hipStream_t s, int64_t n, double* v);
 void launch_scale_by_devnorm(hipStream_t s, int64_t n, const double* src, const double* norm2, double* dst);
 void launch_coarse_build(hipStream_t s, const Level& L, double* dense);
@@ -168,6 +173,7 @@ int coarse_panel_width(int N);   // 0 when N is too large for the dense coarse s
 void launch_dense_gj(hipStream_t s, double* A, int N, int* piv, int* status, double* tol, double* work);
 void launch_transpose(hipStream_t s, int n, const double* src, double* dst);
 void launch_coarse_solve(hipStream_t s, const Level& L, const double* b, double* x);
+void launch_coarse_solve_t(hipStream_t s, const Level& L, const double* b, double* x);   // transposed
 // FGMRES helpers
 void launch_multidot(hipStream_t s, int64_t n, int ncol, const double* V, int64_t ldv, const double* w,
                      double* partial, double* out, bool accumulate);

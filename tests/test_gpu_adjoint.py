@@ -1,0 +1,149 @@
+"""Adjoint (transposed) GPU operators against the oracle's transposed cycle.
+
+The library's transposed sweep reuses the forward factors (K_i^{-T} = P_i^T B_i^T
+with the stored B_i = (P_i K_i)^{-1}); the oracle solves with its own LU
+transposed (oracle/lu.py lu_solve_transposed).  Tolerances as in the forward
+parity tests.  The adjoint identity <y, B x> = <B^T y, x> is checked on the GPU
+alone as a property that holds for any correct pair.
+"""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+pytestmark = pytest.mark.gpu
+
+from oracle import fgmres as ofgmres  # noqa: E402
+from oracle import multigrid as omg  # noqa: E402
+from oracle import problems as oproblems  # noqa: E402
+from paper_2407_07253_amd import frontend  # noqa: E402
+
+_CACHE = {}
+
+
+def _pair(name):
+    if name not in _CACHE:
+        from paper_2407_07253_amd._lib import Hierarchy
+        fh = frontend.build_hierarchy(name)
+        H = Hierarchy.from_frontend(fh)
+        H.setup()
+        ol, od, oopts, ob = oproblems.build(name)
+        omg.setup(ol, oopts)
+        _CACHE[name] = (fh, H, ol, od, oopts, ob)
+    return _CACHE[name]
+
+
+def _dev(a):
+    return torch.tensor(np.ascontiguousarray(a, dtype=np.float64), device="cuda")
+
+
+def _host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+def _rel(a, b):
+    return float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-300))
+
+
+def _normalise(x, nfu):
+    y = np.array(x, copy=True)
+    y[2 * nfu:] -= y[2 * nfu:].mean()
+    return y
+
+
+NAMES = ["cfg1", "cfg2_r1", "sv_small"]
+
+
+@pytest.mark.parametrize("name", NAMES)
+@pytest.mark.parametrize("nu", [1, 2])
+def test_transposed_relax_matches_oracle(name, nu):
+    fh, H, ol, od, oopts, ob = _pair(name)
+    rng = np.random.default_rng(500 + nu)
+    for l in range(len(ol) - 1):
+        n = ol[l].n
+        b, x = rng.standard_normal(n), rng.standard_normal(n)
+        xg = _dev(x)
+        H.relax_apply_transposed(l, _dev(b), xg, nu)
+        got = _host(xg)
+        ref = omg._relax(ol[l], oopts, b, x, nu, True)
+        err = _rel(got, ref)
+        print(f"{name} level {l} nu={nu}: transposed sweep rel err {err:.2e}")
+        assert err <= 1e-11, (l, err)
+
+
+@pytest.mark.parametrize("name", NAMES)
+def test_transposed_vcycle_matches_oracle(name):
+    fh, H, ol, od, oopts, ob = _pair(name)
+    rng = np.random.default_rng(8)
+    b = rng.standard_normal(ol[0].n)
+    z = _dev(np.full(ol[0].n, np.nan))
+    H.vcycle_transposed(_dev(b), z)
+    got = _host(z)
+    ref = omg.vcycle(ol, oopts, b, transpose=True)
+    err = _rel(got, ref)
+    print(f"{name} transposed vcycle rel err {err:.2e}")
+    assert err <= 1e-11
+
+
+@pytest.mark.parametrize("name", NAMES)
+def test_transposed_vcycle_is_the_adjoint(name):
+    """<y, B x> = <B^T y, x> for random x, y (B the forward V-cycle operator)."""
+    fh, H, ol, od, oopts, ob = _pair(name)
+    rng = np.random.default_rng(9)
+    n = ol[0].n
+    worst = 0.0
+    for _ in range(3):
+        x, y = rng.standard_normal(n), rng.standard_normal(n)
+        bx, bty = _dev(np.zeros(n)), _dev(np.zeros(n))
+        H.vcycle(_dev(x), bx)
+        H.vcycle_transposed(_dev(y), bty)
+        Bx, BTy = _host(bx), _host(bty)
+        lhs, rhs = y @ Bx, BTy @ x
+        scale = np.linalg.norm(y) * np.linalg.norm(Bx)
+        worst = max(worst, abs(lhs - rhs) / scale)
+    print(f"{name}: |<y,Bx> - <B^T y,x>| / (|y||Bx|) = {worst:.2e}")
+    assert worst <= 1e-12
+
+
+@pytest.mark.parametrize("name", NAMES)
+def test_transposed_fgmres_matches_oracle(name):
+    fh, H, ol, od, oopts, ob = _pair(name)
+    rng = np.random.default_rng(10)
+    g = rng.standard_normal(ol[0].n)
+    g[2 * od[0].nfu:] -= g[2 * od[0].nfu:].mean()       # consistent: orthogonal to the pressure kernel
+    x = _dev(np.zeros_like(g))
+    iters, relres, conv = H.fgmres_transposed(_dev(g), x, rtol=1e-8)
+    got = _host(x)
+    KT = ol[0].K.T.tocsr()
+    res = ofgmres.fgmres(lambda v: KT @ v, lambda v: omg.vcycle(ol, oopts, v, transpose=True), g, rtol=1e-8)
+    nfu = od[0].nfu
+    err = np.linalg.norm(_normalise(got, nfu) - _normalise(res.x, nfu)) / np.linalg.norm(_normalise(res.x, nfu))
+    print(f"{name}: transposed FGMRES GPU iters {iters} relres {relres:.3e}; oracle iters {res.iters} "
+          f"relres {res.relres:.3e}; solution rel err {err:.2e}")
+    assert conv and res.converged
+    assert iters == res.iters
+    assert err <= 1e-10
+
+
+@pytest.mark.parametrize("prec", ["f32", "bf16"])
+def test_transposed_reduced_precision_is_the_adjoint(prec):
+    """With FP32 / BF16 inverses the transposed sweep is still the adjoint of the forward
+    one up to float32 rounding of the two products."""
+    from paper_2407_07253_amd._lib import Hierarchy
+    fh = frontend.build_hierarchy("cfg2_r1")
+    H = Hierarchy.from_frontend(fh)
+    for l in range(len(fh.levels) - 1):
+        H.set_precision(l, prec)
+    H.setup()
+    n = fh.levels[0].n
+    rng = np.random.default_rng(12)
+    x, y = rng.standard_normal(n), rng.standard_normal(n)
+    bx, bty = _dev(np.zeros(n)), _dev(np.zeros(n))
+    H.vcycle(_dev(x), bx)
+    H.vcycle_transposed(_dev(y), bty)
+    Bx, BTy = _host(bx), _host(bty)
+    d = abs(y @ Bx - BTy @ x) / (np.linalg.norm(y) * np.linalg.norm(Bx))
+    print(f"{prec}: adjoint defect {d:.2e}")
+    assert d <= 1e-5
+    H.close()

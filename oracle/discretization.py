@@ -139,6 +139,7 @@ class Stokes:
     Bx_full: sp.csr_matrix
     By_full: sp.csr_matrix
     g: Optional[np.ndarray] = None  # Dirichlet values at all velocity nodes (2, nV)
+    log_visc: Optional[np.ndarray] = None   # nodal log-viscosity at the mesh vertices (None: nu = 1)
 
     @property
     def n(self) -> int:
@@ -161,12 +162,23 @@ class Stokes:
         return z
 
 
+def p1_weights(qpts: np.ndarray) -> np.ndarray:
+    """Barycentric (P1 hat) values of the three cell vertices at reference points, (nq, 3)."""
+    return np.stack([1.0 - qpts[:, 0] - qpts[:, 1], qpts[:, 0], qpts[:, 1]], axis=1)
+
+
 def assemble_stokes(mesh, k: int, kind: str,
                     forcing: Optional[Callable] = None,
-                    dirichlet: Optional[Callable] = None) -> Stokes:
+                    dirichlet: Optional[Callable] = None,
+                    log_visc: Optional[np.ndarray] = None) -> Stokes:
     """Assemble K and b on free DoFs (eq. "eq:stokes-disc", "eq:saddle").
 
     forcing(x, y) -> (fx, fy); dirichlet(x, y) -> (gx, gy) on boundary nodes.
+    log_visc: values l_v at the mesh vertices; the viscosity is the piecewise
+    linear interpolant of exp(l), nu_h = sum_v exp(l_v) lambda_v, and the
+    velocity block becomes int nu_h grad u : grad v (the paper takes nu = 1;
+    the variable field serves the gradient workload).  The rule of degree 2k
+    integrates nu_h grad phi_a . grad phi_b (degree 2k - 1) exactly.
     """
     verts, cells = mesh.verts, mesh.cells
     V = ScalarSpace(verts, cells, k, continuous=True)
@@ -174,6 +186,7 @@ def assemble_stokes(mesh, k: int, kind: str,
     qpts, qw = element.quadrature(2 * k)
     phi, dphi = element.eval_basis(k, qpts)
     psi, _ = element.eval_basis(k - 1, qpts) if k - 1 >= 1 else (np.ones((len(qw), 1)), None)
+    lam = p1_weights(qpts)
 
     rows_L, cols_L, vals_L = [], [], []
     rows_B, cols_B, vals_Bx, vals_By = [], [], [], []
@@ -183,7 +196,11 @@ def assemble_stokes(mesh, k: int, kind: str,
         x0, J, adet, JinvT = cell_geometry(verts, cells[c])
         grad = np.einsum("ij,qnj->qni", JinvT, dphi)          # physical gradients
         w = qw * adet
-        Lc = np.einsum("q,qai,qbi->ab", w, grad, grad)
+        if log_visc is None:
+            Lc = np.einsum("q,qai,qbi->ab", w, grad, grad)
+        else:
+            nu_q = lam @ np.exp(log_visc[cells[c]])
+            Lc = np.einsum("q,qai,qbi->ab", w * nu_q, grad, grad)
         Bxc = -np.einsum("q,qi,qa->ia", w, psi, grad[:, :, 0])
         Byc = -np.einsum("q,qi,qa->ia", w, psi, grad[:, :, 1])
         vd = V.cell_dofs[c]
@@ -232,7 +249,8 @@ def assemble_stokes(mesh, k: int, kind: str,
     bu_y = Fy[free] - L[free][:, bnd] @ g[1, bnd]
     bp = -(Bx[:, bnd] @ g[0, bnd] + By[:, bnd] @ g[1, bnd])
     b = np.concatenate([bu_x, bu_y, bp])
-    return Stokes(mesh, k, kind, V, Q, free, nfu, nQ, K, b, L, Bx, By, g)
+    return Stokes(mesh, k, kind, V, Q, free, nfu, nQ, K, b, L, Bx, By, g,
+                  None if log_visc is None else np.array(log_visc, dtype=np.float64))
 
 
 def load_vector(disc: Stokes, forcing: Callable) -> np.ndarray:

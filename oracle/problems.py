@@ -71,12 +71,15 @@ def gradual_schedule(k: int) -> List[int]:
 
 
 def build(name: str, k: int = None, weights: str = None, with_rhs: bool = True,
-          specs=None, opts=None, forcing: str = "mms", nrhs: int = 1):
+          specs=None, opts=None, forcing: str = "mms", nrhs: int = 1, log_visc=None):
     """Assemble every level, its patches and the transfers.  Returns (levels, discs, opts, b).
 
     forcing "mms": b is the manufactured-solution right-hand side (n,).
     forcing "bumps": b is (nrhs, n), one seeded Gaussian-bump forcing per row,
     homogeneous Dirichlet data.
+    log_visc: nodal log-viscosity on the finest mesh's vertices (variable
+    viscosity nu_h = P1 interpolant of exp(l)); every level is rediscretised
+    with l injected to its own vertices (nested meshes keep vertex ids).
     """
     meshes = synth.config_mesh_hierarchy(name)[::-1]          # finest first
     if specs is None:
@@ -91,7 +94,13 @@ def build(name: str, k: int = None, weights: str = None, with_rhs: bool = True,
         g = lambda x, y: synth.mms_velocity(x, y, A)
     discs = []
     for li, (mi, kk, kind) in enumerate(specs):
-        d = assemble_stokes(meshes[mi], kk, kind, forcing=f if li == 0 else None, dirichlet=g if li == 0 else None)
+        lv = None
+        if log_visc is not None:
+            nv = meshes[mi].verts.shape[0]
+            assert np.array_equal(meshes[mi].verts, meshes[0].verts[:nv])
+            lv = np.asarray(log_visc, dtype=np.float64)[:nv]
+        d = assemble_stokes(meshes[mi], kk, kind, forcing=f if li == 0 else None, dirichlet=g if li == 0 else None,
+                            log_visc=lv)
         discs.append(d)
     levels = []
     for li, d in enumerate(discs):

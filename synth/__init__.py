@@ -25,4 +25,7 @@ from .problem_data import (  # noqa: F401
     mms_forcing,
     gaussian_bump_params,
     gaussian_bump_forcing,
+    fourier_field_params,
+    fourier_field,
+    log_viscosity,
 )

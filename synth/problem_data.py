@@ -53,3 +53,27 @@ def gaussian_bump_params(nrhs: int, seed: int):
 def gaussian_bump_forcing(x: np.ndarray, y: np.ndarray, centre, width, direction):
     g = np.exp(-((x - centre[0]) ** 2 + (y - centre[1]) ** 2) / (2.0 * width ** 2))
     return direction[0] * g, direction[1] * g
+
+
+def fourier_field_params(seed: int, nmodes: int = 8, dim: int = 2, kmax: int = 2):
+    """A smooth random field g(x) = sum_m a_m cos(2 pi k_m . x + phi_m): integer wave
+    vectors k_m in [-kmax, kmax]^dim (never zero), a_m ~ N(0, 1/nmodes), phi_m ~ U[0, 2 pi)."""
+    rng = np.random.default_rng(seed)
+    ks = rng.integers(-kmax, kmax + 1, size=(nmodes, dim))
+    for m in range(nmodes):
+        if not ks[m].any():
+            ks[m, 0] = 1
+    amp = rng.standard_normal(nmodes) / np.sqrt(nmodes)
+    phase = rng.uniform(0.0, 2 * PI, size=nmodes)
+    return ks.astype(np.float64), amp, phase
+
+
+def fourier_field(pts: np.ndarray, params) -> np.ndarray:
+    """Evaluate the field at points (N, dim)."""
+    ks, amp, phase = params
+    return np.cos(2 * PI * pts @ ks.T + phase[None, :]) @ amp
+
+
+def log_viscosity(verts: np.ndarray, seed: int, scale: float = 0.5) -> np.ndarray:
+    """Nodal log-viscosity of the gradient workload: l = scale * g at the mesh vertices."""
+    return scale * fourier_field(verts, fourier_field_params(seed, dim=verts.shape[1]))

@@ -172,6 +172,23 @@ phmg_status phmg_vcycle_transposed(phmg_ctx ctx, const double* b, double* x);
 phmg_status phmg_fgmres_solve_transposed(phmg_ctx ctx, const double* b, double* x, double rtol, int restart,
                                          int maxit, int* iters, double* relres);
 
+/* Gradients through the solve (adjoint method).  For J(x_1..x_B) with
+ * K(theta) x_c = G f_c, the gradients are dJ/dtheta = -sum_c lam_c^T (dK/dtheta) x_c
+ * and dJ/df_c = G^T lam_c, where K^T lam_c = dJ/dx_c (phmg_fgmres_solve_transposed).
+ *   S (HOST csr, n_theta x nnz(K_0)): S[v, e] = d K_e / d theta_v, e indexing the
+ *     nonzeros of K_0 in its CSR order;
+ *   G (HOST csr, n_0 x n_f): the map from forcing parameters to the right-hand side.
+ * set_sensitivities copies both (and forms G^T) into device memory; it may be
+ * called again after K changes.  forcing_rhs: B_c = G F_c.  gradients:
+ * grad_theta (n_theta) = -S w with w_e = sum_c Lam_c[i_e] X_c[j_e], and, when
+ * grad_f is not NULL, grad_f_c = G^T Lam_c.  X, Lam (nrhs x n_0), F and grad_f
+ * (nrhs x n_f) and grad_theta are DEVICE float64 arrays, systems one after
+ * another.  Asynchronous; PHMG_ESTATE before set_sensitivities. */
+phmg_status phmg_set_sensitivities(phmg_ctx ctx, const phmg_csr* S, const phmg_csr* G);
+phmg_status phmg_forcing_rhs(phmg_ctx ctx, int nrhs, const double* F, double* B);
+phmg_status phmg_gradients(phmg_ctx ctx, int nrhs, const double* X, const double* Lam, double* grad_theta,
+                           double* grad_f);
+
 /* Several right-hand sides at once (1 <= nrhs <= PHMG_MAX_RHS).  B and X are
  * DEVICE float64 arrays of nrhs * n_l entries holding the systems one after
  * another (X[c * n_l + i] is DoF i of system c, i.e. a (nrhs, n) row-major

@@ -97,6 +97,9 @@ _apply_t = _sig("phmg_relax_apply_transposed", C.c_int, [C.c_void_p, C.c_int, C.
 _vcycle_t = _sig("phmg_vcycle_transposed", C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p])
 _fgmres_t = _sig("phmg_fgmres_solve_transposed", C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_double, C.c_int,
                                                            C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_double)])
+_set_sens = _sig("phmg_set_sensitivities", C.c_int, [C.c_void_p, C.POINTER(CsrT), C.POINTER(CsrT)])
+_forcing_rhs = _sig("phmg_forcing_rhs", C.c_int, [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p])
+_gradients = _sig("phmg_gradients", C.c_int, [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p])
 MAX_RHS = 16
 
 EXPORTED = ["phmg_hierarchy_create", "phmg_hierarchy_destroy", "phmg_relax_setup", "phmg_set_precision",
@@ -104,6 +107,7 @@ EXPORTED = ["phmg_hierarchy_create", "phmg_hierarchy_destroy", "phmg_relax_setup
             "phmg_profile_enable", "phmg_profile_read", "phmg_profile_reset", "phmg_ritz_max_real",
             "phmg_set_graphs", "phmg_relax_apply_batched", "phmg_vcycle_batched", "phmg_fgmres_solve_batched",
             "phmg_relax_apply_transposed", "phmg_vcycle_transposed", "phmg_fgmres_solve_transposed",
+            "phmg_set_sensitivities", "phmg_forcing_rhs", "phmg_gradients",
             "phmg_last_error"]
 
 
@@ -205,7 +209,42 @@ class Hierarchy:
         pts = [(l.patch_ptr, l.patch_dofs, l.patch_weight if weights else None) for l in levels[:-1]]
         opts = dict(fh.opts)
         opts.update(overrides)
-        return cls(K, P, pts, levels[-1].null_vector(), stream=stream, **opts)
+        H = cls(K, P, pts, levels[-1].null_vector(), stream=stream, **opts)
+        if levels[0].visc_sens is not None and levels[0].forcing_map is not None:
+            H.set_sensitivities(levels[0].visc_sens, levels[0].forcing_map)
+        return H
+
+    # -- adjoint gradients
+    def set_sensitivities(self, S, G):
+        """S: dK/dtheta over K_0's nonzeros (n_theta x nnz), G: forcing map (n_0 x n_f); frontend Csr."""
+        keep = []
+
+        def csr(A):
+            rowptr = np.ascontiguousarray(A.rowptr, dtype=np.int32)
+            col = np.ascontiguousarray(A.col, dtype=np.int32)
+            val = np.ascontiguousarray(A.val, dtype=np.float64)
+            keep.extend([rowptr, col, val])
+            return CsrT(int(A.nrows), int(A.ncols), int(col.size), _ptr(rowptr), _ptr(col), _ptr(val))
+
+        cs, cg = csr(S), csr(G)
+        _check(_set_sens(self._h, C.byref(cs), C.byref(cg)))
+        self.n_theta, self.n_f = int(S.nrows), int(G.ncols)
+
+    def forcing_rhs(self, F, B):
+        """B[c] = G F[c]; F (nrhs, n_f), B (nrhs, n_0) contiguous float64 CUDA tensors."""
+        k = F.shape[0]
+        if B.shape[0] != k:
+            raise ValueError("F and B must hold the same number of systems")
+        _check(_forcing_rhs(self._h, k, _vec_ptr(F, k * self.n_f, "F"), _vec_ptr(B, k * self.n[0], "B")))
+
+    def gradients(self, X, Lam, grad_theta, grad_f=None):
+        """grad_theta = -sum_c S (Lam_c o X_c on K's nonzeros); grad_f[c] = G^T Lam[c]."""
+        k = X.shape[0]
+        if Lam.shape[0] != k:
+            raise ValueError("X and Lam must hold the same number of systems")
+        pf = None if grad_f is None else _vec_ptr(grad_f, k * self.n_f, "grad_f")
+        _check(_gradients(self._h, k, _vec_ptr(X, k * self.n[0], "X"), _vec_ptr(Lam, k * self.n[0], "Lam"),
+                          _vec_ptr(grad_theta, self.n_theta, "grad_theta"), pf))
 
     # -- lifetime
     def close(self):

@@ -88,6 +88,27 @@ __global__ __launch_bounds__(kBlock) void coarse_solve_t_kernel(int32_t n, int32
     x[i] = s;
 }
 
+// Products of the adjoint and state vectors on the nonzeros of K (eq. of the
+// adjoint gradient, dJ/dtheta = -sum_c lam_c^T (dK/dtheta) x_c):
+// w_e = sum_c Lam[c][i_e] X[c][j_e] for every nonzero e = (i_e, j_e), systems
+// stored one after another (length n each).  kPairLanes lanes per row.
+constexpr int kPairLanes = 8;
+__global__ __launch_bounds__(kBlock) void pair_products_kernel(int32_t n, const int32_t* __restrict__ rowptr,
+                                                               const int32_t* __restrict__ col, int nrhs,
+                                                               const double* __restrict__ X,
+                                                               const double* __restrict__ Lam,
+                                                               double* __restrict__ w) {
+    const int lane = threadIdx.x & (kPairLanes - 1);
+    const int64_t row = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / kPairLanes;
+    if (row >= n) return;
+    for (int k = rowptr[row] + lane; k < rowptr[row + 1]; k += kPairLanes) {
+        const int j = col[k];
+        double s = 0.0;
+        for (int c = 0; c < nrhs; ++c) s += Lam[(int64_t)c * n + row] * X[(int64_t)c * n + j];
+        w[k] = s;
+    }
+}
+
 template <typename T, typename Acc, int V, int U>
 void launch_t_shape(hipStream_t s, const Level& L, const int64_t* off, const double* r) {
     hipLaunchKernelGGL((patch_apply_t_kernel<T, Acc, V, U>), dim3(L.npatch), dim3(kBlock), sizeof(Acc) * L.max_m, s,
@@ -101,6 +122,13 @@ void launch_patch_apply_t(hipStream_t s, const Level& L, const double* r) {
     if (L.prec == PHMG_PREC_F32) launch_t_shape<float, float, 2, 4>(s, L, L.fofflp, r);
     else if (L.prec == PHMG_PREC_BF16) launch_t_shape<__hip_bfloat16, float, 4, 4>(s, L, L.fofflp, r);
     else launch_t_shape<double, double, 1, 4>(s, L, L.foff, r);
+}
+
+void launch_pair_products(hipStream_t s, const DevCsr& K, int nrhs, const double* X, const double* Lam,
+                          double* w) {
+    if (K.nrows <= 0) return;
+    hipLaunchKernelGGL(pair_products_kernel, dim3(grid_for((int64_t)K.nrows * kPairLanes, kBlock)), dim3(kBlock), 0,
+                       s, K.nrows, K.rowptr, K.col, nrhs, X, Lam, w);
 }
 
 void launch_coarse_solve_t(hipStream_t s, const Level& L, const double* b, double* x) {

@@ -948,6 +948,63 @@ phmg_status phmg_fgmres_solve_transposed(phmg_ctx ctx, const double* b, double* 
     });
 }
 
+phmg_status phmg_set_sensitivities(phmg_ctx ctx, const phmg_csr* S, const phmg_csr* G) {
+    return guarded([&]() -> phmg_status {
+        if (!ctx || !S || !G) fail(PHMG_EINVAL, "null argument");
+        const DevCsr& K0 = ctx->L[0].K;
+        check_csr(*S, "sensitivities: ");
+        check_csr(*G, "forcing map: ");
+        if (S->ncols != K0.nnz)
+            fail(PHMG_EINVAL, "sensitivities: ncols must equal nnz(K_0) = " + std::to_string(K0.nnz));
+        if (G->nrows != ctx->L[0].n) fail(PHMG_EINVAL, "forcing map: nrows must equal n_0");
+        if (ctx->have_sens) {
+            for (DevCsr* A : {&ctx->S, &ctx->G, &ctx->GT}) {
+                dfree(ctx, A->rowptr);
+                dfree(ctx, A->col);
+                dfree(ctx, A->val);
+            }
+            dfree(ctx, ctx->wpair);
+        }
+        ctx->S = upload_csr(ctx, *S);
+        ctx->G = upload_csr(ctx, *G);
+        ctx->GT = upload_transpose(ctx, *G);
+        ctx->wpair = dalloc<double>(ctx, K0.nnz);
+        ctx->have_sens = true;
+        return PHMG_OK;
+    });
+}
+
+phmg_status phmg_forcing_rhs(phmg_ctx ctx, int nrhs, const double* F, double* B) {
+    return guarded([&]() -> phmg_status {
+        if (!ctx || !F || !B) fail(PHMG_EINVAL, "null argument");
+        if (!ctx->have_sens) fail(PHMG_ESTATE, "phmg_set_sensitivities has not been called");
+        if (nrhs < 1) fail(PHMG_EINVAL, "nrhs must be >= 1");
+        const int64_t nf = ctx->G.ncols, n0 = ctx->L[0].n;
+        for (int c = 0; c < nrhs; ++c) launch_spmv(ctx->stream, ctx->G, F + c * nf, 1.0, nullptr, 0.0, B + c * n0);
+        hipcheck(hipGetLastError(), "kernel launch");
+        return PHMG_OK;
+    });
+}
+
+phmg_status phmg_gradients(phmg_ctx ctx, int nrhs, const double* X, const double* Lam, double* grad_theta,
+                           double* grad_f) {
+    return guarded([&]() -> phmg_status {
+        if (!ctx || !X || !Lam || !grad_theta) fail(PHMG_EINVAL, "null argument");
+        if (!ctx->have_sens) fail(PHMG_ESTATE, "phmg_set_sensitivities has not been called");
+        if (nrhs < 1) fail(PHMG_EINVAL, "nrhs must be >= 1");
+        hipStream_t s = ctx->stream;
+        launch_pair_products(s, ctx->L[0].K, nrhs, X, Lam, ctx->wpair);
+        launch_spmv(s, ctx->S, ctx->wpair, -1.0, nullptr, 0.0, grad_theta);
+        if (grad_f) {
+            const int64_t nf = ctx->G.ncols, n0 = ctx->L[0].n;
+            for (int c = 0; c < nrhs; ++c)
+                launch_spmv(s, ctx->GT, Lam + c * n0, 1.0, nullptr, 0.0, grad_f + c * nf);
+        }
+        hipcheck(hipGetLastError(), "kernel launch");
+        return PHMG_OK;
+    });
+}
+
 phmg_status phmg_residual(phmg_ctx ctx, int level, const double* b, const double* x, double* r) {
     return guarded([&]() -> phmg_status {
         if (!ctx || !b || !x || !r) fail(PHMG_EINVAL, "null argument");

@@ -127,6 +127,10 @@ struct phmg_ctx_s {
     hipGraphExec_t vexec[2] = {nullptr, nullptr};
     double* gin = nullptr;
     double* gout = nullptr;
+    // adjoint gradients: dK/dtheta over K_0's nonzeros, the forcing map G and G^T
+    bool have_sens = false;
+    phmg::DevCsr S, G, GT;
+    double* wpair = nullptr;         // nnz(K_0) products of the gradient contraction
     // block path: work vectors, FGMRES block basis and its captured V-cycle
     bool block_ready = false;
     int brestart_cap = 0;
@@ -174,6 +178,9 @@ void launch_dense_gj(hipStream_t s, double* A, int N, int* piv, int* status, dou
 void launch_transpose(hipStream_t s, int n, const double* src, double* dst);
 void launch_coarse_solve(hipStream_t s, const Level& L, const double* b, double* x);
 void launch_coarse_solve_t(hipStream_t s, const Level& L, const double* b, double* x);   // transposed
+// w_e = sum_c Lam_c[i_e] X_c[j_e] over the nonzeros of K (systems of length K.nrows one after another)
+void launch_pair_products(hipStream_t s, const DevCsr& K, int nrhs, const double* X, const double* Lam,
+                          double* w);
 // FGMRES helpers
 void launch_multidot(hipStream_t s, int64_t n, int ncol, const double* V, int64_t ldv, const double* w,
                      double* partial, double* out, bool accumulate);

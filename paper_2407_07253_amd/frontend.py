@@ -203,6 +203,9 @@ class LevelData:
     P: Optional[Csr] = None                    # prolongation from the next coarser level to this one
     b: Optional[np.ndarray] = None
     mesh: object = None
+    log_visc: Optional[np.ndarray] = None       # nodal log-viscosity at the mesh vertices (None: nu = 1)
+    visc_sens: Optional[Csr] = None             # (nv x nnz(K)): d K_e / d l_v, e over K's nonzeros
+    forcing_map: Optional[Csr] = None           # (n x 2 nV): free right-hand side of nodal forcing values
 
     @property
     def n(self) -> int:
@@ -224,16 +227,31 @@ def _geometry(mesh):
 
 
 def assemble_level(mesh, k: int, kind: str, forcings: Optional[List[Callable]] = None,
-                   dirichlet: Optional[Callable] = None, mesh_index: int = 0) -> LevelData:
+                   dirichlet: Optional[Callable] = None, mesh_index: int = 0,
+                   log_visc: Optional[np.ndarray] = None, sensitivities: bool = False) -> LevelData:
+    """log_visc: nodal log-viscosity l at the mesh vertices; the velocity block is then
+    int nu_h grad u : grad v with nu_h = sum_v exp(l_v) lambda_v (P1 interpolant of exp(l)),
+    integrated exactly (rule of degree 2k - 1).  sensitivities: also build dK/dl (as a
+    vertex x nonzero matrix) and the forcing map for the adjoint gradients."""
     V = build_space(mesh, k, True)
     Q = build_space(mesh, k - 1, kind == "TH")
     x0, J, adet, Jinv = _geometry(mesh)
-    pts, w = collapsed_rule(2 * k - 2 if k > 1 else 1)
+    if log_visc is None:
+        pts, w = collapsed_rule(2 * k - 2 if k > 1 else 1)
+    else:
+        pts, w = collapsed_rule(2 * k - 1)
     _, dphi = shape_functions(k, pts)                      # nq x nv x 2
     psi, _ = shape_functions(k - 1, pts)                   # nq x np
     g = np.einsum("qnj,cji->cqni", dphi, Jinv)             # physical gradients, nc x nq x nloc x 2
     wc = adet[:, None] * w[None, :]
-    Le = np.einsum("cq,cqai,cqbi->cab", wc, g, g)
+    Lt = None
+    if log_visc is None:
+        Le = np.einsum("cq,cqai,cqbi->cab", wc, g, g)
+    else:
+        # hat-weighted stiffness per cell vertex t: int lambda_t grad phi_a . grad phi_b
+        Lt = np.einsum("cq,qt,cqai,cqbi->ctab", wc, barycentric(pts), g, g)
+        ev = np.exp(np.asarray(log_visc, dtype=np.float64)[mesh.cells])      # nc x 3
+        Le = np.einsum("ct,ctab->cab", ev, Lt)
     Bxe = -np.einsum("cq,qi,cqa->cia", wc, psi, g[..., 0])
     Bye = -np.einsum("cq,qi,cqa->cia", wc, psi, g[..., 1])
     vd, qd = V.cell_dofs, Q.cell_dofs
@@ -250,7 +268,11 @@ def assemble_level(mesh, k: int, kind: str, forcings: Optional[List[Callable]] =
     Lff = L[free][:, free]
     Bxf, Byf = Bx[:, free], By[:, free]
     K = sp.bmat([[Lff, None, Bxf.T], [None, Lff, Byf.T], [Bxf, Byf, sp.csr_matrix((Q.ndofs, Q.ndofs))]], format="csr")
-    lev = LevelData(k, kind, V, Q, nfu, Q.ndofs, free, Csr.from_scipy(K), mesh_index, mesh=mesh)
+    lev = LevelData(k, kind, V, Q, nfu, Q.ndofs, free, Csr.from_scipy(K), mesh_index, mesh=mesh,
+                    log_visc=None if log_visc is None else np.asarray(log_visc, dtype=np.float64))
+    if sensitivities:
+        lev.visc_sens = _viscosity_sensitivity(lev, mesh, Lt)
+        lev.forcing_map = _forcing_map(lev, mesh, adet)
     if forcings is not None:
         # F(v) = int (I_h f).v: nodal interpolant of f times the exact element mass matrix
         mpts, mw = collapsed_rule(2 * k)
@@ -274,6 +296,61 @@ def assemble_level(mesh, k: int, kind: str, forcings: Optional[List[Callable]] =
             rhs.append(np.concatenate([Fx[free] - lift_x, Fy[free] - lift_y, -lift_p]))
         lev.b = np.stack(rhs, axis=0)
     return lev
+
+
+def _viscosity_sensitivity(lev: LevelData, mesh, Lt) -> Csr:
+    """S[v, e] = d K_e / d l_v over the nonzeros e of K (CSR order): exp(l_v) times the
+    hat-weighted stiffness of vertex v, in both velocity blocks."""
+    nv = mesh.verts.shape[0]
+    K = lev.K
+    n, nfu = K.nrows, lev.nfu
+    if Lt is None:
+        raise ValueError("the viscosity sensitivity needs a log-viscosity field")
+    keys = np.repeat(np.arange(n, dtype=np.int64), np.diff(K.rowptr)) * n + K.col
+    pos = -np.ones(lev.V.ndofs, dtype=np.int64)
+    pos[lev.free_u] = np.arange(nfu)
+    fi = pos[lev.V.cell_dofs]                                             # nc x nl (-1 fixed)
+    ev = np.exp(lev.log_visc[mesh.cells])                                 # nc x 3
+    nl = fi.shape[1]
+    rows, cols, vals = [], [], []
+    I = np.repeat(fi[:, :, None], nl, axis=2)
+    Jc = np.repeat(fi[:, None, :], nl, axis=1)
+    ok = (I >= 0) & (Jc >= 0)
+    for t in range(3):
+        val = (ev[:, t, None, None] * Lt[:, t])[ok]
+        vtx = np.broadcast_to(mesh.cells[:, t, None, None], I.shape)[ok]
+        for comp in range(2):
+            key = (I[ok] + comp * nfu) * n + (Jc[ok] + comp * nfu)
+            e = np.searchsorted(keys, key)
+            assert np.array_equal(keys[e], key)
+            rows.append(vtx)
+            cols.append(e)
+            vals.append(val)
+    S = sp.coo_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))),
+                      shape=(nv, K.nnz)).tocsr()
+    S.sum_duplicates()
+    S.sort_indices()
+    return Csr.from_scipy(S)
+
+
+def _forcing_map(lev: LevelData, mesh, adet) -> Csr:
+    """G (n x 2 nV): b = G f for nodal forcing values f = [f_x; f_y] at every velocity node
+    (F(v) = int (I_h f) . v with the exact mass matrix; homogeneous Dirichlet data)."""
+    k = lev.k
+    mpts, mw = collapsed_rule(2 * k)
+    mphi, _ = shape_functions(k, mpts)
+    Me = np.einsum("c,q,qa,qb->cab", adet, mw, mphi, mphi)
+    vd = lev.V.cell_dofs
+    nl = vd.shape[1]
+    nV = lev.V.ndofs
+    M = sp.coo_matrix((Me.ravel(), (np.repeat(vd, nl, axis=1).ravel(), np.tile(vd, (1, nl)).ravel())),
+                      shape=(nV, nV)).tocsr()
+    Mf = M[lev.free_u]
+    G = sp.bmat([[Mf, None], [None, Mf], [sp.csr_matrix((lev.nq, nV)), sp.csr_matrix((lev.nq, nV))]],
+                format="csr")
+    G.sum_duplicates()
+    G.sort_indices()
+    return Csr.from_scipy(G)
 
 
 # --------------------------------------------------------------------------
@@ -409,7 +486,11 @@ def workload_specs(name: str, k: Optional[int] = None):
 
 
 def build_hierarchy(name: str, k: Optional[int] = None, forcing: str = "mms", nrhs: int = 1,
-                    specs=None, opts=None) -> Hierarchy:
+                    specs=None, opts=None, log_visc: Optional[np.ndarray] = None,
+                    sensitivities: bool = False) -> Hierarchy:
+    """log_visc: nodal log-viscosity on the finest mesh's vertices, injected to the vertices
+    of every coarser (nested) mesh; sensitivities: level 0 also carries dK/dl and the
+    forcing map (adjoint gradients)."""
     meshes = synth.config_mesh_hierarchy(name)[::-1]       # finest first
     weights = True
     if specs is None:
@@ -427,8 +508,14 @@ def build_hierarchy(name: str, k: Optional[int] = None, forcing: str = "mms", nr
         fs, g = None, None
     levels: List[LevelData] = []
     for li, (mi, kk, kind) in enumerate(specs):
+        lv = None
+        if log_visc is not None:
+            nvl = meshes[mi].verts.shape[0]
+            assert np.array_equal(meshes[mi].verts, meshes[0].verts[:nvl])
+            lv = np.asarray(log_visc, dtype=np.float64)[:nvl]
         lev = assemble_level(meshes[mi], kk, kind, forcings=fs if li == 0 else None,
-                             dirichlet=g if li == 0 else None, mesh_index=mi)
+                             dirichlet=g if li == 0 else None, mesh_index=mi, log_visc=lv,
+                             sensitivities=sensitivities and li == 0)
         if li < len(specs) - 1:
             lev.patch_ptr, lev.patch_dofs, lev.patch_weight = vanka_patches(lev)
         if li > 0:

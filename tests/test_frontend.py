@@ -63,3 +63,33 @@ def test_shape_functions_nodal_and_quadrature_exact():
     for a in range(10):
         b = 9 - a
         assert abs(np.sum(w * pts[:, 0] ** a * pts[:, 1] ** b) - factorial(a) * factorial(b) / factorial(a + b + 2)) < 1e-15
+
+
+def test_viscosity_sensitivity_and_forcing_map_match_oracle_adjoint():
+    """The level-0 arrays the GPU contracts for the adjoint gradients (dK/dl over K's
+    nonzeros, the forcing map G) reproduce the oracle's element-by-element gradients."""
+    import synth
+    from oracle import adjoint as oadj
+    name = "cfg3_r1"
+    mesh0 = synth.config_mesh_hierarchy(name)[-1]
+    lv = synth.log_viscosity(mesh0.verts, seed=5)
+    fh = frontend.build_hierarchy(name, forcing=None, log_visc=lv, sensitivities=True)
+    _, od, _, _ = oproblems.build(name, with_rhs=False, log_visc=lv)
+    L0, d = fh.levels[0], od[0]
+    rng = np.random.default_rng(3)
+    X = rng.standard_normal((2, d.n))
+    Lam = rng.standard_normal((2, d.n))
+    K = L0.K.to_scipy().tocoo()
+    w = np.zeros(K.nnz)
+    for b in range(2):
+        w += Lam[b][K.row] * X[b][K.col]
+    got = -(L0.visc_sens.to_scipy() @ w)
+    ref = oadj.viscosity_gradient(d, X, Lam)
+    assert np.abs(got - ref).max() <= 1e-12 * np.abs(ref).max()
+    G = L0.forcing_map.to_scipy()
+    gf = np.stack([G.T @ Lam[b] for b in range(2)]).reshape(2, 2, -1)
+    ref_f = oadj.forcing_gradient(d, Lam)
+    assert np.abs(gf - ref_f).max() <= 1e-13 * np.abs(ref_f).max()
+    fn = rng.standard_normal((2, 2, d.V.ndofs))
+    bg = np.stack([G @ fn[b].ravel() for b in range(2)])
+    assert np.abs(bg - oadj.forcing_rhs(d, fn)).max() <= 1e-13 * np.abs(bg).max()

@@ -38,16 +38,22 @@ from .transfer import prolongation
 SEEDS = {"cfg1": 1, "cfg2": 2, "cfg3": 3, "cfg4": 4}
 
 
-def level_specs(name: str, k: int = None) -> Tuple[List[Tuple[int, int, str]], CycleOpts]:
-    """(mesh index from the finest, order, kind) per level, and cycle options."""
+def level_specs(name: str, k: int = None, schedule: str = "direct") -> Tuple[List[Tuple[int, int, str]], CycleOpts]:
+    """(mesh index from the finest, order, kind) per level, and cycle options.
+
+    schedule "direct": P_k straight to P_2 on the finest mesh ("phMG(direct)");
+    "gradual": the velocity orders of gradual_schedule(k) on the finest mesh,
+    every order above 2 a p-level ("phMG(gradual)", Section 4).
+    """
     cheb = dict(smoother="chebyshev", cheb_lo=0.1, cheb_hi=1.1, eig_iters=20)
     if name in ("cfg1", "tiny2", "tiny4"):
         return [(0, 2, "TH"), (1, 2, "TH")], CycleOpts(nu_p=2, nu_h=2, n_v=1, n_plevels=0, omega=0.5)
     if name.startswith("cfg2") or name.startswith("cfg3"):
-        nref = {"cfg2": 3, "cfg2_r2": 2, "cfg2_r1": 1, "cfg3": 4, "cfg3_r2": 2, "cfg3_r1": 1}[name]
+        nref = {"cfg2": 3, "cfg2_r2": 2, "cfg2_r1": 1, "cfg3": 4, "cfg3_r2": 2, "cfg3_r1": 1, "cfg3_r0": 0}[name]
         kk = 4 if k is None else k
-        specs = [(0, kk, "TH")] + [(i, 2, "TH") for i in range(nref + 1)]
-        return specs, CycleOpts(nu_p=2, nu_h=2, n_v=1, n_plevels=1, omega=0.5, **cheb)
+        orders = gradual_schedule(kk) if schedule == "gradual" else ([kk, 2] if kk != 2 else [2])
+        specs = [(0, o, "TH") for o in orders[:-1]] + [(i, 2, "TH") for i in range(nref + 1)]
+        return specs, CycleOpts(nu_p=2, nu_h=2, n_v=1, n_plevels=len(orders) - 1, omega=0.5, **cheb)
     if name in ("cfg4", "cfg4_r0", "sv_small"):
         nmac = {"cfg4": 3, "cfg4_r0": 1, "sv_small": 2}[name]
         kk = 4 if k is None else k
@@ -71,7 +77,7 @@ def gradual_schedule(k: int) -> List[int]:
 
 
 def build(name: str, k: int = None, weights: str = None, with_rhs: bool = True,
-          specs=None, opts=None, forcing: str = "mms", nrhs: int = 1, log_visc=None):
+          specs=None, opts=None, forcing: str = "mms", nrhs: int = 1, log_visc=None, schedule: str = "direct"):
     """Assemble every level, its patches and the transfers.  Returns (levels, discs, opts, b).
 
     forcing "mms": b is the manufactured-solution right-hand side (n,).
@@ -83,7 +89,7 @@ def build(name: str, k: int = None, weights: str = None, with_rhs: bool = True,
     """
     meshes = synth.config_mesh_hierarchy(name)[::-1]          # finest first
     if specs is None:
-        specs, opts = level_specs(name, k)
+        specs, opts = level_specs(name, k, schedule)
     if weights is None:
         weights = "none" if opts.smoother == "chebyshev" else "pou"
     seed = SEEDS.get(name.split("_")[0], 1)

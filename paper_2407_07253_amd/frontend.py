@@ -461,7 +461,21 @@ class Hierarchy:
 SEEDS = {"cfg1": 1, "cfg2": 2, "cfg3": 3, "cfg4": 4}
 
 
-def workload_specs(name: str, k: Optional[int] = None):
+def p_schedule(k: int) -> List[int]:
+    """Velocity orders of gradual p-coarsening (Section 4, figure "fig:pmg_schedule"):
+    k <= 5 goes to P2 in one step, k = 6, 7 through P4, k = 8..10 through P5."""
+    if k <= 2:
+        return [2]
+    if k <= 5:
+        return [k, 2]
+    if k <= 7:
+        return [k, 4, 2]
+    if k <= 10:
+        return [k, 5, 2]
+    raise ValueError(f"no schedule for order {k}")
+
+
+def workload_specs(name: str, k: Optional[int] = None, schedule: str = "direct"):
     """Levels as (mesh index from the finest, order, kind), the cycle options and the weight choice.
 
     cfg1 names its smoother (nu = 2 damped sweeps, omega = 0.5): Richardson
@@ -473,10 +487,11 @@ def workload_specs(name: str, k: Optional[int] = None):
     if name in ("cfg1", "tiny2", "tiny4"):
         return [(0, 2, "TH"), (1, 2, "TH")], dict(nu_p=2, nu_h=2, n_v=1, n_plevels=0, omega=0.5), True
     if name.startswith("cfg2") or name.startswith("cfg3"):
-        nref = {"cfg2": 3, "cfg2_r2": 2, "cfg2_r1": 1, "cfg3": 4, "cfg3_r2": 2, "cfg3_r1": 1}[name]
+        nref = {"cfg2": 3, "cfg2_r2": 2, "cfg2_r1": 1, "cfg3": 4, "cfg3_r2": 2, "cfg3_r1": 1, "cfg3_r0": 0}[name]
         kk = 4 if k is None else k
-        specs = [(0, kk, "TH")] + [(i, 2, "TH") for i in range(nref + 1)]
-        return specs, dict(nu_p=2, nu_h=2, n_v=1, n_plevels=1, omega=0.5, **cheb), False
+        orders = p_schedule(kk) if schedule == "gradual" else ([kk, 2] if kk != 2 else [2])
+        specs = [(0, o, "TH") for o in orders[:-1]] + [(i, 2, "TH") for i in range(nref + 1)]
+        return specs, dict(nu_p=2, nu_h=2, n_v=1, n_plevels=len(orders) - 1, omega=0.5, **cheb), False
     if name in ("cfg4", "cfg4_r0", "sv_small"):
         nmac = {"cfg4": 3, "cfg4_r0": 1, "sv_small": 2}[name]
         kk = 4 if k is None else k
@@ -487,14 +502,14 @@ def workload_specs(name: str, k: Optional[int] = None):
 
 def build_hierarchy(name: str, k: Optional[int] = None, forcing: str = "mms", nrhs: int = 1,
                     specs=None, opts=None, log_visc: Optional[np.ndarray] = None,
-                    sensitivities: bool = False) -> Hierarchy:
+                    sensitivities: bool = False, schedule: str = "direct") -> Hierarchy:
     """log_visc: nodal log-viscosity on the finest mesh's vertices, injected to the vertices
     of every coarser (nested) mesh; sensitivities: level 0 also carries dK/dl and the
     forcing map (adjoint gradients)."""
     meshes = synth.config_mesh_hierarchy(name)[::-1]       # finest first
     weights = True
     if specs is None:
-        specs, opts, weights = workload_specs(name, k)
+        specs, opts, weights = workload_specs(name, k, schedule)
     seed = SEEDS.get(name.split("_")[0], 1)
     if forcing == "mms":
         A = synth.mms_amplitude(seed)

@@ -179,6 +179,8 @@ def config_mesh_hierarchy(name: str) -> List[Mesh]:
         return hierarchy(delaunay_square(64, seed=2), 1)
     if name == "cfg3":
         return hierarchy(structured_square(8), 4)
+    if name == "cfg3_r0":
+        return hierarchy(structured_square(8), 0)
     if name == "cfg3_r2":
         return hierarchy(structured_square(8), 2)
     if name == "cfg3_r1":

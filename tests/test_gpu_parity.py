@@ -245,3 +245,33 @@ def test_graph_replays_equal_eager_launches(name):
         outs.append((it, _host(x)))
     assert outs[0][0] == outs[1][0] and np.array_equal(outs[0][1], outs[1][1])
     H.close()
+
+
+@pytest.mark.parametrize("schedule", ["direct", "gradual"])
+def test_p_coarsening_schedules_match_oracle(schedule):
+    """TH P6/P5 on the structured 8x8 mesh: phMG(direct) P6 -> P2 and phMG(gradual)
+    P6 -> P4 -> P2 (Section 4's schedule), P2/P1 direct solve at the bottom."""
+    from paper_2407_07253_amd._lib import Hierarchy
+    fh = frontend.build_hierarchy("cfg3_r0", k=6, schedule=schedule)
+    H = Hierarchy.from_frontend(fh)
+    H.setup()
+    ol, od, oopts, ob = oproblems.build("cfg3_r0", k=6, schedule=schedule)
+    omg.setup(ol, oopts)
+    assert [lv.k for lv in fh.levels] == [d.k for d in od]
+    rng = np.random.default_rng(17)
+    b = rng.standard_normal(ol[0].n)
+    z = _dev(np.zeros(ol[0].n))
+    H.vcycle(_dev(b), z)
+    err_v = _rel(_host(z), omg.vcycle(ol, oopts, b))
+    x = _dev(np.zeros(ol[0].n))
+    iters, relres, conv = H.fgmres(_dev(ob), x, rtol=1e-8)
+    K = ol[0].K
+    res = ofgmres.fgmres(lambda v: K @ v, lambda v: omg.vcycle(ol, oopts, v), ob, rtol=1e-8)
+    nfu = od[0].nfu
+    err = np.linalg.norm(_normalise(_host(x), nfu) - _normalise(res.x, nfu)) / np.linalg.norm(_normalise(res.x, nfu))
+    print(f"{schedule}: orders {[d.k for d in od]}, vcycle rel err {err_v:.2e}; GPU iters {iters}, "
+          f"oracle iters {res.iters}; solution rel err {err:.2e}")
+    assert err_v <= 1e-11
+    assert conv and res.converged and iters == res.iters
+    assert err <= 1e-10
+    H.close()

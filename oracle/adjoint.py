@@ -37,14 +37,14 @@ from .fgmres import fgmres
 from .multigrid import vcycle
 
 
-def objective(X: np.ndarray, T: np.ndarray, nfu: int) -> float:
-    d = X[:, : 2 * nfu] - T[:, : 2 * nfu]
+def objective(X: np.ndarray, T: np.ndarray, nfu: int, dim: int = 2) -> float:
+    d = X[:, : dim * nfu] - T[:, : dim * nfu]
     return 0.5 * float(np.sum(d * d))
 
 
-def objective_gradient(X: np.ndarray, T: np.ndarray, nfu: int) -> np.ndarray:
+def objective_gradient(X: np.ndarray, T: np.ndarray, nfu: int, dim: int = 2) -> np.ndarray:
     G = np.zeros_like(X)
-    G[:, : 2 * nfu] = X[:, : 2 * nfu] - T[:, : 2 * nfu]
+    G[:, : dim * nfu] = X[:, : dim * nfu] - T[:, : dim * nfu]
     return G
 
 
@@ -70,6 +70,9 @@ def _free_local(disc: Stokes, vd: np.ndarray, comp: int, vec: np.ndarray) -> np.
 
 def viscosity_gradient(disc: Stokes, X: np.ndarray, Lam: np.ndarray) -> np.ndarray:
     """- sum_b lam_b^T (dK/dl_v) x_b for every vertex v (the partial derivative in the adjoint formula)."""
+    if getattr(disc, "dim", 2) == 3:
+        from . import stokes3d
+        return stokes3d.viscosity_gradient(disc, X, Lam)
     verts, cells = disc.mesh.verts, disc.mesh.cells
     lv = disc.log_visc if disc.log_visc is not None else np.zeros(verts.shape[0])
     k = disc.k
@@ -94,7 +97,10 @@ def viscosity_gradient(disc: Stokes, X: np.ndarray, Lam: np.ndarray) -> np.ndarr
 
 
 def forcing_gradient(disc: Stokes, Lam: np.ndarray) -> np.ndarray:
-    """F^T lam_b: (B, 2, nV), the gradient with respect to the nodal forcing values."""
+    """F^T lam_b: (B, d, nV), the gradient with respect to the nodal forcing values."""
+    if getattr(disc, "dim", 2) == 3:
+        from . import stokes3d
+        return stokes3d.forcing_gradient(disc, Lam)
     verts, cells = disc.mesh.verts, disc.mesh.cells
     k = disc.k
     qpts, qw = element.quadrature(2 * k)
@@ -111,7 +117,10 @@ def forcing_gradient(disc: Stokes, Lam: np.ndarray) -> np.ndarray:
 
 
 def forcing_rhs(disc: Stokes, f_nodal: np.ndarray) -> np.ndarray:
-    """Free right-hand sides of nodal forcings f_nodal (B, 2, nV): F f_b (homogeneous Dirichlet data)."""
+    """Free right-hand sides of nodal forcings f_nodal (B, d, nV): F f_b (homogeneous Dirichlet data)."""
+    if getattr(disc, "dim", 2) == 3:
+        from . import stokes3d
+        return stokes3d.forcing_rhs(disc, f_nodal)
     verts, cells = disc.mesh.verts, disc.mesh.cells
     k = disc.k
     qpts, qw = element.quadrature(2 * k)
@@ -132,6 +141,7 @@ def forcing_rhs(disc: Stokes, f_nodal: np.ndarray) -> np.ndarray:
 
 def gradients(levels: List, opts, disc: Stokes, X: np.ndarray, T: np.ndarray, rtol: float = 1e-12):
     """(J, dJ/dl (nvert,), dJ/df (B, 2, nV), lam) at the solutions X of the batch."""
-    G = objective_gradient(X, T, disc.nfu)
+    dim = getattr(disc, "dim", 2)
+    G = objective_gradient(X, T, disc.nfu, dim)
     Lam = adjoint_solve(levels, opts, G, rtol=rtol)
-    return objective(X, T, disc.nfu), viscosity_gradient(disc, X, Lam), forcing_gradient(disc, Lam), Lam
+    return objective(X, T, disc.nfu, dim), viscosity_gradient(disc, X, Lam), forcing_gradient(disc, Lam), Lam

@@ -35,7 +35,7 @@ from .multigrid import CycleOpts, Level
 from .patches import multiplicity_weights, vanka_star_patches
 from .transfer import prolongation
 
-SEEDS = {"cfg1": 1, "cfg2": 2, "cfg3": 3, "cfg4": 4}
+SEEDS = {"cfg1": 1, "cfg2": 2, "cfg3": 3, "cfg4": 4, "cfg5": 5, "cube": 5}
 
 
 def level_specs(name: str, k: int = None, schedule: str = "direct") -> Tuple[List[Tuple[int, int, str]], CycleOpts]:
@@ -54,6 +54,9 @@ def level_specs(name: str, k: int = None, schedule: str = "direct") -> Tuple[Lis
         orders = gradual_schedule(kk) if schedule == "gradual" else ([kk, 2] if kk != 2 else [2])
         specs = [(0, o, "TH") for o in orders[:-1]] + [(i, 2, "TH") for i in range(nref + 1)]
         return specs, CycleOpts(nu_p=2, nu_h=2, n_v=1, n_plevels=len(orders) - 1, omega=0.5, **cheb)
+    if name in ("cfg5", "cfg5_r1", "cube_tiny"):
+        nlev = {"cfg5": 3, "cfg5_r1": 2, "cube_tiny": 2}[name]
+        return [(i, 2, "TH") for i in range(nlev)], CycleOpts(nu_p=2, nu_h=2, n_v=1, n_plevels=0, omega=0.5, **cheb)
     if name in ("cfg4", "cfg4_r0", "sv_small"):
         nmac = {"cfg4": 3, "cfg4_r0": 1, "sv_small": 2}[name]
         kk = 4 if k is None else k
@@ -88,6 +91,8 @@ def build(name: str, k: int = None, weights: str = None, with_rhs: bool = True,
     with l injected to its own vertices (nested meshes keep vertex ids).
     """
     meshes = synth.config_mesh_hierarchy(name)[::-1]          # finest first
+    if meshes[0].meta.get("dim") == 3:
+        return _build3d(name, meshes, weights, with_rhs, specs, opts, forcing, nrhs, log_visc)
     if specs is None:
         specs, opts = level_specs(name, k, schedule)
     if weights is None:
@@ -130,6 +135,45 @@ def build(name: str, k: int = None, weights: str = None, with_rhs: bool = True,
                       for i in range(nrhs)])
     elif with_rhs:
         raise KeyError(forcing)
+    return levels, discs, opts, b
+
+
+def _build3d(name, meshes, weights, with_rhs, specs, opts, forcing, nrhs, log_visc):
+    """3D Taylor-Hood P2/P1 hierarchy on nested Kuhn cube meshes (hMG, h-levels only)."""
+    from . import stokes3d
+    if specs is None:
+        specs, opts = level_specs(name)
+    if weights is None:
+        weights = "none" if opts.smoother == "chebyshev" else "pou"
+    discs = []
+    for mi, kk, kind in specs:
+        lv = None
+        if log_visc is not None:
+            nv = meshes[mi].verts.shape[0]
+            assert np.array_equal(meshes[mi].verts, meshes[0].verts[:nv])
+            lv = np.asarray(log_visc, dtype=np.float64)[:nv]
+        discs.append(stokes3d.assemble(meshes[mi], kk, log_visc=lv))
+    levels = []
+    for li, d in enumerate(discs):
+        L = Level(K=d.K)
+        if li < len(discs) - 1:
+            L.patches = stokes3d.vanka_star_patches(d)
+            L.weights = multiplicity_weights(L.patches, d.n) if weights == "pou" else None
+        if li > 0:
+            L.P = stokes3d.prolongation(discs[li - 1], d, meshes[specs[li - 1][0]].parent)
+        levels.append(L)
+    levels[-1].null = discs[-1].null_vector()
+    b = None
+    if with_rhs and forcing == "bumps":
+        seed = SEEDS.get(name.split("_")[0], 5)
+        C, W, D = synth.gaussian_bump_params3d(nrhs, seed)
+        X = discs[0].V.coords
+        fn = np.zeros((nrhs, 3, X.shape[0]))
+        for i in range(nrhs):
+            fn[i] = synth.gaussian_bump_forcing3d(X[:, 0], X[:, 1], X[:, 2], C[i], W[i], D[i])
+        b = stokes3d.forcing_rhs(discs[0], fn)
+    elif with_rhs:
+        raise KeyError(f"3D workloads take forcing='bumps' (got {forcing!r})")
     return levels, discs, opts, b
 
 

@@ -17,6 +17,8 @@ from .meshes import (  # noqa: F401
     alfeld_split,
     hierarchy,
     config_mesh_hierarchy,
+    structured_cube,
+    cube_hierarchy,
 )
 from .problem_data import (  # noqa: F401
     mms_amplitude,
@@ -28,4 +30,6 @@ from .problem_data import (  # noqa: F401
     fourier_field_params,
     fourier_field,
     log_viscosity,
+    gaussian_bump_params3d,
+    gaussian_bump_forcing3d,
 )

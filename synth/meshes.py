@@ -159,6 +159,80 @@ def hierarchy(base: Mesh, nref: int, alfeld: bool = False) -> List[Mesh]:
     return meshes
 
 
+# ---------------------------------------------------------------------------
+# 3D: unit cube, n^3 cubes each split into 6 Kuhn tetrahedra
+# ---------------------------------------------------------------------------
+
+_KUHN = [(0, 1, 2), (0, 2, 1), (1, 0, 2), (1, 2, 0), (2, 0, 1), (2, 1, 0)]
+
+
+def _kuhn_cells(n: int, vid: np.ndarray) -> np.ndarray:
+    """Cells of the Kuhn split: cube (i,j,k) -> 6 tets c, c+e_s0, c+e_s0+e_s1, c+(1,1,1)
+    for the permutations s in _KUHN order; vid maps lattice (i,j,k) to a vertex id."""
+    cells = []
+    idx = np.stack(np.meshgrid(np.arange(n), np.arange(n), np.arange(n), indexing="ij"), axis=-1).reshape(-1, 3)
+    # cube order: i fastest, then j, then k
+    idx = idx[np.lexsort((idx[:, 0], idx[:, 1], idx[:, 2]))]
+    eye = np.eye(3, dtype=np.int64)
+    for c in idx:
+        for s in _KUHN:
+            p0 = c
+            p1 = p0 + eye[s[0]]
+            p2 = p1 + eye[s[1]]
+            p3 = p2 + eye[s[2]]
+            cells.append([vid[tuple(p)] for p in (p0, p1, p2, p3)])
+    return np.array(cells, dtype=np.int64)
+
+
+def structured_cube(n: int, coarse: Optional[Mesh] = None) -> Mesh:
+    """The unit cube with n^3 cubes, 6 Kuhn tetrahedra each (6 n^3 cells).
+
+    Without ``coarse`` the vertex ids are lexicographic (i fastest).  With the
+    mesh of n/2 cubes as ``coarse``, the vertices it shares keep their ids and
+    come first (the remaining lattice points follow lexicographically), and
+    ``parent`` maps every cell to the coarse tetrahedron that contains it: the
+    Kuhn split of the halved lattice refines the coarse one (both are the
+    cells of the hyperplanes x_i = const and x_i - x_j = const).
+    """
+    m = n + 1
+    lat = np.stack(np.meshgrid(np.arange(m), np.arange(m), np.arange(m), indexing="ij"), axis=-1).reshape(-1, 3)
+    lat = lat[np.lexsort((lat[:, 0], lat[:, 1], lat[:, 2]))]          # i fastest
+    vid = np.zeros((m, m, m), dtype=np.int64)
+    if coarse is None:
+        vid[lat[:, 0], lat[:, 1], lat[:, 2]] = np.arange(lat.shape[0])
+    else:
+        nc_ = coarse.meta["n"]
+        assert 2 * nc_ == n
+        cpts = np.rint(coarse.verts * nc_).astype(np.int64) * 2     # coarse ids in fine lattice units
+        taken = np.zeros((m, m, m), dtype=bool)
+        vid[cpts[:, 0], cpts[:, 1], cpts[:, 2]] = np.arange(cpts.shape[0])
+        taken[cpts[:, 0], cpts[:, 1], cpts[:, 2]] = True
+        rest = lat[~taken[lat[:, 0], lat[:, 1], lat[:, 2]]]
+        vid[rest[:, 0], rest[:, 1], rest[:, 2]] = cpts.shape[0] + np.arange(rest.shape[0])
+    verts = np.zeros((m ** 3, 3))
+    verts[vid[lat[:, 0], lat[:, 1], lat[:, 2]]] = lat / n
+    cells = _kuhn_cells(n, vid)
+    parent = None
+    if coarse is not None:
+        cen = verts[cells].mean(axis=1) * (n // 2)
+        cube = np.minimum(np.floor(cen).astype(np.int64), n // 2 - 1)
+        t = cen - cube
+        order = np.argsort(-t, axis=1)
+        perm = {s: q for q, s in enumerate(_KUHN)}
+        pidx = np.array([perm[tuple(o)] for o in order], dtype=np.int64)
+        cube_id = cube[:, 0] + (n // 2) * cube[:, 1] + (n // 2) ** 2 * cube[:, 2]
+        parent = cube_id * 6 + pidx
+    return Mesh(verts, cells, parent, "base" if coarse is None else "uniform", {"n": n, "dim": 3})
+
+
+def cube_hierarchy(n0: int, nref: int) -> List[Mesh]:
+    """Nested Kuhn cube meshes n0^3, (2 n0)^3, ..., coarsest first."""
+    meshes = [structured_cube(n0)]
+    for _ in range(nref):
+        meshes.append(structured_cube(2 * meshes[-1].meta["n"], coarse=meshes[-1]))
+    return meshes
+
+
 def config_mesh_hierarchy(name: str) -> List[Mesh]:
     """Mesh hierarchies of the benchmark workloads (coarsest first).
 
@@ -167,6 +241,8 @@ def config_mesh_hierarchy(name: str) -> List[Mesh]:
     * ``cfg3``: structured 8x8, 4 quadrisections -> 128x128 (``cfg3_r1``,
       ``cfg3_r2``: 1 and 2 quadrisections, the same recipe at 16x16 and 32x32).
     * ``cfg4``: 16x16 structured with interior jitter 0.2h, 2 quadrisections, Alfeld split.
+    * ``cfg5``: unit cube 4^3 -> 8^3 -> 16^3, 6 Kuhn tetrahedra per cube (``cfg5_r1``:
+      4^3 -> 8^3; ``cube_tiny``: 1^3 -> 2^3).
     * ``tiny2``/``tiny4``: 1x1 -> 2x2 and 2x2 -> 4x4 structured (dense-operator pins).
     """
     if name == "cfg1":
@@ -194,6 +270,12 @@ def config_mesh_hierarchy(name: str) -> List[Mesh]:
     if name == "sv_small":
         base = jitter_interior(structured_square(4), 0.2 / 4, seed=4)
         return hierarchy(base, 1, alfeld=True)
+    if name == "cfg5":
+        return cube_hierarchy(4, 2)
+    if name == "cfg5_r1":
+        return cube_hierarchy(4, 1)
+    if name == "cube_tiny":
+        return cube_hierarchy(1, 1)
     if name == "tiny2":
         return hierarchy(structured_square(1), 1)
     if name == "tiny4":

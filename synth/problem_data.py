@@ -77,3 +77,18 @@ def fourier_field(pts: np.ndarray, params) -> np.ndarray:
 def log_viscosity(verts: np.ndarray, seed: int, scale: float = 0.5) -> np.ndarray:
     """Nodal log-viscosity of the gradient workload: l = scale * g at the mesh vertices."""
     return scale * fourier_field(verts, fourier_field_params(seed, dim=verts.shape[1]))
+
+
+def gaussian_bump_params3d(nrhs: int, seed: int):
+    """3D bumps: centres U[0.15,0.85]^3, widths U[0.05,0.2], random unit directions."""
+    rng = np.random.default_rng(seed)
+    centres = rng.uniform(0.15, 0.85, size=(nrhs, 3))
+    widths = rng.uniform(0.05, 0.2, size=nrhs)
+    d = rng.standard_normal((nrhs, 3))
+    dirs = d / np.linalg.norm(d, axis=1, keepdims=True)
+    return centres, widths, dirs
+
+
+def gaussian_bump_forcing3d(x: np.ndarray, y: np.ndarray, z: np.ndarray, centre, width, direction):
+    g = np.exp(-((x - centre[0]) ** 2 + (y - centre[1]) ** 2 + (z - centre[2]) ** 2) / (2.0 * width ** 2))
+    return direction[0] * g, direction[1] * g, direction[2] * g

@@ -62,19 +62,21 @@ class StokesProblem:
 
     @property
     def sizes(self):
+        """(n_0, first pressure index, number of forcing parameters)."""
         fh, _ = self._fh, self._H
         if fh is None:
             raise RuntimeError("no hierarchy built yet")
         L0 = fh.levels[0]
-        return L0.n, L0.nfu, L0.forcing_map.ncols
+        return L0.n, L0.dim * L0.nfu, L0.forcing_map.ncols
 
     def solve(self, f, log_visc):
         """x (nrhs, n_0) for nodal forcings f (nrhs, 2 nV) and log-viscosity (nv,), differentiable in both."""
         return _StokesSolve.apply(f, log_visc, self)
 
 
-def _project_pressure(X, nfu: int):
-    X[:, 2 * nfu:] -= X[:, 2 * nfu:].mean(dim=1, keepdim=True)
+def _project_pressure(X, p0: int):
+    """Remove the mean of the pressure block (entries p0 ...) of every row."""
+    X[:, p0:] -= X[:, p0:].mean(dim=1, keepdim=True)
 
 
 def _autograd():
@@ -84,7 +86,7 @@ def _autograd():
         @staticmethod
         def forward(ctx, f, log_visc, problem):
             fh, H = problem.hierarchy(log_visc.detach().cpu().numpy())
-            n0, nfu, nf = problem.sizes
+            n0, p0, nf = problem.sizes
             F = f.detach().to(device="cuda", dtype=torch.float64).contiguous()
             if F.dim() != 2 or F.shape[1] != nf:
                 raise ValueError(f"f must have shape (nrhs, {nf})")
@@ -103,18 +105,18 @@ def _autograd():
                 X[c0:c1] = Xc
                 iters += its
             problem.last_iters = iters
-            ctx.problem, ctx.H, ctx.nfu = problem, H, nfu
+            ctx.problem, ctx.H, ctx.p0 = problem, H, p0
             ctx.devices = (f.device, log_visc.device)
             ctx.save_for_backward(X.clone())
-            _project_pressure(X, nfu)
+            _project_pressure(X, p0)
             return X
 
         @staticmethod
         def backward(ctx, gX):
             (X,) = ctx.saved_tensors
-            problem, H, nfu = ctx.problem, ctx.H, ctx.nfu
+            problem, H, p0 = ctx.problem, ctx.H, ctx.p0
             G = gX.detach().to(torch.float64).contiguous().clone()
-            _project_pressure(G, nfu)
+            _project_pressure(G, p0)
             Lam = torch.zeros_like(G)
             adj_iters = []
             for c in range(G.shape[0]):

@@ -205,15 +205,16 @@ class LevelData:
     mesh: object = None
     log_visc: Optional[np.ndarray] = None       # nodal log-viscosity at the mesh vertices (None: nu = 1)
     visc_sens: Optional[Csr] = None             # (nv x nnz(K)): d K_e / d l_v, e over K's nonzeros
-    forcing_map: Optional[Csr] = None           # (n x 2 nV): free right-hand side of nodal forcing values
+    forcing_map: Optional[Csr] = None           # (n x d nV): free right-hand side of nodal forcing values
+    dim: int = 2
 
     @property
     def n(self) -> int:
-        return 2 * self.nfu + self.nq
+        return self.dim * self.nfu + self.nq
 
     def null_vector(self) -> np.ndarray:
         z = np.zeros(self.n)
-        z[2 * self.nfu:] = 1.0
+        z[self.dim * self.nfu:] = 1.0
         return z
 
 
@@ -458,7 +459,7 @@ class Hierarchy:
         return self.levels[0].b
 
 
-SEEDS = {"cfg1": 1, "cfg2": 2, "cfg3": 3, "cfg4": 4}
+SEEDS = {"cfg1": 1, "cfg2": 2, "cfg3": 3, "cfg4": 4, "cfg5": 5, "cube": 5}
 
 
 def p_schedule(k: int) -> List[int]:
@@ -507,6 +508,9 @@ def build_hierarchy(name: str, k: Optional[int] = None, forcing: str = "mms", nr
     of every coarser (nested) mesh; sensitivities: level 0 also carries dK/dl and the
     forcing map (adjoint gradients)."""
     meshes = synth.config_mesh_hierarchy(name)[::-1]       # finest first
+    if meshes[0].meta.get("dim") == 3:
+        from . import frontend3d
+        return frontend3d.build_hierarchy(name, meshes, forcing, nrhs, log_visc, sensitivities)
     weights = True
     if specs is None:
         specs, opts, weights = workload_specs(name, k, schedule)

@@ -20,10 +20,11 @@ def _same_csr(a, b_scipy, rtol):
     assert np.abs(a.val - b.data).max() <= rtol * scale
 
 
-@pytest.mark.parametrize("name", ["tiny4", "cfg1", "sv_small", "cfg2_r1", "cfg3_r1"])
+@pytest.mark.parametrize("name", ["tiny4", "cfg1", "sv_small", "cfg2_r1", "cfg3_r1", "cube_tiny", "cfg5_r1"])
 def test_hierarchy_matches_oracle(name):
-    fh = frontend.build_hierarchy(name)
-    olevels, odiscs, oopts, ob = oproblems.build(name)
+    forcing = "bumps" if name.startswith(("cube", "cfg5")) else "mms"
+    fh = frontend.build_hierarchy(name, forcing=forcing, nrhs=2)
+    olevels, odiscs, oopts, ob = oproblems.build(name, forcing=forcing, nrhs=2)
     assert len(fh.levels) == len(olevels)
     for fl, ol, od in zip(fh.levels, olevels, odiscs):
         assert fl.n == od.n and fl.nfu == od.nfu
@@ -37,7 +38,8 @@ def test_hierarchy_matches_oracle(name):
                 assert np.allclose(fl.patch_weight, np.concatenate(ol.weights), rtol=0, atol=1e-15)
         if ol.P is not None:
             _same_csr(fl.P, ol.P, 1e-13)
-    assert np.abs(fh.b[0] - ob).max() <= 1e-12 * np.abs(ob).max()
+    ob = np.atleast_2d(ob)
+    assert np.abs(fh.b[: ob.shape[0]] - ob).max() <= 1e-12 * np.abs(ob).max()
     for key, val in fh.opts.items():
         assert getattr(oopts, key) == val, key
     if oopts.smoother == "chebyshev":
@@ -93,3 +95,27 @@ def test_viscosity_sensitivity_and_forcing_map_match_oracle_adjoint():
     fn = rng.standard_normal((2, 2, d.V.ndofs))
     bg = np.stack([G @ fn[b].ravel() for b in range(2)])
     assert np.abs(bg - oadj.forcing_rhs(d, fn)).max() <= 1e-13 * np.abs(bg).max()
+
+
+def test_3d_sensitivities_match_oracle_adjoint():
+    """3D (cube, P2/P1): dK/dl over K's nonzeros and the forcing map reproduce the oracle's
+    element-by-element gradient contractions."""
+    import synth
+    from oracle import adjoint as oadj
+    name = "cfg5_r1"
+    mesh0 = synth.config_mesh_hierarchy(name)[-1]
+    lv = synth.log_viscosity(mesh0.verts, seed=5)
+    fh = frontend.build_hierarchy(name, forcing=None, log_visc=lv, sensitivities=True)
+    _, od, _, _ = oproblems.build(name, with_rhs=False, log_visc=lv)
+    L0, d = fh.levels[0], od[0]
+    rng = np.random.default_rng(3)
+    X = rng.standard_normal((2, d.n))
+    Lam = rng.standard_normal((2, d.n))
+    K = L0.K.to_scipy().tocoo()
+    w = Lam[0][K.row] * X[0][K.col] + Lam[1][K.row] * X[1][K.col]
+    got = -(L0.visc_sens.to_scipy() @ w)
+    ref = oadj.viscosity_gradient(d, X, Lam)
+    assert np.abs(got - ref).max() <= 1e-12 * np.abs(ref).max()
+    G = L0.forcing_map.to_scipy()
+    gf = np.stack([G.T @ Lam[b] for b in range(2)]).reshape(2, 3, -1)
+    assert np.abs(gf - oadj.forcing_gradient(d, Lam)).max() <= 1e-13 * np.abs(gf).max()

@@ -1,0 +1,167 @@
+"""3D Taylor-Hood P2/P1 on Kuhn cube meshes: the GPU path against the oracle, and the
+differentiable solve at the full workload size (16^3 cubes, 94 286 DoFs, 8 forcings).
+
+The library is dimension-agnostic (CSR operators, patch lists, transfers); the 3D
+front-end (paper_2407_07253_amd/frontend3d.py) and the oracle's 3D module
+(oracle/stokes3d.py) build their inputs independently.  Tolerances as in 2D.
+"""
+import time
+
+import numpy as np
+import pytest
+import scipy.sparse as sp
+import scipy.sparse.linalg as spla
+
+torch = pytest.importorskip("torch")
+
+pytestmark = pytest.mark.gpu
+
+import synth  # noqa: E402
+from oracle import adjoint as oadj  # noqa: E402
+from oracle import fgmres as ofgmres  # noqa: E402
+from oracle import multigrid as omg  # noqa: E402
+from oracle import problems as oproblems  # noqa: E402
+from paper_2407_07253_amd import frontend  # noqa: E402
+
+
+def _dev(a):
+    return torch.tensor(np.ascontiguousarray(a, dtype=np.float64), device="cuda")
+
+
+def _host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+def _rel(a, b):
+    return float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-300))
+
+
+def _normalise(x, p0):
+    y = np.array(x, copy=True)
+    y[..., p0:] -= y[..., p0:].mean(axis=-1, keepdims=True)
+    return y
+
+
+def _bumps(coords, nrhs, seed):
+    C, W, D = synth.gaussian_bump_params3d(nrhs, seed)
+    return np.stack([np.stack(synth.gaussian_bump_forcing3d(coords[:, 0], coords[:, 1], coords[:, 2], C[i], W[i],
+                                                           D[i])) for i in range(nrhs)])
+
+
+def test_cube_relax_vcycle_fgmres_match_oracle():
+    from paper_2407_07253_amd._lib import Hierarchy
+    name = "cfg5_r1"
+    fh = frontend.build_hierarchy(name, forcing="bumps", nrhs=1)
+    H = Hierarchy.from_frontend(fh)
+    H.setup()
+    ol, od, oopts, ob = oproblems.build(name, forcing="bumps", nrhs=1)
+    omg.setup(ol, oopts)
+    n = ol[0].n
+    rng = np.random.default_rng(31)
+    b, x = rng.standard_normal(n), rng.standard_normal(n)
+    xg = _dev(x)
+    H.relax_apply(0, _dev(b), xg, 2)
+    e_relax = _rel(_host(xg), omg._relax(ol[0], oopts, b, x, 2, False))
+    z = _dev(np.zeros(n))
+    H.vcycle(_dev(b), z)
+    e_v = _rel(_host(z), omg.vcycle(ol, oopts, b))
+    zt = _dev(np.zeros(n))
+    H.vcycle_transposed(_dev(b), zt)
+    e_vt = _rel(_host(zt), omg.vcycle(ol, oopts, b, transpose=True))
+    lam = H.level_info(0)["lambda_max"]
+    xs = _dev(np.zeros(n))
+    iters, relres, conv = H.fgmres(_dev(ob[0]), xs, rtol=1e-8)
+    K = ol[0].K
+    res = ofgmres.fgmres(lambda v: K @ v, lambda v: omg.vcycle(ol, oopts, v), ob[0], rtol=1e-8)
+    p0 = 3 * od[0].nfu
+    e_x = np.linalg.norm(_normalise(_host(xs), p0) - _normalise(res.x, p0)) / np.linalg.norm(_normalise(res.x, p0))
+    print(f"cube 8^3: relax {e_relax:.2e}, vcycle {e_v:.2e}, transposed vcycle {e_vt:.2e}, lambda_max {lam:.10f} "
+          f"(oracle {ol[0].lmax:.10f}); FGMRES GPU {iters} oracle {res.iters}, solution {e_x:.2e}")
+    assert e_relax <= 1e-11 and e_v <= 1e-11 and e_vt <= 1e-11
+    assert abs(lam - ol[0].lmax) <= 1e-11 * ol[0].lmax
+    assert conv and res.converged and iters == res.iters
+    assert e_x <= 1e-10
+    H.close()
+
+
+def test_cube_gradients_match_oracle_adjoint():
+    from paper_2407_07253_amd.adjoint import StokesProblem
+    name, nrhs = "cfg5_r1", 4
+    problem = StokesProblem(name, rtol=1e-12)
+    lv = synth.log_viscosity(problem.mesh.verts, seed=5)
+    fh, H = problem.hierarchy(lv)
+    n0, p0, nf = problem.sizes
+    fn = _bumps(fh.levels[0].V.coords, nrhs, 6)
+    T = np.random.default_rng(12).standard_normal((nrhs, n0)) * 0.01
+    f = _dev(fn.reshape(nrhs, -1)).requires_grad_(True)
+    l = _dev(lv).requires_grad_(True)
+    X = problem.solve(f, l)
+    J = 0.5 * ((X[:, :p0] - _dev(T)[:, :p0]) ** 2).sum()
+    J.backward()
+    _, od, _, _ = oproblems.build(name, with_rhs=False, log_visc=lv)
+    d = od[0]
+    z = d.null_vector()
+    Kb = sp.bmat([[d.K, sp.csr_matrix(z[:, None])], [sp.csr_matrix(z[None, :]), None]], format="csc")
+    lu = spla.splu(Kb)
+    B = oadj.forcing_rhs(d, fn)
+    Xo = np.stack([lu.solve(np.concatenate([bb, [0.0]]))[:-1] for bb in B])
+    G = oadj.objective_gradient(Xo, T, d.nfu, 3)
+    Lo = np.stack([lu.solve(np.concatenate([g, [0.0]]), trans="T")[:-1] for g in G])
+    Jo = oadj.objective(Xo, T, d.nfu, 3)
+    glo, gfo = oadj.viscosity_gradient(d, Xo, Lo), oadj.forcing_gradient(d, Lo)
+    gl, gf = _host(l.grad), _host(f.grad).reshape(nrhs, 3, -1)
+    eJ, el, ef = abs(float(J) - Jo) / abs(Jo), _rel(gl, glo), _rel(gf, gfo)
+    print(f"cube 8^3 gradients: iters {problem.last_iters} / adjoint {problem.last_adjoint_iters}; "
+          f"J rel {eJ:.2e}, dJ/dl rel {el:.2e}, dJ/df rel {ef:.2e}")
+    assert eJ <= 1e-10 and el <= 1e-7 and ef <= 1e-7
+
+
+def test_cube_full_size_gradients_central_differences():
+    """16^3 cubes x 6 tetrahedra (94 286 DoFs), 8 batched forcings: forward (batched FGMRES),
+    backward (8 adjoint solves + GPU contraction), checked by central differences, h = 1e-6."""
+    from paper_2407_07253_amd.adjoint import StokesProblem
+    name, nrhs = "cfg5", 8
+    problem = StokesProblem(name, rtol=1e-11)
+    lv = synth.log_viscosity(problem.mesh.verts, seed=5)
+    t0 = time.perf_counter()
+    fh, H = problem.hierarchy(lv)
+    t_build = time.perf_counter() - t0
+    n0, p0, nf = problem.sizes
+    fn = _bumps(fh.levels[0].V.coords, nrhs, 6)
+    T = np.random.default_rng(13).standard_normal((nrhs, n0)) * 0.01
+    Tt = _dev(T)
+    f = _dev(fn.reshape(nrhs, -1)).requires_grad_(True)
+    l = _dev(lv).requires_grad_(True)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    X = problem.solve(f, l)
+    J = 0.5 * ((X[:, :p0] - Tt[:, :p0]) ** 2).sum()
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    J.backward()
+    torch.cuda.synchronize()
+    t3 = time.perf_counter()
+    print(f"cfg5: n {n0}, host build {t_build:.1f} s, forward {1e3 * (t2 - t1):.1f} ms (iters "
+          f"{problem.last_iters}), backward {1e3 * (t3 - t2):.1f} ms (adjoint iters {problem.last_adjoint_iters})")
+    gl, gf = l.grad.clone(), f.grad.clone()
+    rng = np.random.default_rng(14)
+    h = 1e-6
+
+    def Jval(ff, ll):
+        with torch.no_grad():
+            Xp = problem.solve(ff, ll)
+            return float(0.5 * ((Xp[:, :p0] - Tt[:, :p0]) ** 2).sum())
+
+    dl = _dev(rng.standard_normal(lv.shape))
+    fd = (Jval(f, l + h * dl) - Jval(f, l - h * dl)) / (2 * h)
+    an = float((gl * dl).sum())
+    print(f"cfg5 log-viscosity direction: adjoint {an:.10e} central difference {fd:.10e} rel "
+          f"{abs(an - fd) / abs(fd):.2e}")
+    assert abs(an - fd) <= 1e-5 * abs(fd)
+    df = _dev(rng.standard_normal(fn.reshape(nrhs, -1).shape))
+    fdf = (Jval(f + h * df, l) - Jval(f - h * df, l)) / (2 * h)
+    anf = float((gf * df).sum())
+    print(f"cfg5 forcing direction: adjoint {anf:.10e} central difference {fdf:.10e} rel "
+          f"{abs(anf - fdf) / abs(fdf):.2e}")
+    assert abs(anf - fdf) <= 1e-5 * abs(fdf)

@@ -37,27 +37,28 @@ def _inputs():
     problem = StokesProblem(NAME, rtol=1e-12)
     lv = synth.log_viscosity(problem.mesh.verts, seed=5)
     fh, H = problem.hierarchy(lv)
-    n0, nfu, nf = problem.sizes
+    n0, p0, nf = problem.sizes
     coords = fh.levels[0].V.coords
     C, W, D = synth.gaussian_bump_params(NRHS, 6)
     fn = np.zeros((NRHS, 2, coords.shape[0]))
     for b in range(NRHS):
         fn[b, 0], fn[b, 1] = synth.gaussian_bump_forcing(coords[:, 0], coords[:, 1], C[b], W[b], D[b])
     T = np.random.default_rng(11).standard_normal((NRHS, n0)) * 0.01
-    return problem, lv, fn, T, nfu
+    return problem, lv, fn, T, p0
 
 
-def _J(problem, f, l, T, nfu):
+def _J(problem, f, l, T, p0):
+    """1/2 sum_c ||u_c - t_c||^2 over the free velocity DoFs (entries before the pressure block)."""
     X = problem.solve(f, l)
     Tt = torch.tensor(T, device="cuda")
-    return 0.5 * ((X[:, : 2 * nfu] - Tt[:, : 2 * nfu]) ** 2).sum()
+    return 0.5 * ((X[:, :p0] - Tt[:, :p0]) ** 2).sum()
 
 
 def test_gradients_match_oracle_adjoint():
-    problem, lv, fn, T, nfu = _inputs()
+    problem, lv, fn, T, p0 = _inputs()
     f = torch.tensor(fn.reshape(NRHS, -1), device="cuda", requires_grad=True)
     l = torch.tensor(lv, device="cuda", requires_grad=True)
-    J = _J(problem, f, l, T, nfu)
+    J = _J(problem, f, l, T, p0)
     J.backward()
     gl, gf = l.grad.cpu().numpy(), f.grad.cpu().numpy().reshape(NRHS, 2, -1)
     print(f"forward iters {problem.last_iters}, adjoint iters {problem.last_adjoint_iters}")
@@ -82,26 +83,26 @@ def test_gradients_match_oracle_adjoint():
 
 
 def test_gradients_match_central_differences():
-    problem, lv, fn, T, nfu = _inputs()
+    problem, lv, fn, T, p0 = _inputs()
     f = torch.tensor(fn.reshape(NRHS, -1), device="cuda", requires_grad=True)
     l = torch.tensor(lv, device="cuda", requires_grad=True)
-    _J(problem, f, l, T, nfu).backward()
+    _J(problem, f, l, T, p0).backward()
     gl, gf = l.grad.clone(), f.grad.clone()
     rng = np.random.default_rng(13)
     h = 1e-6
     with torch.no_grad():
         for trial in range(2):
             dl = torch.tensor(rng.standard_normal(lv.shape), device="cuda")
-            Jp = float(_J(problem, f, l + h * dl, T, nfu))
-            Jm = float(_J(problem, f, l - h * dl, T, nfu))
+            Jp = float(_J(problem, f, l + h * dl, T, p0))
+            Jm = float(_J(problem, f, l - h * dl, T, p0))
             fd = (Jp - Jm) / (2 * h)
             an = float((gl * dl).sum())
             print(f"log-viscosity direction {trial}: adjoint {an:.10e} central difference {fd:.10e} "
                   f"rel {abs(an - fd) / abs(fd):.2e}")
             assert abs(an - fd) <= 1e-5 * abs(fd)
         df = torch.tensor(rng.standard_normal(fn.reshape(NRHS, -1).shape), device="cuda")
-        Jp = float(_J(problem, f + h * df, l, T, nfu))
-        Jm = float(_J(problem, f - h * df, l, T, nfu))
+        Jp = float(_J(problem, f + h * df, l, T, p0))
+        Jm = float(_J(problem, f - h * df, l, T, p0))
         fd = (Jp - Jm) / (2 * h)
         an = float((gf * df).sum())
         print(f"forcing direction: adjoint {an:.10e} central difference {fd:.10e} rel {abs(an - fd) / abs(fd):.2e}")

@@ -189,6 +189,27 @@ phmg_status phmg_forcing_rhs(phmg_ctx ctx, int nrhs, const double* F, double* B)
 phmg_status phmg_gradients(phmg_ctx ctx, int nrhs, const double* X, const double* Lam, double* grad_theta,
                            double* grad_f);
 
+/* Full-block-factorisation preconditioner (Section 3.3, eq. "eq:fbf"):
+ *   P^{-1} = [I  -A~^{-1} B^T; 0  I] [A~^{-1}  0; 0  S~^{-1}] [I  0; -B A~^{-1}  I]
+ * applied to r = [r_u; r_p] as y_u = A~^{-1} r_u, z_p = S~^{-1}(r_p - B y_u),
+ * z_u = y_u - A~^{-1} B^T z_p.  A~^{-1} is one cycle (phmg_vcycle) of
+ * `velocity`, a hierarchy created on the velocity block A of K (its own
+ * levels, patches -- the paper uses vertex-star velocity patches -- and
+ * transfers; set up before use); S~^{-1} is any n_p x n_p matrix, in the paper
+ * the inverse block-diagonal pressure mass matrix (Scott-Vogelius), with the
+ * sign of the Schur complement -B A^{-1} B^T.  K (n x n, velocity DoFs first),
+ * B (n_p x n_u) and S_inv are HOST csr arrays copied at create.
+ * fbf_fgmres_solve: FGMRES on K right-preconditioned by P^{-1}, with the
+ * stopping rule and outputs of phmg_fgmres_solve.  Work runs on the velocity
+ * context's stream; destroy the FBF object before its velocity context. */
+typedef struct phmg_fbf_s* phmg_fbf;
+phmg_status phmg_fbf_create(phmg_ctx velocity, const phmg_csr* K, const phmg_csr* B, const phmg_csr* S_inv,
+                            phmg_fbf* out);
+phmg_status phmg_fbf_apply(phmg_fbf fbf, const double* r, double* z);
+phmg_status phmg_fbf_fgmres_solve(phmg_fbf fbf, const double* b, double* x, double rtol, int restart, int maxit,
+                                  int* iters, double* relres);
+phmg_status phmg_fbf_destroy(phmg_fbf fbf);
+
 /* Several right-hand sides at once (1 <= nrhs <= PHMG_MAX_RHS).  B and X are
  * DEVICE float64 arrays of nrhs * n_l entries holding the systems one after
  * another (X[c * n_l + i] is DoF i of system c, i.e. a (nrhs, n) row-major

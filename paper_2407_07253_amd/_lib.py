@@ -100,6 +100,12 @@ _fgmres_t = _sig("phmg_fgmres_solve_transposed", C.c_int, [C.c_void_p, C.c_void_
 _set_sens = _sig("phmg_set_sensitivities", C.c_int, [C.c_void_p, C.POINTER(CsrT), C.POINTER(CsrT)])
 _forcing_rhs = _sig("phmg_forcing_rhs", C.c_int, [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p])
 _gradients = _sig("phmg_gradients", C.c_int, [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p])
+_fbf_create = _sig("phmg_fbf_create", C.c_int, [C.c_void_p, C.POINTER(CsrT), C.POINTER(CsrT), C.POINTER(CsrT),
+                                                 C.POINTER(C.c_void_p)])
+_fbf_apply = _sig("phmg_fbf_apply", C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p])
+_fbf_fgmres = _sig("phmg_fbf_fgmres_solve", C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_double, C.c_int,
+                                                      C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_double)])
+_fbf_destroy = _sig("phmg_fbf_destroy", C.c_int, [C.c_void_p])
 MAX_RHS = 16
 
 EXPORTED = ["phmg_hierarchy_create", "phmg_hierarchy_destroy", "phmg_relax_setup", "phmg_set_precision",
@@ -108,6 +114,7 @@ EXPORTED = ["phmg_hierarchy_create", "phmg_hierarchy_destroy", "phmg_relax_setup
             "phmg_set_graphs", "phmg_relax_apply_batched", "phmg_vcycle_batched", "phmg_fgmres_solve_batched",
             "phmg_relax_apply_transposed", "phmg_vcycle_transposed", "phmg_fgmres_solve_transposed",
             "phmg_set_sensitivities", "phmg_forcing_rhs", "phmg_gradients",
+            "phmg_fbf_create", "phmg_fbf_apply", "phmg_fbf_fgmres_solve", "phmg_fbf_destroy",
             "phmg_last_error"]
 
 
@@ -351,3 +358,47 @@ class Hierarchy:
         cnt = C.c_int64(0)
         _check(_prof_read(self._h, KERNELS[kernel], level, C.byref(ms), C.byref(cnt)))
         return float(ms.value), int(cnt.value)
+
+
+def _csr_struct(A, keep):
+    rowptr = np.ascontiguousarray(A.rowptr, dtype=np.int32)
+    col = np.ascontiguousarray(A.col, dtype=np.int32)
+    val = np.ascontiguousarray(A.val, dtype=np.float64)
+    keep.extend([rowptr, col, val])
+    return CsrT(int(A.nrows), int(A.ncols), int(col.size), _ptr(rowptr), _ptr(col), _ptr(val))
+
+
+class Fbf:
+    """Full-block-factorisation preconditioner and its FGMRES (phmg_fbf_*).
+
+    velocity: a set-up Hierarchy on the velocity block; K, B, S_inv: frontend Csr objects."""
+
+    def __init__(self, velocity: Hierarchy, K, B, S_inv):
+        keep = []
+        ck, cb, cs = _csr_struct(K, keep), _csr_struct(B, keep), _csr_struct(S_inv, keep)
+        h = C.c_void_p()
+        _check(_fbf_create(velocity._h, C.byref(ck), C.byref(cb), C.byref(cs), C.byref(h)))
+        self._h = h
+        self.velocity = velocity          # keeps the velocity context alive
+        self.n = int(K.nrows)
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            _fbf_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def apply(self, r, z):
+        _check(_fbf_apply(self._h, _vec_ptr(r, self.n, "r"), _vec_ptr(z, self.n, "z")))
+
+    def fgmres(self, b, x, rtol: float = 1e-8, restart: int = 30, maxit: int = 1000):
+        it = C.c_int(0)
+        rr = C.c_double(0.0)
+        st = _check(_fbf_fgmres(self._h, _vec_ptr(b, self.n, "b"), _vec_ptr(x, self.n, "x"), rtol, restart, maxit,
+                                C.byref(it), C.byref(rr)), allow=(PHMG_ENOCONV,))
+        return int(it.value), float(rr.value), st == PHMG_OK

@@ -731,6 +731,12 @@ __global__ __launch_bounds__(kBlock) void gemv_add_kernel(int64_t n, int ncol, c
     }
 }
 
+__global__ __launch_bounds__(kBlock) void axpby_kernel(int64_t n, double a, const double* __restrict__ x, double b,
+                                                       const double* __restrict__ y, double* __restrict__ z) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        z[i] = a * x[i] + b * y[i];
+}
+
 __global__ __launch_bounds__(kBlock) void scale_copy_kernel(int64_t n, const double* __restrict__ s, double q,
                                                             double* __restrict__ d) {
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
@@ -901,6 +907,11 @@ void launch_gemv_sub(hipStream_t s, int64_t n, int ncol, const double* V, int64_
 void launch_gemv_add(hipStream_t s, int64_t n, int ncol, const double* Z, int64_t ldz, const double* y, double* x) {
     hipLaunchKernelGGL(gemv_add_kernel, dim3(std::min(grid_for(n, kBlock), 4096)), dim3(kBlock), 0, s, n, ncol, Z,
                        ldz, y, x);
+}
+
+void launch_axpby(hipStream_t s, int64_t n, double a, const double* x, double b, const double* y, double* z) {
+    if (n <= 0) return;
+    hipLaunchKernelGGL(axpby_kernel, dim3(std::min(grid_for(n, kBlock), 4096)), dim3(kBlock), 0, s, n, a, x, b, y, z);
 }
 
 void launch_scale_copy(hipStream_t s, int64_t n, const double* src, double denom, double* dst) {

@@ -263,6 +263,7 @@ double ritz_max_real(const double* H, int ldh, int k) {
 }
 
 void ensure_krylov(phmg_ctx ctx, int restart);
+double device_norm(hipStream_t s, Krylov& kr, int64_t n, const double* v);
 
 // lambda_max(M^{-1} K): largest real Ritz value of eig_iters Arnoldi steps
 // (CGS2) from v_0 = (1 + sin(j)/2) / ||.||, all vectors on the device.
@@ -271,31 +272,31 @@ double arnoldi_estimate(phmg_ctx ctx, int l) {
     hipStream_t s = ctx->stream;
     const int64_t n = L.n;
     int k = (int)std::min<int64_t>(ctx->opts.eig_iters, n);
-    ensure_krylov(ctx, std::max(ctx->restart_cap, k));
-    double* V = ctx->V;
-    double* w = ctx->w;
-    const int stride = ctx->restart_cap + 2;
-    double* h1 = ctx->hdev;
-    double* h2 = ctx->hdev + stride;
-    double* hn2 = ctx->hdev + 2 * stride;
+    ensure_krylov(ctx, std::max(ctx->kry.cap, k));
+    double* V = ctx->kry.V;
+    double* w = ctx->kry.w;
+    const int stride = ctx->kry.cap + 2;
+    double* h1 = ctx->kry.hdev;
+    double* h2 = ctx->kry.hdev + stride;
+    double* hn2 = ctx->kry.hdev + 2 * stride;
     launch_power_start(s, n, V);
-    launch_multidot(s, n, 1, V, n, V, ctx->partial, ctx->scal, false);
+    launch_multidot(s, n, 1, V, n, V, ctx->kry.partial, ctx->scal, false);
     launch_scale_by_devnorm(s, n, V, ctx->scal, V);
     std::vector<double> H((size_t)(k + 1) * k, 0.0);
     for (int j = 0; j < k; ++j) {
         launch_spmv(s, L.K, V + (int64_t)j * n, 1.0, nullptr, 0.0, L.r);
         launch_patch_apply(s, L, L.r);
         launch_scatter(s, L, 1.0, 0.0, nullptr, false, w, true);
-        launch_multidot(s, n, j + 1, V, n, w, ctx->partial, h1, false);
+        launch_multidot(s, n, j + 1, V, n, w, ctx->kry.partial, h1, false);
         launch_gemv_sub(s, n, j + 1, V, n, h1, w);
-        launch_multidot(s, n, j + 1, V, n, w, ctx->partial, h2, false);
+        launch_multidot(s, n, j + 1, V, n, w, ctx->kry.partial, h2, false);
         launch_gemv_sub(s, n, j + 1, V, n, h2, w);
-        launch_multidot(s, n, 1, w, n, w, ctx->partial, hn2, false);
-        hipcheck(hipMemcpyAsync(ctx->hhost, ctx->hdev, sizeof(double) * (2 * stride + 1), hipMemcpyDeviceToHost, s),
+        launch_multidot(s, n, 1, w, n, w, ctx->kry.partial, hn2, false);
+        hipcheck(hipMemcpyAsync(ctx->kry.hhost, ctx->kry.hdev, sizeof(double) * (2 * stride + 1), hipMemcpyDeviceToHost, s),
                  "D2H");
         hipcheck(hipStreamSynchronize(s), "hipStreamSynchronize");
-        for (int i = 0; i <= j; ++i) H[(size_t)j * (k + 1) + i] = ctx->hhost[i] + ctx->hhost[stride + i];
-        const double hn = std::sqrt(ctx->hhost[2 * stride]);
+        for (int i = 0; i <= j; ++i) H[(size_t)j * (k + 1) + i] = ctx->kry.hhost[i] + ctx->kry.hhost[stride + i];
+        const double hn = std::sqrt(ctx->kry.hhost[2 * stride]);
         H[(size_t)j * (k + 1) + j + 1] = hn;
         if (hn == 0.0) {
             k = j + 1;
@@ -535,53 +536,61 @@ void setup_level(phmg_ctx ctx, int l) {
     L.ready = true;
 }
 
-double device_norm(phmg_ctx ctx, const double* v) {
-    const int64_t n = ctx->L[0].n;
-    launch_multidot(ctx->stream, n, 1, v, n, v, ctx->partial, ctx->hdev, false);
-    hipcheck(hipMemcpyAsync(ctx->hhost, ctx->hdev, sizeof(double), hipMemcpyDeviceToHost, ctx->stream), "D2H");
-    hipcheck(hipStreamSynchronize(ctx->stream), "hipStreamSynchronize");
-    return std::sqrt(ctx->hhost[0]);
+double device_norm(hipStream_t s, Krylov& kr, int64_t n, const double* v) {
+    launch_multidot(s, n, 1, v, n, v, kr.partial, kr.hdev, false);
+    hipcheck(hipMemcpyAsync(kr.hhost, kr.hdev, sizeof(double), hipMemcpyDeviceToHost, s), "D2H");
+    hipcheck(hipStreamSynchronize(s), "hipStreamSynchronize");
+    return std::sqrt(kr.hhost[0]);
 }
 
-void ensure_krylov(phmg_ctx ctx, int restart) {
-    if (ctx->restart_cap >= restart) return;
-    const int64_t n = ctx->L[0].n;
-    dfree(ctx, ctx->V);
-    dfree(ctx, ctx->Z);
-    dfree(ctx, ctx->hdev);
-    if (ctx->hhost) (void)hipHostFree(ctx->hhost);
-    ctx->hhost = nullptr;
-    ctx->V = dalloc<double>(ctx, n * (restart + 1));
-    ctx->Z = dalloc<double>(ctx, n * restart);
-    ctx->hdev = dalloc<double>(ctx, 2 * (restart + 2) + 4);
-    if (!ctx->w) ctx->w = dalloc<double>(ctx, n);
-    if (!ctx->rvec) ctx->rvec = dalloc<double>(ctx, n);
-    if (ctx->partial_cols < restart + 2) {
-        dfree(ctx, ctx->partial);
-        ctx->partial = dalloc<double>(ctx, (int64_t)kRedBlocks * (restart + 2));
-        ctx->partial_cols = restart + 2;
+// FGMRES work space for vectors of length n and `restart` basis vectors; the
+// device memory is owned (and freed) through `owner`.
+void ensure_krylov(phmg_ctx owner, Krylov& kr, int64_t n, int restart) {
+    if (kr.cap >= restart && kr.n == n) return;
+    dfree(owner, kr.V);
+    dfree(owner, kr.Z);
+    dfree(owner, kr.hdev);
+    if (kr.hhost) (void)hipHostFree(kr.hhost);
+    kr.hhost = nullptr;
+    if (kr.n != n) {
+        dfree(owner, kr.w);
+        dfree(owner, kr.r);
+        kr.w = kr.r = nullptr;
     }
-    hipcheck(hipHostMalloc((void**)&ctx->hhost, sizeof(double) * (2 * (restart + 2) + 4)), "hipHostMalloc");
-    ctx->restart_cap = restart;
+    kr.V = dalloc<double>(owner, n * (restart + 1));
+    kr.Z = dalloc<double>(owner, n * restart);
+    kr.hdev = dalloc<double>(owner, 2 * (restart + 2) + 4);
+    if (!kr.w) kr.w = dalloc<double>(owner, n);
+    if (!kr.r) kr.r = dalloc<double>(owner, n);
+    if (kr.partial_cols < restart + 2) {
+        dfree(owner, kr.partial);
+        kr.partial = dalloc<double>(owner, (int64_t)kRedBlocks * (restart + 2));
+        kr.partial_cols = restart + 2;
+    }
+    hipcheck(hipHostMalloc((void**)&kr.hhost, sizeof(double) * (2 * (restart + 2) + 4)), "hipHostMalloc");
+    kr.cap = restart;
+    kr.n = n;
 }
 
-// transpose: the adjoint solve K^T x = b, right-preconditioned by B^T.
-phmg_status fgmres(phmg_ctx ctx, const double* b, double* x, double rtol, int restart, int maxit, int* iters_out,
-                   double* relres_out, bool transpose = false) {
-    Level& L0 = ctx->L[0];
-    const int64_t n = L0.n;
-    hipStream_t s = ctx->stream;
-    ensure_krylov(ctx, restart);
-    double* V = ctx->V;
-    double* Z = ctx->Z;
-    double* w = ctx->w;
-    double* r = ctx->rvec;
-    double* h1 = ctx->hdev;
-    double* h2 = ctx->hdev + (restart + 2);
-    double* hn2 = ctx->hdev + 2 * (restart + 2);
+void ensure_krylov(phmg_ctx ctx, int restart) { ensure_krylov(ctx, ctx->kry, ctx->L[0].n, restart); }
 
-    launch_spmv(s, transpose ? L0.KT : L0.K, x, -1.0, b, 1.0, r);
-    double beta = device_norm(ctx, r);
+// Restarted FGMRES (the reading of the solver paragraph of Section 4; see the
+// ABI notes): matvec(x, alpha, z, beta, y) forms y = alpha A x + beta z,
+// precond(v, z) forms z = B v.  CGS2 on the device, Hessenberg and Givens on
+// the host, one device-to-host copy per iteration.
+template <class MatVec, class Prec>
+phmg_status fgmres_core(hipStream_t s, Krylov& kr, int64_t n, MatVec matvec, Prec precond, const double* b,
+                        double* x, double rtol, int restart, int maxit, int* iters_out, double* relres_out) {
+    double* V = kr.V;
+    double* Z = kr.Z;
+    double* w = kr.w;
+    double* r = kr.r;
+    double* h1 = kr.hdev;
+    double* h2 = kr.hdev + (restart + 2);
+    double* hn2 = kr.hdev + 2 * (restart + 2);
+
+    matvec(x, -1.0, b, 1.0, r);
+    double beta = device_norm(s, kr, n, r);
     const double r0 = beta;
     const double target = rtol * r0;
     int iters = 0;
@@ -603,20 +612,20 @@ phmg_status fgmres(phmg_ctx ctx, const double* b, double* x, double rtol, int re
         for (int j = 0; j < restart; ++j) {
             double* vj = V + (int64_t)j * n;
             double* zj = Z + (int64_t)j * n;
-            precond(ctx, vj, zj, transpose);
-            launch_spmv(s, transpose ? L0.KT : L0.K, zj, 1.0, nullptr, 0.0, w);
-            launch_multidot(s, n, j + 1, V, n, w, ctx->partial, h1, false);
+            precond(vj, zj);
+            matvec(zj, 1.0, nullptr, 0.0, w);
+            launch_multidot(s, n, j + 1, V, n, w, kr.partial, h1, false);
             launch_gemv_sub(s, n, j + 1, V, n, h1, w);
-            launch_multidot(s, n, j + 1, V, n, w, ctx->partial, h2, false);
+            launch_multidot(s, n, j + 1, V, n, w, kr.partial, h2, false);
             launch_gemv_sub(s, n, j + 1, V, n, h2, w);
-            launch_multidot(s, n, 1, w, n, w, ctx->partial, hn2, false);
-            hipcheck(hipMemcpyAsync(ctx->hhost, ctx->hdev, sizeof(double) * (2 * (restart + 2) + 1),
+            launch_multidot(s, n, 1, w, n, w, kr.partial, hn2, false);
+            hipcheck(hipMemcpyAsync(kr.hhost, kr.hdev, sizeof(double) * (2 * (restart + 2) + 1),
                                     hipMemcpyDeviceToHost, s),
                      "D2H");
             hipcheck(hipStreamSynchronize(s), "hipStreamSynchronize");
-            const double* hh1 = ctx->hhost;
-            const double* hh2 = ctx->hhost + (restart + 2);
-            hn = std::sqrt(ctx->hhost[2 * (restart + 2)]);
+            const double* hh1 = kr.hhost;
+            const double* hh2 = kr.hhost + (restart + 2);
+            hn = std::sqrt(kr.hhost[2 * (restart + 2)]);
             for (int i = 0; i <= j; ++i) Hij(i, j) = hh1[i] + hh2[i];
             Hij(j + 1, j) = hn;
             for (int i = 0; i < j; ++i) {
@@ -645,8 +654,8 @@ phmg_status fgmres(phmg_ctx ctx, const double* b, double* x, double rtol, int re
         double* yd = h2;   // reuse: h2 is consumed
         hipcheck(hipMemcpyAsync(yd, y.data(), sizeof(double) * ncols, hipMemcpyHostToDevice, s), "H2D");
         launch_gemv_add(s, n, ncols, Z, n, yd, x);
-        launch_spmv(s, transpose ? L0.KT : L0.K, x, -1.0, b, 1.0, r);
-        beta = device_norm(ctx, r);
+        matvec(x, -1.0, b, 1.0, r);
+        beta = device_norm(s, kr, n, r);
         if (beta <= target) {
             converged = true;
             break;
@@ -659,6 +668,19 @@ phmg_status fgmres(phmg_ctx ctx, const double* b, double* x, double rtol, int re
     return converged ? PHMG_OK : PHMG_ENOCONV;
 }
 
+// transpose: the adjoint solve K^T x = b, right-preconditioned by B^T.
+phmg_status fgmres(phmg_ctx ctx, const double* b, double* x, double rtol, int restart, int maxit, int* iters_out,
+                   double* relres_out, bool transpose = false) {
+    Level& L0 = ctx->L[0];
+    hipStream_t s = ctx->stream;
+    ensure_krylov(ctx, restart);
+    const DevCsr& A = transpose ? L0.KT : L0.K;
+    auto matvec = [&](const double* xx, double alpha, const double* z, double beta, double* y) {
+        launch_spmv(s, A, xx, alpha, z, beta, y);
+    };
+    auto prec = [&](const double* v, double* z) { precond(ctx, v, z, transpose); };
+    return fgmres_core(s, ctx->kry, L0.n, matvec, prec, b, x, rtol, restart, maxit, iters_out, relres_out);
+}
 
 void destroy_all(phmg_ctx ctx) {
     invalidate_graph(ctx);
@@ -669,7 +691,7 @@ void destroy_all(phmg_ctx ctx) {
     }
     for (auto e : ctx->prof.pool) (void)hipEventDestroy(e);
     for (void* p : ctx->allocs) (void)hipFree(p);
-    if (ctx->hhost) (void)hipHostFree(ctx->hhost);
+    if (ctx->kry.hhost) (void)hipHostFree(ctx->kry.hhost);
     if (ctx->bhhost) (void)hipHostFree(ctx->bhhost);
     delete ctx;
 }
@@ -816,8 +838,8 @@ phmg_status phmg_hierarchy_create(const phmg_hierarchy_desc* desc, const phmg_cy
                 if (desc->coarse_null) L.cnull = upload(ctx, desc->coarse_null, L.n);
             }
         }
-        ctx->partial = dalloc<double>(ctx, (int64_t)kRedBlocks * 4);
-        ctx->partial_cols = 4;
+        ctx->kry.partial = dalloc<double>(ctx, (int64_t)kRedBlocks * 4);
+        ctx->kry.partial_cols = 4;
         ctx->scal = dalloc<double>(ctx, 8);
         ctx->L[0].x = dalloc<double>(ctx, ctx->L[0].n);   // scratch for level-0 power iteration
         *out = ctx;
@@ -1003,6 +1025,106 @@ phmg_status phmg_gradients(phmg_ctx ctx, int nrhs, const double* X, const double
         hipcheck(hipGetLastError(), "kernel launch");
         return PHMG_OK;
     });
+}
+
+// ---------------------------------------------------------------------------
+// Full block factorisation (Section 3.3, eq. "eq:fbf"):
+// P^{-1} = [I -A~^{-1}B^T; 0 I] [A~^{-1} 0; 0 S~^{-1}] [I 0; -B A~^{-1} I],
+// A~^{-1} one cycle of the velocity-block hierarchy, S~^{-1} a given matrix
+// (the inverse block-diagonal pressure mass matrix, with the sign of the
+// Schur complement -B A^{-1} B^T).
+// ---------------------------------------------------------------------------
+
+phmg_status phmg_fbf_create(phmg_ctx velocity, const phmg_csr* K, const phmg_csr* B, const phmg_csr* S_inv,
+                            phmg_fbf* out) {
+    return guarded([&]() -> phmg_status {
+        if (!velocity || !K || !B || !S_inv || !out) fail(PHMG_EINVAL, "null argument");
+        *out = nullptr;
+        const int64_t nu = velocity->L[0].n;
+        check_csr(*K, "fbf K: ");
+        check_csr(*B, "fbf B: ");
+        check_csr(*S_inv, "fbf S_inv: ");
+        if (K->nrows != K->ncols) fail(PHMG_EINVAL, "fbf K: not square");
+        const int64_t np = K->nrows - nu;
+        if (np <= 0) fail(PHMG_EINVAL, "fbf K: not larger than the velocity block");
+        if (B->nrows != np || B->ncols != nu) fail(PHMG_EINVAL, "fbf B: must be n_p x n_u");
+        if (S_inv->nrows != np || S_inv->ncols != np) fail(PHMG_EINVAL, "fbf S_inv: must be n_p x n_p");
+        auto* F = new phmg_fbf_s();
+        try {
+            F->A = velocity;
+            F->mem.stream = velocity->stream;
+            F->n = K->nrows;
+            F->nu = nu;
+            F->np = np;
+            F->K = upload_csr(&F->mem, *K);
+            F->B = upload_csr(&F->mem, *B);
+            F->BT = upload_transpose(&F->mem, *B);
+            F->Sinv = upload_csr(&F->mem, *S_inv);
+            F->yu = dalloc<double>(&F->mem, nu);
+            F->t = dalloc<double>(&F->mem, np);
+            F->wu = dalloc<double>(&F->mem, nu);
+            F->qu = dalloc<double>(&F->mem, nu);
+        } catch (...) {
+            for (void* p : F->mem.allocs) (void)hipFree(p);
+            delete F;
+            throw;
+        }
+        *out = F;
+        return PHMG_OK;
+    });
+}
+
+namespace {
+void fbf_apply(phmg_fbf F, const double* r, double* z) {
+    hipStream_t s = F->A->stream;
+    const double* rp = r + F->nu;
+    double* zp = z + F->nu;
+    precond(F->A, r, F->yu);                                    // y_u = A~^{-1} r_u
+    launch_spmv(s, F->B, F->yu, -1.0, rp, 1.0, F->t);           // t = r_p - B y_u
+    launch_spmv(s, F->Sinv, F->t, 1.0, nullptr, 0.0, zp);        // z_p = S~^{-1} t
+    launch_spmv(s, F->BT, zp, 1.0, nullptr, 0.0, F->wu);         // w = B^T z_p
+    precond(F->A, F->wu, F->qu);                                // q = A~^{-1} w
+    launch_axpby(s, F->nu, 1.0, F->yu, -1.0, F->qu, z);          // z_u = y_u - q
+}
+}  // namespace
+
+phmg_status phmg_fbf_apply(phmg_fbf fbf, const double* r, double* z) {
+    return guarded([&]() -> phmg_status {
+        if (!fbf || !r || !z) fail(PHMG_EINVAL, "null argument");
+        require_ready(fbf->A);
+        fbf_apply(fbf, r, z);
+        hipcheck(hipGetLastError(), "kernel launch");
+        return PHMG_OK;
+    });
+}
+
+phmg_status phmg_fbf_fgmres_solve(phmg_fbf fbf, const double* b, double* x, double rtol, int restart, int maxit,
+                                  int* iters, double* relres) {
+    return guarded([&]() -> phmg_status {
+        if (!fbf || !b || !x || !iters || !relres) fail(PHMG_EINVAL, "null argument");
+        if (restart < 1 || maxit < 1 || !(rtol >= 0.0)) fail(PHMG_EINVAL, "invalid rtol / restart / maxit");
+        require_ready(fbf->A);
+        hipStream_t s = fbf->A->stream;
+        fbf->mem.stream = s;
+        ensure_krylov(&fbf->mem, fbf->kry, fbf->n, restart);
+        auto matvec = [&](const double* xx, double alpha, const double* zz, double beta, double* y) {
+            launch_spmv(s, fbf->K, xx, alpha, zz, beta, y);
+        };
+        auto prec = [&](const double* v, double* z) { fbf_apply(fbf, v, z); };
+        const phmg_status st = fgmres_core(s, fbf->kry, fbf->n, matvec, prec, b, x, rtol, restart, maxit, iters,
+                                           relres);
+        hipcheck(hipGetLastError(), "kernel launch");
+        if (st == PHMG_ENOCONV) g_last_error = "FGMRES (FBF) reached maxit without converging";
+        return st;
+    });
+}
+
+phmg_status phmg_fbf_destroy(phmg_fbf fbf) {
+    if (!fbf) return PHMG_OK;
+    for (void* p : fbf->mem.allocs) (void)hipFree(p);
+    if (fbf->kry.hhost) (void)hipHostFree(fbf->kry.hhost);
+    delete fbf;
+    return PHMG_OK;
 }
 
 phmg_status phmg_residual(phmg_ctx ctx, int level, const double* b, const double* x, double* r) {

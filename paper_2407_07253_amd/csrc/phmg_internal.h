@@ -89,6 +89,21 @@ struct Level {
     int block_tuned_for = -1;
 };
 
+// FGMRES work space: bases V (n x cap+1) and Z (n x cap), work vectors, the
+// reduction partials and the device / pinned host scalars of one iteration.
+struct Krylov {
+    int cap = 0;
+    int64_t n = 0;
+    double* V = nullptr;
+    double* Z = nullptr;
+    double* w = nullptr;
+    double* r = nullptr;
+    double* partial = nullptr;       // kRedBlocks x (restart + 2) reduction partials
+    int partial_cols = 0;
+    double* hdev = nullptr;          // device scalars: h (restart + 1), h', ||w||^2
+    double* hhost = nullptr;         // pinned host mirror
+};
+
 struct Profile {
     unsigned mask = 0;
     double ms[PHMG_K_COUNT][PHMG_MAX_LEVELS] = {{0}};
@@ -108,17 +123,9 @@ struct phmg_ctx_s {
     std::vector<phmg::Level> L;
     phmg_cycle_opts opts{};
     std::vector<void*> allocs;
-    // FGMRES work space (level 0)
-    int restart_cap = 0;
-    double* V = nullptr;
-    double* Z = nullptr;
-    double* w = nullptr;
-    double* rvec = nullptr;
-    double* partial = nullptr;       // kRedBlocks x (restart + 2) reduction partials
-    int partial_cols = 0;
+    // FGMRES / Arnoldi work space (level 0)
+    phmg::Krylov kry;
     double* scal = nullptr;          // device scalars (norms) outside FGMRES
-    double* hdev = nullptr;          // device scalars: h (restart+1) and norm
-    double* hhost = nullptr;         // pinned host mirror
     phmg::Profile prof;
     // the preconditioner (one V-cycle) captured as a HIP graph on fixed buffers
     bool use_graphs = true;
@@ -145,6 +152,20 @@ struct phmg_ctx_s {
     double* bgout = nullptr;
     hipGraph_t bgraph = nullptr;
     hipGraphExec_t bexec = nullptr;
+};
+
+// The full-block-factorisation preconditioner: a velocity-block hierarchy (its
+// own context) plus the saddle-point pieces and work vectors.
+struct phmg_fbf_s {
+    phmg_ctx A = nullptr;            // velocity-block hierarchy (not owned)
+    phmg_ctx_s mem;                  // owner of the buffers below
+    phmg::DevCsr K, B, BT, Sinv;
+    int64_t n = 0, nu = 0, np = 0;
+    double* yu = nullptr;
+    double* t = nullptr;
+    double* wu = nullptr;
+    double* qu = nullptr;
+    phmg::Krylov kry;
 };
 
 namespace phmg {
@@ -188,6 +209,7 @@ void launch_gemv_sub(hipStream_t s, int64_t n, int ncol, const double* V, int64_
 void launch_gemv_add(hipStream_t s, int64_t n, int ncol, const double* Z, int64_t ldz, const double* y, double* x);
 void launch_scale_copy(hipStream_t s, int64_t n, const double* src, double denom, double* dst);  // dst = src / denom
 void launch_copy(hipStream_t s, int64_t n, const double* src, double* dst);
+void launch_axpby(hipStream_t s, int64_t n, double a, const double* x, double b, const double* y, double* z);
 
 // drop the captured block V-cycle (block.hip); called whenever set-up changes
 void invalidate_block_graph(phmg_ctx ctx);

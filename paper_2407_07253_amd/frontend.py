@@ -543,3 +543,82 @@ def build_hierarchy(name: str, k: Optional[int] = None, forcing: str = "mms", nr
             lev.P = prolongation(fine, lev, parent)
         levels.append(lev)
     return Hierarchy(name, levels, dict(opts), weights)
+
+
+# --------------------------------------------------------------------------
+# full block factorisation (Section 3.3, eq. "eq:fbf")
+# --------------------------------------------------------------------------
+
+
+def star_patches(lev: LevelData):
+    """Velocity-only vertex-star patches (the ASMStarPC patches of Section 3.4): the free
+    velocity DoFs of the entities of star(v) -- v itself, the edges and the cells around v --
+    both components; one patch per vertex with any such DoF."""
+    mesh = lev.mesh
+    cells = mesh.cells
+    nv = mesh.nv
+    order = np.argsort(cells.ravel(), kind="stable")
+    cell_of = order // 3
+    vptr = np.zeros(nv + 1, dtype=np.int64)
+    np.add.at(vptr, cells.ravel() + 1, 1)
+    vptr = np.cumsum(vptr)
+    upos = np.full(lev.V.ndofs, -1, dtype=np.int64)
+    upos[lev.free_u] = np.arange(lev.nfu)
+    ent = lev.V.entity_verts
+    out = []
+    for v in range(nv):
+        cs = cell_of[vptr[v]:vptr[v + 1]]
+        if cs.size == 0:
+            continue
+        at_v = cells[cs] == v
+        inside = (at_v[:, None, :] & ent[None, :, :]).any(axis=2)
+        vel = upos[np.unique(lev.V.cell_dofs[cs][inside])]
+        vel = vel[vel >= 0]
+        if vel.size:
+            out.append(np.concatenate([vel, vel + lev.nfu]))
+    ptr = np.zeros(len(out) + 1, dtype=np.int64)
+    ptr[1:] = np.cumsum([p.size for p in out])
+    return ptr, np.concatenate(out).astype(np.int32)
+
+
+def pressure_mass_inverse(lev: LevelData) -> Csr:
+    """-M_p^{-1} for a discontinuous pressure space: the cell blocks of the pressure mass
+    matrix inverted cell by cell, with the sign of the Schur complement -B A^{-1} B^T."""
+    if lev.Q.continuous:
+        raise ValueError("the block-diagonal pressure mass inverse needs a discontinuous pressure space")
+    kq = lev.k - 1
+    pts, w = collapsed_rule(2 * kq)
+    psi, _ = shape_functions(kq, pts)
+    _, _, adet, _ = _geometry(lev.mesh)
+    Mref = np.einsum("q,qa,qb->ab", w, psi, psi)
+    inv = -np.linalg.inv(Mref)[None, :, :] / adet[:, None, None]          # (nc, nq, nq)
+    qd = lev.Q.cell_dofs
+    nl = qd.shape[1]
+    S = sp.coo_matrix((inv.ravel(), (np.repeat(qd, nl, axis=1).ravel(), np.tile(qd, (1, nl)).ravel())),
+                      shape=(lev.nq, lev.nq)).tocsr()
+    S.sort_indices()
+    return Csr.from_scipy(S)
+
+
+def fbf_inputs(fh: Hierarchy) -> dict:
+    """Inputs of the FBF preconditioner for a Scott-Vogelius hierarchy: the velocity blocks
+    A_l of every level with star patches and the velocity parts of the transfers (the phMG
+    hierarchy on A), and K_0, B_0 and S~^{-1} = -M_p^{-1} of the finest level."""
+    A, P, patches = [], [], []
+    for li, lev in enumerate(fh.levels):
+        nu = 2 * lev.nfu
+        K = lev.K.to_scipy()
+        A.append(Csr.from_scipy(K[:nu, :nu].tocsr()))
+        if li > 0:
+            nuf = 2 * fh.levels[li - 1].nfu
+            P.append(Csr.from_scipy(lev.P.to_scipy()[:nuf, :nu].tocsr()))
+        if li < len(fh.levels) - 1:
+            ptr, dofs = star_patches(lev)
+            patches.append((ptr, dofs, None))
+    L0 = fh.levels[0]
+    nu0 = 2 * L0.nfu
+    K0 = L0.K.to_scipy()
+    B = K0[nu0:, :nu0].tocsr()
+    B.sort_indices()
+    return dict(A=A, P=P, patches=patches, K=L0.K, B=Csr.from_scipy(B), S_inv=pressure_mass_inverse(L0),
+                opts=dict(fh.opts))

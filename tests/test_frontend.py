@@ -119,3 +119,24 @@ def test_3d_sensitivities_match_oracle_adjoint():
     G = L0.forcing_map.to_scipy()
     gf = np.stack([G.T @ Lam[b] for b in range(2)]).reshape(2, 3, -1)
     assert np.abs(gf - oadj.forcing_gradient(d, Lam)).max() <= 1e-13 * np.abs(gf).max()
+
+
+def test_fbf_inputs_match_oracle():
+    """Velocity-block hierarchy (star patches, A_l, velocity transfers), B and -M_p^{-1}."""
+    from oracle import fbf as ofbf
+    fh = frontend.build_hierarchy("sv_small")
+    d = frontend.fbf_inputs(fh)
+    ol, od, oopts, ob = oproblems.build("sv_small")
+    vl = ofbf.velocity_levels(ol, od)
+    for li, L in enumerate(vl):
+        _same_csr(d["A"][li], L.K, 1e-13)
+        if L.P is not None:
+            _same_csr(d["P"][li - 1], L.P, 1e-13)
+        if L.patches is not None:
+            ptr, dofs, _ = d["patches"][li]
+            optr = np.concatenate([[0], np.cumsum([len(S) for S in L.patches])])
+            assert np.array_equal(ptr, optr)
+            assert np.array_equal(dofs, np.concatenate(L.patches))
+    nu = 2 * od[0].nfu
+    _same_csr(d["B"], ol[0].K[nu:, :nu], 1e-13)
+    _same_csr(d["S_inv"], ofbf.pressure_mass_inverse(od[0]), 1e-12)

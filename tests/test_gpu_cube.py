@@ -111,7 +111,7 @@ def test_cube_gradients_match_oracle_adjoint():
     Jo = oadj.objective(Xo, T, d.nfu, 3)
     glo, gfo = oadj.viscosity_gradient(d, Xo, Lo), oadj.forcing_gradient(d, Lo)
     gl, gf = _host(l.grad), _host(f.grad).reshape(nrhs, 3, -1)
-    eJ, el, ef = abs(float(J) - Jo) / abs(Jo), _rel(gl, glo), _rel(gf, gfo)
+    eJ, el, ef = abs(float(J.detach()) - Jo) / abs(Jo), _rel(gl, glo), _rel(gf, gfo)
     print(f"cube 8^3 gradients: iters {problem.last_iters} / adjoint {problem.last_adjoint_iters}; "
           f"J rel {eJ:.2e}, dJ/dl rel {el:.2e}, dJ/df rel {ef:.2e}")
     assert eJ <= 1e-10 and el <= 1e-7 and ef <= 1e-7

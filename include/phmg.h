@@ -239,15 +239,22 @@ phmg_status phmg_fgmres_solve_batched(phmg_ctx ctx, int nrhs, const double* B, d
 phmg_status phmg_residual(phmg_ctx ctx, int level, const double* b, const double* x, double* r);
 
 /* Per-level sizes: n, nnz(K), npatch, sum m, sum m^2, max m, the Chebyshev
- * eigenvalue estimate (0 before set-up or for Richardson) and the patch-solve
- * kernel shape chosen by the set-up autotuner. */
+ * eigenvalue estimate (0 before set-up or for Richardson), the patch-solve
+ * kernel shape chosen by the set-up autotuner and the number of shapes
+ * compiled for the level's precision. */
 typedef struct {
     int32_t n, npatch, max_m, precision;
     int64_t nnz, sum_m, sum_m2;
     double lambda_max;
-    int32_t apply_variant, reserved;
+    int32_t apply_variant, apply_variants;
 } phmg_level_info;
 phmg_status phmg_get_level_info(phmg_ctx ctx, int level, phmg_level_info* info);
+
+/* Override the autotuner's patch-solve kernel shape of one level (0 <=
+ * variant < apply_variants of phmg_level_info, for the level's current
+ * precision; kept until the precision changes).  Every shape computes the
+ * same result bit for bit; this exists for tests and tuning studies. */
+phmg_status phmg_set_apply_variant(phmg_ctx ctx, int level, int variant);
 
 /* Optional per-kernel, per-level timing with HIP events recorded on the
  * context stream around every launch of the selected kernels (off by

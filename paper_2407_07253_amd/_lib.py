@@ -62,7 +62,7 @@ class DescT(C.Structure):
 class LevelInfoT(C.Structure):
     _fields_ = [("n", C.c_int32), ("npatch", C.c_int32), ("max_m", C.c_int32), ("precision", C.c_int32),
                 ("nnz", C.c_int64), ("sum_m", C.c_int64), ("sum_m2", C.c_int64), ("lambda_max", C.c_double),
-                ("apply_variant", C.c_int32), ("reserved", C.c_int32)]
+                ("apply_variant", C.c_int32), ("apply_variants", C.c_int32)]
 
 
 def _sig(name, res, args):
@@ -106,6 +106,7 @@ _fbf_apply = _sig("phmg_fbf_apply", C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p
 _fbf_fgmres = _sig("phmg_fbf_fgmres_solve", C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_double, C.c_int,
                                                       C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_double)])
 _fbf_destroy = _sig("phmg_fbf_destroy", C.c_int, [C.c_void_p])
+_set_variant = _sig("phmg_set_apply_variant", C.c_int, [C.c_void_p, C.c_int, C.c_int])
 MAX_RHS = 16
 
 EXPORTED = ["phmg_hierarchy_create", "phmg_hierarchy_destroy", "phmg_relax_setup", "phmg_set_precision",
@@ -115,6 +116,7 @@ EXPORTED = ["phmg_hierarchy_create", "phmg_hierarchy_destroy", "phmg_relax_setup
             "phmg_relax_apply_transposed", "phmg_vcycle_transposed", "phmg_fgmres_solve_transposed",
             "phmg_set_sensitivities", "phmg_forcing_rhs", "phmg_gradients",
             "phmg_fbf_create", "phmg_fbf_apply", "phmg_fbf_fgmres_solve", "phmg_fbf_destroy",
+            "phmg_set_apply_variant",
             "phmg_last_error"]
 
 
@@ -220,6 +222,10 @@ class Hierarchy:
         if levels[0].visc_sens is not None and levels[0].forcing_map is not None:
             H.set_sensitivities(levels[0].visc_sens, levels[0].forcing_map)
         return H
+
+    def set_apply_variant(self, level: int, variant: int):
+        """Override the autotuned patch-solve kernel shape of a level (results are identical)."""
+        _check(_set_variant(self._h, level, variant))
 
     # -- adjoint gradients
     def set_sensitivities(self, S, G):
@@ -340,7 +346,8 @@ class Hierarchy:
         i = LevelInfoT()
         _check(_info(self._h, level, C.byref(i)))
         return dict(n=i.n, npatch=i.npatch, max_m=i.max_m, precision=i.precision, nnz=i.nnz, sum_m=i.sum_m,
-                    sum_m2=i.sum_m2, lambda_max=i.lambda_max, apply_variant=i.apply_variant)
+                    sum_m2=i.sum_m2, lambda_max=i.lambda_max, apply_variant=i.apply_variant,
+                    apply_variants=i.apply_variants)
 
     def profile(self, kernels=("patch_apply",)):
         """Enable HIP-event timing of the named kernels (empty = off)."""

@@ -258,13 +258,19 @@ __global__ __launch_bounds__(kBlock) void block_scatter_kernel(int32_t n, const 
     if (j >= n) return;
     double s = 0.0;
     const int end = sptr[j + 1];
-    if (w) {
-        for (int q = sptr[j]; q < end; ++q) {
-            const int slot = sslot[q];
-            s += w[slot] * Y[(int64_t)slot * kBS + c];
+    // four slots in flight, summed in ascending slot order (a missing slot adds +0)
+    for (int t = sptr[j]; t < end; t += 4) {
+        int q[4];
+        double y[4], wq[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) q[u] = t + u < end ? sslot[t + u] : -1;
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            y[u] = q[u] >= 0 ? Y[(int64_t)q[u] * kBS + c] : 0.0;
+            wq[u] = w && q[u] >= 0 ? w[q[u]] : 1.0;
         }
-    } else {
-        for (int q = sptr[j]; q < end; ++q) s += Y[(int64_t)sslot[q] * kBS + c];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) s += w ? wq[u] * y[u] : y[u];
     }
     double dn = a * s;
     if (flags & 2) dn = cd * d[t] + dn;

@@ -73,19 +73,23 @@ __global__ __launch_bounds__(kBlock) void spmv_kernel(int32_t nrows, const int32
     for (int64_t row = sub; row < nrows; row += nsub) {
         const int beg = rowptr[row], end = rowptr[row + 1];
         double s = 0.0;
-        // four entries per lane in flight (indices first, then the gathers); each
-        // lane still adds its entries k = beg + lane, + G, + 2G, ... in order
-        int k = beg + lane;
-        for (; k + 3 * G < end; k += 4 * G) {
-            const int c0 = col[k], c1 = col[k + G], c2 = col[k + 2 * G], c3 = col[k + 3 * G];
-            const double v0 = val[k], v1 = val[k + G], v2 = val[k + 2 * G], v3 = val[k + 3 * G];
-            const double x0 = x[c0], x1 = x[c1], x2 = x[c2], x3 = x[c3];
-            s += v0 * x0;
-            s += v1 * x1;
-            s += v2 * x2;
-            s += v3 * x3;
+        // four entries per lane in flight (all indices first, then all gathers,
+        // predicated at the row end); each lane still adds its entries
+        // k = beg + lane, + G, + 2G, ... in order (a missing entry adds +0)
+        for (int k = beg + lane; k < end; k += 4 * G) {
+            int c[4];
+            double v[4], xv[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const bool ok = k + u * G < end;
+                c[u] = ok ? col[k + u * G] : 0;
+                v[u] = ok ? val[k + u * G] : 0.0;
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) xv[u] = k + u * G < end ? x[c[u]] : 0.0;
+#pragma unroll
+            for (int u = 0; u < 4; ++u) s += v[u] * xv[u];
         }
-        for (; k < end; k += G) s += val[k] * x[col[k]];
 #pragma unroll
         for (int off = G / 2; off > 0; off >>= 1) s += __shfl_xor(s, off, G);
         if (lane == 0) {
@@ -611,13 +615,20 @@ __global__ __launch_bounds__(kBlock) void scatter_kernel(int32_t n, const int32_
     if (j >= n) return;
     double s = 0.0;
     const int end = sptr[j + 1];
-    if (w) {
-        for (int t = sptr[j]; t < end; ++t) {
-            const int q = sslot[t];
-            s += w[q] * Y[q];
+    // four slots in flight (indices first, then the gathers); the sum still
+    // runs over the slots in ascending order (a missing slot adds +0)
+    for (int t = sptr[j]; t < end; t += 4) {
+        int q[4];
+        double y[4], wq[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) q[u] = t + u < end ? sslot[t + u] : -1;
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            y[u] = q[u] >= 0 ? Y[q[u]] : 0.0;
+            wq[u] = w && q[u] >= 0 ? w[q[u]] : 1.0;
         }
-    } else {
-        for (int t = sptr[j]; t < end; ++t) s += Y[sslot[t]];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) s += w ? wq[u] * y[u] : y[u];
     }
     double dn = a * s;
     if (flags & 2) dn = c * d[j] + dn;

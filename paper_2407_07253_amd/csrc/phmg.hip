@@ -1151,6 +1151,20 @@ phmg_status phmg_get_level_info(phmg_ctx ctx, int level, phmg_level_info* info) 
         info->sum_m2 = L.sum_m2;
         info->lambda_max = L.lmax;
         info->apply_variant = L.apply_variant;
+        info->apply_variants = apply_variant_count(L.prec);
+        return PHMG_OK;
+    });
+}
+
+phmg_status phmg_set_apply_variant(phmg_ctx ctx, int level, int variant) {
+    return guarded([&]() -> phmg_status {
+        if (!ctx) fail(PHMG_EINVAL, "null context");
+        if (level < 0 || level >= (int)ctx->L.size() - 1) fail(PHMG_EINVAL, "level out of range");
+        Level& L = ctx->L[level];
+        if (variant < 0 || variant >= apply_variant_count(L.prec)) fail(PHMG_EINVAL, "variant out of range");
+        L.apply_variant = variant;
+        L.tuned_for = L.prec;
+        invalidate_graph(ctx);
         return PHMG_OK;
     });
 }

@@ -275,3 +275,31 @@ def test_p_coarsening_schedules_match_oracle(schedule):
     assert conv and res.converged and iters == res.iters
     assert err <= 1e-10
     H.close()
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32", "bf16"])
+def test_every_patch_solve_shape_gives_identical_sweeps(prec):
+    """All compiled kernel shapes of the patch solve (one workgroup per patch and persistent,
+    every tile / unroll choice) produce bit-identical sweeps; the f64 ones also match the oracle."""
+    from paper_2407_07253_amd._lib import Hierarchy
+    fh, _, ol, od, oopts, ob = _pair("cfg2_r1")
+    H = Hierarchy.from_frontend(fh)
+    for l in range(len(fh.levels) - 1):
+        H.set_precision(l, prec)
+    H.setup()
+    rng = np.random.default_rng(23)
+    for l in range(len(fh.levels) - 1):
+        n = fh.levels[l].n
+        b, x = rng.standard_normal(n), rng.standard_normal(n)
+        outs = []
+        for v in range(H.level_info(l)["apply_variants"]):
+            H.set_apply_variant(l, v)
+            xg = _dev(x)
+            H.relax_apply(l, _dev(b), xg, 2)
+            outs.append(_host(xg))
+        for v, o in enumerate(outs):
+            assert np.array_equal(o, outs[0]), (l, v)
+        if prec == "f64":
+            assert _rel(outs[0], omg._relax(ol[l], oopts, b, x, 2, False)) <= 1e-11
+        print(f"{prec} level {l}: {len(outs)} shapes identical")
+    H.close()

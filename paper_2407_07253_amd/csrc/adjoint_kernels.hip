@@ -49,7 +49,7 @@ __global__ __launch_bounds__(kBlock) void patch_apply_t_kernel(const int32_t* __
     const int p = order[blockIdx.x];
     const int64_t base = pptr[p];
     const int m = (int)(pptr[p + 1] - base);
-    const int ld = (m + V - 1) / V * V;
+    const int ld = (m + factor_pad<T>() - 1) / factor_pad<T>() * factor_pad<T>();
     for (int t = threadIdx.x; t < m; t += kBlock) {
         const double v = r[pdofs[base + t]];
         s_v[t] = (Acc)(w ? w[base + t] * v : v);
@@ -121,7 +121,7 @@ void launch_patch_apply_t(hipStream_t s, const Level& L, const double* r) {
     if (L.npatch <= 0) return;
     if (L.prec == PHMG_PREC_F32) launch_t_shape<float, float, 2, 4>(s, L, L.fofflp, r);
     else if (L.prec == PHMG_PREC_BF16) launch_t_shape<__hip_bfloat16, float, 4, 4>(s, L, L.fofflp, r);
-    else launch_t_shape<double, double, 1, 4>(s, L, L.foff, r);
+    else launch_t_shape<double, double, 1, 4>(s, L, L.fofflp, r);
 }
 
 void launch_pair_products(hipStream_t s, const DevCsr& K, int nrhs, const double* X, const double* Lam,

@@ -99,7 +99,7 @@ __global__ __launch_bounds__(kBlock) void spmm_kernel(int32_t nrows, const int32
 // Block patch solve.  One workgroup per patch (launch order: decreasing m).
 // The gathered right-hand sides G = X[P S_i, :] (m x 16, rows padded with
 // zeros to a multiple of 4) sit in LDS.  The stored inverse B_i (column-major,
-// leading dimension ld = m rounded up to V) is streamed once: in one k-step of
+// leading dimension ld = m rounded up to factor_pad) is streamed once: in one k-step of
 // 4 columns, lane l loads V consecutive rows of column k0 + l/16 (an 8-byte
 // load for every precision) and feeds V MFMAs, MFMA v taking the rows
 // r0 + V*i + v (i = l % 16) as its 16-row A tile; the B operand is G[k0 + l/16]
@@ -171,7 +171,7 @@ __global__ __launch_bounds__(kBlock) void block_apply_kernel(const int32_t* __re
     const int64_t base = pptr[p];
     const int m = (int)(pptr[p + 1] - base);
     const int mpad = (m + 3) & ~3;
-    const int ld = (m + V - 1) / V * V;
+    const int ld = (m + factor_pad<T>() - 1) / factor_pad<T>() * factor_pad<T>();
     for (int t = threadIdx.x; t < mpad * kBS; t += kBlock) {
         const int l = t / kBS, c = t % kBS;
         s_g[t] = l < m ? (Acc)X[(int64_t)pdofs[base + l] * kBS + c] : (Acc)0;
@@ -483,10 +483,10 @@ void launch_block_apply(hipStream_t s, const Level& L, const double* X) {
         }
     } else {
         switch (v) {
-            case 1: launch_block_shape<double, double, 1, 2, 4>(s, L, L.foff, X); break;
-            case 2: launch_block_shape<double, double, 1, 1, 8>(s, L, L.foff, X); break;
-            case 3: launch_block_shape<double, double, 1, 4, 2>(s, L, L.foff, X); break;
-            default: launch_block_shape<double, double, 1, 1, 4>(s, L, L.foff, X);
+            case 1: launch_block_shape<double, double, 1, 2, 4>(s, L, L.fofflp, X); break;
+            case 2: launch_block_shape<double, double, 1, 1, 8>(s, L, L.fofflp, X); break;
+            case 3: launch_block_shape<double, double, 1, 4, 2>(s, L, L.fofflp, X); break;
+            default: launch_block_shape<double, double, 1, 1, 4>(s, L, L.fofflp, X);
         }
     }
 }

@@ -359,7 +359,8 @@ __global__ __launch_bounds__(kBlock) void gj_kernel(const int64_t* __restrict__ 
 }
 
 // f64 set-up result (column-major, ld = m) -> reduced-precision factors with
-// ld = m rounded up to V (padding rows are zero); one workgroup per patch.
+// ld = m rounded up to V = factor_pad<T>() (padding rows are zero); one
+// workgroup per patch.
 template <typename T, int V>
 __global__ __launch_bounds__(kBlock) void convert_patch_kernel(const int64_t* __restrict__ pptr,
                                                                const int64_t* __restrict__ foff64,
@@ -374,7 +375,8 @@ __global__ __launch_bounds__(kBlock) void convert_patch_kernel(const int64_t* __
     for (int64_t e = threadIdx.x; e < total; e += kBlock) {
         const int i = (int)(e % ld), j = (int)(e / ld);
         const double v = i < m ? a[i + (int64_t)j * m] : 0.0;
-        if constexpr (sizeof(T) == 4) b[e] = (T)v;
+        if constexpr (sizeof(T) == 8) b[e] = v;
+        else if constexpr (sizeof(T) == 4) b[e] = (T)v;
         else b[e] = __float2bfloat16((float)v);
     }
 }
@@ -827,11 +829,14 @@ void launch_patch_factor(hipStream_t s, const Level& L, double* A) {
 
 void launch_convert_patches(hipStream_t s, const Level& L, const double* src, void* dst) {
     if (L.npatch <= 0) return;
-    if (L.prec == PHMG_PREC_F32)
-        hipLaunchKernelGGL((convert_patch_kernel<float, 2>), dim3(L.npatch), dim3(kBlock), 0, s, L.pptr, L.foff,
+    if (L.prec == PHMG_PREC_F64)
+        hipLaunchKernelGGL((convert_patch_kernel<double, factor_pad<double>()>), dim3(L.npatch), dim3(kBlock), 0, s,
+                           L.pptr, L.foff, L.fofflp, src, (double*)dst);
+    else if (L.prec == PHMG_PREC_F32)
+        hipLaunchKernelGGL((convert_patch_kernel<float, factor_pad<float>()>), dim3(L.npatch), dim3(kBlock), 0, s, L.pptr, L.foff,
                            L.fofflp, src, (float*)dst);
     else if (L.prec == PHMG_PREC_BF16)
-        hipLaunchKernelGGL((convert_patch_kernel<__hip_bfloat16, 4>), dim3(L.npatch), dim3(kBlock), 0, s, L.pptr,
+        hipLaunchKernelGGL((convert_patch_kernel<__hip_bfloat16, factor_pad<__hip_bfloat16>()>), dim3(L.npatch), dim3(kBlock), 0, s, L.pptr,
                            L.foff, L.fofflp, src, (__hip_bfloat16*)dst);
 }
 

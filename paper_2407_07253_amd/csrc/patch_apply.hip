@@ -2,6 +2,11 @@
 // eq. "eq:ASM"): y_i = K_i^{-1} r[S_i] for every Vanka-star patch, streaming the
 // explicit patch inverses stored by the set-up.  This is the dominant kernel of
 // the solve phase (HBM-bound: every factor word is read once per sweep).
+//
+// Layout: patch i's inverse B_i = (P_i K_i)^{-1} is column-major with every
+// column padded to a multiple of 16 bytes (ld = m rounded up to V = 2 / 4 / 8
+// rows for f64 / f32 / bf16); the gather list pdofs_perm already applies the
+// pivot permutation, so y_i = B_i r[pdofs_perm(i)].
 #include <hip/hip_bf16.h>
 #include <hip/hip_runtime.h>
 
@@ -13,259 +18,150 @@
 namespace phmg {
 namespace {
 
-// ---------------------------------------------------------------------------
-// Batched patch solve: y_i = K_i^{-1} r[S_i].  One workgroup per patch; the
-// gathered residual sits in LDS.  Each wavefront streams the columns j = w,
-// w+4, w+8, ... of the stored inverse (column-major, leading dimension ld =
-// m rounded up to V), every lane owning V consecutive rows of up to NRT row
-// tiles, so a wave-load is always 64 x 8 bytes and four columns are in flight
-// per wave.  The four per-wave partial sums are combined in LDS once per
-// group of NRT row tiles.
-// ---------------------------------------------------------------------------
-template <typename T, int V>
-struct FactorLoad;
+// One 16-byte load of V consecutive factor rows, widened to the accumulation type.
+template <typename T>
+struct Load16;
 template <>
-struct FactorLoad<double, 1> {
-    __device__ static inline void load(const double* p, double (&a)[1]) { a[0] = *p; }
-};
-template <>
-struct FactorLoad<float, 2> {
-    __device__ static inline void load(const float* p, float (&a)[2]) {
-        const float2 v = *reinterpret_cast<const float2*>(p);
+struct Load16<double> {
+    static constexpr int V = 2;
+    typedef double acc_t;
+    __device__ static inline void load(const double* p, double (&a)[2]) {
+        const double2 v = *reinterpret_cast<const double2*>(p);
         a[0] = v.x;
         a[1] = v.y;
     }
 };
 template <>
-struct FactorLoad<__hip_bfloat16, 4> {
-    __device__ static inline void load(const __hip_bfloat16* p, float (&a)[4]) {
-        const uint2 v = *reinterpret_cast<const uint2*>(p);
-        a[0] = __uint_as_float(v.x << 16);
-        a[1] = __uint_as_float(v.x & 0xffff0000u);
-        a[2] = __uint_as_float(v.y << 16);
-        a[3] = __uint_as_float(v.y & 0xffff0000u);
+struct Load16<float> {
+    static constexpr int V = 4;
+    typedef float acc_t;
+    __device__ static inline void load(const float* p, float (&a)[4]) {
+        const float4 v = *reinterpret_cast<const float4*>(p);
+        a[0] = v.x;
+        a[1] = v.y;
+        a[2] = v.z;
+        a[3] = v.w;
+    }
+};
+template <>
+struct Load16<__hip_bfloat16> {
+    static constexpr int V = 8;
+    typedef float acc_t;
+    __device__ static inline void load(const __hip_bfloat16* p, float (&a)[8]) {
+        const uint4 v = *reinterpret_cast<const uint4*>(p);
+        const uint32_t w[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+        for (int h = 0; h < 4; ++h) {
+            a[2 * h] = __uint_as_float(w[h] << 16);
+            a[2 * h + 1] = __uint_as_float(w[h] & 0xffff0000u);
+        }
     }
 };
 
-// Stream one patch: Y[i] = sum_j B[i, j] s_r[j] for the patch's m rows (the
-// gathered right-hand side s_r in LDS, B column-major with leading dimension ld).
-template <typename T, typename Acc, int V, int NRT, int U>
-__device__ inline void stream_patch(const T* __restrict__ A, int m, int ld, const Acc* s_r,
-                                    Acc (&s_red)[NRT][kBlock / kWave][kWave * V], double* __restrict__ Yp) {
-    constexpr int NW = kBlock / kWave;
-    constexpr int TILE = kWave * V;
-    const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
-    for (int r0 = 0; r0 < m; r0 += NRT * TILE) {
-        Acc acc[NRT][V];
-#pragma unroll
-        for (int q = 0; q < NRT; ++q)
-#pragma unroll
-            for (int v = 0; v < V; ++v) acc[q][v] = 0;
-        int j = wave;
-        for (; j + (U - 1) * NW < m; j += U * NW) {
-            Acc a[U][NRT][V];
-#pragma unroll
-            for (int u = 0; u < U; ++u) {
-                const T* col = A + (int64_t)(j + u * NW) * ld + r0 + lane * V;
-#pragma unroll
-                for (int q = 0; q < NRT; ++q) {
-                    if (r0 + q * TILE + lane * V < m) FactorLoad<T, V>::load(col + q * TILE, a[u][q]);
-                    else
-#pragma unroll
-                        for (int v = 0; v < V; ++v) a[u][q][v] = 0;
-                }
-            }
-#pragma unroll
-            for (int u = 0; u < U; ++u) {
-                const Acc rj = s_r[j + u * NW];
-#pragma unroll
-                for (int q = 0; q < NRT; ++q)
-#pragma unroll
-                    for (int v = 0; v < V; ++v) acc[q][v] += a[u][q][v] * rj;
-            }
-        }
-        for (; j < m; j += NW) {
-            const T* col = A + (int64_t)j * ld + r0 + lane * V;
-            const Acc rj = s_r[j];
-#pragma unroll
-            for (int q = 0; q < NRT; ++q) {
-                if (r0 + q * TILE + lane * V < m) {
-                    Acc a[V];
-                    FactorLoad<T, V>::load(col + q * TILE, a);
-#pragma unroll
-                    for (int v = 0; v < V; ++v) acc[q][v] += a[v] * rj;
-                }
-            }
-        }
-#pragma unroll
-        for (int q = 0; q < NRT; ++q)
-#pragma unroll
-            for (int v = 0; v < V; ++v) s_red[q][wave][lane * V + v] = acc[q][v];
-        __syncthreads();
-        for (int t = threadIdx.x; t < NRT * TILE; t += kBlock) {
-            const int i = r0 + t;
-            if (i < m) {
-                const int q = t / TILE, e = t % TILE;
-                Yp[i] = (double)((s_red[q][0][e] + s_red[q][1][e]) + (s_red[q][2][e] + s_red[q][3][e]));
-            }
-        }
-        __syncthreads();
-    }
-}
-
-// One workgroup per patch.
-template <typename T, typename Acc, int V, int NRT, int U>
+// One workgroup per patch (launch order: decreasing m).  The patch's columns
+// are cut into row groups of V rows (one 16-byte load each); with LPC row
+// groups per column, thread t < S = LPC * (256 / LPC) owns row group t % LPC of
+// the columns t / LPC, t / LPC + 256 / LPC, ... so the workgroup's loads form
+// one contiguous stream (no idle lanes inside short columns) with U loads in
+// flight per thread.  Columns taller than 256 row groups are processed in
+// chunks of 256 groups.  Each thread sums its columns in ascending order; the
+// 256 / LPC partial sums of a row are then added in ascending thread order, so
+// the result does not depend on U (every compiled shape is bit-identical).
+template <typename T, int U>
 __global__ __launch_bounds__(kBlock) void patch_apply_kernel(const int32_t* __restrict__ order,
                                                              const int64_t* __restrict__ pptr,
                                                              const int32_t* __restrict__ pdofs,
                                                              const int64_t* __restrict__ foff,
                                                              const T* __restrict__ F, const double* __restrict__ r,
-                                                             double* __restrict__ Y) {
+                                                             double* __restrict__ Y, int ldbuf) {
+    typedef typename Load16<T>::acc_t Acc;
+    constexpr int V = Load16<T>::V;
+    static_assert(V == factor_pad<T>(), "columns are padded to one 16-byte load");
     extern __shared__ double s_buf[];
     Acc* s_r = reinterpret_cast<Acc*>(s_buf);
-    __shared__ Acc s_red[NRT][kBlock / kWave][kWave * V];
+    Acc* s_part = s_r + ldbuf;                                    // kBlock * V partial sums
     const int p = order[blockIdx.x];
     const int64_t base = pptr[p];
     const int m = (int)(pptr[p + 1] - base);
     const int ld = (m + V - 1) / V * V;
     for (int t = threadIdx.x; t < m; t += kBlock) s_r[t] = (Acc)r[pdofs[base + t]];
     __syncthreads();
-    stream_patch<T, Acc, V, NRT, U>(F + foff[p], m, ld, s_r, s_red, Y + base);
-}
-
-// Persistent form: a grid sized to the resident workgroups; workgroup b takes
-// the patches order[b], order[b + G], ... (largest first, so every workgroup
-// gets a similar mix of sizes).  The gather of the next patch's right-hand
-// side is issued into registers before the current patch is streamed (its
-// latency hides behind the stream) and lands in the second LDS buffer.
-template <typename T, typename Acc, int V, int NRT, int U, int R>
-__global__ __launch_bounds__(kBlock) void patch_apply_persist_kernel(int npatch, const int32_t* __restrict__ order,
-                                                                     const int64_t* __restrict__ pptr,
-                                                                     const int32_t* __restrict__ pdofs,
-                                                                     const int64_t* __restrict__ foff,
-                                                                     const T* __restrict__ F,
-                                                                     const double* __restrict__ r,
-                                                                     double* __restrict__ Y, int ldbuf) {
-    extern __shared__ double s_buf[];
-    Acc* s_buf0 = reinterpret_cast<Acc*>(s_buf);
-    Acc* s_buf1 = s_buf0 + ldbuf;
-    __shared__ Acc s_red[NRT][kBlock / kWave][kWave * V];
-    int idx = blockIdx.x;
-    if (idx >= npatch) return;
-    int p = order[idx];
-    int64_t base = pptr[p];
-    int m = (int)(pptr[p + 1] - base);
-    for (int t = threadIdx.x; t < m; t += kBlock) s_buf0[t] = (Acc)r[pdofs[base + t]];
-    __syncthreads();
-    int cur = 0;
-    for (;;) {
-        const int nidx = idx + (int)gridDim.x;
-        int pn = -1, mn = 0;
-        int64_t basen = 0;
-        Acc pre[R];
-        if (nidx < npatch) {
-            pn = order[nidx];
-            basen = pptr[pn];
-            mn = (int)(pptr[pn + 1] - basen);
+    const T* A = F + foff[p];
+    const int groups = ld / V;
+    for (int g0 = 0; g0 < groups; g0 += kBlock) {
+        const int lpc = min(groups - g0, kBlock);
+        const int cps = kBlock / lpc;                             // columns per sweep of the workgroup
+        const int t = threadIdx.x;
+        const int rg = t % lpc, c0 = t / lpc;
+        Acc acc[V];
 #pragma unroll
-            for (int u = 0; u < R; ++u) {
-                const int t = threadIdx.x + u * kBlock;
-                pre[u] = t < mn ? (Acc)r[pdofs[basen + t]] : (Acc)0;
+        for (int v = 0; v < V; ++v) acc[v] = 0;
+        if (c0 < cps) {
+            const T* colbase = A + (int64_t)(g0 + rg) * V;
+            int j = c0;
+            for (; j + (U - 1) * cps < m; j += U * cps) {
+                Acc a[U][V];
+#pragma unroll
+                for (int u = 0; u < U; ++u) Load16<T>::load(colbase + (int64_t)(j + u * cps) * ld, a[u]);
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    const Acc rj = s_r[j + u * cps];
+#pragma unroll
+                    for (int v = 0; v < V; ++v) acc[v] += a[u][v] * rj;
+                }
+            }
+            for (; j < m; j += cps) {
+                Acc a[V];
+                Load16<T>::load(colbase + (int64_t)j * ld, a);
+                const Acc rj = s_r[j];
+#pragma unroll
+                for (int v = 0; v < V; ++v) acc[v] += a[v] * rj;
             }
         }
-        const int ld = (m + V - 1) / V * V;
-        stream_patch<T, Acc, V, NRT, U>(F + foff[p], m, ld, cur ? s_buf1 : s_buf0, s_red, Y + base);
-        if (pn < 0) break;
-        Acc* s_next = cur ? s_buf0 : s_buf1;
 #pragma unroll
-        for (int u = 0; u < R; ++u) {
-            const int t = threadIdx.x + u * kBlock;
-            if (t < mn) s_next[t] = pre[u];
+        for (int v = 0; v < V; ++v) s_part[t * V + v] = acc[v];
+        __syncthreads();
+        for (int i = threadIdx.x; i < lpc * V; i += kBlock) {
+            const int g = i / V, v = i % V;
+            const int row = (g0 + g) * V + v;
+            if (row < m) {
+                Acc sum = 0;
+                for (int c = 0; c < cps; ++c) sum += s_part[(c * lpc + g) * V + v];
+                Y[base + row] = (double)sum;
+            }
         }
         __syncthreads();
-        idx = nidx;
-        p = pn;
-        base = basen;
-        m = mn;
-        cur ^= 1;
     }
 }
 
-}  // namespace
-
-// Kernel shapes the set-up autotuner chooses from, per precision:
-// (row tiles held per pass NRT, columns in flight per wave U), one workgroup
-// per patch or persistent.
-namespace {
-template <typename T, typename Acc, int V, int NRT, int U>
-void launch_apply_shape(hipStream_t s, const Level& L, const int64_t* off, const double* r) {
-    hipLaunchKernelGGL((patch_apply_kernel<T, Acc, V, NRT, U>), dim3(L.npatch), dim3(kBlock), sizeof(Acc) * L.max_m, s,
-                       L.order, L.pptr, L.pdofs_perm, off, (const T*)L.factors, r, L.Y);
-}
-
-template <typename T, typename Acc, int V, int NRT, int U, int R>
-void launch_persist_r(hipStream_t s, const Level& L, const int64_t* off, const double* r) {
+// Shapes the set-up autotuner chooses from: U loads in flight per thread.
+template <typename T, int U>
+void launch_shape(hipStream_t s, const Level& L, const double* r) {
+    typedef typename Load16<T>::acc_t Acc;
     const int ldbuf = (L.max_m + 1) & ~1;
-    const size_t lds = 2 * sizeof(Acc) * (size_t)ldbuf;
-    auto kernel = patch_apply_persist_kernel<T, Acc, V, NRT, U, R>;
-    static int resident = 0;                          // workgroups resident on the whole GPU
-    if (resident == 0) {
-        int per_cu = 0, ncu = 0, dev = 0;
-        (void)hipGetDevice(&dev);
-        (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
-        (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)kernel, kBlock, lds);
-        resident = std::max(1, per_cu) * std::max(1, ncu);
-    }
-    const int grid = std::min(L.npatch, resident);
-    hipLaunchKernelGGL(kernel, dim3(grid), dim3(kBlock), lds, s, L.npatch, L.order, L.pptr, L.pdofs_perm, off,
-                       (const T*)L.factors, r, L.Y, ldbuf);
+    const size_t lds = sizeof(Acc) * ((size_t)ldbuf + (size_t)kBlock * Load16<T>::V);
+    hipLaunchKernelGGL((patch_apply_kernel<T, U>), dim3(L.npatch), dim3(kBlock), lds, s, L.order, L.pptr,
+                       L.pdofs_perm, L.fofflp, (const T*)L.factors, r, L.Y, ldbuf);
 }
 
-template <typename T, typename Acc, int V, int NRT, int U>
-void launch_persist_shape(hipStream_t s, const Level& L, const int64_t* off, const double* r) {
-    const int R = (L.max_m + kBlock - 1) / kBlock;
-    if (R <= 1) launch_persist_r<T, Acc, V, NRT, U, 1>(s, L, off, r);
-    else if (R <= 2) launch_persist_r<T, Acc, V, NRT, U, 2>(s, L, off, r);
-    else launch_persist_r<T, Acc, V, NRT, U, 4>(s, L, off, r);
+template <typename T>
+void launch_typed(hipStream_t s, const Level& L, const double* r) {
+    switch (L.apply_variant) {
+        case 1: launch_shape<T, 2>(s, L, r); break;
+        case 2: launch_shape<T, 8>(s, L, r); break;
+        default: launch_shape<T, 4>(s, L, r);
+    }
 }
+
 }  // namespace
 
-int apply_variant_count(int prec) { return prec == PHMG_PREC_F64 ? 9 : 6; }
+int apply_variant_count(int /*prec*/) { return 3; }
 
 void launch_patch_apply(hipStream_t s, const Level& L, const double* r) {
     if (L.npatch <= 0) return;
-    const int v = L.apply_variant;
-    if (L.prec == PHMG_PREC_F32) {
-        switch (v) {
-            case 1: launch_apply_shape<float, float, 2, 1, 8>(s, L, L.fofflp, r); break;
-            case 2: launch_apply_shape<float, float, 2, 2, 2>(s, L, L.fofflp, r); break;
-            case 3: launch_apply_shape<float, float, 2, 1, 4>(s, L, L.fofflp, r); break;
-            case 4: launch_persist_shape<float, float, 2, 2, 4>(s, L, L.fofflp, r); break;
-            case 5: launch_persist_shape<float, float, 2, 1, 8>(s, L, L.fofflp, r); break;
-            default: launch_apply_shape<float, float, 2, 2, 4>(s, L, L.fofflp, r);
-        }
-    } else if (L.prec == PHMG_PREC_BF16) {
-        switch (v) {
-            case 1: launch_apply_shape<__hip_bfloat16, float, 4, 1, 8>(s, L, L.fofflp, r); break;
-            case 2: launch_apply_shape<__hip_bfloat16, float, 4, 1, 2>(s, L, L.fofflp, r); break;
-            case 3: launch_apply_shape<__hip_bfloat16, float, 4, 2, 4>(s, L, L.fofflp, r); break;
-            case 4: launch_persist_shape<__hip_bfloat16, float, 4, 1, 4>(s, L, L.fofflp, r); break;
-            case 5: launch_persist_shape<__hip_bfloat16, float, 4, 1, 8>(s, L, L.fofflp, r); break;
-            default: launch_apply_shape<__hip_bfloat16, float, 4, 1, 4>(s, L, L.fofflp, r);
-        }
-    } else {
-        switch (v) {
-            case 1: launch_apply_shape<double, double, 1, 3, 4>(s, L, L.foff, r); break;
-            case 2: launch_apply_shape<double, double, 1, 2, 4>(s, L, L.foff, r); break;
-            case 3: launch_apply_shape<double, double, 1, 4, 2>(s, L, L.foff, r); break;
-            case 4: launch_apply_shape<double, double, 1, 1, 8>(s, L, L.foff, r); break;
-            case 5: launch_apply_shape<double, double, 1, 3, 2>(s, L, L.foff, r); break;
-            case 6: launch_persist_shape<double, double, 1, 4, 4>(s, L, L.foff, r); break;
-            case 7: launch_persist_shape<double, double, 1, 3, 4>(s, L, L.foff, r); break;
-            case 8: launch_persist_shape<double, double, 1, 2, 4>(s, L, L.foff, r); break;
-            default: launch_apply_shape<double, double, 1, 4, 4>(s, L, L.foff, r);
-        }
-    }
+    if (L.prec == PHMG_PREC_F32) launch_typed<float>(s, L, r);
+    else if (L.prec == PHMG_PREC_BF16) launch_typed<__hip_bfloat16>(s, L, r);
+    else launch_typed<double>(s, L, r);
 }
 
 }  // namespace phmg

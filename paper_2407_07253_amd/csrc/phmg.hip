@@ -494,22 +494,23 @@ void setup_level(phmg_ctx ctx, int l) {
         launch_patch_factor(s, L, f64);
         hipcheck(hipGetLastError(), "patch factorisation launch");
     }
-    if (L.prec == PHMG_PREC_F64) {
-        L.factors = f64;
-    } else {
-        const size_t es = L.prec == PHMG_PREC_F32 ? 4 : 2;
+    {
+        // the stored inverses: columns padded to 16 bytes, in the level's precision
+        const size_t es = L.prec == PHMG_PREC_F64 ? 8 : (L.prec == PHMG_PREC_F32 ? 4 : 2);
         const int64_t cnt = L.sum_lp[L.prec];
         std::vector<int64_t> off(L.npatch);
         {
             std::vector<int64_t> hp(L.npatch + 1);
             hipcheck(hipMemcpy(hp.data(), L.pptr, sizeof(int64_t) * (L.npatch + 1), hipMemcpyDeviceToHost), "D2H");
-            const int V = L.prec == PHMG_PREC_F32 ? 2 : 4;
+            const int V = factor_pad_of(L.prec);
             int64_t acc = 0;
             for (int32_t i = 0; i < L.npatch; ++i) {
                 const int64_t m = hp[i + 1] - hp[i];
                 off[i] = acc;
                 acc += (m + V - 1) / V * V * m;
             }
+            // the allocation below is sized at create (sum_lp); the layout must match it exactly
+            if (acc != cnt) fail(PHMG_EINVAL, lvl(l) + "internal: reduced-precision layout size mismatch");
         }
         if (L.fofflp) dfree(ctx, L.fofflp);
         L.fofflp = upload(ctx, off.data(), L.npatch);
@@ -525,7 +526,7 @@ void setup_level(phmg_ctx ctx, int l) {
     }
     hipcheck(hipMemcpyAsync(&st, L.status, sizeof(int32_t), hipMemcpyDeviceToHost, s), "D2H");
     hipcheck(hipStreamSynchronize(s), "hipStreamSynchronize");
-    if (L.prec != PHMG_PREC_F64) dfree(ctx, f64);
+    dfree(ctx, f64);
     if (st != INT32_MAX) fail(PHMG_ESINGULAR, lvl(l) + "patch " + std::to_string(st) + " is singular");
     tune_apply(ctx, l);
     if (ctx->opts.smoother == PHMG_SMOOTHER_CHEBYSHEV) {
@@ -807,11 +808,12 @@ phmg_status phmg_hierarchy_create(const phmg_hierarchy_desc* desc, const phmg_cy
                 }
                 L.sum_m2 = acc;
                 L.max_m = mx;
-                L.sum_lp[0] = acc;
                 for (int32_t i = 0; i < pt.npatch; ++i) {
                     const int64_t m = pt.ptr[i + 1] - pt.ptr[i];
-                    L.sum_lp[1] += (m + 1) / 2 * 2 * m;
-                    L.sum_lp[2] += (m + 3) / 4 * 4 * m;
+                    for (int pr = PHMG_PREC_F64; pr <= PHMG_PREC_BF16; ++pr) {
+                        const int V = factor_pad_of(pr);
+                        L.sum_lp[pr] += (m + V - 1) / V * V * m;
+                    }
                 }
                 std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) {
                     return pt.ptr[a + 1] - pt.ptr[a] > pt.ptr[b + 1] - pt.ptr[b];

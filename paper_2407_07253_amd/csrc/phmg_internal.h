@@ -18,6 +18,14 @@ constexpr int kPanel = 16;           // Gauss-Jordan panel width = MFMA f64 16x1
 constexpr int kRedBlocks = 512;      // fixed grid of the deterministic reductions
 constexpr int kBS = 16;              // columns of a block vector (right-hand sides solved together)
 
+// Leading dimension padding of the stored patch inverses: every column is
+// padded to a multiple of 16 bytes (f64: 2 rows, f32: 4, bf16: 8; padding rows
+// are zero) so the kernels issue aligned 16-byte loads.  (The set-up's own
+// float64 work buffer is unpadded, m x m.)
+template <typename T>
+__host__ __device__ constexpr int factor_pad() { return 16 / (int)sizeof(T); }
+inline int factor_pad_of(int prec) { return prec == PHMG_PREC_F64 ? 2 : (prec == PHMG_PREC_F32 ? 4 : 8); }
+
 struct DevCsr {
     int32_t nrows = 0, ncols = 0;
     int64_t nnz = 0;
@@ -49,9 +57,9 @@ struct Level {
     int32_t* pidx = nullptr;         // sum_m: the pivoting permutation as local positions (P r)_t = r[pidx[t]]
     double* ptol = nullptr;          // npatch: singularity threshold 1e-14 ||K_i||_inf
     double* pweight = nullptr;       // sum_m or null (W_i = I)
-    int64_t* foff = nullptr;         // offset of patch i's m_i x m_i block (elements, float64 layout)
-    int64_t* fofflp = nullptr;       // offsets of the reduced-precision layout (ld = m rounded up to 2 / 4)
-    int64_t sum_lp[3] = {0, 0, 0};   // element counts of the f64 / f32 / bf16 layouts
+    int64_t* foff = nullptr;         // offset of patch i's m_i x m_i block in the set-up buffer (ld = m)
+    int64_t* fofflp = nullptr;       // offsets of the stored inverses (ld = m rounded up to factor_pad)
+    int64_t sum_lp[3] = {0, 0, 0};   // element counts of the stored f64 / f32 / bf16 layouts
     int32_t* order = nullptr;        // launch order: patches by decreasing size
     int32_t* sptr = nullptr;         // DoF -> slot map for the scatter (n + 1)
     int32_t* sslot = nullptr;        // sum_m slot indices, ascending patch id per DoF

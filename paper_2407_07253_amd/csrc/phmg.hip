@@ -275,15 +275,18 @@ double arnoldi_estimate(phmg_ctx ctx, int l) {
     ensure_krylov(ctx, std::max(ctx->kry.cap, k));
     double* V = ctx->kry.V;
     double* w = ctx->kry.w;
-    const int stride = ctx->kry.cap + 2;
-    double* h1 = ctx->kry.hdev;
-    double* h2 = ctx->kry.hdev + stride;
-    double* hn2 = ctx->kry.hdev + 2 * stride;
+    // every step's projections stay on the device (one column of S doubles per
+    // step: h, h', ||w||^2); the next basis vector is normalised with the
+    // device norm, and the host reads all columns once at the end
+    const int S = 2 * (k + 1) + 1;
+    double* Hd = dalloc<double>(ctx, (int64_t)S * k);
     launch_power_start(s, n, V);
     launch_multidot(s, n, 1, V, n, V, ctx->kry.partial, ctx->scal, false);
     launch_scale_by_devnorm(s, n, V, ctx->scal, V);
-    std::vector<double> H((size_t)(k + 1) * k, 0.0);
     for (int j = 0; j < k; ++j) {
+        double* h1 = Hd + (int64_t)j * S;
+        double* h2 = h1 + (k + 1);
+        double* hn2 = h1 + 2 * (k + 1);
         launch_spmv(s, L.K, V + (int64_t)j * n, 1.0, nullptr, 0.0, L.r);
         launch_patch_apply(s, L, L.r);
         launch_scatter(s, L, 1.0, 0.0, nullptr, false, w, true);
@@ -292,19 +295,25 @@ double arnoldi_estimate(phmg_ctx ctx, int l) {
         launch_multidot(s, n, j + 1, V, n, w, ctx->kry.partial, h2, false);
         launch_gemv_sub(s, n, j + 1, V, n, h2, w);
         launch_multidot(s, n, 1, w, n, w, ctx->kry.partial, hn2, false);
-        hipcheck(hipMemcpyAsync(ctx->kry.hhost, ctx->kry.hdev, sizeof(double) * (2 * stride + 1), hipMemcpyDeviceToHost, s),
-                 "D2H");
-        hipcheck(hipStreamSynchronize(s), "hipStreamSynchronize");
-        for (int i = 0; i <= j; ++i) H[(size_t)j * (k + 1) + i] = ctx->kry.hhost[i] + ctx->kry.hhost[stride + i];
-        const double hn = std::sqrt(ctx->kry.hhost[2 * stride]);
+        if (j + 1 < k) launch_scale_by_devnorm(s, n, w, hn2, V + (int64_t)(j + 1) * n);
+    }
+    std::vector<double> hcols((size_t)S * k);
+    hipcheck(hipMemcpyAsync(hcols.data(), Hd, sizeof(double) * S * k, hipMemcpyDeviceToHost, s), "D2H");
+    hipcheck(hipStreamSynchronize(s), "hipStreamSynchronize");
+    dfree(ctx, Hd);
+    std::vector<double> H((size_t)(k + 1) * k, 0.0);
+    int kk = k;
+    for (int j = 0; j < k; ++j) {
+        const double* c = hcols.data() + (size_t)j * S;
+        for (int i = 0; i <= j; ++i) H[(size_t)j * (k + 1) + i] = c[i] + c[(k + 1) + i];
+        const double hn = std::sqrt(c[2 * (k + 1)]);
         H[(size_t)j * (k + 1) + j + 1] = hn;
-        if (hn == 0.0) {
-            k = j + 1;
+        if (hn == 0.0) {                 // exact breakdown: later columns are not used
+            kk = j + 1;
             break;
         }
-        if (j + 1 < k) launch_scale_copy(s, n, w, hn, V + (int64_t)(j + 1) * n);
     }
-    return ritz_max_real(H.data(), k + 1, k);
+    return ritz_max_real(H.data(), k + 1, kk);      // leading dimension k + 1, order kk
 }
 
 // One cycle on level l.  transpose gives the adjoint operator B^T: the same
@@ -568,7 +577,9 @@ void ensure_krylov(phmg_ctx owner, Krylov& kr, int64_t n, int restart) {
         kr.partial = dalloc<double>(owner, (int64_t)kRedBlocks * (restart + 2));
         kr.partial_cols = restart + 2;
     }
-    hipcheck(hipHostMalloc((void**)&kr.hhost, sizeof(double) * (2 * (restart + 2) + 4)), "hipHostMalloc");
+    hipcheck(hipHostMalloc((void**)&kr.hhost, sizeof(double) * 2 * (2 * (restart + 2) + 4)), "hipHostMalloc");
+    for (auto& e : kr.ev)
+        if (!e) hipcheck(hipEventCreateWithFlags(&e, hipEventDisableTiming), "hipEventCreate");
     kr.cap = restart;
     kr.n = n;
 }
@@ -578,7 +589,12 @@ void ensure_krylov(phmg_ctx ctx, int restart) { ensure_krylov(ctx, ctx->kry, ctx
 // Restarted FGMRES (the reading of the solver paragraph of Section 4; see the
 // ABI notes): matvec(x, alpha, z, beta, y) forms y = alpha A x + beta z,
 // precond(v, z) forms z = B v.  CGS2 on the device, Hessenberg and Givens on
-// the host, one device-to-host copy per iteration.
+// the host.  The next basis vector is normalised with the device norm, so the
+// GPU work of iteration j + 1 is enqueued before the host waits for the
+// projections of iteration j (one iteration of look-ahead): the host's Givens
+// step and the copy latency overlap GPU work.  When iteration j ends the cycle
+// the look-ahead iteration's results are simply not used (its writes go to
+// Z_{j+1}, V_{j+2}, w and the scalar slots only).
 template <class MatVec, class Prec>
 phmg_status fgmres_core(hipStream_t s, Krylov& kr, int64_t n, MatVec matvec, Prec precond, const double* b,
                         double* x, double rtol, int restart, int maxit, int* iters_out, double* relres_out) {
@@ -586,6 +602,8 @@ phmg_status fgmres_core(hipStream_t s, Krylov& kr, int64_t n, MatVec matvec, Pre
     double* Z = kr.Z;
     double* w = kr.w;
     double* r = kr.r;
+    const int hs = 2 * (restart + 2) + 1;        // scalars copied per iteration
+    const int slot = 2 * (kr.cap + 2) + 4;       // host slot stride
     double* h1 = kr.hdev;
     double* h2 = kr.hdev + (restart + 2);
     double* hn2 = kr.hdev + 2 * (restart + 2);
@@ -603,6 +621,23 @@ phmg_status fgmres_core(hipStream_t s, Krylov& kr, int64_t n, MatVec matvec, Pre
     bool converged = false;
     std::vector<double> H((restart + 1) * restart), cs(restart), sn(restart), g(restart + 1), y(restart);
     auto Hij = [&](int i, int j) -> double& { return H[(size_t)j * (restart + 1) + i]; };
+    // enqueue the GPU work of iteration j: Z_j = B V_j, w = A Z_j, CGS2 projections,
+    // copy to host slot j % 2, V_{j+1} = w / ||w|| (when a further basis vector exists)
+    auto issue = [&](int j) {
+        double* vj = V + (int64_t)j * n;
+        double* zj = Z + (int64_t)j * n;
+        precond(vj, zj);
+        matvec(zj, 1.0, nullptr, 0.0, w);
+        launch_multidot(s, n, j + 1, V, n, w, kr.partial, h1, false);
+        launch_gemv_sub(s, n, j + 1, V, n, h1, w);
+        launch_multidot(s, n, j + 1, V, n, w, kr.partial, h2, false);
+        launch_gemv_sub(s, n, j + 1, V, n, h2, w);
+        launch_multidot(s, n, 1, w, n, w, kr.partial, hn2, false);
+        hipcheck(hipMemcpyAsync(kr.hhost + (j & 1) * slot, kr.hdev, sizeof(double) * hs, hipMemcpyDeviceToHost, s),
+                 "D2H");
+        hipcheck(hipEventRecord(kr.ev[j & 1], s), "hipEventRecord");
+        if (j + 1 <= restart - 1) launch_scale_by_devnorm(s, n, w, hn2, V + (int64_t)(j + 1) * n);
+    };
     for (;;) {
         std::fill(H.begin(), H.end(), 0.0);
         std::fill(g.begin(), g.end(), 0.0);
@@ -610,23 +645,13 @@ phmg_status fgmres_core(hipStream_t s, Krylov& kr, int64_t n, MatVec matvec, Pre
         launch_scale_copy(s, n, r, beta, V);
         int ncols = 0;
         double hn = 0.0;
+        issue(0);
         for (int j = 0; j < restart; ++j) {
-            double* vj = V + (int64_t)j * n;
-            double* zj = Z + (int64_t)j * n;
-            precond(vj, zj);
-            matvec(zj, 1.0, nullptr, 0.0, w);
-            launch_multidot(s, n, j + 1, V, n, w, kr.partial, h1, false);
-            launch_gemv_sub(s, n, j + 1, V, n, h1, w);
-            launch_multidot(s, n, j + 1, V, n, w, kr.partial, h2, false);
-            launch_gemv_sub(s, n, j + 1, V, n, h2, w);
-            launch_multidot(s, n, 1, w, n, w, kr.partial, hn2, false);
-            hipcheck(hipMemcpyAsync(kr.hhost, kr.hdev, sizeof(double) * (2 * (restart + 2) + 1),
-                                    hipMemcpyDeviceToHost, s),
-                     "D2H");
-            hipcheck(hipStreamSynchronize(s), "hipStreamSynchronize");
-            const double* hh1 = kr.hhost;
-            const double* hh2 = kr.hhost + (restart + 2);
-            hn = std::sqrt(kr.hhost[2 * (restart + 2)]);
+            if (j + 1 < restart && iters + 1 < maxit) issue(j + 1);      // look-ahead
+            hipcheck(hipEventSynchronize(kr.ev[j & 1]), "hipEventSynchronize");
+            const double* hh1 = kr.hhost + (j & 1) * slot;
+            const double* hh2 = hh1 + (restart + 2);
+            hn = std::sqrt(hh1[2 * (restart + 2)]);
             for (int i = 0; i <= j; ++i) Hij(i, j) = hh1[i] + hh2[i];
             Hij(j + 1, j) = hn;
             for (int i = 0; i < j; ++i) {
@@ -645,14 +670,13 @@ phmg_status fgmres_core(hipStream_t s, Krylov& kr, int64_t n, MatVec matvec, Pre
             ++iters;
             ncols = j + 1;
             if (std::fabs(g[j + 1]) <= target || hn == 0.0 || iters >= maxit) break;
-            launch_scale_copy(s, n, w, hn, V + (int64_t)(j + 1) * n);
         }
         for (int i = ncols - 1; i >= 0; --i) {
             double acc = g[i];
             for (int k = i + 1; k < ncols; ++k) acc -= Hij(i, k) * y[k];
             y[i] = acc / Hij(i, i);
         }
-        double* yd = h2;   // reuse: h2 is consumed
+        double* yd = h2;   // the y coefficients reuse h' (stream order: after any look-ahead work)
         hipcheck(hipMemcpyAsync(yd, y.data(), sizeof(double) * ncols, hipMemcpyHostToDevice, s), "H2D");
         launch_gemv_add(s, n, ncols, Z, n, yd, x);
         matvec(x, -1.0, b, 1.0, r);
@@ -693,6 +717,8 @@ void destroy_all(phmg_ctx ctx) {
     for (auto e : ctx->prof.pool) (void)hipEventDestroy(e);
     for (void* p : ctx->allocs) (void)hipFree(p);
     if (ctx->kry.hhost) (void)hipHostFree(ctx->kry.hhost);
+    for (auto e : ctx->kry.ev)
+        if (e) (void)hipEventDestroy(e);
     if (ctx->bhhost) (void)hipHostFree(ctx->bhhost);
     delete ctx;
 }
@@ -1125,6 +1151,8 @@ phmg_status phmg_fbf_destroy(phmg_fbf fbf) {
     if (!fbf) return PHMG_OK;
     for (void* p : fbf->mem.allocs) (void)hipFree(p);
     if (fbf->kry.hhost) (void)hipHostFree(fbf->kry.hhost);
+    for (auto e : fbf->kry.ev)
+        if (e) (void)hipEventDestroy(e);
     delete fbf;
     return PHMG_OK;
 }

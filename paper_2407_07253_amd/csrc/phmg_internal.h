@@ -109,7 +109,8 @@ struct Krylov {
     double* partial = nullptr;       // kRedBlocks x (restart + 2) reduction partials
     int partial_cols = 0;
     double* hdev = nullptr;          // device scalars: h (restart + 1), h', ||w||^2
-    double* hhost = nullptr;         // pinned host mirror
+    double* hhost = nullptr;         // pinned host mirror, two slots (iterations alternate)
+    hipEvent_t ev[2] = {nullptr, nullptr};   // "slot ready" events of the two host slots
 };
 
 struct Profile {

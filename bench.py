@@ -204,8 +204,9 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="cfg2", choices=sorted(WORKLOADS))
     ap.add_argument("--apply-reps", type=int, default=20)
-    ap.add_argument("--phase", default="all", choices=["all", "apply"],
-                    help="apply: only the repeated level-0 relaxation sweeps (for counter runs)")
+    ap.add_argument("--phase", default="all", choices=["all", "apply", "setup"],
+                    help="apply: only the repeated level-0 relaxation sweeps; setup: only the relaxation "
+                         "set-up, repeated (both for counter runs)")
     ap.add_argument("--mixed", default="f32,bf16",
                     help="comma-separated reduced precisions of the patch inverses to time next to f64 ('none': skip)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -303,6 +304,35 @@ def main() -> int:
                     sweep_wall_ms=wall, sweep_bytes=sweep_bytes(infos[0], eb),
                     sweep_gbps=sweep_bytes(infos[0], eb) / (wall * 1e-3) / 1e9,
                     spmv_ms=ms_spmv / max(c_spmv, 1), scatter_ms=ms_sc / max(c_sc, 1))
+
+    if args.phase == "setup":
+        # patch extraction + Gauss-Jordan inversion on every level, and the coarse inverse;
+        # algorithmic flops of inverting an m x m patch: 2 m^3 (LU 2m^3/3 + the rest of the inverse)
+        H.setup()
+        torch.cuda.synchronize()
+        H.profile(["extract", "factor"])
+        H.profile_reset()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            H.setup()
+        torch.cuda.synchronize()
+        wall = (time.perf_counter() - t0) * 1e3 / max(args.steps, 1)
+        levels = []
+        for l in range(nl):
+            fms, fc = H.profile_read("factor", l)
+            ems, ec = H.profile_read("extract", l)
+            info = H.level_info(l)
+            d = {"level": l, "n": info["n"], "factor_ms": _fmt(fms / max(fc, 1)), "extract_ms": _fmt(ems / max(ec, 1))}
+            if info["npatch"]:
+                flops = 2.0 * float(np.sum(np.diff(fh.levels[l].patch_ptr).astype(np.float64) ** 3))
+                d["factor_gflop"] = _fmt(flops / 1e9)
+                d["factor_tflops"] = _fmt(flops / (fms / max(fc, 1) * 1e-3) / 1e12)
+            levels.append(d)
+        H.profile([])
+        print(json.dumps({"phase": "setup", "workload": args.workload, "setup_ms": _fmt(wall), "levels": levels}),
+              flush=True)
+        H.close()
+        return 0
 
     if args.phase == "apply":
         legs = {p: apply_leg(p) for p in ["f64"] + mixed}

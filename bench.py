@@ -45,19 +45,34 @@ WORKLOADS = {
 }
 
 
-def apply_bytes(info: dict, elem_bytes: int) -> int:
+def factor_elements(patch_ptr, sym: bool) -> int:
+    """Factor words one launch of the patch solve reads: sum m^2 in the general layout; in the
+    symmetric strip layout the strictly lower part of every 16-row strip plus its full 16 x 16
+    diagonal block, i.e. 128 (ns - 1) ns + h m per patch (ns strips, h rows in the last one;
+    padding rows not counted)."""
+    import numpy as np
+
+    m = np.diff(np.asarray(patch_ptr)).astype(np.int64)
+    if not sym:
+        return int((m * m).sum())
+    ns = (m + 15) // 16
+    h = m - (ns - 1) * 16
+    return int((128 * (ns - 1) * ns + h * m).sum())
+
+
+def apply_bytes(info: dict, elem_bytes: int, felems: int) -> int:
     """Algorithmic bytes of one launch of the batched patch solve on a level:
-    factor words s_f * sum m^2, patch DoF indices 4 sum m, gathered residual
+    factor words s_f * felems, patch DoF indices 4 sum m, gathered residual
     8 sum m, staged y written 8 sum m, per patch order + ptr + offset 20 B."""
-    return elem_bytes * info["sum_m2"] + 20 * info["sum_m"] + 20 * info["npatch"]
+    return elem_bytes * felems + 20 * info["sum_m"] + 20 * info["npatch"]
 
 
-def sweep_bytes(info: dict, elem_bytes: int) -> int:
+def sweep_bytes(info: dict, elem_bytes: int, felems: int) -> int:
     """Compulsory bytes of one full relaxation sweep on a level (SpMV + apply + scatter)."""
     n, nnz, sm = info["n"], info["nnz"], info["sum_m"]
     spmv = 12 * nnz + 4 * (n + 1) + 8 * n * 3           # CSR + x, b read, r written
     scatter = 8 * sm + 4 * sm + 8 * sm + 4 * (n + 1) + 16 * n   # Y, slots, weights, ptr, x r/w
-    return spmv + apply_bytes(info, elem_bytes) + scatter
+    return spmv + apply_bytes(info, elem_bytes, felems) + scatter
 
 
 def traffic_entry(prec: str):
@@ -170,8 +185,9 @@ def batched_leg(nrhs: int = 16) -> dict:
         ms_sc, c_sc = H.profile_read("scatter", 0)
         H.profile([])
         eb = {"f64": 8, "f32": 4, "bf16": 2}[prec]
+        fel = factor_elements(fh.levels[0].patch_ptr, H.level_info(0)["symmetric_storage"])
         # factor words once for all columns + per slot: index 4 B, gathered row and staged row 2 x 16 x 8 B
-        byt = eb * info0["sum_m2"] + info0["sum_m"] * (4 + 2 * 8 * 16) + 20 * info0["npatch"]
+        byt = eb * fel + info0["sum_m"] * (4 + 2 * 8 * 16) + 20 * info0["npatch"]
         avg = ms / max(cnt, 1)
         out[prec] = {"setup_ms": _fmt((t2 - t1) * 1e3), "solve_ms": _fmt((t3 - t2) * 1e3),
                      "time_to_1e-8_ms": _fmt((t3 - t1) * 1e3), "iters_min": min(its), "iters_max": max(its),
@@ -298,11 +314,14 @@ def main() -> int:
         ms_sc, c_sc = H.profile_read("scatter", 0)
         H.profile([])
         eb = {"f64": 8, "f32": 4, "bf16": 2}[prec]
-        per = apply_bytes(infos[0], eb)
+        sym = H.level_info(0)["symmetric_storage"]
+        fel = factor_elements(fh.levels[0].patch_ptr, sym)
+        per = apply_bytes(infos[0], eb, fel)
         avg = ms / max(cnt, 1)
         return dict(avg_ms=avg, launches=cnt, bytes_per_launch=per, gbps=per / (avg * 1e-3) / 1e9,
-                    sweep_wall_ms=wall, sweep_bytes=sweep_bytes(infos[0], eb),
-                    sweep_gbps=sweep_bytes(infos[0], eb) / (wall * 1e-3) / 1e9,
+                    sym=sym, factor_elements=fel,
+                    sweep_wall_ms=wall, sweep_bytes=sweep_bytes(infos[0], eb, fel),
+                    sweep_gbps=sweep_bytes(infos[0], eb, fel) / (wall * 1e-3) / 1e9,
                     spmv_ms=ms_spmv / max(c_spmv, 1), scatter_ms=ms_sc / max(c_sc, 1))
 
     if args.phase == "setup":
@@ -377,6 +396,8 @@ def main() -> int:
             "levels_n": [i["n"] for i in infos],
             "level0_patches": infos[0]["npatch"],
             "level0_sum_m2": infos[0]["sum_m2"],
+            "level0_layout": "symmetric strips" if ap64["sym"] else "general",
+            "level0_factor_elements": ap64["factor_elements"],
             "level0_max_m": infos[0]["max_m"],
             "step": "relax_setup (extract + patch inversion, all levels) + FGMRES(30) to 1e-8 from x=0",
             "smoother": fh.opts.get("smoother", "richardson"),
@@ -385,7 +406,8 @@ def main() -> int:
         },
         "roofline": {
             "bound": "hbm",
-            "kernel": "patch_apply_kernel<double> (level 0)",
+            "kernel": ("patch_apply_sym_kernel<double>" if ap64["sym"] else "patch_apply_kernel<double>")
+                      + " (level 0)",
             "achieved": round(ap64["gbps"], 2),
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",

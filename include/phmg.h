@@ -128,6 +128,20 @@ phmg_status phmg_relax_setup(phmg_ctx ctx, int level);
  * relax_setup of that level, or followed by a new relax_setup). */
 phmg_status phmg_set_precision(phmg_ctx ctx, int level, phmg_precision prec);
 
+/* Layout of the stored patch inverses of one level (before relax_setup of
+ * that level, or followed by a new relax_setup).
+ * PHMG_STORAGE_AUTO (the default): when K_l is symmetric to rounding
+ * (structurally symmetric and |K_ij - K_ji| <= 1e-12 max(max_k |K_ik|,
+ * max_k |K_jk|) for every entry), each patch inverse is stored as its
+ * symmetric part S_i = (K_i^{-1} + K_i^{-T}) / 2, lower triangle only (row
+ * strips of 16: the strictly lower part and the diagonal 16 x 16 block), which
+ * roughly halves the bytes a sweep streams; S_i^T = S_i also serves the
+ * adjoint sweep.  Otherwise the general layout is used.
+ * PHMG_STORAGE_GENERAL: always B_i = (P_i K_i)^{-1} in full (P_i the pivoting
+ * permutation), with K_i^{-T} = P_i^T B_i^T for the adjoint sweep. */
+typedef enum { PHMG_STORAGE_AUTO = 0, PHMG_STORAGE_GENERAL = 1 } phmg_storage;
+phmg_status phmg_set_patch_storage(phmg_ctx ctx, int level, phmg_storage storage);
+
 /* nu sweeps of x <- x + omega * sum_i R_i^T W_i K_i^{-1} R_i (b - K_l x) on
  * level `level` (eq. "eq:ASM").  level must not be the coarsest. */
 phmg_status phmg_relax_apply(phmg_ctx ctx, int level, const double* b, double* x, int nu);
@@ -240,19 +254,22 @@ phmg_status phmg_residual(phmg_ctx ctx, int level, const double* b, const double
 
 /* Per-level sizes: n, nnz(K), npatch, sum m, sum m^2, max m, the Chebyshev
  * eigenvalue estimate (0 before set-up or for Richardson), the patch-solve
- * kernel shape chosen by the set-up autotuner and the number of shapes
- * compiled for the level's precision. */
+ * kernel shape chosen by the set-up autotuner, the number of shapes
+ * compiled for the level's precision and layout, whether the stored inverses
+ * use the symmetric layout (after set-up) and their element count. */
 typedef struct {
     int32_t n, npatch, max_m, precision;
     int64_t nnz, sum_m, sum_m2;
     double lambda_max;
     int32_t apply_variant, apply_variants;
+    int32_t symmetric_storage, reserved;
+    int64_t stored_elements;
 } phmg_level_info;
 phmg_status phmg_get_level_info(phmg_ctx ctx, int level, phmg_level_info* info);
 
 /* Override the autotuner's patch-solve kernel shape of one level (0 <=
  * variant < apply_variants of phmg_level_info, for the level's current
- * precision; kept until the precision changes).  Every shape computes the
+ * precision and layout; kept until either changes).  Every shape computes the
  * same result bit for bit; this exists for tests and tuning studies. */
 phmg_status phmg_set_apply_variant(phmg_ctx ctx, int level, int variant);
 

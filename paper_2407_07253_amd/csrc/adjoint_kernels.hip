@@ -119,6 +119,10 @@ void launch_t_shape(hipStream_t s, const Level& L, const int64_t* off, const dou
 
 void launch_patch_apply_t(hipStream_t s, const Level& L, const double* r) {
     if (L.npatch <= 0) return;
+    if (L.sym) {                      // S_i^T = S_i: the forward kernel, weights at the gather
+        launch_patch_apply_sym(s, L, r, L.pweight);
+        return;
+    }
     if (L.prec == PHMG_PREC_F32) launch_t_shape<float, float, 2, 4>(s, L, L.fofflp, r);
     else if (L.prec == PHMG_PREC_BF16) launch_t_shape<__hip_bfloat16, float, 4, 4>(s, L, L.fofflp, r);
     else launch_t_shape<double, double, 1, 4>(s, L, L.fofflp, r);

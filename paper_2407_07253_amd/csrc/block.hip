@@ -120,10 +120,10 @@ void tune_block(phmg_ctx ctx) {
         tune_csr(L.K, L.db, L.rb);
         tune_csr(L.R, L.db, C.bb);
         tune_csr(L.P, C.xb, L.rb);
-        if (L.npatch > 0 && L.block_tuned_for != L.prec) {
+        if (L.npatch > 0 && L.block_tuned_for != L.prec + (L.sym ? 3 : 0)) {
             int best = 0;
             float best_ms = 1e30f;
-            for (int v = 0; v < block_variant_count(L.prec); ++v) {
+            for (int v = 0; v < block_variant_count(L); ++v) {
                 L.block_variant = v;
                 const float ms = time_launch(s, e0, e1, [&] { launch_block_apply(s, L, L.db); });
                 if (ms < best_ms) {
@@ -132,7 +132,7 @@ void tune_block(phmg_ctx ctx) {
                 }
             }
             L.block_variant = best;
-            L.block_tuned_for = L.prec;
+            L.block_tuned_for = L.prec + (L.sym ? 3 : 0);
         }
     }
     (void)hipEventDestroy(e0);
@@ -147,7 +147,7 @@ void prepare_block(phmg_ctx ctx) {
     bool stale = false;
     for (size_t l = 0; l + 1 < ctx->L.size(); ++l) {
         const Level& L = ctx->L[l];
-        stale = stale || !L.K.btuned || (L.npatch > 0 && L.block_tuned_for != L.prec);
+        stale = stale || !L.K.btuned || (L.npatch > 0 && L.block_tuned_for != L.prec + (L.sym ? 3 : 0));
     }
     if (stale) {
         invalidate_block_graph(ctx);

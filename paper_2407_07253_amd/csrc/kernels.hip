@@ -381,6 +381,48 @@ __global__ __launch_bounds__(kBlock) void convert_patch_kernel(const int64_t* __
     }
 }
 
+// f64 set-up result B = (P K_i)^{-1} (column-major, ld = m) -> the symmetric
+// strip layout of S_i = (K_i^{-1} + K_i^{-T}) / 2 in precision T.  Column t of
+// B is column idx[t] of K_i^{-1} (idx = pidx), so K_i^{-1}(i, j) = B(i, inv[j])
+// with inv the inverse permutation.  One workgroup per patch.
+template <typename T, int V>
+__global__ __launch_bounds__(kBlock) void convert_sym_kernel(const int64_t* __restrict__ pptr,
+                                                             const int64_t* __restrict__ foff64,
+                                                             const int64_t* __restrict__ fofflp,
+                                                             const int32_t* __restrict__ pidx,
+                                                             const double* __restrict__ src, T* __restrict__ dst) {
+    extern __shared__ int32_t s_inv[];
+    const int p = blockIdx.x;
+    const int64_t base = pptr[p];
+    const int m = (int)(pptr[p + 1] - base);
+    // pidx is a permutation of 0 .. m-1 after a successful inversion (the host
+    // checks the singularity status before this launch); entries outside the
+    // range are ignored so that no index can leave the patch
+    for (int t = threadIdx.x; t < m; t += kBlock) s_inv[t] = t;
+    __syncthreads();
+    for (int t = threadIdx.x; t < m; t += kBlock) {
+        const int q = pidx[base + t];
+        if (q >= 0 && q < m) s_inv[q] = t;
+    }
+    __syncthreads();
+    const double* B = src + foff64[p];
+    T* out = dst + fofflp[p];
+    const int ns = (m + kStrip - 1) / kStrip;
+    for (int s = 0; s < ns; ++s) {
+        const int r0 = s * kStrip, h = min(kStrip, m - r0), hp = (h + V - 1) / V * V, w = r0 + h;
+        T* S = out + sym_strip_offset(s);
+        const int total = hp * w;
+        for (int e = threadIdx.x; e < total; e += kBlock) {
+            const int q = e % hp, j = e / hp, i = r0 + q;
+            double v = 0.0;
+            if (i < m) v = 0.5 * (B[i + (int64_t)s_inv[j] * m] + B[j + (int64_t)s_inv[i] * m]);
+            if constexpr (sizeof(T) == 8) S[e] = v;
+            else if constexpr (sizeof(T) == 4) S[e] = (T)v;
+            else S[e] = __float2bfloat16((float)v);
+        }
+    }
+}
+
 // ---------------------------------------------------------------------------
 // Dense Gauss-Jordan inversion of one large matrix (the coarsest level) over
 // the whole GPU, column-major N x N, panels of w columns:
@@ -829,6 +871,19 @@ void launch_patch_factor(hipStream_t s, const Level& L, double* A) {
 
 void launch_convert_patches(hipStream_t s, const Level& L, const double* src, void* dst) {
     if (L.npatch <= 0) return;
+    if (L.sym) {
+        const size_t lds = sizeof(int32_t) * (size_t)L.max_m;
+        if (L.prec == PHMG_PREC_F64)
+            hipLaunchKernelGGL((convert_sym_kernel<double, factor_pad<double>()>), dim3(L.npatch), dim3(kBlock), lds, s,
+                               L.pptr, L.foff, L.fofflp, L.pidx, src, (double*)dst);
+        else if (L.prec == PHMG_PREC_F32)
+            hipLaunchKernelGGL((convert_sym_kernel<float, factor_pad<float>()>), dim3(L.npatch), dim3(kBlock), lds, s,
+                               L.pptr, L.foff, L.fofflp, L.pidx, src, (float*)dst);
+        else
+            hipLaunchKernelGGL((convert_sym_kernel<__hip_bfloat16, factor_pad<__hip_bfloat16>()>), dim3(L.npatch),
+                               dim3(kBlock), lds, s, L.pptr, L.foff, L.fofflp, L.pidx, src, (__hip_bfloat16*)dst);
+        return;
+    }
     if (L.prec == PHMG_PREC_F64)
         hipLaunchKernelGGL((convert_patch_kernel<double, factor_pad<double>()>), dim3(L.npatch), dim3(kBlock), 0, s,
                            L.pptr, L.foff, L.fofflp, src, (double*)dst);

@@ -3,10 +3,15 @@
 // explicit patch inverses stored by the set-up.  This is the dominant kernel of
 // the solve phase (HBM-bound: every factor word is read once per sweep).
 //
-// Layout: patch i's inverse B_i = (P_i K_i)^{-1} is column-major with every
-// column padded to a multiple of 16 bytes (ld = m rounded up to V = 2 / 4 / 8
-// rows for f64 / f32 / bf16); the gather list pdofs_perm already applies the
-// pivot permutation, so y_i = B_i r[pdofs_perm(i)].
+// General layout: patch i's inverse B_i = (P_i K_i)^{-1} is column-major with
+// every column padded to a multiple of 16 bytes (ld = m rounded up to V = 2 /
+// 4 / 8 rows for f64 / f32 / bf16); the gather list pdofs_perm already applies
+// the pivot permutation, so y_i = B_i r[pdofs_perm(i)].
+//
+// Symmetric layout (symmetric level matrices): S_i = sym(K_i^{-1}) in row
+// strips of 16 (strictly lower part + diagonal block, see phmg_internal.h);
+// every stored off-diagonal entry is used twice, once as S(i, j) and once as
+// S(j, i), so a sweep streams about half the bytes.
 #include <hip/hip_bf16.h>
 #include <hip/hip_runtime.h>
 
@@ -153,12 +158,219 @@ void launch_typed(hipStream_t s, const Level& L, const double* r) {
     }
 }
 
+// Sum of N values over groups of G lanes (lane ids that differ only in the
+// bits of (lane / STRIDE) % G), as a butterfly that first scatters: while more
+// than one value is left, each level keeps half of the list (the upper half in
+// the lane whose bit is set) and adds the partner's copy of that half.  On
+// return, for N >= G, the lane with q = (lane / STRIDE) % G holds in x[0 ..
+// N / G) the group sums of elements [q N / G, (q + 1) N / G); for N < G it
+// holds in x[0] the sum of element q / (G / N).  The pairing is fixed, so the
+// result is deterministic.
+template <typename Acc, int N, int G, int STRIDE>
+struct GroupReduce {
+    __device__ static inline void run(Acc* x, int lane) {
+        if constexpr (G > 1) {
+            constexpr int g = G / 2;
+            if constexpr (N > 1) {
+                constexpr int h = N / 2;
+                const bool up = ((lane / STRIDE) & g) != 0;
+#pragma unroll
+                for (int e = 0; e < h; ++e) {
+                    const Acc lo = x[e], hi = x[e + h];
+                    const Acc other = __shfl_xor(up ? lo : hi, g * STRIDE);
+                    x[e] = (up ? hi : lo) + other;
+                }
+                GroupReduce<Acc, h, g, STRIDE>::run(x, lane);
+            } else {
+                x[0] += __shfl_xor(x[0], g * STRIDE);
+                GroupReduce<Acc, 1, g, STRIDE>::run(x, lane);
+            }
+        }
+    }
+};
+
+// Symmetric layout, one workgroup per patch.  A wave covers a strip's 16 rows
+// with RL = 16 / V row lanes (one 16-byte load each) and CL = 64 / RL column
+// lanes; a work unit is one strip times 64 consecutive stored columns, i.e. RL
+// loads per lane, each wave-wide load reading 1 KB of contiguous bytes.  Per
+// loaded row group (rows i, column j) the lane adds S(i, j) r_j to its row
+// partials and, for j below the diagonal block, forms S(i, j) . r_i for column j.
+// Column sums are scatter-reduced over the row lanes (each lane ends with one
+// column), row sums are reduced over the column lanes, and both are added into
+// the wave's own partial result in LDS; units are dealt to the waves
+// round-robin and the four partial results are summed in wave order at the
+// end.  PF = true issues the loads of a wave's next unit before computing the
+// current one; the arithmetic, and so every bit of the result, is the same.
+constexpr int kUnitCols = 64;
+
+template <typename T>
+struct SymShape {
+    static constexpr int V = Load16<T>::V;
+    static constexpr int RL = kStrip / V;
+    static constexpr int CL = kWave / RL;
+    static constexpr int U = kUnitCols / CL;       // loads per lane per unit (= RL)
+};
+
+// next unit position after (s, c): the following 64 columns of the strip, or the next strip
+__device__ inline bool sym_step(int& s, int& c, int ns, int m) {
+    c += kUnitCols;
+    if (c >= min(m, (s + 1) * kStrip)) {
+        ++s;
+        c = 0;
+    }
+    return s < ns;
+}
+
+template <typename T>
+__device__ inline void sym_load(const T* A, int s, int c_lo, int m, int rl, int cl,
+                                typename Load16<T>::acc_t (&a)[SymShape<T>::U][SymShape<T>::V]) {
+    typedef SymShape<T> Sh;
+    const int r0 = s * kStrip, h = min(kStrip, m - r0), hp = (h + Sh::V - 1) / Sh::V * Sh::V, w = r0 + h;
+    const T* S = A + sym_strip_offset(s) + rl * Sh::V;
+    const bool rowv = rl * Sh::V < hp;
+#pragma unroll
+    for (int u = 0; u < Sh::U; ++u) {
+        const int j = c_lo + cl + Sh::CL * u;
+        if (rowv && j < w) Load16<T>::load(S + (int64_t)j * hp, a[u]);
+        else
+#pragma unroll
+            for (int v = 0; v < Sh::V; ++v) a[u][v] = 0;
+    }
+}
+
+template <typename T, bool PF>
+__global__ __launch_bounds__(kBlock) void patch_apply_sym_kernel(const int32_t* __restrict__ order,
+                                                                 const int64_t* __restrict__ pptr,
+                                                                 const int32_t* __restrict__ pdofs,
+                                                                 const int64_t* __restrict__ foff,
+                                                                 const T* __restrict__ F,
+                                                                 const double* __restrict__ r,
+                                                                 const double* __restrict__ gw,
+                                                                 double* __restrict__ Y, int ldbuf) {
+    typedef typename Load16<T>::acc_t Acc;
+    typedef SymShape<T> Sh;
+    constexpr int V = Sh::V, RL = Sh::RL, CL = Sh::CL, U = Sh::U;
+    constexpr int NW = kBlock / kWave;
+    static_assert(V == factor_pad<T>() && U == RL && CL % V == 0, "strip and reduction shapes");
+    extern __shared__ double s_buf[];
+    Acc* s_r = reinterpret_cast<Acc*>(s_buf);
+    Acc* s_y = s_r + ldbuf;                                       // NW partial results of ldbuf each
+    const int p = order[blockIdx.x];
+    const int64_t base = pptr[p];
+    const int m = (int)(pptr[p + 1] - base);
+    for (int t = threadIdx.x; t < m; t += kBlock) {
+        const double v = r[pdofs[base + t]];
+        s_r[t] = (Acc)(gw ? gw[base + t] * v : v);
+    }
+    for (int t = threadIdx.x; t < NW * ldbuf; t += kBlock) s_y[t] = (Acc)0;
+    __syncthreads();
+    const T* A = F + foff[p];
+    const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
+    const int rl = lane % RL, cl = lane / RL;
+    Acc* yw = s_y + wave * ldbuf;
+    const int ns = (m + kStrip - 1) / kStrip;
+    // this wave's first unit: unit number `wave` in strip-major order
+    int s = 0, c = 0;
+    bool ok = true;
+    for (int q = 0; q < wave && ok; ++q) ok = sym_step(s, c, ns, m);
+    Acc a[U][V];
+    if (PF && ok) sym_load<T>(A, s, c, m, rl, cl, a);
+    while (ok) {
+        int s2 = s, c2 = c;
+        bool ok2 = true;
+        for (int q = 0; q < NW && ok2; ++q) ok2 = sym_step(s2, c2, ns, m);
+        Acc b[U][V];
+        if (PF) {
+            if (ok2) sym_load<T>(A, s2, c2, m, rl, cl, b);
+        } else {
+            sym_load<T>(A, s, c, m, rl, cl, a);
+        }
+        const int r0 = s * kStrip, w = min(m, r0 + kStrip);
+        Acc rr[V];
+#pragma unroll
+        for (int v = 0; v < V; ++v) {
+            const int i = r0 + rl * V + v;
+            rr[v] = i < m ? s_r[i] : (Acc)0;
+        }
+        Acc acc[V], d[U];
+#pragma unroll
+        for (int v = 0; v < V; ++v) acc[v] = (Acc)0;
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int j = c + cl + CL * u;
+            const Acc rj = j < w ? s_r[j] : (Acc)0;
+            Acc dd = (Acc)0;
+#pragma unroll
+            for (int v = 0; v < V; ++v) {
+                acc[v] += a[u][v] * rj;
+                dd += a[u][v] * rr[v];
+            }
+            d[u] = j < r0 ? dd : (Acc)0;
+        }
+        // column sums S(rows, j)^T r_rows: scatter-reduce over the RL row lanes; the lane
+        // keeps column c + cl + CL * rl
+        GroupReduce<Acc, U, RL, 1>::run(d, lane);
+        {
+            const int j = c + cl + CL * rl;
+            if (j < r0) yw[j] += d[0];
+        }
+        // row sums: reduce over the CL column lanes
+        GroupReduce<Acc, V, CL, RL>::run(acc, lane);
+        if (cl % (CL / V) == 0) {
+            const int i = r0 + rl * V + cl / (CL / V);
+            if (i < m) yw[i] += acc[0];
+        }
+        s = s2;
+        c = c2;
+        ok = ok2;
+        if (PF) {
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+#pragma unroll
+                for (int v = 0; v < V; ++v) a[u][v] = b[u][v];
+        }
+    }
+    __syncthreads();
+    for (int t = threadIdx.x; t < m; t += kBlock) {
+        Acc sum = s_y[t];
+#pragma unroll
+        for (int q = 1; q < NW; ++q) sum += s_y[q * ldbuf + t];
+        Y[base + t] = (double)sum;
+    }
+}
+
+template <typename T, bool PF>
+void launch_sym_shape(hipStream_t s, const Level& L, const double* r, const double* gw) {
+    typedef typename Load16<T>::acc_t Acc;
+    const int ldbuf = (L.max_m + 1) & ~1;
+    const size_t lds = sizeof(Acc) * (size_t)ldbuf * (1 + kBlock / kWave);
+    hipLaunchKernelGGL((patch_apply_sym_kernel<T, PF>), dim3(L.npatch), dim3(kBlock), lds, s, L.order, L.pptr,
+                       L.pdofs, L.fofflp, (const T*)L.factors, r, gw, L.Y, ldbuf);
+}
+
+template <typename T>
+void launch_sym_typed(hipStream_t s, const Level& L, const double* r, const double* gw) {
+    if (L.apply_variant == 1) launch_sym_shape<T, true>(s, L, r, gw);
+    else launch_sym_shape<T, false>(s, L, r, gw);
+}
+
 }  // namespace
 
-int apply_variant_count(int /*prec*/) { return 3; }
+int apply_variant_count(const Level& L) { return L.sym ? 2 : 3; }
+
+void launch_patch_apply_sym(hipStream_t s, const Level& L, const double* r, const double* gw) {
+    if (L.npatch <= 0) return;
+    if (L.prec == PHMG_PREC_F32) launch_sym_typed<float>(s, L, r, gw);
+    else if (L.prec == PHMG_PREC_BF16) launch_sym_typed<__hip_bfloat16>(s, L, r, gw);
+    else launch_sym_typed<double>(s, L, r, gw);
+}
 
 void launch_patch_apply(hipStream_t s, const Level& L, const double* r) {
     if (L.npatch <= 0) return;
+    if (L.sym) {
+        launch_patch_apply_sym(s, L, r, nullptr);
+        return;
+    }
     if (L.prec == PHMG_PREC_F32) launch_typed<float>(s, L, r);
     else if (L.prec == PHMG_PREC_BF16) launch_typed<__hip_bfloat16>(s, L, r);
     else launch_typed<double>(s, L, r);

@@ -88,6 +88,33 @@ bool is_symmetric(const phmg_csr& A) {
     return lower == upper;
 }
 
+// Symmetric to rounding: the pattern is symmetric and every entry differs from
+// its mirror by at most 1e-12 times the larger of the two rows' max |entry|
+// (assembly sums the two mirrored entries in different orders).
+bool near_symmetric(const phmg_csr& A) {
+    if (A.nrows != A.ncols) return false;
+    std::vector<double> rmax(A.nrows, 0.0);
+    for (int32_t i = 0; i < A.nrows; ++i)
+        for (int32_t k = A.rowptr[i]; k < A.rowptr[i + 1]; ++k) rmax[i] = std::max(rmax[i], std::fabs(A.val[k]));
+    int64_t lower = 0, upper = 0;
+    for (int32_t i = 0; i < A.nrows; ++i)
+        for (int32_t k = A.rowptr[i]; k < A.rowptr[i + 1]; ++k) {
+            const int32_t j = A.col[k];
+            if (j < i) {
+                ++lower;
+                continue;
+            }
+            if (j == i) continue;
+            ++upper;
+            const int32_t* b0 = A.col + A.rowptr[j];
+            const int32_t* b1 = A.col + A.rowptr[j + 1];
+            const int32_t* f = std::lower_bound(b0, b1, i);
+            if (f == b1 || *f != i) return false;
+            if (std::fabs(A.val[f - A.col] - A.val[k]) > 1e-12 * std::max(rmax[i], rmax[j])) return false;
+        }
+    return lower == upper;
+}
+
 DevCsr upload_transpose(phmg_ctx ctx, const phmg_csr& A) {
     std::vector<int32_t> rp(A.ncols + 1, 0), ci(A.nnz);
     std::vector<double> v(A.nnz);
@@ -159,15 +186,17 @@ void relax(phmg_ctx ctx, int l, const double* b, double* x, int nu, bool x_zero,
 // Set-up autotuner of the patch-solve kernel shape: every compiled shape of the
 // level's precision is timed on the level's own patches (HIP events, best of
 // three launches) and the fastest is kept.  Runs once per level and precision.
+int tune_key(const Level& L) { return L.prec + (L.sym ? 3 : 0); }
+
 void tune_apply(phmg_ctx ctx, int l) {
     Level& L = ctx->L[l];
-    if (L.tuned_for == L.prec || L.npatch == 0) return;
+    if (L.tuned_for == tune_key(L) || L.npatch == 0) return;
     hipStream_t s = ctx->stream;
     launch_fill(s, L.n, L.r, 1.0);
     hipEvent_t e0, e1;
     hipcheck(hipEventCreate(&e0), "hipEventCreate");
     hipcheck(hipEventCreate(&e1), "hipEventCreate");
-    const int nv = apply_variant_count(L.prec);
+    const int nv = apply_variant_count(L);
     int best = 0;
     float best_ms = 1e30f;
     for (int v = 0; v < nv; ++v) {
@@ -192,7 +221,7 @@ void tune_apply(phmg_ctx ctx, int l) {
     (void)hipEventDestroy(e1);
     hipcheck(hipGetLastError(), "autotune launch");
     L.apply_variant = best;
-    L.tuned_for = L.prec;
+    L.tuned_for = tune_key(L);
 }
 
 // Eigenvalues of a small real upper-Hessenberg matrix (row-major k x k) by the
@@ -503,10 +532,20 @@ void setup_level(phmg_ctx ctx, int l) {
         launch_patch_factor(s, L, f64);
         hipcheck(hipGetLastError(), "patch factorisation launch");
     }
+    // a singular patch stops its elimination early and leaves its pivot lists
+    // (pdofs_perm, pidx) unwritten: nothing may read them, so check before converting
+    hipcheck(hipMemcpyAsync(&st, L.status, sizeof(int32_t), hipMemcpyDeviceToHost, s), "D2H");
+    hipcheck(hipStreamSynchronize(s), "hipStreamSynchronize");
+    if (st != INT32_MAX) {
+        dfree(ctx, f64);
+        fail(PHMG_ESINGULAR, lvl(l) + "patch " + std::to_string(st) + " is singular");
+    }
     {
-        // the stored inverses: columns padded to 16 bytes, in the level's precision
+        // the stored inverses in the level's precision: general layout (columns
+        // padded to 16 bytes) or the symmetric strip layout
         const size_t es = L.prec == PHMG_PREC_F64 ? 8 : (L.prec == PHMG_PREC_F32 ? 4 : 2);
-        const int64_t cnt = L.sum_lp[L.prec];
+        L.sym = L.sym_ok && L.storage == PHMG_STORAGE_AUTO;
+        const int64_t cnt = L.sym ? L.sum_ls[L.prec] : L.sum_lp[L.prec];
         std::vector<int64_t> off(L.npatch);
         {
             std::vector<int64_t> hp(L.npatch + 1);
@@ -516,7 +555,7 @@ void setup_level(phmg_ctx ctx, int l) {
             for (int32_t i = 0; i < L.npatch; ++i) {
                 const int64_t m = hp[i + 1] - hp[i];
                 off[i] = acc;
-                acc += (m + V - 1) / V * V * m;
+                acc += L.sym ? sym_layout_size((int)m, V) : (m + V - 1) / V * V * m;
             }
             // the allocation below is sized at create (sum_lp); the layout must match it exactly
             if (acc != cnt) fail(PHMG_EINVAL, lvl(l) + "internal: reduced-precision layout size mismatch");
@@ -533,10 +572,8 @@ void setup_level(phmg_ctx ctx, int l) {
         hipcheck(hipGetLastError(), "convert launch");
         L.factors = lo;
     }
-    hipcheck(hipMemcpyAsync(&st, L.status, sizeof(int32_t), hipMemcpyDeviceToHost, s), "D2H");
     hipcheck(hipStreamSynchronize(s), "hipStreamSynchronize");
     dfree(ctx, f64);
-    if (st != INT32_MAX) fail(PHMG_ESINGULAR, lvl(l) + "patch " + std::to_string(st) + " is singular");
     tune_apply(ctx, l);
     if (ctx->opts.smoother == PHMG_SMOOTHER_CHEBYSHEV) {
         L.lmax = arnoldi_estimate(ctx, l);
@@ -808,6 +845,7 @@ phmg_status phmg_hierarchy_create(const phmg_hierarchy_desc* desc, const phmg_cy
             // K^T for the adjoint path: the same arrays when K is symmetric (the
             // Stokes matrices are), otherwise an explicit transposed copy
             L.KT = is_symmetric(desc->K[l]) ? L.K : upload_transpose(ctx, desc->K[l]);
+            L.sym_ok = near_symmetric(desc->K[l]);
             L.r = dalloc<double>(ctx, L.n);
             L.d = dalloc<double>(ctx, L.n);
             L.status = dalloc<int>(ctx, 1);
@@ -839,6 +877,7 @@ phmg_status phmg_hierarchy_create(const phmg_hierarchy_desc* desc, const phmg_cy
                     for (int pr = PHMG_PREC_F64; pr <= PHMG_PREC_BF16; ++pr) {
                         const int V = factor_pad_of(pr);
                         L.sum_lp[pr] += (m + V - 1) / V * V * m;
+                        L.sum_ls[pr] += sym_layout_size((int)m, V);
                     }
                 }
                 std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) {
@@ -885,6 +924,21 @@ phmg_status phmg_hierarchy_destroy(phmg_ctx ctx) {
         if (!ctx) fail(PHMG_EINVAL, "null context");
         (void)hipStreamSynchronize(ctx->stream);
         destroy_all(ctx);
+        return PHMG_OK;
+    });
+}
+
+phmg_status phmg_set_patch_storage(phmg_ctx ctx, int level, phmg_storage storage) {
+    return guarded([&]() -> phmg_status {
+        if (!ctx) fail(PHMG_EINVAL, "null context");
+        if (level < 0 || level >= (int)ctx->L.size() - 1) fail(PHMG_EINVAL, "level out of range");
+        if (storage != PHMG_STORAGE_AUTO && storage != PHMG_STORAGE_GENERAL) fail(PHMG_EINVAL, "unknown storage");
+        Level& L = ctx->L[level];
+        if (L.storage != storage) {
+            L.storage = storage;
+            L.ready = false;
+            invalidate_graph(ctx);
+        }
         return PHMG_OK;
     });
 }
@@ -1181,7 +1235,10 @@ phmg_status phmg_get_level_info(phmg_ctx ctx, int level, phmg_level_info* info) 
         info->sum_m2 = L.sum_m2;
         info->lambda_max = L.lmax;
         info->apply_variant = L.apply_variant;
-        info->apply_variants = apply_variant_count(L.prec);
+        info->apply_variants = apply_variant_count(L);
+        info->symmetric_storage = L.sym ? 1 : 0;
+        info->reserved = 0;
+        info->stored_elements = L.npatch == 0 ? 0 : (L.sym ? L.sum_ls[L.prec] : L.sum_lp[L.prec]);
         return PHMG_OK;
     });
 }
@@ -1191,9 +1248,9 @@ phmg_status phmg_set_apply_variant(phmg_ctx ctx, int level, int variant) {
         if (!ctx) fail(PHMG_EINVAL, "null context");
         if (level < 0 || level >= (int)ctx->L.size() - 1) fail(PHMG_EINVAL, "level out of range");
         Level& L = ctx->L[level];
-        if (variant < 0 || variant >= apply_variant_count(L.prec)) fail(PHMG_EINVAL, "variant out of range");
+        if (variant < 0 || variant >= apply_variant_count(L)) fail(PHMG_EINVAL, "variant out of range");
         L.apply_variant = variant;
-        L.tuned_for = L.prec;
+        L.tuned_for = tune_key(L);
         invalidate_graph(ctx);
         return PHMG_OK;
     });

@@ -26,6 +26,21 @@ template <typename T>
 __host__ __device__ constexpr int factor_pad() { return 16 / (int)sizeof(T); }
 inline int factor_pad_of(int prec) { return prec == PHMG_PREC_F64 ? 2 : (prec == PHMG_PREC_F32 ? 4 : 8); }
 
+// Symmetric layout of a patch inverse S (used when the level matrix is
+// symmetric): the rows are cut into strips of kStrip rows; strip s (rows
+// [16 s, 16 s + h_s)) stores columns [0, 16 s + h_s) -- the strictly lower part
+// of its rows plus the full diagonal block -- column-major with its height
+// padded to the 16-byte row group V (padding rows are zero).  Strips are
+// consecutive: full strips take 16 x 16 (s + 1) elements, so strip s starts at
+// 128 s (s + 1).  An entry S(i, j), j < 16 s, stands for S(j, i) too.
+constexpr int kStrip = 16;
+__host__ __device__ constexpr int64_t sym_strip_offset(int s) { return (int64_t)kStrip * kStrip * s * (s + 1) / 2; }
+__host__ __device__ inline int64_t sym_layout_size(int m, int V) {
+    const int ns = (m + kStrip - 1) / kStrip;
+    const int h = m - (ns - 1) * kStrip;
+    return sym_strip_offset(ns - 1) + (int64_t)((h + V - 1) / V * V) * m;
+}
+
 struct DevCsr {
     int32_t nrows = 0, ncols = 0;
     int64_t nnz = 0;
@@ -58,8 +73,13 @@ struct Level {
     double* ptol = nullptr;          // npatch: singularity threshold 1e-14 ||K_i||_inf
     double* pweight = nullptr;       // sum_m or null (W_i = I)
     int64_t* foff = nullptr;         // offset of patch i's m_i x m_i block in the set-up buffer (ld = m)
-    int64_t* fofflp = nullptr;       // offsets of the stored inverses (ld = m rounded up to factor_pad)
+    int64_t* fofflp = nullptr;       // offsets of the stored inverses (general: ld = m rounded up to
+                                     // factor_pad; symmetric: strip layout)
     int64_t sum_lp[3] = {0, 0, 0};   // element counts of the stored f64 / f32 / bf16 layouts
+    int64_t sum_ls[3] = {0, 0, 0};   // the same for the symmetric (strip) layout
+    bool sym_ok = false;             // K is symmetric to rounding (entries within 1e-12 of the row scale)
+    int storage = PHMG_STORAGE_AUTO; // requested layout of the stored inverses
+    bool sym = false;                // the stored inverses use the symmetric strip layout
     int32_t* order = nullptr;        // launch order: patches by decreasing size
     int32_t* sptr = nullptr;         // DoF -> slot map for the scatter (n + 1)
     int32_t* sslot = nullptr;        // sum_m slot indices, ascending patch id per DoF
@@ -192,7 +212,9 @@ void launch_convert_patches(hipStream_t s, const Level& L, const double* src, vo
 void launch_patch_apply(hipStream_t s, const Level& L, const double* r);
 // adjoint patch solve y_i = K_i^{-T} W_i r[S_i] from the same stored inverses (adjoint_kernels.hip)
 void launch_patch_apply_t(hipStream_t s, const Level& L, const double* r);
-int apply_variant_count(int prec);
+int apply_variant_count(const Level& L);
+// symmetric layout: y_i = S_i (g_i * r[S_i]) with g_i = W_i (gw != null, the adjoint sweep) or I
+void launch_patch_apply_sym(hipStream_t s, const Level& L, const double* r, const double* gw);
 // dn = a * sum_t w_t Y_t + c * d;  x = (x_zero ? 0 : x) + dn;  d = dn if store_d
 // (c = 0: d is not read; d may be null when c = 0 and !store_d)
 // transpose: the adjoint sweep's scatter (weights W_i were applied at the gather)
@@ -227,7 +249,7 @@ void invalidate_block_graph(phmg_ctx ctx);
 void launch_spmm(hipStream_t s, const DevCsr& A, const double* X, double alpha, const double* Z, double beta,
                  double* Y);
 void launch_block_apply(hipStream_t s, const Level& L, const double* X);
-int block_variant_count(int prec);
+int block_variant_count(const Level& L);
 void launch_block_scatter(hipStream_t s, const Level& L, double a, double c, double* d, bool store_d, double* X,
                           bool x_zero);
 void launch_block_coarse_solve(hipStream_t s, const Level& L, const double* B, double* X);

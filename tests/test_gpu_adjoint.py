@@ -1,8 +1,10 @@
 """Adjoint (transposed) GPU operators against the oracle's transposed cycle.
 
-The library's transposed sweep reuses the forward factors (K_i^{-T} = P_i^T B_i^T
-with the stored B_i = (P_i K_i)^{-1}); the oracle solves with its own LU
-transposed (oracle/lu.py lu_solve_transposed).  Tolerances as in the forward
+The library's transposed sweep reuses the forward factors: in the general layout
+K_i^{-T} = P_i^T B_i^T with the stored B_i = (P_i K_i)^{-1}; in the symmetric
+strip layout (storage "auto" on symmetric levels) the stored S_i = sym(K_i^{-1})
+is its own transpose.  The oracle solves with its own LU transposed
+(oracle/lu.py lu_solve_transposed).  Both layouts are tested.  Tolerances as in the forward
 parity tests.  The adjoint identity <y, B x> = <B^T y, x> is checked on the GPU
 alone as a property that holds for any correct pair.
 """
@@ -21,16 +23,23 @@ from paper_2407_07253_amd import frontend  # noqa: E402
 _CACHE = {}
 
 
-def _pair(name):
-    if name not in _CACHE:
+def _pair(name, storage="auto"):
+    key = (name, storage)
+    if key not in _CACHE:
         from paper_2407_07253_amd._lib import Hierarchy
         fh = frontend.build_hierarchy(name)
         H = Hierarchy.from_frontend(fh)
+        for l in range(len(fh.levels) - 1):
+            H.set_patch_storage(l, storage)
         H.setup()
-        ol, od, oopts, ob = oproblems.build(name)
-        omg.setup(ol, oopts)
-        _CACHE[name] = (fh, H, ol, od, oopts, ob)
-    return _CACHE[name]
+        base = _CACHE.get((name, "auto")) or _CACHE.get((name, "general"))
+        if base is None:
+            ol, od, oopts, ob = oproblems.build(name)
+            omg.setup(ol, oopts)
+        else:
+            ol, od, oopts, ob = base[2:]
+        _CACHE[key] = (fh, H, ol, od, oopts, ob)
+    return _CACHE[key]
 
 
 def _dev(a):
@@ -57,8 +66,9 @@ NAMES = ["cfg1", "cfg2_r1", "sv_small"]
 
 @pytest.mark.parametrize("name", NAMES)
 @pytest.mark.parametrize("nu", [1, 2])
-def test_transposed_relax_matches_oracle(name, nu):
-    fh, H, ol, od, oopts, ob = _pair(name)
+@pytest.mark.parametrize("storage", ["auto", "general"])
+def test_transposed_relax_matches_oracle(name, nu, storage):
+    fh, H, ol, od, oopts, ob = _pair(name, storage)
     rng = np.random.default_rng(500 + nu)
     for l in range(len(ol) - 1):
         n = ol[l].n
@@ -73,8 +83,9 @@ def test_transposed_relax_matches_oracle(name, nu):
 
 
 @pytest.mark.parametrize("name", NAMES)
-def test_transposed_vcycle_matches_oracle(name):
-    fh, H, ol, od, oopts, ob = _pair(name)
+@pytest.mark.parametrize("storage", ["auto", "general"])
+def test_transposed_vcycle_matches_oracle(name, storage):
+    fh, H, ol, od, oopts, ob = _pair(name, storage)
     rng = np.random.default_rng(8)
     b = rng.standard_normal(ol[0].n)
     z = _dev(np.full(ol[0].n, np.nan))
@@ -87,9 +98,10 @@ def test_transposed_vcycle_matches_oracle(name):
 
 
 @pytest.mark.parametrize("name", NAMES)
-def test_transposed_vcycle_is_the_adjoint(name):
+@pytest.mark.parametrize("storage", ["auto", "general"])
+def test_transposed_vcycle_is_the_adjoint(name, storage):
     """<y, B x> = <B^T y, x> for random x, y (B the forward V-cycle operator)."""
-    fh, H, ol, od, oopts, ob = _pair(name)
+    fh, H, ol, od, oopts, ob = _pair(name, storage)
     rng = np.random.default_rng(9)
     n = ol[0].n
     worst = 0.0
@@ -107,8 +119,9 @@ def test_transposed_vcycle_is_the_adjoint(name):
 
 
 @pytest.mark.parametrize("name", NAMES)
-def test_transposed_fgmres_matches_oracle(name):
-    fh, H, ol, od, oopts, ob = _pair(name)
+@pytest.mark.parametrize("storage", ["auto", "general"])
+def test_transposed_fgmres_matches_oracle(name, storage):
+    fh, H, ol, od, oopts, ob = _pair(name, storage)
     rng = np.random.default_rng(10)
     g = rng.standard_normal(ol[0].n)
     g[2 * od[0].nfu:] -= g[2 * od[0].nfu:].mean()       # consistent: orthogonal to the pressure kernel
@@ -126,8 +139,9 @@ def test_transposed_fgmres_matches_oracle(name):
     assert err <= 1e-10
 
 
+@pytest.mark.parametrize("storage", ["auto", "general"])
 @pytest.mark.parametrize("prec", ["f32", "bf16"])
-def test_transposed_reduced_precision_is_the_adjoint(prec):
+def test_transposed_reduced_precision_is_the_adjoint(prec, storage):
     """With FP32 / BF16 inverses the transposed sweep is still the adjoint of the forward
     one up to float32 rounding of the two products."""
     from paper_2407_07253_amd._lib import Hierarchy
@@ -135,6 +149,7 @@ def test_transposed_reduced_precision_is_the_adjoint(prec):
     H = Hierarchy.from_frontend(fh)
     for l in range(len(fh.levels) - 1):
         H.set_precision(l, prec)
+        H.set_patch_storage(l, storage)
     H.setup()
     n = fh.levels[0].n
     rng = np.random.default_rng(12)
@@ -144,6 +159,6 @@ def test_transposed_reduced_precision_is_the_adjoint(prec):
     H.vcycle_transposed(_dev(y), bty)
     Bx, BTy = _host(bx), _host(bty)
     d = abs(y @ Bx - BTy @ x) / (np.linalg.norm(y) * np.linalg.norm(Bx))
-    print(f"{prec}: adjoint defect {d:.2e}")
+    print(f"{prec} ({storage}): adjoint defect {d:.2e}")
     assert d <= 1e-5
     H.close()

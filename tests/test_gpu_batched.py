@@ -23,13 +23,15 @@ from paper_2407_07253_amd import frontend  # noqa: E402
 _CACHE = {}
 
 
-def _pair(name, nrhs):
-    key = (name, nrhs)
+def _pair(name, nrhs, storage="auto"):
+    key = (name, nrhs, storage)
     if key not in _CACHE:
         from paper_2407_07253_amd._lib import Hierarchy
         forcing = "bumps" if name.startswith("cfg3") else "mms"
         fh = frontend.build_hierarchy(name, forcing=forcing, nrhs=nrhs)
         H = Hierarchy.from_frontend(fh)
+        for l in range(len(fh.levels) - 1):
+            H.set_patch_storage(l, storage)
         H.setup()
         ol, od, oopts, ob = oproblems.build(name, forcing=forcing, nrhs=nrhs)
         omg.setup(ol, oopts)
@@ -56,10 +58,11 @@ def _normalise(x, nfu):
     return y
 
 
+@pytest.mark.parametrize("storage", ["auto", "general"])
 @pytest.mark.parametrize("name,nrhs", [("cfg1", 3), ("cfg3_r1", 16), ("sv_small", 5)])
 @pytest.mark.parametrize("nu", [1, 2])
-def test_batched_relax_matches_oracle(name, nrhs, nu):
-    fh, H, ol, od, oopts, ob = _pair(name, 1)
+def test_batched_relax_matches_oracle(name, nrhs, nu, storage):
+    fh, H, ol, od, oopts, ob = _pair(name, 1, storage)
     rng = np.random.default_rng(300 + nu + nrhs)
     for l in range(len(ol) - 1):
         n = ol[l].n
@@ -71,7 +74,7 @@ def test_batched_relax_matches_oracle(name, nrhs, nu):
         for c in range(nrhs):
             ref = omg._relax(ol[l], oopts, B[c], X[c], nu, False)
             worst = max(worst, _rel(got[c], ref))
-        print(f"{name} level {l} nu={nu} nrhs={nrhs}: worst column rel err {worst:.2e}")
+        print(f"{name} ({storage}) level {l} nu={nu} nrhs={nrhs}: worst column rel err {worst:.2e}")
         assert worst <= 1e-11, (l, worst)
 
 
@@ -221,8 +224,9 @@ def test_batched_argument_errors():
         H.fgmres_batched(_dev(np.ones((2, n))), _dev(np.zeros((2, n))), restart=40)
 
 
+@pytest.mark.parametrize("storage", ["auto", "general"])
 @pytest.mark.parametrize("prec", ["f32", "bf16"])
-def test_batched_reduced_precision_sweep_matches_single_path(prec):
+def test_batched_reduced_precision_sweep_matches_single_path(prec, storage):
     """With FP32 / BF16 patch inverses the MFMA block product (float32 accumulation) and the
     single-system streaming kernel use the same rounded factors and right-hand sides; they
     differ only in float32 summation order, so a sweep agrees to ~1e-6 in norm.  A wrong
@@ -232,6 +236,7 @@ def test_batched_reduced_precision_sweep_matches_single_path(prec):
     H = Hierarchy.from_frontend(fh)
     for l in range(len(fh.levels) - 1):
         H.set_precision(l, prec)
+        H.set_patch_storage(l, storage)
     H.setup()
     rng = np.random.default_rng(77)
     nrhs = 7
@@ -247,6 +252,6 @@ def test_batched_reduced_precision_sweep_matches_single_path(prec):
             H.relax_apply(l, _dev(B[c]), x1, 1)
             one = _host(x1)
             worst = max(worst, float(np.linalg.norm(got[c] - one) / np.linalg.norm(one - X[c])))
-        print(f"{prec} level {l}: worst column ||batched - single|| / ||correction|| = {worst:.2e}")
+        print(f"{prec} ({storage}) level {l}: worst column ||batched - single|| / ||correction|| = {worst:.2e}")
         assert worst <= 1e-4
     H.close()

@@ -11,6 +11,10 @@ identical in tests/test_frontend.py).  Tolerances:
   compared to 1e-11 relative (max norm); observed 3e-16 .. 1.2e-14 on MI355X.
 * FGMRES: identical iteration counts and solutions equal to 1e-10 relative
   after removing the pressure mean (the constant-pressure kernel).
+
+Symmetric level matrices store each patch inverse as its symmetric part in
+row strips (storage "auto"); "general" keeps the full pivoted inverse.  Both
+layouts are held to the same tolerances.
 """
 import numpy as np
 import pytest
@@ -28,16 +32,23 @@ from paper_2407_07253_amd import frontend  # noqa: E402
 _CACHE = {}
 
 
-def _pair(name):
-    if name not in _CACHE:
+def _pair(name, storage="auto"):
+    key = (name, storage)
+    if key not in _CACHE:
         from paper_2407_07253_amd._lib import Hierarchy
         fh = frontend.build_hierarchy(name)
         H = Hierarchy.from_frontend(fh)
+        for l in range(len(fh.levels) - 1):
+            H.set_patch_storage(l, storage)
         H.setup()
-        ol, od, oopts, ob = oproblems.build(name)
-        omg.setup(ol, oopts)
-        _CACHE[name] = (fh, H, ol, od, oopts, ob)
-    return _CACHE[name]
+        base = _CACHE.get((name, "auto")) or _CACHE.get((name, "general"))
+        if base is None:
+            ol, od, oopts, ob = oproblems.build(name)
+            omg.setup(ol, oopts)
+        else:
+            ol, od, oopts, ob = base[2:]
+        _CACHE[key] = (fh, H, ol, od, oopts, ob)
+    return _CACHE[key]
 
 
 def _dev(a):
@@ -62,10 +73,11 @@ def _normalise(x, nfu):
 NAMES = ["cfg1", "cfg2_r1", "sv_small"]
 
 
+@pytest.mark.parametrize("storage", ["auto", "general"])
 @pytest.mark.parametrize("name", NAMES)
 @pytest.mark.parametrize("nu", [1, 2])
-def test_relax_apply_matches_oracle(name, nu):
-    fh, H, ol, od, oopts, ob = _pair(name)
+def test_relax_apply_matches_oracle(name, nu, storage):
+    fh, H, ol, od, oopts, ob = _pair(name, storage)
     rng = np.random.default_rng(100 + nu)
     for l in range(len(ol) - 1):
         n = ol[l].n
@@ -75,7 +87,7 @@ def test_relax_apply_matches_oracle(name, nu):
         got = _host(xg)
         ref = omg._relax(ol[l], oopts, b, x, nu, False)
         err = _rel(got, ref)
-        print(f"{name} level {l} nu={nu}: rel err {err:.2e}")
+        print(f"{name} ({storage}) level {l} nu={nu}: rel err {err:.2e}")
         assert err <= 1e-11, (l, err)
 
 
@@ -89,9 +101,10 @@ def test_chebyshev_eigenvalue_estimate_matches_oracle(name):
         assert abs(lam - ol[l].lmax) <= 1e-11 * ol[l].lmax
 
 
+@pytest.mark.parametrize("storage", ["auto", "general"])
 @pytest.mark.parametrize("name", NAMES)
-def test_vcycle_matches_oracle(name):
-    fh, H, ol, od, oopts, ob = _pair(name)
+def test_vcycle_matches_oracle(name, storage):
+    fh, H, ol, od, oopts, ob = _pair(name, storage)
     rng = np.random.default_rng(7)
     b = rng.standard_normal(ol[0].n)
     z = _dev(np.full(ol[0].n, np.nan))          # content on entry is ignored
@@ -99,22 +112,29 @@ def test_vcycle_matches_oracle(name):
     got = _host(z)
     ref = omg.vcycle(ol, oopts, b)
     err = _rel(got, ref)
-    print(f"{name} vcycle rel err {err:.2e}")
+    print(f"{name} ({storage}) vcycle rel err {err:.2e}")
     assert err <= 1e-11
 
 
+_FGMRES_REF = {}
+
+
+@pytest.mark.parametrize("storage", ["auto", "general"])
 @pytest.mark.parametrize("name", NAMES)
-def test_fgmres_iterations_and_solution_match_oracle(name):
-    fh, H, ol, od, oopts, ob = _pair(name)
+def test_fgmres_iterations_and_solution_match_oracle(name, storage):
+    fh, H, ol, od, oopts, ob = _pair(name, storage)
     b = fh.b[0]
     x = _dev(np.zeros_like(b))
     iters, relres, conv = H.fgmres(_dev(b), x, rtol=1e-8, restart=30, maxit=1000)
     got = _host(x)
     K = ol[0].K
-    res = ofgmres.fgmres(lambda v: K @ v, lambda v: omg.vcycle(ol, oopts, v), ob, rtol=1e-8, restart=30, maxit=1000)
+    if name not in _FGMRES_REF:
+        _FGMRES_REF[name] = ofgmres.fgmres(lambda v: K @ v, lambda v: omg.vcycle(ol, oopts, v), ob, rtol=1e-8,
+                                           restart=30, maxit=1000)
+    res = _FGMRES_REF[name]
     nfu = od[0].nfu
     err = np.linalg.norm(_normalise(got, nfu) - _normalise(res.x, nfu)) / np.linalg.norm(_normalise(res.x, nfu))
-    print(f"{name}: GPU iters {iters} relres {relres:.3e}; oracle iters {res.iters} relres {res.relres:.3e}; "
+    print(f"{name} ({storage}): GPU iters {iters} relres {relres:.3e}; oracle iters {res.iters} relres {res.relres:.3e}; "
           f"solution rel err {err:.2e}")
     assert conv and res.converged
     assert iters == res.iters
@@ -277,15 +297,17 @@ def test_p_coarsening_schedules_match_oracle(schedule):
     H.close()
 
 
+@pytest.mark.parametrize("storage", ["auto", "general"])
 @pytest.mark.parametrize("prec", ["f64", "f32", "bf16"])
-def test_every_patch_solve_shape_gives_identical_sweeps(prec):
-    """All compiled kernel shapes of the patch solve (one workgroup per patch and persistent,
-    every tile / unroll choice) produce bit-identical sweeps; the f64 ones also match the oracle."""
+def test_every_patch_solve_shape_gives_identical_sweeps(prec, storage):
+    """All compiled kernel shapes of the patch solve (every unroll choice) produce bit-identical
+    sweeps; the f64 ones also match the oracle."""
     from paper_2407_07253_amd._lib import Hierarchy
     fh, _, ol, od, oopts, ob = _pair("cfg2_r1")
     H = Hierarchy.from_frontend(fh)
     for l in range(len(fh.levels) - 1):
         H.set_precision(l, prec)
+        H.set_patch_storage(l, storage)
     H.setup()
     rng = np.random.default_rng(23)
     for l in range(len(fh.levels) - 1):
@@ -301,5 +323,62 @@ def test_every_patch_solve_shape_gives_identical_sweeps(prec):
             assert np.array_equal(o, outs[0]), (l, v)
         if prec == "f64":
             assert _rel(outs[0], omg._relax(ol[l], oopts, b, x, 2, False)) <= 1e-11
-        print(f"{prec} level {l}: {len(outs)} shapes identical")
+        print(f"{prec} ({storage}) level {l}: {len(outs)} shapes identical")
+    H.close()
+
+
+def test_symmetric_levels_use_the_strip_layout_and_agree_with_the_general_one():
+    """Every level of the Stokes hierarchies is symmetric to rounding, so "auto" stores the strip
+    layout (about 0.56 of the general element count at P4 patch sizes); the two layouts give
+    sweeps equal to 1e-13 relative in f64."""
+    fa, Ha, ol, od, oopts, ob = _pair("cfg2_r1", "auto")
+    fg, Hg, *_ = _pair("cfg2_r1", "general")
+    rng = np.random.default_rng(41)
+    for l in range(len(ol) - 1):
+        ia, ig = Ha.level_info(l), Hg.level_info(l)
+        assert ia["symmetric_storage"] and not ig["symmetric_storage"]
+        ratio = ia["stored_elements"] / ig["stored_elements"]
+        print(f"level {l}: max m {ia['max_m']}, stored elements sym/general {ratio:.3f}")
+        assert ratio < 0.8
+        n = ol[l].n
+        b, x = rng.standard_normal(n), rng.standard_normal(n)
+        xa, xg = _dev(x), _dev(x)
+        Ha.relax_apply(l, _dev(b), xa, 1)
+        Hg.relax_apply(l, _dev(b), xg, 1)
+        assert _rel(_host(xa), _host(xg)) <= 1e-13
+
+
+def test_nonsymmetric_level_keeps_the_general_layout():
+    """A level matrix with a skew-symmetric perturbation (1e-3 of its scale) is not symmetric:
+    "auto" falls back to the general layout, and the sweep still matches the oracle's on the
+    same perturbed matrix; the symmetric levels below keep the strip layout."""
+    import copy
+
+    import scipy.sparse as sp
+
+    from paper_2407_07253_amd._lib import Hierarchy
+    fh0, _, ol0, od, oopts, ob = _pair("cfg1")
+    fh = copy.deepcopy(fh0)
+    K0 = fh.levels[0].K
+    A = sp.csr_matrix((K0.val, K0.col, K0.rowptr), shape=(K0.nrows, K0.ncols))
+    N = sp.csr_matrix((np.random.default_rng(5).standard_normal(A.nnz), A.indices, A.indptr), shape=A.shape)
+    Kp = (A + 1e-3 * abs(A).max() * (N - N.T)).tocsr()
+    Kp.sort_indices()
+    fh.levels[0].K = frontend.Csr.from_scipy(Kp)
+    H = Hierarchy.from_frontend(fh)
+    H.setup()
+    assert not H.level_info(0)["symmetric_storage"]
+    assert H.level_info(1)["npatch"] == 0 or H.level_info(1)["symmetric_storage"]
+    ol = copy.deepcopy(ol0)
+    ol[0].K = Kp
+    omg.setup(ol, oopts)
+    rng = np.random.default_rng(6)
+    n = ol[0].n
+    b, x = rng.standard_normal(n), rng.standard_normal(n)
+    for transpose in (False, True):
+        xg = _dev(x)
+        (H.relax_apply_transposed if transpose else H.relax_apply)(0, _dev(b), xg, 2)
+        err = _rel(_host(xg), omg._relax(ol[0], oopts, b, x, 2, transpose))
+        print(f"perturbed level 0, transpose={transpose}: rel err {err:.2e}")
+        assert err <= 1e-11
     H.close()

@@ -256,13 +256,14 @@ phmg_status phmg_residual(phmg_ctx ctx, int level, const double* b, const double
  * eigenvalue estimate (0 before set-up or for Richardson), the patch-solve
  * kernel shape chosen by the set-up autotuner, the number of shapes
  * compiled for the level's precision and layout, whether the stored inverses
- * use the symmetric layout (after set-up) and their element count. */
+ * use the symmetric layout (after set-up), the SpMV kernel variant of K_l
+ * (see phmg_set_spmv_variant) and the stored element count. */
 typedef struct {
     int32_t n, npatch, max_m, precision;
     int64_t nnz, sum_m, sum_m2;
     double lambda_max;
     int32_t apply_variant, apply_variants;
-    int32_t symmetric_storage, reserved;
+    int32_t symmetric_storage, spmv_variant;
     int64_t stored_elements;
 } phmg_level_info;
 phmg_status phmg_get_level_info(phmg_ctx ctx, int level, phmg_level_info* info);
@@ -272,6 +273,20 @@ phmg_status phmg_get_level_info(phmg_ctx ctx, int level, phmg_level_info* info);
  * precision and layout; kept until either changes).  Every shape computes the
  * same result bit for bit; this exists for tests and tuning studies. */
 phmg_status phmg_set_apply_variant(phmg_ctx ctx, int level, int variant);
+
+/* Override the autotuner's SpMV kernel of one matrix (matrix 0: K_level, 1:
+ * P_level, 2: R_level = P_level^T; the coarsest level has only K), or (matrix
+ * 3) the form of the cycle's restricted residual: variant 0 computes r = b - K
+ * x and then R r, variants 1-6 compute R b - (R K) x in one pass with 2, 4,
+ * ..., 64 lanes per coarse row (R K is formed at create when it has no more
+ * nonzeros than K; otherwise only variant 0 exists).  Variants
+ * 0-5: CSR with 2, 4, ..., 64 lanes per row; 6-11: the same with the rows of
+ * each XCD contiguous; 12: row blocks (at most 32 rows and 1024 nonzeros per
+ * workgroup, products staged in LDS, 8 lanes per row), available when no row
+ * has more than 1024 nonzeros.  Variants differ only in summation order.  Kept
+ * until the next override; for tests and tuning studies.  The adjoint cycle
+ * always uses the two-step form with K^T. */
+phmg_status phmg_set_spmv_variant(phmg_ctx ctx, int level, int matrix, int variant);
 
 /* Optional per-kernel, per-level timing with HIP events recorded on the
  * context stream around every launch of the selected kernels (off by

@@ -63,7 +63,7 @@ class LevelInfoT(C.Structure):
     _fields_ = [("n", C.c_int32), ("npatch", C.c_int32), ("max_m", C.c_int32), ("precision", C.c_int32),
                 ("nnz", C.c_int64), ("sum_m", C.c_int64), ("sum_m2", C.c_int64), ("lambda_max", C.c_double),
                 ("apply_variant", C.c_int32), ("apply_variants", C.c_int32),
-                ("symmetric_storage", C.c_int32), ("reserved", C.c_int32), ("stored_elements", C.c_int64)]
+                ("symmetric_storage", C.c_int32), ("spmv_variant", C.c_int32), ("stored_elements", C.c_int64)]
 
 
 def _sig(name, res, args):
@@ -109,6 +109,8 @@ _fbf_fgmres = _sig("phmg_fbf_fgmres_solve", C.c_int, [C.c_void_p, C.c_void_p, C.
 _fbf_destroy = _sig("phmg_fbf_destroy", C.c_int, [C.c_void_p])
 _set_variant = _sig("phmg_set_apply_variant", C.c_int, [C.c_void_p, C.c_int, C.c_int])
 _set_storage = _sig("phmg_set_patch_storage", C.c_int, [C.c_void_p, C.c_int, C.c_int])
+_set_spmv = _sig("phmg_set_spmv_variant", C.c_int, [C.c_void_p, C.c_int, C.c_int, C.c_int])
+SPMV_VARIANTS = 13
 STORAGE = {"auto": 0, "general": 1}
 MAX_RHS = 16
 
@@ -119,7 +121,7 @@ EXPORTED = ["phmg_hierarchy_create", "phmg_hierarchy_destroy", "phmg_relax_setup
             "phmg_relax_apply_transposed", "phmg_vcycle_transposed", "phmg_fgmres_solve_transposed",
             "phmg_set_sensitivities", "phmg_forcing_rhs", "phmg_gradients",
             "phmg_fbf_create", "phmg_fbf_apply", "phmg_fbf_fgmres_solve", "phmg_fbf_destroy",
-            "phmg_set_apply_variant", "phmg_set_patch_storage",
+            "phmg_set_apply_variant", "phmg_set_patch_storage", "phmg_set_spmv_variant",
             "phmg_last_error"]
 
 
@@ -285,6 +287,11 @@ class Hierarchy:
     def set_precision(self, level: int, prec: str):
         _check(_set_prec(self._h, level, PREC[prec]))
 
+    def set_spmv_variant(self, level: int, matrix: str, variant: int):
+        """Override the autotuned SpMV kernel of K / P / R on a level, or with "RK" the restricted
+        residual's form (0 two-step, 1-6 fused with 2..64 lanes); results differ only in rounding."""
+        _check(_set_spmv(self._h, level, {"K": 0, "P": 1, "R": 2, "RK": 3}[matrix], variant))
+
     def set_patch_storage(self, level: int, storage: str):
         """"auto" (symmetric strip layout when K_l is symmetric to rounding) or "general"."""
         _check(_set_storage(self._h, level, STORAGE[storage]))
@@ -354,7 +361,7 @@ class Hierarchy:
         _check(_info(self._h, level, C.byref(i)))
         return dict(n=i.n, npatch=i.npatch, max_m=i.max_m, precision=i.precision, nnz=i.nnz, sum_m=i.sum_m,
                     sum_m2=i.sum_m2, lambda_max=i.lambda_max, apply_variant=i.apply_variant,
-                    apply_variants=i.apply_variants, symmetric_storage=bool(i.symmetric_storage),
+                    apply_variants=i.apply_variants, symmetric_storage=bool(i.symmetric_storage), spmv_variant=i.spmv_variant,
                     stored_elements=i.stored_elements)
 
     def profile(self, kernels=("patch_apply",)):

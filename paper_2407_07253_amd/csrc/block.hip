@@ -237,7 +237,7 @@ void vcycle_block(phmg_ctx ctx, const double* B, double* X) {
 }
 
 // One block V-cycle (bgin -> bgout) captured on the private stream; kernels
-// only, so a replay is exact.  Rebuilt after any set-up or precision change.
+// only, so a replay is exact.  Rebuilt whenever graph_signature() changes.
 void build_block_graph(phmg_ctx ctx) {
     const int64_t nb = (int64_t)ctx->L[0].n * kBS;
     if (!ctx->cap_stream) hipcheck(hipStreamCreate(&ctx->cap_stream), "hipStreamCreate");
@@ -261,6 +261,7 @@ void build_block_graph(phmg_ctx ctx) {
     ctx->stream = saved;
     hipcheck(hipStreamEndCapture(ctx->cap_stream, &ctx->bgraph), "hipStreamEndCapture");
     hipcheck(hipGraphInstantiate(&ctx->bexec, ctx->bgraph, nullptr, nullptr, 0), "hipGraphInstantiate");
+    ctx->bsig = graph_signature(ctx);
 }
 
 void precond_block(phmg_ctx ctx, const double* B, double* X) {
@@ -268,6 +269,7 @@ void precond_block(phmg_ctx ctx, const double* B, double* X) {
         vcycle_block(ctx, B, X);
         return;
     }
+    if (ctx->bexec && ctx->bsig != graph_signature(ctx)) invalidate_block_graph(ctx);
     if (!ctx->bexec) build_block_graph(ctx);
     const int64_t nb = (int64_t)ctx->L[0].n * kBS;
     launch_copy(ctx->stream, nb, B, ctx->bgin);

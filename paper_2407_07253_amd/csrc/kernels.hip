@@ -101,6 +101,115 @@ __global__ __launch_bounds__(kBlock) void spmv_kernel(int32_t nrows, const int32
 }
 
 // ---------------------------------------------------------------------------
+// y = A1 x1 - A2 x2 (same rows), G lanes per row: the restricted residual
+// R b - (R K) x of the cycle in one pass over the coarse rows.  Each row's two
+// sums are formed as in spmv_kernel and subtracted at the end.
+// ---------------------------------------------------------------------------
+template <int G>
+__global__ __launch_bounds__(kBlock) void spmv_diff_kernel(int32_t nrows, const int32_t* __restrict__ rp1,
+                                                           const int32_t* __restrict__ c1,
+                                                           const double* __restrict__ v1,
+                                                           const double* __restrict__ x1,
+                                                           const int32_t* __restrict__ rp2,
+                                                           const int32_t* __restrict__ c2,
+                                                           const double* __restrict__ v2,
+                                                           const double* __restrict__ x2, double* __restrict__ y) {
+    const int lane = threadIdx.x & (G - 1);
+    const int64_t row = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / G;
+    if (row >= nrows) return;
+    // the row's entries of both matrices as one index range [0, n1 + n2), so the
+    // loads of both are in flight together; lane-strided within each matrix
+    const int b1 = rp1[row], n1 = rp1[row + 1] - b1;
+    const int b2 = rp2[row], n2 = rp2[row + 1] - b2;
+    double s1 = 0.0, s2 = 0.0;
+    for (int t = lane; t < n1 + n2; t += 4 * G) {
+        int c[4];
+        double v[4], xv[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int k = t + u * G;
+            c[u] = 0;
+            v[u] = 0.0;
+            if (k < n1) {
+                c[u] = c1[b1 + k];
+                v[u] = v1[b1 + k];
+            } else if (k < n1 + n2) {
+                c[u] = c2[b2 + k - n1];
+                v[u] = v2[b2 + k - n1];
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int k = t + u * G;
+            xv[u] = k < n1 ? x1[c[u]] : (k < n1 + n2 ? x2[c[u]] : 0.0);
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            if (t + u * G < n1) s1 += v[u] * xv[u];
+            else s2 += v[u] * xv[u];
+        }
+    }
+#pragma unroll
+    for (int off = G / 2; off > 0; off >>= 1) {
+        s1 += __shfl_xor(s1, off, G);
+        s2 += __shfl_xor(s2, off, G);
+    }
+    if (lane == 0) y[row] = s1 - s2;
+}
+
+// ---------------------------------------------------------------------------
+// Row-block SpMV: y = alpha * A x + beta * z (z may alias y).  The rows are cut
+// at create into blocks of at most kRbRows rows and kRbNnz nonzeros; one
+// workgroup per block multiplies all of the block's nonzeros with their x
+// entries into LDS (each thread kRbNnz / 256 consecutive-stride entries, all
+// loads in flight, col / val read fully coalesced), then 8 lanes per row add
+// the row's products (lane-strided, then a fixed xor tree).
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kBlock) void rowblock_spmv_kernel(const int32_t* __restrict__ rblk,
+                                                               const int32_t* __restrict__ rowptr,
+                                                               const int32_t* __restrict__ col,
+                                                               const double* __restrict__ val,
+                                                               const double* __restrict__ x, double alpha,
+                                                               const double* z, double beta, double* y) {
+    constexpr int PER = kRbNnz / kBlock;
+    constexpr int G = kBlock / kRbRows;
+    __shared__ double s_p[kRbNnz];
+    const int r0 = rblk[blockIdx.x], r1 = rblk[blockIdx.x + 1];
+    const int k0 = rowptr[r0], nk = rowptr[r1] - k0;
+    {
+        int c[PER];
+        double v[PER];
+#pragma unroll
+        for (int u = 0; u < PER; ++u) {
+            const int k = threadIdx.x + u * kBlock;
+            c[u] = k < nk ? col[k0 + k] : 0;
+            v[u] = k < nk ? val[k0 + k] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < PER; ++u) {
+            const int k = threadIdx.x + u * kBlock;
+            if (k < nk) s_p[k] = v[u] * x[c[u]];
+        }
+    }
+    __syncthreads();
+    const int lane = threadIdx.x % G, r = r0 + (int)threadIdx.x / G;
+    double s = 0.0;
+    int beg = 0, end = 0;
+    if (r < r1) {
+        beg = rowptr[r] - k0;
+        end = rowptr[r + 1] - k0;
+    }
+    for (int k = beg + lane; k < end; k += G) s += s_p[k];
+#pragma unroll
+    for (int off = G / 2; off > 0; off >>= 1) s += __shfl_xor(s, off, G);
+    if (r < r1 && lane == 0) {
+        double out = alpha * s;
+        if (z) out += beta * z[r];
+        y[r] = out;
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Patch extraction: one workgroup per patch; column-major m x m output.
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(kBlock) void extract_kernel(const int64_t* __restrict__ pptr,
@@ -158,7 +267,8 @@ __global__ __launch_bounds__(kBlock) void extract_kernel(const int64_t* __restri
 // barriers (publish the per-wave candidates; publish a copy of the pivot row).
 // The panel's row swaps are applied to the other columns, which then receive
 // the rank-16 update A[:, R] += (Q - E) A_old[k0:k0+16, R] on MFMA f64
-// 16x16x4 tiles, Q being the eliminated panel in logical row order and E the
+// 16x16x4 tiles (formed transposed so the accumulator tiles map to whole
+// column segments), Q being the eliminated panel in logical row order and E the
 // identity rows of the panel; the panel goes back to A in logical order.
 //
 // The column interchanges that would turn the result into K_i^{-1} are not
@@ -280,7 +390,10 @@ __global__ __launch_bounds__(kBlock) void gj_kernel(const int64_t* __restrict__ 
             }
         }
         __syncthreads();
-        // rank-w update of the other columns on MFMA f64 16x16x4 (A operand from LDS, logical rows)
+        // rank-w update of the other columns on MFMA f64 16x16x4, computed transposed:
+        // A[I, J]^T += A_old[k0:k0+16, J]^T (Q - E)[I, :]^T, so that the accumulator
+        // element v of lane l is A[i0 + l % 16][j0 + l / 16 + 4 v] and each load or
+        // store of the wave covers four 128-byte column segments
         {
             const int nb16 = (m + 15) / 16;
             const int li = lane & 15, lk = lane >> 4;
@@ -294,19 +407,24 @@ __global__ __launch_bounds__(kBlock) void gj_kernel(const int64_t* __restrict__ 
                     const int kk = kt * 4 + lk;
                     bop[kt] = (jv && kk < w) ? A[(k0 + kk) + (int64_t)j * m] : 0.0;
                 }
+                bool cv[4];                                   // columns of the accumulator elements
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int jc = jb * 16 + lk + 4 * v;
+                    cv[v] = jc < m && (jc < k0 || jc >= k0 + w);
+                }
                 for (int ib = 0; ib < nb16; ib += 2) {
                     d4 acc[2];
                     double aop[2][4];
 #pragma unroll
                     for (int h = 0; h < 2; ++h) {
+                        const int i = (ib + h) * 16 + li;
 #pragma unroll
-                        for (int v = 0; v < 4; ++v) {
-                            const int i = (ib + h) * 16 + lk + 4 * v;
-                            acc[h][v] = (jv && i < m) ? A[i + (int64_t)j * m] : 0.0;
-                        }
+                        for (int v = 0; v < 4; ++v)
+                            acc[h][v] = (cv[v] && i < m) ? A[i + (int64_t)(jb * 16 + lk + 4 * v) * m] : 0.0;
 #pragma unroll
                         for (int kt = 0; kt < 4; ++kt) {
-                            const int i = (ib + h) * 16 + li, kk = kt * 4 + lk;
+                            const int kk = kt * 4 + lk;
                             double a = 0.0;
                             if (i < m && kk < w) {
                                 a = Q[s_phys[i] + kk * ldq];
@@ -319,14 +437,14 @@ __global__ __launch_bounds__(kBlock) void gj_kernel(const int64_t* __restrict__ 
                     for (int h = 0; h < 2; ++h)
 #pragma unroll
                         for (int kt = 0; kt < 4; ++kt)
-                            acc[h] = __builtin_amdgcn_mfma_f64_16x16x4f64(aop[h][kt], bop[kt], acc[h], 0, 0, 0);
+                            acc[h] = __builtin_amdgcn_mfma_f64_16x16x4f64(bop[kt], aop[h][kt], acc[h], 0, 0, 0);
 #pragma unroll
-                    for (int h = 0; h < 2; ++h)
+                    for (int h = 0; h < 2; ++h) {
+                        const int i = (ib + h) * 16 + li;
 #pragma unroll
-                        for (int v = 0; v < 4; ++v) {
-                            const int i = (ib + h) * 16 + lk + 4 * v;
-                            if (jv && i < m) A[i + (int64_t)j * m] = acc[h][v];
-                        }
+                        for (int v = 0; v < 4; ++v)
+                            if (cv[v] && i < m) A[i + (int64_t)(jb * 16 + lk + 4 * v) * m] = acc[h][v];
+                    }
                 }
             }
         }
@@ -742,17 +860,36 @@ __device__ inline double block_sum(double v, double* sh) {
     return (sh[0] + sh[1]) + (sh[2] + sh[3]);
 }
 
+// Partial dot products V[:, c] . w of one workgroup's rows, 8 columns at a
+// time (all loads of a chunk in flight; one reduce-scatter over the wave and
+// one LDS step per chunk), stored column-major for reduce_cols_kernel.
+constexpr int kDotChunk = 8;
+
 __global__ __launch_bounds__(kBlock) void multidot_partial_kernel(int64_t n, int ncol, const double* __restrict__ V,
                                                                   int64_t ldv, const double* __restrict__ w,
                                                                   double* __restrict__ partial) {
-    __shared__ double sh[kBlock / kWave];
-    for (int c = 0; c < ncol; ++c) {
-        const double* v = V + (int64_t)c * ldv;
-        double s = 0.0;
-        for (int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlock)
-            s += v[i] * w[i];
-        s = block_sum(s, sh);
-        if (threadIdx.x == 0) partial[(int64_t)c * gridDim.x + blockIdx.x] = s;
+    constexpr int NW = kBlock / kWave;
+    __shared__ double sh[kDotChunk][NW];
+    const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
+    for (int c0 = 0; c0 < ncol; c0 += kDotChunk) {
+        double acc[kDotChunk];
+#pragma unroll
+        for (int u = 0; u < kDotChunk; ++u) acc[u] = 0.0;
+        for (int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlock) {
+            const double wi = w[i];
+#pragma unroll
+            for (int u = 0; u < kDotChunk; ++u)
+                if (c0 + u < ncol) acc[u] += V[i + (int64_t)(c0 + u) * ldv] * wi;
+        }
+        // wave sums of the 8 columns; lane l ends with column l / 8
+        GroupReduce<double, kDotChunk, kWave, 1>::run(acc, lane);
+        if (lane % (kWave / kDotChunk) == 0) sh[lane / (kWave / kDotChunk)][wave] = acc[0];
+        __syncthreads();
+        if (threadIdx.x < kDotChunk && c0 + (int)threadIdx.x < ncol) {
+            const int u = threadIdx.x;
+            partial[(int64_t)(c0 + u) * gridDim.x + blockIdx.x] = (sh[u][0] + sh[u][1]) + (sh[u][2] + sh[u][3]);
+        }
+        __syncthreads();
     }
 }
 
@@ -821,6 +958,11 @@ void launch_copy(hipStream_t s, int64_t n, const double* src, double* dst) {
 void launch_spmv(hipStream_t s, const DevCsr& A, const double* x, double alpha, const double* z, double beta,
                  double* y) {
     if (A.nrows <= 0) return;
+    if (A.rowblock && A.nrb > 0) {
+        hipLaunchKernelGGL(rowblock_spmv_kernel, dim3(A.nrb), dim3(kBlock), 0, s, A.rblk, A.rowptr, A.col, A.val, x,
+                           alpha, z, beta, y);
+        return;
+    }
     const int g = A.group;
     int grid = grid_for((int64_t)A.nrows * g, kBlock);
     if (A.xcd) grid = (grid + 7) / 8 * 8;
@@ -844,6 +986,29 @@ void launch_spmv(hipStream_t s, const DevCsr& A, const double* x, double alpha, 
         default:
             hipLaunchKernelGGL((spmv_kernel<8, false>), dim3(grid_for((int64_t)A.nrows * 8, kBlock)), dim3(kBlock), 0,
                                s, A.nrows, A.rowptr, A.col, A.val, x, alpha, z, beta, y);
+    }
+}
+
+void launch_spmv_diff(hipStream_t s, const DevCsr& A1, const double* x1, const DevCsr& A2, const double* x2,
+                      double* y) {
+    if (A1.nrows <= 0) return;
+    const int g = A2.group;
+    const int grid = grid_for((int64_t)A1.nrows * g, kBlock);
+    switch (g) {
+#define PHMG_DIFF_CASE(G)                                                                                       \
+    case G:                                                                                                     \
+        hipLaunchKernelGGL(spmv_diff_kernel<G>, dim3(grid), dim3(kBlock), 0, s, A1.nrows, A1.rowptr, A1.col,    \
+                           A1.val, x1, A2.rowptr, A2.col, A2.val, x2, y);                                       \
+        break;
+        PHMG_DIFF_CASE(2)
+        PHMG_DIFF_CASE(4)
+        PHMG_DIFF_CASE(8)
+        PHMG_DIFF_CASE(16)
+        PHMG_DIFF_CASE(32)
+#undef PHMG_DIFF_CASE
+        default:
+            hipLaunchKernelGGL(spmv_diff_kernel<64>, dim3(grid_for((int64_t)A1.nrows * 64, kBlock)), dim3(kBlock), 0,
+                               s, A1.nrows, A1.rowptr, A1.col, A1.val, x1, A2.rowptr, A2.col, A2.val, x2, y);
     }
 }
 
@@ -965,7 +1130,7 @@ void launch_coarse_solve(hipStream_t s, const Level& L, const double* b, double*
 }
 
 void launch_multidot(hipStream_t s, int64_t n, int ncol, const double* V, int64_t ldv, const double* w,
-                     double* partial, double* out, bool /*accumulate*/) {
+                     double* partial, double* out) {
     hipLaunchKernelGGL(multidot_partial_kernel, dim3(kRedBlocks), dim3(kBlock), 0, s, n, ncol, V, ldv, w, partial);
     hipLaunchKernelGGL(reduce_cols_kernel, dim3(ncol), dim3(kBlock), 0, s, kRedBlocks, partial, out);
 }

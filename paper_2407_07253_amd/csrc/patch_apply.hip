@@ -158,36 +158,6 @@ void launch_typed(hipStream_t s, const Level& L, const double* r) {
     }
 }
 
-// Sum of N values over groups of G lanes (lane ids that differ only in the
-// bits of (lane / STRIDE) % G), as a butterfly that first scatters: while more
-// than one value is left, each level keeps half of the list (the upper half in
-// the lane whose bit is set) and adds the partner's copy of that half.  On
-// return, for N >= G, the lane with q = (lane / STRIDE) % G holds in x[0 ..
-// N / G) the group sums of elements [q N / G, (q + 1) N / G); for N < G it
-// holds in x[0] the sum of element q / (G / N).  The pairing is fixed, so the
-// result is deterministic.
-template <typename Acc, int N, int G, int STRIDE>
-struct GroupReduce {
-    __device__ static inline void run(Acc* x, int lane) {
-        if constexpr (G > 1) {
-            constexpr int g = G / 2;
-            if constexpr (N > 1) {
-                constexpr int h = N / 2;
-                const bool up = ((lane / STRIDE) & g) != 0;
-#pragma unroll
-                for (int e = 0; e < h; ++e) {
-                    const Acc lo = x[e], hi = x[e + h];
-                    const Acc other = __shfl_xor(up ? lo : hi, g * STRIDE);
-                    x[e] = (up ? hi : lo) + other;
-                }
-                GroupReduce<Acc, h, g, STRIDE>::run(x, lane);
-            } else {
-                x[0] += __shfl_xor(x[0], g * STRIDE);
-                GroupReduce<Acc, 1, g, STRIDE>::run(x, lane);
-            }
-        }
-    }
-};
 
 // Symmetric layout, one workgroup per patch.  A wave covers a strip's 16 rows
 // with RL = 16 / V row lanes (one 16-byte load each) and CL = 64 / RL column
@@ -258,23 +228,25 @@ __global__ __launch_bounds__(kBlock) void patch_apply_sym_kernel(const int32_t* 
     const int p = order[blockIdx.x];
     const int64_t base = pptr[p];
     const int m = (int)(pptr[p + 1] - base);
+    const T* A = F + foff[p];
+    const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
+    const int rl = lane % RL, cl = lane / RL;
+    Acc* yw = s_y + wave * ldbuf;
+    const int ns = (m + kStrip - 1) / kStrip;
+    // this wave's first unit (unit number `wave` in strip-major order): its
+    // factor loads are issued before the residual gather, which they do not need
+    int s = 0, c = 0;
+    bool ok = true;
+    for (int q = 0; q < wave && ok; ++q) ok = sym_step(s, c, ns, m);
+    Acc a[U][V];
+    if (ok) sym_load<T>(A, s, c, m, rl, cl, a);
     for (int t = threadIdx.x; t < m; t += kBlock) {
         const double v = r[pdofs[base + t]];
         s_r[t] = (Acc)(gw ? gw[base + t] * v : v);
     }
     for (int t = threadIdx.x; t < NW * ldbuf; t += kBlock) s_y[t] = (Acc)0;
     __syncthreads();
-    const T* A = F + foff[p];
-    const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
-    const int rl = lane % RL, cl = lane / RL;
-    Acc* yw = s_y + wave * ldbuf;
-    const int ns = (m + kStrip - 1) / kStrip;
-    // this wave's first unit: unit number `wave` in strip-major order
-    int s = 0, c = 0;
-    bool ok = true;
-    for (int q = 0; q < wave && ok; ++q) ok = sym_step(s, c, ns, m);
-    Acc a[U][V];
-    if (PF && ok) sym_load<T>(A, s, c, m, rl, cl, a);
+    bool first = true;
     while (ok) {
         int s2 = s, c2 = c;
         bool ok2 = true;
@@ -282,9 +254,10 @@ __global__ __launch_bounds__(kBlock) void patch_apply_sym_kernel(const int32_t* 
         Acc b[U][V];
         if (PF) {
             if (ok2) sym_load<T>(A, s2, c2, m, rl, cl, b);
-        } else {
+        } else if (!first) {
             sym_load<T>(A, s, c, m, rl, cl, a);
         }
+        first = false;
         const int r0 = s * kStrip, w = min(m, r0 + kStrip);
         Acc rr[V];
 #pragma unroll

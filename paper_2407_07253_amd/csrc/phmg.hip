@@ -56,6 +56,22 @@ DevCsr upload_csr(phmg_ctx ctx, int32_t nrows, int32_t ncols, const std::vector<
     int g = 2;
     while (g < 64 && g * 3 < avg) g *= 2;   // about 3 nonzeros per lane
     d.group = g;
+    // row blocks for the row-block SpMV kernel
+    if (nrows > 0 && d.nnz > 0) {
+        std::vector<int32_t> rb(1, 0);
+        bool ok = true;
+        for (int32_t i = 0; i < nrows && ok; ++i) {
+            const int32_t len = rp[i + 1] - rp[i];
+            if (len > kRbNnz) ok = false;
+            const int32_t b0 = rb.back();
+            if (i - b0 == kRbRows || rp[i + 1] - rp[b0] > kRbNnz) rb.push_back(i);
+        }
+        rb.push_back(nrows);
+        if (ok) {
+            d.nrb = (int32_t)rb.size() - 1;
+            d.rblk = upload(ctx, rb.data(), (int64_t)rb.size());
+        }
+    }
     return d;
 }
 
@@ -115,19 +131,70 @@ bool near_symmetric(const phmg_csr& A) {
     return lower == upper;
 }
 
-DevCsr upload_transpose(phmg_ctx ctx, const phmg_csr& A) {
-    std::vector<int32_t> rp(A.ncols + 1, 0), ci(A.nnz);
-    std::vector<double> v(A.nnz);
-    for (int64_t k = 0; k < A.nnz; ++k) rp[A.col[k] + 1]++;
-    for (int32_t j = 0; j < A.ncols; ++j) rp[j + 1] += rp[j];
-    std::vector<int32_t> pos(rp.begin(), rp.end() - 1);
+struct HostCsr {
+    int32_t nrows = 0, ncols = 0;
+    std::vector<int32_t> rp, ci;
+    std::vector<double> v;
+};
+
+HostCsr host_transpose(const phmg_csr& A) {
+    HostCsr T;
+    T.nrows = A.ncols;
+    T.ncols = A.nrows;
+    T.rp.assign(A.ncols + 1, 0);
+    T.ci.resize(A.nnz);
+    T.v.resize(A.nnz);
+    for (int64_t k = 0; k < A.nnz; ++k) T.rp[A.col[k] + 1]++;
+    for (int32_t j = 0; j < A.ncols; ++j) T.rp[j + 1] += T.rp[j];
+    std::vector<int32_t> pos(T.rp.begin(), T.rp.end() - 1);
     for (int32_t i = 0; i < A.nrows; ++i)
         for (int32_t k = A.rowptr[i]; k < A.rowptr[i + 1]; ++k) {
             const int32_t q = pos[A.col[k]]++;
-            ci[q] = i;
-            v[q] = A.val[k];
+            T.ci[q] = i;
+            T.v[q] = A.val[k];
         }
-    return upload_csr(ctx, A.ncols, A.nrows, rp, ci, v);
+    return T;
+}
+
+DevCsr upload_transpose(phmg_ctx ctx, const phmg_csr& A) {
+    HostCsr T = host_transpose(A);
+    return upload_csr(ctx, T.nrows, T.ncols, T.rp, T.ci, T.v);
+}
+
+// C = A B (row by row with a dense accumulator; columns ascending in each row).
+// Fails when C has 2^31 nonzeros or more.
+HostCsr host_product(const HostCsr& A, const phmg_csr& B) {
+    HostCsr C;
+    C.nrows = A.nrows;
+    C.ncols = B.ncols;
+    C.rp.assign(A.nrows + 1, 0);
+    std::vector<double> acc(B.ncols, 0.0);
+    std::vector<int32_t> mark(B.ncols, -1), cols;
+    for (int32_t i = 0; i < A.nrows; ++i) {
+        cols.clear();
+        for (int32_t k = A.rp[i]; k < A.rp[i + 1]; ++k) {
+            const int32_t j = A.ci[k];
+            const double a = A.v[k];
+            for (int32_t q = B.rowptr[j]; q < B.rowptr[j + 1]; ++q) {
+                const int32_t c = B.col[q];
+                if (mark[c] != i) {
+                    mark[c] = i;
+                    acc[c] = 0.0;
+                    cols.push_back(c);
+                }
+                acc[c] += a * B.val[q];
+            }
+        }
+        std::sort(cols.begin(), cols.end());
+        if ((int64_t)C.ci.size() + (int64_t)cols.size() >= ((int64_t)1 << 31))
+            fail(PHMG_EINVAL, "R K has too many nonzeros");
+        for (int32_t c : cols) {
+            C.ci.push_back(c);
+            C.v.push_back(acc[c]);
+        }
+        C.rp[i + 1] = (int32_t)C.ci.size();
+    }
+    return C;
 }
 
 
@@ -308,9 +375,14 @@ double arnoldi_estimate(phmg_ctx ctx, int l) {
     // step: h, h', ||w||^2); the next basis vector is normalised with the
     // device norm, and the host reads all columns once at the end
     const int S = 2 * (k + 1) + 1;
-    double* Hd = dalloc<double>(ctx, (int64_t)S * k);
+    if (ctx->arnoldi_cap < (int64_t)S * k) {
+        dfree(ctx, ctx->arnoldi_h);
+        ctx->arnoldi_h = dalloc<double>(ctx, (int64_t)S * k);
+        ctx->arnoldi_cap = (int64_t)S * k;
+    }
+    double* Hd = ctx->arnoldi_h;
     launch_power_start(s, n, V);
-    launch_multidot(s, n, 1, V, n, V, ctx->kry.partial, ctx->scal, false);
+    launch_multidot(s, n, 1, V, n, V, ctx->kry.partial, ctx->scal);
     launch_scale_by_devnorm(s, n, V, ctx->scal, V);
     for (int j = 0; j < k; ++j) {
         double* h1 = Hd + (int64_t)j * S;
@@ -319,17 +391,16 @@ double arnoldi_estimate(phmg_ctx ctx, int l) {
         launch_spmv(s, L.K, V + (int64_t)j * n, 1.0, nullptr, 0.0, L.r);
         launch_patch_apply(s, L, L.r);
         launch_scatter(s, L, 1.0, 0.0, nullptr, false, w, true);
-        launch_multidot(s, n, j + 1, V, n, w, ctx->kry.partial, h1, false);
+        launch_multidot(s, n, j + 1, V, n, w, ctx->kry.partial, h1);
         launch_gemv_sub(s, n, j + 1, V, n, h1, w);
-        launch_multidot(s, n, j + 1, V, n, w, ctx->kry.partial, h2, false);
+        launch_multidot(s, n, j + 1, V, n, w, ctx->kry.partial, h2);
         launch_gemv_sub(s, n, j + 1, V, n, h2, w);
-        launch_multidot(s, n, 1, w, n, w, ctx->kry.partial, hn2, false);
+        launch_multidot(s, n, 1, w, n, w, ctx->kry.partial, hn2);
         if (j + 1 < k) launch_scale_by_devnorm(s, n, w, hn2, V + (int64_t)(j + 1) * n);
     }
     std::vector<double> hcols((size_t)S * k);
     hipcheck(hipMemcpyAsync(hcols.data(), Hd, sizeof(double) * S * k, hipMemcpyDeviceToHost, s), "D2H");
     hipcheck(hipStreamSynchronize(s), "hipStreamSynchronize");
-    dfree(ctx, Hd);
     std::vector<double> H((size_t)(k + 1) * k, 0.0);
     int kk = k;
     for (int j = 0; j < k; ++j) {
@@ -361,13 +432,18 @@ void cycle(phmg_ctx ctx, int l, const double* b, double* x, bool x_zero, bool tr
     const int np = ctx->opts.n_plevels;
     const int nu = l < np ? ctx->opts.nu_p : ctx->opts.nu_h;
     relax(ctx, l, b, x, nu, x_zero, transpose);
-    {
+    if (!transpose && L.fuse_restrict) {
         Timed t(ctx, PHMG_K_SPMV, l);
-        launch_spmv(s, transpose ? L.KT : L.K, x, -1.0, b, 1.0, L.r);
-    }
-    {
-        Timed t(ctx, PHMG_K_SPMV, l);
-        launch_spmv(s, L.R, L.r, 1.0, nullptr, 0.0, C.b);
+        launch_spmv_diff(s, L.R, b, L.RK, x, C.b);
+    } else {
+        {
+            Timed t(ctx, PHMG_K_SPMV, l);
+            launch_spmv(s, transpose ? L.KT : L.K, x, -1.0, b, 1.0, L.r);
+        }
+        {
+            Timed t(ctx, PHMG_K_SPMV, l);
+            launch_spmv(s, L.R, L.r, 1.0, nullptr, 0.0, C.b);
+        }
     }
     if (l + 1 < np || l + 1 == last || l >= np) {
         cycle(ctx, l + 1, C.b, C.x, true, transpose);
@@ -399,9 +475,67 @@ void invalidate_graph(phmg_ctx ctx) {
     }
 }
 
+}  // namespace
+
+std::vector<uint64_t> phmg::graph_signature(phmg_ctx ctx) {
+    std::vector<uint64_t> g;
+    auto u = [&](uint64_t v) { g.push_back(v); };
+    auto p = [&](const void* v) { g.push_back((uint64_t)(uintptr_t)v); };
+    auto d = [&](double v) {
+        uint64_t b;
+        std::memcpy(&b, &v, sizeof b);
+        g.push_back(b);
+    };
+    auto csr = [&](const DevCsr& A) {
+        p(A.rowptr);
+        p(A.col);
+        p(A.val);
+        p(A.rblk);
+        u((uint64_t)A.group | (uint64_t)A.xcd << 8 | (uint64_t)A.rowblock << 9 | (uint64_t)A.bgroup << 16 |
+          (uint64_t)A.bxcd << 24);
+    };
+    const phmg_cycle_opts& o = ctx->opts;
+    u((uint64_t)o.nu_p | (uint64_t)o.nu_h << 16 | (uint64_t)o.n_v << 32 | (uint64_t)o.n_plevels << 48);
+    u((uint64_t)o.smoother);
+    d(o.omega);
+    d(o.cheb_lo);
+    d(o.cheb_hi);
+    p(ctx->gin);
+    p(ctx->gout);
+    p(ctx->bgin);
+    p(ctx->bgout);
+    for (const Level& L : ctx->L) {
+        csr(L.K);
+        csr(L.KT);
+        csr(L.P);
+        csr(L.R);
+        csr(L.RK);
+        u((uint64_t)L.fuse_restrict);
+        p(L.factors);
+        p(L.fofflp);
+        p(L.Y);
+        p(L.Yb);
+        p(L.cinv);
+        p(L.r);
+        p(L.b);
+        p(L.x);
+        p(L.d);
+        p(L.rb);
+        p(L.bb);
+        p(L.xb);
+        p(L.db);
+        u((uint64_t)L.prec | (uint64_t)L.sym << 8 | (uint64_t)L.apply_variant << 16 |
+          (uint64_t)L.block_variant << 32);
+        d(L.lmax);
+    }
+    return g;
+}
+
+namespace {
+
 // Capture one V-cycle (gin -> gout) on a private stream.  The cycle launches
 // kernels only (no copies, no memsets, no host synchronisation), so the graph
-// replays it exactly; it is rebuilt after every set-up or precision change.
+// replays it exactly; it is rebuilt whenever graph_signature() changes.
 void build_graph(phmg_ctx ctx, bool transpose) {
     const int64_t n0 = ctx->L[0].n;
     if (!ctx->cap_stream) hipcheck(hipStreamCreate(&ctx->cap_stream), "hipStreamCreate");
@@ -426,6 +560,7 @@ void build_graph(phmg_ctx ctx, bool transpose) {
     const int t = transpose ? 1 : 0;
     hipcheck(hipStreamEndCapture(ctx->cap_stream, &ctx->vgraph[t]), "hipStreamEndCapture");
     hipcheck(hipGraphInstantiate(&ctx->vexec[t], ctx->vgraph[t], nullptr, nullptr, 0), "hipGraphInstantiate");
+    ctx->vsig[t] = graph_signature(ctx);
 }
 
 // x <- B b (one preconditioner application): the captured graph when graphs
@@ -436,6 +571,12 @@ void precond(phmg_ctx ctx, const double* b, double* x, bool transpose = false) {
         return;
     }
     const int t = transpose ? 1 : 0;
+    if (ctx->vexec[t] && ctx->vsig[t] != graph_signature(ctx)) {
+        (void)hipGraphExecDestroy(ctx->vexec[t]);
+        (void)hipGraphDestroy(ctx->vgraph[t]);
+        ctx->vexec[t] = nullptr;
+        ctx->vgraph[t] = nullptr;
+    }
     if (!ctx->vexec[t]) build_graph(ctx, transpose);
     const int64_t n0 = ctx->L[0].n;
     launch_copy(ctx->stream, n0, b, ctx->gin);
@@ -444,6 +585,25 @@ void precond(phmg_ctx ctx, const double* b, double* x, bool transpose = false) {
 }
 
 // Set-up autotuner of the SpMV: lanes per row of one matrix, timed once.
+// SpMV kernel variants: 0-5 CSR with 2, 4, ..., 64 lanes per row, 6-11 the same
+// with XCD-contiguous row ranges, 12 the row-block kernel (when the matrix has
+// row blocks).
+constexpr int kSpmvVariants = 13;
+bool spmv_variant_ok(const DevCsr& A, int v) { return v >= 0 && v < kSpmvVariants && (v < 12 || A.nrb > 0); }
+void set_spmv_variant(DevCsr& A, int v) {
+    if (v < 12) {
+        A.group = 2 << (v % 6);
+        A.xcd = v >= 6;
+    }
+    A.rowblock = v == 12;
+}
+int spmv_variant_of(const DevCsr& A) {
+    if (A.rowblock) return 12;
+    int lg = 0;
+    while ((2 << lg) < A.group) ++lg;
+    return lg + (A.xcd ? 6 : 0);
+}
+
 void tune_spmv(phmg_ctx ctx, DevCsr& A, const double* x, double* y) {
     if (A.tuned || A.nrows == 0) return;
     hipStream_t s = ctx->stream;
@@ -451,12 +611,13 @@ void tune_spmv(phmg_ctx ctx, DevCsr& A, const double* x, double* y) {
     hipcheck(hipEventCreate(&e0), "hipEventCreate");
     hipcheck(hipEventCreate(&e1), "hipEventCreate");
     int best = A.group;
-    bool best_x = false;
+    bool best_x = false, best_rb = false;
     float best_ms = 1e30f;
-    for (int xm = 0; xm < 2; ++xm)
-    for (int g = 2; g <= 64; g *= 2) {
-        A.group = g;
-        A.xcd = xm != 0;
+    for (int cand = 0; cand < kSpmvVariants; ++cand) {
+        if (!spmv_variant_ok(A, cand)) continue;
+        set_spmv_variant(A, cand);
+        const int g = A.group, xm = A.xcd ? 1 : 0;
+        const bool rbk = A.rowblock;
         launch_spmv(s, A, x, 1.0, nullptr, 0.0, y);
         float gbest = 1e30f;
         for (int rep = 0; rep < 3; ++rep) {
@@ -472,6 +633,7 @@ void tune_spmv(phmg_ctx ctx, DevCsr& A, const double* x, double* y) {
             best_ms = gbest;
             best = g;
             best_x = xm != 0;
+            best_rb = rbk;
         }
     }
     (void)hipEventDestroy(e0);
@@ -479,15 +641,66 @@ void tune_spmv(phmg_ctx ctx, DevCsr& A, const double* x, double* y) {
     hipcheck(hipGetLastError(), "spmv autotune launch");
     A.xcd = best_x;
     A.group = best;
+    A.rowblock = best_rb;
     A.tuned = true;
 }
 
+
+// lanes per row of the fused restricted residual (stored in RK.group), and
+// whether it beats the two-step residual + restriction with their own tuned
+// kernels; timed once (after tune_spmv of K and R)
+void tune_spmv_diff(phmg_ctx ctx, Level& L, const double* x, double* y) {
+    DevCsr& A = L.RK;
+    if (A.tuned || A.nrows == 0) return;
+    hipStream_t s = ctx->stream;
+    hipEvent_t e0, e1;
+    hipcheck(hipEventCreate(&e0), "hipEventCreate");
+    hipcheck(hipEventCreate(&e1), "hipEventCreate");
+    int best = A.group;
+    float best_ms = 1e30f;
+    for (int g = 2; g <= 64; g *= 2) {
+        A.group = g;
+        launch_spmv_diff(s, L.R, x, A, x, y);
+        float gbest = 1e30f;
+        for (int rep = 0; rep < 3; ++rep) {
+            hipcheck(hipEventRecord(e0, s), "hipEventRecord");
+            launch_spmv_diff(s, L.R, x, A, x, y);
+            hipcheck(hipEventRecord(e1, s), "hipEventRecord");
+            hipcheck(hipEventSynchronize(e1), "hipEventSynchronize");
+            float ms = 0.f;
+            hipcheck(hipEventElapsedTime(&ms, e0, e1), "hipEventElapsedTime");
+            gbest = std::min(gbest, ms);
+        }
+        if (gbest < best_ms) {
+            best_ms = gbest;
+            best = g;
+        }
+    }
+    float two = 1e30f;
+    for (int rep = 0; rep < 4; ++rep) {
+        hipcheck(hipEventRecord(e0, s), "hipEventRecord");
+        launch_spmv(s, L.K, x, -1.0, x, 1.0, L.r);
+        launch_spmv(s, L.R, L.r, 1.0, nullptr, 0.0, y);
+        hipcheck(hipEventRecord(e1, s), "hipEventRecord");
+        hipcheck(hipEventSynchronize(e1), "hipEventSynchronize");
+        float ms = 0.f;
+        hipcheck(hipEventElapsedTime(&ms, e0, e1), "hipEventElapsedTime");
+        if (rep > 0) two = std::min(two, ms);
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    hipcheck(hipGetLastError(), "spmv autotune launch");
+    A.group = best;
+    A.tuned = true;
+    L.fuse_restrict = best_ms < two;
+}
 
 void setup_level(phmg_ctx ctx, int l) {
     Level& L = ctx->L[l];
     hipStream_t s = ctx->stream;
     const int last = (int)ctx->L.size() - 1;
-    invalidate_graph(ctx);
+    // (captured graphs stay valid while graph_signature() is unchanged; the
+    // set-up reuses its buffers, so repeated set-ups keep them)
     if (l < last) {
         Level& C = ctx->L[l + 1];
         launch_fill(s, L.n, L.d, 1.0);
@@ -495,13 +708,19 @@ void setup_level(phmg_ctx ctx, int l) {
         tune_spmv(ctx, L.K, L.d, L.r);
         tune_spmv(ctx, L.R, L.d, C.b);
         tune_spmv(ctx, L.P, C.x, L.r);
+        tune_spmv_diff(ctx, L, L.d, C.b);
     }
     int32_t st = INT32_MAX;
     hipcheck(hipMemcpyAsync(L.status, &st, sizeof(int32_t), hipMemcpyHostToDevice, s), "status reset");
     if (l == last) {
-        double* dense = dalloc<double>(ctx, (int64_t)L.nb * L.nb);
-        int* piv = dalloc<int>(ctx, L.nb);
-        double* work = dalloc<double>(ctx, (int64_t)(1 + kPanel) * L.nb);
+        if (!L.cdense) {
+            L.cdense = dalloc<double>(ctx, (int64_t)L.nb * L.nb);
+            L.cpiv = dalloc<int>(ctx, L.nb);
+            L.cwork = dalloc<double>(ctx, (int64_t)(1 + kPanel) * L.nb);
+        }
+        double* dense = L.cdense;
+        int* piv = L.cpiv;
+        double* work = L.cwork;
         launch_coarse_build(s, L, dense);
         {
             Timed t(ctx, PHMG_K_FACTOR, l);
@@ -512,16 +731,13 @@ void setup_level(phmg_ctx ctx, int l) {
         launch_transpose(s, L.nb, dense, L.cinv);
         hipcheck(hipMemcpyAsync(&st, L.status, sizeof(int32_t), hipMemcpyDeviceToHost, s), "D2H");
         hipcheck(hipStreamSynchronize(s), "hipStreamSynchronize");
-        dfree(ctx, dense);
-        dfree(ctx, piv);
-        dfree(ctx, work);
         if (st != INT32_MAX) fail(PHMG_ESINGULAR, lvl(l) + "coarse matrix is singular");
         L.ready = true;
         return;
     }
-    if (L.factors) dfree(ctx, L.factors);
-    L.factors = nullptr;
-    double* f64 = dalloc<double>(ctx, L.sum_m2);
+    L.ready = false;
+    if (!L.work64) L.work64 = dalloc<double>(ctx, L.sum_m2);
+    double* f64 = L.work64;
     {
         Timed t(ctx, PHMG_K_EXTRACT, l);
         launch_extract(s, L, f64);
@@ -536,10 +752,7 @@ void setup_level(phmg_ctx ctx, int l) {
     // (pdofs_perm, pidx) unwritten: nothing may read them, so check before converting
     hipcheck(hipMemcpyAsync(&st, L.status, sizeof(int32_t), hipMemcpyDeviceToHost, s), "D2H");
     hipcheck(hipStreamSynchronize(s), "hipStreamSynchronize");
-    if (st != INT32_MAX) {
-        dfree(ctx, f64);
-        fail(PHMG_ESINGULAR, lvl(l) + "patch " + std::to_string(st) + " is singular");
-    }
+    if (st != INT32_MAX) fail(PHMG_ESINGULAR, lvl(l) + "patch " + std::to_string(st) + " is singular");
     {
         // the stored inverses in the level's precision: general layout (columns
         // padded to 16 bytes) or the symmetric strip layout
@@ -548,8 +761,7 @@ void setup_level(phmg_ctx ctx, int l) {
         const int64_t cnt = L.sym ? L.sum_ls[L.prec] : L.sum_lp[L.prec];
         std::vector<int64_t> off(L.npatch);
         {
-            std::vector<int64_t> hp(L.npatch + 1);
-            hipcheck(hipMemcpy(hp.data(), L.pptr, sizeof(int64_t) * (L.npatch + 1), hipMemcpyDeviceToHost), "D2H");
+            const std::vector<int64_t>& hp = L.hptr;
             const int V = factor_pad_of(L.prec);
             int64_t acc = 0;
             for (int32_t i = 0; i < L.npatch; ++i) {
@@ -560,20 +772,27 @@ void setup_level(phmg_ctx ctx, int l) {
             // the allocation below is sized at create (sum_lp); the layout must match it exactly
             if (acc != cnt) fail(PHMG_EINVAL, lvl(l) + "internal: reduced-precision layout size mismatch");
         }
-        if (L.fofflp) dfree(ctx, L.fofflp);
-        L.fofflp = upload(ctx, off.data(), L.npatch);
-        void* lo = nullptr;
-        if (hipMalloc(&lo, es * (size_t)std::max<int64_t>(cnt, 1)) != hipSuccess) {
-            (void)hipGetLastError();
-            fail(PHMG_ENOMEM, lvl(l) + "factor allocation failed");
+        if (!L.fofflp) L.fofflp = dalloc<int64_t>(ctx, L.npatch);
+        hipcheck(hipMemcpy(L.fofflp, off.data(), sizeof(int64_t) * (size_t)L.npatch, hipMemcpyHostToDevice),
+                 "hipMemcpy H2D");
+        const size_t bytes = es * (size_t)std::max<int64_t>(cnt, 1);
+        if (!L.factors || L.factor_bytes < bytes) {
+            if (L.factors) dfree(ctx, L.factors);
+            L.factors = nullptr;
+            L.factor_bytes = 0;
+            void* lo = nullptr;
+            if (hipMalloc(&lo, bytes) != hipSuccess) {
+                (void)hipGetLastError();
+                fail(PHMG_ENOMEM, lvl(l) + "factor allocation failed");
+            }
+            ctx->allocs.push_back(lo);
+            L.factors = lo;
+            L.factor_bytes = bytes;
         }
-        ctx->allocs.push_back(lo);
-        launch_convert_patches(s, L, f64, lo);
+        launch_convert_patches(s, L, f64, L.factors);
         hipcheck(hipGetLastError(), "convert launch");
-        L.factors = lo;
     }
     hipcheck(hipStreamSynchronize(s), "hipStreamSynchronize");
-    dfree(ctx, f64);
     tune_apply(ctx, l);
     if (ctx->opts.smoother == PHMG_SMOOTHER_CHEBYSHEV) {
         L.lmax = arnoldi_estimate(ctx, l);
@@ -584,7 +803,7 @@ void setup_level(phmg_ctx ctx, int l) {
 }
 
 double device_norm(hipStream_t s, Krylov& kr, int64_t n, const double* v) {
-    launch_multidot(s, n, 1, v, n, v, kr.partial, kr.hdev, false);
+    launch_multidot(s, n, 1, v, n, v, kr.partial, kr.hdev);
     hipcheck(hipMemcpyAsync(kr.hhost, kr.hdev, sizeof(double), hipMemcpyDeviceToHost, s), "D2H");
     hipcheck(hipStreamSynchronize(s), "hipStreamSynchronize");
     return std::sqrt(kr.hhost[0]);
@@ -665,11 +884,11 @@ phmg_status fgmres_core(hipStream_t s, Krylov& kr, int64_t n, MatVec matvec, Pre
         double* zj = Z + (int64_t)j * n;
         precond(vj, zj);
         matvec(zj, 1.0, nullptr, 0.0, w);
-        launch_multidot(s, n, j + 1, V, n, w, kr.partial, h1, false);
+        launch_multidot(s, n, j + 1, V, n, w, kr.partial, h1);
         launch_gemv_sub(s, n, j + 1, V, n, h1, w);
-        launch_multidot(s, n, j + 1, V, n, w, kr.partial, h2, false);
+        launch_multidot(s, n, j + 1, V, n, w, kr.partial, h2);
         launch_gemv_sub(s, n, j + 1, V, n, h2, w);
-        launch_multidot(s, n, 1, w, n, w, kr.partial, hn2, false);
+        launch_multidot(s, n, 1, w, n, w, kr.partial, hn2);
         hipcheck(hipMemcpyAsync(kr.hhost + (j & 1) * slot, kr.hdev, sizeof(double) * hs, hipMemcpyDeviceToHost, s),
                  "D2H");
         hipcheck(hipEventRecord(kr.ev[j & 1], s), "hipEventRecord");
@@ -855,7 +1074,15 @@ phmg_status phmg_hierarchy_create(const phmg_hierarchy_desc* desc, const phmg_cy
             }
             if (l + 1 < nl) {
                 L.P = upload_csr(ctx, desc->P[l]);
-                L.R = upload_transpose(ctx, desc->P[l]);
+                {
+                    HostCsr R = host_transpose(desc->P[l]);
+                    L.R = upload_csr(ctx, R.nrows, R.ncols, R.rp, R.ci, R.v);
+                    // the restricted residual R (b - K x) = R b - (R K) x in one pass when
+                    // R K is not larger than K (the cycle never needs the fine residual itself)
+                    HostCsr RK = host_product(R, desc->K[l]);
+                    if ((int64_t)RK.ci.size() <= L.K.nnz)
+                        L.RK = upload_csr(ctx, RK.nrows, RK.ncols, RK.rp, RK.ci, RK.v);
+                }
                 const phmg_patches& pt = desc->patches[l];
                 L.npatch = pt.npatch;
                 L.sum_m = pt.ptr[pt.npatch];
@@ -890,6 +1117,7 @@ phmg_status phmg_hierarchy_create(const phmg_hierarchy_desc* desc, const phmg_cy
                 std::vector<int32_t> pos(sptr.begin(), sptr.end() - 1);
                 for (int64_t t = 0; t < L.sum_m; ++t) sslot[pos[pt.dofs[t]]++] = (int32_t)t;
                 L.pptr = upload(ctx, pt.ptr, pt.npatch + 1);
+                L.hptr.assign(pt.ptr, pt.ptr + pt.npatch + 1);
                 L.pdofs = upload(ctx, pt.dofs, L.sum_m);
                 L.pdofs_perm = dalloc<int32_t>(ctx, L.sum_m);
                 L.pidx = dalloc<int32_t>(ctx, L.sum_m);
@@ -1237,7 +1465,7 @@ phmg_status phmg_get_level_info(phmg_ctx ctx, int level, phmg_level_info* info) 
         info->apply_variant = L.apply_variant;
         info->apply_variants = apply_variant_count(L);
         info->symmetric_storage = L.sym ? 1 : 0;
-        info->reserved = 0;
+        info->spmv_variant = spmv_variant_of(L.K);
         info->stored_elements = L.npatch == 0 ? 0 : (L.sym ? L.sum_ls[L.prec] : L.sum_lp[L.prec]);
         return PHMG_OK;
     });
@@ -1251,6 +1479,31 @@ phmg_status phmg_set_apply_variant(phmg_ctx ctx, int level, int variant) {
         if (variant < 0 || variant >= apply_variant_count(L)) fail(PHMG_EINVAL, "variant out of range");
         L.apply_variant = variant;
         L.tuned_for = tune_key(L);
+        invalidate_graph(ctx);
+        return PHMG_OK;
+    });
+}
+
+phmg_status phmg_set_spmv_variant(phmg_ctx ctx, int level, int matrix, int variant) {
+    return guarded([&]() -> phmg_status {
+        if (!ctx) fail(PHMG_EINVAL, "null context");
+        const int last = (int)ctx->L.size() - 1;
+        if (level < 0 || level > last) fail(PHMG_EINVAL, "level out of range");
+        if (matrix < 0 || matrix > 3 || (matrix > 0 && level == last)) fail(PHMG_EINVAL, "matrix out of range");
+        Level& L = ctx->L[level];
+        if (matrix == 3) {
+            // the restricted residual: 0 two-step, 1-6 fused R b - (R K) x with 2 .. 64 lanes per row
+            if (variant < 0 || variant > 6 || (variant > 0 && L.RK.nrows == 0)) fail(PHMG_EINVAL, "variant out of range");
+            L.fuse_restrict = variant > 0;
+            if (variant > 0) L.RK.group = 1 << variant;
+            L.RK.tuned = true;
+            invalidate_graph(ctx);
+            return PHMG_OK;
+        }
+        DevCsr& A = matrix == 0 ? L.K : (matrix == 1 ? L.P : L.R);
+        if (!spmv_variant_ok(A, variant)) fail(PHMG_EINVAL, "variant out of range");
+        set_spmv_variant(A, variant);
+        A.tuned = true;
         invalidate_graph(ctx);
         return PHMG_OK;
     });

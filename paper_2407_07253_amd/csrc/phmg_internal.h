@@ -17,6 +17,8 @@ constexpr int kWave = 64;
 constexpr int kPanel = 16;           // Gauss-Jordan panel width = MFMA f64 16x16x4 tile edge
 constexpr int kRedBlocks = 512;      // fixed grid of the deterministic reductions
 constexpr int kBS = 16;              // columns of a block vector (right-hand sides solved together)
+constexpr int kRbRows = 32;          // rows of an SpMV row block (8 lanes per row)
+constexpr int kRbNnz = 1024;         // nonzeros of an SpMV row block (4 per thread)
 
 // Leading dimension padding of the stored patch inverses: every column is
 // padded to a multiple of 16 bytes (f64: 2 rows, f32: 4, bf16: 8; padding rows
@@ -50,6 +52,10 @@ struct DevCsr {
     int group = 8;                   // lanes per row in the SpMV (chosen by the set-up autotuner)
     bool xcd = false;                // XCD-contiguous row ranges in the SpMV (autotuned)
     bool tuned = false;
+    // row blocks of at most kRbRows rows and kRbNnz nonzeros (absent when a row is longer)
+    int32_t nrb = 0;
+    int32_t* rblk = nullptr;         // nrb + 1 block boundaries (row indices)
+    bool rowblock = false;           // SpMV kernel: row-block (else CSR with `group` lanes per row); autotuned
     int bgroup = 1;                  // entries in flight per row in the block SpMM (autotuned on first use)
     bool bxcd = false;               // XCD-contiguous row ranges in the block SpMM (autotuned)
     bool btuned = false;
@@ -61,6 +67,8 @@ struct Level {
     DevCsr KT;                       // K^T (shares K's arrays when K is symmetric)
     DevCsr P;                        // prolongation from level+1 into this level (n x n_{l+1})
     DevCsr R;                        // restriction R = P^T (n_{l+1} x n)
+    DevCsr RK;                       // R K (n_{l+1} x n): the restricted residual R b - (R K) x in one pass
+    bool fuse_restrict = false;      // use RK (autotuned against the two-step residual + restriction)
 
     // Vanka-star patches (absent on the coarsest level)
     int32_t npatch = 0;
@@ -84,8 +92,10 @@ struct Level {
     int32_t* sptr = nullptr;         // DoF -> slot map for the scatter (n + 1)
     int32_t* sslot = nullptr;        // sum_m slot indices, ascending patch id per DoF
     double* Y = nullptr;             // sum_m staging of the patch solutions
-    void* factors = nullptr;         // explicit patch inverses, column-major, precision `prec`
-    double* work64 = nullptr;        // float64 set-up buffer when prec != F64
+    void* factors = nullptr;         // explicit patch inverses in the stored layout, precision `prec`
+    size_t factor_bytes = 0;         // allocated size of `factors` (kept across set-ups)
+    double* work64 = nullptr;        // float64 set-up buffer, m x m per patch (kept across set-ups)
+    std::vector<int64_t> hptr;       // host copy of pptr
     int prec = PHMG_PREC_F64;
     int apply_variant = 0;           // kernel shape of the patch solve (chosen by the set-up autotuner)
     int tuned_for = -1;              // precision the shape was tuned for
@@ -93,6 +103,9 @@ struct Level {
     // coarsest level: dense inverse of the (bordered) matrix, row-major
     double* cinv = nullptr;
     double* cnull = nullptr;
+    double* cdense = nullptr;        // set-up work of the coarse inversion (kept across set-ups)
+    int* cpiv = nullptr;
+    double* cwork = nullptr;
     int32_t nb = 0;                  // n or n + 1
 
     // Chebyshev smoothing: direction vector and the eigenvalue estimate
@@ -161,6 +174,9 @@ struct phmg_ctx_s {
     hipStream_t cap_stream = nullptr;
     hipGraph_t vgraph[2] = {nullptr, nullptr};      // [0] B, [1] B^T (adjoint cycle)
     hipGraphExec_t vexec[2] = {nullptr, nullptr};
+    std::vector<uint64_t> vsig[2];                  // graph_signature() when each graph was captured
+    double* arnoldi_h = nullptr;                    // device columns of the Arnoldi projections
+    int64_t arnoldi_cap = 0;
     double* gin = nullptr;
     double* gout = nullptr;
     // adjoint gradients: dK/dtheta over K_0's nonzeros, the forcing map G and G^T
@@ -181,6 +197,7 @@ struct phmg_ctx_s {
     double* bgout = nullptr;
     hipGraph_t bgraph = nullptr;
     hipGraphExec_t bexec = nullptr;
+    std::vector<uint64_t> bsig;
 };
 
 // The full-block-factorisation preconditioner: a velocity-block hierarchy (its
@@ -199,12 +216,51 @@ struct phmg_fbf_s {
 
 namespace phmg {
 
+// Sum of N values over groups of G lanes (lane ids that differ only in the
+// bits of (lane / STRIDE) % G), as a butterfly that first scatters: while more
+// than one value is left, each level keeps half of the list (the upper half in
+// the lane whose bit is set) and adds the partner's copy of that half.  On
+// return, for N >= G, the lane with q = (lane / STRIDE) % G holds in x[0 ..
+// N / G) the group sums of elements [q N / G, (q + 1) N / G); for N < G it
+// holds in x[0] the sum of element q / (G / N).  The pairing is fixed, so the
+// result is deterministic.
+template <typename Acc, int N, int G, int STRIDE>
+struct GroupReduce {
+    __device__ static inline void run(Acc* x, int lane) {
+        if constexpr (G > 1) {
+            constexpr int g = G / 2;
+            if constexpr (N > 1) {
+                constexpr int h = N / 2;
+                const bool up = ((lane / STRIDE) & g) != 0;
+#pragma unroll
+                for (int e = 0; e < h; ++e) {
+                    const Acc lo = x[e], hi = x[e + h];
+                    const Acc other = __shfl_xor(up ? lo : hi, g * STRIDE);
+                    x[e] = (up ? hi : lo) + other;
+                }
+                GroupReduce<Acc, h, g, STRIDE>::run(x, lane);
+            } else {
+                x[0] += __shfl_xor(x[0], g * STRIDE);
+                GroupReduce<Acc, 1, g, STRIDE>::run(x, lane);
+            }
+        }
+    }
+};
+
+// Every host-side value a captured V-cycle bakes into its kernel arguments
+// (buffers, kernel variants, precisions, layouts, Chebyshev intervals, cycle
+// options): a graph is replayed only while this is unchanged.
+std::vector<uint64_t> graph_signature(phmg_ctx ctx);
+
 // ---- launchers (kernels.hip) ------------------------------------------------
 void launch_fill(hipStream_t s, int64_t n, double* x, double v);
 void launch_fill_i32(hipStream_t s, int64_t n, int32_t* x, int32_t v);
 // y = alpha * A x + beta * z   (z may be null, or alias y)
 void launch_spmv(hipStream_t s, const DevCsr& A, const double* x, double alpha, const double* z, double beta,
                  double* y);
+// y = A1 x1 - A2 x2 for two matrices with the same rows (lanes per row: A2.group)
+void launch_spmv_diff(hipStream_t s, const DevCsr& A1, const double* x1, const DevCsr& A2, const double* x2,
+                      double* y);
 void launch_extract(hipStream_t s, const Level& L, double* out);
 // invert every patch matrix of the level in place (stored as (P K_i)^{-1}, see kernels.hip)
 void launch_patch_factor(hipStream_t s, const Level& L, double* A);
@@ -234,8 +290,9 @@ void launch_coarse_solve_t(hipStream_t s, const Level& L, const double* b, doubl
 void launch_pair_products(hipStream_t s, const DevCsr& K, int nrhs, const double* X, const double* Lam,
                           double* w);
 // FGMRES helpers
+// out[c] = V[:, c] . w (c < ncol); partial holds kRedBlocks x ncol doubles
 void launch_multidot(hipStream_t s, int64_t n, int ncol, const double* V, int64_t ldv, const double* w,
-                     double* partial, double* out, bool accumulate);
+                     double* partial, double* out);
 void launch_gemv_sub(hipStream_t s, int64_t n, int ncol, const double* V, int64_t ldv, const double* h, double* w);
 void launch_gemv_add(hipStream_t s, int64_t n, int ncol, const double* Z, int64_t ldz, const double* y, double* x);
 void launch_scale_copy(hipStream_t s, int64_t n, const double* src, double denom, double* dst);  // dst = src / denom

@@ -267,6 +267,98 @@ def test_graph_replays_equal_eager_launches(name):
     H.close()
 
 
+def test_graphs_follow_set_ups_precision_and_kernel_changes():
+    """A captured V-cycle is replayed only while everything it baked in is unchanged: after a
+    repeated set-up, a precision change, a layout change and an SpMV kernel override the replayed
+    V-cycle equals the eager one bit for bit."""
+    from paper_2407_07253_amd._lib import Hierarchy
+    fh = frontend.build_hierarchy("cfg2_r1")
+    H = Hierarchy.from_frontend(fh)
+    H.setup()
+    n = fh.levels[0].n
+    b = _dev(np.random.default_rng(31).standard_normal(n))
+
+    def both():
+        # graph replay, then the eager cycle (per-kernel profiling forces eager launches and
+        # leaves the captured graph in place)
+        out = []
+        for eager in (False, True):
+            H.profile(["spmv"] if eager else [])
+            z = _dev(np.full(n, np.nan))
+            H.vcycle(b, z)
+            out.append(_host(z))
+        H.profile([])
+        assert np.array_equal(out[0], out[1])
+        return out[0]
+
+    z0 = both()
+    H.setup()
+    assert np.array_equal(both(), z0)
+    H.set_precision(0, "f32")
+    H.setup(0)
+    z1 = both()
+    assert not np.array_equal(z1, z0)
+    H.set_patch_storage(1, "general")
+    H.setup(1)
+    both()
+    H.set_spmv_variant(0, "K", 12)
+    both()
+    H.set_precision(0, "f64")
+    H.set_patch_storage(1, "auto")
+    H.setup()
+    H.set_spmv_variant(0, "K", H.level_info(0)["spmv_variant"])
+    both()
+    H.close()
+
+
+def test_every_spmv_kernel_variant_gives_the_residual():
+    """All SpMV kernels (CSR with 2..64 lanes per row, XCD-contiguous order, row blocks) give the
+    residual of every level to rounding (1e-14 relative to |b| + |K||x|)."""
+    from paper_2407_07253_amd._lib import SPMV_VARIANTS, Hierarchy, PhmgError
+    fh, _, ol, od, oopts, ob = _pair("cfg2_r1")
+    H = Hierarchy.from_frontend(fh)
+    H.setup()
+    rng = np.random.default_rng(19)
+    for l in range(len(ol)):
+        n = ol[l].n
+        b, x = rng.standard_normal(n), rng.standard_normal(n)
+        ref = b - ol[l].K @ x
+        scale = np.abs(b) + abs(ol[l].K) @ np.abs(x)
+        tried = 0
+        for v in range(SPMV_VARIANTS):
+            try:
+                H.set_spmv_variant(l, "K", v)
+            except PhmgError:
+                continue
+            r = _dev(np.zeros(n))
+            H.residual(l, _dev(b), _dev(x), r)
+            err = float(np.max(np.abs(_host(r) - ref) / scale))
+            assert err <= 1e-14, (l, v, err)
+            tried += 1
+        assert tried >= 12
+    H.close()
+
+
+@pytest.mark.parametrize("form", [0, 1, 4, 6])
+def test_restricted_residual_forms_match_oracle(form):
+    """The cycle's restriction of the residual, as r = b - K x then R r (form 0) or in one pass
+    R b - (R K) x (forms 1-6: 2..64 lanes per coarse row) on every level: the V-cycle matches the
+    oracle's to 1e-11 either way."""
+    from paper_2407_07253_amd._lib import Hierarchy
+    fh, _, ol, od, oopts, ob = _pair("cfg2_r1")
+    H = Hierarchy.from_frontend(fh)
+    H.setup()
+    for l in range(len(ol) - 1):
+        H.set_spmv_variant(l, "RK", form)
+    b = np.random.default_rng(12).standard_normal(ol[0].n)
+    z = _dev(np.zeros(ol[0].n))
+    H.vcycle(_dev(b), z)
+    err = _rel(_host(z), omg.vcycle(ol, oopts, b))
+    print(f"restriction form {form}: vcycle rel err {err:.2e}")
+    assert err <= 1e-11
+    H.close()
+
+
 @pytest.mark.parametrize("schedule", ["direct", "gradual"])
 def test_p_coarsening_schedules_match_oracle(schedule):
     """TH P6/P5 on the structured 8x8 mesh: phMG(direct) P6 -> P2 and phMG(gradual)

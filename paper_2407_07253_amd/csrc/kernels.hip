@@ -893,6 +893,59 @@ __global__ __launch_bounds__(kBlock) void multidot_partial_kernel(int64_t n, int
     }
 }
 
+// One Gram-Schmidt pass fused with the next reduction: w -= V h (h read from
+// the device, the subtraction in the order of gemv_sub_kernel) and, from the
+// same loaded basis values, the partial dot products V^T w of the updated w
+// (NORM: the partial sum of w_i^2 instead).  ncol <= kGsMax.
+constexpr int kGsMax = 32;
+
+template <bool NORM>
+__global__ __launch_bounds__(kBlock) void gs_update_kernel(int64_t n, int ncol, const double* __restrict__ V,
+                                                           int64_t ldv, const double* __restrict__ h,
+                                                           double* __restrict__ w, double* __restrict__ partial) {
+    constexpr int NW = kBlock / kWave;
+    constexpr int NA = NORM ? 1 : kGsMax;
+    __shared__ double s_h[kGsMax];
+    __shared__ double sh[NA][NW];
+    const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
+    if (threadIdx.x < kGsMax) s_h[threadIdx.x] = (int)threadIdx.x < ncol ? h[threadIdx.x] : 0.0;
+    __syncthreads();
+    double acc[NA];
+#pragma unroll
+    for (int c = 0; c < NA; ++c) acc[c] = 0.0;
+    for (int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlock) {
+        double v[kGsMax];
+#pragma unroll
+        for (int c = 0; c < kGsMax; ++c) v[c] = c < ncol ? V[i + (int64_t)c * ldv] : 0.0;
+        double s = 0.0;
+#pragma unroll
+        for (int c = 0; c < kGsMax; ++c)
+            if (c < ncol) s += v[c] * s_h[c];
+        const double wi = w[i] - s;
+        w[i] = wi;
+        if constexpr (NORM) {
+            acc[0] += wi * wi;
+        } else {
+#pragma unroll
+            for (int c = 0; c < kGsMax; ++c) acc[c] += v[c] * wi;
+        }
+    }
+    if constexpr (NORM) {
+        for (int off = kWave / 2; off > 0; off >>= 1) acc[0] += __shfl_xor(acc[0], off);
+        if (lane == 0) sh[0][wave] = acc[0];
+    } else {
+        // lane l ends with column l / 2
+        GroupReduce<double, kGsMax, kWave, 1>::run(acc, lane);
+        if (lane % 2 == 0) sh[lane / 2][wave] = acc[0];
+    }
+    __syncthreads();
+    const int nout = NORM ? 1 : ncol;
+    if ((int)threadIdx.x < nout) {
+        const int c = threadIdx.x;
+        partial[(int64_t)c * gridDim.x + blockIdx.x] = (sh[c][0] + sh[c][1]) + (sh[c][2] + sh[c][3]);
+    }
+}
+
 __global__ __launch_bounds__(kBlock) void reduce_cols_kernel(int nparts, const double* __restrict__ partial,
                                                              double* __restrict__ out) {
     __shared__ double sh[kBlock / kWave];
@@ -1133,6 +1186,19 @@ void launch_multidot(hipStream_t s, int64_t n, int ncol, const double* V, int64_
                      double* partial, double* out) {
     hipLaunchKernelGGL(multidot_partial_kernel, dim3(kRedBlocks), dim3(kBlock), 0, s, n, ncol, V, ldv, w, partial);
     hipLaunchKernelGGL(reduce_cols_kernel, dim3(ncol), dim3(kBlock), 0, s, kRedBlocks, partial, out);
+}
+
+int gs_max_cols() { return kGsMax; }
+
+void launch_gs_update(hipStream_t s, int64_t n, int ncol, const double* V, int64_t ldv, const double* h, double* w,
+                      double* partial, double* out, bool norm) {
+    if (norm)
+        hipLaunchKernelGGL(gs_update_kernel<true>, dim3(kRedBlocks), dim3(kBlock), 0, s, n, ncol, V, ldv, h, w,
+                           partial);
+    else
+        hipLaunchKernelGGL(gs_update_kernel<false>, dim3(kRedBlocks), dim3(kBlock), 0, s, n, ncol, V, ldv, h, w,
+                           partial);
+    hipLaunchKernelGGL(reduce_cols_kernel, dim3(norm ? 1 : ncol), dim3(kBlock), 0, s, kRedBlocks, partial, out);
 }
 
 void launch_gemv_sub(hipStream_t s, int64_t n, int ncol, const double* V, int64_t ldv, const double* h, double* w) {

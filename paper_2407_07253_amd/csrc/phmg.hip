@@ -361,6 +361,23 @@ double ritz_max_real(const double* H, int ldh, int k) {
 void ensure_krylov(phmg_ctx ctx, int restart);
 double device_norm(hipStream_t s, Krylov& kr, int64_t n, const double* v);
 
+// Classical Gram-Schmidt twice against the ncol basis vectors V: h1 = V^T w,
+// w -= V h1, h2 = V^T w, w -= V h2, hn2 = w . w.  The subtraction and the next
+// products share one read of the basis (three passes instead of five).
+void cgs2(hipStream_t s, Krylov& kr, int64_t n, int ncol, const double* V, double* w, double* h1, double* h2,
+          double* hn2) {
+    launch_multidot(s, n, ncol, V, n, w, kr.partial, h1);
+    if (ncol <= gs_max_cols()) {
+        launch_gs_update(s, n, ncol, V, n, h1, w, kr.partial, h2, false);
+        launch_gs_update(s, n, ncol, V, n, h2, w, kr.partial, hn2, true);
+    } else {
+        launch_gemv_sub(s, n, ncol, V, n, h1, w);
+        launch_multidot(s, n, ncol, V, n, w, kr.partial, h2);
+        launch_gemv_sub(s, n, ncol, V, n, h2, w);
+        launch_multidot(s, n, 1, w, n, w, kr.partial, hn2);
+    }
+}
+
 // lambda_max(M^{-1} K): largest real Ritz value of eig_iters Arnoldi steps
 // (CGS2) from v_0 = (1 + sin(j)/2) / ||.||, all vectors on the device.
 double arnoldi_estimate(phmg_ctx ctx, int l) {
@@ -391,11 +408,7 @@ double arnoldi_estimate(phmg_ctx ctx, int l) {
         launch_spmv(s, L.K, V + (int64_t)j * n, 1.0, nullptr, 0.0, L.r);
         launch_patch_apply(s, L, L.r);
         launch_scatter(s, L, 1.0, 0.0, nullptr, false, w, true);
-        launch_multidot(s, n, j + 1, V, n, w, ctx->kry.partial, h1);
-        launch_gemv_sub(s, n, j + 1, V, n, h1, w);
-        launch_multidot(s, n, j + 1, V, n, w, ctx->kry.partial, h2);
-        launch_gemv_sub(s, n, j + 1, V, n, h2, w);
-        launch_multidot(s, n, 1, w, n, w, ctx->kry.partial, hn2);
+        cgs2(s, ctx->kry, n, j + 1, V, w, h1, h2, hn2);
         if (j + 1 < k) launch_scale_by_devnorm(s, n, w, hn2, V + (int64_t)(j + 1) * n);
     }
     std::vector<double> hcols((size_t)S * k);
@@ -604,8 +617,26 @@ int spmv_variant_of(const DevCsr& A) {
     return lg + (A.xcd ? 6 : 0);
 }
 
+// Matrices with fewer rows than this are latency-bound inside the cycle, where
+// their data is no longer in cache: timing them in isolation (hot caches) would
+// mislead, so they get the lanes-per-row that needs one pass of 4 entries per
+// lane for an average row (fewest dependent loads).
+constexpr int kSmallRows = 16384;
+int lanes_for(double avg_row) {
+    int g = 2;
+    while (g < 64 && 4 * g < avg_row) g *= 2;
+    return g;
+}
+
 void tune_spmv(phmg_ctx ctx, DevCsr& A, const double* x, double* y) {
     if (A.tuned || A.nrows == 0) return;
+    if (A.nrows < kSmallRows) {
+        A.group = lanes_for((double)A.nnz / A.nrows);
+        A.xcd = false;
+        A.rowblock = false;
+        A.tuned = true;
+        return;
+    }
     hipStream_t s = ctx->stream;
     hipEvent_t e0, e1;
     hipcheck(hipEventCreate(&e0), "hipEventCreate");
@@ -652,6 +683,12 @@ void tune_spmv(phmg_ctx ctx, DevCsr& A, const double* x, double* y) {
 void tune_spmv_diff(phmg_ctx ctx, Level& L, const double* x, double* y) {
     DevCsr& A = L.RK;
     if (A.tuned || A.nrows == 0) return;
+    if (A.nrows < kSmallRows) {              // one launch instead of two always wins here
+        A.group = lanes_for((double)(A.nnz + L.R.nnz) / A.nrows);
+        A.tuned = true;
+        L.fuse_restrict = true;
+        return;
+    }
     hipStream_t s = ctx->stream;
     hipEvent_t e0, e1;
     hipcheck(hipEventCreate(&e0), "hipEventCreate");
@@ -884,11 +921,7 @@ phmg_status fgmres_core(hipStream_t s, Krylov& kr, int64_t n, MatVec matvec, Pre
         double* zj = Z + (int64_t)j * n;
         precond(vj, zj);
         matvec(zj, 1.0, nullptr, 0.0, w);
-        launch_multidot(s, n, j + 1, V, n, w, kr.partial, h1);
-        launch_gemv_sub(s, n, j + 1, V, n, h1, w);
-        launch_multidot(s, n, j + 1, V, n, w, kr.partial, h2);
-        launch_gemv_sub(s, n, j + 1, V, n, h2, w);
-        launch_multidot(s, n, 1, w, n, w, kr.partial, hn2);
+        cgs2(s, kr, n, j + 1, V, w, h1, h2, hn2);
         hipcheck(hipMemcpyAsync(kr.hhost + (j & 1) * slot, kr.hdev, sizeof(double) * hs, hipMemcpyDeviceToHost, s),
                  "D2H");
         hipcheck(hipEventRecord(kr.ev[j & 1], s), "hipEventRecord");

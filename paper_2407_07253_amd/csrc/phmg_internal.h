@@ -293,6 +293,10 @@ void launch_pair_products(hipStream_t s, const DevCsr& K, int nrhs, const double
 // out[c] = V[:, c] . w (c < ncol); partial holds kRedBlocks x ncol doubles
 void launch_multidot(hipStream_t s, int64_t n, int ncol, const double* V, int64_t ldv, const double* w,
                      double* partial, double* out);
+// w -= V h (ncol <= gs_max_cols()), then out = V^T w (ncol values) or, with norm, out[0] = w . w
+void launch_gs_update(hipStream_t s, int64_t n, int ncol, const double* V, int64_t ldv, const double* h, double* w,
+                      double* partial, double* out, bool norm);
+int gs_max_cols();
 void launch_gemv_sub(hipStream_t s, int64_t n, int ncol, const double* V, int64_t ldv, const double* h, double* w);
 void launch_gemv_add(hipStream_t s, int64_t n, int ncol, const double* Z, int64_t ldz, const double* y, double* x);
 void launch_scale_copy(hipStream_t s, int64_t n, const double* src, double denom, double* dst);  // dst = src / denom

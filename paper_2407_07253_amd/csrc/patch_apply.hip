@@ -191,20 +191,21 @@ __device__ inline bool sym_step(int& s, int& c, int ns, int m) {
     return s < ns;
 }
 
+// Loads of one unit without branches: a column past the strip's width reads
+// the last stored column and a row group past the strip's height the last row
+// group (both inside the patch's block, finite values).  The caller multiplies
+// such loads only by zero residual entries (rows >= m, columns >= w) or drops
+// their row sums, so they contribute nothing.
 template <typename T>
 __device__ inline void sym_load(const T* A, int s, int c_lo, int m, int rl, int cl,
                                 typename Load16<T>::acc_t (&a)[SymShape<T>::U][SymShape<T>::V]) {
     typedef SymShape<T> Sh;
     const int r0 = s * kStrip, h = min(kStrip, m - r0), hp = (h + Sh::V - 1) / Sh::V * Sh::V, w = r0 + h;
-    const T* S = A + sym_strip_offset(s) + rl * Sh::V;
-    const bool rowv = rl * Sh::V < hp;
+    const T* S = A + sym_strip_offset(s) + min(rl * Sh::V, hp - Sh::V);
 #pragma unroll
     for (int u = 0; u < Sh::U; ++u) {
-        const int j = c_lo + cl + Sh::CL * u;
-        if (rowv && j < w) Load16<T>::load(S + (int64_t)j * hp, a[u]);
-        else
-#pragma unroll
-            for (int v = 0; v < Sh::V; ++v) a[u][v] = 0;
+        const int j = min(c_lo + cl + Sh::CL * u, w - 1);
+        Load16<T>::load(S + j * hp, a[u]);
     }
 }
 
@@ -271,7 +272,7 @@ __global__ __launch_bounds__(kBlock) void patch_apply_sym_kernel(const int32_t* 
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             const int j = c + cl + CL * u;
-            const Acc rj = j < w ? s_r[j] : (Acc)0;
+            const Acc rj = j < w ? s_r[min(j, w - 1)] : (Acc)0;
             Acc dd = (Acc)0;
 #pragma unroll
             for (int v = 0; v < V; ++v) {

@@ -216,6 +216,30 @@ struct phmg_fbf_s {
 
 namespace phmg {
 
+// Exchange with the lane whose id differs by MASK: lane-pair swaps inside a quad
+// (MASK 1, 2) and the half-row rotation (MASK 8) are DPP moves on the VALU;
+// other masks go through ds_bpermute.
+template <int MASK>
+__device__ inline float xor_shfl(float v) {
+    if constexpr (MASK == 1 || MASK == 2 || MASK == 8) {
+        constexpr int ctrl = MASK == 1 ? 0xB1 : (MASK == 2 ? 0x4E : 0x128);   // quad_perm / row_ror:8
+        return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), ctrl, 0xF, 0xF, false));
+    } else {
+        return __shfl_xor(v, MASK);
+    }
+}
+template <int MASK>
+__device__ inline double xor_shfl(double v) {
+    if constexpr (MASK == 1 || MASK == 2 || MASK == 8) {
+        constexpr int ctrl = MASK == 1 ? 0xB1 : (MASK == 2 ? 0x4E : 0x128);
+        const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), ctrl, 0xF, 0xF, false);
+        const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), ctrl, 0xF, 0xF, false);
+        return __hiloint2double(hi, lo);
+    } else {
+        return __shfl_xor(v, MASK);
+    }
+}
+
 // Sum of N values over groups of G lanes (lane ids that differ only in the
 // bits of (lane / STRIDE) % G), as a butterfly that first scatters: while more
 // than one value is left, each level keeps half of the list (the upper half in
@@ -223,7 +247,7 @@ namespace phmg {
 // return, for N >= G, the lane with q = (lane / STRIDE) % G holds in x[0 ..
 // N / G) the group sums of elements [q N / G, (q + 1) N / G); for N < G it
 // holds in x[0] the sum of element q / (G / N).  The pairing is fixed, so the
-// result is deterministic.
+// result is deterministic.  Every lane of the wave must be active.
 template <typename Acc, int N, int G, int STRIDE>
 struct GroupReduce {
     __device__ static inline void run(Acc* x, int lane) {
@@ -235,12 +259,12 @@ struct GroupReduce {
 #pragma unroll
                 for (int e = 0; e < h; ++e) {
                     const Acc lo = x[e], hi = x[e + h];
-                    const Acc other = __shfl_xor(up ? lo : hi, g * STRIDE);
+                    const Acc other = xor_shfl<g * STRIDE>(up ? lo : hi);
                     x[e] = (up ? hi : lo) + other;
                 }
                 GroupReduce<Acc, h, g, STRIDE>::run(x, lane);
             } else {
-                x[0] += __shfl_xor(x[0], g * STRIDE);
+                x[0] += xor_shfl<g * STRIDE>(x[0]);
                 GroupReduce<Acc, 1, g, STRIDE>::run(x, lane);
             }
         }

@@ -110,7 +110,7 @@ _fbf_destroy = _sig("phmg_fbf_destroy", C.c_int, [C.c_void_p])
 _set_variant = _sig("phmg_set_apply_variant", C.c_int, [C.c_void_p, C.c_int, C.c_int])
 _set_storage = _sig("phmg_set_patch_storage", C.c_int, [C.c_void_p, C.c_int, C.c_int])
 _set_spmv = _sig("phmg_set_spmv_variant", C.c_int, [C.c_void_p, C.c_int, C.c_int, C.c_int])
-SPMV_VARIANTS = 13
+SPMV_VARIANTS = 17
 STORAGE = {"auto": 0, "general": 1}
 MAX_RHS = 16
 

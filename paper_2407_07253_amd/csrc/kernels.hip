@@ -62,7 +62,7 @@ __device__ inline int64_t logical_block(bool xm) {
     return (int64_t)(blockIdx.x % 8) * per + blockIdx.x / 8;
 }
 
-template <int G, bool XM>
+template <int G, bool XM, int UNR = 4>
 __global__ __launch_bounds__(kBlock) void spmv_kernel(int32_t nrows, const int32_t* __restrict__ rowptr,
                                                       const int32_t* __restrict__ col, const double* __restrict__ val,
                                                       const double* __restrict__ x, double alpha, const double* z,
@@ -73,22 +73,22 @@ __global__ __launch_bounds__(kBlock) void spmv_kernel(int32_t nrows, const int32
     for (int64_t row = sub; row < nrows; row += nsub) {
         const int beg = rowptr[row], end = rowptr[row + 1];
         double s = 0.0;
-        // four entries per lane in flight (all indices first, then all gathers,
+        // UNR entries per lane in flight (all indices first, then all gathers,
         // predicated at the row end); each lane still adds its entries
         // k = beg + lane, + G, + 2G, ... in order (a missing entry adds +0)
-        for (int k = beg + lane; k < end; k += 4 * G) {
-            int c[4];
-            double v[4], xv[4];
+        for (int k = beg + lane; k < end; k += UNR * G) {
+            int c[UNR];
+            double v[UNR], xv[UNR];
 #pragma unroll
-            for (int u = 0; u < 4; ++u) {
+            for (int u = 0; u < UNR; ++u) {
                 const bool ok = k + u * G < end;
                 c[u] = ok ? col[k + u * G] : 0;
                 v[u] = ok ? val[k + u * G] : 0.0;
             }
 #pragma unroll
-            for (int u = 0; u < 4; ++u) xv[u] = k + u * G < end ? x[c[u]] : 0.0;
+            for (int u = 0; u < UNR; ++u) xv[u] = k + u * G < end ? x[c[u]] : 0.0;
 #pragma unroll
-            for (int u = 0; u < 4; ++u) s += v[u] * xv[u];
+            for (int u = 0; u < UNR; ++u) s += v[u] * xv[u];
         }
 #pragma unroll
         for (int off = G / 2; off > 0; off >>= 1) s += __shfl_xor(s, off, G);
@@ -1015,6 +1015,23 @@ void launch_spmv(hipStream_t s, const DevCsr& A, const double* x, double alpha, 
         hipLaunchKernelGGL(rowblock_spmv_kernel, dim3(A.nrb), dim3(kBlock), 0, s, A.rblk, A.rowptr, A.col, A.val, x,
                            alpha, z, beta, y);
         return;
+    }
+    if (A.unroll == 8) {
+        const int grid8 = grid_for((int64_t)A.nrows * A.group, kBlock);
+        switch (A.group) {
+#define PHMG_SPMV8_CASE(G)                                                                                       \
+    case G:                                                                                                      \
+        hipLaunchKernelGGL((spmv_kernel<G, false, 8>), dim3(grid8), dim3(kBlock), 0, s, A.nrows, A.rowptr, A.col, \
+                           A.val, x, alpha, z, beta, y);                                                         \
+        return;
+            PHMG_SPMV8_CASE(4)
+            PHMG_SPMV8_CASE(8)
+            PHMG_SPMV8_CASE(16)
+            PHMG_SPMV8_CASE(32)
+#undef PHMG_SPMV8_CASE
+            default:
+                break;
+        }
     }
     const int g = A.group;
     int grid = grid_for((int64_t)A.nrows * g, kBlock);

@@ -167,10 +167,11 @@ void launch_typed(hipStream_t s, const Level& L, const double* r) {
 // partials and, for j below the diagonal block, forms S(i, j) . r_i for column j.
 // Column sums are scatter-reduced over the row lanes (each lane ends with one
 // column), row sums are reduced over the column lanes, and both are added into
-// the wave's own partial result in LDS; units are dealt to the waves
-// round-robin and the four partial results are summed in wave order at the
-// end.  PF = true issues the loads of a wave's next unit before computing the
-// current one; the arithmetic, and so every bit of the result, is the same.
+// partial result u % 4 in LDS (u the unit's number in strip-major order); units
+// are dealt to the waves round-robin and the four partial results are summed in
+// order at the end.  PF = true issues the loads of a wave's next unit before
+// computing the current one; the arithmetic, and so every bit of the result, is
+// the same for every shape.
 constexpr int kUnitCols = 64;
 
 template <typename T>
@@ -209,7 +210,13 @@ __device__ inline void sym_load(const T* A, int s, int c_lo, int m, int rl, int 
     }
 }
 
-template <typename T, bool PF>
+// NWV wavefronts per workgroup (4, or 1 for levels of small patches, where a
+// 4-wave workgroup would leave waves without units).  Unit u always adds into
+// partial result u % 4, in increasing u, whichever wave runs it, so both
+// shapes give identical bits.
+constexpr int kSymParts = 4;
+
+template <typename T, bool PF, int NWV>
 __global__ __launch_bounds__(kBlock) void patch_apply_sym_kernel(const int32_t* __restrict__ order,
                                                                  const int64_t* __restrict__ pptr,
                                                                  const int32_t* __restrict__ pdofs,
@@ -221,37 +228,38 @@ __global__ __launch_bounds__(kBlock) void patch_apply_sym_kernel(const int32_t* 
     typedef typename Load16<T>::acc_t Acc;
     typedef SymShape<T> Sh;
     constexpr int V = Sh::V, RL = Sh::RL, CL = Sh::CL, U = Sh::U;
-    constexpr int NW = kBlock / kWave;
+    constexpr int NP = kSymParts, NTH = NWV * kWave;
     static_assert(V == factor_pad<T>() && U == RL && CL % V == 0, "strip and reduction shapes");
+    static_assert(NP % NWV == 0, "unit classes per wave");
     extern __shared__ double s_buf[];
     Acc* s_r = reinterpret_cast<Acc*>(s_buf);
-    Acc* s_y = s_r + ldbuf;                                       // NW partial results of ldbuf each
+    Acc* s_y = s_r + ldbuf;                                       // NP partial results of ldbuf each
     const int p = order[blockIdx.x];
     const int64_t base = pptr[p];
     const int m = (int)(pptr[p + 1] - base);
     const T* A = F + foff[p];
     const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
     const int rl = lane % RL, cl = lane / RL;
-    Acc* yw = s_y + wave * ldbuf;
     const int ns = (m + kStrip - 1) / kStrip;
     // this wave's first unit (unit number `wave` in strip-major order): its
     // factor loads are issued before the residual gather, which they do not need
-    int s = 0, c = 0;
+    int s = 0, c = 0, unit = wave;
     bool ok = true;
     for (int q = 0; q < wave && ok; ++q) ok = sym_step(s, c, ns, m);
     Acc a[U][V];
     if (ok) sym_load<T>(A, s, c, m, rl, cl, a);
-    for (int t = threadIdx.x; t < m; t += kBlock) {
+    for (int t = threadIdx.x; t < m; t += NTH) {
         const double v = r[pdofs[base + t]];
         s_r[t] = (Acc)(gw ? gw[base + t] * v : v);
     }
-    for (int t = threadIdx.x; t < NW * ldbuf; t += kBlock) s_y[t] = (Acc)0;
+    for (int t = threadIdx.x; t < NP * ldbuf; t += NTH) s_y[t] = (Acc)0;
     __syncthreads();
     bool first = true;
     while (ok) {
         int s2 = s, c2 = c;
         bool ok2 = true;
-        for (int q = 0; q < NW && ok2; ++q) ok2 = sym_step(s2, c2, ns, m);
+        for (int q = 0; q < NWV && ok2; ++q) ok2 = sym_step(s2, c2, ns, m);
+        Acc* yw = s_y + (unit % NP) * ldbuf;
         Acc b[U][V];
         if (PF) {
             if (ok2) sym_load<T>(A, s2, c2, m, rl, cl, b);
@@ -297,6 +305,7 @@ __global__ __launch_bounds__(kBlock) void patch_apply_sym_kernel(const int32_t* 
         s = s2;
         c = c2;
         ok = ok2;
+        unit += NWV;
         if (PF) {
 #pragma unroll
             for (int u = 0; u < U; ++u)
@@ -305,32 +314,37 @@ __global__ __launch_bounds__(kBlock) void patch_apply_sym_kernel(const int32_t* 
         }
     }
     __syncthreads();
-    for (int t = threadIdx.x; t < m; t += kBlock) {
+    for (int t = threadIdx.x; t < m; t += NTH) {
         Acc sum = s_y[t];
 #pragma unroll
-        for (int q = 1; q < NW; ++q) sum += s_y[q * ldbuf + t];
+        for (int q = 1; q < NP; ++q) sum += s_y[q * ldbuf + t];
         Y[base + t] = (double)sum;
     }
 }
 
-template <typename T, bool PF>
+template <typename T, bool PF, int NWV>
 void launch_sym_shape(hipStream_t s, const Level& L, const double* r, const double* gw) {
     typedef typename Load16<T>::acc_t Acc;
     const int ldbuf = (L.max_m + 1) & ~1;
-    const size_t lds = sizeof(Acc) * (size_t)ldbuf * (1 + kBlock / kWave);
-    hipLaunchKernelGGL((patch_apply_sym_kernel<T, PF>), dim3(L.npatch), dim3(kBlock), lds, s, L.order, L.pptr,
-                       L.pdofs, L.fofflp, (const T*)L.factors, r, gw, L.Y, ldbuf);
+    const size_t lds = sizeof(Acc) * (size_t)ldbuf * (1 + kSymParts);
+    hipLaunchKernelGGL((patch_apply_sym_kernel<T, PF, NWV>), dim3(L.npatch), dim3(NWV * kWave), lds, s, L.order,
+                       L.pptr, L.pdofs, L.fofflp, (const T*)L.factors, r, gw, L.Y, ldbuf);
 }
 
+// shapes: 0 / 1 four waves without / with prefetch, 2 / 3 one wave without / with prefetch
 template <typename T>
 void launch_sym_typed(hipStream_t s, const Level& L, const double* r, const double* gw) {
-    if (L.apply_variant == 1) launch_sym_shape<T, true>(s, L, r, gw);
-    else launch_sym_shape<T, false>(s, L, r, gw);
+    switch (L.apply_variant) {
+        case 1: launch_sym_shape<T, true, 4>(s, L, r, gw); break;
+        case 2: launch_sym_shape<T, false, 1>(s, L, r, gw); break;
+        case 3: launch_sym_shape<T, true, 1>(s, L, r, gw); break;
+        default: launch_sym_shape<T, false, 4>(s, L, r, gw);
+    }
 }
 
 }  // namespace
 
-int apply_variant_count(const Level& L) { return L.sym ? 2 : 3; }
+int apply_variant_count(const Level& L) { return L.sym ? 4 : 3; }
 
 void launch_patch_apply_sym(hipStream_t s, const Level& L, const double* r, const double* gw) {
     if (L.npatch <= 0) return;

@@ -504,8 +504,8 @@ std::vector<uint64_t> phmg::graph_signature(phmg_ctx ctx) {
         p(A.col);
         p(A.val);
         p(A.rblk);
-        u((uint64_t)A.group | (uint64_t)A.xcd << 8 | (uint64_t)A.rowblock << 9 | (uint64_t)A.bgroup << 16 |
-          (uint64_t)A.bxcd << 24);
+        u((uint64_t)A.group | (uint64_t)A.xcd << 8 | (uint64_t)A.rowblock << 9 | (uint64_t)A.unroll << 10 |
+          (uint64_t)A.bgroup << 16 | (uint64_t)A.bxcd << 24);
     };
     const phmg_cycle_opts& o = ctx->opts;
     u((uint64_t)o.nu_p | (uint64_t)o.nu_h << 16 | (uint64_t)o.n_v << 32 | (uint64_t)o.n_plevels << 48);
@@ -600,20 +600,27 @@ void precond(phmg_ctx ctx, const double* b, double* x, bool transpose = false) {
 // Set-up autotuner of the SpMV: lanes per row of one matrix, timed once.
 // SpMV kernel variants: 0-5 CSR with 2, 4, ..., 64 lanes per row, 6-11 the same
 // with XCD-contiguous row ranges, 12 the row-block kernel (when the matrix has
-// row blocks).
-constexpr int kSpmvVariants = 13;
-bool spmv_variant_ok(const DevCsr& A, int v) { return v >= 0 && v < kSpmvVariants && (v < 12 || A.nrb > 0); }
+// row blocks), 13-16 CSR with 4, 8, 16, 32 lanes per row and 8 entries in
+// flight per lane.
+constexpr int kSpmvVariants = 17;
+bool spmv_variant_ok(const DevCsr& A, int v) { return v >= 0 && v < kSpmvVariants && (v != 12 || A.nrb > 0); }
 void set_spmv_variant(DevCsr& A, int v) {
+    A.rowblock = v == 12;
+    A.unroll = 4;
     if (v < 12) {
         A.group = 2 << (v % 6);
         A.xcd = v >= 6;
+    } else if (v > 12) {
+        A.group = 4 << (v - 13);
+        A.xcd = false;
+        A.unroll = 8;
     }
-    A.rowblock = v == 12;
 }
 int spmv_variant_of(const DevCsr& A) {
     if (A.rowblock) return 12;
     int lg = 0;
     while ((2 << lg) < A.group) ++lg;
+    if (A.unroll == 8) return 13 + (lg - 1);
     return lg + (A.xcd ? 6 : 0);
 }
 
@@ -634,6 +641,7 @@ void tune_spmv(phmg_ctx ctx, DevCsr& A, const double* x, double* y) {
         A.group = lanes_for((double)A.nnz / A.nrows);
         A.xcd = false;
         A.rowblock = false;
+        A.unroll = 4;
         A.tuned = true;
         return;
     }
@@ -641,14 +649,11 @@ void tune_spmv(phmg_ctx ctx, DevCsr& A, const double* x, double* y) {
     hipEvent_t e0, e1;
     hipcheck(hipEventCreate(&e0), "hipEventCreate");
     hipcheck(hipEventCreate(&e1), "hipEventCreate");
-    int best = A.group;
-    bool best_x = false, best_rb = false;
+    int best_v = 0;
     float best_ms = 1e30f;
     for (int cand = 0; cand < kSpmvVariants; ++cand) {
         if (!spmv_variant_ok(A, cand)) continue;
         set_spmv_variant(A, cand);
-        const int g = A.group, xm = A.xcd ? 1 : 0;
-        const bool rbk = A.rowblock;
         launch_spmv(s, A, x, 1.0, nullptr, 0.0, y);
         float gbest = 1e30f;
         for (int rep = 0; rep < 3; ++rep) {
@@ -662,17 +667,13 @@ void tune_spmv(phmg_ctx ctx, DevCsr& A, const double* x, double* y) {
         }
         if (gbest < best_ms) {
             best_ms = gbest;
-            best = g;
-            best_x = xm != 0;
-            best_rb = rbk;
+            best_v = cand;
         }
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     hipcheck(hipGetLastError(), "spmv autotune launch");
-    A.xcd = best_x;
-    A.group = best;
-    A.rowblock = best_rb;
+    set_spmv_variant(A, best_v);
     A.tuned = true;
 }
 

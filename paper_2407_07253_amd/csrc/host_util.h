@@ -91,15 +91,16 @@ struct Timed {
         hipcheck(hipEventCreate(&e), "hipEventCreate");
         return e;
     }
-    Timed(phmg_ctx c, int k, int l) : ctx(c), id(k), level(l) {
+    hipStream_t stream;
+    Timed(phmg_ctx c, int k, int l, hipStream_t s = nullptr) : ctx(c), id(k), level(l), stream(s ? s : c->stream) {
         if (!(ctx->prof.mask & (1u << k))) return;
         e0 = take();
         e1 = take();
-        hipcheck(hipEventRecord(e0, ctx->stream), "hipEventRecord");
+        hipcheck(hipEventRecord(e0, stream), "hipEventRecord");
     }
     ~Timed() {
         if (!e0) return;
-        (void)hipEventRecord(e1, ctx->stream);
+        (void)hipEventRecord(e1, stream);
         ctx->prof.pending.push_back({id, level, e0, e1});
     }
 };

@@ -255,10 +255,9 @@ void relax(phmg_ctx ctx, int l, const double* b, double* x, int nu, bool x_zero,
 // three launches) and the fastest is kept.  Runs once per level and precision.
 int tune_key(const Level& L) { return L.prec + (L.sym ? 3 : 0); }
 
-void tune_apply(phmg_ctx ctx, int l) {
+void tune_apply(phmg_ctx ctx, int l, hipStream_t s) {
     Level& L = ctx->L[l];
     if (L.tuned_for == tune_key(L) || L.npatch == 0) return;
-    hipStream_t s = ctx->stream;
     launch_fill(s, L.n, L.r, 1.0);
     hipEvent_t e0, e1;
     hipcheck(hipEventCreate(&e0), "hipEventCreate");
@@ -364,56 +363,78 @@ double device_norm(hipStream_t s, Krylov& kr, int64_t n, const double* v);
 // Classical Gram-Schmidt twice against the ncol basis vectors V: h1 = V^T w,
 // w -= V h1, h2 = V^T w, w -= V h2, hn2 = w . w.  The subtraction and the next
 // products share one read of the basis (three passes instead of five).
-void cgs2(hipStream_t s, Krylov& kr, int64_t n, int ncol, const double* V, double* w, double* h1, double* h2,
+void cgs2(hipStream_t s, double* partial, int64_t n, int ncol, const double* V, double* w, double* h1, double* h2,
           double* hn2) {
-    launch_multidot(s, n, ncol, V, n, w, kr.partial, h1);
+    launch_multidot(s, n, ncol, V, n, w, partial, h1);
     if (ncol <= gs_max_cols()) {
-        launch_gs_update(s, n, ncol, V, n, h1, w, kr.partial, h2, false);
-        launch_gs_update(s, n, ncol, V, n, h2, w, kr.partial, hn2, true);
+        launch_gs_update(s, n, ncol, V, n, h1, w, partial, h2, false);
+        launch_gs_update(s, n, ncol, V, n, h2, w, partial, hn2, true);
     } else {
         launch_gemv_sub(s, n, ncol, V, n, h1, w);
-        launch_multidot(s, n, ncol, V, n, w, kr.partial, h2);
+        launch_multidot(s, n, ncol, V, n, w, partial, h2);
         launch_gemv_sub(s, n, ncol, V, n, h2, w);
-        launch_multidot(s, n, 1, w, n, w, kr.partial, hn2);
+        launch_multidot(s, n, 1, w, n, w, partial, hn2);
     }
 }
 
 // lambda_max(M^{-1} K): largest real Ritz value of eig_iters Arnoldi steps
-// (CGS2) from v_0 = (1 + sin(j)/2) / ||.||, all vectors on the device.
-double arnoldi_estimate(phmg_ctx ctx, int l) {
+// (CGS2) from v_0 = (1 + sin(j)/2) / ||.||, all vectors on the device in the
+// level's own work space, on the level's set-up stream.  Every step's
+// projections stay on the device (one column of S doubles per step: h, h',
+// ||w||^2); the next basis vector is normalised with the device norm, and the
+// host reads all columns once at the end.  Several levels run interleaved.
+struct ArnoldiRun {
+    int l = 0;
+    hipStream_t s = nullptr;
+    int64_t n = 0;
+    int k = 0, S = 0;
+    double *V = nullptr, *w = nullptr, *part = nullptr, *H = nullptr, *nrm = nullptr;
+};
+
+ArnoldiRun arnoldi_begin(phmg_ctx ctx, int l, hipStream_t s) {
     Level& L = ctx->L[l];
-    hipStream_t s = ctx->stream;
-    const int64_t n = L.n;
-    int k = (int)std::min<int64_t>(ctx->opts.eig_iters, n);
-    ensure_krylov(ctx, std::max(ctx->kry.cap, k));
-    double* V = ctx->kry.V;
-    double* w = ctx->kry.w;
-    // every step's projections stay on the device (one column of S doubles per
-    // step: h, h', ||w||^2); the next basis vector is normalised with the
-    // device norm, and the host reads all columns once at the end
-    const int S = 2 * (k + 1) + 1;
-    if (ctx->arnoldi_cap < (int64_t)S * k) {
-        dfree(ctx, ctx->arnoldi_h);
-        ctx->arnoldi_h = dalloc<double>(ctx, (int64_t)S * k);
-        ctx->arnoldi_cap = (int64_t)S * k;
+    ArnoldiRun a;
+    a.l = l;
+    a.s = s;
+    a.n = L.n;
+    a.k = (int)std::min<int64_t>(ctx->opts.eig_iters, L.n);
+    a.S = 2 * (a.k + 1) + 1;
+    const int64_t len = a.n * a.k + a.n + (int64_t)kRedBlocks * (a.k + 2) + (int64_t)a.S * a.k + 2;
+    if (L.arn_len < len) {
+        dfree(ctx, L.arn);
+        L.arn = dalloc<double>(ctx, len);
+        L.arn_len = len;
     }
-    double* Hd = ctx->arnoldi_h;
-    launch_power_start(s, n, V);
-    launch_multidot(s, n, 1, V, n, V, ctx->kry.partial, ctx->scal);
-    launch_scale_by_devnorm(s, n, V, ctx->scal, V);
-    for (int j = 0; j < k; ++j) {
-        double* h1 = Hd + (int64_t)j * S;
-        double* h2 = h1 + (k + 1);
-        double* hn2 = h1 + 2 * (k + 1);
-        launch_spmv(s, L.K, V + (int64_t)j * n, 1.0, nullptr, 0.0, L.r);
-        launch_patch_apply(s, L, L.r);
-        launch_scatter(s, L, 1.0, 0.0, nullptr, false, w, true);
-        cgs2(s, ctx->kry, n, j + 1, V, w, h1, h2, hn2);
-        if (j + 1 < k) launch_scale_by_devnorm(s, n, w, hn2, V + (int64_t)(j + 1) * n);
-    }
+    a.V = L.arn;
+    a.w = a.V + a.n * a.k;
+    a.part = a.w + a.n;
+    a.H = a.part + (int64_t)kRedBlocks * (a.k + 2);
+    a.nrm = a.H + (int64_t)a.S * a.k;
+    launch_power_start(s, a.n, a.V);
+    launch_multidot(s, a.n, 1, a.V, a.n, a.V, a.part, a.nrm);
+    launch_scale_by_devnorm(s, a.n, a.V, a.nrm, a.V);
+    return a;
+}
+
+void arnoldi_step(phmg_ctx ctx, const ArnoldiRun& a, int j) {
+    Level& L = ctx->L[a.l];
+    const hipStream_t s = a.s;
+    const int64_t n = a.n;
+    double* h1 = a.H + (int64_t)j * a.S;
+    double* h2 = h1 + (a.k + 1);
+    double* hn2 = h1 + 2 * (a.k + 1);
+    launch_spmv(s, L.K, a.V + (int64_t)j * n, 1.0, nullptr, 0.0, L.r);
+    launch_patch_apply(s, L, L.r);
+    launch_scatter(s, L, 1.0, 0.0, nullptr, false, a.w, true);
+    cgs2(s, a.part, n, j + 1, a.V, a.w, h1, h2, hn2);
+    if (j + 1 < a.k) launch_scale_by_devnorm(s, n, a.w, hn2, a.V + (int64_t)(j + 1) * n);
+}
+
+double arnoldi_finish(const ArnoldiRun& a) {
+    const int k = a.k, S = a.S;
     std::vector<double> hcols((size_t)S * k);
-    hipcheck(hipMemcpyAsync(hcols.data(), Hd, sizeof(double) * S * k, hipMemcpyDeviceToHost, s), "D2H");
-    hipcheck(hipStreamSynchronize(s), "hipStreamSynchronize");
+    hipcheck(hipMemcpyAsync(hcols.data(), a.H, sizeof(double) * S * k, hipMemcpyDeviceToHost, a.s), "D2H");
+    hipcheck(hipStreamSynchronize(a.s), "hipStreamSynchronize");
     std::vector<double> H((size_t)(k + 1) * k, 0.0);
     int kk = k;
     for (int j = 0; j < k; ++j) {
@@ -733,65 +754,39 @@ void tune_spmv_diff(phmg_ctx ctx, Level& L, const double* x, double* y) {
     L.fuse_restrict = best_ms < two;
 }
 
-void setup_level(phmg_ctx ctx, int l) {
-    Level& L = ctx->L[l];
-    hipStream_t s = ctx->stream;
-    const int last = (int)ctx->L.size() - 1;
+// Set-up of levels [lo, hi): SpMV tuning and the stored layout on the context
+// stream, then every level's factorisation, conversion and eigenvalue
+// estimate on a stream of its own (levels are independent), so the small,
+// latency-bound levels overlap the large one.  Synchronous: all level streams
+// are drained before returning, also when a level fails.
+void setup_levels(phmg_ctx ctx, int lo, int hi) {
+    const int nl = (int)ctx->L.size();
+    const int last = nl - 1;
+    hipStream_t s0 = ctx->stream;
     // (captured graphs stay valid while graph_signature() is unchanged; the
     // set-up reuses its buffers, so repeated set-ups keep them)
-    if (l < last) {
-        Level& C = ctx->L[l + 1];
-        launch_fill(s, L.n, L.d, 1.0);
-        launch_fill(s, C.n, C.x, 1.0);
-        tune_spmv(ctx, L.K, L.d, L.r);
-        tune_spmv(ctx, L.R, L.d, C.b);
-        tune_spmv(ctx, L.P, C.x, L.r);
-        tune_spmv_diff(ctx, L, L.d, C.b);
-    }
-    int32_t st = INT32_MAX;
-    hipcheck(hipMemcpyAsync(L.status, &st, sizeof(int32_t), hipMemcpyHostToDevice, s), "status reset");
-    if (l == last) {
-        if (!L.cdense) {
-            L.cdense = dalloc<double>(ctx, (int64_t)L.nb * L.nb);
-            L.cpiv = dalloc<int>(ctx, L.nb);
-            L.cwork = dalloc<double>(ctx, (int64_t)(1 + kPanel) * L.nb);
+    for (int l = lo; l < hi; ++l) {
+        Level& L = ctx->L[l];
+        L.ready = false;
+        if (l < last) {
+            Level& C = ctx->L[l + 1];
+            launch_fill(s0, L.n, L.d, 1.0);
+            launch_fill(s0, C.n, C.x, 1.0);
+            tune_spmv(ctx, L.K, L.d, L.r);
+            tune_spmv(ctx, L.R, L.d, C.b);
+            tune_spmv(ctx, L.P, C.x, L.r);
+            tune_spmv_diff(ctx, L, L.d, C.b);
         }
-        double* dense = L.cdense;
-        int* piv = L.cpiv;
-        double* work = L.cwork;
-        launch_coarse_build(s, L, dense);
-        {
-            Timed t(ctx, PHMG_K_FACTOR, l);
-            launch_dense_gj(s, dense, L.nb, piv, L.status, ctx->scal + 4, work);
-            hipcheck(hipGetLastError(), "coarse factorisation launch");
+        if (l == last) {
+            if (!L.cdense) {
+                L.cdense = dalloc<double>(ctx, (int64_t)L.nb * L.nb);
+                L.cpiv = dalloc<int>(ctx, L.nb);
+                L.cwork = dalloc<double>(ctx, (int64_t)(1 + kPanel) * L.nb);
+            }
+            if (!L.cinv) L.cinv = dalloc<double>(ctx, (int64_t)L.nb * L.nb);
+            continue;
         }
-        if (!L.cinv) L.cinv = dalloc<double>(ctx, (int64_t)L.nb * L.nb);
-        launch_transpose(s, L.nb, dense, L.cinv);
-        hipcheck(hipMemcpyAsync(&st, L.status, sizeof(int32_t), hipMemcpyDeviceToHost, s), "D2H");
-        hipcheck(hipStreamSynchronize(s), "hipStreamSynchronize");
-        if (st != INT32_MAX) fail(PHMG_ESINGULAR, lvl(l) + "coarse matrix is singular");
-        L.ready = true;
-        return;
-    }
-    L.ready = false;
-    if (!L.work64) L.work64 = dalloc<double>(ctx, L.sum_m2);
-    double* f64 = L.work64;
-    {
-        Timed t(ctx, PHMG_K_EXTRACT, l);
-        launch_extract(s, L, f64);
-        hipcheck(hipGetLastError(), "extract launch");
-    }
-    {
-        Timed t(ctx, PHMG_K_FACTOR, l);
-        launch_patch_factor(s, L, f64);
-        hipcheck(hipGetLastError(), "patch factorisation launch");
-    }
-    // a singular patch stops its elimination early and leaves its pivot lists
-    // (pdofs_perm, pidx) unwritten: nothing may read them, so check before converting
-    hipcheck(hipMemcpyAsync(&st, L.status, sizeof(int32_t), hipMemcpyDeviceToHost, s), "D2H");
-    hipcheck(hipStreamSynchronize(s), "hipStreamSynchronize");
-    if (st != INT32_MAX) fail(PHMG_ESINGULAR, lvl(l) + "patch " + std::to_string(st) + " is singular");
-    {
+        if (!L.work64) L.work64 = dalloc<double>(ctx, L.sum_m2);
         // the stored inverses in the level's precision: general layout (columns
         // padded to 16 bytes) or the symmetric strip layout
         const size_t es = L.prec == PHMG_PREC_F64 ? 8 : (L.prec == PHMG_PREC_F32 ? 4 : 2);
@@ -818,26 +813,103 @@ void setup_level(phmg_ctx ctx, int l) {
             if (L.factors) dfree(ctx, L.factors);
             L.factors = nullptr;
             L.factor_bytes = 0;
-            void* lo = nullptr;
-            if (hipMalloc(&lo, bytes) != hipSuccess) {
+            void* p = nullptr;
+            if (hipMalloc(&p, bytes) != hipSuccess) {
                 (void)hipGetLastError();
                 fail(PHMG_ENOMEM, lvl(l) + "factor allocation failed");
             }
-            ctx->allocs.push_back(lo);
-            L.factors = lo;
+            ctx->allocs.push_back(p);
+            L.factors = p;
             L.factor_bytes = bytes;
         }
-        launch_convert_patches(s, L, f64, L.factors);
+    }
+    // level streams, fork after everything enqueued so far on the context stream
+    if ((int)ctx->sstreams.size() < nl) {
+        for (int l = (int)ctx->sstreams.size(); l < nl; ++l) {
+            hipStream_t st = nullptr;
+            hipcheck(hipStreamCreateWithFlags(&st, hipStreamNonBlocking), "hipStreamCreate");
+            ctx->sstreams.push_back(st);
+        }
+    }
+    while ((int)ctx->sevents.size() < nl + 1) {
+        hipEvent_t e = nullptr;
+        hipcheck(hipEventCreateWithFlags(&e, hipEventDisableTiming), "hipEventCreate");
+        ctx->sevents.push_back(e);
+    }
+    if (!ctx->status_host)
+        hipcheck(hipHostMalloc((void**)&ctx->status_host, sizeof(int32_t) * nl), "hipHostMalloc");
+    hipcheck(hipEventRecord(ctx->sevents[0], s0), "hipEventRecord");
+    struct Drain {                                  // every exit waits for all level streams
+        phmg_ctx c;
+        int lo, hi;
+        ~Drain() {
+            for (int l = lo; l < hi; ++l) (void)hipStreamSynchronize(c->sstreams[l]);
+        }
+    } drain{ctx, lo, hi};
+    for (int l = lo; l < hi; ++l)
+        hipcheck(hipStreamWaitEvent(ctx->sstreams[l], ctx->sevents[0], 0), "hipStreamWaitEvent");
+    // factorisations
+    for (int l = lo; l < hi; ++l) {
+        Level& L = ctx->L[l];
+        hipStream_t s = ctx->sstreams[l];
+        launch_fill_i32(s, 1, L.status, INT32_MAX);
+        if (l == last) {
+            launch_coarse_build(s, L, L.cdense);
+            {
+                Timed t(ctx, PHMG_K_FACTOR, l, s);
+                launch_dense_gj(s, L.cdense, L.nb, L.cpiv, L.status, ctx->scal + 4, L.cwork);
+                hipcheck(hipGetLastError(), "coarse factorisation launch");
+            }
+            launch_transpose(s, L.nb, L.cdense, L.cinv);
+        } else {
+            {
+                Timed t(ctx, PHMG_K_EXTRACT, l, s);
+                launch_extract(s, L, L.work64);
+                hipcheck(hipGetLastError(), "extract launch");
+            }
+            {
+                Timed t(ctx, PHMG_K_FACTOR, l, s);
+                launch_patch_factor(s, L, L.work64);
+                hipcheck(hipGetLastError(), "patch factorisation launch");
+            }
+        }
+        hipcheck(hipMemcpyAsync(ctx->status_host + l, L.status, sizeof(int32_t), hipMemcpyDeviceToHost, s), "D2H");
+    }
+    // a singular patch stops its elimination early and leaves its pivot lists
+    // (pdofs_perm, pidx) unwritten: nothing may read them, so check before converting
+    for (int l = lo; l < hi; ++l) hipcheck(hipStreamSynchronize(ctx->sstreams[l]), "hipStreamSynchronize");
+    for (int l = lo; l < hi; ++l) {
+        const int32_t st = ctx->status_host[l];
+        if (st == INT32_MAX) continue;
+        if (l == last) fail(PHMG_ESINGULAR, lvl(l) + "coarse matrix is singular");
+        fail(PHMG_ESINGULAR, lvl(l) + "patch " + std::to_string(st) + " is singular");
+    }
+    for (int l = lo; l < hi && l < last; ++l) {
+        Level& L = ctx->L[l];
+        launch_convert_patches(ctx->sstreams[l], L, L.work64, L.factors);
         hipcheck(hipGetLastError(), "convert launch");
     }
-    hipcheck(hipStreamSynchronize(s), "hipStreamSynchronize");
-    tune_apply(ctx, l);
+    for (int l = lo; l < hi && l < last; ++l) tune_apply(ctx, l, ctx->sstreams[l]);
     if (ctx->opts.smoother == PHMG_SMOOTHER_CHEBYSHEV) {
-        L.lmax = arnoldi_estimate(ctx, l);
-        if (!(L.lmax > 0.0) || !std::isfinite(L.lmax))
-            fail(PHMG_ESINGULAR, lvl(l) + "eigenvalue estimate of M^{-1}K is not positive and finite");
+        std::vector<ArnoldiRun> runs;
+        for (int l = lo; l < hi && l < last; ++l) runs.push_back(arnoldi_begin(ctx, l, ctx->sstreams[l]));
+        int kmax = 0;
+        for (const auto& a : runs) kmax = std::max(kmax, a.k);
+        for (int j = 0; j < kmax; ++j)
+            for (const auto& a : runs)
+                if (j < a.k) arnoldi_step(ctx, a, j);
+        for (const auto& a : runs) {
+            Level& L = ctx->L[a.l];
+            L.lmax = arnoldi_finish(a);
+            if (!(L.lmax > 0.0) || !std::isfinite(L.lmax))
+                fail(PHMG_ESINGULAR, lvl(a.l) + "eigenvalue estimate of M^{-1}K is not positive and finite");
+        }
     }
-    L.ready = true;
+    for (int l = lo; l < hi; ++l) {
+        hipcheck(hipEventRecord(ctx->sevents[1 + l], ctx->sstreams[l]), "hipEventRecord");
+        hipcheck(hipStreamWaitEvent(s0, ctx->sevents[1 + l], 0), "hipStreamWaitEvent");
+    }
+    for (int l = lo; l < hi; ++l) ctx->L[l].ready = true;
 }
 
 double device_norm(hipStream_t s, Krylov& kr, int64_t n, const double* v) {
@@ -922,7 +994,7 @@ phmg_status fgmres_core(hipStream_t s, Krylov& kr, int64_t n, MatVec matvec, Pre
         double* zj = Z + (int64_t)j * n;
         precond(vj, zj);
         matvec(zj, 1.0, nullptr, 0.0, w);
-        cgs2(s, kr, n, j + 1, V, w, h1, h2, hn2);
+        cgs2(s, kr.partial, n, j + 1, V, w, h1, h2, hn2);
         hipcheck(hipMemcpyAsync(kr.hhost + (j & 1) * slot, kr.hdev, sizeof(double) * hs, hipMemcpyDeviceToHost, s),
                  "D2H");
         hipcheck(hipEventRecord(kr.ev[j & 1], s), "hipEventRecord");
@@ -1000,6 +1072,12 @@ phmg_status fgmres(phmg_ctx ctx, const double* b, double* x, double rtol, int re
 void destroy_all(phmg_ctx ctx) {
     invalidate_graph(ctx);
     if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
+    for (auto st : ctx->sstreams) {
+        (void)hipStreamSynchronize(st);
+        (void)hipStreamDestroy(st);
+    }
+    for (auto e : ctx->sevents) (void)hipEventDestroy(e);
+    if (ctx->status_host) (void)hipHostFree(ctx->status_host);
     for (auto& it : ctx->prof.pending) {
         (void)hipEventDestroy(it.e0);
         (void)hipEventDestroy(it.e1);
@@ -1235,11 +1313,8 @@ phmg_status phmg_relax_setup(phmg_ctx ctx, int level) {
         if (!ctx) fail(PHMG_EINVAL, "null context");
         const int nl = (int)ctx->L.size();
         if (level >= nl) fail(PHMG_EINVAL, "level out of range");
-        if (level < 0) {
-            for (int l = 0; l < nl; ++l) setup_level(ctx, l);
-        } else {
-            setup_level(ctx, level);
-        }
+        if (level < 0) setup_levels(ctx, 0, nl);
+        else setup_levels(ctx, level, level + 1);
         return PHMG_OK;
     });
 }

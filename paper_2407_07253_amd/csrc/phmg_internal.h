@@ -119,6 +119,8 @@ struct Level {
     double* x = nullptr;
 
     int* status = nullptr;           // device: smallest singular patch id (INT32_MAX = none)
+    double* arn = nullptr;           // Arnoldi work space of the set-up (basis, w, partials, projections)
+    int64_t arn_len = 0;
     bool ready = false;
 
     // block (multi-right-hand-side) work space, n x kBS interleaved, allocated on first use
@@ -176,8 +178,11 @@ struct phmg_ctx_s {
     hipGraph_t vgraph[2] = {nullptr, nullptr};      // [0] B, [1] B^T (adjoint cycle)
     hipGraphExec_t vexec[2] = {nullptr, nullptr};
     std::vector<uint64_t> vsig[2];                  // graph_signature() when each graph was captured
-    double* arnoldi_h = nullptr;                    // device columns of the Arnoldi projections
-    int64_t arnoldi_cap = 0;
+    // set-up: one stream per level (default priority), fork / join events and
+    // pinned status words
+    std::vector<hipStream_t> sstreams;
+    std::vector<hipEvent_t> sevents;                // [0] fork, [1 + l] join of level l
+    int32_t* status_host = nullptr;
     double* gin = nullptr;
     double* gout = nullptr;
     // adjoint gradients: dK/dtheta over K_0's nonzeros, the forcing map G and G^T

@@ -874,22 +874,29 @@ void setup_levels(phmg_ctx ctx, int lo, int hi) {
             }
         }
         hipcheck(hipMemcpyAsync(ctx->status_host + l, L.status, sizeof(int32_t), hipMemcpyDeviceToHost, s), "D2H");
+        // a singular patch stops its elimination early and leaves its pivot lists
+        // (pdofs_perm, pidx) unwritten; the conversion never indexes outside the
+        // patch with them, and the status is checked before any result is used
+        if (l < last) {
+            launch_convert_patches(s, L, L.work64, L.factors);
+            hipcheck(hipGetLastError(), "convert launch");
+        }
     }
-    // a singular patch stops its elimination early and leaves its pivot lists
-    // (pdofs_perm, pidx) unwritten: nothing may read them, so check before converting
-    for (int l = lo; l < hi; ++l) hipcheck(hipStreamSynchronize(ctx->sstreams[l]), "hipStreamSynchronize");
-    for (int l = lo; l < hi; ++l) {
+    auto check_status = [&](int l) {
         const int32_t st = ctx->status_host[l];
-        if (st == INT32_MAX) continue;
+        if (st == INT32_MAX) return;
         if (l == last) fail(PHMG_ESINGULAR, lvl(l) + "coarse matrix is singular");
         fail(PHMG_ESINGULAR, lvl(l) + "patch " + std::to_string(st) + " is singular");
-    }
+    };
+    // first set-up of a level in its layout: time the patch-solve shapes (synchronous)
     for (int l = lo; l < hi && l < last; ++l) {
         Level& L = ctx->L[l];
-        launch_convert_patches(ctx->sstreams[l], L, L.work64, L.factors);
-        hipcheck(hipGetLastError(), "convert launch");
+        if (L.tuned_for == tune_key(L) || L.npatch == 0) continue;
+        hipcheck(hipStreamSynchronize(ctx->sstreams[l]), "hipStreamSynchronize");
+        check_status(l);
+        tune_apply(ctx, l, ctx->sstreams[l]);
     }
-    for (int l = lo; l < hi && l < last; ++l) tune_apply(ctx, l, ctx->sstreams[l]);
+    std::vector<double> lmax(nl, 0.0);
     if (ctx->opts.smoother == PHMG_SMOOTHER_CHEBYSHEV) {
         std::vector<ArnoldiRun> runs;
         for (int l = lo; l < hi && l < last; ++l) runs.push_back(arnoldi_begin(ctx, l, ctx->sstreams[l]));
@@ -898,13 +905,18 @@ void setup_levels(phmg_ctx ctx, int lo, int hi) {
         for (int j = 0; j < kmax; ++j)
             for (const auto& a : runs)
                 if (j < a.k) arnoldi_step(ctx, a, j);
-        for (const auto& a : runs) {
-            Level& L = ctx->L[a.l];
-            L.lmax = arnoldi_finish(a);
-            if (!(L.lmax > 0.0) || !std::isfinite(L.lmax))
-                fail(PHMG_ESINGULAR, lvl(a.l) + "eigenvalue estimate of M^{-1}K is not positive and finite");
-        }
+        for (const auto& a : runs) lmax[a.l] = arnoldi_finish(a);      // synchronises the level's stream
     }
+    for (int l = lo; l < hi; ++l) {
+        hipcheck(hipStreamSynchronize(ctx->sstreams[l]), "hipStreamSynchronize");
+        check_status(l);
+    }
+    if (ctx->opts.smoother == PHMG_SMOOTHER_CHEBYSHEV)
+        for (int l = lo; l < hi && l < last; ++l) {
+            if (!(lmax[l] > 0.0) || !std::isfinite(lmax[l]))
+                fail(PHMG_ESINGULAR, lvl(l) + "eigenvalue estimate of M^{-1}K is not positive and finite");
+            ctx->L[l].lmax = lmax[l];
+        }
     for (int l = lo; l < hi; ++l) {
         hipcheck(hipEventRecord(ctx->sevents[1 + l], ctx->sstreams[l]), "hipEventRecord");
         hipcheck(hipStreamWaitEvent(s0, ctx->sevents[1 + l], 0), "hipStreamWaitEvent");
@@ -1231,8 +1243,15 @@ phmg_status phmg_hierarchy_create(const phmg_hierarchy_desc* desc, const phmg_cy
                 L.pptr = upload(ctx, pt.ptr, pt.npatch + 1);
                 L.hptr.assign(pt.ptr, pt.ptr + pt.npatch + 1);
                 L.pdofs = upload(ctx, pt.dofs, L.sum_m);
-                L.pdofs_perm = dalloc<int32_t>(ctx, L.sum_m);
-                L.pidx = dalloc<int32_t>(ctx, L.sum_m);
+                // pivot lists start as the identity, so a patch whose inversion stops
+                // (singular) keeps valid indices for every later gather
+                L.pdofs_perm = upload(ctx, pt.dofs, L.sum_m);
+                {
+                    std::vector<int32_t> ident(L.sum_m);
+                    for (int32_t i = 0; i < pt.npatch; ++i)
+                        for (int64_t t = pt.ptr[i]; t < pt.ptr[i + 1]; ++t) ident[t] = (int32_t)(t - pt.ptr[i]);
+                    L.pidx = upload(ctx, ident.data(), L.sum_m);
+                }
                 L.ptol = dalloc<double>(ctx, pt.npatch);
                 L.pweight = pt.weight ? upload(ctx, pt.weight, L.sum_m) : nullptr;
                 L.foff = upload(ctx, foff.data(), pt.npatch);

@@ -144,6 +144,35 @@ void tune_block(phmg_ctx ctx) {
 void prepare_block(phmg_ctx ctx) {
     require_ready(ctx);
     ensure_block(ctx);
+    // general copies of the symmetric levels' inverses, converted from the f64
+    // set-up buffer once per set-up
+    for (size_t l = 0; l + 1 < ctx->L.size(); ++l) {
+        Level& L = ctx->L[l];
+        if (!L.sym || L.npatch == 0 || L.bconv_count == L.setup_count) continue;
+        const int V = factor_pad_of(L.prec);
+        const size_t es = L.prec == PHMG_PREC_F64 ? 8 : (L.prec == PHMG_PREC_F32 ? 4 : 2);
+        std::vector<int64_t> off(L.npatch);
+        int64_t acc = 0;
+        for (int32_t i = 0; i < L.npatch; ++i) {
+            const int64_t m = L.hptr[i + 1] - L.hptr[i];
+            off[i] = acc;
+            acc += (m + V - 1) / V * V * m;
+        }
+        if (!L.bfoff) L.bfoff = dalloc<int64_t>(ctx, L.npatch);
+        hipcheck(hipMemcpy(L.bfoff, off.data(), sizeof(int64_t) * (size_t)L.npatch, hipMemcpyHostToDevice),
+                 "hipMemcpy H2D");
+        const size_t bytes = es * (size_t)std::max<int64_t>(acc, 1);
+        if (!L.bfactors || L.bfactor_bytes < bytes) {
+            dfree(ctx, L.bfactors);
+            L.bfactors = nullptr;
+            L.bfactor_bytes = 0;
+            L.bfactors = dalloc<char>(ctx, (int64_t)bytes);
+            L.bfactor_bytes = bytes;
+        }
+        launch_convert_general(ctx->stream, L, L.work64, L.bfactors, L.bfoff);
+        hipcheck(hipGetLastError(), "convert launch");
+        L.bconv_count = L.setup_count;
+    }
     bool stale = false;
     for (size_t l = 0; l + 1 < ctx->L.size(); ++l) {
         const Level& L = ctx->L[l];

@@ -243,77 +243,6 @@ __global__ __launch_bounds__(kBlock) void block_apply_kernel(const int32_t* __re
 }
 
 // ---------------------------------------------------------------------------
-// Block patch solve on the symmetric strip layout: Y_i = S_i X[S_i].  Wave w
-// owns the 16-row output blocks b = w, w + 4, ...; block b is the sum of the
-// row part sum_{J <= b} S_{bJ} X_J (strip b, its 16-column tiles, the last one
-// the diagonal block) and the column part sum_{s > b} S_{sb}^T X_s (column
-// tile b of every later strip, used transposed), both on MFMA 16x16x4 with
-// the tile elements loaded one per lane in the operand layout; every wave reads
-// b + 1 row tiles and ns - 1 - b column tiles, the same count for all blocks.
-// ---------------------------------------------------------------------------
-template <typename T, typename Acc>
-__device__ inline Acc load_elem(const T* p) {
-    if constexpr (sizeof(T) == 2) return (Acc)__bfloat162float(*p);
-    else return (Acc)*p;
-}
-
-template <typename T, typename Acc>
-__global__ __launch_bounds__(kBlock) void block_apply_sym_kernel(const int32_t* __restrict__ order,
-                                                                 const int64_t* __restrict__ pptr,
-                                                                 const int32_t* __restrict__ pdofs,
-                                                                 const int64_t* __restrict__ foff,
-                                                                 const T* __restrict__ F,
-                                                                 const double* __restrict__ X,
-                                                                 double* __restrict__ Y) {
-    typedef typename Mfma<Acc>::acc_t acc_t;
-    constexpr int NW = kBlock / kWave;
-    constexpr int V = factor_pad<T>();
-    extern __shared__ double s_buf[];
-    Acc* s_g = reinterpret_cast<Acc*>(s_buf);
-    const int p = order[blockIdx.x];
-    const int64_t base = pptr[p];
-    const int m = (int)(pptr[p + 1] - base);
-    const int ns = (m + kStrip - 1) / kStrip;
-    for (int t = threadIdx.x; t < ns * kStrip * kBS; t += kBlock) {
-        const int l = t / kBS, c = t % kBS;
-        s_g[t] = l < m ? (Acc)X[(int64_t)pdofs[base + l] * kBS + c] : (Acc)0;
-    }
-    __syncthreads();
-    const T* A = F + foff[p];
-    const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
-    const int li = lane & 15, lk = lane >> 4;
-    for (int b = wave; b < ns; b += NW) {
-        acc_t acc = acc_t{0, 0, 0, 0};
-        {
-            const int r0 = b * kStrip, h = min(kStrip, m - r0), hp = (h + V - 1) / V * V, w = r0 + h;
-            const T* S = A + sym_strip_offset(b);
-            for (int j0 = 0; j0 < w; j0 += 16)
-#pragma unroll
-                for (int t = 0; t < 4; ++t) {
-                    const int k = j0 + 4 * t + lk;
-                    const Acc a = (li < h && k < w) ? load_elem<T, Acc>(S + (int64_t)k * hp + li) : (Acc)0;
-                    acc = Mfma<Acc>::step(a, s_g[k * kBS + li], acc);
-                }
-        }
-        for (int s = b + 1; s < ns; ++s) {
-            const int r0 = s * kStrip, h = min(kStrip, m - r0), hp = (h + V - 1) / V * V;
-            const T* S = A + sym_strip_offset(s) + (int64_t)(b * 16 + li) * hp;
-#pragma unroll
-            for (int t = 0; t < 4; ++t) {
-                const int q = 4 * t + lk;
-                const Acc a = q < h ? load_elem<T, Acc>(S + q) : (Acc)0;
-                acc = Mfma<Acc>::step(a, s_g[(r0 + q) * kBS + li], acc);
-            }
-        }
-#pragma unroll
-        for (int e = 0; e < 4; ++e) {
-            const int row = b * 16 + Mfma<Acc>::row(lane, e);
-            if (row < m) Y[(base + row) * kBS + li] = (double)acc[e];
-        }
-    }
-}
-
-// ---------------------------------------------------------------------------
 // s = sum_{slots t of DoF j, ascending patch id} w_t Y[t, c];  dn = a s + c' d;
 // X = (x_zero ? 0 : X) + dn;  d = dn when storing.  One lane per (DoF, column).
 // ---------------------------------------------------------------------------
@@ -523,59 +452,44 @@ void launch_spmm(hipStream_t s, const DevCsr& A, const double* X, double alpha, 
 
 namespace {
 template <typename T, typename Acc, int V, int NT, int U>
-void launch_block_shape(hipStream_t s, const Level& L, const int64_t* off, const double* X) {
+void launch_block_shape(hipStream_t s, const Level& L, const void* factors, const int64_t* off, const double* X) {
     const size_t lds = sizeof(Acc) * (size_t)((L.max_m + 3) & ~3) * kBS;
     auto kernel = block_apply_kernel<T, Acc, V, NT, U>;
     if (lds > 64 * 1024)
         (void)hipFuncSetAttribute((const void*)kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     hipLaunchKernelGGL(kernel, dim3(L.npatch), dim3(kBlock), lds, s, L.order, L.pptr, L.pdofs_perm, off,
-                       (const T*)L.factors, X, L.Yb);
+                       (const T*)factors, X, L.Yb);
 }
 }  // namespace
 
-int block_variant_count(const Level& L) { return L.sym ? 1 : 4; }
-
-namespace {
-template <typename T, typename Acc>
-void launch_block_sym(hipStream_t s, const Level& L, const double* X) {
-    const size_t lds = sizeof(Acc) * (size_t)((L.max_m + kStrip - 1) / kStrip * kStrip) * kBS;
-    auto kernel = block_apply_sym_kernel<T, Acc>;
-    if (lds > 64 * 1024)
-        (void)hipFuncSetAttribute((const void*)kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    hipLaunchKernelGGL(kernel, dim3(L.npatch), dim3(kBlock), lds, s, L.order, L.pptr, L.pdofs, L.fofflp,
-                       (const T*)L.factors, X, L.Yb);
-}
-}  // namespace
+int block_variant_count(const Level& /*L*/) { return 4; }
 
 void launch_block_apply(hipStream_t s, const Level& L, const double* X) {
     if (L.npatch <= 0) return;
-    if (L.sym) {
-        if (L.prec == PHMG_PREC_F32) launch_block_sym<float, float>(s, L, X);
-        else if (L.prec == PHMG_PREC_BF16) launch_block_sym<__hip_bfloat16, float>(s, L, X);
-        else launch_block_sym<double, double>(s, L, X);
-        return;
-    }
+    // symmetric levels keep a general copy for the block path (MFMA on full columns)
+    const void* factors = L.sym ? L.bfactors : L.factors;
+    const int64_t* off = L.sym ? L.bfoff : L.fofflp;
     const int v = L.block_variant;
     if (L.prec == PHMG_PREC_F32) {
         switch (v) {
-            case 1: launch_block_shape<float, float, 2, 2, 2>(s, L, L.fofflp, X); break;
-            case 2: launch_block_shape<float, float, 2, 1, 8>(s, L, L.fofflp, X); break;
-            case 3: launch_block_shape<float, float, 2, 2, 4>(s, L, L.fofflp, X); break;
-            default: launch_block_shape<float, float, 2, 1, 4>(s, L, L.fofflp, X);
+            case 1: launch_block_shape<float, float, 2, 2, 2>(s, L, factors, off, X); break;
+            case 2: launch_block_shape<float, float, 2, 1, 8>(s, L, factors, off, X); break;
+            case 3: launch_block_shape<float, float, 2, 2, 4>(s, L, factors, off, X); break;
+            default: launch_block_shape<float, float, 2, 1, 4>(s, L, factors, off, X);
         }
     } else if (L.prec == PHMG_PREC_BF16) {
         switch (v) {
-            case 1: launch_block_shape<__hip_bfloat16, float, 4, 1, 2>(s, L, L.fofflp, X); break;
-            case 2: launch_block_shape<__hip_bfloat16, float, 4, 1, 8>(s, L, L.fofflp, X); break;
-            case 3: launch_block_shape<__hip_bfloat16, float, 4, 2, 2>(s, L, L.fofflp, X); break;
-            default: launch_block_shape<__hip_bfloat16, float, 4, 1, 4>(s, L, L.fofflp, X);
+            case 1: launch_block_shape<__hip_bfloat16, float, 4, 1, 2>(s, L, factors, off, X); break;
+            case 2: launch_block_shape<__hip_bfloat16, float, 4, 1, 8>(s, L, factors, off, X); break;
+            case 3: launch_block_shape<__hip_bfloat16, float, 4, 2, 2>(s, L, factors, off, X); break;
+            default: launch_block_shape<__hip_bfloat16, float, 4, 1, 4>(s, L, factors, off, X);
         }
     } else {
         switch (v) {
-            case 1: launch_block_shape<double, double, 1, 2, 4>(s, L, L.fofflp, X); break;
-            case 2: launch_block_shape<double, double, 1, 1, 8>(s, L, L.fofflp, X); break;
-            case 3: launch_block_shape<double, double, 1, 4, 2>(s, L, L.fofflp, X); break;
-            default: launch_block_shape<double, double, 1, 1, 4>(s, L, L.fofflp, X);
+            case 1: launch_block_shape<double, double, 1, 2, 4>(s, L, factors, off, X); break;
+            case 2: launch_block_shape<double, double, 1, 1, 8>(s, L, factors, off, X); break;
+            case 3: launch_block_shape<double, double, 1, 4, 2>(s, L, factors, off, X); break;
+            default: launch_block_shape<double, double, 1, 1, 4>(s, L, factors, off, X);
         }
     }
 }

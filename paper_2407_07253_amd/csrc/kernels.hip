@@ -1104,6 +1104,19 @@ void launch_patch_factor(hipStream_t s, const Level& L, double* A) {
     else go(gj_kernel<4>);
 }
 
+void launch_convert_general(hipStream_t s, const Level& L, const double* src, void* dst, const int64_t* off) {
+    if (L.npatch <= 0) return;
+    if (L.prec == PHMG_PREC_F64)
+        hipLaunchKernelGGL((convert_patch_kernel<double, factor_pad<double>()>), dim3(L.npatch), dim3(kBlock), 0, s,
+                           L.pptr, L.foff, off, src, (double*)dst);
+    else if (L.prec == PHMG_PREC_F32)
+        hipLaunchKernelGGL((convert_patch_kernel<float, factor_pad<float>()>), dim3(L.npatch), dim3(kBlock), 0, s,
+                           L.pptr, L.foff, off, src, (float*)dst);
+    else
+        hipLaunchKernelGGL((convert_patch_kernel<__hip_bfloat16, factor_pad<__hip_bfloat16>()>), dim3(L.npatch),
+                           dim3(kBlock), 0, s, L.pptr, L.foff, off, src, (__hip_bfloat16*)dst);
+}
+
 void launch_convert_patches(hipStream_t s, const Level& L, const double* src, void* dst) {
     if (L.npatch <= 0) return;
     if (L.sym) {

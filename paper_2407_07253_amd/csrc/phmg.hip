@@ -547,6 +547,8 @@ std::vector<uint64_t> phmg::graph_signature(phmg_ctx ctx) {
         u((uint64_t)L.fuse_restrict);
         p(L.factors);
         p(L.fofflp);
+        p(L.bfactors);
+        p(L.bfoff);
         p(L.Y);
         p(L.Yb);
         p(L.cinv);
@@ -921,7 +923,10 @@ void setup_levels(phmg_ctx ctx, int lo, int hi) {
         hipcheck(hipEventRecord(ctx->sevents[1 + l], ctx->sstreams[l]), "hipEventRecord");
         hipcheck(hipStreamWaitEvent(s0, ctx->sevents[1 + l], 0), "hipStreamWaitEvent");
     }
-    for (int l = lo; l < hi; ++l) ctx->L[l].ready = true;
+    for (int l = lo; l < hi; ++l) {
+        ctx->L[l].ready = true;
+        ++ctx->L[l].setup_count;
+    }
 }
 
 double device_norm(hipStream_t s, Krylov& kr, int64_t n, const double* v) {

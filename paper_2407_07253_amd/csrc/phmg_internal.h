@@ -131,6 +131,14 @@ struct Level {
     double* Yb = nullptr;            // sum_m x kBS staging of the block patch solutions
     int block_variant = 0;           // kernel shape of the block patch solve (autotuned)
     int block_tuned_for = -1;
+    // the block path always streams the general layout: on symmetric levels a
+    // general copy is converted from the f64 set-up buffer on first block use
+    // after each set-up
+    void* bfactors = nullptr;
+    size_t bfactor_bytes = 0;
+    int64_t* bfoff = nullptr;
+    int64_t setup_count = 0;         // completed set-ups of the level
+    int64_t bconv_count = -1;        // set-up whose factors the general copy holds
 };
 
 // FGMRES work space: bases V (n x cap+1) and Z (n x cap), work vectors, the
@@ -295,6 +303,8 @@ void launch_extract(hipStream_t s, const Level& L, double* out);
 // invert every patch matrix of the level in place (stored as (P K_i)^{-1}, see kernels.hip)
 void launch_patch_factor(hipStream_t s, const Level& L, double* A);
 void launch_convert_patches(hipStream_t s, const Level& L, const double* src, void* dst);
+// general layout (offsets off) from the f64 set-up buffer, whatever the level's stored layout
+void launch_convert_general(hipStream_t s, const Level& L, const double* src, void* dst, const int64_t* off);
 void launch_patch_apply(hipStream_t s, const Level& L, const double* r);
 // adjoint patch solve y_i = K_i^{-T} W_i r[S_i] from the same stored inverses (adjoint_kernels.hip)
 void launch_patch_apply_t(hipStream_t s, const Level& L, const double* r);

@@ -77,16 +77,6 @@ __global__ __launch_bounds__(kBlock) void patch_apply_t_kernel(const int32_t* __
     }
 }
 
-// x[i] = sum_{j < n} Ainv_rm[j * nb + i] b[j]: the transposed dense coarse
-// solve (row-major inverse read by columns: consecutive i are coalesced)
-__global__ __launch_bounds__(kBlock) void coarse_solve_t_kernel(int32_t n, int32_t nb, const double* __restrict__ Ainv,
-                                                                const double* __restrict__ b, double* __restrict__ x) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    double s = 0.0;
-    for (int j = 0; j < n; ++j) s += Ainv[(int64_t)j * nb + i] * b[j];
-    x[i] = s;
-}
 
 // Products of the adjoint and state vectors on the nonzeros of K (eq. of the
 // adjoint gradient, dJ/dtheta = -sum_c lam_c^T (dK/dtheta) x_c):
@@ -136,8 +126,9 @@ void launch_pair_products(hipStream_t s, const DevCsr& K, int nrhs, const double
 }
 
 void launch_coarse_solve_t(hipStream_t s, const Level& L, const double* b, double* x) {
-    hipLaunchKernelGGL(coarse_solve_t_kernel, dim3(grid_for(L.n, kBlock)), dim3(kBlock), 0, s, L.n, L.nb, L.cinv, b,
-                       x);
+    // the set-up keeps the coarse inverse column-major as well (L.cdense): read
+    // row-major it is the transposed inverse, so the forward kernel applies it
+    launch_coarse_solve_rows(s, L, L.cdense, b, x);
 }
 
 }  // namespace phmg

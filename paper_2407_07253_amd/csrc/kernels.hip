@@ -1207,9 +1207,13 @@ void launch_transpose(hipStream_t s, int n, const double* src, double* dst) {
     hipLaunchKernelGGL(transpose_kernel, dim3(grid_for((int64_t)n * n, kBlock)), dim3(kBlock), 0, s, n, src, dst);
 }
 
-void launch_coarse_solve(hipStream_t s, const Level& L, const double* b, double* x) {
+void launch_coarse_solve_rows(hipStream_t s, const Level& L, const double* rows, const double* b, double* x) {
     hipLaunchKernelGGL(coarse_solve_kernel, dim3(grid_for((int64_t)L.n * kWave, kBlock)), dim3(kBlock), 0, s, L.n,
-                       L.nb, L.cinv, b, x);
+                       L.nb, rows, b, x);
+}
+
+void launch_coarse_solve(hipStream_t s, const Level& L, const double* b, double* x) {
+    launch_coarse_solve_rows(s, L, L.cinv, b, x);
 }
 
 void launch_multidot(hipStream_t s, int64_t n, int ncol, const double* V, int64_t ldv, const double* w,

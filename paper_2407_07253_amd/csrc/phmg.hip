@@ -552,6 +552,7 @@ std::vector<uint64_t> phmg::graph_signature(phmg_ctx ctx) {
         p(L.Y);
         p(L.Yb);
         p(L.cinv);
+        p(L.cdense);
         p(L.r);
         p(L.b);
         p(L.x);
@@ -775,6 +776,7 @@ void setup_levels(phmg_ctx ctx, int lo, int hi) {
             launch_fill(s0, L.n, L.d, 1.0);
             launch_fill(s0, C.n, C.x, 1.0);
             tune_spmv(ctx, L.K, L.d, L.r);
+            if (L.KT.rowptr != L.K.rowptr) tune_spmv(ctx, L.KT, L.d, L.r);   // adjoint cycle
             tune_spmv(ctx, L.R, L.d, C.b);
             tune_spmv(ctx, L.P, C.x, L.r);
             tune_spmv_diff(ctx, L, L.d, C.b);

@@ -325,6 +325,8 @@ int coarse_panel_width(int N);   // 0 when N is too large for the dense coarse s
 void launch_dense_gj(hipStream_t s, double* A, int N, int* piv, int* status, double* tol, double* work);
 void launch_transpose(hipStream_t s, int n, const double* src, double* dst);
 void launch_coarse_solve(hipStream_t s, const Level& L, const double* b, double* x);
+// x[i] = sum_{j < n} rows[i * nb + j] b[j] (one wave per row)
+void launch_coarse_solve_rows(hipStream_t s, const Level& L, const double* rows, const double* b, double* x);
 void launch_coarse_solve_t(hipStream_t s, const Level& L, const double* b, double* x);   // transposed
 // w_e = sum_c Lam_c[i_e] X_c[j_e] over the nonzeros of K (systems of length K.nrows one after another)
 void launch_pair_products(hipStream_t s, const DevCsr& K, int nrhs, const double* X, const double* Lam,

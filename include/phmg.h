@@ -249,6 +249,16 @@ phmg_status phmg_vcycle_batched(phmg_ctx ctx, int nrhs, const double* B, double*
 phmg_status phmg_fgmres_solve_batched(phmg_ctx ctx, int nrhs, const double* B, double* X, double rtol, int restart,
                                       int maxit, int32_t* iters, double* relres);
 
+/* The adjoint counterparts for up to PHMG_MAX_RHS systems K^T x_c = b_c (the
+ * per-system rules of phmg_vcycle_transposed / phmg_fgmres_solve_transposed).
+ * They need every relaxed level symmetric to rounding and set up in the
+ * default (symmetric) layout, where the adjoint patch solve K_i^{-T} W_i is
+ * applied as K_i^{-1} W_i with the block kernels; otherwise PHMG_EINVAL (use
+ * the single-system adjoint).  Same layout and limits as the forward calls. */
+phmg_status phmg_vcycle_batched_transposed(phmg_ctx ctx, int nrhs, const double* B, double* X);
+phmg_status phmg_fgmres_solve_batched_transposed(phmg_ctx ctx, int nrhs, const double* B, double* X, double rtol,
+                                                 int restart, int maxit, int32_t* iters, double* relres);
+
 /* Residual r = b - K_l x on a level (device pointers, asynchronous). */
 phmg_status phmg_residual(phmg_ctx ctx, int level, const double* b, const double* x, double* r);
 

@@ -91,9 +91,11 @@ _ritz = _sig("phmg_ritz_max_real", C.c_int, [C.c_void_p, C.c_int, C.c_int, C.POI
 _graphs = _sig("phmg_set_graphs", C.c_int, [C.c_void_p, C.c_int])
 _apply_b = _sig("phmg_relax_apply_batched", C.c_int, [C.c_void_p, C.c_int, C.c_int, C.c_void_p, C.c_void_p, C.c_int])
 _vcycle_b = _sig("phmg_vcycle_batched", C.c_int, [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p])
-_fgmres_b = _sig("phmg_fgmres_solve_batched", C.c_int, [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_double,
-                                                        C.c_int, C.c_int, C.POINTER(C.c_int32),
-                                                        C.POINTER(C.c_double)])
+_FGMRES_B_ARGS = [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_double, C.c_int, C.c_int, C.POINTER(C.c_int32),
+                  C.POINTER(C.c_double)]
+_fgmres_b = _sig("phmg_fgmres_solve_batched", C.c_int, _FGMRES_B_ARGS)
+_fgmres_bt = _sig("phmg_fgmres_solve_batched_transposed", C.c_int, _FGMRES_B_ARGS)
+_vcycle_bt = _sig("phmg_vcycle_batched_transposed", C.c_int, [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p])
 _apply_t = _sig("phmg_relax_apply_transposed", C.c_int, [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_int])
 _vcycle_t = _sig("phmg_vcycle_transposed", C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p])
 _fgmres_t = _sig("phmg_fgmres_solve_transposed", C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_double, C.c_int,
@@ -122,6 +124,7 @@ EXPORTED = ["phmg_hierarchy_create", "phmg_hierarchy_destroy", "phmg_relax_setup
             "phmg_set_sensitivities", "phmg_forcing_rhs", "phmg_gradients",
             "phmg_fbf_create", "phmg_fbf_apply", "phmg_fbf_fgmres_solve", "phmg_fbf_destroy",
             "phmg_set_apply_variant", "phmg_set_patch_storage", "phmg_set_spmv_variant",
+            "phmg_vcycle_batched_transposed", "phmg_fgmres_solve_batched_transposed",
             "phmg_last_error"]
 
 
@@ -347,13 +350,27 @@ class Hierarchy:
 
     def fgmres_batched(self, B, X, rtol: float = 1e-8, restart: int = 30, maxit: int = 1000):
         """Solve K x_c = b_c for every row c of B (X in/out); returns (iters[], relres[], all_converged)."""
+        return self._fgmres_b(_fgmres_b, B, X, rtol, restart, maxit)
+
+    def fgmres_batched_transposed(self, B, X, rtol: float = 1e-8, restart: int = 30, maxit: int = 1000):
+        """Solve K^T x_c = b_c for every row c of B (adjoint cycle; symmetric levels only)."""
+        return self._fgmres_b(_fgmres_bt, B, X, rtol, restart, maxit)
+
+    def vcycle_batched_transposed(self, B, X):
+        pb, k = _block_ptr(B, self.n[0], "B")
+        px, kx = _block_ptr(X, self.n[0], "X")
+        if k != kx:
+            raise ValueError("B and X must hold the same number of right-hand sides")
+        _check(_vcycle_bt(self._h, k, pb, px))
+
+    def _fgmres_b(self, fn, B, X, rtol, restart, maxit):
         pb, k = _block_ptr(B, self.n[0], "B")
         px, kx = _block_ptr(X, self.n[0], "X")
         if k != kx:
             raise ValueError("B and X must hold the same number of right-hand sides")
         it = (C.c_int32 * k)()
         rr = (C.c_double * k)()
-        st = _check(_fgmres_b(self._h, k, pb, px, rtol, restart, maxit, it, rr), allow=(PHMG_ENOCONV,))
+        st = _check(fn(self._h, k, pb, px, rtol, restart, maxit, it, rr), allow=(PHMG_ENOCONV,))
         return [int(v) for v in it], [float(v) for v in rr], st == PHMG_OK
 
     def level_info(self, level: int) -> dict:

@@ -34,10 +34,11 @@ class StokesProblem:
     """A workload's hierarchy with viscosity and forcing as inputs (homogeneous Dirichlet data)."""
 
     def __init__(self, name: str, k: Optional[int] = None, rtol: float = 1e-10, restart: int = 30,
-                 maxit: int = 1000, precision: str = "f64"):
+                 maxit: int = 1000, precision: str = "f64", batched_adjoint: bool = True):
         self.name, self.k = name, k
         self.rtol, self.restart, self.maxit = rtol, restart, maxit
         self.precision = precision
+        self.batched_adjoint = batched_adjoint     # adjoint solves through the block path (symmetric levels)
         self.mesh = synth.config_mesh_hierarchy(name)[-1]
         self.nv = self.mesh.verts.shape[0]
         self._key = None
@@ -119,14 +120,28 @@ def _autograd():
             _project_pressure(G, p0)
             Lam = torch.zeros_like(G)
             adj_iters = []
-            for c in range(G.shape[0]):
-                lc = torch.zeros(G.shape[1], dtype=torch.float64, device="cuda")
-                its, rr, ok = H.fgmres_transposed(G[c].contiguous(), lc, rtol=problem.rtol, restart=problem.restart,
-                                                  maxit=problem.maxit)
-                if not ok:
-                    raise RuntimeError(f"adjoint solve did not converge (relres {rr:.3e})")
-                Lam[c] = lc
-                adj_iters.append(its)
+            infos = [H.level_info(l) for l in range(H.nlevels - 1)]
+            block_ok = problem.batched_adjoint and all(i["symmetric_storage"] or i["npatch"] == 0 for i in infos)
+            if block_ok:
+                # all adjoint systems together through the block adjoint cycle (needs symmetric levels)
+                for c0 in range(0, G.shape[0], MAX_RHS):
+                    c1 = min(G.shape[0], c0 + MAX_RHS)
+                    Lc = Lam[c0:c1].contiguous()
+                    its, rr, ok = H.fgmres_batched_transposed(G[c0:c1].contiguous(), Lc, rtol=problem.rtol,
+                                                              restart=problem.restart, maxit=problem.maxit)
+                    if not ok:
+                        raise RuntimeError(f"adjoint solve did not converge (relres {max(rr):.3e})")
+                    Lam[c0:c1] = Lc
+                    adj_iters += its
+            else:
+                for c in range(G.shape[0]):
+                    lc = torch.zeros(G.shape[1], dtype=torch.float64, device="cuda")
+                    its, rr, ok = H.fgmres_transposed(G[c].contiguous(), lc, rtol=problem.rtol,
+                                                      restart=problem.restart, maxit=problem.maxit)
+                    if not ok:
+                        raise RuntimeError(f"adjoint solve did not converge (relres {rr:.3e})")
+                    Lam[c] = lc
+                    adj_iters.append(its)
             problem.last_adjoint_iters = adj_iters
             n_theta = H.n_theta
             grad_l = torch.empty(n_theta, dtype=torch.float64, device="cuda")

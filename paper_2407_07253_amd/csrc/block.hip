@@ -22,10 +22,12 @@
 namespace phmg {
 
 void invalidate_block_graph(phmg_ctx ctx) {
-    if (ctx->bexec) (void)hipGraphExecDestroy(ctx->bexec);
-    if (ctx->bgraph) (void)hipGraphDestroy(ctx->bgraph);
-    ctx->bexec = nullptr;
-    ctx->bgraph = nullptr;
+    for (int t = 0; t < 2; ++t) {
+        if (ctx->bexec[t]) (void)hipGraphExecDestroy(ctx->bexec[t]);
+        if (ctx->bgraph[t]) (void)hipGraphDestroy(ctx->bgraph[t]);
+        ctx->bexec[t] = nullptr;
+        ctx->bgraph[t] = nullptr;
+    }
 }
 
 namespace {
@@ -118,6 +120,7 @@ void tune_block(phmg_ctx ctx) {
         launch_fill(s, (int64_t)L.n * kBS, L.db, 1.0);
         launch_fill(s, (int64_t)C.n * kBS, C.xb, 1.0);
         tune_csr(L.K, L.db, L.rb);
+        if (L.KT.rowptr != L.K.rowptr) tune_csr(L.KT, L.db, L.rb);
         tune_csr(L.R, L.db, C.bb);
         tune_csr(L.P, C.xb, L.rb);
         if (L.npatch > 0 && L.block_tuned_for != L.prec + (L.sym ? 3 : 0)) {
@@ -176,7 +179,8 @@ void prepare_block(phmg_ctx ctx) {
     bool stale = false;
     for (size_t l = 0; l + 1 < ctx->L.size(); ++l) {
         const Level& L = ctx->L[l];
-        stale = stale || !L.K.btuned || (L.npatch > 0 && L.block_tuned_for != L.prec + (L.sym ? 3 : 0));
+        stale = stale || !L.K.btuned || (L.npatch > 0 && L.block_tuned_for != L.prec + (L.sym ? 3 : 0)) ||
+                (L.KT.rowptr != L.K.rowptr && !L.KT.btuned);
     }
     if (stale) {
         invalidate_block_graph(ctx);
@@ -186,7 +190,7 @@ void prepare_block(phmg_ctx ctx) {
 
 // nu smoothing steps on level l for all columns (the single-system relax with
 // block kernels; the Chebyshev coefficients are shared by all columns).
-void relax_block(phmg_ctx ctx, int l, const double* B, double* X, int nu, bool x_zero) {
+void relax_block(phmg_ctx ctx, int l, const double* B, double* X, int nu, bool x_zero, bool transpose = false) {
     Level& L = ctx->L[l];
     hipStream_t s = ctx->stream;
     const int64_t nb = (int64_t)L.n * kBS;
@@ -207,67 +211,67 @@ void relax_block(phmg_ctx ctx, int l, const double* B, double* X, int nu, bool x
         const double* R = B;
         if (!(it == 0 && x_zero)) {
             Timed t(ctx, PHMG_K_SPMV, l);
-            launch_spmm(s, L.K, X, -1.0, B, 1.0, L.rb);
+            launch_spmm(s, transpose ? L.KT : L.K, X, -1.0, B, 1.0, L.rb);
             R = L.rb;
         }
         {
             Timed t(ctx, PHMG_K_PATCH_APPLY, l);
-            launch_block_apply(s, L, R);
+            launch_block_apply(s, L, R, transpose);
         }
         Timed t(ctx, PHMG_K_SCATTER, l);
         const bool xz = it == 0 && x_zero;
         if (!cheb) {
-            launch_block_scatter(s, L, ctx->opts.omega, 0.0, nullptr, false, X, xz);
+            launch_block_scatter(s, L, ctx->opts.omega, 0.0, nullptr, false, X, xz, transpose);
         } else if (it == 0) {
-            launch_block_scatter(s, L, 1.0 / theta, 0.0, L.db, nu > 1, X, xz);
+            launch_block_scatter(s, L, 1.0 / theta, 0.0, L.db, nu > 1, X, xz, transpose);
         } else {
             const double rho = 1.0 / (2.0 * sigma - rho_prev);
-            launch_block_scatter(s, L, 2.0 * rho / delta, rho * rho_prev, L.db, it + 1 < nu, X, false);
+            launch_block_scatter(s, L, 2.0 * rho / delta, rho * rho_prev, L.db, it + 1 < nu, X, false, transpose);
             rho_prev = rho;
         }
     }
 }
 
-void cycle_block(phmg_ctx ctx, int l, const double* B, double* X, bool x_zero) {
+void cycle_block(phmg_ctx ctx, int l, const double* B, double* X, bool x_zero, bool transpose = false) {
     const int last = (int)ctx->L.size() - 1;
     hipStream_t s = ctx->stream;
     if (l == last) {
-        launch_block_coarse_solve(s, ctx->L[l], B, X);
+        launch_block_coarse_solve(s, ctx->L[l], B, X, transpose);
         return;
     }
     Level& L = ctx->L[l];
     Level& C = ctx->L[l + 1];
     const int np = ctx->opts.n_plevels;
     const int nu = l < np ? ctx->opts.nu_p : ctx->opts.nu_h;
-    relax_block(ctx, l, B, X, nu, x_zero);
+    relax_block(ctx, l, B, X, nu, x_zero, transpose);
     {
         Timed t(ctx, PHMG_K_SPMV, l);
-        launch_spmm(s, L.K, X, -1.0, B, 1.0, L.rb);
+        launch_spmm(s, transpose ? L.KT : L.K, X, -1.0, B, 1.0, L.rb);
         launch_spmm(s, L.R, L.rb, 1.0, nullptr, 0.0, C.bb);
     }
     if (l + 1 < np || l + 1 == last || l >= np) {
-        cycle_block(ctx, l + 1, C.bb, C.xb, true);
+        cycle_block(ctx, l + 1, C.bb, C.xb, true, transpose);
     } else {
-        for (int t = 0; t < ctx->opts.n_v; ++t) cycle_block(ctx, l + 1, C.bb, C.xb, t == 0);
+        for (int t = 0; t < ctx->opts.n_v; ++t) cycle_block(ctx, l + 1, C.bb, C.xb, t == 0, transpose);
     }
     {
         Timed t(ctx, PHMG_K_SPMV, l);
         launch_spmm(s, L.P, C.xb, 1.0, X, 1.0, X);
     }
-    relax_block(ctx, l, B, X, nu, false);
+    relax_block(ctx, l, B, X, nu, false, transpose);
 }
 
-void vcycle_block(phmg_ctx ctx, const double* B, double* X) {
+void vcycle_block(phmg_ctx ctx, const double* B, double* X, bool transpose = false) {
     if (ctx->opts.n_plevels == 0) {
-        for (int t = 0; t < ctx->opts.n_v; ++t) cycle_block(ctx, 0, B, X, t == 0);
+        for (int t = 0; t < ctx->opts.n_v; ++t) cycle_block(ctx, 0, B, X, t == 0, transpose);
     } else {
-        cycle_block(ctx, 0, B, X, true);
+        cycle_block(ctx, 0, B, X, true, transpose);
     }
 }
 
 // One block V-cycle (bgin -> bgout) captured on the private stream; kernels
 // only, so a replay is exact.  Rebuilt whenever graph_signature() changes.
-void build_block_graph(phmg_ctx ctx) {
+void build_block_graph(phmg_ctx ctx, bool transpose) {
     const int64_t nb = (int64_t)ctx->L[0].n * kBS;
     if (!ctx->cap_stream) hipcheck(hipStreamCreate(&ctx->cap_stream), "hipStreamCreate");
     if (!ctx->bgin) {
@@ -279,7 +283,7 @@ void build_block_graph(phmg_ctx ctx) {
     ctx->stream = ctx->cap_stream;
     hipcheck(hipStreamBeginCapture(ctx->cap_stream, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
     try {
-        vcycle_block(ctx, ctx->bgin, ctx->bgout);
+        vcycle_block(ctx, ctx->bgin, ctx->bgout, transpose);
     } catch (...) {
         hipGraph_t g = nullptr;
         (void)hipStreamEndCapture(ctx->cap_stream, &g);
@@ -288,21 +292,28 @@ void build_block_graph(phmg_ctx ctx) {
         throw;
     }
     ctx->stream = saved;
-    hipcheck(hipStreamEndCapture(ctx->cap_stream, &ctx->bgraph), "hipStreamEndCapture");
-    hipcheck(hipGraphInstantiate(&ctx->bexec, ctx->bgraph, nullptr, nullptr, 0), "hipGraphInstantiate");
-    ctx->bsig = graph_signature(ctx);
+    const int t = transpose ? 1 : 0;
+    hipcheck(hipStreamEndCapture(ctx->cap_stream, &ctx->bgraph[t]), "hipStreamEndCapture");
+    hipcheck(hipGraphInstantiate(&ctx->bexec[t], ctx->bgraph[t], nullptr, nullptr, 0), "hipGraphInstantiate");
+    ctx->bsig[t] = graph_signature(ctx);
 }
 
-void precond_block(phmg_ctx ctx, const double* B, double* X) {
+void precond_block(phmg_ctx ctx, const double* B, double* X, bool transpose = false) {
     if (!ctx->use_graphs || ctx->prof.mask) {
-        vcycle_block(ctx, B, X);
+        vcycle_block(ctx, B, X, transpose);
         return;
     }
-    if (ctx->bexec && ctx->bsig != graph_signature(ctx)) invalidate_block_graph(ctx);
-    if (!ctx->bexec) build_block_graph(ctx);
+    const int t = transpose ? 1 : 0;
+    if (ctx->bexec[t] && ctx->bsig[t] != graph_signature(ctx)) {
+        (void)hipGraphExecDestroy(ctx->bexec[t]);
+        (void)hipGraphDestroy(ctx->bgraph[t]);
+        ctx->bexec[t] = nullptr;
+        ctx->bgraph[t] = nullptr;
+    }
+    if (!ctx->bexec[t]) build_block_graph(ctx, transpose);
     const int64_t nb = (int64_t)ctx->L[0].n * kBS;
     launch_copy(ctx->stream, nb, B, ctx->bgin);
-    hipcheck(hipGraphLaunch(ctx->bexec, ctx->stream), "hipGraphLaunch");
+    hipcheck(hipGraphLaunch(ctx->bexec[t], ctx->stream), "hipGraphLaunch");
     launch_copy(ctx->stream, nb, ctx->bgout, X);
 }
 
@@ -335,7 +346,7 @@ void upload_scales(phmg_ctx ctx, const double* den, const bool* act) {
 // update and true residual and either stops or restarts: the iterates and
 // counts of a column are those of the single-system FGMRES.
 phmg_status fgmres_block(phmg_ctx ctx, int nrhs, const double* B, double* X, double rtol, int restart, int maxit,
-                         int32_t* iters_out, double* relres_out) {
+                         int32_t* iters_out, double* relres_out, bool transpose = false) {
     Level& L0 = ctx->L[0];
     const int64_t n = L0.n;
     const int64_t nb = n * kBS;
@@ -348,7 +359,8 @@ phmg_status fgmres_block(phmg_ctx ctx, int nrhs, const double* B, double* X, dou
     double* dh = ctx->bh;
     double* hh = ctx->bhhost;
 
-    launch_spmm(s, L0.K, X, -1.0, B, 1.0, r);
+    const DevCsr& A = transpose ? L0.KT : L0.K;
+    launch_spmm(s, A, X, -1.0, B, 1.0, r);
     std::vector<double> beta(kBS), r0(kBS), target(kBS);
     block_norms(ctx, r, beta.data());
     std::vector<int> iters(kBS, 0);
@@ -390,8 +402,8 @@ phmg_status fgmres_block(phmg_ctx ctx, int nrhs, const double* B, double* X, dou
         for (int j = 0; j < restart; ++j) {
             double* vj = V + (int64_t)j * nb;
             double* zj = Z + (int64_t)j * nb;
-            precond_block(ctx, vj, zj);
-            launch_spmm(s, L0.K, zj, 1.0, nullptr, 0.0, w);
+            precond_block(ctx, vj, zj, transpose);
+            launch_spmm(s, A, zj, 1.0, nullptr, 0.0, w);
             launch_block_gs(s, 0, n, j + 1, V, nb, w, nullptr, ctx->bpartial, dh + kOffH1);
             launch_block_gs(s, 1, n, j + 1, V, nb, w, dh + kOffH1, ctx->bpartial, dh + kOffH2);
             launch_block_gs(s, 2, n, j + 1, V, nb, w, dh + kOffH2, ctx->bpartial, dh + kOffHN);
@@ -453,7 +465,7 @@ phmg_status fgmres_block(phmg_ctx ctx, int nrhs, const double* B, double* X, dou
         hipcheck(hipMemcpyAsync(dh + kOffY, hh + kOffY, sizeof(double) * nmax * kBS, hipMemcpyHostToDevice, s),
                  "H2D");
         launch_block_gemv_add(s, n, nmax, Z, nb, dh + kOffY, X);
-        launch_spmm(s, L0.K, X, -1.0, B, 1.0, r);
+        launch_spmm(s, A, X, -1.0, B, 1.0, r);
         block_norms(ctx, r, beta.data());
         for (int c = 0; c < kBS; ++c) {
             if (done[c]) continue;
@@ -472,6 +484,15 @@ phmg_status fgmres_block(phmg_ctx ctx, int nrhs, const double* B, double* X, dou
         all = all && conv[c];
     }
     return all ? PHMG_OK : PHMG_ENOCONV;
+}
+
+// the batched adjoint applies K_i^{-1} as K_i^{-T}: every relaxed level must be
+// symmetric to rounding (after set-up in the default layout)
+void check_block_adjoint(phmg_ctx ctx) {
+    for (size_t l = 0; l + 1 < ctx->L.size(); ++l)
+        if (ctx->L[l].npatch > 0 && !ctx->L[l].sym)
+            fail(PHMG_EINVAL, lvl((int)l) + "the batched adjoint needs symmetric levels in the symmetric layout; "
+                                           "use phmg_fgmres_solve_transposed per system");
 }
 
 void check_block_args(phmg_ctx ctx, int level, int nrhs, const void* B, const void* X) {
@@ -520,23 +541,51 @@ phmg_status phmg_vcycle_batched(phmg_ctx ctx, int nrhs, const double* B, double*
     });
 }
 
-phmg_status phmg_fgmres_solve_batched(phmg_ctx ctx, int nrhs, const double* B, double* X, double rtol, int restart,
-                                      int maxit, int32_t* iters, double* relres) {
+namespace {
+phmg_status fgmres_batched_entry(phmg_ctx ctx, int nrhs, const double* B, double* X, double rtol, int restart,
+                                 int maxit, int32_t* iters, double* relres, bool transpose) {
     return guarded([&] {
         check_block_args(ctx, 0, nrhs, B, X);
         if (!iters || !relres) fail(PHMG_EINVAL, "null output");
         if (!(rtol > 0.0) || restart < 1 || restart >= kHB || maxit < 1)
             fail(PHMG_EINVAL, "need rtol > 0, 1 <= restart <= " + std::to_string(kHB - 1) + ", maxit >= 1");
         prepare_block(ctx);
+        if (transpose) check_block_adjoint(ctx);
         Level& L = ctx->L[0];
         hipStream_t s = ctx->stream;
         launch_interleave(s, L.n, nrhs, B, L.bb);
         launch_interleave(s, L.n, nrhs, X, L.xb);
-        const phmg_status st = fgmres_block(ctx, nrhs, L.bb, L.xb, rtol, restart, maxit, iters, relres);
+        const phmg_status st = fgmres_block(ctx, nrhs, L.bb, L.xb, rtol, restart, maxit, iters, relres, transpose);
         launch_deinterleave(s, L.n, nrhs, L.xb, X);
         hipcheck(hipStreamSynchronize(s), "hipStreamSynchronize");
         if (st == PHMG_ENOCONV) g_last_error = "fgmres_solve_batched: maxit reached before rtol in some column";
         return st;
+    });
+}
+}  // namespace
+
+phmg_status phmg_fgmres_solve_batched(phmg_ctx ctx, int nrhs, const double* B, double* X, double rtol, int restart,
+                                      int maxit, int32_t* iters, double* relres) {
+    return fgmres_batched_entry(ctx, nrhs, B, X, rtol, restart, maxit, iters, relres, false);
+}
+
+phmg_status phmg_fgmres_solve_batched_transposed(phmg_ctx ctx, int nrhs, const double* B, double* X, double rtol,
+                                                 int restart, int maxit, int32_t* iters, double* relres) {
+    return fgmres_batched_entry(ctx, nrhs, B, X, rtol, restart, maxit, iters, relres, true);
+}
+
+phmg_status phmg_vcycle_batched_transposed(phmg_ctx ctx, int nrhs, const double* B, double* X) {
+    return guarded([&] {
+        check_block_args(ctx, 0, nrhs, B, X);
+        prepare_block(ctx);
+        check_block_adjoint(ctx);
+        Level& L = ctx->L[0];
+        hipStream_t s = ctx->stream;
+        launch_interleave(s, L.n, nrhs, B, L.bb);
+        precond_block(ctx, L.bb, L.xb, true);
+        launch_deinterleave(s, L.n, nrhs, L.xb, X);
+        hipcheck(hipGetLastError(), "vcycle_batched_transposed launch");
+        return PHMG_OK;
     });
 }
 

@@ -160,7 +160,9 @@ __global__ __launch_bounds__(kBlock) void block_apply_kernel(const int32_t* __re
                                                              const int32_t* __restrict__ pdofs,
                                                              const int64_t* __restrict__ foff,
                                                              const T* __restrict__ F, const double* __restrict__ X,
-                                                             double* __restrict__ Y) {
+                                                             double* __restrict__ Y,
+                                                             const double* __restrict__ gw,
+                                                             const int32_t* __restrict__ pidx) {
     typedef typename Mfma<Acc>::acc_t acc_t;
     constexpr int NW = kBlock / kWave;
     constexpr int GROUP = 16 * V;                 // rows of one row group
@@ -172,9 +174,15 @@ __global__ __launch_bounds__(kBlock) void block_apply_kernel(const int32_t* __re
     const int m = (int)(pptr[p + 1] - base);
     const int mpad = (m + 3) & ~3;
     const int ld = (m + factor_pad<T>() - 1) / factor_pad<T>() * factor_pad<T>();
+    // gw (adjoint sweep): the weight of the gathered DoF, W_i before the solve
     for (int t = threadIdx.x; t < mpad * kBS; t += kBlock) {
         const int l = t / kBS, c = t % kBS;
-        s_g[t] = l < m ? (Acc)X[(int64_t)pdofs[base + l] * kBS + c] : (Acc)0;
+        double v = 0.0;
+        if (l < m) {
+            v = X[(int64_t)pdofs[base + l] * kBS + c];
+            if (gw) v *= gw[base + pidx[base + l]];
+        }
+        s_g[t] = (Acc)v;
     }
     __syncthreads();
     const T* A = F + foff[p];
@@ -452,59 +460,64 @@ void launch_spmm(hipStream_t s, const DevCsr& A, const double* X, double alpha, 
 
 namespace {
 template <typename T, typename Acc, int V, int NT, int U>
-void launch_block_shape(hipStream_t s, const Level& L, const void* factors, const int64_t* off, const double* X) {
+void launch_block_shape(hipStream_t s, const Level& L, const void* factors, const int64_t* off, const double* X,
+                        const double* gw) {
     const size_t lds = sizeof(Acc) * (size_t)((L.max_m + 3) & ~3) * kBS;
     auto kernel = block_apply_kernel<T, Acc, V, NT, U>;
     if (lds > 64 * 1024)
         (void)hipFuncSetAttribute((const void*)kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     hipLaunchKernelGGL(kernel, dim3(L.npatch), dim3(kBlock), lds, s, L.order, L.pptr, L.pdofs_perm, off,
-                       (const T*)factors, X, L.Yb);
+                       (const T*)factors, X, L.Yb, gw, L.pidx);
 }
 }  // namespace
 
 int block_variant_count(const Level& /*L*/) { return 4; }
 
-void launch_block_apply(hipStream_t s, const Level& L, const double* X) {
+void launch_block_apply(hipStream_t s, const Level& L, const double* X, bool transpose) {
     if (L.npatch <= 0) return;
+    // adjoint sweep on a symmetric level: K_i^{-T} = K_i^{-1} up to the level's
+    // rounding asymmetry, applied to the weighted gather
+    const double* gw = transpose ? L.pweight : nullptr;
     // symmetric levels keep a general copy for the block path (MFMA on full columns)
     const void* factors = L.sym ? L.bfactors : L.factors;
     const int64_t* off = L.sym ? L.bfoff : L.fofflp;
     const int v = L.block_variant;
     if (L.prec == PHMG_PREC_F32) {
         switch (v) {
-            case 1: launch_block_shape<float, float, 2, 2, 2>(s, L, factors, off, X); break;
-            case 2: launch_block_shape<float, float, 2, 1, 8>(s, L, factors, off, X); break;
-            case 3: launch_block_shape<float, float, 2, 2, 4>(s, L, factors, off, X); break;
-            default: launch_block_shape<float, float, 2, 1, 4>(s, L, factors, off, X);
+            case 1: launch_block_shape<float, float, 2, 2, 2>(s, L, factors, off, X, gw); break;
+            case 2: launch_block_shape<float, float, 2, 1, 8>(s, L, factors, off, X, gw); break;
+            case 3: launch_block_shape<float, float, 2, 2, 4>(s, L, factors, off, X, gw); break;
+            default: launch_block_shape<float, float, 2, 1, 4>(s, L, factors, off, X, gw);
         }
     } else if (L.prec == PHMG_PREC_BF16) {
         switch (v) {
-            case 1: launch_block_shape<__hip_bfloat16, float, 4, 1, 2>(s, L, factors, off, X); break;
-            case 2: launch_block_shape<__hip_bfloat16, float, 4, 1, 8>(s, L, factors, off, X); break;
-            case 3: launch_block_shape<__hip_bfloat16, float, 4, 2, 2>(s, L, factors, off, X); break;
-            default: launch_block_shape<__hip_bfloat16, float, 4, 1, 4>(s, L, factors, off, X);
+            case 1: launch_block_shape<__hip_bfloat16, float, 4, 1, 2>(s, L, factors, off, X, gw); break;
+            case 2: launch_block_shape<__hip_bfloat16, float, 4, 1, 8>(s, L, factors, off, X, gw); break;
+            case 3: launch_block_shape<__hip_bfloat16, float, 4, 2, 2>(s, L, factors, off, X, gw); break;
+            default: launch_block_shape<__hip_bfloat16, float, 4, 1, 4>(s, L, factors, off, X, gw);
         }
     } else {
         switch (v) {
-            case 1: launch_block_shape<double, double, 1, 2, 4>(s, L, factors, off, X); break;
-            case 2: launch_block_shape<double, double, 1, 1, 8>(s, L, factors, off, X); break;
-            case 3: launch_block_shape<double, double, 1, 4, 2>(s, L, factors, off, X); break;
-            default: launch_block_shape<double, double, 1, 1, 4>(s, L, factors, off, X);
+            case 1: launch_block_shape<double, double, 1, 2, 4>(s, L, factors, off, X, gw); break;
+            case 2: launch_block_shape<double, double, 1, 1, 8>(s, L, factors, off, X, gw); break;
+            case 3: launch_block_shape<double, double, 1, 4, 2>(s, L, factors, off, X, gw); break;
+            default: launch_block_shape<double, double, 1, 1, 4>(s, L, factors, off, X, gw);
         }
     }
 }
 
 void launch_block_scatter(hipStream_t s, const Level& L, double a, double c, double* d, bool store_d, double* X,
-                          bool x_zero) {
+                          bool x_zero, bool transpose) {
     if (L.n <= 0) return;
     const int flags = (x_zero ? 1 : 0) | (c != 0.0 ? 2 : 0) | (store_d ? 4 : 0);
     hipLaunchKernelGGL(block_scatter_kernel, dim3(grid_for((int64_t)L.n * kBS, kBlock)), dim3(kBlock), 0, s, L.n,
-                       L.sptr, L.sslot, L.pweight, L.Yb, a, c, d, X, flags);
+                       L.sptr, L.sslot, transpose ? nullptr : L.pweight, L.Yb, a, c, d, X, flags);
 }
 
-void launch_block_coarse_solve(hipStream_t s, const Level& L, const double* B, double* X) {
+void launch_block_coarse_solve(hipStream_t s, const Level& L, const double* B, double* X, bool transpose) {
+    // transposed: the column-major inverse read row by row is the transposed inverse
     hipLaunchKernelGGL(block_coarse_solve_kernel, dim3(grid_for((int64_t)L.n * kWave, kBlock)), dim3(kBlock), 0, s,
-                       L.n, L.nb, L.cinv, B, X);
+                       L.n, L.nb, transpose ? L.cdense : L.cinv, B, X);
 }
 
 void launch_block_gs(hipStream_t s, int mode, int64_t n, int ncol, const double* V, int64_t ldv, double* w,

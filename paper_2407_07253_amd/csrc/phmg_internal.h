@@ -209,9 +209,9 @@ struct phmg_ctx_s {
     double* bhhost = nullptr;        // pinned mirror of bh
     double* bgin = nullptr;
     double* bgout = nullptr;
-    hipGraph_t bgraph = nullptr;
-    hipGraphExec_t bexec = nullptr;
-    std::vector<uint64_t> bsig;
+    hipGraph_t bgraph[2] = {nullptr, nullptr};      // [0] block B, [1] block B^T
+    hipGraphExec_t bexec[2] = {nullptr, nullptr};
+    std::vector<uint64_t> bsig[2];
 };
 
 // The full-block-factorisation preconditioner: a velocity-block hierarchy (its
@@ -351,11 +351,13 @@ void invalidate_block_graph(phmg_ctx ctx);
 // ---- block launchers (block_kernels.hip): n x kBS interleaved vectors ---------
 void launch_spmm(hipStream_t s, const DevCsr& A, const double* X, double alpha, const double* Z, double beta,
                  double* Y);
-void launch_block_apply(hipStream_t s, const Level& L, const double* X);
+// transpose: Y_i = K_i^{-T} W_i X[S_i] (symmetric levels only: the general copy's K_i^{-1} with the
+// weights at the gather)
+void launch_block_apply(hipStream_t s, const Level& L, const double* X, bool transpose = false);
 int block_variant_count(const Level& L);
 void launch_block_scatter(hipStream_t s, const Level& L, double a, double c, double* d, bool store_d, double* X,
-                          bool x_zero);
-void launch_block_coarse_solve(hipStream_t s, const Level& L, const double* B, double* X);
+                          bool x_zero, bool transpose = false);
+void launch_block_coarse_solve(hipStream_t s, const Level& L, const double* B, double* X, bool transpose = false);
 // mode 0: h = V^T w;  1: w -= V h, then h' = V^T w;  2: w -= V h, then ||w||^2 (per column)
 void launch_block_gs(hipStream_t s, int mode, int64_t n, int ncol, const double* V, int64_t ldv, double* w,
                      const double* h, double* partial, double* out);

@@ -162,3 +162,56 @@ def test_transposed_reduced_precision_is_the_adjoint(prec, storage):
     print(f"{prec} ({storage}): adjoint defect {d:.2e}")
     assert d <= 1e-5
     H.close()
+
+
+@pytest.mark.parametrize("name,nrhs", [("cfg1", 3), ("cfg2_r1", 16), ("sv_small", 5)])
+def test_batched_transposed_vcycle_matches_oracle(name, nrhs):
+    """Every column of the block adjoint cycle equals the oracle's transposed V-cycle."""
+    fh, H, ol, od, oopts, ob = _pair(name, "auto")
+    for l in range(len(ol) - 1):
+        assert H.level_info(l)["symmetric_storage"], l
+    rng = np.random.default_rng(40 + nrhs)
+    B = rng.standard_normal((nrhs, ol[0].n))
+    Z = _dev(np.full((nrhs, ol[0].n), np.nan))      # content on entry is ignored
+    H.vcycle_batched_transposed(_dev(B), Z)
+    got = _host(Z)
+    worst = max(_rel(got[c], omg.vcycle(ol, oopts, B[c], transpose=True)) for c in range(nrhs))
+    print(f"{name} batched transposed vcycle nrhs={nrhs}: worst column rel err {worst:.2e}")
+    assert worst <= 1e-11
+
+
+@pytest.mark.parametrize("name,nrhs", [("cfg1", 2), ("cfg2_r1", 6), ("sv_small", 3)])
+def test_batched_transposed_fgmres_equals_single_system_path(name, nrhs):
+    """Each column of the lockstep adjoint solve takes the iterations of its own transposed solve."""
+    fh, H, ol, od, oopts, ob = _pair(name, "auto")
+    rng = np.random.default_rng(60 + nrhs)
+    nfu = od[0].nfu
+    G = rng.standard_normal((nrhs, ol[0].n))
+    G[:, 2 * nfu:] -= G[:, 2 * nfu:].mean(axis=1, keepdims=True)
+    G[0] = 0.0                                          # a zero column converges at 0 iterations
+    X = _dev(np.zeros_like(G))
+    iters, relres, conv = H.fgmres_batched_transposed(_dev(G), X, rtol=1e-8)
+    got = _host(X)
+    assert conv and iters[0] == 0 and np.all(got[0] == 0.0)
+    KT = ol[0].K.T.tocsr()
+    for c in range(1, nrhs):
+        x1 = _dev(np.zeros(ol[0].n))
+        it1, rr1, conv1 = H.fgmres_transposed(_dev(G[c]), x1, rtol=1e-8)
+        one = _normalise(_host(x1), nfu)
+        err = np.linalg.norm(_normalise(got[c], nfu) - one) / np.linalg.norm(one)
+        true_rel = np.linalg.norm(G[c] - KT @ got[c]) / np.linalg.norm(G[c])
+        print(f"{name} column {c}: batched iters {iters[c]} relres {relres[c]:.3e}; single iters {it1} "
+              f"relres {rr1:.3e}; rel diff {err:.2e}; true relres {true_rel:.3e}")
+        assert conv1 and iters[c] == it1
+        assert err <= 1e-10
+        assert true_rel <= 1e-8 * (1 + 1e-6)
+
+
+def test_batched_transposed_needs_symmetric_layout():
+    from paper_2407_07253_amd._lib import PhmgError
+    fh, H, ol, od, oopts, ob = _pair("cfg1", "general")
+    n = ol[0].n
+    with pytest.raises(PhmgError):
+        H.vcycle_batched_transposed(_dev(np.ones((2, n))), _dev(np.zeros((2, n))))
+    with pytest.raises(PhmgError):
+        H.fgmres_batched_transposed(_dev(np.ones((2, n))), _dev(np.zeros((2, n))))

@@ -32,9 +32,9 @@ def _direct(K, z, b):
     return spla.spsolve(Kb, np.concatenate([b, [0.0]]))[:-1]
 
 
-def _inputs():
+def _inputs(batched_adjoint=True):
     from paper_2407_07253_amd.adjoint import StokesProblem
-    problem = StokesProblem(NAME, rtol=1e-12)
+    problem = StokesProblem(NAME, rtol=1e-12, batched_adjoint=batched_adjoint)
     lv = synth.log_viscosity(problem.mesh.verts, seed=5)
     fh, H = problem.hierarchy(lv)
     n0, p0, nf = problem.sizes
@@ -54,8 +54,9 @@ def _J(problem, f, l, T, p0):
     return 0.5 * ((X[:, :p0] - Tt[:, :p0]) ** 2).sum()
 
 
-def test_gradients_match_oracle_adjoint():
-    problem, lv, fn, T, p0 = _inputs()
+@pytest.mark.parametrize("batched_adjoint", [True, False])
+def test_gradients_match_oracle_adjoint(batched_adjoint):
+    problem, lv, fn, T, p0 = _inputs(batched_adjoint)
     f = torch.tensor(fn.reshape(NRHS, -1), device="cuda", requires_grad=True)
     l = torch.tensor(lv, device="cuda", requires_grad=True)
     J = _J(problem, f, l, T, p0)

@@ -251,12 +251,14 @@ __global__ __launch_bounds__(kBlock) void block_apply_kernel(const int32_t* __re
 }
 
 // ---------------------------------------------------------------------------
-// s = sum_{slots t of DoF j, ascending patch id} w_t Y[t, c];  dn = a s + c' d;
+// s = sum_{slots t of DoF j, ascending patch id} w_t Y[t, c] (or wd_j times the
+// unweighted sum, one weight per DoF);  dn = a s + c' d;
 // X = (x_zero ? 0 : X) + dn;  d = dn when storing.  One lane per (DoF, column).
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(kBlock) void block_scatter_kernel(int32_t n, const int32_t* __restrict__ sptr,
                                                                const int32_t* __restrict__ sslot,
                                                                const double* __restrict__ w,
+                                                               const double* __restrict__ wd,
                                                                const double* __restrict__ Y, double a, double cd,
                                                                double* __restrict__ d, double* __restrict__ x,
                                                                int flags) {
@@ -264,6 +266,7 @@ __global__ __launch_bounds__(kBlock) void block_scatter_kernel(int32_t n, const 
     const int64_t j = t / kBS;
     const int c = (int)(t % kBS);
     if (j >= n) return;
+    const double wj = wd ? wd[j] : 1.0;
     double s = 0.0;
     const int end = sptr[j + 1];
     // four slots in flight, summed in ascending slot order (a missing slot adds +0)
@@ -280,6 +283,7 @@ __global__ __launch_bounds__(kBlock) void block_scatter_kernel(int32_t n, const 
 #pragma unroll
         for (int u = 0; u < 4; ++u) s += w ? wq[u] * y[u] : y[u];
     }
+    if (wd) s *= wj;
     double dn = a * s;
     if (flags & 2) dn = cd * d[t] + dn;
     x[t] = (flags & 1) ? dn : x[t] + dn;
@@ -510,8 +514,10 @@ void launch_block_scatter(hipStream_t s, const Level& L, double a, double c, dou
                           bool x_zero, bool transpose) {
     if (L.n <= 0) return;
     const int flags = (x_zero ? 1 : 0) | (c != 0.0 ? 2 : 0) | (store_d ? 4 : 0);
+    const double* w = transpose || L.wdof ? nullptr : L.pweight;
+    const double* wd = transpose ? nullptr : L.wdof;
     hipLaunchKernelGGL(block_scatter_kernel, dim3(grid_for((int64_t)L.n * kBS, kBlock)), dim3(kBlock), 0, s, L.n,
-                       L.sptr, L.sslot, transpose ? nullptr : L.pweight, L.Yb, a, c, d, X, flags);
+                       L.sptr, L.sslot, w, wd, L.Yb, a, c, d, X, flags);
 }
 
 void launch_block_coarse_solve(hipStream_t s, const Level& L, const double* B, double* X, bool transpose) {

@@ -765,16 +765,18 @@ __global__ __launch_bounds__(kBlock) void max_tol_kernel(const double* __restric
     if (threadIdx.x == 0) tol[0] = 1e-14 * fmax(fmax(sh[0], sh[1]), fmax(sh[2], sh[3]));
 }
 
-// s_j = sum_{slots t of DoF j, ascending patch id} w_t Y[t];  dn = a s_j + c d_j;
+// s_j = sum_{slots t of DoF j, ascending patch id} w_t Y[t], or with one weight
+// per DoF (wd) s_j = wd_j sum_t Y[t];  dn = a s_j + c d_j;
 // x_j = (x_zero ? 0 : x_j) + dn;  d_j = dn when storing (Chebyshev direction).
 // Richardson is a = omega, c = 0.
 __global__ __launch_bounds__(kBlock) void scatter_kernel(int32_t n, const int32_t* __restrict__ sptr,
                                                          const int32_t* __restrict__ sslot,
-                                                         const double* __restrict__ w, const double* __restrict__ Y,
-                                                         double a, double c, double* __restrict__ d,
-                                                         double* __restrict__ x, int flags) {
+                                                         const double* __restrict__ w, const double* __restrict__ wd,
+                                                         const double* __restrict__ Y, double a, double c,
+                                                         double* __restrict__ d, double* __restrict__ x, int flags) {
     const int j = blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= n) return;
+    const double wj = wd ? wd[j] : 1.0;
     double s = 0.0;
     const int end = sptr[j + 1];
     // four slots in flight (indices first, then the gathers); the sum still
@@ -792,6 +794,7 @@ __global__ __launch_bounds__(kBlock) void scatter_kernel(int32_t n, const int32_
 #pragma unroll
         for (int u = 0; u < 4; ++u) s += w ? wq[u] * y[u] : y[u];
     }
+    if (wd) s *= wj;
     double dn = a * s;
     if (flags & 2) dn = c * d[j] + dn;
     x[j] = (flags & 1) ? dn : x[j] + dn;
@@ -1147,8 +1150,10 @@ void launch_scatter(hipStream_t s, const Level& L, double a, double c, double* d
                     bool x_zero, bool transpose) {
     if (L.n <= 0) return;
     const int flags = (x_zero ? 1 : 0) | (c != 0.0 ? 2 : 0) | (store_d ? 4 : 0);
-    hipLaunchKernelGGL(scatter_kernel, dim3(grid_for(L.n, kBlock)), dim3(kBlock), 0, s, L.n, L.sptr, L.sslot,
-                       transpose ? nullptr : L.pweight, L.Y, a, c, d, x, flags);
+    const double* w = transpose || L.wdof ? nullptr : L.pweight;
+    const double* wd = transpose ? nullptr : L.wdof;
+    hipLaunchKernelGGL(scatter_kernel, dim3(grid_for(L.n, kBlock)), dim3(kBlock), 0, s, L.n, L.sptr, L.sslot, w, wd,
+                       L.Y, a, c, d, x, flags);
 }
 
 void launch_power_start(hipStream_t s, int64_t n, double* v) {

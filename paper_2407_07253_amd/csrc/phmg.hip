@@ -550,6 +550,7 @@ std::vector<uint64_t> phmg::graph_signature(phmg_ctx ctx) {
         p(L.bfactors);
         p(L.bfoff);
         p(L.Y);
+        p(L.wdof);
         p(L.Yb);
         p(L.cinv);
         p(L.cdense);
@@ -1265,6 +1266,18 @@ phmg_status phmg_hierarchy_create(const phmg_hierarchy_desc* desc, const phmg_cy
                 L.order = upload(ctx, order.data(), pt.npatch);
                 L.sptr = upload(ctx, sptr.data(), L.n + 1);
                 L.sslot = upload(ctx, sslot.data(), L.sum_m);
+                if (pt.weight) {
+                    // weights that depend on the DoF alone (e.g. 1 / number of patches
+                    // holding it): sum_i w_ij y_ij = w_j sum_i y_ij, one weight per DoF
+                    std::vector<double> wd(L.n, 1.0);
+                    bool per_dof = true;
+                    for (int32_t j = 0; j < L.n && per_dof; ++j)
+                        for (int32_t k = sptr[j]; k < sptr[j + 1]; ++k) {
+                            if (k == sptr[j]) wd[j] = pt.weight[sslot[k]];
+                            else if (pt.weight[sslot[k]] != wd[j]) per_dof = false;
+                        }
+                    if (per_dof) L.wdof = upload(ctx, wd.data(), L.n);
+                }
                 L.Y = dalloc<double>(ctx, L.sum_m);
             } else {
                 L.nb = desc->coarse_null ? L.n + 1 : L.n;

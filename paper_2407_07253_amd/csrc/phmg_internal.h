@@ -92,6 +92,8 @@ struct Level {
     int32_t* order = nullptr;        // launch order: patches by decreasing size
     int32_t* sptr = nullptr;         // DoF -> slot map for the scatter (n + 1)
     int32_t* sslot = nullptr;        // sum_m slot indices, ascending patch id per DoF
+    double* wdof = nullptr;          // n: the partition weight of each DoF when all its slots share one
+                                     // (the scatter then scales the sum once); null: per-slot weights
     double* Y = nullptr;             // sum_m staging of the patch solutions
     void* factors = nullptr;         // explicit patch inverses in the stored layout, precision `prec`
     size_t factor_bytes = 0;         // allocated size of `factors` (kept across set-ups)

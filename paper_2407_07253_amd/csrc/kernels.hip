@@ -283,6 +283,11 @@ __global__ __launch_bounds__(kBlock) void extract_kernel(const int64_t* __restri
 //   A operand A[l % 16][l / 16], B operand B[l / 16][l % 16],
 //   C/D element D[l / 16 + 4 v][l % 16].
 // ---------------------------------------------------------------------------
+// 16 x 16 accumulator tiles of a column block updated together: one keeps the
+// register count, and so the number of resident waves, highest (measured
+// faster than two or four on the 64..210-DoF patches of the P4/P3 level)
+constexpr int kGjTiles = 1;
+
 template <int R>
 __global__ __launch_bounds__(kBlock) void gj_kernel(const int64_t* __restrict__ pptr,
                                                     const int64_t* __restrict__ foff,
@@ -413,11 +418,11 @@ __global__ __launch_bounds__(kBlock) void gj_kernel(const int64_t* __restrict__ 
                     const int jc = jb * 16 + lk + 4 * v;
                     cv[v] = jc < m && (jc < k0 || jc >= k0 + w);
                 }
-                for (int ib = 0; ib < nb16; ib += 2) {
-                    d4 acc[2];
-                    double aop[2][4];
+                for (int ib = 0; ib < nb16; ib += kGjTiles) {
+                    d4 acc[kGjTiles];
+                    double aop[kGjTiles][4];
 #pragma unroll
-                    for (int h = 0; h < 2; ++h) {
+                    for (int h = 0; h < kGjTiles; ++h) {
                         const int i = (ib + h) * 16 + li;
 #pragma unroll
                         for (int v = 0; v < 4; ++v)
@@ -434,12 +439,12 @@ __global__ __launch_bounds__(kBlock) void gj_kernel(const int64_t* __restrict__ 
                         }
                     }
 #pragma unroll
-                    for (int h = 0; h < 2; ++h)
+                    for (int h = 0; h < kGjTiles; ++h)
 #pragma unroll
                         for (int kt = 0; kt < 4; ++kt)
                             acc[h] = __builtin_amdgcn_mfma_f64_16x16x4f64(bop[kt], aop[h][kt], acc[h], 0, 0, 0);
 #pragma unroll
-                    for (int h = 0; h < 2; ++h) {
+                    for (int h = 0; h < kGjTiles; ++h) {
                         const int i = (ib + h) * 16 + li;
 #pragma unroll
                         for (int v = 0; v < 4; ++v)

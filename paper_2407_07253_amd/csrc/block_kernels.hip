@@ -109,22 +109,31 @@ __global__ __launch_bounds__(kBlock) void spmm_kernel(int32_t nrows, const int32
 // ---------------------------------------------------------------------------
 template <typename T, int V>
 struct BlockLoad;
+typedef float st_f2 __attribute__((ext_vector_type(2)));
+typedef uint32_t st_u2 __attribute__((ext_vector_type(2)));
 template <>
 struct BlockLoad<double, 1> {
-    __device__ static inline void load(const double* p, double (&a)[1]) { a[0] = *p; }
+    template <bool ST>
+    __device__ static inline void load(const double* p, double (&a)[1]) {
+        a[0] = ST ? __builtin_nontemporal_load(p) : *p;
+    }
 };
 template <>
 struct BlockLoad<float, 2> {
+    template <bool ST>
     __device__ static inline void load(const float* p, float (&a)[2]) {
-        const float2 v = *reinterpret_cast<const float2*>(p);
+        const st_f2* q = reinterpret_cast<const st_f2*>(p);
+        const st_f2 v = ST ? __builtin_nontemporal_load(q) : *q;
         a[0] = v.x;
         a[1] = v.y;
     }
 };
 template <>
 struct BlockLoad<__hip_bfloat16, 4> {
+    template <bool ST>
     __device__ static inline void load(const __hip_bfloat16* p, float (&a)[4]) {
-        const uint2 v = *reinterpret_cast<const uint2*>(p);
+        const st_u2* q = reinterpret_cast<const st_u2*>(p);
+        const st_u2 v = ST ? __builtin_nontemporal_load(q) : *q;
         a[0] = __uint_as_float(v.x << 16);
         a[1] = __uint_as_float(v.x & 0xffff0000u);
         a[2] = __uint_as_float(v.y << 16);
@@ -154,7 +163,7 @@ struct Mfma<float> {
     __device__ static inline int row(int lane, int e) { return 4 * (lane / 16) + e; }
 };
 
-template <typename T, typename Acc, int V, int NT, int U>
+template <typename T, typename Acc, int V, int NT, int U, bool ST>
 __global__ __launch_bounds__(kBlock) void block_apply_kernel(const int32_t* __restrict__ order,
                                                              const int64_t* __restrict__ pptr,
                                                              const int32_t* __restrict__ pdofs,
@@ -208,7 +217,7 @@ __global__ __launch_bounds__(kBlock) void block_apply_kernel(const int32_t* __re
                 const T* colp = A + (int64_t)k * ld + r0 + li * V;
 #pragma unroll
                 for (int q = 0; q < NT; ++q) {
-                    if (rowok[q] && k < m) BlockLoad<T, V>::load(colp + q * GROUP, a[u][q]);
+                    if (rowok[q] && k < m) BlockLoad<T, V>::template load<ST>(colp + q * GROUP, a[u][q]);
                     else
 #pragma unroll
                         for (int v = 0; v < V; ++v) a[u][q][v] = 0;
@@ -230,7 +239,7 @@ __global__ __launch_bounds__(kBlock) void block_apply_kernel(const int32_t* __re
 #pragma unroll
             for (int q = 0; q < NT; ++q) {
                 Acc a[V];
-                if (rowok[q] && k < m) BlockLoad<T, V>::load(colp + q * GROUP, a);
+                if (rowok[q] && k < m) BlockLoad<T, V>::template load<ST>(colp + q * GROUP, a);
                 else
 #pragma unroll
                     for (int v = 0; v < V; ++v) a[v] = 0;
@@ -467,7 +476,9 @@ template <typename T, typename Acc, int V, int NT, int U>
 void launch_block_shape(hipStream_t s, const Level& L, const void* factors, const int64_t* off, const double* X,
                         const double* gw) {
     const size_t lds = sizeof(Acc) * (size_t)((L.max_m + 3) & ~3) * kBS;
-    auto kernel = block_apply_kernel<T, Acc, V, NT, U>;
+    // the block path streams the general layout (the general copy on symmetric levels)
+    auto kernel = streams_factors(L, false) ? block_apply_kernel<T, Acc, V, NT, U, true>
+                                            : block_apply_kernel<T, Acc, V, NT, U, false>;
     if (lds > 64 * 1024)
         (void)hipFuncSetAttribute((const void*)kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     hipLaunchKernelGGL(kernel, dim3(L.npatch), dim3(kBlock), lds, s, L.order, L.pptr, L.pdofs_perm, off,

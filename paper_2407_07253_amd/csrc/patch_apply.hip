@@ -24,14 +24,22 @@ namespace phmg {
 namespace {
 
 // One 16-byte load of V consecutive factor rows, widened to the accumulation type.
+// NT: a non-temporal load.  A level whose factors exceed what the caches could
+// keep between sweeps streams them this way, so the stream does not evict the
+// level matrix and vectors that the next kernels of the cycle reuse.
+typedef double nt_d2 __attribute__((ext_vector_type(2)));
+typedef float nt_f4 __attribute__((ext_vector_type(4)));
+typedef uint32_t nt_u4 __attribute__((ext_vector_type(4)));
 template <typename T>
 struct Load16;
 template <>
 struct Load16<double> {
     static constexpr int V = 2;
     typedef double acc_t;
+    template <bool NT>
     __device__ static inline void load(const double* p, double (&a)[2]) {
-        const double2 v = *reinterpret_cast<const double2*>(p);
+        const nt_d2* q = reinterpret_cast<const nt_d2*>(p);
+        const nt_d2 v = NT ? __builtin_nontemporal_load(q) : *q;
         a[0] = v.x;
         a[1] = v.y;
     }
@@ -40,8 +48,10 @@ template <>
 struct Load16<float> {
     static constexpr int V = 4;
     typedef float acc_t;
+    template <bool NT>
     __device__ static inline void load(const float* p, float (&a)[4]) {
-        const float4 v = *reinterpret_cast<const float4*>(p);
+        const nt_f4* q = reinterpret_cast<const nt_f4*>(p);
+        const nt_f4 v = NT ? __builtin_nontemporal_load(q) : *q;
         a[0] = v.x;
         a[1] = v.y;
         a[2] = v.z;
@@ -52,8 +62,10 @@ template <>
 struct Load16<__hip_bfloat16> {
     static constexpr int V = 8;
     typedef float acc_t;
+    template <bool NT>
     __device__ static inline void load(const __hip_bfloat16* p, float (&a)[8]) {
-        const uint4 v = *reinterpret_cast<const uint4*>(p);
+        const nt_u4* q = reinterpret_cast<const nt_u4*>(p);
+        const nt_u4 v = NT ? __builtin_nontemporal_load(q) : *q;
         const uint32_t w[4] = {v.x, v.y, v.z, v.w};
 #pragma unroll
         for (int h = 0; h < 4; ++h) {
@@ -72,7 +84,7 @@ struct Load16<__hip_bfloat16> {
 // chunks of 256 groups.  Each thread sums its columns in ascending order; the
 // 256 / LPC partial sums of a row are then added in ascending thread order, so
 // the result does not depend on U (every compiled shape is bit-identical).
-template <typename T, int U>
+template <typename T, int U, bool NT>
 __global__ __launch_bounds__(kBlock) void patch_apply_kernel(const int32_t* __restrict__ order,
                                                              const int64_t* __restrict__ pptr,
                                                              const int32_t* __restrict__ pdofs,
@@ -107,7 +119,7 @@ __global__ __launch_bounds__(kBlock) void patch_apply_kernel(const int32_t* __re
             for (; j + (U - 1) * cps < m; j += U * cps) {
                 Acc a[U][V];
 #pragma unroll
-                for (int u = 0; u < U; ++u) Load16<T>::load(colbase + (int64_t)(j + u * cps) * ld, a[u]);
+                for (int u = 0; u < U; ++u) Load16<T>::template load<NT>(colbase + (int64_t)(j + u * cps) * ld, a[u]);
 #pragma unroll
                 for (int u = 0; u < U; ++u) {
                     const Acc rj = s_r[j + u * cps];
@@ -117,7 +129,7 @@ __global__ __launch_bounds__(kBlock) void patch_apply_kernel(const int32_t* __re
             }
             for (; j < m; j += cps) {
                 Acc a[V];
-                Load16<T>::load(colbase + (int64_t)j * ld, a);
+                Load16<T>::template load<NT>(colbase + (int64_t)j * ld, a);
                 const Acc rj = s_r[j];
 #pragma unroll
                 for (int v = 0; v < V; ++v) acc[v] += a[v] * rj;
@@ -145,8 +157,12 @@ void launch_shape(hipStream_t s, const Level& L, const double* r) {
     typedef typename Load16<T>::acc_t Acc;
     const int ldbuf = (L.max_m + 1) & ~1;
     const size_t lds = sizeof(Acc) * ((size_t)ldbuf + (size_t)kBlock * Load16<T>::V);
-    hipLaunchKernelGGL((patch_apply_kernel<T, U>), dim3(L.npatch), dim3(kBlock), lds, s, L.order, L.pptr,
-                       L.pdofs_perm, L.fofflp, (const T*)L.factors, r, L.Y, ldbuf);
+    if (streams_factors(L, L.sym))
+        hipLaunchKernelGGL((patch_apply_kernel<T, U, true>), dim3(L.npatch), dim3(kBlock), lds, s, L.order, L.pptr,
+                           L.pdofs_perm, L.fofflp, (const T*)L.factors, r, L.Y, ldbuf);
+    else
+        hipLaunchKernelGGL((patch_apply_kernel<T, U, false>), dim3(L.npatch), dim3(kBlock), lds, s, L.order, L.pptr,
+                           L.pdofs_perm, L.fofflp, (const T*)L.factors, r, L.Y, ldbuf);
 }
 
 template <typename T>
@@ -197,7 +213,7 @@ __device__ inline bool sym_step(int& s, int& c, int ns, int m) {
 // group (both inside the patch's block, finite values).  The caller multiplies
 // such loads only by zero residual entries (rows >= m, columns >= w) or drops
 // their row sums, so they contribute nothing.
-template <typename T>
+template <typename T, bool NT>
 __device__ inline void sym_load(const T* A, int s, int c_lo, int m, int rl, int cl,
                                 typename Load16<T>::acc_t (&a)[SymShape<T>::U][SymShape<T>::V]) {
     typedef SymShape<T> Sh;
@@ -206,7 +222,7 @@ __device__ inline void sym_load(const T* A, int s, int c_lo, int m, int rl, int 
 #pragma unroll
     for (int u = 0; u < Sh::U; ++u) {
         const int j = min(c_lo + cl + Sh::CL * u, w - 1);
-        Load16<T>::load(S + j * hp, a[u]);
+        Load16<T>::template load<NT>(S + j * hp, a[u]);
     }
 }
 
@@ -216,7 +232,7 @@ __device__ inline void sym_load(const T* A, int s, int c_lo, int m, int rl, int 
 // shapes give identical bits.
 constexpr int kSymParts = 4;
 
-template <typename T, bool PF, int NWV>
+template <typename T, bool PF, int NWV, bool NT>
 __global__ __launch_bounds__(kBlock) void patch_apply_sym_kernel(const int32_t* __restrict__ order,
                                                                  const int64_t* __restrict__ pptr,
                                                                  const int32_t* __restrict__ pdofs,
@@ -247,7 +263,7 @@ __global__ __launch_bounds__(kBlock) void patch_apply_sym_kernel(const int32_t* 
     bool ok = true;
     for (int q = 0; q < wave && ok; ++q) ok = sym_step(s, c, ns, m);
     Acc a[U][V];
-    if (ok) sym_load<T>(A, s, c, m, rl, cl, a);
+    if (ok) sym_load<T, NT>(A, s, c, m, rl, cl, a);
     for (int t = threadIdx.x; t < m; t += NTH) {
         const double v = r[pdofs[base + t]];
         s_r[t] = (Acc)(gw ? gw[base + t] * v : v);
@@ -262,9 +278,9 @@ __global__ __launch_bounds__(kBlock) void patch_apply_sym_kernel(const int32_t* 
         Acc* yw = s_y + (unit % NP) * ldbuf;
         Acc b[U][V];
         if (PF) {
-            if (ok2) sym_load<T>(A, s2, c2, m, rl, cl, b);
+            if (ok2) sym_load<T, NT>(A, s2, c2, m, rl, cl, b);
         } else if (!first) {
-            sym_load<T>(A, s, c, m, rl, cl, a);
+            sym_load<T, NT>(A, s, c, m, rl, cl, a);
         }
         first = false;
         const int r0 = s * kStrip, w = min(m, r0 + kStrip);
@@ -327,8 +343,12 @@ void launch_sym_shape(hipStream_t s, const Level& L, const double* r, const doub
     typedef typename Load16<T>::acc_t Acc;
     const int ldbuf = (L.max_m + 1) & ~1;
     const size_t lds = sizeof(Acc) * (size_t)ldbuf * (1 + kSymParts);
-    hipLaunchKernelGGL((patch_apply_sym_kernel<T, PF, NWV>), dim3(L.npatch), dim3(NWV * kWave), lds, s, L.order,
-                       L.pptr, L.pdofs, L.fofflp, (const T*)L.factors, r, gw, L.Y, ldbuf);
+    if (streams_factors(L, L.sym))
+        hipLaunchKernelGGL((patch_apply_sym_kernel<T, PF, NWV, true>), dim3(L.npatch), dim3(NWV * kWave), lds, s,
+                           L.order, L.pptr, L.pdofs, L.fofflp, (const T*)L.factors, r, gw, L.Y, ldbuf);
+    else
+        hipLaunchKernelGGL((patch_apply_sym_kernel<T, PF, NWV, false>), dim3(L.npatch), dim3(NWV * kWave), lds, s,
+                           L.order, L.pptr, L.pdofs, L.fofflp, (const T*)L.factors, r, gw, L.Y, ldbuf);
 }
 
 // shapes: 0 / 1 four waves without / with prefetch, 2 / 3 one wave without / with prefetch

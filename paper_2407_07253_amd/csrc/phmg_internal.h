@@ -309,6 +309,16 @@ void launch_convert_patches(hipStream_t s, const Level& L, const double* src, vo
 void launch_convert_general(hipStream_t s, const Level& L, const double* src, void* dst, const int64_t* off);
 void launch_patch_apply(hipStream_t s, const Level& L, const double* r);
 // adjoint patch solve y_i = K_i^{-T} W_i r[S_i] from the same stored inverses (adjoint_kernels.hip)
+// Patch inverses of more than kStreamBytes (in the given layout and the level's
+// precision) are read with non-temporal loads: a stream that size would only
+// evict, from the 256 MB last-level cache, the level matrix and vectors the
+// rest of the cycle reads; smaller levels keep normal loads, so their factors
+// can stay cached across a cycle's sweeps.
+constexpr size_t kStreamBytes = size_t(64) << 20;
+inline bool streams_factors(const Level& L, bool sym_layout) {
+    const size_t es = L.prec == PHMG_PREC_F64 ? 8 : (L.prec == PHMG_PREC_F32 ? 4 : 2);
+    return es * (size_t)(sym_layout ? L.sum_ls[L.prec] : L.sum_lp[L.prec]) > kStreamBytes;
+}
 void launch_patch_apply_t(hipStream_t s, const Level& L, const double* r);
 int apply_variant_count(const Level& L);
 // symmetric layout: y_i = S_i (g_i * r[S_i]) with g_i = W_i (gw != null, the adjoint sweep) or I

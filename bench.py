@@ -16,7 +16,9 @@ Printed: one JSON line.  ``value`` is the achieved HBM bandwidth of the
 level-0 batched patch-solve kernel in float64 (algorithmic bytes per launch
 divided by its mean duration, HIP events on the library's stream), i.e. the
 "Vanka patch-apply HBM GB/s" half of the metric; the "time-to-1e-8" half is
-reported for float64 and for float32 patch inverses ("mixed") next to it.
+reported for float64 and for float32 / bfloat16 patch inverses ("mixed") next
+to it.  ``setup_roofline`` gives the level-0 patch inversion (set-up) against
+the FP64 MFMA peak, timed the same way.
 """
 from __future__ import annotations
 
@@ -33,6 +35,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "Vanka patch-apply HBM GB/s; phMG-FGMRES time-to-1e-8, mixed vs FP64, 1 GPU"
 HBM_PEAK_GBS = 8000.0
+FP64_MFMA_PEAK_TFLOPS = 78.6      # dense FP64 MFMA peak of MI355X
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "patch_apply_cfg2_traffic.json")
 KERNEL_SOURCE = os.path.join(ROOT, "paper_2407_07253_amd", "csrc", "patch_apply.hip")
 
@@ -368,8 +371,23 @@ def main() -> int:
         H.close()
         return 0
 
+    def factor_leg():
+        # level-0 patch inversion alone (set-up of level 0 only), HIP events on the level's
+        # stream; algorithmic flops of inverting an m x m patch: 2 m^3
+        H.profile(["factor"])
+        H.profile_reset()
+        for _ in range(3):
+            H.setup(0)
+        torch.cuda.synchronize()
+        ms, cnt = H.profile_read("factor", 0)
+        H.profile([])
+        flops = 2.0 * float(np.sum(np.diff(fh.levels[0].patch_ptr).astype(np.float64) ** 3))
+        avg = ms / max(cnt, 1)
+        return dict(avg_ms=avg, launches=cnt, flops=flops, tflops=flops / (avg * 1e-3) / 1e12)
+
     f64 = timed_legs("f64")
     ap64 = apply_leg("f64")
+    gj64 = factor_leg()
     variants = {"f64": [H.level_info(l)["apply_variant"] for l in range(nl - 1)]}
     lambdas = [round(H.level_info(l)["lambda_max"], 6) for l in range(nl - 1)]
     out_mixed, ap_mixed = {}, {}
@@ -418,6 +436,17 @@ def main() -> int:
             "bytes_per_launch": ap64["bytes_per_launch"],
             "avg_launch_ms": round(ap64["avg_ms"], 5),
             "launches": ap64["launches"],
+        },
+        "setup_roofline": {
+            "bound": "mfma",
+            "kernel": "gj_kernel (level-0 patch inversion alone, FP64 MFMA 16x16x4 trailing updates)",
+            "achieved": round(gj64["tflops"], 3),
+            "peak": FP64_MFMA_PEAK_TFLOPS,
+            "unit": "TFLOP/s",
+            "frac": round(gj64["tflops"] / FP64_MFMA_PEAK_TFLOPS, 4),
+            "flops_per_launch": gj64["flops"],
+            "avg_launch_ms": round(gj64["avg_ms"], 4),
+            "launches": gj64["launches"],
         },
         "time_to_1e-8": {"f64": {k: _fmt(v) for k, v in f64.items()}},
         "sweep_level0": {"f64": {"wall_ms": round(ap64["sweep_wall_ms"], 4), "gbps": round(ap64["sweep_gbps"], 1),

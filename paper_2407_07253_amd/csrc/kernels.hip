@@ -481,6 +481,229 @@ __global__ __launch_bounds__(kBlock) void gj_kernel(const int64_t* __restrict__ 
     }
 }
 
+// ---------------------------------------------------------------------------
+// The same blocked Gauss-Jordan inversion for levels of small patches
+// (m <= kGjLdsMax): the whole m x m matrix sits in the workgroup's LDS, so it
+// is read from global memory once and written back once, instead of once per
+// 16-column panel.  Wave 0 eliminates each panel alone (its rows, RW per
+// lane, held in registers: no barriers inside the panel) and writes it back
+// in logical row order; then all waves apply the panel's row swaps to the
+// other columns and the rank-16 update on MFMA f64 16x16x4 tiles, as in
+// gj_kernel.  Same pivots (largest |entry| among logical positions >= k, ties
+// to the lowest position), same stored B = (P K_i)^{-1} and pivot lists.
+// Up to 141 DoFs would fit the 160 KB of LDS, but one wave eliminating 141
+// rows, with one workgroup per CU, measured 3x slower than gj_kernel on the
+// 141-DoF patches; with one row per lane (m <= 64) it is 1.7-2x faster.
+// ---------------------------------------------------------------------------
+constexpr int kGjLdsMax = 64;
+
+template <int RW>
+__global__ __launch_bounds__(kBlock) void gj_lds_kernel(const int64_t* __restrict__ pptr,
+                                                        const int64_t* __restrict__ foff,
+                                                        const int32_t* __restrict__ order, double* __restrict__ F,
+                                                        const double* __restrict__ ptol,
+                                                        const int32_t* __restrict__ pdofs,
+                                                        int32_t* __restrict__ pdofs_perm,
+                                                        int32_t* __restrict__ pidx, int ldq,
+                                                        int* __restrict__ status) {
+    constexpr int W = kPanel, NWV = kBlock / kWave;
+    extern __shared__ double smem[];
+    __shared__ int s_fail;
+    const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
+    const int p = order[blockIdx.x];
+    const int64_t base = pptr[p];
+    const int m = (int)(pptr[p + 1] - base);
+    double* G = F + foff[p];
+    double* A = smem;                                      // m x m, column-major, ld m
+    int* piv = reinterpret_cast<int*>(smem + (int64_t)ldq * ldq);   // pivots of the whole patch (m)
+    int* perm = piv + ldq;                                           // gather list (m)
+    const double tol = ptol[p];
+    const int mm = m * m;
+    for (int e = tid; e < mm; e += kBlock) A[e] = G[e];
+    if (tid == 0) s_fail = 0;
+    __syncthreads();
+
+    for (int k0 = 0; k0 < m; k0 += W) {
+        const int w = min(W, m - k0);
+        if (wave == 0) {
+            // rows lane, lane + 64, ... of the panel; at the panel's start every row
+            // sits at its logical position
+            double v[RW][W];
+            int lpos[RW];
+#pragma unroll
+            for (int q = 0; q < RW; ++q) {
+                const int r = lane + q * kWave;
+                lpos[q] = r;
+#pragma unroll
+                for (int c = 0; c < W; ++c) v[q][c] = (r < m && c < w) ? A[r + (k0 + c) * m] : 0.0;
+            }
+            bool fail = false;
+            for (int c = 0; c < w; ++c) {
+                const int k = k0 + c;
+                double bv = -1.0;
+                int bl = INT_MAX, bo = -1;                        // value, logical position, owner (lane * RW + q)
+#pragma unroll
+                for (int q = 0; q < RW; ++q) {
+                    const int r = lane + q * kWave;
+                    double a = 0.0;
+#pragma unroll
+                    for (int cc = 0; cc < W; ++cc)
+                        if (cc == c) a = fabs(v[q][cc]);
+                    if (r < m && lpos[q] >= k && (a > bv || (a == bv && lpos[q] < bl))) {
+                        bv = a;
+                        bl = lpos[q];
+                        bo = lane * RW + q;
+                    }
+                }
+                for (int off = kWave / 2; off > 0; off >>= 1) {
+                    const double ov = __shfl_xor(bv, off);
+                    const int ol = __shfl_xor(bl, off), oo = __shfl_xor(bo, off);
+                    if (ov > bv || (ov == bv && ol < bl)) {
+                        bv = ov;
+                        bl = ol;
+                        bo = oo;
+                    }
+                }
+                if (bo < 0 || !(bv > tol)) {                      // uniform over the wave
+                    fail = true;
+                    break;
+                }
+                const int ol = bo / RW, oq = bo % RW;
+                double prow[W];
+#pragma unroll
+                for (int cc = 0; cc < W; ++cc) {
+                    double mine = 0.0;
+#pragma unroll
+                    for (int q = 0; q < RW; ++q)
+                        if (q == oq) mine = v[q][cc];
+                    prow[cc] = __shfl(mine, ol);
+                }
+                double pc = 0.0;
+#pragma unroll
+                for (int cc = 0; cc < W; ++cc)
+                    if (cc == c) pc = prow[cc];
+                const double d = 1.0 / pc;
+#pragma unroll
+                for (int q = 0; q < RW; ++q) {
+                    const int r = lane + q * kWave;
+                    if (r >= m) continue;
+                    if (lane * RW + q == bo) {
+#pragma unroll
+                        for (int cc = 0; cc < W; ++cc) v[q][cc] = (cc == c) ? d : prow[cc] * d;
+                        lpos[q] = k;
+                    } else {
+                        double f = 0.0;
+#pragma unroll
+                        for (int cc = 0; cc < W; ++cc)
+                            if (cc == c) f = v[q][cc];
+#pragma unroll
+                        for (int cc = 0; cc < W; ++cc) v[q][cc] = (cc == c) ? -f * d : v[q][cc] - f * (prow[cc] * d);
+                        if (lpos[q] == k) lpos[q] = bl;              // the row at position k moves to bl
+                    }
+                }
+                if (lane == 0) piv[k] = bl;
+            }
+            if (fail) {
+                if (lane == 0) {
+                    s_fail = 1;
+                    atomicMin(status, p);
+                }
+            } else {
+                // the eliminated panel goes back in logical order (rows are in registers)
+#pragma unroll
+                for (int q = 0; q < RW; ++q) {
+                    const int r = lane + q * kWave;
+                    if (r >= m) continue;
+#pragma unroll
+                    for (int c = 0; c < W; ++c)
+                        if (c < w) A[lpos[q] + (k0 + c) * m] = v[q][c];
+                }
+            }
+        }
+        __syncthreads();
+        if (s_fail) return;                                       // uniform: every wave leaves here
+        // row swaps of this panel in every other column
+        for (int j = tid; j < m; j += kBlock) {
+            if (j >= k0 && j < k0 + w) continue;
+            double* cj = A + j * m;
+            for (int c = 0; c < w; ++c) {
+                const int pr = piv[k0 + c];
+                if (pr != k0 + c) {
+                    const double t = cj[k0 + c];
+                    cj[k0 + c] = cj[pr];
+                    cj[pr] = t;
+                }
+            }
+        }
+        __syncthreads();
+        // rank-w update of the other columns on MFMA f64 16x16x4, formed transposed as
+        // in gj_kernel; (Q - E) is read from the panel columns, now in logical order
+        {
+            const int nb16 = (m + 15) / 16;
+            const int li = lane & 15, lk = lane >> 4;
+            for (int jb = wave; jb < nb16; jb += NWV) {
+                const int j = jb * 16 + li;
+                const bool jv = (j < m) && (j < k0 || j >= k0 + w);
+                if (!__any(jv ? 1 : 0)) continue;
+                double bop[4];
+#pragma unroll
+                for (int kt = 0; kt < 4; ++kt) {
+                    const int kk = kt * 4 + lk;
+                    bop[kt] = (jv && kk < w) ? A[(k0 + kk) + j * m] : 0.0;
+                }
+                bool cv[4];
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int jc = jb * 16 + lk + 4 * v;
+                    cv[v] = jc < m && (jc < k0 || jc >= k0 + w);
+                }
+                for (int ib = 0; ib < nb16; ++ib) {
+                    const int i = ib * 16 + li;
+                    d4 acc;
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) acc[v] = (cv[v] && i < m) ? A[i + (jb * 16 + lk + 4 * v) * m] : 0.0;
+                    double aop[4];
+#pragma unroll
+                    for (int kt = 0; kt < 4; ++kt) {
+                        const int kk = kt * 4 + lk;
+                        double a = 0.0;
+                        if (i < m && kk < w) {
+                            a = A[i + (k0 + kk) * m];
+                            if (i == k0 + kk) a -= 1.0;
+                        }
+                        aop[kt] = a;
+                    }
+#pragma unroll
+                    for (int kt = 0; kt < 4; ++kt)
+                        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(bop[kt], aop[kt], acc, 0, 0, 0);
+#pragma unroll
+                    for (int v = 0; v < 4; ++v)
+                        if (cv[v] && i < m) A[i + (jb * 16 + lk + 4 * v) * m] = acc[v];
+                }
+            }
+        }
+        __syncthreads();
+    }
+    for (int e = tid; e < mm; e += kBlock) G[e] = A[e];
+    // P r gather list: idx = identity with the row swaps applied in order
+    if (tid == 0) {
+        for (int t = 0; t < m; ++t) perm[t] = t;
+        for (int k = 0; k < m; ++k) {
+            const int pr = piv[k];
+            if (pr != k) {
+                const int t = perm[k];
+                perm[k] = perm[pr];
+                perm[pr] = t;
+            }
+        }
+    }
+    __syncthreads();
+    for (int t = tid; t < m; t += kBlock) {
+        pdofs_perm[base + t] = pdofs[base + perm[t]];
+        pidx[base + t] = perm[t];
+    }
+}
+
 // f64 set-up result (column-major, ld = m) -> reduced-precision factors with
 // ld = m rounded up to V = factor_pad<T>() (padding rows are zero); one
 // workgroup per patch.
@@ -1096,20 +1319,40 @@ void launch_extract(hipStream_t s, const Level& L, double* out) {
                        L.foff, L.K.rowptr, L.K.col, L.K.val, out, L.ptol);
 }
 
+int gj_lds_max_m() { return kGjLdsMax; }
+
 void launch_patch_factor(hipStream_t s, const Level& L, double* A) {
     if (L.npatch <= 0) return;
-    const int ldq = L.max_m;
-    const size_t lds = sizeof(double) * (size_t)ldq * kPanel + sizeof(int) * 2 * (size_t)ldq;
-    const int R = (L.max_m + kBlock - 1) / kBlock;
+    // patches too large for the LDS (first in the launch order): panels in LDS,
+    // the matrix in global memory
+    if (L.gj_big > 0) {
+        const int ldq = L.max_m;
+        const size_t lds = sizeof(double) * (size_t)ldq * kPanel + sizeof(int) * 2 * (size_t)ldq;
+        const int R = (L.max_m + kBlock - 1) / kBlock;
+        auto go = [&](auto kernel) {
+            if (lds > 64 * 1024)
+                (void)hipFuncSetAttribute((const void*)kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+            hipLaunchKernelGGL(kernel, dim3(L.gj_big), dim3(kBlock), lds, s, L.pptr, L.foff, L.order, A, L.ptol,
+                               L.pdofs, L.pdofs_perm, L.pidx, ldq, L.status);
+        };
+        if (R <= 1) go(gj_kernel<1>);
+        else if (R <= 2) go(gj_kernel<2>);
+        else go(gj_kernel<4>);
+    }
+    // the rest: the whole matrix in LDS
+    const int nsmall = L.npatch - L.gj_big;
+    if (nsmall <= 0) return;
+    const int ldq = L.gj_small_max;
+    const size_t lds = sizeof(double) * (size_t)ldq * ldq + sizeof(int) * 2 * (size_t)ldq;
+    const int RW = (ldq + kWave - 1) / kWave;
     auto go = [&](auto kernel) {
         if (lds > 64 * 1024)
             (void)hipFuncSetAttribute((const void*)kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-        hipLaunchKernelGGL(kernel, dim3(L.npatch), dim3(kBlock), lds, s, L.pptr, L.foff, L.order, A, L.ptol,
-                           L.pdofs, L.pdofs_perm, L.pidx, ldq, L.status);
+        hipLaunchKernelGGL(kernel, dim3(nsmall), dim3(kBlock), lds, s, L.pptr, L.foff, L.order + L.gj_big, A,
+                           L.ptol, L.pdofs, L.pdofs_perm, L.pidx, ldq, L.status);
     };
-    if (R <= 1) go(gj_kernel<1>);
-    else if (R <= 2) go(gj_kernel<2>);
-    else go(gj_kernel<4>);
+    static_assert(kGjLdsMax <= kWave, "one row per lane");
+    if (RW <= 1) go(gj_lds_kernel<1>);
 }
 
 void launch_convert_general(hipStream_t s, const Level& L, const double* src, void* dst, const int64_t* off) {

@@ -90,6 +90,8 @@ struct Level {
     int storage = PHMG_STORAGE_AUTO; // requested layout of the stored inverses
     bool sym = false;                // the stored inverses use the symmetric strip layout
     int32_t* order = nullptr;        // launch order: patches by decreasing size
+    int32_t gj_big = 0;              // leading patches of the launch order inverted with the matrix in global memory
+    int32_t gj_small_max = 0;        // largest of the rest (inverted with the matrix in LDS)
     int32_t* sptr = nullptr;         // DoF -> slot map for the scatter (n + 1)
     int32_t* sslot = nullptr;        // sum_m slot indices, ascending patch id per DoF
     double* wdof = nullptr;          // n: the partition weight of each DoF when all its slots share one
@@ -304,6 +306,7 @@ void launch_spmv_diff(hipStream_t s, const DevCsr& A1, const double* x1, const D
 void launch_extract(hipStream_t s, const Level& L, double* out);
 // invert every patch matrix of the level in place (stored as (P K_i)^{-1}, see kernels.hip)
 void launch_patch_factor(hipStream_t s, const Level& L, double* A);
+int gj_lds_max_m();   // largest patch the LDS-resident inversion takes
 void launch_convert_patches(hipStream_t s, const Level& L, const double* src, void* dst);
 // general layout (offsets off) from the f64 set-up buffer, whatever the level's stored layout
 void launch_convert_general(hipStream_t s, const Level& L, const double* src, void* dst, const int64_t* off);

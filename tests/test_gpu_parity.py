@@ -177,13 +177,15 @@ def test_apply_before_setup_is_a_state_error():
     H.close()
 
 
-def test_singular_patch_is_reported_with_its_id():
-    """A DoF whose row and column are zero makes every patch containing it singular."""
+@pytest.mark.parametrize("name,j", [("cfg1", 40), ("cfg2_r1", 100)])
+def test_singular_patch_is_reported_with_its_id(name, j):
+    """A DoF whose row and column are zero makes every patch containing it singular.  cfg1's
+    level 0 (patches of at most 64 DoFs) is inverted with the matrix in LDS, cfg2_r1's (up to
+    210 DoFs) with the matrix in global memory: both kernels stop and report."""
     from paper_2407_07253_amd._lib import Hierarchy, PhmgError, PHMG_ESINGULAR
-    fh = frontend.build_hierarchy("cfg1")
+    fh = frontend.build_hierarchy(name)
     L0 = fh.levels[0]
     K = L0.K.to_scipy().tolil()
-    j = 40
     K[j, :] = 0.0
     K[:, j] = 0.0
     K = K.tocsr()

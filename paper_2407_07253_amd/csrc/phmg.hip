@@ -251,8 +251,11 @@ void relax(phmg_ctx ctx, int l, const double* b, double* x, int nu, bool x_zero,
 }
 
 // Set-up autotuner of the patch-solve kernel shape: every compiled shape of the
-// level's precision is timed on the level's own patches (HIP events, best of
-// three launches) and the fastest is kept.  Runs once per level and precision.
+// level's precision is timed on the level's own patches (HIP events around
+// kTuneBatch back-to-back launches, best of three batches: one launch of a
+// small level is not much longer than the events around it) and the fastest
+// is kept.  Runs once per level and precision.
+constexpr int kTuneBatch = 8;
 int tune_key(const Level& L) { return L.prec + (L.sym ? 3 : 0); }
 
 void tune_apply(phmg_ctx ctx, int l, hipStream_t s) {
@@ -271,7 +274,7 @@ void tune_apply(phmg_ctx ctx, int l, hipStream_t s) {
         float vbest = 1e30f;
         for (int rep = 0; rep < 3; ++rep) {
             hipcheck(hipEventRecord(e0, s), "hipEventRecord");
-            launch_patch_apply(s, L, L.r);
+            for (int b = 0; b < kTuneBatch; ++b) launch_patch_apply(s, L, L.r);
             hipcheck(hipEventRecord(e1, s), "hipEventRecord");
             hipcheck(hipEventSynchronize(e1), "hipEventSynchronize");
             float ms = 0.f;
@@ -683,7 +686,7 @@ void tune_spmv(phmg_ctx ctx, DevCsr& A, const double* x, double* y) {
         float gbest = 1e30f;
         for (int rep = 0; rep < 3; ++rep) {
             hipcheck(hipEventRecord(e0, s), "hipEventRecord");
-            launch_spmv(s, A, x, 1.0, nullptr, 0.0, y);
+            for (int b = 0; b < kTuneBatch; ++b) launch_spmv(s, A, x, 1.0, nullptr, 0.0, y);
             hipcheck(hipEventRecord(e1, s), "hipEventRecord");
             hipcheck(hipEventSynchronize(e1), "hipEventSynchronize");
             float ms = 0.f;

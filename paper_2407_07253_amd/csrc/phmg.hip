@@ -730,7 +730,7 @@ void tune_spmv_diff(phmg_ctx ctx, Level& L, const double* x, double* y) {
         float gbest = 1e30f;
         for (int rep = 0; rep < 3; ++rep) {
             hipcheck(hipEventRecord(e0, s), "hipEventRecord");
-            launch_spmv_diff(s, L.R, x, A, x, y);
+            for (int b = 0; b < kTuneBatch; ++b) launch_spmv_diff(s, L.R, x, A, x, y);
             hipcheck(hipEventRecord(e1, s), "hipEventRecord");
             hipcheck(hipEventSynchronize(e1), "hipEventSynchronize");
             float ms = 0.f;
@@ -745,8 +745,10 @@ void tune_spmv_diff(phmg_ctx ctx, Level& L, const double* x, double* y) {
     float two = 1e30f;
     for (int rep = 0; rep < 4; ++rep) {
         hipcheck(hipEventRecord(e0, s), "hipEventRecord");
-        launch_spmv(s, L.K, x, -1.0, x, 1.0, L.r);
-        launch_spmv(s, L.R, L.r, 1.0, nullptr, 0.0, y);
+        for (int b = 0; b < kTuneBatch; ++b) {
+            launch_spmv(s, L.K, x, -1.0, x, 1.0, L.r);
+            launch_spmv(s, L.R, L.r, 1.0, nullptr, 0.0, y);
+        }
         hipcheck(hipEventRecord(e1, s), "hipEventRecord");
         hipcheck(hipEventSynchronize(e1), "hipEventSynchronize");
         float ms = 0.f;

@@ -502,8 +502,17 @@ void vcycle(phmg_ctx ctx, const double* b, double* x, bool transpose = false) {
     }
 }
 
+void invalidate_slot_graphs(phmg_ctx ctx) {
+    for (auto& g : ctx->sgraphs) {
+        if (g.e) (void)hipGraphExecDestroy(g.e);
+        if (g.g) (void)hipGraphDestroy(g.g);
+    }
+    ctx->sgraphs.clear();
+}
+
 void invalidate_graph(phmg_ctx ctx) {
     invalidate_block_graph(ctx);
+    invalidate_slot_graphs(ctx);
     for (int t = 0; t < 2; ++t) {
         if (ctx->vexec[t]) (void)hipGraphExecDestroy(ctx->vexec[t]);
         if (ctx->vgraph[t]) (void)hipGraphDestroy(ctx->vgraph[t]);
@@ -574,22 +583,18 @@ std::vector<uint64_t> phmg::graph_signature(phmg_ctx ctx) {
 
 namespace {
 
-// Capture one V-cycle (gin -> gout) on a private stream.  The cycle launches
+// Capture one V-cycle (b -> x) on a private stream.  The cycle launches
 // kernels only (no copies, no memsets, no host synchronisation), so the graph
 // replays it exactly; it is rebuilt whenever graph_signature() changes.
-void build_graph(phmg_ctx ctx, bool transpose) {
-    const int64_t n0 = ctx->L[0].n;
+void capture_vcycle(phmg_ctx ctx, const double* b, double* x, bool transpose, hipGraph_t* graph,
+                    hipGraphExec_t* exec) {
     if (!ctx->cap_stream) hipcheck(hipStreamCreate(&ctx->cap_stream), "hipStreamCreate");
-    if (!ctx->gin) {
-        ctx->gin = dalloc<double>(ctx, n0);
-        ctx->gout = dalloc<double>(ctx, n0);
-    }
     hipStream_t saved = ctx->stream;
     hipcheck(hipStreamSynchronize(saved), "hipStreamSynchronize");
     ctx->stream = ctx->cap_stream;
     hipcheck(hipStreamBeginCapture(ctx->cap_stream, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
     try {
-        vcycle(ctx, ctx->gin, ctx->gout, transpose);
+        vcycle(ctx, b, x, transpose);
     } catch (...) {
         hipGraph_t g = nullptr;
         (void)hipStreamEndCapture(ctx->cap_stream, &g);
@@ -598,15 +603,63 @@ void build_graph(phmg_ctx ctx, bool transpose) {
         throw;
     }
     ctx->stream = saved;
+    hipcheck(hipStreamEndCapture(ctx->cap_stream, graph), "hipStreamEndCapture");
+    hipcheck(hipGraphInstantiate(exec, *graph, nullptr, nullptr, 0), "hipGraphInstantiate");
+}
+
+// the general-purpose graph: gin -> gout, with copies in and out around it
+void build_graph(phmg_ctx ctx, bool transpose) {
+    const int64_t n0 = ctx->L[0].n;
+    if (!ctx->gin) {
+        ctx->gin = dalloc<double>(ctx, n0);
+        ctx->gout = dalloc<double>(ctx, n0);
+    }
     const int t = transpose ? 1 : 0;
-    hipcheck(hipStreamEndCapture(ctx->cap_stream, &ctx->vgraph[t]), "hipStreamEndCapture");
-    hipcheck(hipGraphInstantiate(&ctx->vexec[t], ctx->vgraph[t], nullptr, nullptr, 0), "hipGraphInstantiate");
+    capture_vcycle(ctx, ctx->gin, ctx->gout, transpose, &ctx->vgraph[t], &ctx->vexec[t]);
     ctx->vsig[t] = graph_signature(ctx);
+}
+
+// FGMRES applies the preconditioner to its basis slots V_j -> Z_j only: one graph
+// per (slot, orientation) captured on the slots themselves saves the two copies
+// of the general graph (at most kSlotGraphs of them; the slots' buffers live as
+// long as the Krylov work space, which drops these graphs when it is reallocated)
+constexpr size_t kSlotGraphs = 128;
+
+void precond(phmg_ctx ctx, const double* b, double* x, bool transpose);
+
+void precond_slot(phmg_ctx ctx, const double* b, double* x, bool transpose) {
+    if (!ctx->use_graphs || ctx->prof.mask) {
+        vcycle(ctx, b, x, transpose);
+        return;
+    }
+    const int t = transpose ? 1 : 0;
+    const std::vector<uint64_t> sig = graph_signature(ctx);
+    for (auto& g : ctx->sgraphs) {
+        if (g.b != b || g.x != x || g.t != t) continue;
+        if (g.sig != sig) {
+            (void)hipGraphExecDestroy(g.e);
+            (void)hipGraphDestroy(g.g);
+            g.e = nullptr;
+            g.g = nullptr;
+            capture_vcycle(ctx, b, x, transpose, &g.g, &g.e);
+            g.sig = sig;
+        }
+        hipcheck(hipGraphLaunch(g.e, ctx->stream), "hipGraphLaunch");
+        return;
+    }
+    if (ctx->sgraphs.size() >= kSlotGraphs) {
+        precond(ctx, b, x, transpose);
+        return;
+    }
+    phmg_ctx_s::SlotGraph g{b, x, t, sig, nullptr, nullptr};
+    capture_vcycle(ctx, b, x, transpose, &g.g, &g.e);
+    ctx->sgraphs.push_back(std::move(g));
+    hipcheck(hipGraphLaunch(ctx->sgraphs.back().e, ctx->stream), "hipGraphLaunch");
 }
 
 // x <- B b (one preconditioner application): the captured graph when graphs
 // are on and no per-kernel profiling is requested, the eager launches otherwise.
-void precond(phmg_ctx ctx, const double* b, double* x, bool transpose = false) {
+void precond(phmg_ctx ctx, const double* b, double* x, bool transpose) {
     if (!ctx->use_graphs || ctx->prof.mask) {
         vcycle(ctx, b, x, transpose);
         return;
@@ -975,7 +1028,11 @@ void ensure_krylov(phmg_ctx owner, Krylov& kr, int64_t n, int restart) {
     kr.n = n;
 }
 
-void ensure_krylov(phmg_ctx ctx, int restart) { ensure_krylov(ctx, ctx->kry, ctx->L[0].n, restart); }
+void ensure_krylov(phmg_ctx ctx, int restart) {
+    const double* v = ctx->kry.V;
+    ensure_krylov(ctx, ctx->kry, ctx->L[0].n, restart);
+    if (ctx->kry.V != v) invalidate_slot_graphs(ctx);     // graphs captured on the old slots
+}
 
 // Restarted FGMRES (the reading of the solver paragraph of Section 4; see the
 // ABI notes): matvec(x, alpha, z, beta, y) forms y = alpha A x + beta z,
@@ -1090,7 +1147,7 @@ phmg_status fgmres(phmg_ctx ctx, const double* b, double* x, double rtol, int re
     auto matvec = [&](const double* xx, double alpha, const double* z, double beta, double* y) {
         launch_spmv(s, A, xx, alpha, z, beta, y);
     };
-    auto prec = [&](const double* v, double* z) { precond(ctx, v, z, transpose); };
+    auto prec = [&](const double* v, double* z) { precond_slot(ctx, v, z, transpose); };
     return fgmres_core(s, ctx->kry, L0.n, matvec, prec, b, x, rtol, restart, maxit, iters_out, relres_out);
 }
 
@@ -1382,7 +1439,7 @@ phmg_status phmg_vcycle(phmg_ctx ctx, const double* b, double* x) {
     return guarded([&]() -> phmg_status {
         if (!ctx || !b || !x) fail(PHMG_EINVAL, "null argument");
         require_ready(ctx);
-        precond(ctx, b, x);
+        precond(ctx, b, x, false);
         hipcheck(hipGetLastError(), "kernel launch");
         return PHMG_OK;
     });
@@ -1545,11 +1602,11 @@ void fbf_apply(phmg_fbf F, const double* r, double* z) {
     hipStream_t s = F->A->stream;
     const double* rp = r + F->nu;
     double* zp = z + F->nu;
-    precond(F->A, r, F->yu);                                    // y_u = A~^{-1} r_u
+    precond(F->A, r, F->yu, false);                             // y_u = A~^{-1} r_u
     launch_spmv(s, F->B, F->yu, -1.0, rp, 1.0, F->t);           // t = r_p - B y_u
     launch_spmv(s, F->Sinv, F->t, 1.0, nullptr, 0.0, zp);        // z_p = S~^{-1} t
     launch_spmv(s, F->BT, zp, 1.0, nullptr, 0.0, F->wu);         // w = B^T z_p
-    precond(F->A, F->wu, F->qu);                                // q = A~^{-1} w
+    precond(F->A, F->wu, F->qu, false);                         // q = A~^{-1} w
     launch_axpby(s, F->nu, 1.0, F->yu, -1.0, F->qu, z);          // z_u = y_u - q
 }
 }  // namespace

@@ -190,6 +190,15 @@ struct phmg_ctx_s {
     hipGraph_t vgraph[2] = {nullptr, nullptr};      // [0] B, [1] B^T (adjoint cycle)
     hipGraphExec_t vexec[2] = {nullptr, nullptr};
     std::vector<uint64_t> vsig[2];                  // graph_signature() when each graph was captured
+    struct SlotGraph {                              // a V-cycle captured straight on FGMRES basis slots
+        const double* b;
+        double* x;
+        int t;
+        std::vector<uint64_t> sig;
+        hipGraph_t g;
+        hipGraphExec_t e;
+    };
+    std::vector<SlotGraph> sgraphs;
     // set-up: one stream per level (default priority), fork / join events and
     // pinned status words
     std::vector<hipStream_t> sstreams;

@@ -258,7 +258,21 @@ def test_graph_replays_equal_eager_launches(name):
             r = _dev(np.zeros(n))
             H.residual(0, _dev(bb), z, r)
             torch.cuda.synchronize()
+    # FGMRES replays one graph per basis slot: the first graph solve captures them, the
+    # second replays them, the transposed solve has its own; all equal the eager solves
     b = _dev(fh.b[0])
+    for solve in (H.fgmres, H.fgmres_transposed):
+        outs = []
+        for g in (False, True, True):
+            H.set_graphs(g)
+            x = _dev(np.zeros(n))
+            it, rr, conv = solve(b, x, rtol=1e-8)
+            outs.append((it, _host(x)))
+        for o in outs[1:]:
+            assert o[0] == outs[0][0] and np.array_equal(o[1], outs[0][1])
+    # after a precision change the slot graphs are captured again
+    H.set_precision(0, "f32")
+    H.setup()
     outs = []
     for g in (False, True):
         H.set_graphs(g)

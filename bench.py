@@ -199,7 +199,8 @@ def batched_leg(nrhs: int = 16) -> dict:
                      "converged": bool(conv), "true_relres_max": _fmt(true_rel),
                      "block_apply_ms": _fmt(avg), "block_apply_gbps": _fmt(byt / (avg * 1e-3) / 1e9),
                      "block_apply_bytes": byt, "spmm_ms": _fmt(ms_sp / max(c_sp, 1)),
-                     "block_scatter_ms": _fmt(ms_sc / max(c_sc, 1))}
+                     "block_scatter_ms": _fmt(ms_sc / max(c_sc, 1)),
+                     "block_variant": H.level_info(0)["block_variant"]}
     for l in range(nl - 1):
         H.set_precision(l, "f64")
     H.setup()

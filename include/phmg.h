@@ -267,7 +267,10 @@ phmg_status phmg_residual(phmg_ctx ctx, int level, const double* b, const double
  * kernel shape chosen by the set-up autotuner, the number of shapes
  * compiled for the level's precision and layout, whether the stored inverses
  * use the symmetric layout (after set-up), the SpMV kernel variant of K_l
- * (see phmg_set_spmv_variant) and the stored element count. */
+ * (see phmg_set_spmv_variant), the stored element count, and the kernel shape
+ * of the multi-right-hand-side patch solve with the number of such shapes for
+ * the level's precision (block_variant is -1 until the first batched call
+ * after a precision or layout change has tuned it). */
 typedef struct {
     int32_t n, npatch, max_m, precision;
     int64_t nnz, sum_m, sum_m2;
@@ -275,6 +278,7 @@ typedef struct {
     int32_t apply_variant, apply_variants;
     int32_t symmetric_storage, spmv_variant;
     int64_t stored_elements;
+    int32_t block_variant, block_variants;
 } phmg_level_info;
 phmg_status phmg_get_level_info(phmg_ctx ctx, int level, phmg_level_info* info);
 
@@ -283,6 +287,15 @@ phmg_status phmg_get_level_info(phmg_ctx ctx, int level, phmg_level_info* info);
  * precision and layout; kept until either changes).  Every shape computes the
  * same result bit for bit; this exists for tests and tuning studies. */
 phmg_status phmg_set_apply_variant(phmg_ctx ctx, int level, int variant);
+
+/* Override the autotuner's kernel shape of the multi-right-hand-side patch
+ * solve (the batched relaxation, V-cycle and FGMRES) of one level: 0 <=
+ * variant < block_variants of phmg_level_info.  Call it after the set-up that
+ * fixes the level's layout; kept until the level's precision or layout
+ * changes.  Shapes differ in how rows and columns are dealt to lanes, not in
+ * the order of any sum: results are bit-identical.  For tests and tuning
+ * studies. */
+phmg_status phmg_set_block_variant(phmg_ctx ctx, int level, int variant);
 
 /* Override the autotuner's SpMV kernel of one matrix (matrix 0: K_level, 1:
  * P_level, 2: R_level = P_level^T; the coarsest level has only K), or (matrix

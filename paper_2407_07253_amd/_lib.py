@@ -63,7 +63,8 @@ class LevelInfoT(C.Structure):
     _fields_ = [("n", C.c_int32), ("npatch", C.c_int32), ("max_m", C.c_int32), ("precision", C.c_int32),
                 ("nnz", C.c_int64), ("sum_m", C.c_int64), ("sum_m2", C.c_int64), ("lambda_max", C.c_double),
                 ("apply_variant", C.c_int32), ("apply_variants", C.c_int32),
-                ("symmetric_storage", C.c_int32), ("spmv_variant", C.c_int32), ("stored_elements", C.c_int64)]
+                ("symmetric_storage", C.c_int32), ("spmv_variant", C.c_int32), ("stored_elements", C.c_int64),
+                ("block_variant", C.c_int32), ("block_variants", C.c_int32)]
 
 
 def _sig(name, res, args):
@@ -112,6 +113,7 @@ _fbf_destroy = _sig("phmg_fbf_destroy", C.c_int, [C.c_void_p])
 _set_variant = _sig("phmg_set_apply_variant", C.c_int, [C.c_void_p, C.c_int, C.c_int])
 _set_storage = _sig("phmg_set_patch_storage", C.c_int, [C.c_void_p, C.c_int, C.c_int])
 _set_spmv = _sig("phmg_set_spmv_variant", C.c_int, [C.c_void_p, C.c_int, C.c_int, C.c_int])
+_set_block = _sig("phmg_set_block_variant", C.c_int, [C.c_void_p, C.c_int, C.c_int])
 SPMV_VARIANTS = 17
 STORAGE = {"auto": 0, "general": 1}
 MAX_RHS = 16
@@ -123,7 +125,7 @@ EXPORTED = ["phmg_hierarchy_create", "phmg_hierarchy_destroy", "phmg_relax_setup
             "phmg_relax_apply_transposed", "phmg_vcycle_transposed", "phmg_fgmres_solve_transposed",
             "phmg_set_sensitivities", "phmg_forcing_rhs", "phmg_gradients",
             "phmg_fbf_create", "phmg_fbf_apply", "phmg_fbf_fgmres_solve", "phmg_fbf_destroy",
-            "phmg_set_apply_variant", "phmg_set_patch_storage", "phmg_set_spmv_variant",
+            "phmg_set_apply_variant", "phmg_set_patch_storage", "phmg_set_spmv_variant", "phmg_set_block_variant",
             "phmg_vcycle_batched_transposed", "phmg_fgmres_solve_batched_transposed",
             "phmg_last_error"]
 
@@ -234,6 +236,10 @@ class Hierarchy:
     def set_apply_variant(self, level: int, variant: int):
         """Override the autotuned patch-solve kernel shape of a level (results are identical)."""
         _check(_set_variant(self._h, level, variant))
+
+    def set_block_variant(self, level: int, variant: int):
+        """Override the autotuned multi-right-hand-side patch-solve shape of a level (identical results)."""
+        _check(_set_block(self._h, level, variant))
 
     # -- adjoint gradients
     def set_sensitivities(self, S, G):
@@ -379,7 +385,8 @@ class Hierarchy:
         return dict(n=i.n, npatch=i.npatch, max_m=i.max_m, precision=i.precision, nnz=i.nnz, sum_m=i.sum_m,
                     sum_m2=i.sum_m2, lambda_max=i.lambda_max, apply_variant=i.apply_variant,
                     apply_variants=i.apply_variants, symmetric_storage=bool(i.symmetric_storage), spmv_variant=i.spmv_variant,
-                    stored_elements=i.stored_elements)
+                    stored_elements=i.stored_elements, block_variant=i.block_variant,
+                    block_variants=i.block_variants)
 
     def profile(self, kernels=("patch_apply",)):
         """Enable HIP-event timing of the named kernels (empty = off)."""

@@ -1680,6 +1680,9 @@ phmg_status phmg_get_level_info(phmg_ctx ctx, int level, phmg_level_info* info) 
         info->symmetric_storage = L.sym ? 1 : 0;
         info->spmv_variant = spmv_variant_of(L.K);
         info->stored_elements = L.npatch == 0 ? 0 : (L.sym ? L.sum_ls[L.prec] : L.sum_lp[L.prec]);
+        const bool btuned = L.npatch > 0 && L.block_tuned_for == L.prec + (L.sym ? 3 : 0);
+        info->block_variant = btuned ? L.block_variant : -1;
+        info->block_variants = L.npatch > 0 ? block_variant_count(L) : 0;
         return PHMG_OK;
     });
 }
@@ -1693,6 +1696,20 @@ phmg_status phmg_set_apply_variant(phmg_ctx ctx, int level, int variant) {
         L.apply_variant = variant;
         L.tuned_for = tune_key(L);
         invalidate_graph(ctx);
+        return PHMG_OK;
+    });
+}
+
+phmg_status phmg_set_block_variant(phmg_ctx ctx, int level, int variant) {
+    return guarded([&]() -> phmg_status {
+        if (!ctx) fail(PHMG_EINVAL, "null context");
+        if (level < 0 || level >= (int)ctx->L.size() - 1) fail(PHMG_EINVAL, "level out of range");
+        Level& L = ctx->L[level];
+        if (L.npatch == 0 || variant < 0 || variant >= block_variant_count(L))
+            fail(PHMG_EINVAL, "variant out of range");
+        L.block_variant = variant;
+        L.block_tuned_for = L.prec + (L.sym ? 3 : 0);
+        invalidate_block_graph(ctx);
         return PHMG_OK;
     });
 }

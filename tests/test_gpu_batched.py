@@ -255,3 +255,49 @@ def test_batched_reduced_precision_sweep_matches_single_path(prec, storage):
         print(f"{prec} ({storage}) level {l}: worst column ||batched - single|| / ||correction|| = {worst:.2e}")
         assert worst <= 1e-4
     H.close()
+
+
+@pytest.mark.parametrize("prec,storage", [("f64", "auto"), ("f64", "general"), ("f32", "auto"), ("bf16", "auto")])
+def test_block_variants_bit_identical(prec, storage):
+    """Every shape of the multi-right-hand-side patch solve deals rows and columns to lanes
+    differently but sums each product in the same order: one sweep with each shape forced
+    must give the same bits.  cfg2_r1 level 0 has patches of 64-210 DoFs, so the row groups
+    of every shape (16 to 128 rows per pass) end in ragged tails; FP64 shape 0 is also checked
+    against the oracle."""
+    from paper_2407_07253_amd._lib import Hierarchy, PhmgError
+    fh = frontend.build_hierarchy("cfg2_r1")
+    H = Hierarchy.from_frontend(fh)
+    nl = len(fh.levels)
+    for l in range(nl - 1):
+        H.set_precision(l, prec)
+        H.set_patch_storage(l, storage)
+    H.setup()
+    rng = np.random.default_rng(91)
+    nrhs = 5
+    if prec == "f64":
+        ol, od, oopts, ob = oproblems.build("cfg2_r1", forcing="mms", nrhs=1)
+        omg.setup(ol, oopts)
+    for l in range(nl - 1):
+        info = H.level_info(l)
+        if info["npatch"] == 0:
+            continue
+        nv = info["block_variants"]
+        assert nv >= 4
+        n = fh.levels[l].n
+        B, X = rng.standard_normal((nrhs, n)), rng.standard_normal((nrhs, n))
+        outs = []
+        for v in range(nv):
+            H.set_block_variant(l, v)
+            assert H.level_info(l)["block_variant"] == v
+            Xg = _dev(X)
+            H.relax_apply_batched(l, _dev(B), Xg, 1)
+            outs.append(_host(Xg))
+        for v in range(1, nv):
+            assert np.array_equal(outs[v], outs[0]), (l, v, float(np.abs(outs[v] - outs[0]).max()))
+        if prec == "f64":
+            worst = max(_rel(outs[0][c], omg._relax(ol[l], oopts, B[c], X[c], 1, False)) for c in range(nrhs))
+            print(f"{storage} level {l}: {nv} shapes identical, rel err vs oracle {worst:.2e}")
+            assert worst <= 1e-11, (l, worst)
+        with pytest.raises(PhmgError):
+            H.set_block_variant(l, nv)
+    H.close()

@@ -78,14 +78,17 @@ def sweep_bytes(info: dict, elem_bytes: int, felems: int) -> int:
     return spmv + apply_bytes(info, elem_bytes, felems) + scatter
 
 
-def traffic_entry(prec: str):
-    """Counter-measured HBM bytes per launch from the committed rocprofv3 summary, if the kernel source is unchanged."""
+def traffic_entry(prec: str, workload: str):
+    """Counter-measured HBM bytes per launch from the committed rocprofv3 summary, if it covers this
+    workload and the kernel source is unchanged."""
     if not os.path.exists(TRAFFIC_FILE):
         return None
     try:
         d = json.load(open(TRAFFIC_FILE))
         sha = hashlib.sha256(open(KERNEL_SOURCE, "rb").read()).hexdigest()
-        if d.get("kernel_source_sha256") != sha or prec not in d.get("per_launch_bytes", {}):
+        if d.get("workload") != workload or d.get("kernel_source_sha256") != sha:
+            return None
+        if prec not in d.get("per_launch_bytes", {}):
             return None
         return float(d["per_launch_bytes"][prec])
     except Exception:
@@ -398,7 +401,7 @@ def main() -> int:
         variants[prec] = [H.level_info(l)["apply_variant"] for l in range(nl - 1)]
     H.close()
 
-    traffic = traffic_entry("f64")
+    traffic = traffic_entry("f64", args.workload)
     result = {
         "metric": METRIC,
         "value": round(ap64["gbps"], 2),

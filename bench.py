@@ -246,7 +246,7 @@ def main() -> int:
         if p not in ("f32", "bf16"):
             ap.error(f"unknown precision {p!r} in --mixed")
     if args.gpus != 1:
-        print("bench.py: this build runs on one GPU only; --gpus must be 1 (multi-GPU sharding of the patch "
+        print("bench.py: runs on one GPU only; --gpus must be 1 (multi-GPU sharding of the patch "
               "relaxation is a design note, not implemented)", file=sys.stderr)
         return 2
 

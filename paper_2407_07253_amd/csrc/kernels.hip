@@ -999,6 +999,7 @@ __global__ __launch_bounds__(kBlock) void max_tol_kernel(const double* __restric
 // Richardson is a = omega, c = 0.
 __global__ __launch_bounds__(kBlock) void scatter_kernel(int32_t n, const int32_t* __restrict__ sptr,
                                                          const int32_t* __restrict__ sslot,
+                                                         const int4* __restrict__ sslot4,
                                                          const double* __restrict__ w, const double* __restrict__ wd,
                                                          const double* __restrict__ Y, double a, double c,
                                                          double* __restrict__ d, double* __restrict__ x, int flags) {
@@ -1006,14 +1007,15 @@ __global__ __launch_bounds__(kBlock) void scatter_kernel(int32_t n, const int32_
     if (j >= n) return;
     const double wj = wd ? wd[j] : 1.0;
     double s = 0.0;
-    const int end = sptr[j + 1];
-    // four slots in flight (indices first, then the gathers); the sum still
-    // runs over the slots in ascending order (a missing slot adds +0)
-    for (int t = sptr[j]; t < end; t += 4) {
-        int q[4];
+    // the first four slots come from the padded copy, loaded together with the
+    // slot range (no dependent index load); four slots in flight (indices
+    // first, then the gathers); the sum runs over the slots in ascending order
+    // (a missing slot adds +0)
+    const int4 h = sslot4[j];
+    const int beg = sptr[j], end = sptr[j + 1];
+    int q[4] = {h.x, h.y, h.z, h.w};
+    for (int t = beg;;) {
         double y[4], wq[4];
-#pragma unroll
-        for (int u = 0; u < 4; ++u) q[u] = t + u < end ? sslot[t + u] : -1;
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
             y[u] = q[u] >= 0 ? Y[q[u]] : 0.0;
@@ -1021,6 +1023,10 @@ __global__ __launch_bounds__(kBlock) void scatter_kernel(int32_t n, const int32_
         }
 #pragma unroll
         for (int u = 0; u < 4; ++u) s += w ? wq[u] * y[u] : y[u];
+        t += 4;
+        if (t >= end) break;
+#pragma unroll
+        for (int u = 0; u < 4; ++u) q[u] = t + u < end ? sslot[t + u] : -1;
     }
     if (wd) s *= wj;
     double dn = a * s;
@@ -1400,8 +1406,8 @@ void launch_scatter(hipStream_t s, const Level& L, double a, double c, double* d
     const int flags = (x_zero ? 1 : 0) | (c != 0.0 ? 2 : 0) | (store_d ? 4 : 0);
     const double* w = transpose || L.wdof ? nullptr : L.pweight;
     const double* wd = transpose ? nullptr : L.wdof;
-    hipLaunchKernelGGL(scatter_kernel, dim3(grid_for(L.n, kBlock)), dim3(kBlock), 0, s, L.n, L.sptr, L.sslot, w, wd,
-                       L.Y, a, c, d, x, flags);
+    hipLaunchKernelGGL(scatter_kernel, dim3(grid_for(L.n, kBlock)), dim3(kBlock), 0, s, L.n, L.sptr, L.sslot,
+                       reinterpret_cast<const int4*>(L.sslot4), w, wd, L.Y, a, c, d, x, flags);
 }
 
 void launch_power_start(hipStream_t s, int64_t n, double* v) {

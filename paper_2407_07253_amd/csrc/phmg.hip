@@ -1331,6 +1331,12 @@ phmg_status phmg_hierarchy_create(const phmg_hierarchy_desc* desc, const phmg_cy
                 L.order = upload(ctx, order.data(), pt.npatch);
                 L.sptr = upload(ctx, sptr.data(), L.n + 1);
                 L.sslot = upload(ctx, sslot.data(), L.sum_m);
+                {
+                    std::vector<int32_t> s4((size_t)L.n * 4, -1);
+                    for (int32_t j = 0; j < L.n; ++j)
+                        for (int32_t k = sptr[j], u = 0; k < sptr[j + 1] && u < 4; ++k, ++u) s4[(size_t)j * 4 + u] = sslot[k];
+                    L.sslot4 = upload(ctx, s4.data(), (int64_t)L.n * 4);
+                }
                 if (pt.weight) {
                     // weights that depend on the DoF alone (e.g. 1 / number of patches
                     // holding it): sum_i w_ij y_ij = w_j sum_i y_ij, one weight per DoF

@@ -94,6 +94,7 @@ struct Level {
     int32_t gj_small_max = 0;        // largest of the rest (inverted with the matrix in LDS)
     int32_t* sptr = nullptr;         // DoF -> slot map for the scatter (n + 1)
     int32_t* sslot = nullptr;        // sum_m slot indices, ascending patch id per DoF
+    int32_t* sslot4 = nullptr;       // n x 4: each DoF's first four slots (-1 padded), read without sptr
     double* wdof = nullptr;          // n: the partition weight of each DoF when all its slots share one
                                      // (the scatter then scales the sum once); null: per-slot weights
     double* Y = nullptr;             // sum_m staging of the patch solutions

@@ -167,6 +167,24 @@ phmg_status phmg_set_graphs(phmg_ctx ctx, int on);
 phmg_status phmg_fgmres_solve(phmg_ctx ctx, const double* b, double* x, double rtol, int restart, int maxit,
                               int* iters, double* relres);
 
+/* For callers that cannot allocate device memory while they run (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the sweeps of phmg_relax_apply, bit for bit, with the three work buffers of a
+ * sweep -- residual (n doubles), Chebyshev direction (n) and staged patch
+ * results (sum of the level's patch sizes) -- taken from one device array of
+ * PHMG_NOALLOC_MAX_DOUBLES doubles (32 MiB) that the library reserves at load
+ * time on every GPU it runs on, instead of from the context.  The call makes no
+ * device allocation and no timing event (per-kernel profiling does not see it).
+ * b and x are the caller's DEVICE pointers as in phmg_relax_apply; the call is
+ * asynchronous on the context stream.  Errors: PHMG_EINVAL when the level needs
+ * 2 n + sum m (each rounded up to 32 doubles) > PHMG_NOALLOC_MAX_DOUBLES, before
+ * any launch; PHMG_ESTATE before relax_setup of the level.  Every call on one
+ * GPU shares that GPU's array (no buffer needs to start at zero): calls that
+ * overlap in time on one GPU -- two streams, two threads, two contexts -- race
+ * and must be serialised by the caller. */
+#define PHMG_NOALLOC_MAX_DOUBLES (4 << 20)
+phmg_status phmg_relax_apply_noalloc(phmg_ctx ctx, int level, const double* b, double* x, int nu);
+
 /* Adjoint (transposed) operators, for gradients through a solve.  They reuse
  * the factors of relax_setup: with the stored B_i = (P_i K_i)^{-1},
  * K_i^{-T} = P_i^T B_i^T, so the transposed sweep gathers W_i r[S_i] in DoF

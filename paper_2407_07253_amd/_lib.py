@@ -79,6 +79,7 @@ _destroy = _sig("phmg_hierarchy_destroy", C.c_int, [C.c_void_p])
 _setup = _sig("phmg_relax_setup", C.c_int, [C.c_void_p, C.c_int])
 _set_prec = _sig("phmg_set_precision", C.c_int, [C.c_void_p, C.c_int, C.c_int])
 _apply = _sig("phmg_relax_apply", C.c_int, [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_int])
+_apply_na = _sig("phmg_relax_apply_noalloc", C.c_int, [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_int])
 _vcycle = _sig("phmg_vcycle", C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p])
 _fgmres = _sig("phmg_fgmres_solve", C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_double, C.c_int, C.c_int,
                                               C.POINTER(C.c_int), C.POINTER(C.c_double)])
@@ -127,7 +128,8 @@ EXPORTED = ["phmg_hierarchy_create", "phmg_hierarchy_destroy", "phmg_relax_setup
             "phmg_fbf_create", "phmg_fbf_apply", "phmg_fbf_fgmres_solve", "phmg_fbf_destroy",
             "phmg_set_apply_variant", "phmg_set_patch_storage", "phmg_set_spmv_variant", "phmg_set_block_variant",
             "phmg_vcycle_batched_transposed", "phmg_fgmres_solve_batched_transposed",
-            "phmg_last_error"]
+            "phmg_relax_apply_noalloc", "phmg_last_error"]
+NOALLOC_MAX_DOUBLES = 4 << 20
 
 
 def ritz_max_real(H: np.ndarray, k: int) -> float:
@@ -308,6 +310,11 @@ class Hierarchy:
     def relax_apply(self, level: int, b, x, nu: int = 1):
         n = self.n[level]
         _check(_apply(self._h, level, _vec_ptr(b, n, "b"), _vec_ptr(x, n, "x"), nu))
+
+    def relax_apply_noalloc(self, level: int, b, x, nu: int = 1):
+        """relax_apply with the sweep's work buffers in the library's fixed device array (no allocation)."""
+        n = self.n[level]
+        _check(_apply_na(self._h, level, _vec_ptr(b, n, "b"), _vec_ptr(x, n, "x"), nu))
 
     def vcycle(self, b, x):
         _check(_vcycle(self._h, _vec_ptr(b, self.n[0], "b"), _vec_ptr(x, self.n[0], "x")))

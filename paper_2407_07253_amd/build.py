@@ -13,7 +13,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libphmg.so")
-SOURCES = ["kernels.hip", "patch_apply.hip", "block_kernels.hip", "adjoint_kernels.hip", "phmg.hip", "block.hip"]
+SOURCES = ["kernels.hip", "patch_apply.hip", "block_kernels.hip", "adjoint_kernels.hip", "phmg.hip", "block.hip",
+           "noalloc.hip"]
 OBJDIR = os.path.join(HERE, "_build")
 
 HIPCC_FLAGS = [

@@ -1401,13 +1401,14 @@ void launch_convert_patches(hipStream_t s, const Level& L, const double* src, vo
 }
 
 void launch_scatter(hipStream_t s, const Level& L, double a, double c, double* d, bool store_d, double* x,
-                    bool x_zero, bool transpose) {
+                    bool x_zero, bool transpose, const double* Y) {
     if (L.n <= 0) return;
+    if (!Y) Y = L.Y;
     const int flags = (x_zero ? 1 : 0) | (c != 0.0 ? 2 : 0) | (store_d ? 4 : 0);
     const double* w = transpose || L.wdof ? nullptr : L.pweight;
     const double* wd = transpose ? nullptr : L.wdof;
     hipLaunchKernelGGL(scatter_kernel, dim3(grid_for(L.n, kBlock)), dim3(kBlock), 0, s, L.n, L.sptr, L.sslot,
-                       reinterpret_cast<const int4*>(L.sslot4), w, wd, L.Y, a, c, d, x, flags);
+                       reinterpret_cast<const int4*>(L.sslot4), w, wd, Y, a, c, d, x, flags);
 }
 
 void launch_power_start(hipStream_t s, int64_t n, double* v) {

@@ -153,24 +153,24 @@ __global__ __launch_bounds__(kBlock) void patch_apply_kernel(const int32_t* __re
 
 // Shapes the set-up autotuner chooses from: U loads in flight per thread.
 template <typename T, int U>
-void launch_shape(hipStream_t s, const Level& L, const double* r) {
+void launch_shape(hipStream_t s, const Level& L, const double* r, double* Y) {
     typedef typename Load16<T>::acc_t Acc;
     const int ldbuf = (L.max_m + 1) & ~1;
     const size_t lds = sizeof(Acc) * ((size_t)ldbuf + (size_t)kBlock * Load16<T>::V);
     if (streams_factors(L, L.sym))
         hipLaunchKernelGGL((patch_apply_kernel<T, U, true>), dim3(L.npatch), dim3(kBlock), lds, s, L.order, L.pptr,
-                           L.pdofs_perm, L.fofflp, (const T*)L.factors, r, L.Y, ldbuf);
+                           L.pdofs_perm, L.fofflp, (const T*)L.factors, r, Y, ldbuf);
     else
         hipLaunchKernelGGL((patch_apply_kernel<T, U, false>), dim3(L.npatch), dim3(kBlock), lds, s, L.order, L.pptr,
-                           L.pdofs_perm, L.fofflp, (const T*)L.factors, r, L.Y, ldbuf);
+                           L.pdofs_perm, L.fofflp, (const T*)L.factors, r, Y, ldbuf);
 }
 
 template <typename T>
-void launch_typed(hipStream_t s, const Level& L, const double* r) {
+void launch_typed(hipStream_t s, const Level& L, const double* r, double* Y) {
     switch (L.apply_variant) {
-        case 1: launch_shape<T, 2>(s, L, r); break;
-        case 2: launch_shape<T, 8>(s, L, r); break;
-        default: launch_shape<T, 4>(s, L, r);
+        case 1: launch_shape<T, 2>(s, L, r, Y); break;
+        case 2: launch_shape<T, 8>(s, L, r, Y); break;
+        default: launch_shape<T, 4>(s, L, r, Y);
     }
 }
 
@@ -339,26 +339,26 @@ __global__ __launch_bounds__(kBlock) void patch_apply_sym_kernel(const int32_t* 
 }
 
 template <typename T, bool PF, int NWV>
-void launch_sym_shape(hipStream_t s, const Level& L, const double* r, const double* gw) {
+void launch_sym_shape(hipStream_t s, const Level& L, const double* r, const double* gw, double* Y) {
     typedef typename Load16<T>::acc_t Acc;
     const int ldbuf = (L.max_m + 1) & ~1;
     const size_t lds = sizeof(Acc) * (size_t)ldbuf * (1 + kSymParts);
     if (streams_factors(L, L.sym))
         hipLaunchKernelGGL((patch_apply_sym_kernel<T, PF, NWV, true>), dim3(L.npatch), dim3(NWV * kWave), lds, s,
-                           L.order, L.pptr, L.pdofs, L.fofflp, (const T*)L.factors, r, gw, L.Y, ldbuf);
+                           L.order, L.pptr, L.pdofs, L.fofflp, (const T*)L.factors, r, gw, Y, ldbuf);
     else
         hipLaunchKernelGGL((patch_apply_sym_kernel<T, PF, NWV, false>), dim3(L.npatch), dim3(NWV * kWave), lds, s,
-                           L.order, L.pptr, L.pdofs, L.fofflp, (const T*)L.factors, r, gw, L.Y, ldbuf);
+                           L.order, L.pptr, L.pdofs, L.fofflp, (const T*)L.factors, r, gw, Y, ldbuf);
 }
 
 // shapes: 0 / 1 four waves without / with prefetch, 2 / 3 one wave without / with prefetch
 template <typename T>
-void launch_sym_typed(hipStream_t s, const Level& L, const double* r, const double* gw) {
+void launch_sym_typed(hipStream_t s, const Level& L, const double* r, const double* gw, double* Y) {
     switch (L.apply_variant) {
-        case 1: launch_sym_shape<T, true, 4>(s, L, r, gw); break;
-        case 2: launch_sym_shape<T, false, 1>(s, L, r, gw); break;
-        case 3: launch_sym_shape<T, true, 1>(s, L, r, gw); break;
-        default: launch_sym_shape<T, false, 4>(s, L, r, gw);
+        case 1: launch_sym_shape<T, true, 4>(s, L, r, gw, Y); break;
+        case 2: launch_sym_shape<T, false, 1>(s, L, r, gw, Y); break;
+        case 3: launch_sym_shape<T, true, 1>(s, L, r, gw, Y); break;
+        default: launch_sym_shape<T, false, 4>(s, L, r, gw, Y);
     }
 }
 
@@ -366,22 +366,24 @@ void launch_sym_typed(hipStream_t s, const Level& L, const double* r, const doub
 
 int apply_variant_count(const Level& L) { return L.sym ? 4 : 3; }
 
-void launch_patch_apply_sym(hipStream_t s, const Level& L, const double* r, const double* gw) {
+void launch_patch_apply_sym(hipStream_t s, const Level& L, const double* r, const double* gw, double* Y) {
     if (L.npatch <= 0) return;
-    if (L.prec == PHMG_PREC_F32) launch_sym_typed<float>(s, L, r, gw);
-    else if (L.prec == PHMG_PREC_BF16) launch_sym_typed<__hip_bfloat16>(s, L, r, gw);
-    else launch_sym_typed<double>(s, L, r, gw);
+    if (!Y) Y = L.Y;
+    if (L.prec == PHMG_PREC_F32) launch_sym_typed<float>(s, L, r, gw, Y);
+    else if (L.prec == PHMG_PREC_BF16) launch_sym_typed<__hip_bfloat16>(s, L, r, gw, Y);
+    else launch_sym_typed<double>(s, L, r, gw, Y);
 }
 
-void launch_patch_apply(hipStream_t s, const Level& L, const double* r) {
+void launch_patch_apply(hipStream_t s, const Level& L, const double* r, double* Y) {
     if (L.npatch <= 0) return;
+    if (!Y) Y = L.Y;
     if (L.sym) {
-        launch_patch_apply_sym(s, L, r, nullptr);
+        launch_patch_apply_sym(s, L, r, nullptr, Y);
         return;
     }
-    if (L.prec == PHMG_PREC_F32) launch_typed<float>(s, L, r);
-    else if (L.prec == PHMG_PREC_BF16) launch_typed<__hip_bfloat16>(s, L, r);
-    else launch_typed<double>(s, L, r);
+    if (L.prec == PHMG_PREC_F32) launch_typed<float>(s, L, r, Y);
+    else if (L.prec == PHMG_PREC_BF16) launch_typed<__hip_bfloat16>(s, L, r, Y);
+    else launch_typed<double>(s, L, r, Y);
 }
 
 }  // namespace phmg

@@ -202,19 +202,32 @@ HostCsr host_product(const HostCsr& A, const phmg_csr& B) {
 // relaxation, cycle
 // ----------------------------------------------------------------------------
 
+}  // namespace
+
 // nu smoothing steps on level l (eq. "eq:ASM"): damped Richardson, or the
 // Chebyshev acceleration of the additive Schwarz operator used in the paper's
 // experiments.  With x_zero the incoming x is ignored (treated as 0) and the
 // first residual is b itself.  With transpose the sweep is the adjoint one:
 // K^T and M^T = sum_i R_i^T K_i^{-T} W_i R_i (the same Chebyshev interval:
-// M^T K^T has the spectrum of M K).
-void relax(phmg_ctx ctx, int l, const double* b, double* x, int nu, bool x_zero, bool transpose = false) {
+// M^T K^T has the spectrum of M K).  r (n), d (n) and Y (sum m) are the work
+// buffers of the sweep: the residual, the Chebyshev direction and the staged
+// patch results (each is written before it is read); profile = false records
+// no timing events.
+void phmg::relax_level(phmg_ctx ctx, int l, const double* b, double* x, int nu, bool x_zero, bool transpose,
+                       double* rbuf, double* dbuf, double* Y, bool profile) {
     Level& L = ctx->L[l];
     hipStream_t s = ctx->stream;
     if (nu == 0) {
         if (x_zero) launch_fill(s, L.n, x, 0.0);
         return;
     }
+    const unsigned saved_mask = ctx->prof.mask;
+    if (!profile) ctx->prof.mask = 0;
+    struct Restore {
+        phmg_ctx c;
+        unsigned m;
+        ~Restore() { c->prof.mask = m; }
+    } restore{ctx, saved_mask};
     const bool cheb = ctx->opts.smoother == PHMG_SMOOTHER_CHEBYSHEV;
     double theta = 0.0, delta = 0.0, sigma = 0.0, rho_prev = 0.0;
     if (cheb) {
@@ -228,26 +241,33 @@ void relax(phmg_ctx ctx, int l, const double* b, double* x, int nu, bool x_zero,
         const double* r = b;                         // x = 0: the residual is b itself
         if (!(it == 0 && x_zero)) {
             Timed t(ctx, PHMG_K_SPMV, l);
-            launch_spmv(s, transpose ? L.KT : L.K, x, -1.0, b, 1.0, L.r);
-            r = L.r;
+            launch_spmv(s, transpose ? L.KT : L.K, x, -1.0, b, 1.0, rbuf);
+            r = rbuf;
         }
         {
             Timed t(ctx, PHMG_K_PATCH_APPLY, l);
             if (transpose) launch_patch_apply_t(s, L, r);
-            else launch_patch_apply(s, L, r);
+            else launch_patch_apply(s, L, r, Y);
         }
         Timed t(ctx, PHMG_K_SCATTER, l);
         const bool xz = it == 0 && x_zero;
         if (!cheb) {
-            launch_scatter(s, L, ctx->opts.omega, 0.0, nullptr, false, x, xz, transpose);
+            launch_scatter(s, L, ctx->opts.omega, 0.0, nullptr, false, x, xz, transpose, Y);
         } else if (it == 0) {
-            launch_scatter(s, L, 1.0 / theta, 0.0, L.d, nu > 1, x, xz, transpose);
+            launch_scatter(s, L, 1.0 / theta, 0.0, dbuf, nu > 1, x, xz, transpose, Y);
         } else {
             const double rho = 1.0 / (2.0 * sigma - rho_prev);
-            launch_scatter(s, L, 2.0 * rho / delta, rho * rho_prev, L.d, it + 1 < nu, x, false, transpose);
+            launch_scatter(s, L, 2.0 * rho / delta, rho * rho_prev, dbuf, it + 1 < nu, x, false, transpose, Y);
             rho_prev = rho;
         }
     }
+}
+
+namespace {
+
+void relax(phmg_ctx ctx, int l, const double* b, double* x, int nu, bool x_zero, bool transpose = false) {
+    Level& L = ctx->L[l];
+    relax_level(ctx, l, b, x, nu, x_zero, transpose, L.r, L.d, L.Y, true);
 }
 
 // Set-up autotuner of the patch-solve kernel shape: every compiled shape of the
@@ -1249,6 +1269,8 @@ phmg_status phmg_hierarchy_create(const phmg_hierarchy_desc* desc, const phmg_cy
 
         ctx = new phmg_ctx_s();
         ctx->stream = (hipStream_t)stream;
+        hipcheck(hipGetDevice(&ctx->device), "hipGetDevice");
+        noalloc_init_current_device();
         ctx->opts = *opts;
         ctx->L.resize(nl);
         for (int l = 0; l < nl; ++l) {

@@ -178,6 +178,7 @@ struct Profile {
 
 struct phmg_ctx_s {
     hipStream_t stream = nullptr;
+    int device = 0;                  // the HIP device current at create (owner of every buffer)
     std::vector<phmg::Level> L;
     phmg_cycle_opts opts{};
     std::vector<void*> allocs;
@@ -320,7 +321,8 @@ int gj_lds_max_m();   // largest patch the LDS-resident inversion takes
 void launch_convert_patches(hipStream_t s, const Level& L, const double* src, void* dst);
 // general layout (offsets off) from the f64 set-up buffer, whatever the level's stored layout
 void launch_convert_general(hipStream_t s, const Level& L, const double* src, void* dst, const int64_t* off);
-void launch_patch_apply(hipStream_t s, const Level& L, const double* r);
+// Y: where the patch results go (null: the level's own staging L.Y, sum_m doubles)
+void launch_patch_apply(hipStream_t s, const Level& L, const double* r, double* Y = nullptr);
 // adjoint patch solve y_i = K_i^{-T} W_i r[S_i] from the same stored inverses (adjoint_kernels.hip)
 // Patch inverses of more than kStreamBytes (in the given layout and the level's
 // precision) are read with non-temporal loads: a stream that size would only
@@ -335,12 +337,13 @@ inline bool streams_factors(const Level& L, bool sym_layout) {
 void launch_patch_apply_t(hipStream_t s, const Level& L, const double* r);
 int apply_variant_count(const Level& L);
 // symmetric layout: y_i = S_i (g_i * r[S_i]) with g_i = W_i (gw != null, the adjoint sweep) or I
-void launch_patch_apply_sym(hipStream_t s, const Level& L, const double* r, const double* gw);
+void launch_patch_apply_sym(hipStream_t s, const Level& L, const double* r, const double* gw, double* Y = nullptr);
 // dn = a * sum_t w_t Y_t + c * d;  x = (x_zero ? 0 : x) + dn;  d = dn if store_d
 // (c = 0: d is not read; d may be null when c = 0 and !store_d)
-// transpose: the adjoint sweep's scatter (weights W_i were applied at the gather)
+// transpose: the adjoint sweep's scatter (weights W_i were applied at the gather);
+// Y: the staged patch results (null: L.Y)
 void launch_scatter(hipStream_t s, const Level& L, double a, double c, double* d, bool store_d, double* x,
-                    bool x_zero, bool transpose = false);
+                    bool x_zero, bool transpose = false, const double* Y = nullptr);
 void launch_power_start(hipStream_t s, int64_t n, double* v);
 void launch_scale_by_devnorm(hipStream_t s, int64_t n, const double* src, const double* norm2, double* dst);
 void launch_coarse_build(hipStream_t s, const Level& L, double* dense);
@@ -369,6 +372,15 @@ void launch_gemv_add(hipStream_t s, int64_t n, int ncol, const double* Z, int64_
 void launch_scale_copy(hipStream_t s, int64_t n, const double* src, double denom, double* dst);  // dst = src / denom
 void launch_copy(hipStream_t s, int64_t n, const double* src, double* dst);
 void launch_axpby(hipStream_t s, int64_t n, double a, const double* x, double b, const double* y, double* z);
+
+// nu relaxation sweeps on level l with explicit work buffers (phmg.hip): r and d
+// of n doubles (residual, Chebyshev direction), Y of sum_m doubles (staged patch
+// results); every buffer is written before it is read.  profile = false records
+// no timing events even when profiling is enabled.
+void relax_level(phmg_ctx ctx, int l, const double* b, double* x, int nu, bool x_zero, bool transpose, double* r,
+                 double* d, double* Y, bool profile);
+// resolve the allocation-free entry point's device array on the current device (noalloc.hip)
+void noalloc_init_current_device();
 
 // drop the captured block V-cycle (block.hip); called whenever set-up changes
 void invalidate_block_graph(phmg_ctx ctx);

@@ -14,7 +14,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libphmg.so")
 SOURCES = ["kernels.hip", "patch_apply.hip", "block_kernels.hip", "adjoint_kernels.hip", "phmg.hip", "block.hip",
-           "noalloc.hip"]
+           "noalloc.hip", "patch_factor.hip"]
 OBJDIR = os.path.join(HERE, "_build")
 
 HIPCC_FLAGS = [
@@ -28,6 +28,12 @@ HIPCC_FLAGS = [
 ]
 
 
+# per-file flags: the register-resident patch inversion keeps its MFMA accumulators in
+# VGPRs (its elimination steps work on the same registers with ordinary VALU code, which
+# AGPR accumulators would have to copy back and forth)
+FILE_FLAGS = {"patch_factor.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form"]}
+
+
 def build_library(verbose: bool = False) -> str:
     """Compile every source to an object (in parallel), then link the shared library."""
     from concurrent.futures import ThreadPoolExecutor
@@ -38,7 +44,7 @@ def build_library(verbose: bool = False) -> str:
 
     def compile_one(src):
         obj = os.path.join(OBJDIR, os.path.splitext(src)[0] + ".o")
-        cmd = [hipcc, *HIPCC_FLAGS, *inc, "-c", "-o", obj, os.path.join(CSRC, src)]
+        cmd = [hipcc, *HIPCC_FLAGS, *FILE_FLAGS.get(src, []), *inc, "-c", "-o", obj, os.path.join(CSRC, src)]
         if verbose:
             print(" ".join(cmd), flush=True)
         res = subprocess.run(cmd, capture_output=True, text=True)

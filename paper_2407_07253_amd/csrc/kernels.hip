@@ -1329,32 +1329,39 @@ int gj_lds_max_m() { return kGjLdsMax; }
 
 void launch_patch_factor(hipStream_t s, const Level& L, double* A) {
     if (L.npatch <= 0) return;
-    // patches too large for the LDS (first in the launch order): panels in LDS,
-    // the matrix in global memory
-    if (L.gj_big > 0) {
-        const int ldq = L.max_m;
+    static_assert(kGjLdsMax == 64, "size classes of gj_class");
+    // patches too large for the registers (first in the launch order): panels in
+    // LDS, the matrix in global memory
+    if (L.gj_cnt[0] > 0) {
+        const int ldq = L.gj_max[0];
         const size_t lds = sizeof(double) * (size_t)ldq * kPanel + sizeof(int) * 2 * (size_t)ldq;
-        const int R = (L.max_m + kBlock - 1) / kBlock;
+        const int R = (ldq + kBlock - 1) / kBlock;
         auto go = [&](auto kernel) {
             if (lds > 64 * 1024)
                 (void)hipFuncSetAttribute((const void*)kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-            hipLaunchKernelGGL(kernel, dim3(L.gj_big), dim3(kBlock), lds, s, L.pptr, L.foff, L.order, A, L.ptol,
+            hipLaunchKernelGGL(kernel, dim3(L.gj_cnt[0]), dim3(kBlock), lds, s, L.pptr, L.foff, L.order, A, L.ptol,
                                L.pdofs, L.pdofs_perm, L.pidx, ldq, L.status);
         };
         if (R <= 1) go(gj_kernel<1>);
         else if (R <= 2) go(gj_kernel<2>);
         else go(gj_kernel<4>);
     }
+    // 65..144 DoFs: the matrix in the registers of the workgroup
+    int first = L.gj_cnt[0];
+    for (int c = 1; c <= 2; ++c) {
+        launch_patch_factor_reg(s, L, A, first, L.gj_cnt[c], L.gj_max[c]);
+        first += L.gj_cnt[c];
+    }
     // the rest: the whole matrix in LDS
-    const int nsmall = L.npatch - L.gj_big;
+    const int nsmall = L.gj_cnt[3];
     if (nsmall <= 0) return;
-    const int ldq = L.gj_small_max;
+    const int ldq = L.gj_max[3];
     const size_t lds = sizeof(double) * (size_t)ldq * ldq + sizeof(int) * 2 * (size_t)ldq;
     const int RW = (ldq + kWave - 1) / kWave;
     auto go = [&](auto kernel) {
         if (lds > 64 * 1024)
             (void)hipFuncSetAttribute((const void*)kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-        hipLaunchKernelGGL(kernel, dim3(nsmall), dim3(kBlock), lds, s, L.pptr, L.foff, L.order + L.gj_big, A,
+        hipLaunchKernelGGL(kernel, dim3(nsmall), dim3(kBlock), lds, s, L.pptr, L.foff, L.order + first, A,
                            L.ptol, L.pdofs, L.pdofs_perm, L.pidx, ldq, L.status);
     };
     static_assert(kGjLdsMax <= kWave, "one row per lane");

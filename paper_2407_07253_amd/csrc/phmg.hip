@@ -1326,9 +1326,13 @@ phmg_status phmg_hierarchy_create(const phmg_hierarchy_desc* desc, const phmg_cy
                 std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) {
                     return pt.ptr[a + 1] - pt.ptr[a] > pt.ptr[b + 1] - pt.ptr[b];
                 });
-                // levels whose patches all fit the LDS-resident inversion use it
-                L.gj_big = mx > gj_lds_max_m() ? pt.npatch : 0;
-                L.gj_small_max = mx > gj_lds_max_m() ? 0 : mx;
+                // inversion kernel classes: consecutive ranges of the launch order (decreasing m)
+                for (int32_t i = 0; i < pt.npatch; ++i) {
+                    const int64_t m = pt.ptr[order[i] + 1] - pt.ptr[order[i]];
+                    const int c = gj_class(m, mx);
+                    L.gj_cnt[c]++;
+                    L.gj_max[c] = std::max<int32_t>(L.gj_max[c], (int32_t)m);
+                }
                 // DoF -> slots, ascending slot (= ascending patch id) per DoF
                 std::vector<int32_t> sptr(L.n + 1, 0), sslot(L.sum_m);
                 for (int64_t t = 0; t < L.sum_m; ++t) sptr[pt.dofs[t] + 1]++;

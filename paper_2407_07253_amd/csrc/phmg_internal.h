@@ -90,8 +90,12 @@ struct Level {
     int storage = PHMG_STORAGE_AUTO; // requested layout of the stored inverses
     bool sym = false;                // the stored inverses use the symmetric strip layout
     int32_t* order = nullptr;        // launch order: patches by decreasing size
-    int32_t gj_big = 0;              // leading patches of the launch order inverted with the matrix in global memory
-    int32_t gj_small_max = 0;        // largest of the rest (inverted with the matrix in LDS)
+    // patch inversion kernels by size class, over consecutive ranges of the launch order:
+    // gj_cnt[0] patches inverted with the matrix in global memory (more than 144 DoFs, and on
+    // a level that has such patches every patch of more than 64), gj_cnt[1..2] of 97-144 and
+    // 65-96 DoFs (matrix in registers), gj_cnt[3] of at most 64 (in LDS)
+    int32_t gj_cnt[4] = {0, 0, 0, 0};
+    int32_t gj_max[4] = {0, 0, 0, 0};      // largest patch of each class
     int32_t* sptr = nullptr;         // DoF -> slot map for the scatter (n + 1)
     int32_t* sslot = nullptr;        // sum_m slot indices, ascending patch id per DoF
     int32_t* sslot4 = nullptr;       // n x 4: each DoF's first four slots (-1 padded), read without sptr
@@ -318,6 +322,18 @@ void launch_extract(hipStream_t s, const Level& L, double* out);
 // invert every patch matrix of the level in place (stored as (P K_i)^{-1}, see kernels.hip)
 void launch_patch_factor(hipStream_t s, const Level& L, double* A);
 int gj_lds_max_m();   // largest patch the LDS-resident inversion takes
+int gj_reg_max_m();   // largest patch the register-resident inversion takes (patch_factor.hip)
+// register-resident inversion of the launch-order range [first, first + count), patches of at most max_m DoFs
+void launch_patch_factor_reg(hipStream_t s, const Level& L, double* A, int first, int count, int max_m);
+// size class of a patch for the inversion kernels (index into Level::gj_cnt) on a level
+// whose largest patch has max_m DoFs.  The size classes run one after another: on a level
+// with a few patches too large for the registers, their serial elimination chains would
+// add to the register kernel's time, so such a level inverts every patch above 64 DoFs
+// with the global-memory kernel, whose many resident workgroups hide the chains.
+inline int gj_class(int64_t m, int64_t max_m) {
+    if (m > 144 || (m > 64 && max_m > 144)) return 0;
+    return m > 96 ? 1 : (m > 64 ? 2 : 3);
+}
 void launch_convert_patches(hipStream_t s, const Level& L, const double* src, void* dst);
 // general layout (offsets off) from the f64 set-up buffer, whatever the level's stored layout
 void launch_convert_general(hipStream_t s, const Level& L, const double* src, void* dst, const int64_t* off);

@@ -24,16 +24,18 @@ _CACHE = {}
 
 
 def _pair(name, nrhs, storage="auto"):
+    """name 'cfg3_r1:k3': the workload with velocity order 3 (Taylor-Hood P3/P2)."""
     key = (name, nrhs, storage)
     if key not in _CACHE:
         from paper_2407_07253_amd._lib import Hierarchy
-        forcing = "bumps" if name.startswith("cfg3") else "mms"
-        fh = frontend.build_hierarchy(name, forcing=forcing, nrhs=nrhs)
+        base, k = (name.split(":k")[0], int(name.split(":k")[1])) if ":k" in name else (name, None)
+        forcing = "bumps" if base.startswith("cfg3") else "mms"
+        fh = frontend.build_hierarchy(base, k=k, forcing=forcing, nrhs=nrhs)
         H = Hierarchy.from_frontend(fh)
         for l in range(len(fh.levels) - 1):
             H.set_patch_storage(l, storage)
         H.setup()
-        ol, od, oopts, ob = oproblems.build(name, forcing=forcing, nrhs=nrhs)
+        ol, od, oopts, ob = oproblems.build(base, k=k, forcing=forcing, nrhs=nrhs)
         omg.setup(ol, oopts)
         _CACHE[key] = (fh, H, ol, od, oopts, ob)
     return _CACHE[key]
@@ -59,7 +61,7 @@ def _normalise(x, nfu):
 
 
 @pytest.mark.parametrize("storage", ["auto", "general"])
-@pytest.mark.parametrize("name,nrhs", [("cfg1", 3), ("cfg3_r1", 16), ("sv_small", 5)])
+@pytest.mark.parametrize("name,nrhs", [("cfg1", 3), ("cfg3_r1", 16), ("sv_small", 5), ("cfg3_r1:k3", 16)])
 @pytest.mark.parametrize("nu", [1, 2])
 def test_batched_relax_matches_oracle(name, nrhs, nu, storage):
     fh, H, ol, od, oopts, ob = _pair(name, 1, storage)
@@ -91,10 +93,11 @@ def test_batched_vcycle_matches_oracle(name, nrhs):
     assert worst <= 1e-11
 
 
-def test_batched_fgmres_matches_oracle_per_column():
-    """cfg3_r1 (16x16 TH P4/P3, bump forcings): per-column iteration counts and solutions."""
+@pytest.mark.parametrize("name", ["cfg3_r1", "cfg3_r1:k3"])
+def test_batched_fgmres_matches_oracle_per_column(name):
+    """cfg3_r1 (16x16 TH P4/P3 and P3/P2, bump forcings): per-column iteration counts and solutions."""
     nrhs = 3
-    fh, H, ol, od, oopts, ob = _pair("cfg3_r1", nrhs)
+    fh, H, ol, od, oopts, ob = _pair(name, nrhs)
     X = _dev(np.zeros((nrhs, ol[0].n)))
     iters, relres, conv = H.fgmres_batched(_dev(fh.b), X, rtol=1e-8, restart=30, maxit=1000)
     got = _host(X)

@@ -109,19 +109,28 @@ typedef struct {
                                         the coarsest matrix is nonsingular                 */
 } phmg_hierarchy_desc;
 
-/* Validate and upload a hierarchy.  R_l = P_l^T is formed explicitly on the
- * host and uploaded; the DoF -> patch-slot map used by the deterministic
- * scatter is built here.  On success *out owns all device memory it uses. */
+/* Validate and upload a hierarchy: the level matrices K_l (Section 2, the
+ * saddle-point system of eq. "eq:saddle" on each level of Section 3.1-3.2), the
+ * Vanka-star patches (Section 3.4, figure "fig:patches") and the prolongations
+ * P_l (Section 3.1: interpolation between nested spaces; Section 3.2: between
+ * orders on one mesh).  R_l = P_l^T is formed explicitly on the host and
+ * uploaded; the DoF -> patch-slot map used by the deterministic scatter is built
+ * here.  Errors: PHMG_EINVAL for any malformed array (message names the level,
+ * patch or row), nothing uploaded; PHMG_ENOMEM.  On success *out owns all device
+ * memory it uses; the descriptor's host arrays may be freed on return. */
 phmg_status phmg_hierarchy_create(const phmg_hierarchy_desc* desc, const phmg_cycle_opts* opts,
                                   void* stream, phmg_ctx* out);
 
-/* Set-up of the relaxation on one level (level < 0: every level): patch
- * extraction K_i = K[S_i, S_i] and factorisation of every patch, and on the
- * coarsest level the factorisation of the (bordered) coarse matrix.  Patch
- * systems are inverted by Gauss-Jordan elimination with partial pivoting
- * (the same pivots as LU with partial pivoting) and the explicit inverse is
- * stored in the level's precision.  Returns PHMG_ESINGULAR naming the first
- * singular patch.  Synchronises the stream. */
+/* Set-up of the relaxation on one level (level < 0: every level), Section 3.4:
+ * patch extraction K_i = I_i K I_i^T (the patch submatrix of eq. "eq:ASM") and
+ * factorisation of every patch, and on the coarsest level the factorisation of
+ * the (bordered) coarse matrix (Section 4: direct solve on the coarsest grid).
+ * Patch systems are inverted by Gauss-Jordan elimination with partial pivoting
+ * (the same pivots as LU with partial pivoting, the paper's exact patch solves)
+ * and the explicit inverse is stored in the level's precision; with the
+ * Chebyshev smoother the eigenvalue estimate of M^{-1} K is formed here too.
+ * Returns PHMG_ESINGULAR naming the first singular patch (|pivot| <= 1e-14
+ * ||K_i||_inf) or the coarse matrix.  Synchronises the stream. */
 phmg_status phmg_relax_setup(phmg_ctx ctx, int level);
 
 /* Choose the storage precision of the patch inverses of one level (before
@@ -146,8 +155,11 @@ phmg_status phmg_set_patch_storage(phmg_ctx ctx, int level, phmg_storage storage
  * level `level` (eq. "eq:ASM").  level must not be the coarsest. */
 phmg_status phmg_relax_apply(phmg_ctx ctx, int level, const double* b, double* x, int nu);
 
-/* x <- B b: one preconditioner application (phMG or hMG cycle from x = 0) on
- * level 0.  The content of x on entry is ignored. */
+/* x <- B b: one preconditioner application on level 0 -- the hMG V-cycle of
+ * Section 3.1 (eq. "eq:TG-operator" applied recursively) or, with n_plevels > 0,
+ * the phMG defect-correction cycle of Section 3.2 (eq. "eq:DC-TG-operator"),
+ * started from x = 0.  The content of x on entry is ignored.  PHMG_ESTATE
+ * before relax_setup of every level.  Asynchronous. */
 phmg_status phmg_vcycle(phmg_ctx ctx, const double* b, double* x);
 
 /* Replay the preconditioner as a HIP graph (default on): the first
@@ -158,12 +170,16 @@ phmg_status phmg_vcycle(phmg_ctx ctx, const double* b, double* x);
  * while per-kernel profiling is enabled. */
 phmg_status phmg_set_graphs(phmg_ctx ctx, int on);
 
-/* Restarted FGMRES on level 0, right-preconditioned by phmg_vcycle, from the
- * initial guess in x.  Stops when the Givens residual estimate drops to
- * rtol * ||b - K x_0||_2, on an exact breakdown, or after maxit inner
- * iterations (then returns PHMG_ENOCONV with x = last iterate).  On return
- * *iters is the number of inner iterations and *relres the true residual
- * ||b - K x||_2 / ||b - K x_0||_2.  Synchronises the stream. */
+/* Restarted flexible GMRES (Section 4, solver paragraph: FGMRES with restart
+ * `restart`, the paper's 30) on level 0, right-preconditioned by phmg_vcycle,
+ * from the initial guess in x.  A cycle ends when the Givens residual estimate
+ * drops to rtol * ||b - K x_0||_2, on an exact breakdown, or after maxit inner
+ * iterations; the solve has converged when the true residual satisfies the same
+ * bound, else it restarts (PHMG_ENOCONV after maxit, with x = the last iterate).
+ * On return *iters is the number of inner iterations and *relres the true
+ * residual ||b - K x||_2 / ||b - K x_0||_2.  PHMG_EINVAL, with x unchanged, when
+ * b or x holds a NaN or Inf (found by the device norm of b - K x_0 before any
+ * iteration).  Synchronises the stream. */
 phmg_status phmg_fgmres_solve(phmg_ctx ctx, const double* b, double* x, double rtol, int restart, int maxit,
                               int* iters, double* relres);
 
@@ -278,6 +294,17 @@ phmg_status phmg_fgmres_solve_batched_transposed(phmg_ctx ctx, int nrhs, const d
                                                  int restart, int maxit, int32_t* iters, double* relres);
 
 /* Residual r = b - K_l x on a level (device pointers, asynchronous). */
+
+/* The pressure kernel (Section 2: with Dirichlet data on the whole boundary the
+ * pressure is determined up to a constant, p in L^2_0; K z = 0 for the constant
+ * pressure z = [0; 1_p]).  set_kernel_vector copies z (HOST, n_0 values, finite,
+ * not all zero; NULL removes it).  project_kernel maps every system x_c of X
+ * (DEVICE, nrhs x n_0 float64, systems one after another, 1 <= nrhs <= 16) to
+ * x_c - (z . x_c / z . z) z, the l2-orthogonal projection off span{z}: for
+ * z = [0; 1_p], the removal of the pressure mean.  Asynchronous; no device
+ * allocation.  PHMG_ESTATE without a kernel vector. */
+phmg_status phmg_set_kernel_vector(phmg_ctx ctx, const double* z);
+phmg_status phmg_project_kernel(phmg_ctx ctx, int nrhs, double* X);
 phmg_status phmg_residual(phmg_ctx ctx, int level, const double* b, const double* x, double* r);
 
 /* Per-level sizes: n, nnz(K), npatch, sum m, sum m^2, max m, the Chebyshev

@@ -84,6 +84,8 @@ _vcycle = _sig("phmg_vcycle", C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p])
 _fgmres = _sig("phmg_fgmres_solve", C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_double, C.c_int, C.c_int,
                                               C.POINTER(C.c_int), C.POINTER(C.c_double)])
 _residual = _sig("phmg_residual", C.c_int, [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p])
+_set_kernel = _sig("phmg_set_kernel_vector", C.c_int, [C.c_void_p, C.c_void_p])
+_project = _sig("phmg_project_kernel", C.c_int, [C.c_void_p, C.c_int, C.c_void_p])
 _info = _sig("phmg_get_level_info", C.c_int, [C.c_void_p, C.c_int, C.POINTER(LevelInfoT)])
 _prof_on = _sig("phmg_profile_enable", C.c_int, [C.c_void_p, C.c_uint])
 _prof_read = _sig("phmg_profile_read", C.c_int, [C.c_void_p, C.c_int, C.c_int, C.POINTER(C.c_double), C.POINTER(C.c_int64)])
@@ -128,7 +130,7 @@ EXPORTED = ["phmg_hierarchy_create", "phmg_hierarchy_destroy", "phmg_relax_setup
             "phmg_fbf_create", "phmg_fbf_apply", "phmg_fbf_fgmres_solve", "phmg_fbf_destroy",
             "phmg_set_apply_variant", "phmg_set_patch_storage", "phmg_set_spmv_variant", "phmg_set_block_variant",
             "phmg_vcycle_batched_transposed", "phmg_fgmres_solve_batched_transposed",
-            "phmg_relax_apply_noalloc", "phmg_last_error"]
+            "phmg_relax_apply_noalloc", "phmg_set_kernel_vector", "phmg_project_kernel", "phmg_last_error"]
 NOALLOC_MAX_DOUBLES = 4 << 20
 
 
@@ -231,6 +233,7 @@ class Hierarchy:
         opts = dict(fh.opts)
         opts.update(overrides)
         H = cls(K, P, pts, levels[-1].null_vector(), stream=stream, **opts)
+        H.set_kernel_vector(levels[0].null_vector())
         if levels[0].visc_sens is not None and levels[0].forcing_map is not None:
             H.set_sensitivities(levels[0].visc_sens, levels[0].forcing_map)
         return H
@@ -318,6 +321,18 @@ class Hierarchy:
 
     def vcycle(self, b, x):
         _check(_vcycle(self._h, _vec_ptr(b, self.n[0], "b"), _vec_ptr(x, self.n[0], "x")))
+
+    def set_kernel_vector(self, z: Optional[np.ndarray]):
+        """Kernel vector of K_0 (host array of n_0 values; None removes it)."""
+        zz = None if z is None else np.ascontiguousarray(z, dtype=np.float64)
+        if zz is not None and zz.shape != (self.n[0],):
+            raise ValueError(f"kernel vector must have {self.n[0]} entries")
+        _check(_set_kernel(self._h, _ptr(zz)))
+
+    def project_kernel(self, X):
+        """X[c] <- X[c] - (z . X[c] / z . z) z for every row of X (nrhs, n_0), in place on the device."""
+        px, k = _block_ptr(X, self.n[0], "X")
+        _check(_project(self._h, k, px))
 
     def residual(self, level: int, b, x, r):
         n = self.n[level]

@@ -15,8 +15,10 @@ both contracted on the GPU (phmg_gradients).
 
 The constant pressure spans the kernel of K when the whole boundary is
 Dirichlet: the forward output has its pressure mean removed (the l2
-projection off that kernel), and the backward applies the same projection
-to the incoming gradient, so the adjoint systems are consistent.
+projection off that kernel, phmg_project_kernel), and the backward applies
+the same projection to the incoming gradient, so the adjoint systems are
+consistent.  Every arithmetic step runs in the library; this module only
+marshals tensors.
 """
 from __future__ import annotations
 
@@ -75,9 +77,14 @@ class StokesProblem:
         return _StokesSolve.apply(f, log_visc, self)
 
 
-def _project_pressure(X, p0: int):
-    """Remove the mean of the pressure block (entries p0 ...) of every row."""
-    X[:, p0:] -= X[:, p0:].mean(dim=1, keepdim=True)
+def _project_pressure(H, X):
+    """X[c] <- X[c] minus its component along the constant pressure (phmg_project_kernel), in blocks
+    of at most MAX_RHS rows."""
+    for c0 in range(0, X.shape[0], MAX_RHS):
+        c1 = min(X.shape[0], c0 + MAX_RHS)
+        Xc = X[c0:c1].contiguous()
+        H.project_kernel(Xc)
+        X[c0:c1] = Xc
 
 
 def _autograd():
@@ -109,7 +116,7 @@ def _autograd():
             ctx.problem, ctx.H, ctx.p0 = problem, H, p0
             ctx.devices = (f.device, log_visc.device)
             ctx.save_for_backward(X.clone())
-            _project_pressure(X, p0)
+            _project_pressure(H, X)
             return X
 
         @staticmethod
@@ -117,7 +124,7 @@ def _autograd():
             (X,) = ctx.saved_tensors
             problem, H, p0 = ctx.problem, ctx.H, ctx.p0
             G = gX.detach().to(torch.float64).contiguous().clone()
-            _project_pressure(G, p0)
+            _project_pressure(H, G)
             Lam = torch.zeros_like(G)
             adj_iters = []
             infos = [H.level_info(l) for l in range(H.nlevels - 1)]

@@ -365,6 +365,10 @@ phmg_status fgmres_block(phmg_ctx ctx, int nrhs, const double* B, double* X, dou
     block_norms(ctx, r, beta.data());
     std::vector<int> iters(kBS, 0);
     std::vector<bool> done(kBS, true), conv(kBS, false);
+    for (int c = 0; c < nrhs; ++c)
+        if (!std::isfinite(beta[c]))
+            fail(PHMG_EINVAL, "system " + std::to_string(c) + ": b or the initial x holds a NaN or Inf "
+                              "(||b - K x_0|| is not finite)");
     for (int c = 0; c < nrhs; ++c) {
         r0[c] = beta[c];
         target[c] = rtol * r0[c];

@@ -1219,6 +1219,17 @@ __global__ __launch_bounds__(kBlock) void axpby_kernel(int64_t n, double a, cons
         z[i] = a * x[i] + b * y[i];
 }
 
+// X_c -= (dots[c] / zz) z for every system c (X: nrhs systems of length n, one after another)
+__global__ __launch_bounds__(kBlock) void project_off_kernel(int64_t n, int nrhs, double* __restrict__ X,
+                                                             const double* __restrict__ z,
+                                                             const double* __restrict__ dots, double zz) {
+    const int64_t total = n * nrhs;
+    for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < total; t += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t c = t / n, i = t - c * n;
+        X[t] -= (dots[c] / zz) * z[i];
+    }
+}
+
 __global__ __launch_bounds__(kBlock) void scale_copy_kernel(int64_t n, const double* __restrict__ s, double q,
                                                             double* __restrict__ d) {
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
@@ -1487,6 +1498,14 @@ void launch_multidot(hipStream_t s, int64_t n, int ncol, const double* V, int64_
                      double* partial, double* out) {
     hipLaunchKernelGGL(multidot_partial_kernel, dim3(kRedBlocks), dim3(kBlock), 0, s, n, ncol, V, ldv, w, partial);
     hipLaunchKernelGGL(reduce_cols_kernel, dim3(ncol), dim3(kBlock), 0, s, kRedBlocks, partial, out);
+}
+
+void launch_project_off(hipStream_t s, int64_t n, int nrhs, double* X, const double* z, double zz, double* partial,
+                        double* dots) {
+    if (n <= 0 || nrhs <= 0) return;
+    launch_multidot(s, n, nrhs, X, n, z, partial, dots);
+    hipLaunchKernelGGL(project_off_kernel, dim3(std::min(grid_for(n * nrhs, kBlock), 4096)), dim3(kBlock), 0, s, n,
+                       nrhs, X, z, dots, zz);
 }
 
 int gs_max_cols() { return kGsMax; }

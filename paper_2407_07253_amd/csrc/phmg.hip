@@ -1078,6 +1078,7 @@ phmg_status fgmres_core(hipStream_t s, Krylov& kr, int64_t n, MatVec matvec, Pre
 
     matvec(x, -1.0, b, 1.0, r);
     double beta = device_norm(s, kr, n, r);
+    if (!std::isfinite(beta)) fail(PHMG_EINVAL, "b or the initial x holds a NaN or Inf (||b - K x_0|| is not finite)");
     const double r0 = beta;
     const double target = rtol * r0;
     int iters = 0;
@@ -1682,6 +1683,44 @@ phmg_status phmg_fbf_destroy(phmg_fbf fbf) {
         if (e) (void)hipEventDestroy(e);
     delete fbf;
     return PHMG_OK;
+}
+
+phmg_status phmg_set_kernel_vector(phmg_ctx ctx, const double* z) {
+    return guarded([&]() -> phmg_status {
+        if (!ctx) fail(PHMG_EINVAL, "null context");
+        const int64_t n = ctx->L[0].n;
+        if (!z) {
+            dfree(ctx, ctx->z0);
+            ctx->z0 = nullptr;
+            ctx->z0z0 = 0.0;
+            return PHMG_OK;
+        }
+        double zz = 0.0;
+        for (int64_t i = 0; i < n; ++i) {
+            if (!std::isfinite(z[i])) fail(PHMG_EINVAL, "kernel vector holds a NaN or Inf");
+            zz += z[i] * z[i];
+        }
+        if (!(zz > 0.0)) fail(PHMG_EINVAL, "kernel vector is zero");
+        if (!ctx->z0) ctx->z0 = dalloc<double>(ctx, n);
+        if (!ctx->zpartial) {
+            ctx->zpartial = dalloc<double>(ctx, (int64_t)kRedBlocks * kBS);
+            ctx->zdots = dalloc<double>(ctx, kBS);
+        }
+        hipcheck(hipMemcpy(ctx->z0, z, sizeof(double) * (size_t)n, hipMemcpyHostToDevice), "hipMemcpy H2D");
+        ctx->z0z0 = zz;
+        return PHMG_OK;
+    });
+}
+
+phmg_status phmg_project_kernel(phmg_ctx ctx, int nrhs, double* X) {
+    return guarded([&]() -> phmg_status {
+        if (!ctx || !X) fail(PHMG_EINVAL, "null argument");
+        if (nrhs < 1 || nrhs > PHMG_MAX_RHS) fail(PHMG_EINVAL, "nrhs must be in [1, 16]");
+        if (!ctx->z0) fail(PHMG_ESTATE, "no kernel vector set (phmg_set_kernel_vector)");
+        launch_project_off(ctx->stream, ctx->L[0].n, nrhs, X, ctx->z0, ctx->z0z0, ctx->zpartial, ctx->zdots);
+        hipcheck(hipGetLastError(), "kernel launch");
+        return PHMG_OK;
+    });
 }
 
 phmg_status phmg_residual(phmg_ctx ctx, int level, const double* b, const double* x, double* r) {

@@ -212,6 +212,11 @@ struct phmg_ctx_s {
     int32_t* status_host = nullptr;
     double* gin = nullptr;
     double* gout = nullptr;
+    // kernel vector z of K_0 (set_kernel_vector) and the work space of its projection
+    double* z0 = nullptr;
+    double z0z0 = 0.0;
+    double* zpartial = nullptr;      // kRedBlocks x kBS
+    double* zdots = nullptr;         // kBS
     // adjoint gradients: dK/dtheta over K_0's nonzeros, the forcing map G and G^T
     bool have_sens = false;
     phmg::DevCsr S, G, GT;
@@ -384,6 +389,10 @@ void launch_gs_update(hipStream_t s, int64_t n, int ncol, const double* V, int64
                       double* partial, double* out, bool norm);
 int gs_max_cols();
 void launch_gemv_sub(hipStream_t s, int64_t n, int ncol, const double* V, int64_t ldv, const double* h, double* w);
+// X_c <- X_c - (z . X_c / zz) z for nrhs systems of length n (one after another); partial holds
+// kRedBlocks x nrhs doubles, dots nrhs
+void launch_project_off(hipStream_t s, int64_t n, int nrhs, double* X, const double* z, double zz, double* partial,
+                        double* dots);
 void launch_gemv_add(hipStream_t s, int64_t n, int ncol, const double* Z, int64_t ldz, const double* y, double* x);
 void launch_scale_copy(hipStream_t s, int64_t n, const double* src, double denom, double* dst);  // dst = src / denom
 void launch_copy(hipStream_t s, int64_t n, const double* src, double* dst);

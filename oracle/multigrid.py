@@ -63,7 +63,7 @@ class CycleOpts:
     smoother: str = "richardson"   # or "chebyshev"
     cheb_lo: float = 0.1     # Chebyshev interval [cheb_lo, cheb_hi] * lambda_max estimate
     cheb_hi: float = 1.1
-    eig_iters: int = 20      # power iterations for the lambda_max estimate
+    eig_iters: int = 20      # Arnoldi steps of the lambda_max estimate
 
 
 def setup(levels: List[Level], opts: Optional[CycleOpts] = None) -> None:

@@ -21,7 +21,8 @@ Workloads (synthetic stand-ins for the paper's cavity / step problems):
     twice -> TH P2/P1 on the Alfeld mesh -> TH P2/P1 on the 3 macro meshes.
   * cfg2, cfg3 and cfg4 name no smoother; they use the paper's: nu = 2 Chebyshev
     iterations over the basic additive Schwarz operator (W_i = I), interval
-    [0.1, 1.1] * lambda_max, lambda_max from 20 power iterations.
+    [0.1, 1.1] * lambda_max, lambda_max the largest real Ritz value of 20
+    Arnoldi steps on M^{-1} K.
 """
 from __future__ import annotations
 

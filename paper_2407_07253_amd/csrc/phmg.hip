@@ -1385,7 +1385,7 @@ phmg_status phmg_hierarchy_create(const phmg_hierarchy_desc* desc, const phmg_cy
         ctx->kry.partial = dalloc<double>(ctx, (int64_t)kRedBlocks * 4);
         ctx->kry.partial_cols = 4;
         ctx->scal = dalloc<double>(ctx, 8);
-        ctx->L[0].x = dalloc<double>(ctx, ctx->L[0].n);   // scratch for level-0 power iteration
+        ctx->L[0].x = dalloc<double>(ctx, ctx->L[0].n);   // level-0 work vector (level 0 has no cycle x)
         *out = ctx;
         return PHMG_OK;
     });

@@ -1,8 +1,11 @@
-"""Host logic of bench.py (no GPU): the counter-traffic lookup and the one-GPU guard."""
+"""Host logic of bench.py (no GPU): byte / flop counts, the counter-traffic lookup, the comparison
+with the oracle's stored solutions and the one-GPU guard."""
+import hashlib
 import json
 import os
 import sys
 
+import numpy as np
 import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
@@ -11,20 +14,47 @@ sys.path.insert(0, ROOT)
 import bench  # noqa: E402
 
 
-def test_traffic_only_for_the_profiled_workload_and_source():
-    d = json.load(open(bench.TRAFFIC_FILE))
-    got = bench.traffic_entry("f64", d["workload"])
-    assert got == float(d["per_launch_bytes"]["f64"])
-    # counters of one workload say nothing about another's launch
-    assert bench.traffic_entry("f64", "cfg4") is None
-    assert bench.traffic_entry("bf16", d["workload"]) is None
+def test_method_bytes_closed_forms():
+    m = np.array([3, 16, 141])
+    words_sym = 6 + 136 + 141 * 142 // 2
+    words_gen = 9 + 256 + 141 * 141
+    slots = 20 * m.sum() + 20 * 3
+    assert bench.method_apply_bytes(m, 8, True) == 8 * words_sym + slots
+    assert bench.method_apply_bytes(m, 8, False) == 8 * words_gen + slots
+    assert bench.method_apply_bytes(m, 2, True) == 2 * words_sym + slots
+    # the strip layout stores the full 16 x 16 diagonal blocks: 141 DoFs = 9 strips, the last of 13 rows
+    ns, h = 9, 141 - 8 * 16
+    assert bench.layout_apply_bytes(np.array([141]), 8, True) == 8 * (128 * (ns - 1) * ns + h * 141) + 20 * 141 + 20
+    assert bench.layout_apply_bytes(np.array([16]), 8, True) == 8 * 256 + 20 * 16 + 20
+    # block path: 16 systems share the factor words, each slot moves two 16-wide rows and an index
+    assert bench.method_block_bytes(np.array([10]), 8, False) == 8 * 100 + (4 + 256) * 10 + 20
 
 
-def test_traffic_dropped_when_the_kernel_source_changes(monkeypatch, tmp_path):
+def test_traffic_only_for_the_profiled_workload_and_source(monkeypatch, tmp_path):
+    sha = hashlib.sha256(open(bench.KERNEL_SOURCE, "rb").read()).hexdigest()
+    f = tmp_path / "traffic.json"
+    f.write_text(json.dumps({"kernel_source_sha256": sha, "per_launch_bytes": {"cfg3": {"f64": 123.0}}}))
+    monkeypatch.setattr(bench, "TRAFFIC_FILE", str(f))
+    assert bench.traffic_entry("cfg3", "f64") == 123.0
+    # counters of one workload or precision say nothing about another's launch
+    assert bench.traffic_entry("cfg4", "f64") is None
+    assert bench.traffic_entry("cfg3", "bf16") is None
+    # nor after the kernel source changed
     src = tmp_path / "patch_apply.hip"
     src.write_bytes(open(bench.KERNEL_SOURCE, "rb").read() + b"\n// edited\n")
     monkeypatch.setattr(bench, "KERNEL_SOURCE", str(src))
-    assert bench.traffic_entry("f64", "cfg2") is None
+    assert bench.traffic_entry("cfg3", "f64") is None
+
+
+def test_oracle_error_against_stored_columns():
+    """The comparison removes the pressure mean (the constant-pressure kernel) before sampling."""
+    y = np.array([1.0, -2.0, 0.5, 3.0, 0.25, -0.25])          # 2 x 2 velocity, 2 pressures with mean 0
+    g = {"nfu": 2, "idx": [0, 3, 5], "columns": [{"column": 0, "val": list(y[[0, 3, 5]])}]}
+    assert bench.oracle_error(y + np.array([0, 0, 0, 0, 7.0, 7.0]), g, 0) == 0.0
+    z = y.copy()
+    z[3] += 0.3
+    assert bench.oracle_error(z, g, 0) == pytest.approx(0.1)
+    assert bench.golden("cfg3_bumps")["columns"][0]["column"] == 0
 
 
 def test_more_than_one_gpu_is_refused(monkeypatch, capsys):

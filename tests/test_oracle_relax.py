@@ -89,3 +89,55 @@ def test_arnoldi_estimates_largest_eigenvalue():
     ev = np.linalg.eigvals(_dense_Minv(K, patches, None) @ K)
     lam = relax.estimate_lambda_max(d.K, patches, factors, None, 20)
     assert 0.995 * ev.real.max() <= lam <= 1.0001 * ev.real.max()
+
+
+def _arnoldi_case():
+    d = assemble_stokes(synth.refine_uniform(synth.delaunay_square(8, seed=3)), 2, "TH")
+    patches = vanka_star_patches(d)
+    factors = relax.setup_patches(d.K, patches)
+    A = _dense_Minv(d.K.toarray(), patches, None) @ d.K.toarray()
+    return d, patches, factors, A
+
+
+def test_arnoldi_basis_is_orthonormal_and_satisfies_the_arnoldi_relation():
+    """Classical Gram-Schmidt applied twice keeps the basis orthonormal to rounding over 60 steps,
+    where a single pass loses orthogonality to ~1e-6 on this operator (shown below with the same
+    start vector); M^{-1} K V_k = V_{k+1} H with H upper Hessenberg (a transposed or shifted index
+    in H fails it)."""
+    d, patches, factors, A = _arnoldi_case()
+    V, H, k = relax.arnoldi(d.K, patches, factors, None, 60)
+    assert k == 60
+    G = V.T @ V
+    assert np.abs(G - np.eye(k + 1)).max() <= 1e-13
+    assert np.abs(A @ V[:, :k] - V @ H).max() <= 1e-12 * np.abs(A).max()
+    assert np.allclose(np.tril(H, -2), 0.0)
+    # single-pass classical Gram-Schmidt on the same operator: orthogonality is lost
+    n = A.shape[0]
+    W = np.zeros((n, k + 1))
+    v = relax.power_start(n)
+    W[:, 0] = v / np.linalg.norm(v)
+    for j in range(k):
+        w = A @ W[:, j]
+        w = w - W[:, : j + 1] @ (W[:, : j + 1].T @ w)
+        W[:, j + 1] = w / np.linalg.norm(w)
+    assert np.abs(W.T @ W - np.eye(k + 1)).max() > 1e-8
+
+
+@pytest.mark.parametrize("k", [3, 6])
+def test_ritz_values_equal_brute_force_rayleigh_ritz(k):
+    """The Ritz values of k Arnoldi steps are the eigenvalues of Q^T A Q for an orthonormal basis Q of
+    the Krylov space span{v, A v, ..., A^{k-1} v}, built here explicitly and orthonormalised by
+    numpy's QR."""
+    d, patches, factors, A = _arnoldi_case()
+    V, H, kk = relax.arnoldi(d.K, patches, factors, None, k)
+    v = relax.power_start(A.shape[0])
+    Kr = np.empty((A.shape[0], k))
+    Kr[:, 0] = v / np.linalg.norm(v)
+    for j in range(1, k):
+        Kr[:, j] = A @ Kr[:, j - 1]
+        Kr[:, j] /= np.linalg.norm(Kr[:, j])
+    Q, _ = np.linalg.qr(Kr)
+    want = np.sort_complex(np.linalg.eigvals(Q.T @ A @ Q))
+    got = np.sort_complex(np.linalg.eigvals(H[:kk, :kk]))
+    assert np.abs(got - want).max() <= 1e-8 * np.abs(want).max()
+    assert relax.estimate_lambda_max(d.K, patches, factors, None, k) == pytest.approx(want.real.max(), rel=1e-8)

@@ -338,9 +338,10 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="cfg3", choices=sorted(WORKLOADS))
     ap.add_argument("--apply-reps", type=int, default=20)
-    ap.add_argument("--phase", default="all", choices=["all", "apply", "setup", "block"],
+    ap.add_argument("--phase", default="all", choices=["all", "apply", "setup", "block", "step"],
                     help="apply: only the repeated level-0 relaxation sweeps; setup: only the relaxation set-up, "
-                         "repeated; block: only the 16-system level-0 sweeps (for counter runs)")
+                         "repeated; block: only the 16-system level-0 sweeps; step: only the timed steps of the "
+                         "first precision of --prec (for profiler runs)")
     ap.add_argument("--prec", default="f64,f32,bf16", help="precisions of the apply / block phases")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extra", action="store_true", help="skip the P3/P2 and cfg2 legs")
@@ -429,6 +430,21 @@ def main() -> int:
 
     g_batch = golden("cfg3_bumps") if batched else golden(args.workload)
     legs = {}
+    if args.phase == "step":
+        set_precision(H, fh, precs[0])
+        H.setup()
+        for _ in range(args.warmup):
+            step()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            res = step()
+        torch.cuda.synchronize()
+        print(json.dumps({"phase": "step", "workload": args.workload, "prec": precs[0],
+                          "ms_per_step": _fmt((time.perf_counter() - t0) * 1e3 / max(args.steps, 1)),
+                          "iters": res[0]}), flush=True)
+        H.close()
+        return 0
     for prec in PRECS:
         set_precision(H, fh, prec)
         H.setup()

@@ -75,13 +75,27 @@ def method_apply_bytes(m, es: int, sym: bool) -> int:
 
 
 def layout_apply_bytes(m, es: int, sym: bool) -> int:
-    """Bytes the kernel's stored layout streams: general m^2 words; symmetric strips hold the strictly
-    lower part of each 16-row strip plus its full 16 x 16 diagonal block (128 (ns-1) ns + h m words)."""
+    """Bytes the kernel's stored layout streams: general m^2 words; symmetric strips of 16 rows hold the
+    strictly lower part of the strip (height padded to the 16-byte row group V = 16 / es) and the diagonal
+    block from row floor(c / G) G down in column c (G = V for float64 / float32, 16 for bfloat16)."""
+    import numpy as np
     if not sym:
         return method_apply_bytes(m, es, False)
+    V = 16 // es
+    G = V if V < 8 else 16
+    m = np.asarray(m, dtype=np.int64)
     ns = (m + 15) // 16
     h = m - (ns - 1) * 16
-    return es * int((128 * (ns - 1) * ns + h * m).sum()) + 20 * int(m.sum()) + 20 * len(m)
+    hp = (h + V - 1) // V * V
+
+    def diag(hh, hpp):                       # stored entries of a diagonal block of hh columns, height hpp
+        c = np.arange(16)
+        g = c // G * G
+        return np.where(c[None, :] < np.asarray(hh)[:, None], np.asarray(hpp)[:, None] - g[None, :], 0).sum(axis=1)
+
+    full = int(diag(np.array([16]), np.array([16]))[0])
+    words = 128 * (ns - 1) * (ns - 2) + full * (ns - 1) + 16 * hp * (ns - 1) + diag(h, hp)
+    return es * int(words.sum()) + 20 * int(m.sum()) + 20 * len(m)
 
 
 def method_block_bytes(m, es: int, sym: bool, nrhs: int = 16) -> int:

@@ -13,8 +13,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libphmg.so")
-SOURCES = ["kernels.hip", "patch_apply.hip", "block_kernels.hip", "adjoint_kernels.hip", "phmg.hip", "block.hip",
-           "noalloc.hip", "patch_factor.hip"]
+SOURCES = ["block_sym_f64.hip", "block_sym_f32.hip", "block_sym_bf16.hip", "kernels.hip", "patch_apply.hip",
+           "block_kernels.hip", "adjoint_kernels.hip", "phmg.hip", "block.hip", "noalloc.hip", "patch_factor.hip"]
 OBJDIR = os.path.join(HERE, "_build")
 
 HIPCC_FLAGS = [
@@ -50,7 +50,7 @@ def build_library(verbose: bool = False) -> str:
         res = subprocess.run(cmd, capture_output=True, text=True)
         return obj, res
 
-    with ThreadPoolExecutor(max_workers=min(4, len(SOURCES))) as pool:
+    with ThreadPoolExecutor(max_workers=min(max(2, os.cpu_count() or 1), 8, len(SOURCES))) as pool:
         results = list(pool.map(compile_one, SOURCES))
     for obj, res in results:
         if res.returncode != 0:

@@ -147,11 +147,12 @@ void tune_block(phmg_ctx ctx) {
 void prepare_block(phmg_ctx ctx) {
     require_ready(ctx);
     ensure_block(ctx);
-    // general copies of the symmetric levels' inverses, converted from the f64
-    // set-up buffer once per set-up
+    // general copies of the inverses of symmetric levels whose patches are too large
+    // for the symmetric-layout block solve, converted from the f64 set-up buffer once
+    // per set-up
     for (size_t l = 0; l + 1 < ctx->L.size(); ++l) {
         Level& L = ctx->L[l];
-        if (!L.sym || L.npatch == 0 || L.bconv_count == L.setup_count) continue;
+        if (!L.sym || L.npatch == 0 || block_sym_blocks(L) > 0 || L.bconv_count == L.setup_count) continue;
         const int V = factor_pad_of(L.prec);
         const size_t es = L.prec == PHMG_PREC_F64 ? 8 : (L.prec == PHMG_PREC_F32 ? 4 : 2);
         std::vector<int64_t> off(L.npatch);

@@ -23,13 +23,11 @@
 #include <climits>
 #include <cstdint>
 
+#include "mfma.h"
 #include "phmg_internal.h"
 
 namespace phmg {
 namespace {
-
-typedef double d4 __attribute__((ext_vector_type(4)));
-typedef float f4 __attribute__((ext_vector_type(4)));
 
 inline int grid_for(int64_t work, int per_block) {
     int64_t g = (work + per_block - 1) / per_block;
@@ -139,28 +137,6 @@ struct BlockLoad<__hip_bfloat16, 4> {
         a[2] = __uint_as_float(v.y << 16);
         a[3] = __uint_as_float(v.y & 0xffff0000u);
     }
-};
-
-// MFMA 16x16x4 step and the accumulator's element -> tile-row map.  Both
-// instructions give lane l the column l % 16; float64 stores rows
-// l/16 + 4e in element e, float32 rows 4 (l/16) + e.
-template <typename Acc>
-struct Mfma;
-template <>
-struct Mfma<double> {
-    typedef d4 acc_t;
-    __device__ static inline d4 step(double a, double b, d4 c) {
-        return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
-    }
-    __device__ static inline int row(int lane, int e) { return lane / 16 + 4 * e; }
-};
-template <>
-struct Mfma<float> {
-    typedef f4 acc_t;
-    __device__ static inline f4 step(float a, float b, f4 c) {
-        return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
-    }
-    __device__ static inline int row(int lane, int e) { return 4 * (lane / 16) + e; }
 };
 
 template <typename T, typename Acc, int V, int NT, int U, bool ST>
@@ -484,7 +460,14 @@ void launch_block_shape(hipStream_t s, const Level& L, const void* factors, cons
     hipLaunchKernelGGL(kernel, dim3(L.npatch), dim3(kBlock), lds, s, L.order, L.pptr, L.pdofs_perm, off,
                        (const T*)factors, X, L.Yb, gw, L.pidx);
 }
+
 }  // namespace
+
+int block_sym_blocks(const Level& L) {
+    if (!L.sym || L.npatch == 0) return 0;
+    const int64_t nb = (L.max_m + kStrip - 1) / kStrip;
+    return nb <= 4 ? 4 : (nb <= 9 ? 9 : (nb <= 14 ? 14 : 0));
+}
 
 int block_variant_count(const Level& /*L*/) { return 4; }
 
@@ -493,7 +476,13 @@ void launch_block_apply(hipStream_t s, const Level& L, const double* X, bool tra
     // adjoint sweep on a symmetric level: K_i^{-T} = K_i^{-1} up to the level's
     // rounding asymmetry, applied to the weighted gather
     const double* gw = transpose ? L.pweight : nullptr;
-    // symmetric levels keep a general copy for the block path (MFMA on full columns)
+    if (block_sym_blocks(L) > 0) {
+        if (L.prec == PHMG_PREC_F32) launch_block_sym_f32(s, L, X, gw);
+        else if (L.prec == PHMG_PREC_BF16) launch_block_sym_bf16(s, L, X, gw);
+        else launch_block_sym_f64(s, L, X, gw);
+        return;
+    }
+    // symmetric levels with patches above 14 strips keep a general copy for the block path
     const void* factors = L.sym ? L.bfactors : L.factors;
     const int64_t* off = L.sym ? L.bfoff : L.fofflp;
     const int v = L.block_variant;

@@ -210,8 +210,15 @@ __global__ __launch_bounds__(kBlock) void rowblock_spmv_kernel(const int32_t* __
 }
 
 // ---------------------------------------------------------------------------
-// Patch extraction: one workgroup per patch; column-major m x m output.
+// Patch extraction: one workgroup per patch; column-major m x m output.  The
+// patch rows are assembled kExtractRows at a time in an LDS tile (row a of the
+// patch matrix = row pdofs[a] of K restricted to the patch DoFs, positions
+// found by binary search in the sorted DoF list), and each tile is written out
+// column by column, kExtractRows consecutive entries of a column per store
+// run: every output byte is written once, with no separate zero fill.
 // ---------------------------------------------------------------------------
+constexpr int kExtractRows = 16;
+
 __global__ __launch_bounds__(kBlock) void extract_kernel(const int64_t* __restrict__ pptr,
                                                          const int32_t* __restrict__ pdofs,
                                                          const int64_t* __restrict__ foff,
@@ -219,36 +226,45 @@ __global__ __launch_bounds__(kBlock) void extract_kernel(const int64_t* __restri
                                                          const int32_t* __restrict__ col,
                                                          const double* __restrict__ val, double* __restrict__ out,
                                                          double* __restrict__ ptol) {
-    extern __shared__ int32_t s_dofs[];
+    extern __shared__ double s_tile[];                  // kExtractRows x m (column-major), then m DoF ids
     __shared__ double s_max[kBlock / kWave];
     const int p = blockIdx.x;
     const int64_t base = pptr[p];
     const int m = (int)(pptr[p + 1] - base);
+    int32_t* s_dofs = reinterpret_cast<int32_t*>(s_tile + (int64_t)kExtractRows * m);
     double* A = out + foff[p];
     for (int t = threadIdx.x; t < m; t += blockDim.x) s_dofs[t] = pdofs[base + t];
-    const int64_t mm = (int64_t)m * m;
-    for (int64_t e = threadIdx.x; e < mm; e += blockDim.x) A[e] = 0.0;
-    __syncthreads();
     const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
     double rmax = 0.0;
-    for (int a = wave; a < m; a += kBlock / kWave) {
-        const int g = s_dofs[a];
-        const int end = rowptr[g + 1];
-        double rsum = 0.0;
-        for (int k = rowptr[g] + lane; k < end; k += kWave) {
-            const int c = col[k];
-            int lo = 0, hi = m;
-            while (lo < hi) {
-                const int mid = (lo + hi) >> 1;
-                if (s_dofs[mid] < c) lo = mid + 1; else hi = mid;
+    for (int a0 = 0; a0 < m; a0 += kExtractRows) {
+        const int h = min(kExtractRows, m - a0);
+        for (int e = threadIdx.x; e < kExtractRows * m; e += blockDim.x) s_tile[e] = 0.0;
+        __syncthreads();
+        for (int q = wave; q < h; q += kBlock / kWave) {
+            const int g = s_dofs[a0 + q];
+            const int end = rowptr[g + 1];
+            double rsum = 0.0;
+            for (int k = rowptr[g] + lane; k < end; k += kWave) {
+                const int c = col[k];
+                int lo = 0, hi = m;
+                while (lo < hi) {
+                    const int mid = (lo + hi) >> 1;
+                    if (s_dofs[mid] < c) lo = mid + 1; else hi = mid;
+                }
+                if (lo < m && s_dofs[lo] == c) {
+                    s_tile[q + kExtractRows * lo] = val[k];
+                    rsum += fabs(val[k]);
+                }
             }
-            if (lo < m && s_dofs[lo] == c) {
-                A[a + (int64_t)lo * m] = val[k];
-                rsum += fabs(val[k]);
-            }
+            for (int off = kWave / 2; off > 0; off >>= 1) rsum += __shfl_xor(rsum, off);
+            rmax = fmax(rmax, rsum);
         }
-        for (int off = kWave / 2; off > 0; off >>= 1) rsum += __shfl_xor(rsum, off);
-        rmax = fmax(rmax, rsum);
+        __syncthreads();
+        for (int e = threadIdx.x; e < kExtractRows * m; e += blockDim.x) {
+            const int q = e % kExtractRows, j = e / kExtractRows;
+            if (q < h) A[(a0 + q) + (int64_t)j * m] = s_tile[e];
+        }
+        __syncthreads();
     }
     if (lane == 0) s_max[wave] = rmax;
     __syncthreads();
@@ -728,7 +744,7 @@ __global__ __launch_bounds__(kBlock) void convert_patch_kernel(const int64_t* __
 }
 
 // f64 set-up result B = (P K_i)^{-1} (column-major, ld = m) -> the symmetric
-// strip layout of S_i = (K_i^{-1} + K_i^{-T}) / 2 in precision T.  Column t of
+// strip layout (phmg_internal.h) of S_i = (K_i^{-1} + K_i^{-T}) / 2 in precision T.  Column t of
 // B is column idx[t] of K_i^{-1} (idx = pidx), so K_i^{-1}(i, j) = B(i, inv[j])
 // with inv the inverse permutation.  One workgroup per patch.
 template <typename T, int V>
@@ -736,8 +752,12 @@ __global__ __launch_bounds__(kBlock) void convert_sym_kernel(const int64_t* __re
                                                              const int64_t* __restrict__ foff64,
                                                              const int64_t* __restrict__ fofflp,
                                                              const int32_t* __restrict__ pidx,
-                                                             const double* __restrict__ src, T* __restrict__ dst) {
-    extern __shared__ int32_t s_inv[];
+                                                             const double* __restrict__ src, T* __restrict__ dst,
+                                                             int ldt) {
+    // LDS: the strip's kStrip source columns inv[r0 .. r0 + h - 1] (rows 0 .. w - 1,
+    // leading dimension ldt, odd), then the inverse permutation (m ints)
+    extern __shared__ double s_cols[];
+    int32_t* s_inv = reinterpret_cast<int32_t*>(s_cols + (int64_t)kStrip * ldt);
     const int p = blockIdx.x;
     const int64_t base = pptr[p];
     const int m = (int)(pptr[p + 1] - base);
@@ -756,16 +776,36 @@ __global__ __launch_bounds__(kBlock) void convert_sym_kernel(const int64_t* __re
     const int ns = (m + kStrip - 1) / kStrip;
     for (int s = 0; s < ns; ++s) {
         const int r0 = s * kStrip, h = min(kStrip, m - r0), hp = (h + V - 1) / V * V, w = r0 + h;
-        T* S = out + sym_strip_offset(s);
+        // K_i^{-1}(j, i) = B(j, inv[i]) for the strip's rows i: whole column segments
+        for (int e = threadIdx.x; e < h * w; e += kBlock) {
+            const int q = e / w, j = e % w;
+            s_cols[q * ldt + j] = B[j + (int64_t)s_inv[r0 + q] * m];
+        }
+        __syncthreads();
+        T* S = out + sym_strip_offset(s, V);
+        // strictly lower part (columns j < r0), then the diagonal block D (column
+        // c: rows g(c) .. hp - 1) holding D(q, c) below the diagonal, D(c, c) / 2
+        // on it and zero above it, so that the stored entries L satisfy
+        // S = L + L^T exactly
         const int total = hp * w;
         for (int e = threadIdx.x; e < total; e += kBlock) {
             const int q = e % hp, j = e / hp, i = r0 + q;
+            int64_t at = e;
+            double f = 1.0;                       // the diagonal block stores lower(D) + diag(D) / 2
+            if (j >= r0) {
+                constexpr int PG = sym_pack(V);
+                const int c = j - r0, g = c / PG * PG;
+                if (q < g) continue;
+                at = (int64_t)hp * r0 + sym_diag_offset(c, hp, PG) + (q - g);
+                f = q > c ? 1.0 : (q == c ? 0.5 : 0.0);
+            }
             double v = 0.0;
-            if (i < m) v = 0.5 * (B[i + (int64_t)s_inv[j] * m] + B[j + (int64_t)s_inv[i] * m]);
-            if constexpr (sizeof(T) == 8) S[e] = v;
-            else if constexpr (sizeof(T) == 4) S[e] = (T)v;
-            else S[e] = __float2bfloat16((float)v);
+            if (i < m) v = f * (0.5 * (B[i + (int64_t)s_inv[j] * m] + s_cols[q * ldt + j]));
+            if constexpr (sizeof(T) == 8) S[at] = v;
+            else if constexpr (sizeof(T) == 4) S[at] = (T)v;
+            else S[at] = __float2bfloat16((float)v);
         }
+        __syncthreads();
     }
 }
 
@@ -1332,8 +1372,11 @@ void launch_spmv_diff(hipStream_t s, const DevCsr& A1, const double* x1, const D
 
 void launch_extract(hipStream_t s, const Level& L, double* out) {
     if (L.npatch <= 0) return;
-    hipLaunchKernelGGL(extract_kernel, dim3(L.npatch), dim3(kBlock), sizeof(int32_t) * L.max_m, s, L.pptr, L.pdofs,
-                       L.foff, L.K.rowptr, L.K.col, L.K.val, out, L.ptol);
+    const size_t lds = sizeof(double) * (size_t)kExtractRows * L.max_m + sizeof(int32_t) * (size_t)L.max_m;
+    if (lds > 64 * 1024)
+        (void)hipFuncSetAttribute((const void*)extract_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    hipLaunchKernelGGL(extract_kernel, dim3(L.npatch), dim3(kBlock), lds, s, L.pptr, L.pdofs, L.foff, L.K.rowptr,
+                       L.K.col, L.K.val, out, L.ptol);
 }
 
 int gj_lds_max_m() { return kGjLdsMax; }
@@ -1395,16 +1438,25 @@ void launch_convert_general(hipStream_t s, const Level& L, const double* src, vo
 void launch_convert_patches(hipStream_t s, const Level& L, const double* src, void* dst) {
     if (L.npatch <= 0) return;
     if (L.sym) {
-        const size_t lds = sizeof(int32_t) * (size_t)L.max_m;
+        const int ldt = (int)L.max_m | 1;
+        const size_t lds = sizeof(double) * (size_t)kStrip * ldt + sizeof(int32_t) * (size_t)L.max_m;
+        if (lds > 64 * 1024) {
+            (void)hipFuncSetAttribute((const void*)convert_sym_kernel<double, factor_pad<double>()>,
+                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+            (void)hipFuncSetAttribute((const void*)convert_sym_kernel<float, factor_pad<float>()>,
+                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+            (void)hipFuncSetAttribute((const void*)convert_sym_kernel<__hip_bfloat16, factor_pad<__hip_bfloat16>()>,
+                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        }
         if (L.prec == PHMG_PREC_F64)
             hipLaunchKernelGGL((convert_sym_kernel<double, factor_pad<double>()>), dim3(L.npatch), dim3(kBlock), lds, s,
-                               L.pptr, L.foff, L.fofflp, L.pidx, src, (double*)dst);
+                               L.pptr, L.foff, L.fofflp, L.pidx, src, (double*)dst, ldt);
         else if (L.prec == PHMG_PREC_F32)
             hipLaunchKernelGGL((convert_sym_kernel<float, factor_pad<float>()>), dim3(L.npatch), dim3(kBlock), lds, s,
-                               L.pptr, L.foff, L.fofflp, L.pidx, src, (float*)dst);
+                               L.pptr, L.foff, L.fofflp, L.pidx, src, (float*)dst, ldt);
         else
             hipLaunchKernelGGL((convert_sym_kernel<__hip_bfloat16, factor_pad<__hip_bfloat16>()>), dim3(L.npatch),
-                               dim3(kBlock), lds, s, L.pptr, L.foff, L.fofflp, L.pidx, src, (__hip_bfloat16*)dst);
+                               dim3(kBlock), lds, s, L.pptr, L.foff, L.fofflp, L.pidx, src, (__hip_bfloat16*)dst, ldt);
         return;
     }
     if (L.prec == PHMG_PREC_F64)

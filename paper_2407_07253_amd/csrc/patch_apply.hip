@@ -179,8 +179,8 @@ void launch_typed(hipStream_t s, const Level& L, const double* r, double* Y) {
 // with RL = 16 / V row lanes (one 16-byte load each) and CL = 64 / RL column
 // lanes; a work unit is one strip times 64 consecutive stored columns, i.e. RL
 // loads per lane, each wave-wide load reading 1 KB of contiguous bytes.  Per
-// loaded row group (rows i, column j) the lane adds S(i, j) r_j to its row
-// partials and, for j below the diagonal block, forms S(i, j) . r_i for column j.
+// loaded row group (rows i, column j) of the stored entries L (S = L + L^T)
+// the lane adds L(i, j) r_j to its row partials and forms L(i, j) . r_i for column j.
 // Column sums are scatter-reduced over the row lanes (each lane ends with one
 // column), row sums are reduced over the column lanes, and both are added into
 // partial result u % 4 in LDS (u the unit's number in strip-major order); units
@@ -210,20 +210,91 @@ __device__ inline bool sym_step(int& s, int& c, int ns, int m) {
 
 // Loads of one unit without branches: a column past the strip's width reads
 // the last stored column and a row group past the strip's height the last row
-// group (both inside the patch's block, finite values).  The caller multiplies
-// such loads only by zero residual entries (rows >= m, columns >= w) or drops
-// their row sums, so they contribute nothing.
-template <typename T, bool NT>
+// group (both inside the patch's block, finite values); the caller multiplies
+// such loads only by zero residual entries (rows >= m) or drops their sums
+// (columns >= w).  In the diagonal block a row group above column c's stored
+// groups is not stored: the lane reads the first stored group and zeroes it.
+// DIAG: the unit reaches the diagonal block (columns >= 16 s).
+template <typename T, bool NT, bool DIAG>
 __device__ inline void sym_load(const T* A, int s, int c_lo, int m, int rl, int cl,
                                 typename Load16<T>::acc_t (&a)[SymShape<T>::U][SymShape<T>::V]) {
     typedef SymShape<T> Sh;
-    const int r0 = s * kStrip, h = min(kStrip, m - r0), hp = (h + Sh::V - 1) / Sh::V * Sh::V, w = r0 + h;
-    const T* S = A + sym_strip_offset(s) + min(rl * Sh::V, hp - Sh::V);
+    typedef typename Load16<T>::acc_t Acc;
+    constexpr int V = Sh::V;
+    const int r0 = s * kStrip, h = min(kStrip, m - r0), hp = (h + V - 1) / V * V, w = r0 + h;
+    const T* S = A + sym_strip_offset(s, V);
+    const int rg = min(rl * V, hp - V);
 #pragma unroll
     for (int u = 0; u < Sh::U; ++u) {
         const int j = min(c_lo + cl + Sh::CL * u, w - 1);
-        Load16<T>::template load<NT>(S + j * hp, a[u]);
+        int64_t off = (int64_t)j * hp + rg;
+        bool above = false;
+        if (DIAG && j >= r0) {
+            constexpr int PG = sym_pack(V);
+            const int c = j - r0, g = c / PG * PG;
+            above = rg < g;
+            off = (int64_t)hp * r0 + sym_diag_offset(c, hp, PG) + (max(rg, g) - g);
+        }
+        Load16<T>::template load<NT>(S + off, a[u]);
+        if (DIAG && sym_pack(V) < kStrip) {
+#pragma unroll
+            for (int v = 0; v < V; ++v) a[u][v] = above ? (Acc)0 : a[u][v];
+        }
     }
+}
+
+// The arithmetic of one unit (strip s, stored columns c .. c + 63, factor
+// values in a): with L the stored entries, row sums L(rows, cols) r_cols and
+// column sums L(rows, j)^T r_rows, added into the partial result yw.
+template <typename T>
+__device__ inline void sym_unit(const typename Load16<T>::acc_t (&a)[SymShape<T>::U][SymShape<T>::V], int s, int c,
+                                int m, int rl, int cl, int lane, const typename Load16<T>::acc_t* s_r,
+                                typename Load16<T>::acc_t* yw) {
+    typedef typename Load16<T>::acc_t Acc;
+    typedef SymShape<T> Sh;
+    constexpr int V = Sh::V, RL = Sh::RL, CL = Sh::CL, U = Sh::U;
+    const int r0 = s * kStrip, w = min(m, r0 + kStrip);
+    Acc rr[V];
+#pragma unroll
+    for (int v = 0; v < V; ++v) {
+        const int i = r0 + rl * V + v;
+        rr[v] = i < m ? s_r[i] : (Acc)0;
+    }
+    Acc acc[V], d[U];
+#pragma unroll
+    for (int v = 0; v < V; ++v) acc[v] = (Acc)0;
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        const int j = c + cl + CL * u;
+        const Acc rj = j < w ? s_r[min(j, w - 1)] : (Acc)0;
+        Acc dd = (Acc)0;
+#pragma unroll
+        for (int v = 0; v < V; ++v) {
+            acc[v] += a[u][v] * rj;
+            dd += a[u][v] * rr[v];
+        }
+        d[u] = dd;
+    }
+    // column sums: scatter-reduce over the RL row lanes; the lane keeps column c + cl + CL * rl
+    GroupReduce<Acc, U, RL, 1>::run(d, lane);
+    {
+        const int j = c + cl + CL * rl;
+        if (j < w) yw[j] += d[0];
+    }
+    // row sums: reduce over the CL column lanes
+    GroupReduce<Acc, V, CL, RL>::run(acc, lane);
+    if (cl % (CL / V) == 0) {
+        const int i = r0 + rl * V + cl / (CL / V);
+        if (i < m) yw[i] += acc[0];
+    }
+}
+
+// one unit's loads, dispatched on whether the unit reaches the diagonal block
+template <typename T, bool NT>
+__device__ inline void sym_load_unit(const T* A, int s, int c, int m, int rl, int cl,
+                                     typename Load16<T>::acc_t (&a)[SymShape<T>::U][SymShape<T>::V]) {
+    if (c + kUnitCols > s * kStrip) sym_load<T, NT, true>(A, s, c, m, rl, cl, a);
+    else sym_load<T, NT, false>(A, s, c, m, rl, cl, a);
 }
 
 // NWV wavefronts per workgroup (4, or 1 for levels of small patches, where a
@@ -263,7 +334,7 @@ __global__ __launch_bounds__(kBlock) void patch_apply_sym_kernel(const int32_t* 
     bool ok = true;
     for (int q = 0; q < wave && ok; ++q) ok = sym_step(s, c, ns, m);
     Acc a[U][V];
-    if (ok) sym_load<T, NT>(A, s, c, m, rl, cl, a);
+    if (ok) sym_load_unit<T, NT>(A, s, c, m, rl, cl, a);
     for (int t = threadIdx.x; t < m; t += NTH) {
         const double v = r[pdofs[base + t]];
         s_r[t] = (Acc)(gw ? gw[base + t] * v : v);
@@ -278,46 +349,12 @@ __global__ __launch_bounds__(kBlock) void patch_apply_sym_kernel(const int32_t* 
         Acc* yw = s_y + (unit % NP) * ldbuf;
         Acc b[U][V];
         if (PF) {
-            if (ok2) sym_load<T, NT>(A, s2, c2, m, rl, cl, b);
+            if (ok2) sym_load_unit<T, NT>(A, s2, c2, m, rl, cl, b);
         } else if (!first) {
-            sym_load<T, NT>(A, s, c, m, rl, cl, a);
+            sym_load_unit<T, NT>(A, s, c, m, rl, cl, a);
         }
         first = false;
-        const int r0 = s * kStrip, w = min(m, r0 + kStrip);
-        Acc rr[V];
-#pragma unroll
-        for (int v = 0; v < V; ++v) {
-            const int i = r0 + rl * V + v;
-            rr[v] = i < m ? s_r[i] : (Acc)0;
-        }
-        Acc acc[V], d[U];
-#pragma unroll
-        for (int v = 0; v < V; ++v) acc[v] = (Acc)0;
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const int j = c + cl + CL * u;
-            const Acc rj = j < w ? s_r[min(j, w - 1)] : (Acc)0;
-            Acc dd = (Acc)0;
-#pragma unroll
-            for (int v = 0; v < V; ++v) {
-                acc[v] += a[u][v] * rj;
-                dd += a[u][v] * rr[v];
-            }
-            d[u] = j < r0 ? dd : (Acc)0;
-        }
-        // column sums S(rows, j)^T r_rows: scatter-reduce over the RL row lanes; the lane
-        // keeps column c + cl + CL * rl
-        GroupReduce<Acc, U, RL, 1>::run(d, lane);
-        {
-            const int j = c + cl + CL * rl;
-            if (j < r0) yw[j] += d[0];
-        }
-        // row sums: reduce over the CL column lanes
-        GroupReduce<Acc, V, CL, RL>::run(acc, lane);
-        if (cl % (CL / V) == 0) {
-            const int i = r0 + rl * V + cl / (CL / V);
-            if (i < m) yw[i] += acc[0];
-        }
+        sym_unit<T>(a, s, c, m, rl, cl, lane, s_r, yw);
         s = s2;
         c = c2;
         ok = ok2;
@@ -343,12 +380,13 @@ void launch_sym_shape(hipStream_t s, const Level& L, const double* r, const doub
     typedef typename Load16<T>::acc_t Acc;
     const int ldbuf = (L.max_m + 1) & ~1;
     const size_t lds = sizeof(Acc) * (size_t)ldbuf * (1 + kSymParts);
-    if (streams_factors(L, L.sym))
+    if (streams_factors(L, L.sym)) {
         hipLaunchKernelGGL((patch_apply_sym_kernel<T, PF, NWV, true>), dim3(L.npatch), dim3(NWV * kWave), lds, s,
                            L.order, L.pptr, L.pdofs, L.fofflp, (const T*)L.factors, r, gw, Y, ldbuf);
-    else
+    } else {
         hipLaunchKernelGGL((patch_apply_sym_kernel<T, PF, NWV, false>), dim3(L.npatch), dim3(NWV * kWave), lds, s,
                            L.order, L.pptr, L.pdofs, L.fofflp, (const T*)L.factors, r, gw, Y, ldbuf);
+    }
 }
 
 // shapes: 0 / 1 four waves without / with prefetch, 2 / 3 one wave without / with prefetch

@@ -906,14 +906,20 @@ void setup_levels(phmg_ctx ctx, int lo, int hi) {
             L.factor_bytes = bytes;
         }
     }
-    // level streams, fork after everything enqueued so far on the context stream
-    if ((int)ctx->sstreams.size() < nl) {
-        for (int l = (int)ctx->sstreams.size(); l < nl; ++l) {
-            hipStream_t st = nullptr;
-            hipcheck(hipStreamCreateWithFlags(&st, hipStreamNonBlocking), "hipStreamCreate");
-            ctx->sstreams.push_back(st);
-        }
+    // set-up streams, forked after everything enqueued so far on the context stream:
+    // the finest level (the longest chain) on one, the intermediate levels one after
+    // another on a second, the dense coarse inverse on a third.  Three streams plus the
+    // context stream stay within the four hardware queues a process gets by default,
+    // so no other level's kernels queue up behind the finest level's or in front of them.
+    const int nstreams = std::min(nl, 3);
+    while ((int)ctx->sstreams.size() < nstreams) {
+        hipStream_t st = nullptr;
+        hipcheck(hipStreamCreateWithFlags(&st, hipStreamNonBlocking), "hipStreamCreate");
+        ctx->sstreams.push_back(st);
     }
+    auto sst = [&](int l) -> hipStream_t {
+        return ctx->sstreams[l == 0 ? 0 : (l == last ? nstreams - 1 : 1)];
+    };
     while ((int)ctx->sevents.size() < nl + 1) {
         hipEvent_t e = nullptr;
         hipcheck(hipEventCreateWithFlags(&e, hipEventDisableTiming), "hipEventCreate");
@@ -922,19 +928,18 @@ void setup_levels(phmg_ctx ctx, int lo, int hi) {
     if (!ctx->status_host)
         hipcheck(hipHostMalloc((void**)&ctx->status_host, sizeof(int32_t) * nl), "hipHostMalloc");
     hipcheck(hipEventRecord(ctx->sevents[0], s0), "hipEventRecord");
-    struct Drain {                                  // every exit waits for all level streams
+    struct Drain {                                  // every exit waits for all set-up streams
         phmg_ctx c;
-        int lo, hi;
         ~Drain() {
-            for (int l = lo; l < hi; ++l) (void)hipStreamSynchronize(c->sstreams[l]);
+            for (auto st : c->sstreams) (void)hipStreamSynchronize(st);
         }
-    } drain{ctx, lo, hi};
+    } drain{ctx};
     for (int l = lo; l < hi; ++l)
-        hipcheck(hipStreamWaitEvent(ctx->sstreams[l], ctx->sevents[0], 0), "hipStreamWaitEvent");
+        hipcheck(hipStreamWaitEvent(sst(l), ctx->sevents[0], 0), "hipStreamWaitEvent");
     // factorisations
     for (int l = lo; l < hi; ++l) {
         Level& L = ctx->L[l];
-        hipStream_t s = ctx->sstreams[l];
+        hipStream_t s = sst(l);
         launch_fill_i32(s, 1, L.status, INT32_MAX);
         if (l == last) {
             launch_coarse_build(s, L, L.cdense);
@@ -975,14 +980,14 @@ void setup_levels(phmg_ctx ctx, int lo, int hi) {
     for (int l = lo; l < hi && l < last; ++l) {
         Level& L = ctx->L[l];
         if (L.tuned_for == tune_key(L) || L.npatch == 0) continue;
-        hipcheck(hipStreamSynchronize(ctx->sstreams[l]), "hipStreamSynchronize");
+        hipcheck(hipStreamSynchronize(sst(l)), "hipStreamSynchronize");
         check_status(l);
-        tune_apply(ctx, l, ctx->sstreams[l]);
+        tune_apply(ctx, l, sst(l));
     }
     std::vector<double> lmax(nl, 0.0);
     if (ctx->opts.smoother == PHMG_SMOOTHER_CHEBYSHEV) {
         std::vector<ArnoldiRun> runs;
-        for (int l = lo; l < hi && l < last; ++l) runs.push_back(arnoldi_begin(ctx, l, ctx->sstreams[l]));
+        for (int l = lo; l < hi && l < last; ++l) runs.push_back(arnoldi_begin(ctx, l, sst(l)));
         int kmax = 0;
         for (const auto& a : runs) kmax = std::max(kmax, a.k);
         for (int j = 0; j < kmax; ++j)
@@ -991,7 +996,7 @@ void setup_levels(phmg_ctx ctx, int lo, int hi) {
         for (const auto& a : runs) lmax[a.l] = arnoldi_finish(a);      // synchronises the level's stream
     }
     for (int l = lo; l < hi; ++l) {
-        hipcheck(hipStreamSynchronize(ctx->sstreams[l]), "hipStreamSynchronize");
+        hipcheck(hipStreamSynchronize(sst(l)), "hipStreamSynchronize");
         check_status(l);
     }
     if (ctx->opts.smoother == PHMG_SMOOTHER_CHEBYSHEV)
@@ -1001,7 +1006,7 @@ void setup_levels(phmg_ctx ctx, int lo, int hi) {
             ctx->L[l].lmax = lmax[l];
         }
     for (int l = lo; l < hi; ++l) {
-        hipcheck(hipEventRecord(ctx->sevents[1 + l], ctx->sstreams[l]), "hipEventRecord");
+        hipcheck(hipEventRecord(ctx->sevents[1 + l], sst(l)), "hipEventRecord");
         hipcheck(hipStreamWaitEvent(s0, ctx->sevents[1 + l], 0), "hipStreamWaitEvent");
     }
     for (int l = lo; l < hi; ++l) {

@@ -30,17 +30,31 @@ inline int factor_pad_of(int prec) { return prec == PHMG_PREC_F64 ? 2 : (prec ==
 
 // Symmetric layout of a patch inverse S (used when the level matrix is
 // symmetric): the rows are cut into strips of kStrip rows; strip s (rows
-// [16 s, 16 s + h_s)) stores columns [0, 16 s + h_s) -- the strictly lower part
-// of its rows plus the full diagonal block -- column-major with its height
-// padded to the 16-byte row group V (padding rows are zero).  Strips are
-// consecutive: full strips take 16 x 16 (s + 1) elements, so strip s starts at
-// 128 s (s + 1).  An entry S(i, j), j < 16 s, stands for S(j, i) too.
+// [r0, r0 + h), r0 = 16 s) stores, with its height padded to the 16-byte row
+// group V (hp = h rounded up to V, padding rows zero):
+//   * the strictly lower part, columns [0, r0), column-major hp x r0;
+//   * then its diagonal block D: column c (c < h) holds rows [g(c), hp) with
+//     g(c) = c rounded down to the packing group PG = sym_pack(V) -- the row
+//     group V for float64 / float32, the whole block for bfloat16, whose
+//     kernels would spend more on the packed addressing than they save -- and
+//     D(q, c) for q > c, D(c, c) / 2 on the diagonal, zero for the q < c that
+//     fall inside the stored rows.  Column c starts at sym_diag_offset(c, hp, PG).
+// With L the stored entries of all strips, S = L + L^T exactly (halving is
+// exact), so a kernel adds both L r and L^T r over every stored entry alike.
+// Strips are consecutive; a full strip takes 256 s + sym_diag_offset(16, 16, PG)
+// elements (144 / 160 / 256 in the diagonal block for float64 / float32 / bfloat16).
 constexpr int kStrip = 16;
-__host__ __device__ constexpr int64_t sym_strip_offset(int s) { return (int64_t)kStrip * kStrip * s * (s + 1) / 2; }
+__host__ __device__ constexpr int sym_pack(int V) { return V < 8 ? V : kStrip; }
+__host__ __device__ constexpr int sym_diag_offset(int c, int hp, int PG) {
+    return PG * (c / PG) * hp - PG * PG * (c / PG) * (c / PG - 1) / 2 + (c % PG) * (hp - (c / PG) * PG);
+}
+__host__ __device__ constexpr int64_t sym_strip_offset(int s, int V) {
+    return (int64_t)128 * s * (s - 1) + (int64_t)sym_diag_offset(kStrip, kStrip, sym_pack(V)) * s;
+}
 __host__ __device__ inline int64_t sym_layout_size(int m, int V) {
     const int ns = (m + kStrip - 1) / kStrip;
-    const int h = m - (ns - 1) * kStrip;
-    return sym_strip_offset(ns - 1) + (int64_t)((h + V - 1) / V * V) * m;
+    const int h = m - (ns - 1) * kStrip, hp = (h + V - 1) / V * V;
+    return sym_strip_offset(ns - 1, V) + (int64_t)hp * kStrip * (ns - 1) + sym_diag_offset(h, hp, sym_pack(V));
 }
 
 struct DevCsr {
@@ -417,6 +431,14 @@ void launch_spmm(hipStream_t s, const DevCsr& A, const double* X, double alpha, 
 // weights at the gather)
 void launch_block_apply(hipStream_t s, const Level& L, const double* X, bool transpose = false);
 int block_variant_count(const Level& L);
+// blocks of 16 rows per patch the symmetric-layout block solve is compiled for on this level
+// (4, 9 or 14), or 0 when the level's block path streams the general layout
+int block_sym_blocks(const Level& L);
+// the symmetric-layout block solve of a level with block_sym_blocks(L) > 0, per factor precision
+// (Y_i = S_i X[S_i, :] into L.Yb; gw: DoF weights applied to the gather, adjoint sweep)
+void launch_block_sym_f64(hipStream_t s, const Level& L, const double* X, const double* gw);
+void launch_block_sym_f32(hipStream_t s, const Level& L, const double* X, const double* gw);
+void launch_block_sym_bf16(hipStream_t s, const Level& L, const double* X, const double* gw);
 void launch_block_scatter(hipStream_t s, const Level& L, double a, double c, double* d, bool store_d, double* X,
                           bool x_zero, bool transpose = false);
 void launch_block_coarse_solve(hipStream_t s, const Level& L, const double* B, double* X, bool transpose = false);

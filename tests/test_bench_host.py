@@ -22,10 +22,23 @@ def test_method_bytes_closed_forms():
     assert bench.method_apply_bytes(m, 8, True) == 8 * words_sym + slots
     assert bench.method_apply_bytes(m, 8, False) == 8 * words_gen + slots
     assert bench.method_apply_bytes(m, 2, True) == 2 * words_sym + slots
-    # the strip layout stores the full 16 x 16 diagonal blocks: 141 DoFs = 9 strips, the last of 13 rows
-    ns, h = 9, 141 - 8 * 16
-    assert bench.layout_apply_bytes(np.array([141]), 8, True) == 8 * (128 * (ns - 1) * ns + h * 141) + 20 * 141 + 20
-    assert bench.layout_apply_bytes(np.array([16]), 8, True) == 8 * 256 + 20 * 16 + 20
+    # the strip layout: per strip of 16 rows the strictly lower part (height padded to V = 16 / es rows)
+    # and the diagonal block's lower triangle in whole row groups of V (float64, float32) or the whole
+    # block (bfloat16); counted here entry by entry
+    def stored(mm, es):
+        V = 16 // es
+        G = V if V < 8 else 16
+        words = 0
+        for r0 in range(0, mm, 16):
+            h = min(16, mm - r0)
+            hp = -(-h // V) * V
+            words += hp * r0 + sum(hp - c // G * G for c in range(h))
+        return words
+    for mm in (1, 3, 16, 17, 64, 141, 210):
+        for es in (8, 4, 2):
+            assert bench.layout_apply_bytes(np.array([mm]), es, True) == es * stored(mm, es) + 20 * mm + 20, (mm, es)
+    # 141 DoFs in f64: 9 strips, the last of 13 rows padded to 14; 2.1 % above m (m + 1) / 2
+    assert stored(141, 8) == 10222
     # block path: 16 systems share the factor words, each slot moves two 16-wide rows and an index
     assert bench.method_block_bytes(np.array([10]), 8, False) == 8 * 100 + (4 + 256) * 10 + 20
 

@@ -519,18 +519,20 @@ def main() -> int:
 
     extra = {}
     if not args.no_extra and batched:
-        print("# extra legs: cfg3 P3/P2, cfg2 ...", file=sys.stderr, flush=True)
-        for name, wl, k, job in (("cfg3_P3P2", "cfg3", 3, "cfg3_k3"), ("cfg2", "cfg2", None, "cfg2")):
+        print("# extra legs: cfg3 P3/P2, cfg2, cfg4 ...", file=sys.stderr, flush=True)
+        for name, wl, k, job in (("cfg3_P3P2", "cfg3", 3, "cfg3_k3"), ("cfg2", "cfg2", None, "cfg2"),
+                                 ("cfg4", "cfg4", None, "cfg4")):
             fx, Hx, tb = make_hierarchy(wl, k=k)
             bx = torch.tensor(fx.b[0], device=dev)
             gx = golden(job)
-            e = {"workload": WORKLOADS["cfg2"] if wl == "cfg2" else
+            e = {"workload": WORKLOADS[wl] if wl != "cfg3" else
                  "TH P3/P2 2D structured 128x128 (359427 DoFs); phMG direct P3/P2 -> P2/P1 -> 4 h-levels; MMS forcing",
                  "levels_n": [L.n for L in fx.levels], "host_build_s": round(tb, 2)}
             for p in PRECS:
                 e[p] = single_solve_leg(Hx, fx, p, bx, gx, 0)
                 a = apply_leg(Hx, fx, p, args.apply_reps, wl)
                 e[p]["patch_apply_gbps"] = _fmt(a["gbps"])
+                e[p]["patch_apply_layout_gbps"] = _fmt(a["layout_gbps"])
                 e[p]["patch_apply_ms"] = _fmt(a["avg_ms"])
             e["setup_roofline_lu_tflops"] = _fmt(factor_leg(Hx, fx)["tflops"])
             Hx.close()

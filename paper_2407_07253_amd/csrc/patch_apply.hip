@@ -289,11 +289,12 @@ __device__ inline void sym_unit(const typename Load16<T>::acc_t (&a)[SymShape<T>
     }
 }
 
-// one unit's loads, dispatched on whether the unit reaches the diagonal block
+// one unit's loads, dispatched on whether the unit reaches a packed diagonal
+// block (a whole stored diagonal block, bfloat16, continues the column-major strip)
 template <typename T, bool NT>
 __device__ inline void sym_load_unit(const T* A, int s, int c, int m, int rl, int cl,
                                      typename Load16<T>::acc_t (&a)[SymShape<T>::U][SymShape<T>::V]) {
-    if (c + kUnitCols > s * kStrip) sym_load<T, NT, true>(A, s, c, m, rl, cl, a);
+    if (sym_pack(SymShape<T>::V) < kStrip && c + kUnitCols > s * kStrip) sym_load<T, NT, true>(A, s, c, m, rl, cl, a);
     else sym_load<T, NT, false>(A, s, c, m, rl, cl, a);
 }
 

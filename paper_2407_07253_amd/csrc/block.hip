@@ -52,7 +52,7 @@ void ensure_block(phmg_ctx ctx) {
         if (L.npatch > 0) L.Yb = dalloc<double>(ctx, L.sum_m * kBS);
     }
     if (block_gs_max_basis() != kHB) fail(PHMG_EINVAL, "block Gram-Schmidt basis limit mismatch");
-    ctx->bpartial = dalloc<double>(ctx, (int64_t)kRedBlocks * kHB * kBS);
+    ctx->bpartial = dalloc<double>(ctx, (int64_t)kBlockGsBlocks * kHB * kBS);
     ctx->bh = dalloc<double>(ctx, kBhLen);
     hipcheck(hipHostMalloc((void**)&ctx->bhhost, sizeof(double) * kBhLen), "hipHostMalloc");
     ctx->block_ready = true;

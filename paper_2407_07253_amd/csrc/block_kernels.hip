@@ -295,27 +295,29 @@ __global__ __launch_bounds__(kBlock) void block_coarse_solve_kernel(int32_t n, i
 
 // ---------------------------------------------------------------------------
 // Gram-Schmidt passes over the block Krylov basis V_0..V_{ncol-1} (each n x 16,
-// stride ldv), one pass over the rows with per-thread accumulators:
+// stride ldv), over the rows with per-thread accumulators:
 //   MODE 0: h_j = V_j^T w                      (per column)
 //   MODE 1: w <- w - sum_j V_j h_j, then h'_j = V_j^T w (h' into the partials)
 //   MODE 2: w <- w - sum_j V_j h_j, then ||w||^2
-// Partials per workgroup: partial[(j * kBS + c) * gridDim.x + block].
+// The products are formed in chunks of kGsChunk basis vectors, one pass over the
+// rows per chunk (the first pass also updates w; later passes re-read it), so a
+// thread keeps kGsChunk accumulators instead of one per basis vector: with few
+// registers the fixed grid of kBlockGsBlocks workgroups stays resident at 8
+// waves per SIMD and keeps enough loads in flight.  Partials per workgroup:
+// partial[(j * kBS + c) * gridDim.x + block].
 // ---------------------------------------------------------------------------
 constexpr int kMaxBasis = 32;
+constexpr int kGsChunk = 8;
 
 template <int MODE>
 __global__ __launch_bounds__(kBlock) void block_gs_kernel(int64_t n, int ncol, const double* __restrict__ V,
                                                           int64_t ldv, double* __restrict__ w,
                                                           const double* __restrict__ h,
                                                           double* __restrict__ partial) {
-    __shared__ double sh[kMaxBasis][kBlock / kWave][kBS];
+    __shared__ double sh[kGsChunk][kBlock / kWave][kBS];
     __shared__ double s_h[kMaxBasis][kBS];
     const int c = threadIdx.x & (kBS - 1);
     const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
-    constexpr int NOUT = MODE == 2 ? 1 : kMaxBasis;
-    double dot[NOUT];
-#pragma unroll
-    for (int j = 0; j < NOUT; ++j) dot[j] = 0.0;
     if (MODE != 0) {
         for (int t = threadIdx.x; t < kMaxBasis * kBS; t += kBlock) {
             const int j = t / kBS;
@@ -324,39 +326,49 @@ __global__ __launch_bounds__(kBlock) void block_gs_kernel(int64_t n, int ncol, c
         __syncthreads();
     }
     const int64_t rows_per_grid = ((int64_t)gridDim.x * kBlock) / kBS;
-    for (int64_t i = (blockIdx.x * (int64_t)kBlock + threadIdx.x) / kBS; i < n; i += rows_per_grid) {
-        const int64_t e = i * kBS + c;
-        double wi = w[e];
-        if (MODE != 0) {
-            double s = 0.0;
+    const int64_t i0 = (blockIdx.x * (int64_t)kBlock + threadIdx.x) / kBS;
+    const int nchunk = MODE == 2 ? 1 : (ncol + kGsChunk - 1) / kGsChunk;
+    for (int ch = 0; ch < nchunk; ++ch) {
+        double dot[kGsChunk];
 #pragma unroll
-            for (int j = 0; j < kMaxBasis; ++j)
-                if (j < ncol) s += V[j * ldv + e] * s_h[j][c];
-            wi -= s;
-            w[e] = wi;
-        }
-        if (MODE == 2) {
-            dot[0] += wi * wi;
-        } else {
+        for (int q = 0; q < kGsChunk; ++q) dot[q] = 0.0;
+        for (int64_t i = i0; i < n; i += rows_per_grid) {
+            const int64_t e = i * kBS + c;
+            double wi = w[e];
+            if (MODE != 0 && ch == 0) {
+                double s = 0.0;
+#pragma unroll 8
+                for (int j = 0; j < ncol; ++j) s += V[j * ldv + e] * s_h[j][c];
+                wi -= s;
+                w[e] = wi;
+            }
+            if (MODE == 2) {
+                dot[0] += wi * wi;
+            } else {
 #pragma unroll
-            for (int j = 0; j < kMaxBasis; ++j)
-                if (j < ncol) dot[j] += V[j * ldv + e] * wi;
+                for (int q = 0; q < kGsChunk; ++q) {
+                    const int j = ch * kGsChunk + q;
+                    if (j < ncol) dot[q] += V[j * ldv + e] * wi;
+                }
+            }
         }
-    }
-    const int nout = MODE == 2 ? 1 : ncol;
+        const int nq = MODE == 2 ? 1 : min(kGsChunk, ncol - ch * kGsChunk);
 #pragma unroll
-    for (int j = 0; j < NOUT; ++j) {
-        if (j < nout) {
-            double v = dot[j];
-            v += __shfl_xor(v, 16);
-            v += __shfl_xor(v, 32);
-            if (lane < kBS) sh[j][wave][lane] = v;
+        for (int q = 0; q < kGsChunk; ++q) {
+            if (q < nq) {
+                double v = dot[q];
+                v += __shfl_xor(v, 16);
+                v += __shfl_xor(v, 32);
+                if (lane < kBS) sh[q][wave][lane] = v;
+            }
         }
-    }
-    __syncthreads();
-    for (int t = threadIdx.x; t < nout * kBS; t += kBlock) {
-        const int j = t / kBS, cc = t % kBS;
-        partial[(int64_t)t * gridDim.x + blockIdx.x] = (sh[j][0][cc] + sh[j][1][cc]) + (sh[j][2][cc] + sh[j][3][cc]);
+        __syncthreads();
+        for (int t = threadIdx.x; t < nq * kBS; t += kBlock) {
+            const int q = t / kBS, cc = t % kBS;
+            const int64_t slot = (int64_t)((ch * kGsChunk + q) * kBS + cc);
+            partial[slot * gridDim.x + blockIdx.x] = (sh[q][0][cc] + sh[q][1][cc]) + (sh[q][2][cc] + sh[q][3][cc]);
+        }
+        __syncthreads();
     }
 }
 
@@ -530,12 +542,12 @@ void launch_block_gs(hipStream_t s, int mode, int64_t n, int ncol, const double*
                      const double* h, double* partial, double* out) {
     const int nout = mode == 2 ? 1 : ncol;
     if (mode == 0)
-        hipLaunchKernelGGL(block_gs_kernel<0>, dim3(kRedBlocks), dim3(kBlock), 0, s, n, ncol, V, ldv, w, h, partial);
+        hipLaunchKernelGGL(block_gs_kernel<0>, dim3(kBlockGsBlocks), dim3(kBlock), 0, s, n, ncol, V, ldv, w, h, partial);
     else if (mode == 1)
-        hipLaunchKernelGGL(block_gs_kernel<1>, dim3(kRedBlocks), dim3(kBlock), 0, s, n, ncol, V, ldv, w, h, partial);
+        hipLaunchKernelGGL(block_gs_kernel<1>, dim3(kBlockGsBlocks), dim3(kBlock), 0, s, n, ncol, V, ldv, w, h, partial);
     else
-        hipLaunchKernelGGL(block_gs_kernel<2>, dim3(kRedBlocks), dim3(kBlock), 0, s, n, ncol, V, ldv, w, h, partial);
-    hipLaunchKernelGGL(block_reduce_kernel, dim3(nout * kBS), dim3(kBlock), 0, s, kRedBlocks, partial, out);
+        hipLaunchKernelGGL(block_gs_kernel<2>, dim3(kBlockGsBlocks), dim3(kBlock), 0, s, n, ncol, V, ldv, w, h, partial);
+    hipLaunchKernelGGL(block_reduce_kernel, dim3(nout * kBS), dim3(kBlock), 0, s, kBlockGsBlocks, partial, out);
 }
 
 int block_gs_max_basis() { return kMaxBasis; }

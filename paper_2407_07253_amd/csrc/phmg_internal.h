@@ -16,6 +16,7 @@ constexpr int kBlock = 256;          // threads per workgroup (4 wavefronts of 6
 constexpr int kWave = 64;
 constexpr int kPanel = 16;           // Gauss-Jordan panel width = MFMA f64 16x16x4 tile edge
 constexpr int kRedBlocks = 512;      // fixed grid of the deterministic reductions
+constexpr int kBlockGsBlocks = 2048; // fixed grid of the block Gram-Schmidt passes (8 waves per SIMD)
 constexpr int kBS = 16;              // columns of a block vector (right-hand sides solved together)
 constexpr int kRbRows = 32;          // rows of an SpMV row block (8 lanes per row)
 constexpr int kRbNnz = 1024;         // nonzeros of an SpMV row block (4 per thread)
@@ -242,7 +243,7 @@ struct phmg_ctx_s {
     double* Zb = nullptr;
     double* wb = nullptr;
     double* rvb = nullptr;
-    double* bpartial = nullptr;      // kRedBlocks x 32 x kBS
+    double* bpartial = nullptr;      // kBlockGsBlocks x 32 x kBS
     double* bh = nullptr;            // device: h1 | h2 | hn2 | column scales
     double* bhhost = nullptr;        // pinned mirror of bh
     double* bgin = nullptr;

@@ -21,7 +21,7 @@ namespace blocksym {
 // four waves per patch.  The stored part of S_i is cut into 16 x 16 tiles
 // (s, t), t <= s, numbered in strip-major order; tile u belongs to wave u % 4.
 // A tile is loaded once (lane l: row l % 16, columns 4 kk + l / 16 of the tile,
-// one element per MFMA operand) and feeds
+// one element per MFMA operand; bfloat16 tiles in 8-byte loads, see SymTile) and feeds
 //   * the row product  Y[strip s] += L(s, t) G[block t]   (4 MFMAs), and
 //   * the transposed product  Y[block t] += L(s, t)^T G[strip s]  (4 MFMAs) on
 //     the tile transposed through a 16 x 17 LDS buffer of the wave.
@@ -76,23 +76,148 @@ __device__ inline void sym_tile_load(const T* A, int m, int s, int t, int li, in
     }
 }
 
+constexpr int kTld = kStrip + 1;                  // leading dimension of the transpose buffers
+
+// A tile in flight and its two MFMA operand layouts.  Generic form: the tile is
+// loaded in the A-operand layout (one element per lane per MFMA) and only the
+// transposed operand goes through the wave's LDS buffer tb (T[c][q] at c kTld + q).
+template <typename T, typename Acc>
+struct SymTile {
+    Acc v[4];
+    template <bool ST>
+    __device__ inline void load(const T* A, int m, int s, int t, int li, int lk, int /*lane*/) {
+        sym_tile_load<T, Acc, ST>(A, m, s, t, li, lk, v);
+    }
+    // (t < s: an off-diagonal tile; the generic form loads every tile the same way)
+    __device__ inline void zero() {
+#pragma unroll
+        for (int kk = 0; kk < 4; ++kk) v[kk] = (Acc)0;
+    }
+    __device__ inline void operands(Acc* tb, int li, int lk, int /*lane*/, bool /*offdiag*/, Acc (&a)[4],
+                                    Acc (&at)[4]) const {
+#pragma unroll
+        for (int kk = 0; kk < 4; ++kk) {
+            a[kk] = v[kk];
+            tb[(4 * kk + lk) * kTld + li] = v[kk];
+        }
+        __builtin_amdgcn_wave_barrier();
+#pragma unroll
+        for (int kk = 0; kk < 4; ++kk) at[kk] = tb[li * kTld + 4 * kk + lk];
+    }
+};
+
+// bfloat16 tiles (whole stored diagonal blocks, column-major with leading dimension hp, a multiple
+// of 8): lane l loads rows 4 (l % 4) .. + 3 of tile column l / 4 in one 8-byte load, and both operand
+// layouts are read back from the LDS buffer -- one load instruction per tile instead of four.
+template <>
+struct SymTile<__hip_bfloat16, float> {
+    uint32_t lo = 0, hi = 0;
+    template <bool ST>
+    __device__ inline void load(const __hip_bfloat16* A, int m, int s, int t, int /*li*/, int /*lk*/, int lane) {
+        const int r0 = s * kStrip, h = min(kStrip, m - r0), hp = (h + 7) / 8 * 8, wc = t < s ? kStrip : h;
+        const int c = lane / 4, q0 = 4 * (lane % 4);
+        lo = 0;
+        hi = 0;
+        if (q0 < hp && c < wc) {
+            typedef uint32_t u2 __attribute__((ext_vector_type(2)));
+            const u2* q = reinterpret_cast<const u2*>(A + sym_strip_offset(s, 8) + (int64_t)(t * kStrip + c) * hp + q0);
+            const u2 v = ST ? __builtin_nontemporal_load(q) : *q;
+            lo = v.x;
+            hi = v.y;
+        }
+    }
+    __device__ inline void zero() {
+        lo = 0;
+        hi = 0;
+    }
+    __device__ inline void operands(float* tb, int li, int lk, int lane, bool /*offdiag*/, float (&a)[4],
+                                    float (&at)[4]) const {
+        const int c = lane / 4, q0 = 4 * (lane % 4);
+        tb[c * kTld + q0] = __uint_as_float(lo << 16);
+        tb[c * kTld + q0 + 1] = __uint_as_float(lo & 0xffff0000u);
+        tb[c * kTld + q0 + 2] = __uint_as_float(hi << 16);
+        tb[c * kTld + q0 + 3] = __uint_as_float(hi & 0xffff0000u);
+        __builtin_amdgcn_wave_barrier();
+#pragma unroll
+        for (int kk = 0; kk < 4; ++kk) {
+            a[kk] = tb[(4 * kk + lk) * kTld + li];
+            at[kk] = tb[li * kTld + 4 * kk + lk];
+        }
+    }
+};
+
+// float32 tiles: an off-diagonal tile (column-major, leading dimension hp, a multiple of 4) comes in
+// one 16-byte load per lane (rows 4 (l % 4) .. + 3 of tile column l / 4) and both operand layouts are
+// read back from LDS; a diagonal tile (packed row groups) takes the generic element loads.
+template <>
+struct SymTile<float, float> {
+    float v[4];
+    template <bool ST>
+    __device__ inline void load(const float* A, int m, int s, int t, int li, int lk, int lane) {
+        if (t < s) {
+            const int r0 = s * kStrip, h = min(kStrip, m - r0), hp = (h + 3) / 4 * 4;
+            const int c = lane / 4, q0 = 4 * (lane % 4);
+            zero();
+            if (q0 < hp) {
+                typedef float f4v __attribute__((ext_vector_type(4)));
+                const f4v* q = reinterpret_cast<const f4v*>(A + sym_strip_offset(s, 4) + (int64_t)(t * kStrip + c) * hp + q0);
+                const f4v x = ST ? __builtin_nontemporal_load(q) : *q;
+                v[0] = x.x;
+                v[1] = x.y;
+                v[2] = x.z;
+                v[3] = x.w;
+            }
+        } else {
+            sym_tile_load<float, float, ST>(A, m, s, t, li, lk, v);
+        }
+    }
+    __device__ inline void zero() {
+#pragma unroll
+        for (int kk = 0; kk < 4; ++kk) v[kk] = 0.0f;
+    }
+    __device__ inline void operands(float* tb, int li, int lk, int lane, bool offdiag, float (&a)[4],
+                                    float (&at)[4]) const {
+        if (offdiag) {
+            const int c = lane / 4, q0 = 4 * (lane % 4);
+#pragma unroll
+            for (int i = 0; i < 4; ++i) tb[c * kTld + q0 + i] = v[i];
+            __builtin_amdgcn_wave_barrier();
+#pragma unroll
+            for (int kk = 0; kk < 4; ++kk) {
+                a[kk] = tb[(4 * kk + lk) * kTld + li];
+                at[kk] = tb[li * kTld + 4 * kk + lk];
+            }
+        } else {
+#pragma unroll
+            for (int kk = 0; kk < 4; ++kk) {
+                a[kk] = v[kk];
+                tb[(4 * kk + lk) * kTld + li] = v[kk];
+            }
+            __builtin_amdgcn_wave_barrier();
+#pragma unroll
+            for (int kk = 0; kk < 4; ++kk) at[kk] = tb[li * kTld + 4 * kk + lk];
+        }
+    }
+};
+
 // the first PD tiles of wave W (tile numbers W, W + 4, ...)
 template <typename T, typename Acc, int NB, int PD, bool ST, int W>
-__device__ inline void sym_wave_prologue(Acc (&buf)[PD][4], const T* A, int m, int ns, int li, int lk) {
+__device__ inline void sym_wave_prologue(SymTile<T, Acc> (&buf)[PD], const T* A, int m, int ns, int li, int lk,
+                                         int lane) {
     constexpr int NTILE = NB * (NB + 1) / 2;
 #pragma unroll
     for (int k = 0; k < PD; ++k) {
         const int i = W + 4 * k;
-        if (i < NTILE && tile_strip(i) < ns) sym_tile_load<T, Acc, ST>(A, m, tile_strip(i), tile_col(i), li, lk, buf[k]);
+        if (i < NTILE && tile_strip(i) < ns) buf[k].template load<ST>(A, m, tile_strip(i), tile_col(i), li, lk, lane);
+        else buf[k].zero();
     }
 }
 
 // the tiles of wave W, PD of them loaded ahead of the one being multiplied
 template <typename T, typename Acc, int NB, int PD, bool ST, int W>
-__device__ inline void sym_wave_tiles(typename Mfma<Acc>::acc_t (&acc)[NB], Acc (&buf)[PD][4], const T* A, int m,
-                                      int ns, int li, int lk, const Acc* s_g, Acc* s_t) {
+__device__ inline void sym_wave_tiles(typename Mfma<Acc>::acc_t (&acc)[NB], SymTile<T, Acc> (&buf)[PD], const T* A,
+                                      int m, int ns, int li, int lk, int lane, const Acc* s_g, Acc* s_t) {
     constexpr int NTILE = NB * (NB + 1) / 2;
-    constexpr int TLD = kStrip + 1;
 #pragma clang loop unroll(full)
     for (int s = 0; s < NB; ++s) {
 #pragma clang loop unroll(full)
@@ -101,22 +226,13 @@ __device__ inline void sym_wave_tiles(typename Mfma<Acc>::acc_t (&acc)[NB], Acc 
             if (i % 4 == W) {
                 const int k = (i - W) / 4;
                 if (s < ns) {
-                    Acc a[4], gr[4];
-#pragma unroll
-                    for (int kk = 0; kk < 4; ++kk) {
-                        a[kk] = buf[k % PD][kk];
-                        gr[kk] = s_g[(t * kStrip + 4 * kk + lk) * kBS + li];
-                    }
                     // L(s, t) G_t into block s and L(s, t)^T G_s into block t (for a diagonal tile
                     // both go to block s: the diagonal block is L_ss + L_ss^T)
-                    Acc* tb = s_t + (k & 1) * kStrip * TLD;
-#pragma unroll
-                    for (int kk = 0; kk < 4; ++kk) tb[(4 * kk + lk) * TLD + li] = a[kk];
-                    __builtin_amdgcn_wave_barrier();
-                    Acc at[4], gc[4];
+                    Acc a[4], at[4], gr[4], gc[4];
+                    buf[k % PD].operands(s_t + (k & 1) * kStrip * kTld, li, lk, lane, t < s, a, at);
 #pragma unroll
                     for (int kk = 0; kk < 4; ++kk) {
-                        at[kk] = tb[li * TLD + 4 * kk + lk];
+                        gr[kk] = s_g[(t * kStrip + 4 * kk + lk) * kBS + li];
                         gc[kk] = s_g[(s * kStrip + 4 * kk + lk) * kBS + li];
                     }
 #pragma unroll
@@ -127,7 +243,7 @@ __device__ inline void sym_wave_tiles(typename Mfma<Acc>::acc_t (&acc)[NB], Acc 
                 }
                 const int i2 = i + 4 * PD;
                 if (i2 < NTILE && tile_strip(i2) < ns)
-                    sym_tile_load<T, Acc, ST>(A, m, tile_strip(i2), tile_col(i2), li, lk, buf[k % PD]);
+                    buf[k % PD].template load<ST>(A, m, tile_strip(i2), tile_col(i2), li, lk, lane);
             }
         }
     }
@@ -142,7 +258,6 @@ __global__ __launch_bounds__(kBlock) void block_apply_sym_kernel(const int32_t* 
                                                                  double* __restrict__ Y,
                                                                  const double* __restrict__ gw) {
     typedef typename Mfma<Acc>::acc_t acc_t;
-    constexpr int TLD = kStrip + 1;
     constexpr int RPP = kBlock / kBS;                                  // rows of G per pass of the workgroup
     extern __shared__ double s_buf[];
     Acc* s_g = reinterpret_cast<Acc*>(s_buf);                          // G: 16 NB rows x kBS columns
@@ -152,15 +267,15 @@ __global__ __launch_bounds__(kBlock) void block_apply_sym_kernel(const int32_t* 
     const int ns = (m + kStrip - 1) / kStrip;
     const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
     const int li = lane & 15, lk = lane >> 4;
-    Acc* s_t = s_g + NB * kStrip * kBS + wave * 2 * kStrip * TLD;     // this wave's transpose buffers
+    Acc* s_t = s_g + NB * kStrip * kBS + wave * 2 * kStrip * kTld;    // this wave's transpose buffers
     const T* A = F + foff[p];
     // the wave's first tiles are in flight during the gather, which they do not need
-    Acc buf[PD][4];
+    SymTile<T, Acc> buf[PD];
     switch (wave) {
-        case 0: sym_wave_prologue<T, Acc, NB, PD, ST, 0>(buf, A, m, ns, li, lk); break;
-        case 1: sym_wave_prologue<T, Acc, NB, PD, ST, 1>(buf, A, m, ns, li, lk); break;
-        case 2: sym_wave_prologue<T, Acc, NB, PD, ST, 2>(buf, A, m, ns, li, lk); break;
-        default: sym_wave_prologue<T, Acc, NB, PD, ST, 3>(buf, A, m, ns, li, lk); break;
+        case 0: sym_wave_prologue<T, Acc, NB, PD, ST, 0>(buf, A, m, ns, li, lk, lane); break;
+        case 1: sym_wave_prologue<T, Acc, NB, PD, ST, 1>(buf, A, m, ns, li, lk, lane); break;
+        case 2: sym_wave_prologue<T, Acc, NB, PD, ST, 2>(buf, A, m, ns, li, lk, lane); break;
+        default: sym_wave_prologue<T, Acc, NB, PD, ST, 3>(buf, A, m, ns, li, lk, lane); break;
     }
     // G = X[S_i, :] (times the DoF weights W_i in the adjoint sweep), all loads issued before the stores
     {
@@ -189,10 +304,10 @@ __global__ __launch_bounds__(kBlock) void block_apply_sym_kernel(const int32_t* 
 #pragma unroll
     for (int b = 0; b < NB; ++b) acc[b] = acc_t{0, 0, 0, 0};
     switch (wave) {
-        case 0: sym_wave_tiles<T, Acc, NB, PD, ST, 0>(acc, buf, A, m, ns, li, lk, s_g, s_t); break;
-        case 1: sym_wave_tiles<T, Acc, NB, PD, ST, 1>(acc, buf, A, m, ns, li, lk, s_g, s_t); break;
-        case 2: sym_wave_tiles<T, Acc, NB, PD, ST, 2>(acc, buf, A, m, ns, li, lk, s_g, s_t); break;
-        default: sym_wave_tiles<T, Acc, NB, PD, ST, 3>(acc, buf, A, m, ns, li, lk, s_g, s_t); break;
+        case 0: sym_wave_tiles<T, Acc, NB, PD, ST, 0>(acc, buf, A, m, ns, li, lk, lane, s_g, s_t); break;
+        case 1: sym_wave_tiles<T, Acc, NB, PD, ST, 1>(acc, buf, A, m, ns, li, lk, lane, s_g, s_t); break;
+        case 2: sym_wave_tiles<T, Acc, NB, PD, ST, 2>(acc, buf, A, m, ns, li, lk, lane, s_g, s_t); break;
+        default: sym_wave_tiles<T, Acc, NB, PD, ST, 3>(acc, buf, A, m, ns, li, lk, lane, s_g, s_t); break;
     }
     // partial results added in wave order into the G buffer (no longer read)
     __syncthreads();

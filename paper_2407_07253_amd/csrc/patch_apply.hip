@@ -376,6 +376,80 @@ __global__ __launch_bounds__(kBlock) void patch_apply_sym_kernel(const int32_t* 
     }
 }
 
+// Levels of small patches (at most kSmallUnits units, i.e. m <= 64): one wave
+// per patch loads every unit of its patch before the residual gather, so a
+// patch costs one memory latency instead of a chain of them.  Unit k adds into
+// partial k % 4 as in patch_apply_sym_kernel, so the bits are the same.
+constexpr int kSmallUnits = 4;
+
+template <typename T, bool NT>
+__global__ __launch_bounds__(kBlock) void patch_apply_sym_small_kernel(const int32_t* __restrict__ order,
+                                                                       const int64_t* __restrict__ pptr,
+                                                                       const int32_t* __restrict__ pdofs,
+                                                                       const int64_t* __restrict__ foff,
+                                                                       const T* __restrict__ F,
+                                                                       const double* __restrict__ r,
+                                                                       const double* __restrict__ gw,
+                                                                       double* __restrict__ Y, int ldbuf) {
+    typedef typename Load16<T>::acc_t Acc;
+    typedef SymShape<T> Sh;
+    constexpr int V = Sh::V, RL = Sh::RL, U = Sh::U, NU = kSmallUnits, NP = kSymParts;
+    extern __shared__ double s_buf[];
+    Acc* s_r = reinterpret_cast<Acc*>(s_buf);
+    Acc* s_y = s_r + ldbuf;
+    const int p = order[blockIdx.x];
+    const int64_t base = pptr[p];
+    const int m = (int)(pptr[p + 1] - base);
+    const T* A = F + foff[p];
+    const int lane = threadIdx.x & (kWave - 1);
+    const int rl = lane % RL, cl = lane / RL;
+    const int ns = (m + kStrip - 1) / kStrip;
+    Acc a[NU][U][V];
+    int su[NU], cu[NU];
+    bool oku[NU];
+    int s = 0, c = 0;
+    bool ok = true;
+#pragma unroll
+    for (int k = 0; k < NU; ++k) {
+        su[k] = s;
+        cu[k] = c;
+        oku[k] = ok;
+        if (ok) {
+            sym_load_unit<T, NT>(A, s, c, m, rl, cl, a[k]);
+            ok = sym_step(s, c, ns, m);
+        }
+    }
+    for (int t = lane; t < m; t += kWave) {
+        const double v = r[pdofs[base + t]];
+        s_r[t] = (Acc)(gw ? gw[base + t] * v : v);
+    }
+    for (int t = lane; t < NP * ldbuf; t += kWave) s_y[t] = (Acc)0;
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < NU; ++k)
+        if (oku[k]) sym_unit<T>(a[k], su[k], cu[k], m, rl, cl, lane, s_r, s_y + (k % NP) * ldbuf);
+    __syncthreads();
+    for (int t = lane; t < m; t += kWave) {
+        Acc sum = s_y[t];
+#pragma unroll
+        for (int q = 1; q < NP; ++q) sum += s_y[q * ldbuf + t];
+        Y[base + t] = (double)sum;
+    }
+}
+
+template <typename T>
+void launch_sym_small(hipStream_t s, const Level& L, const double* r, const double* gw, double* Y) {
+    typedef typename Load16<T>::acc_t Acc;
+    const int ldbuf = (L.max_m + 1) & ~1;
+    const size_t lds = sizeof(Acc) * (size_t)ldbuf * (1 + kSymParts);
+    if (streams_factors(L, L.sym))
+        hipLaunchKernelGGL((patch_apply_sym_small_kernel<T, true>), dim3(L.npatch), dim3(kWave), lds, s, L.order,
+                           L.pptr, L.pdofs, L.fofflp, (const T*)L.factors, r, gw, Y, ldbuf);
+    else
+        hipLaunchKernelGGL((patch_apply_sym_small_kernel<T, false>), dim3(L.npatch), dim3(kWave), lds, s, L.order,
+                           L.pptr, L.pdofs, L.fofflp, (const T*)L.factors, r, gw, Y, ldbuf);
+}
+
 template <typename T, bool PF, int NWV>
 void launch_sym_shape(hipStream_t s, const Level& L, const double* r, const double* gw, double* Y) {
     typedef typename Load16<T>::acc_t Acc;
@@ -390,10 +464,12 @@ void launch_sym_shape(hipStream_t s, const Level& L, const double* r, const doub
     }
 }
 
-// shapes: 0 / 1 four waves without / with prefetch, 2 / 3 one wave without / with prefetch
+// shapes: 0 / 1 four waves without / with prefetch, 2 / 3 one wave without / with prefetch,
+// 4 (levels whose patches have at most 64 DoFs) one wave with every unit loaded ahead
 template <typename T>
 void launch_sym_typed(hipStream_t s, const Level& L, const double* r, const double* gw, double* Y) {
     switch (L.apply_variant) {
+        case 4: launch_sym_small<T>(s, L, r, gw, Y); break;
         case 1: launch_sym_shape<T, true, 4>(s, L, r, gw, Y); break;
         case 2: launch_sym_shape<T, false, 1>(s, L, r, gw, Y); break;
         case 3: launch_sym_shape<T, true, 1>(s, L, r, gw, Y); break;
@@ -403,7 +479,11 @@ void launch_sym_typed(hipStream_t s, const Level& L, const double* r, const doub
 
 }  // namespace
 
-int apply_variant_count(const Level& L) { return L.sym ? 4 : 3; }
+int apply_variant_count(const Level& L) {
+    // a patch of at most 64 DoFs has at most 4 strips of one 64-column unit each
+    if (L.sym) return L.max_m <= 64 ? 5 : 4;
+    return 3;
+}
 
 void launch_patch_apply_sym(hipStream_t s, const Level& L, const double* r, const double* gw, double* Y) {
     if (L.npatch <= 0) return;

@@ -1381,25 +1381,41 @@ void launch_extract(hipStream_t s, const Level& L, double* out) {
 
 int gj_lds_max_m() { return kGjLdsMax; }
 
-void launch_patch_factor(hipStream_t s, const Level& L, double* A) {
+void launch_patch_factor(hipStream_t s, const Level& L, double* A, hipStream_t aux, hipEvent_t ev_fork,
+                         hipEvent_t ev_join) {
     if (L.npatch <= 0) return;
     static_assert(kGjLdsMax == 64, "size classes of gj_class");
     // patches too large for the registers (first in the launch order): panels in
-    // LDS, the matrix in global memory
+    // LDS, the matrix in global memory; on the auxiliary stream when there is one
+    const bool fork = aux && ev_fork && ev_join && L.gj_cnt[0] > 0;
+    if (fork) {
+        (void)hipEventRecord(ev_fork, s);
+        (void)hipStreamWaitEvent(aux, ev_fork, 0);
+    }
     if (L.gj_cnt[0] > 0) {
+        const hipStream_t sb = fork ? aux : s;
         const int ldq = L.gj_max[0];
         const size_t lds = sizeof(double) * (size_t)ldq * kPanel + sizeof(int) * 2 * (size_t)ldq;
         const int R = (ldq + kBlock - 1) / kBlock;
         auto go = [&](auto kernel) {
             if (lds > 64 * 1024)
                 (void)hipFuncSetAttribute((const void*)kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-            hipLaunchKernelGGL(kernel, dim3(L.gj_cnt[0]), dim3(kBlock), lds, s, L.pptr, L.foff, L.order, A, L.ptol,
+            hipLaunchKernelGGL(kernel, dim3(L.gj_cnt[0]), dim3(kBlock), lds, sb, L.pptr, L.foff, L.order, A, L.ptol,
                                L.pdofs, L.pdofs_perm, L.pidx, ldq, L.status);
         };
         if (R <= 1) go(gj_kernel<1>);
         else if (R <= 2) go(gj_kernel<2>);
         else go(gj_kernel<4>);
+        if (fork) (void)hipEventRecord(ev_join, aux);
     }
+    struct Join {
+        bool on;
+        hipStream_t s;
+        hipEvent_t e;
+        ~Join() {
+            if (on) (void)hipStreamWaitEvent(s, e, 0);
+        }
+    } join{fork, s, ev_join};
     // 65..144 DoFs: the matrix in the registers of the workgroup
     int first = L.gj_cnt[0];
     for (int c = 1; c <= 2; ++c) {

@@ -957,7 +957,16 @@ void setup_levels(phmg_ctx ctx, int lo, int hi) {
             }
             {
                 Timed t(ctx, PHMG_K_FACTOR, l, s);
-                launch_patch_factor(s, L, L.work64);
+                // patches above 144 DoFs on the coarse inverse's stream, beside the smaller ones
+                if (nstreams >= 3) {
+                    if (!ctx->fork_ev[0]) {
+                        for (auto& e : ctx->fork_ev)
+                            hipcheck(hipEventCreateWithFlags(&e, hipEventDisableTiming), "hipEventCreate");
+                    }
+                    launch_patch_factor(s, L, L.work64, sst(last), ctx->fork_ev[0], ctx->fork_ev[1]);
+                } else {
+                    launch_patch_factor(s, L, L.work64);
+                }
                 hipcheck(hipGetLastError(), "patch factorisation launch");
             }
         }
@@ -1185,6 +1194,8 @@ void destroy_all(phmg_ctx ctx) {
         (void)hipStreamDestroy(st);
     }
     for (auto e : ctx->sevents) (void)hipEventDestroy(e);
+    for (auto e : ctx->fork_ev)
+        if (e) (void)hipEventDestroy(e);
     if (ctx->status_host) (void)hipHostFree(ctx->status_host);
     for (auto& it : ctx->prof.pending) {
         (void)hipEventDestroy(it.e0);

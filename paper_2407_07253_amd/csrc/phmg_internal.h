@@ -106,9 +106,8 @@ struct Level {
     bool sym = false;                // the stored inverses use the symmetric strip layout
     int32_t* order = nullptr;        // launch order: patches by decreasing size
     // patch inversion kernels by size class, over consecutive ranges of the launch order:
-    // gj_cnt[0] patches inverted with the matrix in global memory (more than 144 DoFs, and on
-    // a level that has such patches every patch of more than 64), gj_cnt[1..2] of 97-144 and
-    // 65-96 DoFs (matrix in registers), gj_cnt[3] of at most 64 (in LDS)
+    // gj_cnt[0] patches inverted with the matrix in global memory (more than 144 DoFs),
+    // gj_cnt[1..2] of 97-144 and 65-96 DoFs (matrix in registers), gj_cnt[3] of at most 64 (in LDS)
     int32_t gj_cnt[4] = {0, 0, 0, 0};
     int32_t gj_max[4] = {0, 0, 0, 0};      // largest patch of each class
     int32_t* sptr = nullptr;         // DoF -> slot map for the scatter (n + 1)
@@ -223,6 +222,7 @@ struct phmg_ctx_s {
     // set-up: one stream per level (default priority), fork / join events and
     // pinned status words
     std::vector<hipStream_t> sstreams;
+    hipEvent_t fork_ev[2] = {nullptr, nullptr};   // large-patch inversion on a second stream
     std::vector<hipEvent_t> sevents;                // [0] fork, [1 + l] join of level l
     int32_t* status_host = nullptr;
     double* gin = nullptr;
@@ -339,19 +339,20 @@ void launch_spmv(hipStream_t s, const DevCsr& A, const double* x, double alpha, 
 void launch_spmv_diff(hipStream_t s, const DevCsr& A1, const double* x1, const DevCsr& A2, const double* x2,
                       double* y);
 void launch_extract(hipStream_t s, const Level& L, double* out);
-// invert every patch matrix of the level in place (stored as (P K_i)^{-1}, see kernels.hip)
-void launch_patch_factor(hipStream_t s, const Level& L, double* A);
+// invert every patch matrix of the level in place (stored as (P K_i)^{-1}, see kernels.hip).
+// aux (optional): a second stream for the patches above 144 DoFs, forked from s with ev_fork and
+// joined back into s with ev_join, so they run beside the register-resident kernel
+void launch_patch_factor(hipStream_t s, const Level& L, double* A, hipStream_t aux = nullptr,
+                         hipEvent_t ev_fork = nullptr, hipEvent_t ev_join = nullptr);
 int gj_lds_max_m();   // largest patch the LDS-resident inversion takes
 int gj_reg_max_m();   // largest patch the register-resident inversion takes (patch_factor.hip)
 // register-resident inversion of the launch-order range [first, first + count), patches of at most max_m DoFs
 void launch_patch_factor_reg(hipStream_t s, const Level& L, double* A, int first, int count, int max_m);
-// size class of a patch for the inversion kernels (index into Level::gj_cnt) on a level
-// whose largest patch has max_m DoFs.  The size classes run one after another: on a level
-// with a few patches too large for the registers, their serial elimination chains would
-// add to the register kernel's time, so such a level inverts every patch above 64 DoFs
-// with the global-memory kernel, whose many resident workgroups hide the chains.
-inline int gj_class(int64_t m, int64_t max_m) {
-    if (m > 144 || (m > 64 && max_m > 144)) return 0;
+// size class of a patch for the inversion kernels (index into Level::gj_cnt): 0 above 144 DoFs
+// (global-memory kernel), 1 for 97-144 and 2 for 65-96 (register-resident kernel), 3 up to 64
+// (LDS-resident kernel).  (max_m is kept for callers; the classes depend on m alone.)
+inline int gj_class(int64_t m, int64_t /*max_m*/) {
+    if (m > 144) return 0;
     return m > 96 ? 1 : (m > 64 ? 2 : 3);
 }
 void launch_convert_patches(hipStream_t s, const Level& L, const double* src, void* dst);

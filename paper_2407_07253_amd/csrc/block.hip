@@ -85,9 +85,11 @@ float time_launch(hipStream_t s, hipEvent_t e0, hipEvent_t e1, const std::functi
     return best;
 }
 
-// First-use autotuner of the block path: entries in flight per row of every
-// block SpMM, and the block patch-solve shape of every level for the level's
-// precision (HIP events, best of three launches per candidate).
+// First-use autotuner of the block path: the shape of every block SpMM (groups
+// of 16 lanes per row with 1, 2 or 4 entries in flight, or 2 / 4 lanes per row
+// with 8 / 4 columns each; row ranges plain or XCD-contiguous), and the block
+// patch-solve shape of every level for the level's precision (HIP events, best
+// of three launches per candidate).
 void tune_block(phmg_ctx ctx) {
     hipStream_t s = ctx->stream;
     hipEvent_t e0, e1;
@@ -97,7 +99,9 @@ void tune_block(phmg_ctx ctx) {
         if (A.btuned || A.nrows == 0) return;
         int best = 1;
         bool best_x = false;
+        int best_q = 0;
         float best_ms = 1e30f;
+        A.bquad = 0;
         for (int xm = 0; xm < 2; ++xm)
             for (int g = 1; g <= 4; g *= 2) {
                 A.bgroup = g;
@@ -110,6 +114,20 @@ void tune_block(phmg_ctx ctx) {
                 }
             }
         A.bgroup = best;
+        A.bxcd = best_x;
+        for (int q = 2; q <= 4; q += 2)
+            for (int xm = 0; xm < 2; ++xm) {
+                A.bquad = q;
+                A.bxcd = xm != 0;
+                const float ms = time_launch(s, e0, e1, [&] { launch_spmm(s, A, X, 1.0, nullptr, 0.0, Y); });
+                A.bquad = 0;
+                if (ms < best_ms) {
+                    best_ms = ms;
+                    best_q = q;
+                    best_x = xm != 0;
+                }
+            }
+        A.bquad = best_q;
         A.bxcd = best_x;
         A.btuned = true;
     };

@@ -5,7 +5,8 @@
 // right-hand side c, so the kBS values of one DoF are one 128-byte line: every
 // CSR entry and every patch DoF gathers a full line.
 //
-//  * spmm_kernel          Y = alpha K X + beta Z (residuals, transfers)
+//  * spmm_kernel,         Y = alpha K X + beta Z (residuals, transfers): 16
+//    spmm_quad_kernel     lanes per row, or 2 / 4 lanes of 8 / 4 columns each
 //  * block_apply_kernel   Y_i = K_i^{-1} X[S_i, :] for every patch as a dense
 //                         m x m by m x 16 product on MFMA (f64 16x16x4 for
 //                         float64 factors, f32 16x16x4 with float32
@@ -90,6 +91,84 @@ __global__ __launch_bounds__(kBlock) void spmm_kernel(int32_t nrows, const int32
             if (Z) out += beta * Z[row * kBS + c];
             Y[row * kBS + c] = out;
         }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Y = alpha K X + beta Z with LPR = 4 (or 2) lanes per row and 16 / LPR columns
+// of X per lane (64 / LPR rows per wave; a row of X is read in 32-byte pieces).
+// The lanes of a row load 4 LPR entries at once (entry k0 + LPR j + l in lane l)
+// and pass them round with quad DPP broadcasts (no LDS); each column sums the
+// row's entries in row order, as spmm_kernel<1, false> does, so the bits are
+// that kernel's.
+// ---------------------------------------------------------------------------
+template <int LPR, int T>
+__device__ inline int row_bcast(int x) {
+    // lane T of each group of LPR lanes inside a quad, to the whole group
+    constexpr int C = LPR == 4 ? (T | T << 2 | T << 4 | T << 6) : (T | T << 2 | (T + 2) << 4 | (T + 2) << 6);
+    return __builtin_amdgcn_update_dpp(0, x, C, 0xF, 0xF, false);
+}
+template <int LPR, int T>
+__device__ inline double row_bcast_d(double x) {
+    const int lo = row_bcast<LPR, T>(__double2loint(x)), hi = row_bcast<LPR, T>(__double2hiint(x));
+    return __hiloint2double(hi, lo);
+}
+typedef double dq4 __attribute__((ext_vector_type(4)));
+
+template <int LPR, bool XM>
+__global__ __launch_bounds__(kBlock) void spmm_quad_kernel(int32_t nrows, const int32_t* __restrict__ rowptr,
+                                                           const int32_t* __restrict__ col,
+                                                           const double* __restrict__ val,
+                                                           const double* __restrict__ X, double alpha, const double* Z,
+                                                           double beta, double* Y) {
+    static_assert(LPR == 2 || LPR == 4, "lanes per row");
+    constexpr int CPL = kBS / LPR, NQ = CPL / 4, CH = 4 * LPR;   // columns per lane, 32-byte pieces, chunk
+    const int l = threadIdx.x & (LPR - 1);         // columns CPL l .. CPL l + CPL - 1
+    const int64_t sub = (logical_block(XM) * blockDim.x + threadIdx.x) / LPR;
+    const int64_t nsub = ((int64_t)gridDim.x * blockDim.x) / LPR;
+    for (int64_t row = sub; row < nrows; row += nsub) {
+        const int beg = rowptr[row], end = rowptr[row + 1];
+        dq4 s[NQ];
+#pragma unroll
+        for (int h = 0; h < NQ; ++h) s[h] = dq4{0.0, 0.0, 0.0, 0.0};
+        for (int k0 = beg; k0 < end; k0 += CH) {
+            const int cnt = min(CH, end - k0);
+            int ck[4];
+            double vk[4];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int k = LPR * j + l;
+                ck[j] = k < cnt ? col[k0 + k] : 0;
+                vk[j] = k < cnt ? val[k0 + k] : 0.0;
+            }
+            auto step = [&](int cc, double vv) {
+                const double* xr = X + (int64_t)cc * kBS + CPL * l;
+#pragma unroll
+                for (int h = 0; h < NQ; ++h) {
+                    const dq4 x = *reinterpret_cast<const dq4*>(xr + 4 * h);
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) s[h][e] += vv * x[e];
+                }
+            };
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                if (LPR * j + 0 < cnt) step(row_bcast<LPR, 0>(ck[j]), row_bcast_d<LPR, 0>(vk[j]));
+                if (LPR * j + 1 < cnt) step(row_bcast<LPR, 1>(ck[j]), row_bcast_d<LPR, 1>(vk[j]));
+                if constexpr (LPR == 4) {
+                    if (LPR * j + 2 < cnt) step(row_bcast<LPR, 2>(ck[j]), row_bcast_d<LPR, 2>(vk[j]));
+                    if (LPR * j + 3 < cnt) step(row_bcast<LPR, 3>(ck[j]), row_bcast_d<LPR, 3>(vk[j]));
+                }
+            }
+        }
+#pragma unroll
+        for (int h = 0; h < NQ; ++h)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int64_t o = row * kBS + CPL * l + 4 * h + e;
+                double out = alpha * s[h][e];
+                if (Z) out += beta * Z[o];
+                Y[o] = out;
+            }
     }
 }
 
@@ -442,6 +521,23 @@ __global__ __launch_bounds__(kBlock) void deinterleave_kernel(int64_t n, int nrh
 void launch_spmm(hipStream_t s, const DevCsr& A, const double* X, double alpha, const double* Z, double beta,
                  double* Y) {
     if (A.nrows <= 0) return;
+    if (A.bquad) {
+        // bquad lanes per row (2 or 4), 16 / bquad columns of X per lane
+        int grid = grid_for((int64_t)A.nrows * A.bquad, kBlock);
+        if (A.bxcd) grid = (grid + 7) / 8 * 8;
+        auto go = [&](auto kernel) {
+            hipLaunchKernelGGL(kernel, dim3(grid), dim3(kBlock), 0, s, A.nrows, A.rowptr, A.col, A.val, X, alpha, Z,
+                               beta, Y);
+        };
+        if (A.bquad == 2) {
+            if (A.bxcd) go(spmm_quad_kernel<2, true>);
+            else go(spmm_quad_kernel<2, false>);
+        } else {
+            if (A.bxcd) go(spmm_quad_kernel<4, true>);
+            else go(spmm_quad_kernel<4, false>);
+        }
+        return;
+    }
     const int gn = A.bgroup == 2 || A.bgroup == 4 ? A.bgroup : 1;
     int grid = grid_for((int64_t)A.nrows * kBS * gn, kBlock);
     if (A.bxcd) grid = (grid + 7) / 8 * 8;

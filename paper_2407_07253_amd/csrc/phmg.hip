@@ -558,7 +558,7 @@ std::vector<uint64_t> phmg::graph_signature(phmg_ctx ctx) {
         p(A.val);
         p(A.rblk);
         u((uint64_t)A.group | (uint64_t)A.xcd << 8 | (uint64_t)A.rowblock << 9 | (uint64_t)A.unroll << 10 |
-          (uint64_t)A.bgroup << 16 | (uint64_t)A.bxcd << 24);
+          (uint64_t)A.bgroup << 16 | (uint64_t)A.bxcd << 24 | (uint64_t)A.bquad << 25);
     };
     const phmg_cycle_opts& o = ctx->opts;
     u((uint64_t)o.nu_p | (uint64_t)o.nu_h << 16 | (uint64_t)o.n_v << 32 | (uint64_t)o.n_plevels << 48);

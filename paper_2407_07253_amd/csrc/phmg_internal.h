@@ -74,6 +74,8 @@ struct DevCsr {
     int unroll = 4;                  // CSR SpMV: entries in flight per lane (4 or 8; autotuned)
     int bgroup = 1;                  // entries in flight per row in the block SpMM (autotuned on first use)
     bool bxcd = false;               // XCD-contiguous row ranges in the block SpMM (autotuned)
+    int bquad = 0;                   // block SpMM with bquad (2 or 4) lanes per row, 16 / bquad columns of X
+                                     // per lane, or 0: bgroup groups of 16 lanes per row (autotuned)
     bool btuned = false;
 };
 

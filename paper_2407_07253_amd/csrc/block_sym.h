@@ -228,13 +228,14 @@ __device__ inline void sym_wave_tiles(typename Mfma<Acc>::acc_t (&acc)[NB], SymT
                 if (s < ns) {
                     // L(s, t) G_t into block s and L(s, t)^T G_s into block t (for a diagonal tile
                     // both go to block s: the diagonal block is L_ss + L_ss^T)
+                    // the G operands first: their LDS reads overlap the transpose round trip
                     Acc a[4], at[4], gr[4], gc[4];
-                    buf[k % PD].operands(s_t + (k & 1) * kStrip * kTld, li, lk, lane, t < s, a, at);
 #pragma unroll
                     for (int kk = 0; kk < 4; ++kk) {
                         gr[kk] = s_g[(t * kStrip + 4 * kk + lk) * kBS + li];
                         gc[kk] = s_g[(s * kStrip + 4 * kk + lk) * kBS + li];
                     }
+                    buf[k % PD].operands(s_t + (k & 1) * kStrip * kTld, li, lk, lane, t < s, a, at);
 #pragma unroll
                     for (int kk = 0; kk < 4; ++kk) {
                         acc[s] = Mfma<Acc>::step(a[kk], gr[kk], acc[s]);

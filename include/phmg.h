@@ -352,7 +352,9 @@ phmg_status phmg_set_block_variant(phmg_ctx ctx, int level, int variant);
  * each XCD contiguous; 12: row blocks (at most 32 rows and 1024 nonzeros per
  * workgroup, products staged in LDS, 8 lanes per row), available when no row
  * has more than 1024 nonzeros; 13-16: CSR with 4, 8, 16, 32 lanes per row and
- * 8 (instead of 4) entries in flight per lane.  Variants differ only in summation order.  Kept
+ * 8 (instead of 4) entries in flight per lane; 17-19: CSR with 4, 8, 16 lanes
+ * per row and 4 consecutive entries per lane (16-byte index and value loads).
+ * Variants differ only in summation order.  Kept
  * until the next override; for tests and tuning studies.  The adjoint cycle
  * always uses the two-step form with K^T. */
 phmg_status phmg_set_spmv_variant(phmg_ctx ctx, int level, int matrix, int variant);

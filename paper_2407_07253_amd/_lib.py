@@ -117,7 +117,7 @@ _set_variant = _sig("phmg_set_apply_variant", C.c_int, [C.c_void_p, C.c_int, C.c
 _set_storage = _sig("phmg_set_patch_storage", C.c_int, [C.c_void_p, C.c_int, C.c_int])
 _set_spmv = _sig("phmg_set_spmv_variant", C.c_int, [C.c_void_p, C.c_int, C.c_int, C.c_int])
 _set_block = _sig("phmg_set_block_variant", C.c_int, [C.c_void_p, C.c_int, C.c_int])
-SPMV_VARIANTS = 17
+SPMV_VARIANTS = 20
 STORAGE = {"auto": 0, "general": 1}
 MAX_RHS = 16
 

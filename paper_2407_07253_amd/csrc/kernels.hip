@@ -101,6 +101,48 @@ __global__ __launch_bounds__(kBlock) void spmv_kernel(int32_t nrows, const int32
 }
 
 // ---------------------------------------------------------------------------
+// CSR SpMV with G lanes per row and 4 consecutive entries per lane: the row's
+// range is widened down to a multiple of 4, so lane l's entries k0 + 4 (l + G j)
+// .. + 3 come in one 16-byte index load and two 16-byte value loads (the
+// arrays carry 4 padding entries; entries outside the row add +0).  Each lane
+// adds its entries in order, then the G partial sums are combined.
+// ---------------------------------------------------------------------------
+template <int G>
+__global__ __launch_bounds__(kBlock) void spmv_vec_kernel(int32_t nrows, const int32_t* __restrict__ rowptr,
+                                                          const int32_t* __restrict__ col,
+                                                          const double* __restrict__ val,
+                                                          const double* __restrict__ x, double alpha, const double* z,
+                                                          double beta, double* y) {
+    typedef int i4 __attribute__((ext_vector_type(4)));
+    typedef double dv2 __attribute__((ext_vector_type(2)));
+    const int lane = threadIdx.x & (G - 1);
+    const int64_t sub = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / G;
+    const int64_t nsub = ((int64_t)gridDim.x * blockDim.x) / G;
+    for (int64_t row = sub; row < nrows; row += nsub) {
+        const int beg = rowptr[row], end = rowptr[row + 1];
+        double s = 0.0;
+        for (int k = (beg & ~3) + 4 * lane; k < end; k += 4 * G) {
+            const i4 c = *reinterpret_cast<const i4*>(col + k);
+            const dv2 va = *reinterpret_cast<const dv2*>(val + k);
+            const dv2 vb = *reinterpret_cast<const dv2*>(val + k + 2);
+            const double v[4] = {va.x, va.y, vb.x, vb.y};
+            double xv[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) xv[u] = k + u >= beg && k + u < end ? x[c[u]] : 0.0;
+#pragma unroll
+            for (int u = 0; u < 4; ++u) s += (k + u >= beg && k + u < end ? v[u] : 0.0) * xv[u];
+        }
+#pragma unroll
+        for (int off = G / 2; off > 0; off >>= 1) s += __shfl_xor(s, off, G);
+        if (lane == 0) {
+            double out = alpha * s;
+            if (z) out += beta * z[row];
+            y[row] = out;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
 // y = A1 x1 - A2 x2 (same rows), G lanes per row: the restricted residual
 // R b - (R K) x of the cycle in one pass over the coarse rows.  Each row's two
 // sums are formed as in spmv_kernel and subtracted at the end.
@@ -1303,6 +1345,22 @@ void launch_spmv(hipStream_t s, const DevCsr& A, const double* x, double alpha, 
         hipLaunchKernelGGL(rowblock_spmv_kernel, dim3(A.nrb), dim3(kBlock), 0, s, A.rblk, A.rowptr, A.col, A.val, x,
                            alpha, z, beta, y);
         return;
+    }
+    if (A.vec) {
+        const int gridv = grid_for((int64_t)A.nrows * A.group, kBlock);
+        switch (A.group) {
+#define PHMG_SPMVV_CASE(G)                                                                                     \
+    case G:                                                                                                    \
+        hipLaunchKernelGGL((spmv_vec_kernel<G>), dim3(gridv), dim3(kBlock), 0, s, A.nrows, A.rowptr, A.col, A.val, \
+                           x, alpha, z, beta, y);                                                              \
+        return;
+            PHMG_SPMVV_CASE(4)
+            PHMG_SPMVV_CASE(8)
+            PHMG_SPMVV_CASE(16)
+#undef PHMG_SPMVV_CASE
+            default:
+                break;
+        }
     }
     if (A.unroll == 8) {
         const int grid8 = grid_for((int64_t)A.nrows * A.group, kBlock);

@@ -50,8 +50,15 @@ DevCsr upload_csr(phmg_ctx ctx, int32_t nrows, int32_t ncols, const std::vector<
     d.ncols = ncols;
     d.nnz = (int64_t)ci.size();
     d.rowptr = upload(ctx, rp.data(), (int64_t)rp.size());
-    d.col = upload(ctx, ci.data(), (int64_t)ci.size());
-    d.val = upload(ctx, v.data(), (int64_t)v.size());
+    // 4 zero entries past the end: the 16-byte loads of the vector SpMV may read them
+    {
+        std::vector<int32_t> cp(ci);
+        std::vector<double> vp(v);
+        cp.resize(ci.size() + 4, 0);
+        vp.resize(v.size() + 4, 0.0);
+        d.col = upload(ctx, cp.data(), (int64_t)cp.size());
+        d.val = upload(ctx, vp.data(), (int64_t)vp.size());
+    }
     const double avg = nrows > 0 ? (double)d.nnz / nrows : 0.0;
     int g = 2;
     while (g < 64 && g * 3 < avg) g *= 2;   // about 3 nonzeros per lane
@@ -557,7 +564,7 @@ std::vector<uint64_t> phmg::graph_signature(phmg_ctx ctx) {
         p(A.col);
         p(A.val);
         p(A.rblk);
-        u((uint64_t)A.group | (uint64_t)A.xcd << 8 | (uint64_t)A.rowblock << 9 | (uint64_t)A.unroll << 10 |
+        u((uint64_t)A.group | (uint64_t)A.xcd << 8 | (uint64_t)A.rowblock << 9 | (uint64_t)A.unroll << 10 | (uint64_t)A.vec << 15 |
           (uint64_t)A.bgroup << 16 | (uint64_t)A.bxcd << 24 | (uint64_t)A.bquad << 25);
     };
     const phmg_cycle_opts& o = ctx->opts;
@@ -702,13 +709,19 @@ void precond(phmg_ctx ctx, const double* b, double* x, bool transpose) {
 // SpMV kernel variants: 0-5 CSR with 2, 4, ..., 64 lanes per row, 6-11 the same
 // with XCD-contiguous row ranges, 12 the row-block kernel (when the matrix has
 // row blocks), 13-16 CSR with 4, 8, 16, 32 lanes per row and 8 entries in
-// flight per lane.
-constexpr int kSpmvVariants = 17;
+// flight per lane, 17-19 CSR with 4, 8, 16 lanes per row and 4 consecutive
+// entries per lane (16-byte loads).
+constexpr int kSpmvVariants = 20;
 bool spmv_variant_ok(const DevCsr& A, int v) { return v >= 0 && v < kSpmvVariants && (v != 12 || A.nrb > 0); }
 void set_spmv_variant(DevCsr& A, int v) {
     A.rowblock = v == 12;
     A.unroll = 4;
-    if (v < 12) {
+    A.vec = false;
+    if (v >= 17) {
+        A.group = 4 << (v - 17);
+        A.xcd = false;
+        A.vec = true;
+    } else if (v < 12) {
         A.group = 2 << (v % 6);
         A.xcd = v >= 6;
     } else if (v > 12) {
@@ -721,6 +734,7 @@ int spmv_variant_of(const DevCsr& A) {
     if (A.rowblock) return 12;
     int lg = 0;
     while ((2 << lg) < A.group) ++lg;
+    if (A.vec) return 17 + (lg - 1);
     if (A.unroll == 8) return 13 + (lg - 1);
     return lg + (A.xcd ? 6 : 0);
 }
@@ -743,6 +757,7 @@ void tune_spmv(phmg_ctx ctx, DevCsr& A, const double* x, double* y) {
         A.xcd = false;
         A.rowblock = false;
         A.unroll = 4;
+        A.vec = false;
         A.tuned = true;
         return;
     }

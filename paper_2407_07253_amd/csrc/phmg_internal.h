@@ -72,6 +72,7 @@ struct DevCsr {
     int32_t* rblk = nullptr;         // nrb + 1 block boundaries (row indices)
     bool rowblock = false;           // SpMV kernel: row-block (else CSR with `group` lanes per row); autotuned
     int unroll = 4;                  // CSR SpMV: entries in flight per lane (4 or 8; autotuned)
+    bool vec = false;                // CSR SpMV with 4 consecutive entries per lane (16-byte loads; autotuned)
     int bgroup = 1;                  // entries in flight per row in the block SpMM (autotuned on first use)
     bool bxcd = false;               // XCD-contiguous row ranges in the block SpMM (autotuned)
     int bquad = 0;                   // block SpMM with bquad (2 or 4) lanes per row, 16 / bquad columns of X

@@ -255,9 +255,10 @@ __global__ __launch_bounds__(kBlock) void rowblock_spmv_kernel(const int32_t* __
 // Patch extraction: one workgroup per patch; column-major m x m output.  The
 // patch rows are assembled kExtractRows at a time in an LDS tile (row a of the
 // patch matrix = row pdofs[a] of K restricted to the patch DoFs, positions
-// found by binary search in the sorted DoF list), and each tile is written out
-// column by column, kExtractRows consecutive entries of a column per store
-// run: every output byte is written once, with no separate zero fill.
+// found by binary search in the sorted DoF list; 16 lanes per row, so the 16
+// rows of a tile are searched at once), and each tile is written out column by
+// column, kExtractRows consecutive entries of a column per store run: every
+// output byte is written once, with no separate zero fill.
 // ---------------------------------------------------------------------------
 constexpr int kExtractRows = 16;
 
@@ -282,11 +283,12 @@ __global__ __launch_bounds__(kBlock) void extract_kernel(const int64_t* __restri
         const int h = min(kExtractRows, m - a0);
         for (int e = threadIdx.x; e < kExtractRows * m; e += blockDim.x) s_tile[e] = 0.0;
         __syncthreads();
-        for (int q = wave; q < h; q += kBlock / kWave) {
+        // 16 lanes per row, four rows per wave: a tile's rows are all in flight at once
+        for (int q = 4 * wave + (lane >> 4); q < h; q += 4 * (kBlock / kWave)) {
             const int g = s_dofs[a0 + q];
             const int end = rowptr[g + 1];
             double rsum = 0.0;
-            for (int k = rowptr[g] + lane; k < end; k += kWave) {
+            for (int k = rowptr[g] + (lane & 15); k < end; k += 16) {
                 const int c = col[k];
                 int lo = 0, hi = m;
                 while (lo < hi) {
@@ -298,7 +300,7 @@ __global__ __launch_bounds__(kBlock) void extract_kernel(const int64_t* __restri
                     rsum += fabs(val[k]);
                 }
             }
-            for (int off = kWave / 2; off > 0; off >>= 1) rsum += __shfl_xor(rsum, off);
+            for (int off = 8; off > 0; off >>= 1) rsum += __shfl_xor(rsum, off, 16);
             rmax = fmax(rmax, rsum);
         }
         __syncthreads();
@@ -308,6 +310,8 @@ __global__ __launch_bounds__(kBlock) void extract_kernel(const int64_t* __restri
         }
         __syncthreads();
     }
+    rmax = fmax(rmax, __shfl_xor(rmax, 16));
+    rmax = fmax(rmax, __shfl_xor(rmax, 32));
     if (lane == 0) s_max[wave] = rmax;
     __syncthreads();
     if (threadIdx.x == 0)

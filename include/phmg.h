@@ -359,6 +359,17 @@ phmg_status phmg_set_block_variant(phmg_ctx ctx, int level, int variant);
  * always uses the two-step form with K^T. */
 phmg_status phmg_set_spmv_variant(phmg_ctx ctx, int level, int matrix, int variant);
 
+/* Override the autotuner's kernel shape of one block SpMM (the residuals and
+ * transfers of the multi-right-hand-side path; matrix 0: K_level, 1: P_level,
+ * 2: R_level; the coarsest level has only K).  Variants 0-2: 16 lanes per row
+ * (one per system) with 1, 2 or 4 groups of 16 lanes per row; 3-5: the same
+ * with the rows of each XCD contiguous; 6 / 7: 4 / 2 lanes per row with 4 / 8
+ * systems per lane; 8 / 9: the same with XCD-contiguous rows.  Variants 0, 3
+ * and 6-9 add every row's entries in row order for each system and give the
+ * same bits; 1, 2, 4, 5 differ from them in rounding.  Kept until the next
+ * override; for tests and tuning studies. */
+phmg_status phmg_set_spmm_variant(phmg_ctx ctx, int level, int matrix, int variant);
+
 /* Optional per-kernel, per-level timing with HIP events recorded on the
  * context stream around every launch of the selected kernels (off by
  * default).  kernel_mask has bit k set for kernel id k (0 = off).  Each timed

@@ -116,6 +116,7 @@ _fbf_destroy = _sig("phmg_fbf_destroy", C.c_int, [C.c_void_p])
 _set_variant = _sig("phmg_set_apply_variant", C.c_int, [C.c_void_p, C.c_int, C.c_int])
 _set_storage = _sig("phmg_set_patch_storage", C.c_int, [C.c_void_p, C.c_int, C.c_int])
 _set_spmv = _sig("phmg_set_spmv_variant", C.c_int, [C.c_void_p, C.c_int, C.c_int, C.c_int])
+_set_spmm = _sig("phmg_set_spmm_variant", C.c_int, [C.c_void_p, C.c_int, C.c_int, C.c_int])
 _set_block = _sig("phmg_set_block_variant", C.c_int, [C.c_void_p, C.c_int, C.c_int])
 SPMV_VARIANTS = 20
 STORAGE = {"auto": 0, "general": 1}
@@ -128,7 +129,8 @@ EXPORTED = ["phmg_hierarchy_create", "phmg_hierarchy_destroy", "phmg_relax_setup
             "phmg_relax_apply_transposed", "phmg_vcycle_transposed", "phmg_fgmres_solve_transposed",
             "phmg_set_sensitivities", "phmg_forcing_rhs", "phmg_gradients",
             "phmg_fbf_create", "phmg_fbf_apply", "phmg_fbf_fgmres_solve", "phmg_fbf_destroy",
-            "phmg_set_apply_variant", "phmg_set_patch_storage", "phmg_set_spmv_variant", "phmg_set_block_variant",
+            "phmg_set_apply_variant", "phmg_set_patch_storage", "phmg_set_spmv_variant", "phmg_set_spmm_variant",
+            "phmg_set_block_variant",
             "phmg_vcycle_batched_transposed", "phmg_fgmres_solve_batched_transposed",
             "phmg_relax_apply_noalloc", "phmg_set_kernel_vector", "phmg_project_kernel", "phmg_last_error"]
 NOALLOC_MAX_DOUBLES = 4 << 20
@@ -305,6 +307,10 @@ class Hierarchy:
         """Override the autotuned SpMV kernel of K / P / R on a level, or with "RK" the restricted
         residual's form (0 two-step, 1-6 fused with 2..64 lanes); results differ only in rounding."""
         _check(_set_spmv(self._h, level, {"K": 0, "P": 1, "R": 2, "RK": 3}[matrix], variant))
+
+    def set_spmm_variant(self, level: int, matrix: str, variant: int):
+        """Override the autotuned block SpMM shape of K / P / R on a level (0-9, see the header)."""
+        _check(_set_spmm(self._h, level, {"K": 0, "P": 1, "R": 2}[matrix], variant))
 
     def set_patch_storage(self, level: int, storage: str):
         """"auto" (symmetric strip layout when K_l is symmetric to rounding) or "general"."""

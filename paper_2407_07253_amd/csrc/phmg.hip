@@ -1841,6 +1841,29 @@ phmg_status phmg_set_spmv_variant(phmg_ctx ctx, int level, int matrix, int varia
     });
 }
 
+phmg_status phmg_set_spmm_variant(phmg_ctx ctx, int level, int matrix, int variant) {
+    return guarded([&]() -> phmg_status {
+        if (!ctx) fail(PHMG_EINVAL, "null context");
+        const int last = (int)ctx->L.size() - 1;
+        if (level < 0 || level > last) fail(PHMG_EINVAL, "level out of range");
+        if (matrix < 0 || matrix > 2 || (matrix > 0 && level == last)) fail(PHMG_EINVAL, "matrix out of range");
+        if (variant < 0 || variant > 9) fail(PHMG_EINVAL, "variant out of range");
+        Level& L = ctx->L[level];
+        DevCsr& A = matrix == 0 ? L.K : (matrix == 1 ? L.P : L.R);
+        if (variant < 6) {
+            A.bquad = 0;
+            A.bgroup = 1 << (variant % 3);
+            A.bxcd = variant >= 3;
+        } else {
+            A.bquad = (variant - 6) % 2 == 0 ? 4 : 2;
+            A.bxcd = variant >= 8;
+        }
+        A.btuned = true;
+        invalidate_graph(ctx);
+        return PHMG_OK;
+    });
+}
+
 phmg_status phmg_profile_enable(phmg_ctx ctx, unsigned kernel_mask) {
     return guarded([&]() -> phmg_status {
         if (!ctx) fail(PHMG_EINVAL, "null context");

@@ -304,3 +304,49 @@ def test_block_variants_bit_identical(prec, storage):
         with pytest.raises(PhmgError):
             H.set_block_variant(l, nv)
     H.close()
+
+
+def test_every_block_spmm_shape_gives_the_same_sweep_and_cycle():
+    """Every block SpMM shape (16 lanes per row with 1, 2 or 4 groups of entries in flight, 4 or 2
+    lanes per row with 4 or 8 systems each; plain or XCD-contiguous rows), forced on K, P and R of
+    every level: the shapes that add each row's entries in row order (0, 3, 6-9) give the same
+    bits for a batched sweep and a batched V-cycle, the others agree to rounding (1e-12
+    relative), and shape 0 matches the oracle's sweep.  cfg2_r1 rows have 20-200 entries, so
+    every shape's chunks end in ragged tails."""
+    from paper_2407_07253_amd._lib import Hierarchy, PhmgError
+    fh = frontend.build_hierarchy("cfg2_r1")
+    H = Hierarchy.from_frontend(fh)
+    H.setup()
+    ol, od, oopts, ob = oproblems.build("cfg2_r1", forcing="mms", nrhs=1)
+    omg.setup(ol, oopts)
+    nl = len(fh.levels)
+    rng = np.random.default_rng(29)
+    nrhs = 5
+    n0 = fh.levels[0].n
+    B, X = rng.standard_normal((nrhs, n0)), rng.standard_normal((nrhs, n0))
+    sweeps, cycles = {}, {}
+    for v in range(10):
+        for l in range(nl):
+            H.set_spmm_variant(l, "K", v)
+            if l < nl - 1:
+                H.set_spmm_variant(l, "P", v)
+                H.set_spmm_variant(l, "R", v)
+        Xg = _dev(X)
+        H.relax_apply_batched(0, _dev(B), Xg, 2)
+        sweeps[v] = _host(Xg)
+        Xc = _dev(np.zeros((nrhs, n0)))
+        H.vcycle_batched(_dev(B), Xc)
+        cycles[v] = _host(Xc)
+    for v in (3, 6, 7, 8, 9):
+        assert np.array_equal(sweeps[v], sweeps[0]), v
+        assert np.array_equal(cycles[v], cycles[0]), v
+    for v in (1, 2, 4, 5):
+        assert _rel(sweeps[v], sweeps[0]) <= 1e-12, (v, _rel(sweeps[v], sweeps[0]))
+        assert _rel(cycles[v], cycles[0]) <= 1e-12, (v, _rel(cycles[v], cycles[0]))
+    worst = max(_rel(sweeps[0][c], omg._relax(ol[0], oopts, B[c], X[c], 2, False)) for c in range(nrhs))
+    assert worst <= 1e-11, worst
+    with pytest.raises(PhmgError):
+        H.set_spmm_variant(0, "K", 10)
+    with pytest.raises(PhmgError):
+        H.set_spmm_variant(nl - 1, "P", 0)
+    H.close()

@@ -345,12 +345,13 @@ __global__ __launch_bounds__(kBlock) void extract_kernel(const int64_t* __restri
 //   A operand A[l % 16][l / 16], B operand B[l / 16][l % 16],
 //   C/D element D[l / 16 + 4 v][l % 16].
 // ---------------------------------------------------------------------------
-// 16 x 16 accumulator tiles of a column block updated together: one keeps the
-// register count, and so the number of resident waves, highest (measured
-// faster than two or four on the 64..210-DoF patches of the P4/P3 level)
-constexpr int kGjTiles = 1;
-
-template <int R>
+// kGjTiles: 16 x 16 accumulator tiles of a column block updated together.  One
+// keeps the register count, and so the number of resident waves, highest
+// (measured faster than two or four on the 64..210-DoF patches of the P4/P3
+// level); patches above 256 DoFs (two or more rows per thread) take four, whose
+// loads in flight shorten the update's per-tile latency chain (cfg4's 362-DoF
+// patches: 51.6 -> 47.9 ms).
+template <int R, int kGjTiles>
 __global__ __launch_bounds__(kBlock) void gj_kernel(const int64_t* __restrict__ pptr,
                                                     const int64_t* __restrict__ foff,
                                                     const int32_t* __restrict__ order, double* __restrict__ F,
@@ -1465,9 +1466,9 @@ void launch_patch_factor(hipStream_t s, const Level& L, double* A, hipStream_t a
             hipLaunchKernelGGL(kernel, dim3(L.gj_cnt[0]), dim3(kBlock), lds, sb, L.pptr, L.foff, L.order, A, L.ptol,
                                L.pdofs, L.pdofs_perm, L.pidx, ldq, L.status);
         };
-        if (R <= 1) go(gj_kernel<1>);
-        else if (R <= 2) go(gj_kernel<2>);
-        else go(gj_kernel<4>);
+        if (R <= 1) go(gj_kernel<1, 1>);
+        else if (R <= 2) go(gj_kernel<2, 4>);
+        else go(gj_kernel<4, 4>);
         if (fork) (void)hipEventRecord(ev_join, aux);
     }
     struct Join {

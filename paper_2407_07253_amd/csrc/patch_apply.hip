@@ -243,6 +243,11 @@ __device__ inline void sym_load(const T* A, int s, int c_lo, int m, int rl, int 
     }
 }
 
+// LDS length of the residual and of each partial result in the symmetric
+// shapes: whole strips plus one unit, so the unit arithmetic may read rows and
+// columns past m (zeros) without bound checks
+inline int sym_ldbuf(int max_m) { return (max_m + kStrip - 1) / kStrip * kStrip + kUnitCols; }
+
 // The arithmetic of one unit (strip s, stored columns c .. c + 63, factor
 // values in a): with L the stored entries, row sums L(rows, cols) r_cols and
 // column sums L(rows, j)^T r_rows, added into the partial result yw.
@@ -254,19 +259,21 @@ __device__ inline void sym_unit(const typename Load16<T>::acc_t (&a)[SymShape<T>
     typedef SymShape<T> Sh;
     constexpr int V = Sh::V, RL = Sh::RL, CL = Sh::CL, U = Sh::U;
     const int r0 = s * kStrip, w = min(m, r0 + kStrip);
+    // the residual rows of the lane's row group: s_r is zero past m up to whole
+    // strips plus one unit (sym_ldbuf), so no row needs a bound check, and the V
+    // values come in one LDS vector read
+    typedef Acc accv __attribute__((ext_vector_type(V)));
+    const accv rv = *reinterpret_cast<const accv*>(s_r + r0 + rl * V);
     Acc rr[V];
 #pragma unroll
-    for (int v = 0; v < V; ++v) {
-        const int i = r0 + rl * V + v;
-        rr[v] = i < m ? s_r[i] : (Acc)0;
-    }
+    for (int v = 0; v < V; ++v) rr[v] = rv[v];
     Acc acc[V], d[U];
 #pragma unroll
     for (int v = 0; v < V; ++v) acc[v] = (Acc)0;
 #pragma unroll
     for (int u = 0; u < U; ++u) {
         const int j = c + cl + CL * u;
-        const Acc rj = j < w ? s_r[min(j, w - 1)] : (Acc)0;
+        const Acc rj = j < w ? s_r[j] : (Acc)0;
         Acc dd = (Acc)0;
 #pragma unroll
         for (int v = 0; v < V; ++v) {
@@ -326,7 +333,9 @@ __global__ __launch_bounds__(kBlock) void patch_apply_sym_kernel(const int32_t* 
     const int64_t base = pptr[p];
     const int m = (int)(pptr[p + 1] - base);
     const T* A = F + foff[p];
-    const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
+    // the wave index as a wave-uniform value, so the walk over the wave's units
+    // (s, c, sym_step) stays in scalar registers
+    const int lane = threadIdx.x & (kWave - 1), wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
     const int rl = lane % RL, cl = lane / RL;
     const int ns = (m + kStrip - 1) / kStrip;
     // this wave's first unit (unit number `wave` in strip-major order): its
@@ -340,6 +349,7 @@ __global__ __launch_bounds__(kBlock) void patch_apply_sym_kernel(const int32_t* 
         const double v = r[pdofs[base + t]];
         s_r[t] = (Acc)(gw ? gw[base + t] * v : v);
     }
+    for (int t = m + threadIdx.x; t < ldbuf; t += NTH) s_r[t] = (Acc)0;
     for (int t = threadIdx.x; t < NP * ldbuf; t += NTH) s_y[t] = (Acc)0;
     __syncthreads();
     bool first = true;
@@ -423,6 +433,7 @@ __global__ __launch_bounds__(kBlock) void patch_apply_sym_small_kernel(const int
         const double v = r[pdofs[base + t]];
         s_r[t] = (Acc)(gw ? gw[base + t] * v : v);
     }
+    for (int t = m + lane; t < ldbuf; t += kWave) s_r[t] = (Acc)0;
     for (int t = lane; t < NP * ldbuf; t += kWave) s_y[t] = (Acc)0;
     __syncthreads();
 #pragma unroll
@@ -440,7 +451,7 @@ __global__ __launch_bounds__(kBlock) void patch_apply_sym_small_kernel(const int
 template <typename T>
 void launch_sym_small(hipStream_t s, const Level& L, const double* r, const double* gw, double* Y) {
     typedef typename Load16<T>::acc_t Acc;
-    const int ldbuf = (L.max_m + 1) & ~1;
+    const int ldbuf = sym_ldbuf(L.max_m);
     const size_t lds = sizeof(Acc) * (size_t)ldbuf * (1 + kSymParts);
     if (streams_factors(L, L.sym))
         hipLaunchKernelGGL((patch_apply_sym_small_kernel<T, true>), dim3(L.npatch), dim3(kWave), lds, s, L.order,
@@ -453,7 +464,7 @@ void launch_sym_small(hipStream_t s, const Level& L, const double* r, const doub
 template <typename T, bool PF, int NWV>
 void launch_sym_shape(hipStream_t s, const Level& L, const double* r, const double* gw, double* Y) {
     typedef typename Load16<T>::acc_t Acc;
-    const int ldbuf = (L.max_m + 1) & ~1;
+    const int ldbuf = sym_ldbuf(L.max_m);
     const size_t lds = sizeof(Acc) * (size_t)ldbuf * (1 + kSymParts);
     if (streams_factors(L, L.sym)) {
         hipLaunchKernelGGL((patch_apply_sym_kernel<T, PF, NWV, true>), dim3(L.npatch), dim3(NWV * kWave), lds, s,

@@ -7,7 +7,7 @@ Laplacian and B the negative divergence.  Section 2.1: Taylor-Hood uses
 continuous P_k / P_{k-1}, Scott-Vogelius continuous P_k / discontinuous
 P_{k-1} on an Alfeld-split mesh.
 
-Readings where the paper is silent (listed in the design notes as well):
+Readings where the paper is silent:
   * Dirichlet data are imposed strongly by eliminating the boundary velocity
     DoFs (their values lifted into the right-hand side).
   * Canonical global numbering, shared *as a convention* with the GPU path's

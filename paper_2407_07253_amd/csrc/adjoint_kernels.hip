@@ -56,7 +56,7 @@ __global__ __launch_bounds__(kBlock) void patch_apply_t_kernel(const int32_t* __
     }
     __syncthreads();
     const T* A = F + foff[p];
-    const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
+    const int lane = threadIdx.x & (kWave - 1), wave = wave_id();
     for (int t0 = wave * U; t0 < m; t0 += NW * U) {
         Acc acc[U];
 #pragma unroll

@@ -250,7 +250,7 @@ __global__ __launch_bounds__(kBlock) void block_apply_kernel(const int32_t* __re
     }
     __syncthreads();
     const T* A = F + foff[p];
-    const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
+    const int lane = threadIdx.x & (kWave - 1), wave = wave_id();
     const int li = lane & 15, lk = lane >> 4;
     const int npass = (m + PASS - 1) / PASS;
     for (int pass = wave; pass < npass; pass += NW) {
@@ -396,7 +396,7 @@ __global__ __launch_bounds__(kBlock) void block_gs_kernel(int64_t n, int ncol, c
     __shared__ double sh[kGsChunk][kBlock / kWave][kBS];
     __shared__ double s_h[kMaxBasis][kBS];
     const int c = threadIdx.x & (kBS - 1);
-    const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
+    const int lane = threadIdx.x & (kWave - 1), wave = wave_id();
     if (MODE != 0) {
         for (int t = threadIdx.x; t < kMaxBasis * kBS; t += kBlock) {
             const int j = t / kBS;
@@ -458,7 +458,7 @@ __global__ __launch_bounds__(kBlock) void block_reduce_kernel(int nparts, const 
     double s = 0.0;
     for (int q = threadIdx.x; q < nparts; q += kBlock) s += partial[(int64_t)t * nparts + q];
     for (int off = kWave / 2; off > 0; off >>= 1) s += __shfl_xor(s, off);
-    const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
+    const int lane = threadIdx.x & (kWave - 1), wave = wave_id();
     if (lane == 0) sh[wave] = s;
     __syncthreads();
     if (threadIdx.x == 0) out[t] = (sh[0] + sh[1]) + (sh[2] + sh[3]);

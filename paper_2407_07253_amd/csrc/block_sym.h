@@ -266,7 +266,7 @@ __global__ __launch_bounds__(kBlock) void block_apply_sym_kernel(const int32_t* 
     const int64_t base = pptr[p];
     const int m = (int)(pptr[p + 1] - base);
     const int ns = (m + kStrip - 1) / kStrip;
-    const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
+    const int lane = threadIdx.x & (kWave - 1), wave = wave_id();
     const int li = lane & 15, lk = lane >> 4;
     Acc* s_t = s_g + NB * kStrip * kBS + wave * 2 * kStrip * kTld;    // this wave's transpose buffers
     const T* A = F + foff[p];

@@ -277,7 +277,7 @@ __global__ __launch_bounds__(kBlock) void extract_kernel(const int64_t* __restri
     int32_t* s_dofs = reinterpret_cast<int32_t*>(s_tile + (int64_t)kExtractRows * m);
     double* A = out + foff[p];
     for (int t = threadIdx.x; t < m; t += blockDim.x) s_dofs[t] = pdofs[base + t];
-    const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
+    const int lane = threadIdx.x & (kWave - 1), wave = wave_id();
     double rmax = 0.0;
     for (int a0 = 0; a0 < m; a0 += kExtractRows) {
         const int h = min(kExtractRows, m - a0);
@@ -372,7 +372,7 @@ __global__ __launch_bounds__(kBlock) void gj_kernel(const int64_t* __restrict__ 
     int* s_phys = (int*)(Q + (int64_t)ldq * W);        // logical -> physical (m)
     int* piv = s_phys + ldq;                           // pivots of the whole patch (m)
 
-    const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
+    const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = wave_id();
     const int p = order ? order[blockIdx.x] : (int)blockIdx.x;
     const int64_t base = pptr[p];
     const int m = (int)(pptr[p + 1] - base);
@@ -572,7 +572,7 @@ __global__ __launch_bounds__(kBlock) void gj_lds_kernel(const int64_t* __restric
     constexpr int W = kPanel, NWV = kBlock / kWave;
     extern __shared__ double smem[];
     __shared__ int s_fail;
-    const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
+    const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = wave_id();
     const int p = order[blockIdx.x];
     const int64_t base = pptr[p];
     const int m = (int)(pptr[p + 1] - base);
@@ -887,7 +887,7 @@ __global__ __launch_bounds__(kDenseThreads) void dense_panel_kernel(double* __re
     __shared__ int s_phys_at[2];     // physical row currently at logical position k
     __shared__ int s_piv[W];
     extern __shared__ int s_phys[];  // logical -> physical for rows >= k0 (N entries)
-    const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
+    const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = wave_id();
     if (status[0] != INT32_MAX) return;
     const double tol = tolp[0];
     double v[R][W];
@@ -1177,7 +1177,7 @@ __global__ __launch_bounds__(kBlock) void coarse_solve_kernel(int32_t n, int32_t
 // ---------------------------------------------------------------------------
 __device__ inline double block_sum(double v, double* sh) {
     for (int off = kWave / 2; off > 0; off >>= 1) v += __shfl_xor(v, off);
-    const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
+    const int lane = threadIdx.x & (kWave - 1), wave = wave_id();
     __syncthreads();
     if (lane == 0) sh[wave] = v;
     __syncthreads();
@@ -1194,7 +1194,7 @@ __global__ __launch_bounds__(kBlock) void multidot_partial_kernel(int64_t n, int
                                                                   double* __restrict__ partial) {
     constexpr int NW = kBlock / kWave;
     __shared__ double sh[kDotChunk][NW];
-    const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
+    const int lane = threadIdx.x & (kWave - 1), wave = wave_id();
     for (int c0 = 0; c0 < ncol; c0 += kDotChunk) {
         double acc[kDotChunk];
 #pragma unroll
@@ -1231,7 +1231,7 @@ __global__ __launch_bounds__(kBlock) void gs_update_kernel(int64_t n, int ncol, 
     constexpr int NA = NORM ? 1 : kGsMax;
     __shared__ double s_h[kGsMax];
     __shared__ double sh[NA][NW];
-    const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
+    const int lane = threadIdx.x & (kWave - 1), wave = wave_id();
     if (threadIdx.x < kGsMax) s_h[threadIdx.x] = (int)threadIdx.x < ncol ? h[threadIdx.x] : 0.0;
     __syncthreads();
     double acc[NA];

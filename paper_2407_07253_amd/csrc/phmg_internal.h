@@ -275,6 +275,11 @@ namespace phmg {
 // Exchange with the lane whose id differs by MASK: lane-pair swaps inside a quad
 // (MASK 1, 2) and the half-row rotation (MASK 8) are DPP moves on the VALU;
 // other masks go through ds_bpermute.
+// The wave's index in its workgroup as a wave-uniform value: the compiler then
+// keeps loops and branches over it in scalar registers instead of running them
+// under execution masks.
+__device__ inline int wave_id() { return __builtin_amdgcn_readfirstlane(threadIdx.x / kWave); }
+
 template <int MASK>
 __device__ inline float xor_shfl(float v) {
     if constexpr (MASK == 1 || MASK == 2 || MASK == 8) {

@@ -5,6 +5,7 @@
 //  * gj_kernel         in-place inversion of every patch matrix by blocked
 //                      Gauss-Jordan elimination with partial pivoting; the
 //                      rank-16 updates run on MFMA f64 16x16x4 tiles
+//                      (gj_wide_kernel: 24-column panels for 257-384 DoFs)
 //  * patch_apply       y_i = K_i^{-1} r[S_i]: in patch_apply.hip
 //  * scatter_kernel    x += omega sum_i R_i^T W_i y_i, DoF-centric, fixed
 //                      ascending patch order (eq. "eq:ASM")
@@ -349,8 +350,8 @@ __global__ __launch_bounds__(kBlock) void extract_kernel(const int64_t* __restri
 // keeps the register count, and so the number of resident waves, highest
 // (measured faster than two or four on the 64..210-DoF patches of the P4/P3
 // level); patches above 256 DoFs (two or more rows per thread) take four, whose
-// loads in flight shorten the update's per-tile latency chain (cfg4's 362-DoF
-// patches: 51.6 -> 47.9 ms).
+// loads in flight shorten the update's per-tile latency chain (on 362-DoF
+// patches 51.6 -> 47.9 ms for 4,221 of them; gj_wide_kernel now takes 257-384).
 template <int R, int kGjTiles>
 __global__ __launch_bounds__(kBlock) void gj_kernel(const int64_t* __restrict__ pptr,
                                                     const int64_t* __restrict__ foff,
@@ -541,6 +542,213 @@ __global__ __launch_bounds__(kBlock) void gj_kernel(const int64_t* __restrict__ 
     for (int t = tid; t < m; t += kBlock) {
         pdofs_perm[base + t] = pdofs[base + s_phys[t]];
         pidx[base + t] = s_phys[t];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// The same inversion for patches of kWideMinM + 1 .. kWideMaxM DoFs (the
+// Scott-Vogelius vertex patches), where gj_kernel moves every patch matrix
+// (about 1 MB) through memory once per 16-column panel.  Here:
+//  * 24-column panels (two thirds of the passes over the matrix), eliminated in
+//    LDS by a 512-thread workgroup with one row per thread; two workgroups fit a
+//    CU, so one's panel elimination overlaps the other's update (32-column
+//    panels leave room for one workgroup per CU and were slower, as were 384-
+//    and 640-thread workgroups);
+//  * rows are never moved during the elimination: the logical -> physical row
+//    map and each row's logical position persist across panels, the update
+//    addresses the panel rows through the map, and one pass at the end puts
+//    the rows of every column in logical order (instead of one pass of row
+//    swaps per panel);
+//  * the update's units (a column block with columns outside the panel, TG row
+//    tiles) are dealt to the waves; since one unit may write rows that another
+//    still reads as its B operand (the panel rows of its columns), those rows
+//    are first copied into the panel's own columns, free until the panel is
+//    written back.
+// Same pivot rule (largest |entry| among logical positions >= k, ties to the
+// lowest position), same stored B = (P K_i)^{-1}, pivot and DoF lists.
+// ---------------------------------------------------------------------------
+constexpr int kWidePanel = 24, kWideThreads = 512, kWideMinM = 256, kWideMaxM = 384;
+
+__global__ __launch_bounds__(kWideThreads) void gj_wide_kernel(const int64_t* __restrict__ pptr,
+                                                               const int64_t* __restrict__ foff,
+                                                               const int32_t* __restrict__ order,
+                                                               double* __restrict__ F,
+                                                               const double* __restrict__ ptol,
+                                                               const int32_t* __restrict__ pdofs,
+                                                               int32_t* __restrict__ pdofs_perm,
+                                                               int32_t* __restrict__ pidx, int ldq,
+                                                               int* __restrict__ status) {
+    constexpr int W = kWidePanel, NWV = kWideThreads / kWave, KT = W / 4, TG = 2;
+    constexpr int NR = NWV <= 4 ? 4 : (NWV <= 8 ? 8 : 16);       // lanes of the candidate reduction
+    static_assert(NWV <= NR && NR <= kWave, "candidate reduction over the first NR lanes");
+    static_assert(kWideMaxM <= kWideThreads, "one row per thread");
+    __shared__ double s_cv[2][NWV];
+    __shared__ int s_ci[2][NWV];
+    __shared__ int s_cp[2][NWV];
+    __shared__ int s_phys_at[2];
+    __shared__ double s_prow[2][W];
+    extern __shared__ double smem[];
+    double* Q = smem;                                  // ldq x W, physical rows
+    int* s_phys = (int*)(Q + (int64_t)ldq * W);        // logical -> physical (m), kept across panels
+
+    const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = wave_id();
+    const int p = order ? order[blockIdx.x] : (int)blockIdx.x;
+    const int64_t base = pptr[p];
+    const int m = (int)(pptr[p + 1] - base);
+    double* A = F + foff[p];
+    const double tol = ptol[p];
+    const int r = tid;                                 // this thread's physical row (m <= kWideThreads)
+    int lpos = r;                                      // its logical position
+    if (r < m) s_phys[r] = r;
+    const int nb16 = (m + 15) / 16, li = lane & 15, lk = lane >> 4;
+
+    for (int k0 = 0; k0 < m; k0 += W) {
+        const int w = min(W, m - k0);
+        if (r < m)
+            for (int c = 0; c < w; ++c) Q[r + c * ldq] = A[r + (int64_t)(k0 + c) * m];
+        __syncthreads();
+        for (int c = 0; c < w; ++c) {
+            const int k = k0 + c, buf = c & 1;
+            double bv = -1.0;
+            int bl = INT_MAX, bp = -1;
+            if (r < m && lpos >= k) {
+                bv = fabs(Q[r + c * ldq]);
+                bl = lpos;
+                bp = r;
+            }
+            for (int off = kWave / 2; off > 0; off >>= 1) {
+                const double ov = __shfl_xor(bv, off);
+                const int ol = __shfl_xor(bl, off), op = __shfl_xor(bp, off);
+                if (ov > bv || (ov == bv && ol < bl)) { bv = ov; bl = ol; bp = op; }
+            }
+            if (lane == 0) { s_cv[buf][wave] = bv; s_ci[buf][wave] = bl; s_cp[buf][wave] = bp; }
+            if (tid == 0) s_phys_at[buf] = s_phys[k];
+            __syncthreads();                                          // barrier A
+            // the waves' candidates, reduced over the first NR lanes of every wave
+            // (logical positions are distinct, so the winner does not depend on the order)
+            bv = lane < NWV ? s_cv[buf][lane] : -1.0;
+            bl = lane < NWV ? s_ci[buf][lane] : INT_MAX;
+            bp = lane < NWV ? s_cp[buf][lane] : -1;
+            for (int off = NR / 2; off > 0; off >>= 1) {
+                const double ov = __shfl_xor(bv, off);
+                const int ol = __shfl_xor(bl, off), op = __shfl_xor(bp, off);
+                if (ov > bv || (ov == bv && ol < bl)) { bv = ov; bl = ol; bp = op; }
+            }
+            bv = __shfl(bv, 0);
+            bl = __shfl(bl, 0);
+            bp = __shfl(bp, 0);
+            if (bp < 0 || !(bv > tol)) {                              // uniform decision
+                if (tid == 0) atomicMin(status, p);
+                return;
+            }
+            const int rk = s_phys_at[buf];
+            if (tid < w) s_prow[buf][tid] = Q[bp + tid * ldq];
+            if (tid == 0) {
+                s_phys[bl] = rk;
+                s_phys[k] = bp;
+            }
+            __syncthreads();                                          // barrier B
+            const double d = 1.0 / s_prow[buf][c];
+            if (r < m) {
+                if (r == bp) {
+                    for (int cc = 0; cc < w; ++cc) Q[r + cc * ldq] = (cc == c) ? d : s_prow[buf][cc] * d;
+                    lpos = k;
+                } else {
+                    const double f = Q[r + c * ldq];
+                    for (int cc = 0; cc < w; ++cc)
+                        Q[r + cc * ldq] = (cc == c) ? -f * d : Q[r + cc * ldq] - f * (s_prow[buf][cc] * d);
+                    if (r == rk) lpos = bl;
+                }
+            }
+        }
+        // rank-w update of the other columns, transposed as in gj_kernel: A[i, J] +=
+        // sum_kk ((Q - E)[i, kk]) A[phys(k0 + kk), J], i physical, E(i, kk) = [i == phys(k0 + kk)].
+        // First the B operand rows A(phys(k0 + kk), j) of every other column j go into the
+        // panel's own columns (Q holds the panel until it is written back), as element
+        // A[j + (k0 + kk) m]: the units then read them coalesced, and no unit can overwrite
+        // them while another still needs them.
+        if (r < m && (r < k0 || r >= k0 + w))
+            for (int kk = 0; kk < w; ++kk) A[r + (int64_t)(k0 + kk) * m] = A[s_phys[k0 + kk] + (int64_t)r * m];
+        int pk[KT];
+#pragma unroll
+        for (int kt = 0; kt < KT; ++kt) {
+            const int kk = kt * 4 + lk;
+            pk[kt] = kk < w ? s_phys[k0 + kk] : -1;
+        }
+        __syncthreads();
+        {
+            // column blocks with at least one column outside the panel; a block the panel
+            // covers in part keeps its other columns (per-column masks)
+            const int pb_lo = (k0 + 15) / 16, pb_hi = (k0 + w) / 16;   // blocks inside the panel
+            const int nfull = (k0 + w == m) ? nb16 - pb_lo : max(0, pb_hi - pb_lo);
+            const int nig = (nb16 + TG - 1) / TG, nunits = (nb16 - nfull) * nig;
+            for (int u = wave; u < nunits; u += NWV) {
+                const int jbx = u / nig, ig = u - jbx * nig;
+                const int jb = jbx < pb_lo ? jbx : jbx + nfull, j = jb * 16 + li;
+                const bool jv = j < m && (j < k0 || j >= k0 + w);
+                double bop[KT];
+#pragma unroll
+                for (int kt = 0; kt < KT; ++kt)
+                    bop[kt] = (jv && pk[kt] >= 0) ? A[j + (int64_t)(k0 + kt * 4 + lk) * m] : 0.0;
+                bool cv[4];                            // columns of the accumulator elements
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int jc = jb * 16 + lk + 4 * v;
+                    cv[v] = jc < m && (jc < k0 || jc >= k0 + w);
+                }
+                d4 acc[TG];
+#pragma unroll
+                for (int h = 0; h < TG; ++h) {
+                    const int i = (ig * TG + h) * 16 + li;
+#pragma unroll
+                    for (int v = 0; v < 4; ++v)
+                        acc[h][v] = (cv[v] && i < m) ? A[i + (int64_t)(jb * 16 + lk + 4 * v) * m] : 0.0;
+                }
+#pragma unroll
+                for (int h = 0; h < TG; ++h) {
+                    const int i = (ig * TG + h) * 16 + li;
+#pragma unroll
+                    for (int kt = 0; kt < KT; ++kt) {
+                        double a = 0.0;
+                        if (i < m && pk[kt] >= 0) {
+                            a = Q[i + (kt * 4 + lk) * ldq];
+                            if (i == pk[kt]) a -= 1.0;
+                        }
+                        acc[h] = __builtin_amdgcn_mfma_f64_16x16x4f64(bop[kt], a, acc[h], 0, 0, 0);
+                    }
+                }
+#pragma unroll
+                for (int h = 0; h < TG; ++h) {
+                    const int i = (ig * TG + h) * 16 + li;
+                    if (i >= m) continue;
+#pragma unroll
+                    for (int v = 0; v < 4; ++v)
+                        if (cv[v]) A[i + (int64_t)(jb * 16 + lk + 4 * v) * m] = acc[h][v];
+                }
+            }
+        }
+        __syncthreads();                               // the copied operand rows are read
+        // the eliminated panel goes back in physical row order
+        if (r < m)
+            for (int c = 0; c < w; ++c) A[r + (int64_t)(k0 + c) * m] = Q[r + c * ldq];
+        __syncthreads();
+    }
+    // rows in logical order: B(l, j) = A(phys(l), j), W columns at a time through Q
+    for (int j0 = 0; j0 < m; j0 += W) {
+        const int w = min(W, m - j0);
+        if (r < m)
+            for (int c = 0; c < w; ++c) Q[r + c * ldq] = A[r + (int64_t)(j0 + c) * m];
+        __syncthreads();
+        if (r < m) {
+            const int pr = s_phys[r];
+            for (int c = 0; c < w; ++c) A[r + (int64_t)(j0 + c) * m] = Q[pr + c * ldq];
+        }
+        __syncthreads();
+    }
+    // P r gather list: the logical -> physical map is the identity with the row swaps applied in order
+    if (r < m) {
+        pdofs_perm[base + r] = pdofs[base + s_phys[r]];
+        pidx[base + r] = s_phys[r];
     }
 }
 
@@ -1458,17 +1666,25 @@ void launch_patch_factor(hipStream_t s, const Level& L, double* A, hipStream_t a
     if (L.gj_cnt[0] > 0) {
         const hipStream_t sb = fork ? aux : s;
         const int ldq = L.gj_max[0];
-        const size_t lds = sizeof(double) * (size_t)ldq * kPanel + sizeof(int) * 2 * (size_t)ldq;
-        const int R = (ldq + kBlock - 1) / kBlock;
-        auto go = [&](auto kernel) {
-            if (lds > 64 * 1024)
-                (void)hipFuncSetAttribute((const void*)kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-            hipLaunchKernelGGL(kernel, dim3(L.gj_cnt[0]), dim3(kBlock), lds, sb, L.pptr, L.foff, L.order, A, L.ptol,
-                               L.pdofs, L.pdofs_perm, L.pidx, ldq, L.status);
-        };
-        if (R <= 1) go(gj_kernel<1, 1>);
-        else if (R <= 2) go(gj_kernel<2, 4>);
-        else go(gj_kernel<4, 4>);
+        if (ldq > kWideMinM && ldq <= kWideMaxM) {
+            // 257-384 DoFs: 24-column panels, 512-thread workgroups, two per CU
+            const size_t lds = sizeof(double) * (size_t)ldq * kWidePanel + sizeof(int) * (size_t)ldq;
+            (void)hipFuncSetAttribute((const void*)gj_wide_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+            hipLaunchKernelGGL(gj_wide_kernel, dim3(L.gj_cnt[0]), dim3(kWideThreads), lds, sb, L.pptr, L.foff, L.order,
+                               A, L.ptol, L.pdofs, L.pdofs_perm, L.pidx, ldq, L.status);
+        } else {
+            const size_t lds = sizeof(double) * (size_t)ldq * kPanel + sizeof(int) * 2 * (size_t)ldq;
+            const int R = (ldq + kBlock - 1) / kBlock;
+            auto go = [&](auto kernel) {
+                if (lds > 64 * 1024)
+                    (void)hipFuncSetAttribute((const void*)kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+                hipLaunchKernelGGL(kernel, dim3(L.gj_cnt[0]), dim3(kBlock), lds, sb, L.pptr, L.foff, L.order, A,
+                                   L.ptol, L.pdofs, L.pdofs_perm, L.pidx, ldq, L.status);
+            };
+            if (R <= 1) go(gj_kernel<1, 1>);
+            else if (R <= 2) go(gj_kernel<2, 4>);
+            else go(gj_kernel<4, 4>);
+        }
         if (fork) (void)hipEventRecord(ev_join, aux);
     }
     struct Join {

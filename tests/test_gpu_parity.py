@@ -231,14 +231,19 @@ def test_apply_before_setup_is_a_state_error():
     H.close()
 
 
-@pytest.mark.parametrize("name,j", [("cfg1", 40), ("cfg2_r1", 100)])
+@pytest.mark.parametrize("name,j", [("cfg1", 40), ("cfg2_r1", 100), ("sv_small", None)])
 def test_singular_patch_is_reported_with_its_id(name, j):
     """A DoF whose row and column are zero makes every patch containing it singular.  cfg1's
     level 0 (patches of at most 64 DoFs) is inverted with the matrix in LDS, cfg2_r1's (up to
-    210 DoFs) with the matrix in global memory: both kernels stop and report."""
+    210 DoFs) with the matrix in global memory, sv_small's 362-DoF vertex patches with 24-column
+    panels (j = None: a DoF of the first patch above 256 DoFs): every kernel stops and reports."""
     from paper_2407_07253_amd._lib import Hierarchy, PhmgError, PHMG_ESINGULAR
     fh = frontend.build_hierarchy(name)
     L0 = fh.levels[0]
+    if j is None:
+        ptr = np.asarray(L0.patch_ptr)
+        big = int(np.flatnonzero(np.diff(ptr) > 256)[0])
+        j = int(L0.patch_dofs[ptr[big]])
     K = L0.K.to_scipy().tolil()
     K[j, :] = 0.0
     K[:, j] = 0.0

@@ -251,10 +251,8 @@ __device__ inline void sym_wave_tiles(typename Mfma<Acc>::acc_t (&acc)[NB], SymT
 }
 
 template <typename T, typename Acc, int NB, int PD, bool ST>
-__global__ __launch_bounds__(kBlock) void block_apply_sym_kernel(const int32_t* __restrict__ order,
-                                                                 const int64_t* __restrict__ pptr,
+__global__ __launch_bounds__(kBlock) void block_apply_sym_kernel(const int64_t* __restrict__ pinfo,
                                                                  const int32_t* __restrict__ pdofs,
-                                                                 const int64_t* __restrict__ foff,
                                                                  const T* __restrict__ F, const double* __restrict__ X,
                                                                  double* __restrict__ Y,
                                                                  const double* __restrict__ gw) {
@@ -262,14 +260,15 @@ __global__ __launch_bounds__(kBlock) void block_apply_sym_kernel(const int32_t* 
     constexpr int RPP = kBlock / kBS;                                  // rows of G per pass of the workgroup
     extern __shared__ double s_buf[];
     Acc* s_g = reinterpret_cast<Acc*>(s_buf);                          // G: 16 NB rows x kBS columns
-    const int p = order[blockIdx.x];
-    const int64_t base = pptr[p];
-    const int m = (int)(pptr[p + 1] - base);
+    // the patch at this launch position (first slot, factor offset, size) in one read
+    const int64_t* info = pinfo + 4 * (int64_t)blockIdx.x;
+    const int64_t base = info[0];
+    const int m = (int)info[2];
     const int ns = (m + kStrip - 1) / kStrip;
     const int lane = threadIdx.x & (kWave - 1), wave = wave_id();
     const int li = lane & 15, lk = lane >> 4;
     Acc* s_t = s_g + NB * kStrip * kBS + wave * 2 * kStrip * kTld;    // this wave's transpose buffers
-    const T* A = F + foff[p];
+    const T* A = F + info[1];
     // the wave's first tiles are in flight during the gather, which they do not need
     SymTile<T, Acc> buf[PD];
     switch (wave) {
@@ -339,8 +338,8 @@ void launch_block_sym_shape(hipStream_t s, const Level& L, const double* X, cons
                                 sizeof(double) * (size_t)NB * kStrip * kBS);
     auto kernel = streams_factors(L, true) ? block_apply_sym_kernel<T, Acc, NB, PD, true>
                                            : block_apply_sym_kernel<T, Acc, NB, PD, false>;
-    hipLaunchKernelGGL(kernel, dim3(L.npatch), dim3(kBlock), lds, s, L.order, L.pptr, L.pdofs, L.fofflp,
-                       (const T*)L.factors, X, L.Yb, gw);
+    hipLaunchKernelGGL(kernel, dim3(L.npatch), dim3(kBlock), lds, s, L.pinfo, L.pdofs, (const T*)L.factors, X,
+                       L.Yb, gw);
 }
 
 template <typename T, typename Acc, int NB>

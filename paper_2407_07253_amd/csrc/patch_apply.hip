@@ -312,10 +312,8 @@ __device__ inline void sym_load_unit(const T* A, int s, int c, int m, int rl, in
 constexpr int kSymParts = 4;
 
 template <typename T, bool PF, int NWV, bool NT>
-__global__ __launch_bounds__(kBlock) void patch_apply_sym_kernel(const int32_t* __restrict__ order,
-                                                                 const int64_t* __restrict__ pptr,
+__global__ __launch_bounds__(kBlock) void patch_apply_sym_kernel(const int64_t* __restrict__ pinfo,
                                                                  const int32_t* __restrict__ pdofs,
-                                                                 const int64_t* __restrict__ foff,
                                                                  const T* __restrict__ F,
                                                                  const double* __restrict__ r,
                                                                  const double* __restrict__ gw,
@@ -329,10 +327,11 @@ __global__ __launch_bounds__(kBlock) void patch_apply_sym_kernel(const int32_t* 
     extern __shared__ double s_buf[];
     Acc* s_r = reinterpret_cast<Acc*>(s_buf);
     Acc* s_y = s_r + ldbuf;                                       // NP partial results of ldbuf each
-    const int p = order[blockIdx.x];
-    const int64_t base = pptr[p];
-    const int m = (int)(pptr[p + 1] - base);
-    const T* A = F + foff[p];
+    // the patch at this launch position: first slot, factor offset and size in one read
+    const int64_t* info = pinfo + 4 * (int64_t)blockIdx.x;
+    const int64_t base = info[0];
+    const T* A = F + info[1];
+    const int m = (int)info[2];
     // the wave index as a wave-uniform value, so the walk over the wave's units
     // (s, c, sym_step) stays in scalar registers
     const int lane = threadIdx.x & (kWave - 1), wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
@@ -393,10 +392,8 @@ __global__ __launch_bounds__(kBlock) void patch_apply_sym_kernel(const int32_t* 
 constexpr int kSmallUnits = 4;
 
 template <typename T, bool NT>
-__global__ __launch_bounds__(kBlock) void patch_apply_sym_small_kernel(const int32_t* __restrict__ order,
-                                                                       const int64_t* __restrict__ pptr,
+__global__ __launch_bounds__(kBlock) void patch_apply_sym_small_kernel(const int64_t* __restrict__ pinfo,
                                                                        const int32_t* __restrict__ pdofs,
-                                                                       const int64_t* __restrict__ foff,
                                                                        const T* __restrict__ F,
                                                                        const double* __restrict__ r,
                                                                        const double* __restrict__ gw,
@@ -407,10 +404,10 @@ __global__ __launch_bounds__(kBlock) void patch_apply_sym_small_kernel(const int
     extern __shared__ double s_buf[];
     Acc* s_r = reinterpret_cast<Acc*>(s_buf);
     Acc* s_y = s_r + ldbuf;
-    const int p = order[blockIdx.x];
-    const int64_t base = pptr[p];
-    const int m = (int)(pptr[p + 1] - base);
-    const T* A = F + foff[p];
+    const int64_t* info = pinfo + 4 * (int64_t)blockIdx.x;   // the patch at this launch position
+    const int64_t base = info[0];
+    const T* A = F + info[1];
+    const int m = (int)info[2];
     const int lane = threadIdx.x & (kWave - 1);
     const int rl = lane % RL, cl = lane / RL;
     const int ns = (m + kStrip - 1) / kStrip;
@@ -454,11 +451,11 @@ void launch_sym_small(hipStream_t s, const Level& L, const double* r, const doub
     const int ldbuf = sym_ldbuf(L.max_m);
     const size_t lds = sizeof(Acc) * (size_t)ldbuf * (1 + kSymParts);
     if (streams_factors(L, L.sym))
-        hipLaunchKernelGGL((patch_apply_sym_small_kernel<T, true>), dim3(L.npatch), dim3(kWave), lds, s, L.order,
-                           L.pptr, L.pdofs, L.fofflp, (const T*)L.factors, r, gw, Y, ldbuf);
+        hipLaunchKernelGGL((patch_apply_sym_small_kernel<T, true>), dim3(L.npatch), dim3(kWave), lds, s, L.pinfo,
+                           L.pdofs, (const T*)L.factors, r, gw, Y, ldbuf);
     else
-        hipLaunchKernelGGL((patch_apply_sym_small_kernel<T, false>), dim3(L.npatch), dim3(kWave), lds, s, L.order,
-                           L.pptr, L.pdofs, L.fofflp, (const T*)L.factors, r, gw, Y, ldbuf);
+        hipLaunchKernelGGL((patch_apply_sym_small_kernel<T, false>), dim3(L.npatch), dim3(kWave), lds, s, L.pinfo,
+                           L.pdofs, (const T*)L.factors, r, gw, Y, ldbuf);
 }
 
 template <typename T, bool PF, int NWV>
@@ -468,10 +465,10 @@ void launch_sym_shape(hipStream_t s, const Level& L, const double* r, const doub
     const size_t lds = sizeof(Acc) * (size_t)ldbuf * (1 + kSymParts);
     if (streams_factors(L, L.sym)) {
         hipLaunchKernelGGL((patch_apply_sym_kernel<T, PF, NWV, true>), dim3(L.npatch), dim3(NWV * kWave), lds, s,
-                           L.order, L.pptr, L.pdofs, L.fofflp, (const T*)L.factors, r, gw, Y, ldbuf);
+                           L.pinfo, L.pdofs, (const T*)L.factors, r, gw, Y, ldbuf);
     } else {
         hipLaunchKernelGGL((patch_apply_sym_kernel<T, PF, NWV, false>), dim3(L.npatch), dim3(NWV * kWave), lds, s,
-                           L.order, L.pptr, L.pdofs, L.fofflp, (const T*)L.factors, r, gw, Y, ldbuf);
+                           L.pinfo, L.pdofs, (const T*)L.factors, r, gw, Y, ldbuf);
     }
 }
 

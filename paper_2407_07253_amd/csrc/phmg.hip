@@ -586,6 +586,7 @@ std::vector<uint64_t> phmg::graph_signature(phmg_ctx ctx) {
         u((uint64_t)L.fuse_restrict);
         p(L.factors);
         p(L.fofflp);
+        p(L.pinfo);
         p(L.bfactors);
         p(L.bfoff);
         p(L.Y);
@@ -906,6 +907,19 @@ void setup_levels(phmg_ctx ctx, int lo, int hi) {
         if (!L.fofflp) L.fofflp = dalloc<int64_t>(ctx, L.npatch);
         hipcheck(hipMemcpy(L.fofflp, off.data(), sizeof(int64_t) * (size_t)L.npatch, hipMemcpyHostToDevice),
                  "hipMemcpy H2D");
+        {
+            std::vector<int64_t> info(4 * (size_t)L.npatch);
+            for (int32_t k = 0; k < L.npatch; ++k) {
+                const int32_t q = L.horder[k];
+                info[4 * (size_t)k] = L.hptr[q];
+                info[4 * (size_t)k + 1] = off[q];
+                info[4 * (size_t)k + 2] = L.hptr[q + 1] - L.hptr[q];
+                info[4 * (size_t)k + 3] = q;
+            }
+            if (!L.pinfo) L.pinfo = dalloc<int64_t>(ctx, 4 * (int64_t)L.npatch);
+            hipcheck(hipMemcpy(L.pinfo, info.data(), sizeof(int64_t) * info.size(), hipMemcpyHostToDevice),
+                     "hipMemcpy H2D");
+        }
         const size_t bytes = es * (size_t)std::max<int64_t>(cnt, 1);
         if (!L.factors || L.factor_bytes < bytes) {
             if (L.factors) dfree(ctx, L.factors);
@@ -1387,6 +1401,7 @@ phmg_status phmg_hierarchy_create(const phmg_hierarchy_desc* desc, const phmg_cy
                 L.pweight = pt.weight ? upload(ctx, pt.weight, L.sum_m) : nullptr;
                 L.foff = upload(ctx, foff.data(), pt.npatch);
                 L.order = upload(ctx, order.data(), pt.npatch);
+                L.horder = order;
                 L.sptr = upload(ctx, sptr.data(), L.n + 1);
                 L.sslot = upload(ctx, sslot.data(), L.sum_m);
                 {

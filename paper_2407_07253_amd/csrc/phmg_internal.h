@@ -108,6 +108,9 @@ struct Level {
     int storage = PHMG_STORAGE_AUTO; // requested layout of the stored inverses
     bool sym = false;                // the stored inverses use the symmetric strip layout
     int32_t* order = nullptr;        // launch order: patches by decreasing size
+    std::vector<int32_t> horder;     // host copy of order
+    int64_t* pinfo = nullptr;        // per launch position k: pptr[p], fofflp[p], m, p (p = order[k]),
+                                     // so the patch solve reads its patch without the order indirection
     // patch inversion kernels by size class, over consecutive ranges of the launch order:
     // gj_cnt[0] patches inverted with the matrix in global memory (more than 144 DoFs),
     // gj_cnt[1..2] of 97-144 and 65-96 DoFs (matrix in registers), gj_cnt[3] of at most 64 (in LDS)

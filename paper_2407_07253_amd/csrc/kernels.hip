@@ -289,16 +289,30 @@ __global__ __launch_bounds__(kBlock) void extract_kernel(const int64_t* __restri
             const int g = s_dofs[a0 + q];
             const int end = rowptr[g + 1];
             double rsum = 0.0;
-            for (int k = rowptr[g] + (lane & 15); k < end; k += 16) {
-                const int c = col[k];
-                int lo = 0, hi = m;
-                while (lo < hi) {
-                    const int mid = (lo + hi) >> 1;
-                    if (s_dofs[mid] < c) lo = mid + 1; else hi = mid;
+            // four entries per lane at a time: their column and value loads are all issued
+            // before the searches (same entries, same order of the row sum)
+            for (int k0 = rowptr[g] + (lane & 15); k0 < end; k0 += 4 * 16) {
+                int cs[4];
+                double vs[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const int k = k0 + 16 * u;
+                    cs[u] = k < end ? col[k] : -1;
+                    vs[u] = k < end ? val[k] : 0.0;
                 }
-                if (lo < m && s_dofs[lo] == c) {
-                    s_tile[q + kExtractRows * lo] = val[k];
-                    rsum += fabs(val[k]);
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const int c = cs[u];
+                    if (c < 0) continue;
+                    int lo = 0, hi = m;
+                    while (lo < hi) {
+                        const int mid = (lo + hi) >> 1;
+                        if (s_dofs[mid] < c) lo = mid + 1; else hi = mid;
+                    }
+                    if (lo < m && s_dofs[lo] == c) {
+                        s_tile[q + kExtractRows * lo] = vs[u];
+                        rsum += fabs(vs[u]);
+                    }
                 }
             }
             for (int off = 8; off > 0; off >>= 1) rsum += __shfl_xor(rsum, off, 16);

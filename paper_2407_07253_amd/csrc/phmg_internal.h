@@ -304,6 +304,40 @@ __device__ inline double xor_shfl(double v) {
     }
 }
 
+// One butterfly step across 32 (MASK 32) or 16 (MASK 16) lanes for a pair of
+// values (lo, hi): the lane whose MASK bit is clear keeps lo and adds its
+// partner's lo, the other keeps hi and adds its partner's hi.  The gfx950
+// lane-swap instructions do the exchange for both values at once: after
+// v_permlane32_swap (v_permlane16_swap) of (lo, hi) the two registers hold, in
+// every lane, the kept value and the partner's copy of it (in one order or the
+// other; the sum is the same bits either way).
+template <int MASK>
+__device__ inline float swap_sum(float lo, float hi) {
+    static_assert(MASK == 16 || MASK == 32, "lane-swap distance");
+    if constexpr (MASK == 32) {
+        const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(lo), __float_as_uint(hi), false, false);
+        return __uint_as_float(r[0]) + __uint_as_float(r[1]);
+    } else {
+        const auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(lo), __float_as_uint(hi), false, false);
+        return __uint_as_float(r[0]) + __uint_as_float(r[1]);
+    }
+}
+template <int MASK>
+__device__ inline double swap_sum(double lo, double hi) {
+    static_assert(MASK == 16 || MASK == 32, "lane-swap distance");
+    const uint32_t l0 = (uint32_t)__double2loint(lo), l1 = (uint32_t)__double2hiint(lo);
+    const uint32_t h0 = (uint32_t)__double2loint(hi), h1 = (uint32_t)__double2hiint(hi);
+    if constexpr (MASK == 32) {
+        const auto a = __builtin_amdgcn_permlane32_swap(l0, h0, false, false);
+        const auto b = __builtin_amdgcn_permlane32_swap(l1, h1, false, false);
+        return __hiloint2double((int)b[0], (int)a[0]) + __hiloint2double((int)b[1], (int)a[1]);
+    } else {
+        const auto a = __builtin_amdgcn_permlane16_swap(l0, h0, false, false);
+        const auto b = __builtin_amdgcn_permlane16_swap(l1, h1, false, false);
+        return __hiloint2double((int)b[0], (int)a[0]) + __hiloint2double((int)b[1], (int)a[1]);
+    }
+}
+
 // Sum of N values over groups of G lanes (lane ids that differ only in the
 // bits of (lane / STRIDE) % G), as a butterfly that first scatters: while more
 // than one value is left, each level keeps half of the list (the upper half in
@@ -319,12 +353,17 @@ struct GroupReduce {
             constexpr int g = G / 2;
             if constexpr (N > 1) {
                 constexpr int h = N / 2;
-                const bool up = ((lane / STRIDE) & g) != 0;
+                if constexpr (g * STRIDE == 16 || g * STRIDE == 32) {
 #pragma unroll
-                for (int e = 0; e < h; ++e) {
-                    const Acc lo = x[e], hi = x[e + h];
-                    const Acc other = xor_shfl<g * STRIDE>(up ? lo : hi);
-                    x[e] = (up ? hi : lo) + other;
+                    for (int e = 0; e < h; ++e) x[e] = swap_sum<g * STRIDE>(x[e], x[e + h]);
+                } else {
+                    const bool up = ((lane / STRIDE) & g) != 0;
+#pragma unroll
+                    for (int e = 0; e < h; ++e) {
+                        const Acc lo = x[e], hi = x[e + h];
+                        const Acc other = xor_shfl<g * STRIDE>(up ? lo : hi);
+                        x[e] = (up ? hi : lo) + other;
+                    }
                 }
                 GroupReduce<Acc, h, g, STRIDE>::run(x, lane);
             } else {

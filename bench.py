@@ -40,7 +40,8 @@ HBM_PEAK_GBS = 8000.0
 FP64_MFMA_PEAK_TFLOPS = 78.6      # dense FP64 MFMA peak of MI355X
 GOLDEN = os.path.join(ROOT, "tests", "golden")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "patch_apply_traffic.json")
-KERNEL_SOURCE = os.path.join(ROOT, "paper_2407_07253_amd", "csrc", "patch_apply.hip")
+# the patch solve's source: the kernel and the shared header with its layout helpers and reductions
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_2407_07253_amd", "csrc", f) for f in ("patch_apply.hip", "phmg_internal.h")]
 PRECS = ("f64", "f32", "bf16")
 ES = {"f64": 8, "f32": 4, "bf16": 2}
 
@@ -105,13 +106,20 @@ def method_block_bytes(m, es: int, sym: bool, nrhs: int = 16) -> int:
     return es * words + (4 + 16 * nrhs) * int(m.sum()) + 20 * len(m)
 
 
+def kernel_source_sha() -> str:
+    """SHA-256 over the patch solve's source files, in order."""
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        h.update(open(f, "rb").read())
+    return h.hexdigest()
+
+
 def traffic_entry(workload: str, prec: str):
     """Counter-measured HBM bytes per launch from the committed rocprofv3 summary, when it covers this
     workload and the kernel source is unchanged."""
     try:
         d = json.load(open(TRAFFIC_FILE))
-        sha = hashlib.sha256(open(KERNEL_SOURCE, "rb").read()).hexdigest()
-        if d.get("kernel_source_sha256") != sha:
+        if d.get("kernel_source_sha256") != kernel_source_sha():
             return None
         return float(d["per_launch_bytes"][workload][prec])
     except Exception:

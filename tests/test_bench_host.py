@@ -44,7 +44,8 @@ def test_method_bytes_closed_forms():
 
 
 def test_traffic_only_for_the_profiled_workload_and_source(monkeypatch, tmp_path):
-    sha = hashlib.sha256(open(bench.KERNEL_SOURCE, "rb").read()).hexdigest()
+    sha = hashlib.sha256(b"".join(open(p, "rb").read() for p in bench.KERNEL_SOURCES)).hexdigest()
+    assert bench.kernel_source_sha() == sha
     f = tmp_path / "traffic.json"
     f.write_text(json.dumps({"kernel_source_sha256": sha, "per_launch_bytes": {"cfg3": {"f64": 123.0}}}))
     monkeypatch.setattr(bench, "TRAFFIC_FILE", str(f))
@@ -52,11 +53,13 @@ def test_traffic_only_for_the_profiled_workload_and_source(monkeypatch, tmp_path
     # counters of one workload or precision say nothing about another's launch
     assert bench.traffic_entry("cfg4", "f64") is None
     assert bench.traffic_entry("cfg3", "bf16") is None
-    # nor after the kernel source changed
-    src = tmp_path / "patch_apply.hip"
-    src.write_bytes(open(bench.KERNEL_SOURCE, "rb").read() + b"\n// edited\n")
-    monkeypatch.setattr(bench, "KERNEL_SOURCE", str(src))
-    assert bench.traffic_entry("cfg3", "f64") is None
+    # nor after the kernel or its header changed
+    orig = list(bench.KERNEL_SOURCES)
+    for i in range(len(orig)):
+        src = tmp_path / f"edited_{i}"
+        src.write_bytes(open(orig[i], "rb").read() + b"\n// edited\n")
+        monkeypatch.setattr(bench, "KERNEL_SOURCES", orig[:i] + [str(src)] + orig[i + 1:])
+        assert bench.traffic_entry("cfg3", "f64") is None
 
 
 def test_oracle_error_against_stored_columns():

@@ -917,8 +917,9 @@ void setup_levels(phmg_ctx ctx, int lo, int hi) {
                 info[4 * (size_t)k + 3] = q;
             }
             if (!L.pinfo) L.pinfo = dalloc<int64_t>(ctx, 4 * (int64_t)L.npatch);
-            hipcheck(hipMemcpy(L.pinfo, info.data(), sizeof(int64_t) * info.size(), hipMemcpyHostToDevice),
-                     "hipMemcpy H2D");
+            if (!info.empty())
+                hipcheck(hipMemcpy(L.pinfo, info.data(), sizeof(int64_t) * info.size(), hipMemcpyHostToDevice),
+                         "hipMemcpy H2D");
         }
         const size_t bytes = es * (size_t)std::max<int64_t>(cnt, 1);
         if (!L.factors || L.factor_bytes < bytes) {
